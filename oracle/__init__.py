@@ -1,0 +1,26 @@
+"""CPU FP64 oracle for bootstrapped block Lanczos -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, obviously-correct implementation of what the HIP path computes,
+written from Zbikowski & Johnson, "Bootstrapped Block Lanczos for
+large-dimension eigenvalue problems" (arXiv 2210.15763):
+
+* ``spmm``            -- the block product w_{a,i} = sum_j H_ij v_{a,j}
+                         (Methods, "Block Lanczos algorithm"), a C loop.
+* ``block_lanczos``   -- the block three-term recurrence with the diagonal
+                         block A_n, the residual block W', the overlap O and
+                         its spectral factorisation B_n, V_{n+1}, full
+                         reorthogonalisation, and the band matrix solved by a
+                         dense symmetric eigensolver (Methods).
+* ``scalar_lanczos``  -- the single-vector method (Algorithm "Lanczos method").
+* ``bootstrap_pivot`` -- the pivot block built from eigenvectors of a
+                         truncated leading block (Methods, last paragraphs).
+* ``mlp``             -- a float64 reference of the learned pivot proposer's
+                         network (not in the paper; see that module).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU-baseline
+leg may import this package.  It shares no code with the HIP path; the only
+common dependency is the seeded input generator ``synthgen``.
+"""
+from .spmm import spmm, spmm_abs, build_native  # noqa: F401
+from .lanczos import (block_lanczos, scalar_lanczos, bootstrap_pivot, svqb,  # noqa: F401
+                      ritz_residuals, LanczosResult)
