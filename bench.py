@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Benchmark: time-to-solution of bootstrapped block Lanczos on one MI355X.
+
+Workload (synthetic, seeded): n = 2,000,000, ~200 nnz/row (4.0e8 nnz), 2000
+sectors of 1000 rows, 70/30 in-sector/partner split; FP32 values with int32
+columns; block size 8, lowest 10 eigenpairs to residual 1e-6 * ||H||; pivot
+bootstrapped from the leading 20,000-row block.  One step = bootstrap pivot +
+block Lanczos to convergence + Ritz vectors + explicit FP64 residual, with the
+matrix already resident in HBM.
+
+Prints ONE JSON line (metric, value = mean time-to-solution in seconds, ...)
+with a "roofline" object for the dominant kernel (the CSR SpMM, measured with
+HIP events on the stream it runs on) and a "cpu_baseline" object (the FP64
+CPU oracle timed on a bounded sample of the same solve on the host cores).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
+FP64_PEAK = 78.6e12        # FLOP/s, MI355X FP64 (vector and matrix)
+WORKLOAD = "mid_n2e6"
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def load_matrix(w):
+    import synthgen
+    cache = os.environ.get("BBL_CACHE_DIR")
+    key = "%s_%d_%d_%d_%g_%d" % (w.name, w.n, w.R, w.q, w.p, w.seed)
+    if cache:
+        os.makedirs(cache, exist_ok=True)
+        base = os.path.join(cache, key)
+        if os.path.exists(base + ".val.npy"):
+            H = synthgen.CSR(w.n, np.load(base + ".rp.npy"), np.load(base + ".col.npy"),
+                             np.load(base + ".val.npy"), None, None, w.R)
+            return H
+    H = w.generate()
+    if cache:
+        np.save(base + ".rp.npy", H.row_ptr)
+        np.save(base + ".col.npy", H.col)
+        np.save(base + ".val.npy", H.val)
+    return H
+
+
+def spmm_bytes(n, nnz, b, sv, sx):
+    # values + columns streamed once, row pointers, V read once, W written once
+    return nnz * (sv + 4) + 8 * (n + 1) + 2 * n * b * sx
+
+
+def source_hash(*names):
+    h = hashlib.sha256()
+    for nm in names:
+        with open(os.path.join(ROOT, "paper_2210_15763_amd", "csrc", nm), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_hash):
+    """HBM bytes per SpMM launch measured with rocprofv3 counters (committed
+    summary), or None when the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", "spmm_mid_n2e6_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("spmm_source_hash") != kernel_hash:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def time_kernel(torch, fn, iters):
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(iters):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / 1e3 / iters
+
+
+def cpu_baseline(H, w, pivot_np, gpu_iters):
+    """Oracle (FP64, host cores) on a bounded sample of the same solve: block
+    iterations m1 and m2 from the same pivot on the same (float32-rounded)
+    matrix; per-iteration cost a + c*j fitted from the two runs and summed to
+    the GPU's iteration count.  The truncated-space pivot solve is timed in
+    full."""
+    import oracle
+    H32 = H.as_float32_values()
+    t0 = time.perf_counter()
+    oracle.bootstrap_pivot(H32, w.n_trunc, w.nvec, tol=w.tol, m_max=w.m_max, seed=w.seed)
+    t_piv = time.perf_counter() - t0
+    m1, m2 = 4, 12
+    t0 = time.perf_counter()
+    oracle.block_lanczos(H32, pivot_np, w.k, 1e-300, m1, seed=w.seed)
+    t1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.block_lanczos(H32, pivot_np, w.k, 1e-300, m2, seed=w.seed)
+    t2 = time.perf_counter() - t0
+    # t(m) = a m + c m^2 / 2  (iteration j costs a + c j)
+    A = np.array([[m1, m1 * m1 / 2.0], [m2, m2 * m2 / 2.0]])
+    a, c = np.linalg.solve(A, np.array([t1, t2]))
+    a, c = max(a, 0.0), max(c, 0.0)
+    m = gpu_iters
+    est = t_piv + a * m + c * m * m / 2.0 + a  # + one explicit-residual product
+    return {
+        "value": est, "unit": "s", "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count())),
+        "kind": "oracle",
+        "sample": ("FP64 oracle on the same matrix (float32-rounded values) and pivot: "
+                   "truncated-space pivot solve timed in full (%.1f s); block iterations "
+                   "m=%d (%.1f s) and m=%d (%.1f s) timed, per-iteration cost a+c*j fitted "
+                   "and summed to the GPU's %d iterations" % (t_piv, m1, t1, m2, t2, m)),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--random-arm", action="store_true",
+                    help="also solve once from a random pivot and report its counts")
+    ap.add_argument("--spmm-iters", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the hot path has no multi-GPU build "
+              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synthgen
+    import paper_2210_15763_amd as bbl
+    bbl.load_library()
+    w = synthgen.WORKLOADS[WORKLOAD]
+    t0 = time.time()
+    H = load_matrix(w)
+    log("matrix n=%d nnz=%d (%.1f nnz/row) ready in %.1f s" % (H.n, H.nnz, H.nnz / H.n,
+                                                               time.time() - t0))
+    Hd = bbl.DeviceCSR.from_host(H, "float32")
+    torch.cuda.synchronize()
+    b, k = w.nvec, w.k
+
+    ws_l = torch.empty(bbl.lanczos_workspace_bytes(H.n, b, k, w.m_max, bbl.BBL_F32),
+                       dtype=torch.uint8, device="cuda")
+
+    def step():
+        P, pst = bbl.bootstrap_pivot(Hd, w.n_trunc, b, w.tol, m_max=w.m_max, seed=w.seed)
+        r = bbl.block_lanczos(Hd, P, k, w.tol, m_max=w.m_max, seed=w.seed, workspace=ws_l)
+        return P, pst, r
+
+    for i in range(args.warmup):
+        _, pst, r = step()
+        log("warmup %d: iters=%d converged=%s" % (i, r.stats["iters"], r.converged))
+    torch.cuda.synchronize()
+    times = []
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        P, pst, r = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        log("step %d: %.3f s iters=%d pivot_iters=%d converged=%s" %
+            (i, times[-1], r.stats["iters"], pst["iters"], r.converged))
+    tts = float(np.mean(times))
+
+    # dominant kernel: the SpMM, timed alone with HIP events on the current stream
+    V = torch.randn((H.n, b), dtype=torch.float32, device="cuda")
+    W = torch.empty_like(V)
+    t_spmm = time_kernel(torch, lambda: bbl.spmm(Hd, V, W), args.spmm_iters)
+    alg = spmm_bytes(H.n, H.nnz, b, 4, 4)
+    achieved = alg / t_spmm
+    traffic = read_traffic(source_hash("spmm.hip"))
+
+    # reorthogonalisation gram on FP64 matrix cores: V_{1:j}^T W' at j = 50
+    j = 50
+    Xb = torch.randn((j, H.n, b), dtype=torch.float32, device="cuda")
+    Y = torch.randn((H.n, b), dtype=torch.float64, device="cuda")
+    t_gram = time_kernel(torch, lambda: bbl.gram(Xb, j, b, Y), 5)
+    gram_bytes = j * H.n * b * 4 + H.n * b * 8
+    gram_flops = 2.0 * H.n * j * b * b
+
+    extra = {
+        "bootstrap": {"iters": r.stats["iters"], "spmm_calls": r.stats["spmm_calls"],
+                      "vector_equiv_iters": r.stats["iters"] * b,
+                      "pivot_iters": pst["iters"], "pivot_spmm_calls": pst["spmm_calls"],
+                      "eigvals": [float(x) for x in r.eigvals],
+                      "max_resid_over_hnorm": float(np.max(r.residuals) / r.stats["hnorm_est"]),
+                      "converged": bool(r.converged)},
+        "spmm": {"ms": t_spmm * 1e3, "alg_GBps": achieved / 1e9,
+                 "frac_hbm_peak": achieved / HBM_PEAK,
+                 "time_per_op_ns": t_spmm / (H.nnz * b) * 1e9},
+        "reorth_gram_j50": {"ms": t_gram * 1e3, "alg_GBps": gram_bytes / t_gram / 1e9,
+                            "fp64_TFLOPs": gram_flops / t_gram / 1e12,
+                            "frac_fp64_peak": gram_flops / t_gram / FP64_PEAK},
+    }
+    if args.random_arm:
+        Pr = bbl.random_pivot(H.n, b, synthgen.pivot_key(w.seed))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rr = bbl.block_lanczos(Hd, Pr, k, w.tol, m_max=w.m_max, seed=w.seed)
+        torch.cuda.synchronize()
+        extra["random"] = {"iters": rr.stats["iters"], "spmm_calls": rr.stats["spmm_calls"],
+                           "tts_s": time.perf_counter() - t, "converged": bool(rr.converged),
+                           "max_eig_rel_diff_vs_bootstrap":
+                               float(np.max(np.abs(rr.eigvals - r.eigvals) / np.abs(r.eigvals)))}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample) ...")
+        cpu = cpu_baseline(H, w, P.cpu().numpy(), r.stats["iters"])
+
+    out = {
+        "metric": "time-to-solution, 10 eigpairs @1e-6 resid",
+        "value": tts,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": tts * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sectored symmetric CSR n=2e6, ~200 nnz/row, FP32 values, "
+                               "b=8, k=10, tol=1e-6, bootstrap pivot from leading 20000 rows",
+                   "n": H.n, "nnz": H.nnz, "nvec": b, "k": k, "tol": w.tol,
+                   "n_trunc": w.n_trunc, "m_max": w.m_max, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK,
+                     "traffic": traffic, "kernel": "k_spmm<float,float,float,float,8,64>",
+                     "alg_bytes_per_launch": alg},
+        "cpu_baseline": cpu,
+        "details": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

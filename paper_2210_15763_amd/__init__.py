@@ -1,0 +1,303 @@
+"""Bootstrapped block Lanczos on AMD MI355X -- Python binding of libbbl.so.
+
+Thin ctypes marshalling over the C ABI declared in ``include/bbl.h``: every
+step of the eigensolver runs in the library's HIP kernels; PyTorch only
+provides device memory and the current stream.  There is no CPU fallback:
+importing the binding without a built ``libbbl.so`` raises.
+
+Method: Zbikowski & Johnson, "Bootstrapped Block Lanczos for large-dimension
+eigenvalue problems" (arXiv 2210.15763), Methods section.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbbl.so")
+
+BBL_OK = 0
+BBL_E_INVALID = -1
+BBL_E_NOMEM = -2
+BBL_E_HIP = -3
+BBL_E_NOT_CONVERGED = -4
+BBL_E_BREAKDOWN = -5
+BBL_F32 = 1
+BBL_F64 = 2
+
+_STATUS = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "NOT_CONVERGED", -5: "BREAKDOWN"}
+
+
+class BblError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("bbl error %s (%d): %s" % (_STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("val", ctypes.c_void_p), ("val_dtype", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("m_max", ctypes.c_int32), ("basis_dtype", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("defl_tau", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("spmm_calls", ctypes.c_int32),
+                ("deflations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("checks", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
+                ("hnorm_est", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+# every symbol include/bbl.h declares
+EXPORTS = ("bbl_last_error", "bbl_version", "bbl_spmm", "bbl_lanczos_workspace_size",
+           "bbl_block_lanczos", "bbl_bootstrap_workspace_size", "bbl_bootstrap_pivot",
+           "bbl_random_pivot", "bbl_band_eig_workspace_size", "bbl_band_eig",
+           "bbl_gram_workspace_size", "bbl_gram", "bbl_block_update")
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libbbl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libbbl.so not found at %s: build it with "
+                           "`python -m paper_2210_15763_amd.build`" % path)
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D, SZ, U64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                               ctypes.c_size_t, ctypes.c_uint64)
+    sig = {
+        "bbl_last_error": (ctypes.c_char_p, []),
+        "bbl_version": (ctypes.c_char_p, []),
+        "bbl_spmm": (ctypes.c_int, [P, P, P, I32, I32, P]),
+        "bbl_lanczos_workspace_size": (SZ, [I64, I32, I32, I32, I32]),
+        "bbl_block_lanczos": (ctypes.c_int, [P, P, I32, I32, D, P, SZ, P, P, P, P, P, P]),
+        "bbl_bootstrap_workspace_size": (SZ, [P, I64, I32, I32, I32, P]),
+        "bbl_bootstrap_pivot": (ctypes.c_int, [P, I64, I32, D, P, SZ, P, P, P, P]),
+        "bbl_random_pivot": (ctypes.c_int, [I64, I32, U64, P, P]),
+        "bbl_band_eig_workspace_size": (SZ, [I32, I32, I32]),
+        "bbl_band_eig": (ctypes.c_int, [P, I32, I32, I32, P, SZ, P, P, P, P]),
+        "bbl_gram_workspace_size": (SZ, [I64, I32, I32, I32]),
+        "bbl_gram": (ctypes.c_int, [I64, P, I32, I32, I32, P, I32, I32, P, P, SZ, P]),
+        "bbl_block_update": (ctypes.c_int, [I64, P, I32, I32, I32, P, I32, D, P, I32, D, P, I32,
+                                            P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != BBL_OK and code != BBL_E_NOT_CONVERGED:
+        raise BblError(code, load_library().bbl_last_error().decode())
+    return code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return BBL_F32
+    if t.dtype == torch.float64:
+        return BBL_F64
+    raise TypeError("only float32 / float64 tensors are supported, got %s" % t.dtype)
+
+
+@dataclass
+class DeviceCSR:
+    """Symmetric CSR matrix on the device: int64 row_ptr, int32 col, float32 or
+    float64 values (torch tensors on the current HIP device)."""
+    n: int
+    row_ptr: "object"
+    col: "object"
+    val: "object"
+
+    @property
+    def nnz(self):
+        return int(self.col.numel())
+
+    def _c(self):
+        return _Csr(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
+                    self.val.data_ptr(), _dtype_code(self.val), 0)
+
+    @classmethod
+    def from_host(cls, H, dtype="float32", device="cuda"):
+        """Upload a host CSR (any object with n, row_ptr, col, val)."""
+        torch = _torch()
+        val = np.asarray(H.val, dtype=np.float32 if dtype in ("float32", "f32") else np.float64)
+        return cls(int(H.n), torch.from_numpy(np.ascontiguousarray(H.row_ptr, np.int64)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(H.col, np.int32)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(val)).to(device))
+
+
+def _opts(m_max, basis_dtype, check_every, seed, defl_tau):
+    return _Opts(int(m_max), int(basis_dtype), int(check_every), 0, float(defl_tau),
+                 int(seed) & (2**64 - 1))
+
+
+def spmm(H: DeviceCSR, V, W=None):
+    """W = H V for a row-major n x nvec block V (float32 needs float32 H)."""
+    torch = _torch()
+    assert V.is_contiguous() and V.shape[0] == H.n
+    nvec = V.shape[1]
+    if W is None:
+        W = torch.empty_like(V)
+    lib = load_library()
+    Hc = H._c()
+    _check(lib.bbl_spmm(ctypes.byref(Hc), _ptr(V), _ptr(W), nvec, _dtype_code(V), _stream()))
+    return W
+
+
+def lanczos_workspace_bytes(n, nvec, k, m_max, basis_dtype):
+    return int(load_library().bbl_lanczos_workspace_size(n, nvec, k, m_max, basis_dtype))
+
+
+@dataclass
+class LanczosResult:
+    eigvals: np.ndarray
+    eigvecs: "object"
+    residuals: np.ndarray
+    status: int
+    stats: dict
+
+    @property
+    def converged(self):
+        return self.status == BBL_OK
+
+
+def block_lanczos(H: DeviceCSR, pivot, k: int, tol: float, *, m_max: int = 200,
+                  basis_dtype=None, check_every: int = 0, seed: int = 0, defl_tau: float = 1e-12,
+                  workspace=None, want_vectors: bool = True) -> LanczosResult:
+    """Lowest k eigenpairs of H from the n x nvec float64 pivot block."""
+    torch = _torch()
+    assert pivot.dtype == torch.float64 and pivot.is_contiguous() and pivot.shape[0] == H.n
+    nvec = pivot.shape[1]
+    if basis_dtype is None:
+        basis_dtype = _dtype_code(H.val)
+    lib = load_library()
+    need = lib.bbl_lanczos_workspace_size(H.n, nvec, k, m_max, basis_dtype)
+    if need == 0:
+        raise BblError(BBL_E_INVALID, "invalid sizes for the workspace query")
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=pivot.device)
+    eigvals = np.zeros(k)
+    resid = np.zeros(k)
+    X = torch.empty((H.n, k), dtype=torch.float64, device=pivot.device) if want_vectors else None
+    st = _Stats()
+    Hc = H._c()
+    o = _opts(m_max, basis_dtype, check_every, seed, defl_tau)
+    code = lib.bbl_block_lanczos(ctypes.byref(Hc), _ptr(pivot), nvec, k, tol, _ptr(workspace),
+                                 workspace.numel(), ctypes.byref(o),
+                                 eigvals.ctypes.data_as(ctypes.c_void_p), _ptr(X),
+                                 resid.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st),
+                                 _stream())
+    _check(code)
+    return LanczosResult(eigvals, X, resid, code, st.as_dict())
+
+
+def bootstrap_pivot(H: DeviceCSR, n_trunc: int, nvec: int, tol: float, *, m_max: int = 200,
+                    basis_dtype=None, check_every: int = 0, seed: int = 0, workspace=None):
+    """Pivot block from the lowest nvec eigenvectors of H[0:n_trunc, 0:n_trunc],
+    zero-padded to n rows.  Returns (pivot, stats of the truncated solve)."""
+    torch = _torch()
+    if basis_dtype is None:
+        basis_dtype = _dtype_code(H.val)
+    lib = load_library()
+    Hc = H._c()
+    need = lib.bbl_bootstrap_workspace_size(ctypes.byref(Hc), n_trunc, nvec, m_max, basis_dtype,
+                                            _stream())
+    if need == 0:
+        raise BblError(BBL_E_INVALID, lib.bbl_last_error().decode())
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=H.val.device)
+    pivot = torch.empty((H.n, nvec), dtype=torch.float64, device=H.val.device)
+    st = _Stats()
+    o = _opts(m_max, basis_dtype, check_every, seed, 1e-12)
+    code = lib.bbl_bootstrap_pivot(ctypes.byref(Hc), n_trunc, nvec, tol, _ptr(workspace),
+                                   workspace.numel(), ctypes.byref(o), _ptr(pivot),
+                                   ctypes.byref(st), _stream())
+    _check(code)
+    return pivot, dict(st.as_dict(), status=code)
+
+
+def random_pivot(n: int, nvec: int, key: int, device="cuda"):
+    """n x nvec float64 N(0,1) block from Philox4x32-10 (counter (i, a, 6))."""
+    torch = _torch()
+    out = torch.empty((n, nvec), dtype=torch.float64, device=device)
+    _check(load_library().bbl_random_pivot(n, nvec, int(key) & (2**64 - 1), _ptr(out), _stream()))
+    return out
+
+
+def pivot_key(seed: int) -> int:
+    return (seed ^ 0x9E3779B97F4A7C15) & (2**64 - 1)
+
+
+def band_eig(band, N: int, kd: int, k: int):
+    """Lowest k eigenpairs (+ the largest eigenvalue) of a band matrix stored as
+    band[i*(kd+1)+d] = T[i][i-d] (float64 device tensor)."""
+    torch = _torch()
+    lib = load_library()
+    need = lib.bbl_band_eig_workspace_size(N, kd, k)
+    if need == 0:
+        raise BblError(BBL_E_INVALID, "bad band sizes")
+    ws = torch.empty(need, dtype=torch.uint8, device=band.device)
+    theta = np.zeros(k)
+    top = ctypes.c_double(0.0)
+    S = torch.empty((N, k), dtype=torch.float64, device=band.device)
+    _check(lib.bbl_band_eig(_ptr(band), N, kd, k, _ptr(ws), ws.numel(),
+                            theta.ctypes.data_as(ctypes.c_void_p), _ptr(S), ctypes.byref(top),
+                            _stream()))
+    return theta, S, top.value
+
+
+def gram(X, nblk: int, bx: int, Y):
+    """C = X^T Y where X holds nblk blocks of width bx (block-major, each a
+    row-major n x bx array) and Y is n x ny; float64 result on the device."""
+    torch = _torch()
+    n, ny = Y.shape
+    lib = load_library()
+    need = lib.bbl_gram_workspace_size(n, bx, nblk, ny)
+    ws = torch.empty(need, dtype=torch.uint8, device=Y.device)
+    C = torch.empty((nblk * bx, ny), dtype=torch.float64, device=Y.device)
+    _check(lib.bbl_gram(n, _ptr(X), _dtype_code(X), bx, nblk, _ptr(Y), _dtype_code(Y), ny, _ptr(C),
+                        _ptr(ws), need, _stream()))
+    return C
+
+
+def block_update(X, nblk: int, bx: int, C, alpha: float, Yin, beta: float, Yout):
+    """Yout = beta*Yin + alpha*X*C (X block-major as in gram)."""
+    n, ny = Yout.shape
+    _check(load_library().bbl_block_update(
+        n, _ptr(X), _dtype_code(X), bx, nblk, _ptr(C), ny, alpha, _ptr(Yin),
+        _dtype_code(Yin) if Yin is not None else BBL_F64, beta, _ptr(Yout), _dtype_code(Yout),
+        _stream()))
+    return Yout

@@ -1,0 +1,89 @@
+// Shared declarations of the bbl HIP library (kernels + host driver).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/bbl.h"
+
+namespace bbl {
+
+// ------------------------------------------------------------- error state
+void set_error(const std::string &msg);
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define BBL_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw ::bbl::Error{BBL_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define BBL_REQUIRE(cond, msg)                               \
+  do {                                                       \
+    if (!(cond)) throw ::bbl::Error{BBL_E_INVALID, (msg)};   \
+  } while (0)
+
+inline void check_launch(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error{BBL_E_HIP, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+constexpr int kMaxBlock = 32;    // largest supported block size / k
+constexpr int kWave = 64;
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------- kernel launchers
+// SpMM: Y = H X (templated on value/vector/accumulator types inside).
+void launch_spmm(const bbl_csr &H, const void *X, int xdtype, void *Y, int ydtype, int nvec,
+                 hipStream_t s);
+// Explicit residual: partial[g][c] = sum over the rows of group g of
+// ((H X)_{r,c} - theta_c X_{r,c})^2, float64 accumulation.  Returns the number
+// of partial rows written.
+int launch_residual_spmm(const bbl_csr &H, const double *X, int nvec, const double *theta,
+                         double *partial, int max_partials, hipStream_t s);
+
+// Tall-skinny products on FP64 MFMA.
+//   X: nblk column blocks of width bx, block b at X + b * xstride (row-major
+//      n x bx each), element type xdtype.  M = nblk * bx columns in total.
+//   Y: n x ny row-major, element type ydtype.
+// gram: partial[p][m][c] = sum over chunk p of X[r][m] * Y[r][c]; returns P.
+int launch_gram(int64_t n, const void *X, int xdtype, int bx, int nblk, int64_t xstride,
+                const void *Y, int ydtype, int ny, double *partial, int max_partials,
+                hipStream_t s);
+// out[m][c] = scale * sum_p partial[p][m][c]   (M x ny)
+void launch_reduce(const double *partial, int P, int M, int ny, double *out, hipStream_t s);
+// Yout = beta * Yin + alpha * X C   (C: M x ny float64, Yout type ydtype)
+void launch_update(int64_t n, const void *X, int xdtype, int bx, int nblk, int64_t xstride,
+                   const double *C, int ny, double alpha, const void *Yin, int yindtype,
+                   double beta, void *Yout, int youtdtype, hipStream_t s);
+
+// Small dense kernels (one workgroup).
+void launch_fill(double *p, int64_t count, double v, hipStream_t s);
+
+// Random normal block (Philox4x32-10 + Box-Muller), entry (i, a) from counter
+// (i, a + col0, tag).
+void launch_gauss(int64_t n, int nvec, int ld, int col0, uint64_t key, uint32_t tag,
+                  double *out, const int32_t *colmask, const int *when, hipStream_t s);
+
+// Variants whose kernels return at once when *when == 0 (device flag), so a
+// data-dependent branch needs no host round trip.
+int launch_gram_when(int64_t n, const void *X, int xdtype, int bx, int nblk, int64_t xstride,
+                     const void *Y, int ydtype, int ny, double *partial, int max_partials,
+                     const int *when, hipStream_t s);
+void launch_reduce_when(const double *partial, int P, int M, int ny, double *out,
+                        const int *when, hipStream_t s);
+void launch_update_when(int64_t n, const void *X, int xdtype, int bx, int nblk, int64_t xstride,
+                        const double *C, int ny, double alpha, const void *Yin, int yindtype,
+                        double beta, void *Yout, int youtdtype, const int *when, hipStream_t s);
+
+}  // namespace bbl

@@ -1,0 +1,572 @@
+// Host driver and C ABI of libbbl.so: non-restarted block Lanczos (Methods,
+// "Block Lanczos algorithm") with a random or bootstrapped pivot block.
+//
+// One iteration J (0-based; block V_{J+1} of the paper is basis slot J):
+//   W   = H V_J                                   (SpMM, basis precision)
+//   A_J = sym(V_J^T W)                            (MFMA gram)
+//   W'  = W - V_J A_J - V_{J-1} B_{J-1}^T         (MFMA update, FP64 out)
+//   W' -= V_{0:J} (V_{0:J}^T W'), twice           (full reorthogonalisation)
+//   W'  = V_{J+1} B_J                             (spectral factor of the
+//         overlap with deflation, then a Cholesky polish; V_{J+1} stored in
+//         basis precision, B_J upper triangular)
+//   every few blocks: lowest Ritz pairs of the band matrix, residual
+//   estimates ||B_J s_last||; when all pass, Ritz vectors and the explicit
+//   FP64 residual decide convergence.
+// Every step runs in HIP kernels on the caller's stream; the host only
+// sequences launches and reads 2k+1 doubles per convergence check.
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "bandeig.h"
+#include "common.h"
+#include "pivot.h"
+#include "small.h"
+
+namespace bbl {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+namespace {
+
+constexpr int kMaxPartialRows = 4096;   // residual / column-statistics partials
+constexpr uint32_t kTagDeflation = 7;
+constexpr int kHn2Slot = 200;          // dres slot: max |A_jj| seen so far (<= ||H||)
+
+size_t dsize(int dt) { return dt == BBL_F32 ? 4 : 8; }
+
+struct Opts {
+  int m_max = 200;
+  int basis_dtype = 0;  // 0: from H
+  int check_every = 0;
+  double tau = 1e-12;
+  uint64_t seed = 0;
+};
+
+Opts read_opts(const bbl_opts *o, int val_dtype) {
+  Opts r;
+  if (o) {
+    if (o->m_max > 0) r.m_max = o->m_max;
+    r.basis_dtype = o->basis_dtype;
+    r.check_every = o->check_every;
+    if (o->defl_tau > 0) r.tau = o->defl_tau;
+    r.seed = o->seed;
+  }
+  if (r.basis_dtype == 0) r.basis_dtype = val_dtype;
+  return r;
+}
+
+struct Layout {
+  size_t basis, W, Wp, X, partial, C, band, Bstore, mats, ints, dres, S, eig, norm, total;
+  size_t partial_doubles;
+  BandEigLayout el;
+};
+
+Layout make_layout(int64_t n, int b, int k, int m_max, int bdt) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  const size_t sx = dsize(bdt);
+  const int64_t Mmax = (int64_t)(m_max + 1) * b;
+  const int nyw = std::max(b, k);
+  L.basis = take((size_t)(m_max + 1) * n * b * sx);
+  L.W = take((size_t)n * b * sx);
+  L.Wp = take((size_t)n * b * 8);
+  L.X = take((size_t)n * k * 8);
+  L.partial_doubles = (size_t)(131072 + 2 * Mmax) * nyw + (size_t)kMaxPartialRows * nyw;
+  L.partial = take(L.partial_doubles * 8);
+  L.C = take((size_t)Mmax * nyw * 8);
+  L.band = take((size_t)(Mmax + b) * (b + 1) * 8);
+  L.Bstore = take((size_t)(m_max + 1) * b * b * 8);
+  L.mats = take((size_t)16 * kMaxBlock * kMaxBlock * 8);
+  L.ints = take(256 * sizeof(int));
+  L.dres = take(256 * 8);
+  L.S = take((size_t)m_max * b * k * 8);
+  L.el = band_eig_layout(m_max * b, b, k);
+  L.eig = take(L.el.bytes);
+  L.norm = take(normalize_scratch_bytes(k, kMaxPartialRows));
+  L.total = off + 256;
+  return L;
+}
+
+void validate_csr(const bbl_csr *H) {
+  BBL_REQUIRE(H != nullptr, "H is NULL");
+  BBL_REQUIRE(H->n >= 1, "H.n must be >= 1");
+  BBL_REQUIRE(H->n <= (int64_t)INT32_MAX, "H.n exceeds int32 column range");
+  BBL_REQUIRE(H->nnz >= 0, "H.nnz must be >= 0");
+  BBL_REQUIRE(H->row_ptr && (H->nnz == 0 || (H->col && H->val)), "H has NULL arrays");
+  BBL_REQUIRE(H->val_dtype == BBL_F32 || H->val_dtype == BBL_F64, "H.val_dtype must be F32/F64");
+  BBL_REQUIRE(H->reserved == 0, "H.reserved must be 0");
+}
+
+struct Solver {
+  const bbl_csr &H;
+  int64_t n;
+  int b, k;
+  double tol;
+  Opts o;
+  hipStream_t s;
+  Layout L;
+  char *ws;
+  int xd;  // basis dtype
+  size_t sx;
+  // regions
+  char *basis;
+  void *W;
+  double *Wp, *X, *partial, *C, *band, *Bstore, *S, *dres;
+  double *Araw, *C3, *O, *C0, *QB, *RB, *O2, *Rinv;
+  int *ints;
+  int *mask, *flag, *breakdown, *ndefl;
+  void *eigws, *normws;
+  int qr_calls = 0;
+
+  Solver(const bbl_csr &H_, int b_, int k_, double tol_, const Opts &o_, void *ws_, size_t bytes,
+         hipStream_t s_)
+      : H(H_), n(H_.n), b(b_), k(k_), tol(tol_), o(o_), s(s_) {
+    xd = o.basis_dtype;
+    sx = dsize(xd);
+    L = make_layout(n, b, k, o.m_max, xd);
+    if (bytes < L.total) throw Error{BBL_E_NOMEM, "workspace too small"};
+    ws = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(ws_), 256));
+    basis = ws + L.basis;
+    W = ws + L.W;
+    Wp = reinterpret_cast<double *>(ws + L.Wp);
+    X = reinterpret_cast<double *>(ws + L.X);
+    partial = reinterpret_cast<double *>(ws + L.partial);
+    C = reinterpret_cast<double *>(ws + L.C);
+    band = reinterpret_cast<double *>(ws + L.band);
+    Bstore = reinterpret_cast<double *>(ws + L.Bstore);
+    S = reinterpret_cast<double *>(ws + L.S);
+    dres = reinterpret_cast<double *>(ws + L.dres);
+    double *m = reinterpret_cast<double *>(ws + L.mats);
+    const int sq = kMaxBlock * kMaxBlock;
+    Araw = m;
+    C3 = m + 1 * sq;  // 2 squares
+    O = m + 3 * sq;
+    C0 = m + 4 * sq;
+    QB = m + 5 * sq;
+    RB = m + 6 * sq;
+    O2 = m + 7 * sq;
+    Rinv = m + 8 * sq;
+    ints = reinterpret_cast<int *>(ws + L.ints);
+    mask = ints;
+    flag = ints + 64;
+    breakdown = ints + 65;
+    ndefl = ints + 66;
+    eigws = ws + L.eig;
+    normws = ws + L.norm;
+  }
+
+  char *slot(int J) const { return basis + (size_t)J * n * b * sx; }
+  int64_t slot_stride() const { return n * b; }
+
+  int max_partials(int M, int ny) const {
+    return (int)std::max<size_t>(1, L.partial_doubles / ((size_t)M * ny));
+  }
+
+  // C (M x ny) = X^T Y with X = nblk basis-type blocks
+  void gram(const void *Xp, int xdt, int bx, int nblk, int64_t xstride, const void *Y, int ydt,
+            int ny, double *out, const int *when = nullptr) {
+    const int M = nblk * bx;
+    const int P = launch_gram_when(n, Xp, xdt, bx, nblk, xstride, Y, ydt, ny, partial,
+                                   max_partials(M, ny), when, s);
+    launch_reduce_when(partial, P, M, ny, out, when, s);
+  }
+
+  // W' -= V_{0:nb-1} (V^T W'), twice
+  void reorth(int nb, double *Y, const int *when = nullptr) {
+    for (int pass = 0; pass < 2; ++pass) {
+      gram(basis, xd, b, nb, slot_stride(), Y, BBL_F64, b, C, when);
+      launch_update_when(n, basis, xd, b, nb, slot_stride(), C, b, -1.0, Y, BBL_F64, 1.0, Y,
+                         BBL_F64, when, s);
+    }
+  }
+
+  // Block QR of Wp into basis slot `dest`; Bout = B (upper triangular).
+  void block_qr(int nbasis, int dest, double *Bout, const double *hnorm_dev) {
+    gram(Wp, BBL_F64, b, 1, 0, Wp, BBL_F64, b, O);
+    launch_svqb_prepare(O, b, o.tau, hnorm_dev, dres + kHn2Slot, C0, QB, RB, mask, flag, ndefl,
+                        s);
+    launch_update(n, Wp, BBL_F64, b, 1, 0, C0, b, 1.0, nullptr, BBL_F64, 0.0, Wp, BBL_F64, s);
+    // deflated columns: fresh random directions, orthogonal to the basis
+    const uint64_t key = (o.seed ^ 0x9E3779B97F4A7C15ull) + 0x5DEECE66Dull * (uint64_t)(qr_calls + 1);
+    launch_gauss(n, b, b, 0, key, kTagDeflation, Wp, mask, flag, s);
+    if (nbasis > 0) reorth(nbasis, Wp, flag);
+    launch_update_when(n, Wp, BBL_F64, b, 1, 0, QB, b, 1.0, nullptr, BBL_F64, 0.0, Wp, BBL_F64,
+                       flag, s);
+    gram(Wp, BBL_F64, b, 1, 0, Wp, BBL_F64, b, O2);
+    launch_chol_finish(O2, b, RB, Rinv, Bout, breakdown, s);
+    launch_update(n, Wp, BBL_F64, b, 1, 0, Rinv, b, 1.0, nullptr, BBL_F64, 0.0, slot(dest), xd,
+                  s);
+    ++qr_calls;
+  }
+
+  struct Result {
+    bool converged = false;
+    int iters = 0, spmm_calls = 0, checks = 0;
+    double hnorm = 0.0;
+    std::vector<double> theta, resid;
+  };
+
+  int check_interval(int N) const {
+    if (o.check_every > 0) return o.check_every;
+    if (N <= 256) return 1;
+    if (N <= 1024) return 2;
+    return 4;
+  }
+
+  // Ritz vectors of the last eigensolve into Xout (n x k), normalised;
+  // returns explicit residual norms.
+  std::vector<double> ritz_and_residual(int nblk, int kk, double *Xout) {
+    launch_update(n, basis, xd, b, nblk, slot_stride(), S, kk, 1.0, nullptr, BBL_F64, 0.0, Xout,
+                  BBL_F64, s);
+    launch_normalize_columns(n, kk, Xout, reinterpret_cast<double *>(normws), kMaxPartialRows, s);
+    const int P = launch_residual_spmm(H, Xout, kk, dres, partial, kMaxPartialRows, s);
+    double *r2 = dres + 128;
+    launch_reduce(partial, P, 1, kk, r2, s);
+    std::vector<double> h(kk);
+    BBL_HIP(hipMemcpyAsync(h.data(), r2, kk * sizeof(double), hipMemcpyDeviceToHost, s));
+    BBL_HIP(hipStreamSynchronize(s));
+    for (auto &v : h) v = std::sqrt(std::max(v, 0.0));
+    return h;
+  }
+
+  Result run(const double *pivot, double *eigvecs_out) {
+    Result R;
+    // zero the band matrix, the B store, counters and results
+    launch_fill(band, (int64_t)(o.m_max * b + b) * (b + 1), 0.0, s);
+    launch_fill(Bstore, (int64_t)(o.m_max + 1) * b * b, 0.0, s);
+    launch_fill(dres, 256, 0.0, s);
+    launch_fill(reinterpret_cast<double *>(ints), 128, 0.0, s);
+    double *hnorm_dev = dres + 2 * k;
+    // V_1 from the pivot
+    BBL_HIP(hipMemcpyAsync(Wp, pivot, (size_t)n * b * 8, hipMemcpyDeviceToDevice, s));
+    block_qr(0, 0, Bstore + (size_t)o.m_max * b * b, hnorm_dev);
+    double *Xout = eigvecs_out ? eigvecs_out : X;
+    int last_checked_nblk = 0;
+    std::vector<double> hres(2 * kMaxBlock + 2);
+    for (int J = 0; J < o.m_max; ++J) {
+      launch_spmm(H, slot(J), xd, W, xd, b, s);
+      ++R.spmm_calls;
+      gram(slot(J), xd, b, 1, 0, W, xd, b, Araw);
+      launch_set_A(Araw, b, J, band, b, J > 0 ? Bstore + (size_t)(J - 1) * b * b : nullptr, C3,
+                   dres + kHn2Slot, s);
+      const int nb3 = J > 0 ? 2 : 1;
+      launch_update(n, slot(J > 0 ? J - 1 : 0), xd, b, nb3, slot_stride(), C3, b, -1.0, W, xd,
+                    1.0, Wp, BBL_F64, s);
+      reorth(J + 1, Wp);
+      double *BJ = Bstore + (size_t)J * b * b;
+      block_qr(J + 1, J + 1, BJ, hnorm_dev);
+      launch_set_B(BJ, b, J, band, b, o.m_max * b, s);
+      R.iters = J + 1;
+      const int N = (J + 1) * b;
+      const bool exhausted = (int64_t)N >= n;
+      const bool last = (J == o.m_max - 1);
+      if (N < k && !exhausted) continue;
+      if (!(exhausted || last || ((J + 1) % check_interval(N)) == 0)) continue;
+      const int kk = std::min(k, N);
+      band_eigensolve(band, N, b, kk, eigws, L.el, BJ, b, S, dres, s);
+      ++R.checks;
+      // keep ||H||_est at a fixed slot for the next QR (res[2kk] -> dres[2k])
+      BBL_HIP(hipMemcpyAsync(hres.data(), dres, (2 * kk + 1) * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+      int hflags[2];
+      BBL_HIP(hipMemcpyAsync(hflags, breakdown, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+      BBL_HIP(hipStreamSynchronize(s));
+      if (hflags[0]) throw Error{BBL_E_BREAKDOWN, "block QR lost rank beyond deflation repair"};
+      if (kk < k) BBL_HIP(hipMemcpyAsync(hnorm_dev, dres + 2 * kk, 8, hipMemcpyDeviceToDevice, s));
+      R.hnorm = hres[2 * kk];
+      last_checked_nblk = J + 1;
+      bool est_ok = true;
+      for (int i = 0; i < kk; ++i) est_ok &= (hres[kk + i] <= tol * R.hnorm);
+      if (exhausted || (kk == k && est_ok) || last) {
+        std::vector<double> r = ritz_and_residual(J + 1, kk, Xout);
+        ++R.spmm_calls;
+        bool ok = kk == k || exhausted;
+        for (int i = 0; i < kk; ++i) ok &= (r[i] <= tol * R.hnorm);
+        R.theta.assign(hres.begin(), hres.begin() + kk);
+        R.resid = r;
+        if (ok || exhausted) {
+          R.converged = true;
+          break;
+        }
+      }
+    }
+    (void)last_checked_nblk;
+    return R;
+  }
+};
+
+int64_t read_row_ptr(const bbl_csr &H, int64_t i, hipStream_t s) {
+  int64_t v = 0;
+  BBL_HIP(hipMemcpyAsync(&v, H.row_ptr + i, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  BBL_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+template <typename F>
+int guarded(F &&f) {
+  try {
+    return f();
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::exception &e) {
+    set_error(e.what());
+    return BBL_E_INVALID;
+  } catch (...) {
+    set_error("unknown error");
+    return BBL_E_INVALID;
+  }
+}
+
+void check_solver_args(const bbl_csr *H, int nvec, int k, const Opts &o) {
+  validate_csr(H);
+  BBL_REQUIRE(nvec >= 1 && nvec <= kMaxBlock, "nvec must be in 1..32");
+  BBL_REQUIRE(k >= 1 && k <= kMaxBlock && (int64_t)k <= H->n, "k_eig must be in 1..min(n, 32)");
+  BBL_REQUIRE(o.m_max >= 1, "m_max must be >= 1");
+  BBL_REQUIRE((int64_t)k <= (int64_t)nvec * o.m_max, "k_eig exceeds nvec * m_max");
+  BBL_REQUIRE(o.basis_dtype == BBL_F32 || o.basis_dtype == BBL_F64, "basis_dtype must be F32/F64");
+  BBL_REQUIRE(!(o.basis_dtype == BBL_F32 && H->val_dtype == BBL_F64),
+              "a float32 basis needs float32 matrix values");
+  BBL_REQUIRE((int64_t)o.m_max * nvec <= 8192, "m_max * nvec must be <= 8192");
+}
+
+int solve_impl(const bbl_csr *H, const double *pivot, int32_t nvec, int32_t k, double tol,
+               void *ws, size_t ws_bytes, const Opts &o, double *eigvals, double *eigvecs,
+               double *residuals, bbl_stats *stats, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  check_solver_args(H, nvec, k, o);
+  BBL_REQUIRE(pivot != nullptr, "pivot is NULL");
+  BBL_REQUIRE(ws != nullptr, "workspace is NULL");
+  BBL_REQUIRE(eigvals != nullptr, "eigvals is NULL");
+  BBL_REQUIRE(tol > 0.0, "tol must be > 0");
+  Solver sv(*H, nvec, k, tol, o, ws, ws_bytes, s);
+  Solver::Result R = sv.run(pivot, eigvecs);
+  for (int i = 0; i < k; ++i) {
+    eigvals[i] = i < (int)R.theta.size() ? R.theta[i] : NAN;
+    if (residuals) residuals[i] = i < (int)R.resid.size() ? R.resid[i] : NAN;
+  }
+  int nd = 0;
+  BBL_HIP(hipMemcpyAsync(&nd, sv.ndefl, sizeof(int), hipMemcpyDeviceToHost, s));
+  BBL_HIP(hipStreamSynchronize(s));
+  if (stats) {
+    stats->iters = R.iters;
+    stats->spmm_calls = R.spmm_calls;
+    stats->deflations = nd;
+    stats->converged = R.converged ? 1 : 0;
+    stats->checks = R.checks;
+    stats->fallbacks = 0;
+    stats->hnorm_est = R.hnorm;
+    stats->t_total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return R.converged ? BBL_OK : BBL_E_NOT_CONVERGED;
+}
+
+struct BootLayout {
+  size_t rp, col, val, piv, inner, total;
+};
+
+BootLayout boot_layout(int64_t n_t, int64_t nnz_t, int b, int m_max, int bdt, int vdt) {
+  BootLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  L.rp = take((size_t)(n_t + 1) * 8);
+  L.col = take((size_t)std::max<int64_t>(nnz_t, 1) * 4);
+  L.val = take((size_t)std::max<int64_t>(nnz_t, 1) * dsize(vdt));
+  L.piv = take((size_t)n_t * b * 8);
+  L.inner = take(make_layout(n_t, b, b, m_max, bdt).total + 256);
+  L.total = off + 256;
+  return L;
+}
+
+}  // namespace
+}  // namespace bbl
+
+using namespace bbl;
+
+extern "C" {
+
+const char *bbl_last_error(void) { return g_last_error.c_str(); }
+
+const char *bbl_version(void) { return "bbl 0.1 (gfx950)"; }
+
+int bbl_spmm(const bbl_csr *H, const void *V, void *W, int32_t nvec, int32_t vec_dtype,
+             void *stream) {
+  return guarded([&] {
+    validate_csr(H);
+    BBL_REQUIRE(V && W, "V/W is NULL");
+    BBL_REQUIRE(V != W, "V and W must not overlap");
+    BBL_REQUIRE(nvec >= 1 && nvec <= kMaxBlock, "nvec must be in 1..32");
+    BBL_REQUIRE(vec_dtype == BBL_F32 || vec_dtype == BBL_F64, "vec_dtype must be F32/F64");
+    BBL_REQUIRE(!(vec_dtype == BBL_F32 && H->val_dtype == BBL_F64),
+                "float32 vectors need float32 matrix values");
+    launch_spmm(*H, V, vec_dtype, W, vec_dtype, nvec, static_cast<hipStream_t>(stream));
+    return (int)BBL_OK;
+  });
+}
+
+size_t bbl_lanczos_workspace_size(int64_t n, int32_t nvec, int32_t k_eig, int32_t m_max,
+                                  int32_t basis_dtype) {
+  if (n < 1 || nvec < 1 || nvec > kMaxBlock || k_eig < 1 || k_eig > kMaxBlock || m_max < 1 ||
+      (basis_dtype != BBL_F32 && basis_dtype != BBL_F64))
+    return 0;
+  return make_layout(n, nvec, k_eig, m_max, basis_dtype).total;
+}
+
+int bbl_block_lanczos(const bbl_csr *H, const double *pivot, int32_t nvec, int32_t k_eig,
+                      double tol, void *ws, size_t ws_bytes, const bbl_opts *opts,
+                      double *eigvals, double *eigvecs, double *residuals, bbl_stats *stats,
+                      void *stream) {
+  return guarded([&] {
+    BBL_REQUIRE(H != nullptr, "H is NULL");
+    const Opts o = read_opts(opts, H->val_dtype);
+    return solve_impl(H, pivot, nvec, k_eig, tol, ws, ws_bytes, o, eigvals, eigvecs, residuals,
+                      stats, static_cast<hipStream_t>(stream));
+  });
+}
+
+size_t bbl_bootstrap_workspace_size(const bbl_csr *H, int64_t n_trunc, int32_t nvec,
+                                    int32_t m_max, int32_t basis_dtype, void *stream) {
+  size_t r = 0;
+  const int st = guarded([&] {
+    validate_csr(H);
+    BBL_REQUIRE(nvec >= 1 && nvec <= kMaxBlock, "nvec must be in 1..32");
+    BBL_REQUIRE(n_trunc >= nvec && n_trunc <= H->n, "n_trunc must be in nvec..n");
+    BBL_REQUIRE(m_max >= 1, "m_max must be >= 1");
+    const int bdt = basis_dtype ? basis_dtype : H->val_dtype;
+    const int64_t nnz_t = read_row_ptr(*H, n_trunc, static_cast<hipStream_t>(stream));
+    r = boot_layout(n_trunc, nnz_t, nvec, m_max, bdt, H->val_dtype).total;
+    return (int)BBL_OK;
+  });
+  return st == BBL_OK ? r : 0;
+}
+
+int bbl_bootstrap_pivot(const bbl_csr *H, int64_t n_trunc, int32_t nvec, double tol, void *ws,
+                        size_t ws_bytes, const bbl_opts *opts, double *pivot, bbl_stats *stats,
+                        void *stream) {
+  return guarded([&] {
+    validate_csr(H);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BBL_REQUIRE(nvec >= 1 && nvec <= kMaxBlock, "nvec must be in 1..32");
+    BBL_REQUIRE(n_trunc >= nvec && n_trunc <= H->n, "n_trunc must be in nvec..n");
+    BBL_REQUIRE(pivot && ws, "pivot/workspace is NULL");
+    Opts o = read_opts(opts, H->val_dtype);
+    const int64_t nnz_t = read_row_ptr(*H, n_trunc, s);
+    const BootLayout L = boot_layout(n_trunc, nnz_t, nvec, o.m_max, o.basis_dtype, H->val_dtype);
+    if (ws_bytes < L.total) throw Error{BBL_E_NOMEM, "bootstrap workspace too small"};
+    char *base = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
+    int64_t *rp_t = reinterpret_cast<int64_t *>(base + L.rp);
+    int32_t *col_t = reinterpret_cast<int32_t *>(base + L.col);
+    void *val_t = base + L.val;
+    double *piv_t = reinterpret_cast<double *>(base + L.piv);
+    launch_slice_leading(*H, n_trunc, rp_t, col_t, val_t, s);
+    bbl_csr Ht{};
+    Ht.n = n_trunc;
+    Ht.nnz = read_row_ptr(bbl_csr{n_trunc, 0, rp_t, nullptr, nullptr, BBL_F64, 0}, n_trunc, s);
+    Ht.row_ptr = rp_t;
+    Ht.col = col_t;
+    Ht.val = val_t;
+    Ht.val_dtype = H->val_dtype;
+    // random pivot of the truncated problem, key (seed + 1) ^ golden ratio
+    const uint64_t key = (o.seed + 1) ^ 0x9E3779B97F4A7C15ull;
+    launch_gauss(n_trunc, nvec, nvec, 0, key, 6, piv_t, nullptr, nullptr, s);
+    std::vector<double> ev(nvec);
+    Opts oi = o;
+    oi.seed = o.seed + 1;
+    const int st = solve_impl(&Ht, piv_t, nvec, nvec, tol, base + L.inner, L.total - L.inner, oi,
+                              ev.data(), pivot, nullptr, stats, s);
+    // zero padding: the truncated basis is a subset of the full one
+    launch_fill(pivot + (size_t)n_trunc * nvec, (H->n - n_trunc) * nvec, 0.0, s);
+    BBL_HIP(hipStreamSynchronize(s));
+    return st;
+  });
+}
+
+int bbl_random_pivot(int64_t n, int32_t nvec, uint64_t key, double *pivot, void *stream) {
+  return guarded([&] {
+    BBL_REQUIRE(n >= 1 && nvec >= 1 && nvec <= kMaxBlock, "bad n/nvec");
+    BBL_REQUIRE(pivot != nullptr, "pivot is NULL");
+    launch_gauss(n, nvec, nvec, 0, key, 6, pivot, nullptr, nullptr,
+                 static_cast<hipStream_t>(stream));
+    return (int)BBL_OK;
+  });
+}
+
+size_t bbl_band_eig_workspace_size(int32_t N, int32_t kd, int32_t k) {
+  if (N < 1 || kd < 1 || kd > kMaxBlock || k < 1 || k > kMaxBlock || k > N || N > 8192) return 0;
+  return band_eig_layout(N, kd, k).bytes + 2 * 256 * 8 + 256;
+}
+
+int bbl_band_eig(const double *band, int32_t N, int32_t kd, int32_t k, void *ws, size_t ws_bytes,
+                 double *theta, double *S, double *top, void *stream) {
+  return guarded([&] {
+    BBL_REQUIRE(band && ws && theta && S, "NULL argument");
+    BBL_REQUIRE(N >= 1 && N <= 8192 && kd >= 1 && kd <= kMaxBlock && k >= 1 &&
+                    k <= std::min(N, kMaxBlock),
+                "bad N/kd/k");
+    const size_t need = bbl_band_eig_workspace_size(N, kd, k);
+    if (ws_bytes < need) throw Error{BBL_E_NOMEM, "band eig workspace too small"};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *base = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
+    double *res = reinterpret_cast<double *>(base);
+    const BandEigLayout L = band_eig_layout(N, kd, k);
+    band_eigensolve(band, N, kd, k, base + 2 * 256 * 8, L, nullptr, kd, S, res, s);
+    std::vector<double> h(2 * k + 2);
+    BBL_HIP(hipMemcpyAsync(h.data(), res, h.size() * 8, hipMemcpyDeviceToHost, s));
+    BBL_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < k; ++i) theta[i] = h[i];
+    if (top) *top = h[2 * k + 1];
+    return (int)BBL_OK;
+  });
+}
+
+size_t bbl_gram_workspace_size(int64_t n, int32_t bx, int32_t nblk, int32_t ny) {
+  if (n < 1 || bx < 1 || nblk < 1 || ny < 1 || ny > kMaxBlock) return 0;
+  const size_t M = (size_t)bx * nblk;
+  return ((size_t)131072 + 2 * M) * ny * 8 + 512;
+}
+
+int bbl_gram(int64_t n, const void *X, int32_t xdtype, int32_t bx, int32_t nblk, const void *Y,
+             int32_t ydtype, int32_t ny, double *C, void *ws, size_t ws_bytes, void *stream) {
+  return guarded([&] {
+    BBL_REQUIRE(X && Y && C && ws, "NULL argument");
+    BBL_REQUIRE(n >= 1 && bx >= 1 && nblk >= 1 && ny >= 1 && ny <= kMaxBlock, "bad sizes");
+    BBL_REQUIRE((xdtype == BBL_F32 || xdtype == BBL_F64) && (ydtype == BBL_F32 || ydtype == BBL_F64),
+                "bad dtype");
+    const size_t need = bbl_gram_workspace_size(n, bx, nblk, ny);
+    if (ws_bytes < need) throw Error{BBL_E_NOMEM, "gram workspace too small"};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double *partial = reinterpret_cast<double *>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
+    const int M = bx * nblk;
+    const int maxp = (int)std::max<size_t>(1, (need - 512) / 8 / ((size_t)M * ny));
+    const int P = launch_gram(n, X, xdtype, bx, nblk, n * bx, Y, ydtype, ny, partial, maxp, s);
+    launch_reduce(partial, P, M, ny, C, s);
+    return (int)BBL_OK;
+  });
+}
+
+int bbl_block_update(int64_t n, const void *X, int32_t xdtype, int32_t bx, int32_t nblk,
+                     const double *C, int32_t ny, double alpha, const void *Yin, int32_t yindtype,
+                     double beta, void *Yout, int32_t youtdtype, void *stream) {
+  return guarded([&] {
+    BBL_REQUIRE(X && C && Yout && (beta == 0.0 || Yin), "NULL argument");
+    BBL_REQUIRE(n >= 1 && bx >= 1 && nblk >= 1 && ny >= 1 && ny <= kMaxBlock, "bad sizes");
+    BBL_REQUIRE(!(X == Yout && nblk != 1), "in-place X == Yout needs nblk == 1");
+    launch_update(n, X, xdtype, bx, nblk, n * bx, C, ny, alpha, Yin, yindtype, beta, Yout,
+                  youtdtype, static_cast<hipStream_t>(stream));
+    return (int)BBL_OK;
+  });
+}
+
+}  // extern "C"

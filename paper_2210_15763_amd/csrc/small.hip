@@ -1,0 +1,284 @@
+// Small dense FP64 kernels of the block recurrence (one workgroup each):
+//  * spectral factorisation of the overlap O = W'^T W' = U Lambda U^T with
+//    deflation of near-singular directions (Methods: B_n = Lambda^{1/2} U^T,
+//    V_{n+1} = W' U Lambda^{-1/2}), followed by a Householder QR of the b x b
+//    factor so the coupling block kept in the band matrix is upper triangular;
+//  * the Cholesky polish of the second pass (CholQR) and the final B_n;
+//  * assembly of A_n (symmetrised) and B_n into the band matrix;
+//  * column norms / sign normalisation of Ritz vectors.
+#include "common.h"
+#include "small.h"
+
+namespace bbl {
+
+namespace {
+
+// Overlap factorisation with deflation.  Writes, all row-major b x b:
+//   C0   : matrix taking W' to the next block's pre-image (see below)
+//   QB,RB: QR of the spectral factor Bsv = Lambda^{1/2} U^T (deflated rows 0)
+//   mask : 1 for a deflated column (to be replaced by a random direction)
+//   flag : 1 if any column was deflated
+// Without deflation C0 = U Lambda^{-1/2} QB, so Y = W' C0 satisfies W' = Y RB.
+// With deflation C0 = U_keep Lambda_keep^{-1/2} (zero deflated columns); the
+// caller fills those columns randomly, orthogonalises them, and applies QB.
+__global__ __launch_bounds__(256) void k_svqb_prepare(const double *__restrict__ O, int b,
+                                                      double tau, const double *hnorm_ptr,
+                                                      const double *hn2_ptr, double *C0,
+                                                      double *QB, double *RB, int *mask,
+                                                      int *flag, int *ndefl_total) {
+  __shared__ double A[kMaxBlock * kMaxBlock], U[kMaxBlock * kMaxBlock];
+  __shared__ double Bs[kMaxBlock * kMaxBlock], Q[kMaxBlock * kMaxBlock];
+  __shared__ double lam[kMaxBlock], sig[kMaxBlock], v[kMaxBlock], sc[4];
+  __shared__ int keep[kMaxBlock];
+  const int t = threadIdx.x;
+  for (int i = t; i < b * b; i += blockDim.x) {
+    const int r = i / b, c = i % b;
+    A[i] = 0.5 * (O[r * b + c] + O[c * b + r]);
+  }
+  __syncthreads();
+  wg_jacobi_eig(A, U, lam, b, sc);
+  if (t == 0) {
+    double smax = 0.0;
+    for (int i = 0; i < b; ++i) {
+      sig[i] = sqrt(fmax(lam[i], 0.0));
+      smax = fmax(smax, sig[i]);
+    }
+    const double hn = fmax(hnorm_ptr ? *hnorm_ptr : 0.0, hn2_ptr ? *hn2_ptr : 0.0);
+    const double thr = tau * fmax(smax, hn);
+    int nd = 0;
+    for (int i = 0; i < b; ++i) {
+      keep[i] = sig[i] > thr ? 1 : 0;
+      nd += 1 - keep[i];
+    }
+    sc[3] = (double)nd;
+  }
+  __syncthreads();
+  const int nd = (int)sc[3];
+  for (int i = t; i < b * b; i += blockDim.x) {
+    const int r = i / b, c = i % b;
+    Bs[i] = keep[r] ? sig[r] * U[c * b + r] : 0.0;       // row r = sigma_r u_r^T
+    A[i] = keep[c] ? U[r * b + c] / sig[c] : 0.0;        // column c = u_c / sigma_c
+  }
+  __syncthreads();
+  wg_householder_qr(Bs, Q, b, v, sc);
+  for (int i = t; i < b * b; i += blockDim.x) {
+    const int r = i / b, c = i % b;
+    double cv;
+    if (nd == 0) {
+      cv = 0.0;
+      for (int m = 0; m < b; ++m) cv += A[r * b + m] * Q[m * b + c];
+    } else {
+      cv = A[i];
+    }
+    C0[i] = cv;
+    QB[i] = Q[i];
+    RB[i] = Bs[i];
+  }
+  if (t < b) mask[t] = keep[t] ? 0 : 1;
+  if (t == 0) {
+    *flag = nd > 0 ? 1 : 0;
+    if (ndefl_total) *ndefl_total += nd;
+  }
+}
+
+// Second pass: O2 = Y^T Y = R2^T R2.  Writes R2^{-1} (upper, row-major) and
+// Bout = R2 RB (upper triangular).  breakdown = 1 if O2 is not positive
+// definite to working precision.
+__global__ __launch_bounds__(64) void k_chol_finish(const double *__restrict__ O2, int b,
+                                                    const double *__restrict__ RB, double *Rinv,
+                                                    double *Bout, int *breakdown) {
+  __shared__ double R[kMaxBlock * kMaxBlock], Ri[kMaxBlock * kMaxBlock];
+  const int t = threadIdx.x;
+  if (t == 0) {
+    int bad = 0;
+    double dmax = 0.0;
+    for (int i = 0; i < b; ++i) dmax = fmax(dmax, O2[i * b + i]);
+    for (int i = 0; i < b * b; ++i) R[i] = 0.0;
+    for (int j = 0; j < b; ++j) {
+      double s = 0.5 * (O2[j * b + j] + O2[j * b + j]);
+      for (int k = 0; k < j; ++k) s -= R[k * b + j] * R[k * b + j];
+      if (!(s > 1e-28 * dmax) || !(dmax > 0.0)) {
+        bad = 1;
+        s = 1.0;
+      }
+      const double rjj = sqrt(s);
+      R[j * b + j] = rjj;
+      for (int c = j + 1; c < b; ++c) {
+        double x = 0.5 * (O2[j * b + c] + O2[c * b + j]);
+        for (int k = 0; k < j; ++k) x -= R[k * b + j] * R[k * b + c];
+        R[j * b + c] = x / rjj;
+      }
+    }
+    // inverse of the upper-triangular R, column by column
+    for (int i = 0; i < b * b; ++i) Ri[i] = 0.0;
+    for (int c = 0; c < b; ++c) {
+      Ri[c * b + c] = 1.0 / R[c * b + c];
+      for (int r = c - 1; r >= 0; --r) {
+        double x = 0.0;
+        for (int m = r + 1; m <= c; ++m) x += R[r * b + m] * Ri[m * b + c];
+        Ri[r * b + c] = -x / R[r * b + r];
+      }
+    }
+    *breakdown = bad;
+  }
+  __syncthreads();
+  for (int i = t; i < b * b; i += blockDim.x) {
+    const int r = i / b, c = i % b;
+    Rinv[i] = Ri[i];
+    double x = 0.0;
+    for (int m = r; m <= c; ++m) x += R[r * b + m] * RB[m * b + c];
+    Bout[i] = (c >= r) ? x : 0.0;
+  }
+}
+
+// A_J = (Araw + Araw^T)/2 into the band (rows J*b..), and the stacked
+// three-term matrix C3 = [B_{J-1}^T ; A_J] (or just A_J when J == 0).
+__global__ void k_set_A(const double *__restrict__ Araw, int b, int J, double *band, int kd,
+                        const double *__restrict__ Bprev, double *C3, double *hn2) {
+  const int t = threadIdx.x;
+  if (t == 0 && hn2) {  // |A_ii| = |v_i^T H v_i| <= ||H||: a lower estimate of the norm
+    double m = *hn2;
+    for (int i = 0; i < b; ++i) m = fmax(m, fabs(Araw[i * b + i]));
+    *hn2 = m;
+  }
+  const int off = (J > 0) ? b : 0;
+  for (int i = t; i < b * b; i += blockDim.x) {
+    const int r = i / b, c = i % b;
+    const double a = 0.5 * (Araw[r * b + c] + Araw[c * b + r]);
+    C3[(off + r) * b + c] = a;
+    if (J > 0) C3[r * b + c] = Bprev[c * b + r];  // (B_{J-1}^T)[r][c]
+    if (c <= r) band[((int64_t)J * b + r) * (kd + 1) + (r - c)] = a;
+  }
+}
+
+// B_J (upper triangular) into the band: T[(J+1)b + r][J b + c] = B[r][c].
+__global__ void k_set_B(const double *__restrict__ B, int b, int J, double *band, int kd,
+                        int nrows_max) {
+  const int t = threadIdx.x;
+  for (int i = t; i < b * b; i += blockDim.x) {
+    const int r = i / b, c = i % b;
+    const int row = (J + 1) * b + r;
+    const int d = b + r - c;
+    if (row < nrows_max && d >= 1 && d <= kd) band[(int64_t)row * (kd + 1) + d] = B[i];
+  }
+}
+
+// Column statistics of an n x k row-major block: per workgroup partial sum of
+// squares and the first index of the largest |x|.
+__global__ __launch_bounds__(256) void k_colstats(int64_t n, int k, const double *__restrict__ X,
+                                                  double *sumsq, double *amax, int64_t *aidx) {
+  __shared__ double s_sq[256];
+  __shared__ double s_am[256];
+  __shared__ int64_t s_ix[256];
+  for (int c = 0; c < k; ++c) {
+    double sq = 0.0, am = -1.0;
+    int64_t ix = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+      const double x = X[i * k + c];
+      sq = fma(x, x, sq);
+      if (fabs(x) > am) {
+        am = fabs(x);
+        ix = i;
+      }
+    }
+    s_sq[threadIdx.x] = sq;
+    s_am[threadIdx.x] = am;
+    s_ix[threadIdx.x] = ix;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        s_sq[threadIdx.x] += s_sq[threadIdx.x + w];
+        const double a2 = s_am[threadIdx.x + w];
+        const int64_t i2 = s_ix[threadIdx.x + w];
+        if (a2 > s_am[threadIdx.x] || (a2 == s_am[threadIdx.x] && i2 < s_ix[threadIdx.x])) {
+          s_am[threadIdx.x] = a2;
+          s_ix[threadIdx.x] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      sumsq[(int64_t)blockIdx.x * k + c] = s_sq[0];
+      amax[(int64_t)blockIdx.x * k + c] = s_am[0];
+      aidx[(int64_t)blockIdx.x * k + c] = s_ix[0];
+    }
+    __syncthreads();
+  }
+}
+
+// factor[c] = sign(x[argmax|x|, c]) / ||x_c||
+__global__ void k_colfinish(int P, int k, const double *sumsq, const double *amax,
+                            const int64_t *aidx, const double *__restrict__ X, double *factor) {
+  const int c = threadIdx.x;
+  if (c >= k) return;
+  double sq = 0.0, am = -1.0;
+  int64_t ix = 0;
+  for (int p = 0; p < P; ++p) {
+    sq += sumsq[(int64_t)p * k + c];
+    const double a2 = amax[(int64_t)p * k + c];
+    const int64_t i2 = aidx[(int64_t)p * k + c];
+    if (a2 > am || (a2 == am && i2 < ix)) {
+      am = a2;
+      ix = i2;
+    }
+  }
+  const double sgn = X[ix * k + c] < 0.0 ? -1.0 : 1.0;
+  factor[c] = sq > 0.0 ? sgn / sqrt(sq) : 1.0;
+}
+
+__global__ void k_colscale(int64_t n, int k, double *X, const double *factor) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n * k;
+       i += (int64_t)gridDim.x * blockDim.x)
+    X[i] *= factor[i % k];
+}
+
+}  // namespace
+
+void launch_svqb_prepare(const double *O, int b, double tau, const double *hnorm_ptr,
+                         const double *hn2_ptr, double *C0, double *QB, double *RB, int *mask,
+                         int *flag, int *ndefl_total, hipStream_t s) {
+  hipLaunchKernelGGL(k_svqb_prepare, dim3(1), dim3(256), 0, s, O, b, tau, hnorm_ptr, hn2_ptr, C0,
+                     QB, RB, mask, flag, ndefl_total);
+  check_launch("k_svqb_prepare");
+}
+
+void launch_chol_finish(const double *O2, int b, const double *RB, double *Rinv, double *Bout,
+                        int *breakdown, hipStream_t s) {
+  hipLaunchKernelGGL(k_chol_finish, dim3(1), dim3(64), 0, s, O2, b, RB, Rinv, Bout, breakdown);
+  check_launch("k_chol_finish");
+}
+
+void launch_set_A(const double *Araw, int b, int J, double *band, int kd, const double *Bprev,
+                  double *C3, double *hn2, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_A, dim3(1), dim3(256), 0, s, Araw, b, J, band, kd, Bprev, C3, hn2);
+  check_launch("k_set_A");
+}
+
+void launch_set_B(const double *B, int b, int J, double *band, int kd, int nrows_max,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_set_B, dim3(1), dim3(256), 0, s, B, b, J, band, kd, nrows_max);
+  check_launch("k_set_B");
+}
+
+void launch_normalize_columns(int64_t n, int k, double *X, double *scratch, int max_partials,
+                              hipStream_t s) {
+  const int P = (int)std::max<int64_t>(1, std::min<int64_t>(max_partials, ceil_div(n, 256)));
+  double *sumsq = scratch;
+  double *amax = sumsq + (size_t)P * k;
+  int64_t *aidx = reinterpret_cast<int64_t *>(amax + (size_t)P * k);
+  double *factor = reinterpret_cast<double *>(aidx + (size_t)P * k);
+  hipLaunchKernelGGL(k_colstats, dim3(P), dim3(256), 0, s, n, k, X, sumsq, amax, aidx);
+  check_launch("k_colstats");
+  hipLaunchKernelGGL(k_colfinish, dim3(1), dim3(64), 0, s, P, k, sumsq, amax, aidx, X, factor);
+  check_launch("k_colfinish");
+  const int64_t grid = std::min<int64_t>(4096, ceil_div(n * k, 256));
+  hipLaunchKernelGGL(k_colscale, dim3((unsigned)grid), dim3(256), 0, s, n, k, X, factor);
+  check_launch("k_colscale");
+}
+
+size_t normalize_scratch_bytes(int k, int max_partials) {
+  return (size_t)max_partials * k * (8 + 8 + 8) + (size_t)k * 8 + 256;
+}
+
+}  // namespace bbl

@@ -1,0 +1,294 @@
+// CSR block SpMM  W = H V  (w_{a,i} = sum_j H_ij v_{a,j}; Methods, "Block
+// Lanczos algorithm").  The block index a is innermost, as in the paper, so
+// each matrix element (value + column) is streamed from HBM once per block of
+// vectors; on the GPU the loop over a lives in registers of one lane.
+//
+// Mapping: LPR lanes of a 64-wide wavefront share one row; each lane takes
+// every LPR-th element of the row (coalesced reads of col/val), gathers the
+// whole row of V for that column with vector loads, and accumulates nvec
+// partial sums; a butterfly over the LPR lanes finishes the row.  Rows are
+// independent, no atomics, so results are bitwise reproducible.
+#include "common.h"
+
+namespace bbl {
+namespace {
+
+template <typename T, int B>
+struct RowIO {
+  // loads B consecutive elements starting at p (p aligned to sizeof(T)*B's
+  // largest power-of-two divisor up to 16 bytes)
+  __device__ __forceinline__ static void load(const T *__restrict__ p, T (&v)[B]) {
+    constexpr int bytes = (int)sizeof(T) * B;
+    if constexpr (bytes % 16 == 0) {
+      constexpr int nv = bytes / 16;
+      const uint4 *q = reinterpret_cast<const uint4 *>(p);
+      uint4 tmp[nv];
+#pragma unroll
+      for (int i = 0; i < nv; ++i) tmp[i] = q[i];
+      __builtin_memcpy(v, tmp, bytes);
+    } else if constexpr (bytes % 8 == 0) {
+      constexpr int nv = bytes / 8;
+      const uint2 *q = reinterpret_cast<const uint2 *>(p);
+      uint2 tmp[nv];
+#pragma unroll
+      for (int i = 0; i < nv; ++i) tmp[i] = q[i];
+      __builtin_memcpy(v, tmp, bytes);
+    } else {
+#pragma unroll
+      for (int i = 0; i < B; ++i) v[i] = p[i];
+    }
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ T ldg_stream(const T *p) {
+  return __builtin_nontemporal_load(p);
+}
+
+template <typename VT, typename XT, typename AT, typename YT, int B, int LPR>
+__global__ __launch_bounds__(256) void k_spmm(int64_t n, const int64_t *__restrict__ rp,
+                                              const int32_t *__restrict__ col,
+                                              const VT *__restrict__ val,
+                                              const XT *__restrict__ X, YT *__restrict__ Y) {
+  constexpr int RPW = kWave / LPR;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int sub = lane & (LPR - 1);
+  const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int64_t row = wave_id * RPW + lane / LPR;
+  AT acc[B];
+#pragma unroll
+  for (int a = 0; a < B; ++a) acc[a] = AT(0);
+  if (row < n) {
+    const int64_t p0 = rp[row], p1 = rp[row + 1];
+    int64_t p = p0 + sub;
+    // two independent gathers in flight per lane
+    for (; p + LPR < p1; p += 2 * LPR) {
+      const int c0 = ldg_stream(col + p);
+      const int c1 = ldg_stream(col + p + LPR);
+      const AT h0 = (AT)ldg_stream(val + p);
+      const AT h1 = (AT)ldg_stream(val + p + LPR);
+      XT x0[B], x1[B];
+      RowIO<XT, B>::load(X + (int64_t)c0 * B, x0);
+      RowIO<XT, B>::load(X + (int64_t)c1 * B, x1);
+#pragma unroll
+      for (int a = 0; a < B; ++a) acc[a] = fma(h0, (AT)x0[a], acc[a]);
+#pragma unroll
+      for (int a = 0; a < B; ++a) acc[a] = fma(h1, (AT)x1[a], acc[a]);
+    }
+    if (p < p1) {
+      const int c0 = ldg_stream(col + p);
+      const AT h0 = (AT)ldg_stream(val + p);
+      XT x0[B];
+      RowIO<XT, B>::load(X + (int64_t)c0 * B, x0);
+#pragma unroll
+      for (int a = 0; a < B; ++a) acc[a] = fma(h0, (AT)x0[a], acc[a]);
+    }
+  }
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) {
+#pragma unroll
+    for (int a = 0; a < B; ++a) acc[a] += __shfl_xor(acc[a], off, LPR);
+  }
+  if (row < n) {
+    // lane `sub` stores column `sub` (coalesced), looping for B > LPR
+#pragma unroll
+    for (int a0 = 0; a0 < B; a0 += LPR) {
+      AT v = acc[0];
+#pragma unroll
+      for (int a = 1; a < B; ++a)
+        if (a == a0 + sub) v = acc[a];
+      if (a0 + sub < B) Y[row * B + a0 + sub] = (YT)v;
+    }
+  }
+}
+
+// Generic width (runtime nvec <= 32), used for block sizes without a
+// dedicated instantiation.
+template <typename VT, typename XT, typename AT, typename YT, int LPR>
+__global__ __launch_bounds__(256) void k_spmm_generic(int64_t n, const int64_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ col,
+                                                      const VT *__restrict__ val,
+                                                      const XT *__restrict__ X,
+                                                      YT *__restrict__ Y, int nvec) {
+  constexpr int RPW = kWave / LPR;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int sub = lane & (LPR - 1);
+  const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int64_t row = wave_id * RPW + lane / LPR;
+  AT acc[kMaxBlock];
+#pragma unroll
+  for (int a = 0; a < kMaxBlock; ++a) acc[a] = AT(0);
+  if (row < n) {
+    const int64_t p0 = rp[row], p1 = rp[row + 1];
+    for (int64_t p = p0 + sub; p < p1; p += LPR) {
+      const int c = ldg_stream(col + p);
+      const AT h = (AT)ldg_stream(val + p);
+      const XT *x = X + (int64_t)c * nvec;
+#pragma unroll
+      for (int a = 0; a < kMaxBlock; ++a)
+        if (a < nvec) acc[a] = fma(h, (AT)x[a], acc[a]);
+    }
+  }
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) {
+#pragma unroll
+    for (int a = 0; a < kMaxBlock; ++a) acc[a] += __shfl_xor(acc[a], off, LPR);
+  }
+  if (row < n && sub == 0) {
+#pragma unroll
+    for (int a = 0; a < kMaxBlock; ++a)
+      if (a < nvec) Y[row * nvec + a] = (YT)acc[a];
+  }
+}
+
+// Explicit FP64 residual: per workgroup g, partial[g][c] = sum over its rows of
+// ((H X)_{r,c} - theta_c X_{r,c})^2.  Grid-stride over rows, fixed order.
+template <typename VT, int LPR>
+__global__ __launch_bounds__(256) void k_residual(int64_t n, const int64_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ col,
+                                                  const VT *__restrict__ val,
+                                                  const double *__restrict__ X, int nvec,
+                                                  const double *__restrict__ theta,
+                                                  double *__restrict__ partial) {
+  constexpr int RPW = kWave / LPR;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int sub = lane & (LPR - 1);
+  const int wave = threadIdx.x / kWave;
+  __shared__ double red[4][kMaxBlock];
+  double sq[kMaxBlock];
+#pragma unroll
+  for (int a = 0; a < kMaxBlock; ++a) sq[a] = 0.0;
+  const int64_t rows_per_wg = (int64_t)RPW * (blockDim.x / kWave);
+  for (int64_t base = (int64_t)blockIdx.x * rows_per_wg; base < n;
+       base += (int64_t)gridDim.x * rows_per_wg) {
+    const int64_t row = base + (int64_t)wave * RPW + lane / LPR;
+    double acc[kMaxBlock];
+#pragma unroll
+    for (int a = 0; a < kMaxBlock; ++a) acc[a] = 0.0;
+    if (row < n) {
+      for (int64_t p = rp[row] + sub; p < rp[row + 1]; p += LPR) {
+        const int c = col[p];
+        const double h = (double)val[p];
+        const double *x = X + (int64_t)c * nvec;
+#pragma unroll
+        for (int a = 0; a < kMaxBlock; ++a)
+          if (a < nvec) acc[a] = fma(h, x[a], acc[a]);
+      }
+    }
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) {
+#pragma unroll
+      for (int a = 0; a < kMaxBlock; ++a) acc[a] += __shfl_xor(acc[a], off, LPR);
+    }
+    if (row < n && sub == 0) {
+#pragma unroll
+      for (int a = 0; a < kMaxBlock; ++a) {
+        if (a < nvec) {
+          const double r = acc[a] - theta[a] * X[row * nvec + a];
+          sq[a] = fma(r, r, sq[a]);
+        }
+      }
+    }
+  }
+  // reduce sq over the lanes holding rows (sub == 0 lanes), then over waves
+#pragma unroll
+  for (int off = LPR; off < kWave; off <<= 1) {
+#pragma unroll
+    for (int a = 0; a < kMaxBlock; ++a) sq[a] += __shfl_xor(sq[a], off, kWave);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int a = 0; a < kMaxBlock; ++a) red[wave][a] = sq[a];
+  }
+  __syncthreads();
+  if (threadIdx.x < nvec) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) s += red[w][threadIdx.x];
+    partial[(int64_t)blockIdx.x * nvec + threadIdx.x] = s;
+  }
+}
+
+int pick_lpr(const bbl_csr &H) {
+  const double z = H.n > 0 ? (double)H.nnz / (double)H.n : 0.0;
+  if (z < 40.0) return 16;
+  if (z < 96.0) return 32;
+  return 64;
+}
+
+template <typename VT, typename XT, typename AT, typename YT, int LPR>
+void spmm_dispatch_b(const bbl_csr &H, const XT *X, YT *Y, int nvec, hipStream_t s) {
+  const int rows_per_wg = (256 / kWave) * (kWave / LPR);
+  const int64_t grid = ceil_div(H.n, rows_per_wg);
+  const VT *val = static_cast<const VT *>(H.val);
+#define BBL_SPMM_CASE(BV)                                                                        \
+  case BV:                                                                                       \
+    hipLaunchKernelGGL((k_spmm<VT, XT, AT, YT, BV, LPR>), dim3(grid), dim3(256), 0, s, H.n,     \
+                       H.row_ptr, H.col, val, X, Y);                                             \
+    break;
+  switch (nvec) {
+    BBL_SPMM_CASE(1)
+    BBL_SPMM_CASE(2)
+    BBL_SPMM_CASE(4)
+    BBL_SPMM_CASE(8)
+    BBL_SPMM_CASE(10)
+    BBL_SPMM_CASE(16)
+    default:
+      hipLaunchKernelGGL((k_spmm_generic<VT, XT, AT, YT, LPR>), dim3(grid), dim3(256), 0, s, H.n,
+                         H.row_ptr, H.col, val, X, Y, nvec);
+  }
+#undef BBL_SPMM_CASE
+  check_launch("k_spmm");
+}
+
+template <typename VT, typename XT, typename AT, typename YT>
+void spmm_dispatch(const bbl_csr &H, const XT *X, YT *Y, int nvec, hipStream_t s) {
+  switch (pick_lpr(H)) {
+    case 16: spmm_dispatch_b<VT, XT, AT, YT, 16>(H, X, Y, nvec, s); break;
+    case 32: spmm_dispatch_b<VT, XT, AT, YT, 32>(H, X, Y, nvec, s); break;
+    default: spmm_dispatch_b<VT, XT, AT, YT, 64>(H, X, Y, nvec, s); break;
+  }
+}
+
+}  // namespace
+
+void launch_spmm(const bbl_csr &H, const void *X, int xdtype, void *Y, int ydtype, int nvec,
+                 hipStream_t s) {
+  if (H.n == 0) return;
+  if (H.val_dtype == BBL_F32 && xdtype == BBL_F32 && ydtype == BBL_F32) {
+    spmm_dispatch<float, float, float, float>(H, static_cast<const float *>(X),
+                                              static_cast<float *>(Y), nvec, s);
+  } else if (H.val_dtype == BBL_F64 && xdtype == BBL_F64 && ydtype == BBL_F64) {
+    spmm_dispatch<double, double, double, double>(H, static_cast<const double *>(X),
+                                                  static_cast<double *>(Y), nvec, s);
+  } else if (H.val_dtype == BBL_F32 && xdtype == BBL_F64 && ydtype == BBL_F64) {
+    spmm_dispatch<float, double, double, double>(H, static_cast<const double *>(X),
+                                                 static_cast<double *>(Y), nvec, s);
+  } else {
+    throw Error{BBL_E_INVALID, "spmm: unsupported dtype combination"};
+  }
+}
+
+int launch_residual_spmm(const bbl_csr &H, const double *X, int nvec, const double *theta,
+                         double *partial, int max_partials, hipStream_t s) {
+  const int lpr = pick_lpr(H);
+  const int rows_per_wg = (256 / kWave) * (kWave / lpr);
+  int grid = (int)std::min<int64_t>(ceil_div(H.n, rows_per_wg), max_partials);
+  if (grid < 1) grid = 1;
+#define BBL_RES(VT, L)                                                                        \
+  hipLaunchKernelGGL((k_residual<VT, L>), dim3(grid), dim3(256), 0, s, H.n, H.row_ptr, H.col, \
+                     static_cast<const VT *>(H.val), X, nvec, theta, partial)
+  if (H.val_dtype == BBL_F32) {
+    if (lpr == 16) BBL_RES(float, 16);
+    else if (lpr == 32) BBL_RES(float, 32);
+    else BBL_RES(float, 64);
+  } else {
+    if (lpr == 16) BBL_RES(double, 16);
+    else if (lpr == 32) BBL_RES(double, 32);
+    else BBL_RES(double, 64);
+  }
+#undef BBL_RES
+  check_launch("k_residual");
+  return grid;
+}
+
+}  // namespace bbl

@@ -1,0 +1,86 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2210_15763_amd as bbl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "bbl.h")).read()
+    return sorted(set(re.findall(r"\b(bbl_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert sorted(bbl.EXPORTS) == declared_symbols()
+
+
+def test_library_exports_every_declared_symbol():
+    lib = bbl.load_library()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    assert b"gfx950" in lib.bbl_version()
+
+
+def test_workspace_queries_validate_arguments():
+    lib = bbl.load_library()
+    assert lib.bbl_lanczos_workspace_size(0, 4, 4, 10, bbl.BBL_F64) == 0
+    assert lib.bbl_lanczos_workspace_size(100, 0, 4, 10, bbl.BBL_F64) == 0
+    assert lib.bbl_lanczos_workspace_size(100, 33, 4, 10, bbl.BBL_F64) == 0
+    assert lib.bbl_lanczos_workspace_size(100, 4, 4, 10, 7) == 0
+    s64 = lib.bbl_lanczos_workspace_size(20000, 4, 4, 200, bbl.BBL_F64)
+    s32 = lib.bbl_lanczos_workspace_size(20000, 4, 4, 200, bbl.BBL_F32)
+    # the basis dominates: (m_max + 1) * n * b * sizeof
+    assert s64 > 201 * 20000 * 4 * 8 and s32 > 201 * 20000 * 4 * 4 and s64 > s32
+    assert lib.bbl_band_eig_workspace_size(100, 4, 200) == 0
+    assert lib.bbl_gram_workspace_size(100, 8, 2, 33) == 0
+
+
+def test_null_and_bad_arguments_are_rejected_without_a_device():
+    lib = bbl.load_library()
+    assert lib.bbl_spmm(None, None, None, 4, bbl.BBL_F64, None) == bbl.BBL_E_INVALID
+    assert b"NULL" in lib.bbl_last_error()
+    H = bbl._Csr(0, 0, 0, 0, 0, bbl.BBL_F64, 0)
+    assert lib.bbl_spmm(ctypes.byref(H), None, None, 4, bbl.BBL_F64, None) == bbl.BBL_E_INVALID
+    H = bbl._Csr(10, 0, 1, 1, 1, 9, 0)  # bad dtype
+    assert lib.bbl_spmm(ctypes.byref(H), 1, 2, 4, bbl.BBL_F64, None) == bbl.BBL_E_INVALID
+    H = bbl._Csr(10, 5, 1, 1, 1, bbl.BBL_F64, 0)
+    # float32 vectors with float64 values
+    assert lib.bbl_spmm(ctypes.byref(H), 1, 2, 4, bbl.BBL_F32, None) == bbl.BBL_E_INVALID
+    # nvec out of range
+    assert lib.bbl_spmm(ctypes.byref(H), 1, 2, 40, bbl.BBL_F64, None) == bbl.BBL_E_INVALID
+    ev = np.zeros(4)
+    # k > nvec * m_max
+    o = bbl._Opts(1, bbl.BBL_F64, 0, 0, 1e-12, 0)
+    assert lib.bbl_block_lanczos(ctypes.byref(H), 1, 2, 4, 1e-8, 1, 1 << 30, ctypes.byref(o),
+                                 ev.ctypes.data_as(ctypes.c_void_p), None, None, None,
+                                 None) == bbl.BBL_E_INVALID
+    # float32 basis with float64 values
+    o = bbl._Opts(10, bbl.BBL_F32, 0, 0, 1e-12, 0)
+    assert lib.bbl_block_lanczos(ctypes.byref(H), 1, 2, 2, 1e-8, 1, 1 << 30, ctypes.byref(o),
+                                 ev.ctypes.data_as(ctypes.c_void_p), None, None, None,
+                                 None) == bbl.BBL_E_INVALID
+    # workspace smaller than the query -> NOMEM (checked before any launch)
+    o = bbl._Opts(10, bbl.BBL_F64, 0, 0, 1e-12, 0)
+    assert lib.bbl_block_lanczos(ctypes.byref(H), 1, 2, 2, 1e-8, 1, 16, ctypes.byref(o),
+                                 ev.ctypes.data_as(ctypes.c_void_p), None, None, None,
+                                 None) == bbl.BBL_E_NOMEM
+    assert lib.bbl_random_pivot(0, 4, 1, 1, None) == bbl.BBL_E_INVALID
+    assert lib.bbl_block_update(10, None, 2, 4, 1, None, 4, 1.0, None, 2, 0.0, None, 2,
+                                None) == bbl.BBL_E_INVALID
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    saved = bbl._lib
+    bbl._lib = None
+    try:
+        with pytest.raises(RuntimeError, match="libbbl.so not found"):
+            bbl.load_library(str(tmp_path / "missing.so"))
+    finally:
+        bbl._lib = saved

@@ -1,0 +1,308 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Floating-point bars:
+  * SpMM: elementwise |W_gpu - W_ref| <= gamma_{z_i + 2} (|H| |V|)_i, the
+    standard forward-error bound of a length-z_i dot product (u = 2^-53 for
+    float64, 2^-24 for float32 accumulation), with W_ref the exact product of
+    the same (rounded) inputs computed by the oracle;
+  * tall-skinny products and the band eigensolver: FP64 results within a small
+    multiple of n * u of numpy;
+  * eigenvalues: 1e-10 relative on the float64 path, 1e-5 relative on the
+    float32 path (against the oracle on the float32-rounded matrix);
+  * residuals ||H x - theta x|| <= tol * ||H||_est, recomputed on the host.
+"""
+import numpy as np
+import pytest
+
+import synthgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+U32 = 2.0 ** -24
+
+
+def note(msg):
+    print("[case] " + msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def bbl(torch):
+    import paper_2210_15763_amd as m
+    m.load_library()
+    return m
+
+
+def gamma(m, u):
+    return m * u / (1 - m * u)
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+# ------------------------------------------------------------------- SpMM
+@pytest.mark.parametrize("nvec", [1, 3, 4, 8, 10, 16, 32])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_spmm_matches_oracle_within_dot_product_bound(torch, bbl, nvec, prec):
+    note("spmm n=20000 z~40 nvec=%d %s" % (nvec, prec))
+    H = synthgen.generate(20000, 400, 20, 0.7, 11)
+    V = synthgen.gaussian_block(H.n, nvec, 5)
+    if prec == "f32":
+        V = V.astype(np.float32).astype(np.float64)
+        Href = H.as_float32_values()
+        Hd = bbl.DeviceCSR.from_host(H, "float32")
+        Vd = dev(torch, V.astype(np.float32))
+        u = U32
+    else:
+        Href = H
+        Hd = bbl.DeviceCSR.from_host(H, "float64")
+        Vd = dev(torch, V)
+        u = U64
+    W = bbl.spmm(Hd, Vd).double().cpu().numpy()
+    ref = oracle.spmm(Href, V)
+    scale = oracle.spmm_abs(Href, V)
+    z = np.diff(H.row_ptr)[:, None]
+    bound = gamma(z + 2, u) * scale + 1e-300
+    assert np.all(np.abs(W - ref) <= bound), np.max(np.abs(W - ref) / bound)
+
+
+def test_spmm_ragged_rows_and_empty_rows(torch, bbl):
+    note("spmm ragged/empty rows")
+    rng = np.random.default_rng(0)
+    n = 3001
+    lens = rng.integers(0, 300, n)
+    lens[::17] = 0
+    lens[5] = 1000
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum(lens)
+    col = np.concatenate([np.sort(rng.choice(n, size=l, replace=False)) for l in lens]).astype(np.int32)
+    val = rng.standard_normal(rp[-1])
+    H = synthgen.CSR(n, rp, col, val)
+    V = rng.standard_normal((n, 8))
+    W = bbl.spmm(bbl.DeviceCSR.from_host(H, "float64"), dev(torch, V)).cpu().numpy()
+    ref = oracle.spmm(H, V)
+    bound = gamma(lens[:, None] + 2, U64) * oracle.spmm_abs(H, V) + 1e-300
+    assert np.all(np.abs(W - ref) <= bound)
+    assert np.all(W[lens == 0] == 0.0)
+
+
+def test_spmm_bitwise_reproducible(torch, bbl):
+    note("spmm reproducibility")
+    H = synthgen.generate(40000, 1000, 50, 0.7, 3)
+    Hd = bbl.DeviceCSR.from_host(H, "float32")
+    V = dev(torch, synthgen.gaussian_block(H.n, 8, 1).astype(np.float32))
+    a = bbl.spmm(Hd, V).cpu().numpy()
+    b = bbl.spmm(Hd, V).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------- tall-skinny products
+@pytest.mark.parametrize("bx,nblk,ny,xf32", [(8, 3, 8, True), (16, 2, 16, True), (4, 5, 4, False),
+                                             (10, 3, 10, True), (8, 1, 20, False),
+                                             (8, 7, 8, False)])
+def test_gram_and_update_match_numpy(torch, bbl, bx, nblk, ny, xf32):
+    note("gram/update bx=%d nblk=%d ny=%d f32=%s" % (bx, nblk, ny, xf32))
+    rng = np.random.default_rng(bx * 100 + nblk)
+    n = 5003  # several tiles plus a ragged tail
+    Xb = rng.standard_normal((nblk, n, bx))
+    if xf32:
+        Xb = Xb.astype(np.float32).astype(np.float64)
+    Y = rng.standard_normal((n, ny))
+    Xd = dev(torch, Xb.astype(np.float32) if xf32 else Xb)
+    Yd = dev(torch, Y)
+    Xwide = np.concatenate(list(Xb), axis=1)  # n x (nblk*bx)
+    C = bbl.gram(Xd, nblk, bx, Yd).cpu().numpy()
+    Cref = Xwide.T @ Y
+    assert np.max(np.abs(C - Cref)) <= 64 * n * U64 * np.max(np.abs(Xwide).T @ np.abs(Y))
+    Cm = rng.standard_normal((nblk * bx, ny))
+    Out = torch.empty_like(Yd)
+    bbl.block_update(Xd, nblk, bx, dev(torch, Cm), -1.0, Yd, 1.0, Out)
+    ref = Y - Xwide @ Cm
+    tol = 64 * nblk * bx * U64 * (np.abs(Y) + np.abs(Xwide) @ np.abs(Cm))
+    assert np.all(np.abs(Out.cpu().numpy() - ref) <= tol)
+    # beta = 0 and float32 output
+    Out32 = torch.empty((n, ny), dtype=torch.float32, device="cuda")
+    bbl.block_update(Xd, nblk, bx, dev(torch, Cm), 1.0, None, 0.0, Out32)
+    np.testing.assert_allclose(Out32.double().cpu().numpy(), Xwide @ Cm, rtol=2e-6, atol=2e-6 * np.abs(Xwide @ Cm).max())
+
+
+# ---------------------------------------------------------- band eigensolver
+def band_from_dense(T, kd):
+    N = T.shape[0]
+    band = np.zeros((N, kd + 1))
+    for d in range(kd + 1):
+        band[d:, d] = np.diagonal(T, -d)
+    return band
+
+
+@pytest.mark.parametrize("N,kd,k", [(200, 4, 10), (640, 8, 10), (333, 16, 12), (40, 8, 32),
+                                    (17, 4, 17)])
+def test_band_eig_matches_dense_eigh(torch, bbl, N, kd, k):
+    note("band eig N=%d kd=%d k=%d" % (N, kd, k))
+    rng = np.random.default_rng(N + kd)
+    T = np.zeros((N, N))
+    for d in range(kd + 1):
+        v = rng.standard_normal(N - d) * (3.0 if d == 0 else 1.0)
+        T += np.diag(v, -d) + (np.diag(v, d) if d else 0)
+    T += np.diag(np.linspace(-20, 20, N))
+    lam, S = np.linalg.eigh(T)
+    theta, Sg, top = bbl.band_eig(dev(torch, band_from_dense(T, kd)), N, kd, k)
+    nrm = max(abs(lam[0]), abs(lam[-1]))
+    np.testing.assert_allclose(theta, lam[:k], rtol=0, atol=1e-12 * nrm)
+    assert abs(top - lam[-1]) <= 1e-12 * nrm
+    Sg = Sg.cpu().numpy()
+    assert np.max(np.linalg.norm(T @ Sg - Sg * theta, axis=0)) <= 1e-11 * nrm
+    assert np.max(np.abs(Sg.T @ Sg - np.eye(k))) <= 1e-12
+
+
+def test_band_eig_on_lanczos_band_matrix(torch, bbl):
+    note("band eig on an oracle block-Lanczos band matrix")
+    H = synthgen.generate(20000, 400, 20, 0.7, 0)
+    P = synthgen.gaussian_block(H.n, 4, 3)
+    res = oracle.block_lanczos(H, P, 4, 1e-300, 60, keep=True)
+    from oracle.lanczos import band_matrix
+    T = band_matrix(res.A, res.B[:len(res.A) - 1])
+    lam = np.linalg.eigvalsh(T)
+    theta, Sg, top = bbl.band_eig(dev(torch, band_from_dense(T, 7)), T.shape[0], 7, 10)
+    np.testing.assert_allclose(theta, lam[:10], rtol=0, atol=1e-12 * abs(lam[0]))
+
+
+# ---------------------------------------------------------------- pivots
+def test_random_pivot_matches_generator_stream(torch, bbl):
+    note("random pivot")
+    key = synthgen.pivot_key(7)
+    g = bbl.random_pivot(100003, 8, key).cpu().numpy()
+    ref = synthgen.gaussian_block(100003, 8, key)
+    assert np.max(np.abs(g - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_bootstrap_pivot_spans_truncated_eigenvectors(torch, bbl):
+    note("bootstrap pivot n=20000 n_t=2000 b=4")
+    H = synthgen.WORKLOADS["small_fp64_n2e4"].generate()
+    Hd = bbl.DeviceCSR.from_host(H, "float64")
+    P, st = bbl.bootstrap_pivot(Hd, 2000, 4, 1e-10, m_max=400)
+    P = P.cpu().numpy()
+    assert np.all(P[2000:] == 0)
+    Pref = oracle.bootstrap_pivot(H, 2000, 4)
+    sv = np.linalg.svd(Pref.T @ P, compute_uv=False)
+    assert sv.min() > 1 - 1e-9, sv
+    assert st["converged"] == 1
+
+
+# ----------------------------------------------------------- block Lanczos
+def test_small_fp64_workload_matches_oracle(torch, bbl):
+    """n = 2e4, ~40 nnz/row, FP64 throughout, b = k = 4, tol 1e-8, bootstrap
+    pivot from the leading 2000 x 2000 block."""
+    w = synthgen.WORKLOADS["small_fp64_n2e4"]
+    note("small FP64 workload end to end")
+    H = w.generate()
+    Hd = bbl.DeviceCSR.from_host(H, "float64")
+    P, _ = bbl.bootstrap_pivot(Hd, w.n_trunc, w.nvec, w.tol, m_max=w.m_max)
+    r = bbl.block_lanczos(Hd, P, w.k, w.tol, m_max=w.m_max)
+    assert r.converged, r.stats
+    Pref = oracle.bootstrap_pivot(H, w.n_trunc, w.nvec)
+    ro = oracle.block_lanczos(H, Pref, w.k, w.tol, w.m_max)
+    assert ro.converged
+    np.testing.assert_allclose(r.eigvals, ro.eigvals, rtol=1e-10)
+    X = r.eigvecs.cpu().numpy()
+    res_host = oracle.ritz_residuals(H, X, r.eigvals)
+    assert np.all(res_host <= w.tol * r.stats["hnorm_est"])
+    np.testing.assert_allclose(r.residuals, res_host, rtol=1e-6, atol=1e-3 * w.tol * r.stats["hnorm_est"])
+    sv = np.linalg.svd(ro.eigvecs.T @ X, compute_uv=False)
+    assert sv.min() > 1 - 1e-8
+    # same pivot as the oracle: iteration counts agree to one block
+    r2 = bbl.block_lanczos(Hd, dev(torch, Pref), w.k, w.tol, m_max=w.m_max, check_every=1)
+    assert abs(r2.stats["iters"] - ro.iters) <= 1, (r2.stats["iters"], ro.iters)
+    np.testing.assert_allclose(r2.eigvals, ro.eigvals, rtol=1e-10)
+
+
+def test_random_pivot_finds_same_eigenvalues(torch, bbl):
+    note("random vs bootstrap pivot agree on the eigenvalue set")
+    w = synthgen.WORKLOADS["small_fp64_n2e4"]
+    H = w.generate()
+    Hd = bbl.DeviceCSR.from_host(H, "float64")
+    Pr = bbl.random_pivot(H.n, 4, synthgen.pivot_key(0))
+    r = bbl.block_lanczos(Hd, Pr, 4, 1e-8, m_max=300)
+    Pref = synthgen.gaussian_block(H.n, 4, synthgen.pivot_key(0))
+    ro = oracle.block_lanczos(H, Pref, 4, 1e-8, 300)
+    assert r.converged and ro.converged
+    np.testing.assert_allclose(r.eigvals, ro.eigvals, rtol=1e-10)
+
+
+def test_fp32_path_matches_oracle_on_rounded_matrix(torch, bbl):
+    note("FP32 path n=40000 z~200 b=8 k=10")
+    H = synthgen.generate(40000, 1000, 105, 0.7, 2)
+    Hd = bbl.DeviceCSR.from_host(H, "float32")
+    P, _ = bbl.bootstrap_pivot(Hd, 4000, 8, 1e-6, m_max=200)
+    r = bbl.block_lanczos(Hd, P, 10, 1e-6, m_max=200)
+    assert r.converged, r.stats
+    H32 = H.as_float32_values()
+    Pref = oracle.bootstrap_pivot(H32, 4000, 8)
+    ro = oracle.block_lanczos(H32, Pref, 10, 1e-6, 200)
+    np.testing.assert_allclose(r.eigvals, ro.eigvals, rtol=1e-5)
+    X = r.eigvecs.cpu().numpy()
+    res_host = oracle.ritz_residuals(H32, X, r.eigvals)
+    assert np.all(res_host <= 1e-6 * r.stats["hnorm_est"])
+    # FP64 run of the same matrix
+    Hd64 = bbl.DeviceCSR.from_host(H32, "float64")
+    r64 = bbl.block_lanczos(Hd64, P, 10, 1e-6, m_max=200)
+    np.testing.assert_allclose(r.eigvals, r64.eigvals, rtol=1e-5)
+
+
+def test_exact_eigenvector_pivot_deflates_and_converges_at_once(torch, bbl):
+    note("exact-eigenvector pivot")
+    H = synthgen.generate(1600, 400, 20, 0.7, 6)
+    lam, X = np.linalg.eigh(H.to_dense())
+    Hd = bbl.DeviceCSR.from_host(H, "float64")
+    r = bbl.block_lanczos(Hd, dev(torch, X[:, :4]), 4, 1e-10, m_max=10, check_every=1)
+    assert r.converged and r.stats["iters"] == 1
+    assert r.stats["deflations"] == 4
+    np.testing.assert_allclose(r.eigvals, lam[:4], rtol=1e-12)
+
+
+def test_rank_deficient_pivot_is_repaired(torch, bbl):
+    note("rank-deficient pivot")
+    H = synthgen.generate(4000, 400, 20, 0.7, 4)
+    lam = np.linalg.eigvalsh(H.to_dense())
+    P = synthgen.gaussian_block(H.n, 4, 1)
+    P[:, 3] = P[:, 0]  # duplicated column
+    r = bbl.block_lanczos(bbl.DeviceCSR.from_host(H, "float64"), dev(torch, P), 4, 1e-9, m_max=300)
+    assert r.converged and r.stats["deflations"] >= 1
+    np.testing.assert_allclose(r.eigvals, lam[:4], rtol=1e-10)
+
+
+def test_krylov_exhaustion(torch, bbl):
+    note("Krylov exhaustion n=40 b=4")
+    H = synthgen.generate(40, 20, 6, 0.7, 2)
+    lam = np.linalg.eigvalsh(H.to_dense())
+    r = bbl.block_lanczos(bbl.DeviceCSR.from_host(H, "float64"),
+                          dev(torch, synthgen.gaussian_block(40, 4, 1)), 16, 1e-300, m_max=10)
+    np.testing.assert_allclose(r.eigvals, lam[:16], rtol=0, atol=1e-11 * abs(lam).max())
+
+
+def test_block_size_one(torch, bbl):
+    note("block size 1 (single-vector method)")
+    H = synthgen.generate(2000, 400, 20, 0.7, 9)
+    lam = np.linalg.eigvalsh(H.to_dense())
+    r = bbl.block_lanczos(bbl.DeviceCSR.from_host(H, "float64"),
+                          dev(torch, synthgen.gaussian_block(H.n, 1, 2)), 3, 1e-9, m_max=1000)
+    assert r.converged
+    np.testing.assert_allclose(r.eigvals, lam[:3], rtol=1e-10)
+
+
+def test_not_converged_reports_current_pairs(torch, bbl):
+    note("block cap reached")
+    H = synthgen.generate(20000, 400, 20, 0.7, 0)
+    r = bbl.block_lanczos(bbl.DeviceCSR.from_host(H, "float64"),
+                          dev(torch, synthgen.gaussian_block(H.n, 4, 1)), 4, 1e-10, m_max=5)
+    assert r.status == bbl.BBL_E_NOT_CONVERGED and r.stats["iters"] == 5
+    assert np.all(np.isfinite(r.eigvals)) and np.all(r.residuals > 0)
