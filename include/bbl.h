@@ -69,15 +69,14 @@ typedef struct {
   uint64_t seed;        /* key of random replacement directions (default 0) */
 } bbl_opts;
 
-/* Counters and phase times (milliseconds, host wall clock around
-   stream-synchronised phases are not taken: times are HIP-event based). */
+/* Counters of one solve and its wall time (host clock around the call). */
 typedef struct {
   int32_t iters;        /* block iterations (products H V_j) */
   int32_t spmm_calls;   /* all products with H, explicit residual checks included */
   int32_t deflations;   /* columns replaced because of (near) rank loss */
   int32_t converged;    /* 1 if every wanted pair met the tolerance */
   int32_t checks;       /* band-matrix eigensolves */
-  int32_t fallbacks;    /* block QR steps that needed the spectral fallback */
+  int32_t reorth_second_passes; /* blocks that needed a second Gram-Schmidt sweep */
   double hnorm_est;     /* largest |Ritz value| of the final band matrix */
   double t_total_ms;    /* wall time of the call */
 } bbl_stats;

@@ -52,7 +52,7 @@ class _Opts(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("spmm_calls", ctypes.c_int32),
                 ("deflations", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("checks", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
+                ("checks", ctypes.c_int32), ("reorth_second_passes", ctypes.c_int32),
                 ("hnorm_est", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
 
     def as_dict(self):

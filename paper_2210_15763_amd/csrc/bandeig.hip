@@ -111,8 +111,9 @@ __device__ int ldl_sweep(const double *__restrict__ Tb, int N, int kd, double si
 __global__ __launch_bounds__(64) void k_sturm(const double *__restrict__ Tb, int N, int kd,
                                               const double *__restrict__ shifts,
                                               int *__restrict__ counts, double pivmin) {
-  __shared__ double win[kMaxW * kMaxW];
-  __shared__ double chunk[kChunk * kMaxW];
+  extern __shared__ double smem[];
+  double *win = smem;
+  double *chunk = smem + (kd + 1) * (kd + 1);
   const int c = ldl_sweep(Tb, N, kd, shifts[blockIdx.x], pivmin, false, win, chunk, nullptr,
                           nullptr);
   if (threadIdx.x == 0) counts[blockIdx.x] = c;
@@ -231,8 +232,8 @@ __global__ __launch_bounds__(64) void k_invit(const double *__restrict__ Tb, int
                                               double *X, int niter) {
   extern __shared__ double smem[];
   double *win = smem;
-  double *chunk = win + kMaxW * kMaxW;
-  double *x = chunk + kChunk * kMaxW;
+  double *chunk = win + (kd + 1) * (kd + 1);
+  double *x = chunk + kChunk * (kd + 1);
   __shared__ double red[64];
   const int tg = blockIdx.x;
   const int t = threadIdx.x;
@@ -438,14 +439,16 @@ void band_eigensolve(const double *band, int N, int kd, int k, void *ws, const B
   hipLaunchKernelGGL(k_gersh, dim3(1), dim3(256), 0, s, band, N, kdd, gersh);
   hipLaunchKernelGGL(k_bisect_init, dim3(4), dim3(256), 0, s, gersh, kShifts1, sh_a, brk, NT);
   check_launch("k_bisect_init");
-  hipLaunchKernelGGL(k_sturm, dim3(kShifts1), dim3(64), 0, s, band, N, kdd, sh_a, counts, pivmin);
+  const size_t smem_s = (size_t)((kdd + 1) * (kdd + 1) + kChunk * (kdd + 1)) * sizeof(double);
+  hipLaunchKernelGGL(k_sturm, dim3(kShifts1), dim3(64), smem_s, s, band, N, kdd, sh_a, counts,
+                     pivmin);
   check_launch("k_sturm");
   hipLaunchKernelGGL(k_bisect_update, dim3(1), dim3(256), 0, s, 1, sh_a, counts, kShifts1, N, k,
                      brk, kShiftsT, sh_b);
   check_launch("k_bisect_update");
   for (int r = 1; r < kRounds; ++r) {
-    hipLaunchKernelGGL(k_sturm, dim3(NT * kShiftsT), dim3(64), 0, s, band, N, kdd, sh_b, counts,
-                       pivmin);
+    hipLaunchKernelGGL(k_sturm, dim3(NT * kShiftsT), dim3(64), smem_s, s, band, N, kdd, sh_b,
+                       counts, pivmin);
     check_launch("k_sturm");
     const bool last = (r == kRounds - 1);
     hipLaunchKernelGGL(k_bisect_update, dim3(1), dim3(256), 0, s, 0, sh_b, counts, kShiftsT, N,
@@ -454,7 +457,7 @@ void band_eigensolve(const double *band, int N, int kd, int k, void *ws, const B
     std::swap(sh_a, sh_b);
   }
   // inverse iteration (x staged in LDS)
-  const size_t smem = (size_t)(kMaxW * kMaxW + kChunk * kMaxW + N) * sizeof(double);
+  const size_t smem = (size_t)((kdd + 1) * (kdd + 1) + kChunk * (kdd + 1) + N) * sizeof(double);
   BBL_REQUIRE(smem <= 150 * 1024, "band eigensolve: band matrix too large for LDS staging");
   if (smem > 64 * 1024)
     BBL_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_invit),

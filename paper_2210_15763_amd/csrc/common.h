@@ -39,6 +39,19 @@ inline void check_launch(const char *what) {
 constexpr int kMaxBlock = 32;    // largest supported block size / k
 constexpr int kWave = 64;
 
+// Capacity (doubles) of a partial-sum buffer for gram products with at most
+// Mmax columns of X and ny <= nyw columns of Y, including the reduction's
+// second-stage scratch.
+inline size_t gram_partial_doubles(int64_t Mmax, int nyw) {
+  return ((size_t)524288 + 4 * (size_t)Mmax + 8192) * nyw * 9 / 8 + 65536;
+}
+// Largest partial count a gram over M x ny may produce in such a buffer.
+inline int gram_max_partials(size_t cap_doubles, int M, int ny) {
+  const size_t per = (size_t)M * ny;
+  const size_t p = cap_doubles * 8 / 9 / per;
+  return (int)(p > 1 ? p - 1 : 1);
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 

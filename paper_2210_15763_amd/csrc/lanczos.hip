@@ -15,6 +15,7 @@
 // Every step runs in HIP kernels on the caller's stream; the host only
 // sequences launches and reads 2k+1 doubles per convergence check.
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -78,7 +79,8 @@ Layout make_layout(int64_t n, int b, int k, int m_max, int bdt) {
   L.W = take((size_t)n * b * sx);
   L.Wp = take((size_t)n * b * 8);
   L.X = take((size_t)n * k * 8);
-  L.partial_doubles = (size_t)(131072 + 2 * Mmax) * nyw + (size_t)kMaxPartialRows * nyw;
+  L.partial_doubles =
+      std::max(gram_partial_doubles(Mmax, nyw), (size_t)kMaxPartialRows * nyw * 9 / 8 + 4096);
   L.partial = take(L.partial_doubles * 8);
   L.C = take((size_t)Mmax * nyw * 8);
   L.band = take((size_t)(Mmax + b) * (b + 1) * 8);
@@ -119,9 +121,9 @@ struct Solver {
   char *basis;
   void *W;
   double *Wp, *X, *partial, *C, *band, *Bstore, *S, *dres;
-  double *Araw, *C3, *O, *C0, *QB, *RB, *O2, *Rinv;
+  double *Araw, *C3, *O, *C0, *QB, *RB, *O2, *Rinv, *G0, *G1;
   int *ints;
-  int *mask, *flag, *breakdown, *ndefl;
+  int *mask, *flag, *breakdown, *ndefl, *flag2, *n_second, *chol_fail;
   void *eigws, *normws;
   int qr_calls = 0;
 
@@ -153,11 +155,16 @@ struct Solver {
     RB = m + 6 * sq;
     O2 = m + 7 * sq;
     Rinv = m + 8 * sq;
+    G0 = m + 9 * sq;
+    G1 = m + 10 * sq;
     ints = reinterpret_cast<int *>(ws + L.ints);
     mask = ints;
     flag = ints + 64;
     breakdown = ints + 65;
     ndefl = ints + 66;
+    flag2 = ints + 67;
+    n_second = ints + 68;
+    chol_fail = ints + 69;
     eigws = ws + L.eig;
     normws = ws + L.norm;
   }
@@ -166,7 +173,7 @@ struct Solver {
   int64_t slot_stride() const { return n * b; }
 
   int max_partials(int M, int ny) const {
-    return (int)std::max<size_t>(1, L.partial_doubles / ((size_t)M * ny));
+    return gram_max_partials(L.partial_doubles, M, ny);
   }
 
   // C (M x ny) = X^T Y with X = nblk basis-type blocks
@@ -178,25 +185,41 @@ struct Solver {
     launch_reduce_when(partial, P, M, ny, out, when, s);
   }
 
-  // W' -= V_{0:nb-1} (V^T W'), twice
-  void reorth(int nb, double *Y, const int *when = nullptr) {
-    for (int pass = 0; pass < 2; ++pass) {
-      gram(basis, xd, b, nb, slot_stride(), Y, BBL_F64, b, C, when);
-      launch_update_when(n, basis, xd, b, nb, slot_stride(), C, b, -1.0, Y, BBL_F64, 1.0, Y,
-                         BBL_F64, when, s);
+  // One classical Gram-Schmidt sweep: W' -= V_{0:nb-1} (V^T W').
+  void cgs_pass(int nb, double *Y, const int *when) {
+    gram(basis, xd, b, nb, slot_stride(), Y, BBL_F64, b, C, when);
+    launch_update_when(n, basis, xd, b, nb, slot_stride(), C, b, -1.0, Y, BBL_F64, 1.0, Y,
+                       BBL_F64, when, s);
+  }
+
+  // Full reorthogonalisation against the stored blocks.  always_twice: two
+  // sweeps unconditionally (fresh random directions); otherwise the second
+  // sweep runs only when the first removed a large part of some column
+  // (norm ratio below 1/sqrt(2)), decided on the device.
+  void reorth(int nb, double *Y, const int *when = nullptr, bool always_twice = false) {
+    if (always_twice) {
+      cgs_pass(nb, Y, when);
+      cgs_pass(nb, Y, when);
+      return;
     }
+    gram(Y, BBL_F64, b, 1, 0, Y, BBL_F64, b, G0);
+    cgs_pass(nb, Y, when);
+    gram(Y, BBL_F64, b, 1, 0, Y, BBL_F64, b, G1);
+    launch_reorth_check(G0, G1, b, 0.5, when, flag2, n_second, s);
+    cgs_pass(nb, Y, flag2);
   }
 
   // Block QR of Wp into basis slot `dest`; Bout = B (upper triangular).
   void block_qr(int nbasis, int dest, double *Bout, const double *hnorm_dev) {
     gram(Wp, BBL_F64, b, 1, 0, Wp, BBL_F64, b, O);
+    launch_chol_try(O, b, o.tau, hnorm_dev, dres + kHn2Slot, C0, QB, RB, mask, flag, chol_fail, s);
     launch_svqb_prepare(O, b, o.tau, hnorm_dev, dres + kHn2Slot, C0, QB, RB, mask, flag, ndefl,
-                        s);
+                        chol_fail, s);
     launch_update(n, Wp, BBL_F64, b, 1, 0, C0, b, 1.0, nullptr, BBL_F64, 0.0, Wp, BBL_F64, s);
     // deflated columns: fresh random directions, orthogonal to the basis
     const uint64_t key = (o.seed ^ 0x9E3779B97F4A7C15ull) + 0x5DEECE66Dull * (uint64_t)(qr_calls + 1);
     launch_gauss(n, b, b, 0, key, kTagDeflation, Wp, mask, flag, s);
-    if (nbasis > 0) reorth(nbasis, Wp, flag);
+    if (nbasis > 0) reorth(nbasis, Wp, flag, true);
     launch_update_when(n, Wp, BBL_F64, b, 1, 0, QB, b, 1.0, nullptr, BBL_F64, 0.0, Wp, BBL_F64,
                        flag, s);
     gram(Wp, BBL_F64, b, 1, 0, Wp, BBL_F64, b, O2);
@@ -213,12 +236,31 @@ struct Solver {
     std::vector<double> theta, resid;
   };
 
-  int check_interval(int N) const {
-    if (o.check_every > 0) return o.check_every;
-    if (N <= 256) return 1;
-    if (N <= 1024) return 2;
-    return 4;
+  // When to solve the band matrix next.  A fixed interval if the caller asked
+  // for one; otherwise the decay of the largest residual estimate between the
+  // last two checks is extrapolated to the tolerance and half of the predicted
+  // distance is skipped (at least 1, at most 8 blocks), so the eigensolve runs
+  // a few dozen times per solve instead of every block.
+  int next_check_after(int nblk, double rho_max, double target) {
+    if (o.check_every > 0) return nblk + o.check_every;
+    const double lr = std::log(std::max(rho_max, 1e-300));
+    int step = 2;
+    if (have_prev_ && nblk > prev_nblk_) {
+      const double rate = (lr - prev_log_rho_) / (double)(nblk - prev_nblk_);
+      if (rate < -1e-6) {
+        const double togo = (std::log(std::max(target, 1e-300)) - lr) / rate;
+        step = (int)std::floor(0.5 * togo);
+      }
+    }
+    step = std::max(1, std::min(8, step));
+    have_prev_ = true;
+    prev_nblk_ = nblk;
+    prev_log_rho_ = lr;
+    return nblk + step;
   }
+  bool have_prev_ = false;
+  int prev_nblk_ = 0;
+  double prev_log_rho_ = 0.0;
 
   // Ritz vectors of the last eigensolve into Xout (n x k), normalised;
   // returns explicit residual norms.
@@ -249,6 +291,7 @@ struct Solver {
     block_qr(0, 0, Bstore + (size_t)o.m_max * b * b, hnorm_dev);
     double *Xout = eigvecs_out ? eigvecs_out : X;
     int last_checked_nblk = 0;
+    int next_check = 1;
     std::vector<double> hres(2 * kMaxBlock + 2);
     for (int J = 0; J < o.m_max; ++J) {
       launch_spmm(H, slot(J), xd, W, xd, b, s);
@@ -268,7 +311,7 @@ struct Solver {
       const bool exhausted = (int64_t)N >= n;
       const bool last = (J == o.m_max - 1);
       if (N < k && !exhausted) continue;
-      if (!(exhausted || last || ((J + 1) % check_interval(N)) == 0)) continue;
+      if (!(exhausted || last || J + 1 >= next_check)) continue;
       const int kk = std::min(k, N);
       band_eigensolve(band, N, b, kk, eigws, L.el, BJ, b, S, dres, s);
       ++R.checks;
@@ -283,7 +326,12 @@ struct Solver {
       R.hnorm = hres[2 * kk];
       last_checked_nblk = J + 1;
       bool est_ok = true;
-      for (int i = 0; i < kk; ++i) est_ok &= (hres[kk + i] <= tol * R.hnorm);
+      double rho_max = 0.0;
+      for (int i = 0; i < kk; ++i) {
+        est_ok &= (hres[kk + i] <= tol * R.hnorm);
+        rho_max = std::max(rho_max, hres[kk + i]);
+      }
+      next_check = next_check_after(J + 1, rho_max, tol * R.hnorm);
       if (exhausted || (kk == k && est_ok) || last) {
         std::vector<double> r = ritz_and_residual(J + 1, kk, Xout);
         ++R.spmm_calls;
@@ -352,16 +400,17 @@ int solve_impl(const bbl_csr *H, const double *pivot, int32_t nvec, int32_t k, d
     eigvals[i] = i < (int)R.theta.size() ? R.theta[i] : NAN;
     if (residuals) residuals[i] = i < (int)R.resid.size() ? R.resid[i] : NAN;
   }
-  int nd = 0;
-  BBL_HIP(hipMemcpyAsync(&nd, sv.ndefl, sizeof(int), hipMemcpyDeviceToHost, s));
+  int cnt[3] = {0, 0, 0};  // ndefl, flag2, n_second
+  BBL_HIP(hipMemcpyAsync(cnt, sv.ndefl, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
   BBL_HIP(hipStreamSynchronize(s));
+  const int nd = cnt[0];
   if (stats) {
     stats->iters = R.iters;
     stats->spmm_calls = R.spmm_calls;
     stats->deflations = nd;
     stats->converged = R.converged ? 1 : 0;
     stats->checks = R.checks;
-    stats->fallbacks = 0;
+    stats->reorth_second_passes = cnt[2];
     stats->hnorm_est = R.hnorm;
     stats->t_total_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -533,8 +582,7 @@ int bbl_band_eig(const double *band, int32_t N, int32_t kd, int32_t k, void *ws,
 
 size_t bbl_gram_workspace_size(int64_t n, int32_t bx, int32_t nblk, int32_t ny) {
   if (n < 1 || bx < 1 || nblk < 1 || ny < 1 || ny > kMaxBlock) return 0;
-  const size_t M = (size_t)bx * nblk;
-  return ((size_t)131072 + 2 * M) * ny * 8 + 512;
+  return gram_partial_doubles((int64_t)bx * nblk, ny) * 8 + 512;
 }
 
 int bbl_gram(int64_t n, const void *X, int32_t xdtype, int32_t bx, int32_t nblk, const void *Y,
@@ -549,7 +597,7 @@ int bbl_gram(int64_t n, const void *X, int32_t xdtype, int32_t bx, int32_t nblk,
     hipStream_t s = static_cast<hipStream_t>(stream);
     double *partial = reinterpret_cast<double *>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
     const int M = bx * nblk;
-    const int maxp = (int)std::max<size_t>(1, (need - 512) / 8 / ((size_t)M * ny));
+    const int maxp = gram_max_partials((need - 512) / 8, M, ny);
     const int P = launch_gram(n, X, xdtype, bx, nblk, n * bx, Y, ydtype, ny, partial, maxp, s);
     launch_reduce(partial, P, M, ny, C, s);
     return (int)BBL_OK;

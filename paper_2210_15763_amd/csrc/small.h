@@ -127,7 +127,10 @@ __device__ inline void wg_householder_qr(double *A, double *Q, int n, double *v,
 // launchers of small.hip
 void launch_svqb_prepare(const double *O, int b, double tau, const double *hnorm_ptr,
                          const double *hn2_ptr, double *C0, double *QB, double *RB, int *mask,
-                         int *flag, int *ndefl_total, hipStream_t s);
+                         int *flag, int *ndefl_total, const int *when, hipStream_t s);
+void launch_chol_try(const double *O, int b, double tau, const double *hnorm_ptr,
+                     const double *hn2_ptr, double *C0, double *QB, double *RB, int *mask,
+                     int *flag, int *fail, hipStream_t s);
 void launch_chol_finish(const double *O2, int b, const double *RB, double *Rinv, double *Bout,
                         int *breakdown, hipStream_t s);
 void launch_set_A(const double *Araw, int b, int J, double *band, int kd, const double *Bprev,
@@ -137,5 +140,7 @@ void launch_set_B(const double *B, int b, int J, double *band, int kd, int nrows
 void launch_normalize_columns(int64_t n, int k, double *X, double *scratch, int max_partials,
                               hipStream_t s);
 size_t normalize_scratch_bytes(int k, int max_partials);
+void launch_reorth_check(const double *G0, const double *G1, int b, double eta2, const int *outer,
+                         int *flag, int *counter, hipStream_t s);
 
 }  // namespace bbl

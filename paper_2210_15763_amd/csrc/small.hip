@@ -25,7 +25,9 @@ __global__ __launch_bounds__(256) void k_svqb_prepare(const double *__restrict__
                                                       double tau, const double *hnorm_ptr,
                                                       const double *hn2_ptr, double *C0,
                                                       double *QB, double *RB, int *mask,
-                                                      int *flag, int *ndefl_total) {
+                                                      int *flag, int *ndefl_total,
+                                                      const int *when) {
+  if (when && *when == 0) return;
   __shared__ double A[kMaxBlock * kMaxBlock], U[kMaxBlock * kMaxBlock];
   __shared__ double Bs[kMaxBlock * kMaxBlock], Q[kMaxBlock * kMaxBlock];
   __shared__ double lam[kMaxBlock], sig[kMaxBlock], v[kMaxBlock], sc[4];
@@ -79,6 +81,71 @@ __global__ __launch_bounds__(256) void k_svqb_prepare(const double *__restrict__
     *flag = nd > 0 ? 1 : 0;
     if (ndefl_total) *ndefl_total += nd;
   }
+}
+
+// Single-thread Cholesky O = R^T R (R upper, row-major) and R^{-1}.  Returns
+// the smallest pivot (before the square root); a non-positive pivot is
+// replaced by 1 so the factors stay finite.
+__device__ double chol_upper(const double *O, int b, double *R, double *Ri) {
+  double pmin = 1e308;
+  for (int i = 0; i < b * b; ++i) R[i] = 0.0;
+  for (int j = 0; j < b; ++j) {
+    double s = O[j * b + j];
+    for (int k = 0; k < j; ++k) s -= R[k * b + j] * R[k * b + j];
+    pmin = fmin(pmin, s);
+    if (!(s > 0.0)) s = 1.0;
+    const double rjj = sqrt(s);
+    R[j * b + j] = rjj;
+    for (int c = j + 1; c < b; ++c) {
+      double x = 0.5 * (O[j * b + c] + O[c * b + j]);
+      for (int k = 0; k < j; ++k) x -= R[k * b + j] * R[k * b + c];
+      R[j * b + c] = x / rjj;
+    }
+  }
+  for (int i = 0; i < b * b; ++i) Ri[i] = 0.0;
+  for (int c = 0; c < b; ++c) {
+    Ri[c * b + c] = 1.0 / R[c * b + c];
+    for (int r = c - 1; r >= 0; --r) {
+      double x = 0.0;
+      for (int m = r + 1; m <= c; ++m) x += R[r * b + m] * Ri[m * b + c];
+      Ri[r * b + c] = -x / R[r * b + r];
+    }
+  }
+  return pmin;
+}
+
+// First factorisation of the overlap by Cholesky (CholQR).  Accepted when the
+// overlap is safely positive definite: every pivot above 1e-14 * max O_ii
+// (condition number of W' below ~1e7, where the Cholesky polish pass restores
+// full orthogonality) and above (tau * max(||W'||, ||H||_est))^2 (no column
+// is negligible -- the deflation test of the spectral factorisation).  On
+// success C0 = R^{-1}, RB = R, QB = I, no deflation; otherwise fail = 1 and the
+// spectral factorisation (k_svqb_prepare, gated by fail) takes over.
+__global__ __launch_bounds__(64) void k_chol_try(const double *__restrict__ O, int b, double tau,
+                                                 const double *hnorm_ptr, const double *hn2_ptr,
+                                                 double *C0, double *QB, double *RB, int *mask,
+                                                 int *flag, int *fail) {
+  __shared__ double R[kMaxBlock * kMaxBlock], Ri[kMaxBlock * kMaxBlock];
+  __shared__ int ok;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    double dmax = 0.0;
+    for (int i = 0; i < b; ++i) dmax = fmax(dmax, O[i * b + i]);
+    const double pmin = chol_upper(O, b, R, Ri);
+    const double hn = fmax(hnorm_ptr ? *hnorm_ptr : 0.0, hn2_ptr ? *hn2_ptr : 0.0);
+    const double scale = tau * fmax(sqrt(fmax(dmax, 0.0)), hn);
+    ok = (dmax > 0.0 && pmin > 1e-14 * dmax && pmin > scale * scale) ? 1 : 0;
+    *fail = 1 - ok;
+    if (ok) *flag = 0;
+  }
+  __syncthreads();
+  if (!ok) return;
+  for (int i = t; i < b * b; i += blockDim.x) {
+    C0[i] = Ri[i];
+    RB[i] = R[i];
+    QB[i] = (i / b == i % b) ? 1.0 : 0.0;
+  }
+  if (t < b) mask[t] = 0;
 }
 
 // Second pass: O2 = Y^T Y = R2^T R2.  Writes R2^{-1} (upper, row-major) and
@@ -233,13 +300,42 @@ __global__ void k_colscale(int64_t n, int k, double *X, const double *factor) {
     X[i] *= factor[i % k];
 }
 
+// Second Gram-Schmidt pass needed?  flag = 1 if any column lost more than
+// 1 - eta of its norm in the first pass (||w_after||^2 < eta^2 ||w_before||^2,
+// the "twice is enough" test of Daniel, Gragg, Kaufman and Stewart), gated by
+// an optional outer predicate.
+__global__ void k_reorth_check(const double *G0, const double *G1, int b, double eta2,
+                               const int *outer, int *flag, int *counter) {
+  if (threadIdx.x != 0) return;
+  int need = 0;
+  for (int i = 0; i < b; ++i) need |= (G1[i * b + i] < eta2 * G0[i * b + i]) ? 1 : 0;
+  if (outer && *outer == 0) need = 0;
+  *flag = need;
+  if (counter) *counter += need;
+}
+
 }  // namespace
+
+void launch_reorth_check(const double *G0, const double *G1, int b, double eta2, const int *outer,
+                         int *flag, int *counter, hipStream_t s) {
+  hipLaunchKernelGGL(k_reorth_check, dim3(1), dim3(64), 0, s, G0, G1, b, eta2, outer, flag,
+                     counter);
+  check_launch("k_reorth_check");
+}
 
 void launch_svqb_prepare(const double *O, int b, double tau, const double *hnorm_ptr,
                          const double *hn2_ptr, double *C0, double *QB, double *RB, int *mask,
-                         int *flag, int *ndefl_total, hipStream_t s) {
+                         int *flag, int *ndefl_total, const int *when, hipStream_t s) {
   hipLaunchKernelGGL(k_svqb_prepare, dim3(1), dim3(256), 0, s, O, b, tau, hnorm_ptr, hn2_ptr, C0,
-                     QB, RB, mask, flag, ndefl_total);
+                     QB, RB, mask, flag, ndefl_total, when);
+  check_launch("k_svqb_prepare");
+}
+
+void launch_chol_try(const double *O, int b, double tau, const double *hnorm_ptr,
+                     const double *hn2_ptr, double *C0, double *QB, double *RB, int *mask,
+                     int *flag, int *fail, hipStream_t s) {
+  hipLaunchKernelGGL(k_chol_try, dim3(1), dim3(64), 0, s, O, b, tau, hnorm_ptr, hn2_ptr, C0, QB,
+                     RB, mask, flag, fail);
   check_launch("k_svqb_prepare");
 }
 

@@ -17,6 +17,9 @@
 //   D[i][j]: lane l, element q holds i = l / 16 + 4 * q, j = l % 16
 // (the accumulator's four 64-bit elements are rows strided by 4; checked
 // against numpy by the gram/update parity tests)
+#include <algorithm>
+#include <type_traits>
+
 #include "common.h"
 
 namespace bbl {
@@ -187,6 +190,216 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const XT *X, int bx,
   }
 }
 
+// ---------------------------------------------------------------------------
+// VALU FP64 variants for the common block widths.  At nvec <= 10 the gram's
+// 16x16x4 MFMA would spend most of its FMAs on padding (N = nvec of 16),
+// while plain v_fma_f64 runs at the same peak with no padding; the uniform
+// operand (a row of Y in gram, a row of C in update) is wave-uniform and is
+// fetched with scalar loads into SGPRs.
+template <typename T, int N>
+struct Vec {
+  T v[N];
+};
+
+template <typename T, int N>
+__device__ __forceinline__ Vec<T, N> vload(const T *p) {
+  Vec<T, N> r;
+  constexpr int bytes = (int)sizeof(T) * N;
+  if constexpr (bytes % 16 == 0) {
+    const uint4 *q = reinterpret_cast<const uint4 *>(p);
+    uint4 tmp[bytes / 16];
+#pragma unroll
+    for (int i = 0; i < bytes / 16; ++i) tmp[i] = q[i];
+    __builtin_memcpy(r.v, tmp, bytes);
+  } else if constexpr (bytes % 8 == 0) {
+    const uint2 *q = reinterpret_cast<const uint2 *>(p);
+    uint2 tmp[bytes / 8];
+#pragma unroll
+    for (int i = 0; i < bytes / 8; ++i) tmp[i] = q[i];
+    __builtin_memcpy(r.v, tmp, bytes);
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.v[i] = p[i];
+  }
+  return r;
+}
+
+// Single-block gram C = X^T Y (X, Y: n x B row-major): lane = row, each lane
+// accumulates the B x B outer products of its rows, then one butterfly per
+// wave combines the lanes (fixed order).  partial[p][a][j], p = wave index.
+template <typename XT, typename YT, int B>
+__global__ __launch_bounds__(256) void k_gram1(int64_t n, const XT *__restrict__ X,
+                                               const YT *__restrict__ Y, int64_t rows_per_wave,
+                                               double *__restrict__ partial,
+                                               const int *__restrict__ when) {
+  if (when && *when == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t r0 = wave * rows_per_wave;
+  const int64_t r1 = min(n, r0 + rows_per_wave);
+  double acc[B][B];
+#pragma unroll
+  for (int a = 0; a < B; ++a)
+#pragma unroll
+    for (int j = 0; j < B; ++j) acc[a][j] = 0.0;
+  for (int64_t r = r0 + lane; r < r1; r += 64) {
+    const Vec<XT, B> x = vload<XT, B>(X + r * B);
+    const Vec<YT, B> y = vload<YT, B>(Y + r * B);
+#pragma unroll
+    for (int a = 0; a < B; ++a)
+#pragma unroll
+      for (int j = 0; j < B; ++j) acc[a][j] = fma((double)x.v[a], (double)y.v[j], acc[a][j]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int a = 0; a < B; ++a)
+#pragma unroll
+      for (int j = 0; j < B; ++j) acc[a][j] += __shfl_xor(acc[a][j], off, 64);
+  if (lane == 0) {
+    double *out = partial + wave * B * B;
+#pragma unroll
+    for (int a = 0; a < B; ++a)
+#pragma unroll
+      for (int j = 0; j < B; ++j) out[a * B + j] = acc[a][j];
+  }
+}
+
+// One wave per workgroup; lane owns CPL consecutive columns of X (inside one
+// block) and accumulates their products with all NY columns of Y over the
+// wave's contiguous row range.  partial[p][m][j], p = blockIdx.x.
+template <typename XT, typename YT, int NY, int CPL>
+__global__ __launch_bounds__(64) void k_gram_v(int64_t n, const XT *__restrict__ X, int bx, int M,
+                                               int64_t xstride, const YT *__restrict__ Y,
+                                               int64_t chunk, double *__restrict__ partial,
+                                               const int *__restrict__ when) {
+  if (when && *when == 0) return;
+  const int lane = threadIdx.x;
+  const int m0 = (blockIdx.y * 64 + lane) * CPL;
+  const bool ok = m0 < M;
+  const int blk = ok ? m0 / bx : 0;
+  const int a = ok ? m0 - blk * bx : 0;
+  const XT *xp = X + (int64_t)blk * xstride + a;
+  double acc[CPL][NY];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c)
+#pragma unroll
+    for (int j = 0; j < NY; ++j) acc[c][j] = 0.0;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = min(n, r0 + chunk);
+  int64_t r = r0;
+  constexpr int U = 4;
+  for (; r + U <= r1; r += U) {
+    Vec<XT, CPL> xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (ok) xv[u] = vload<XT, CPL>(xp + (r + u) * bx);
+      else
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) xv[u].v[c] = XT(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const YT *yr = Y + (r + u) * NY;
+#pragma unroll
+      for (int j = 0; j < NY; ++j) {
+        const double y = (double)yr[j];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) acc[c][j] = fma((double)xv[u].v[c], y, acc[c][j]);
+      }
+    }
+  }
+  for (; r < r1; ++r) {
+    Vec<XT, CPL> xv;
+    if (ok) xv = vload<XT, CPL>(xp + r * bx);
+    else
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) xv.v[c] = XT(0);
+    const YT *yr = Y + r * NY;
+#pragma unroll
+    for (int j = 0; j < NY; ++j) {
+      const double y = (double)yr[j];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) acc[c][j] = fma((double)xv.v[c], y, acc[c][j]);
+    }
+  }
+  if (ok) {
+    double *out = partial + ((int64_t)blockIdx.x * M + m0) * NY;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+#pragma unroll
+      for (int j = 0; j < NY; ++j) out[c * NY + j] = acc[c][j];
+  }
+}
+
+// Yout[r][j] = beta*Yin[r][j] + alpha*sum_m X[r][m] C[m][j], X blocks of width
+// BX, one row per lane (RPL rows per lane, 256-row stride), C rows scalar.
+template <typename XT, typename YIT, typename YOT, int BX, int NY, int RPL>
+__global__ __launch_bounds__(256) void k_update_v(int64_t n, const XT *X, int nblk,
+                                                  int64_t xstride, const double *__restrict__ C,
+                                                  double alpha, const YIT *Yin, double beta,
+                                                  YOT *Yout, const int *__restrict__ when) {
+  if (when && *when == 0) return;
+  const int64_t base = (int64_t)blockIdx.x * 256 * RPL + threadIdx.x;
+  double acc[RPL][NY];
+#pragma unroll
+  for (int u = 0; u < RPL; ++u)
+#pragma unroll
+    for (int j = 0; j < NY; ++j) acc[u][j] = 0.0;
+  for (int blk = 0; blk < nblk; ++blk) {
+    Vec<XT, BX> xv[RPL];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      const int64_t r = base + (int64_t)u * 256;
+      if (r < n) xv[u] = vload<XT, BX>(X + (int64_t)blk * xstride + r * BX);
+      else
+#pragma unroll
+        for (int c = 0; c < BX; ++c) xv[u].v[c] = XT(0);
+    }
+    const double *cb = C + (int64_t)blk * BX * NY;
+#pragma unroll
+    for (int a = 0; a < BX; ++a) {
+#pragma unroll
+      for (int j = 0; j < NY; ++j) {
+        const double cv = cb[a * NY + j];
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) acc[u][j] = fma((double)xv[u].v[a], cv, acc[u][j]);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    const int64_t r = base + (int64_t)u * 256;
+    if (r >= n) continue;
+    YOT o[NY];
+    if (beta != 0.0) {
+      const Vec<YIT, NY> yi = vload<YIT, NY>(Yin + r * NY);
+#pragma unroll
+      for (int j = 0; j < NY; ++j) o[j] = (YOT)fma(beta, (double)yi.v[j], alpha * acc[u][j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < NY; ++j) o[j] = (YOT)(alpha * acc[u][j]);
+    }
+#pragma unroll
+    for (int j = 0; j < NY; ++j) Yout[r * NY + j] = o[j];
+  }
+}
+
+// Two-stage fixed-order reduction of partial[P][MN]: stage 1 sums S
+// contiguous ranges of p, stage 2 sums the S results.
+__global__ __launch_bounds__(256) void k_reduce1(const double *__restrict__ partial, int P, int MN,
+                                                 int S, double *__restrict__ tmp,
+                                                 const int *__restrict__ when) {
+  if (when && *when == 0) return;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sidx = blockIdx.y;
+  if (idx >= MN) return;
+  const int p0 = (int)((int64_t)P * sidx / S), p1 = (int)((int64_t)P * (sidx + 1) / S);
+  double s = 0.0;
+  for (int p = p0; p < p1; ++p) s += partial[(int64_t)p * MN + idx];
+  tmp[(int64_t)sidx * MN + idx] = s;
+}
+
 __global__ void k_fill(double *p, int64_t count, double v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -246,10 +459,51 @@ __global__ void k_gauss(int64_t n, int nvec, int ld, int col0, uint64_t key, uin
   }
 }
 
+template <typename XT, typename YT, int NY, int CPL>
+int gram_valu(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const YT *Y,
+              double *partial, int max_partials, const int *when, hipStream_t s) {
+  const int M = nblk * bx;
+  const int gy = (M + 64 * CPL - 1) / (64 * CPL);
+  int64_t gx = std::max<int64_t>(1, std::min<int64_t>(2048 / gy + 1, ceil_div(n, 256)));
+  gx = std::min<int64_t>(gx, std::max(1, max_partials));
+  int64_t chunk = ceil_div(n, gx);
+  gx = ceil_div(n, chunk);
+  hipLaunchKernelGGL((k_gram_v<XT, YT, NY, CPL>), dim3((unsigned)gx, gy), dim3(64), 0, s, n, X, bx,
+                     M, xstride, Y, chunk, partial, when);
+  check_launch("k_gram_v");
+  return (int)gx;
+}
+
 template <typename XT, typename YT>
 int gram_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const YT *Y, int ny,
                double *partial, int max_partials, const int *when, hipStream_t s) {
   const int M = nblk * bx;
+  constexpr bool f32 = sizeof(XT) == 4;
+  if (nblk == 1 && ny == bx && (bx == 4 || bx == 8)) {
+    // one block: rows across lanes, 1024 waves at most
+    const int64_t waves = std::max<int64_t>(1, std::min<int64_t>({(int64_t)max_partials - 4, (int64_t)1024,
+                                                                    ceil_div(n, 1024)}));
+    const int64_t rpw = ceil_div(ceil_div(n, waves), 64) * 64;
+    const int64_t nw = ceil_div(n, rpw);
+    const int64_t grid = ceil_div(nw, 4);
+    if (bx == 4)
+      hipLaunchKernelGGL((k_gram1<XT, YT, 4>), dim3((unsigned)grid), dim3(256), 0, s, n, X, Y, rpw,
+                         partial, when);
+    else
+      hipLaunchKernelGGL((k_gram1<XT, YT, 8>), dim3((unsigned)grid), dim3(256), 0, s, n, X, Y, rpw,
+                         partial, when);
+    check_launch("k_gram1");
+    return (int)(grid * 4);
+  }
+  if (ny == bx) {
+    switch (bx) {
+      case 4: return gram_valu<XT, YT, 4, f32 ? 4 : 2>(n, X, bx, nblk, xstride, Y, partial, max_partials, when, s);
+      case 8: return gram_valu<XT, YT, 8, f32 ? 4 : 2>(n, X, bx, nblk, xstride, Y, partial, max_partials, when, s);
+      case 10: return gram_valu<XT, YT, 10, 2>(n, X, bx, nblk, xstride, Y, partial, max_partials, when, s);
+      case 16: return gram_valu<XT, YT, 16, 2>(n, X, bx, nblk, xstride, Y, partial, max_partials, when, s);
+      default: break;
+    }
+  }
   const int tiles = (M + 15) / 16;
   const int gy = (tiles + kTilesPerWG - 1) / kTilesPerWG;
   // row chunk: enough workgroups to fill the chip, bounded partial count
@@ -268,11 +522,30 @@ int gram_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const 
   return (int)gx;
 }
 
+template <typename XT, typename YIT, typename YOT, int B>
+void update_valu(int64_t n, const XT *X, int nblk, int64_t xstride, const double *C, double alpha,
+                 const YIT *Yin, double beta, YOT *Yout, const int *when, hipStream_t s) {
+  constexpr int RPL = 2;
+  const int64_t grid = ceil_div(n, 256 * RPL);
+  hipLaunchKernelGGL((k_update_v<XT, YIT, YOT, B, B, RPL>), dim3((unsigned)grid), dim3(256), 0, s,
+                     n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when);
+  check_launch("k_update_v");
+}
+
 template <typename XT, typename YIT, typename YOT>
 void update_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const double *C,
                   int ny, double alpha, const YIT *Yin, double beta, YOT *Yout, const int *when,
                   hipStream_t s) {
   const int M = nblk * bx;
+  if (ny == bx) {
+    switch (bx) {
+      case 4: update_valu<XT, YIT, YOT, 4>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, s); return;
+      case 8: update_valu<XT, YIT, YOT, 8>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, s); return;
+      case 10: update_valu<XT, YIT, YOT, 10>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, s); return;
+      case 16: update_valu<XT, YIT, YOT, 16>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, s); return;
+      default: break;
+    }
+  }
   const int64_t grid = ceil_div(n, 64);
   if (ny <= 16)
     hipLaunchKernelGGL((k_update<XT, YIT, YOT, 1>), dim3((unsigned)grid), dim3(256), 0, s, n, X,
@@ -314,8 +587,19 @@ int launch_gram(int64_t n, const void *X, int xdtype, int bx, int nblk, int64_t 
 void launch_reduce_when(const double *partial, int P, int M, int ny, double *out,
                         const int *when, hipStream_t s) {
   const int MN = M * ny;
-  hipLaunchKernelGGL(k_reduce, dim3((MN + 255) / 256), dim3(256), 0, s, partial, P, MN, out,
-                     when);
+  // stage 1 writes S partial sums behind the P partials (the caller's partial
+  // buffer holds (P + S) * MN doubles), stage 2 sums them in order
+  const int S = std::max(1, std::min(P / 8, std::max(1, 8192 / ((MN + 255) / 256))));
+  if (S > 1) {
+    double *tmp = const_cast<double *>(partial) + (size_t)P * MN;
+    hipLaunchKernelGGL(k_reduce1, dim3((MN + 255) / 256, S), dim3(256), 0, s, partial, P, MN, S,
+                       tmp, when);
+    check_launch("k_reduce1");
+    hipLaunchKernelGGL(k_reduce, dim3((MN + 255) / 256), dim3(256), 0, s, tmp, S, MN, out, when);
+  } else {
+    hipLaunchKernelGGL(k_reduce, dim3((MN + 255) / 256), dim3(256), 0, s, partial, P, MN, out,
+                       when);
+  }
   check_launch("k_reduce");
 }
 
