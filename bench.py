@@ -9,9 +9,19 @@ block Lanczos to convergence + Ritz vectors + explicit FP64 residual, with the
 matrix already resident in HBM.
 
 Prints ONE JSON line (metric, value = mean time-to-solution in seconds, ...)
-with a "roofline" object for the dominant kernel (the CSR SpMM, measured with
-HIP events on the stream it runs on) and a "cpu_baseline" object (the FP64
-CPU oracle timed on a bounded sample of the same solve on the host cores).
+with a "roofline" object for the CSR SpMM (its launches inside the timed
+solves, each bracketed by HIP events that the library records on the solver's
+stream) and a "cpu_baseline" object (the FP64 CPU oracle timed on a bounded
+sample of the same solve on the host cores).
+
+Two helper modes serve the hardware-counter measurement of HBM traffic:
+  --kernels-only       runs the SpMM, the reorthogonalisation gram and a plain
+                       1 GiB elementwise copy a few times each (the program run
+                       under `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE`);
+  --traffic F W        reads the two counter CSV directories and writes the
+                       per-launch HBM bytes of the SpMM, scaled by what the
+                       same counters read for the copy, to
+                       profiles/spmm_mid_n2e6_traffic.json.
 """
 from __future__ import annotations
 
@@ -82,6 +92,81 @@ def read_traffic(kernel_hash):
     return rec.get("hbm_bytes_per_launch")
 
 
+COPY_BYTES = 1 << 30   # bytes read (and written) by the calibration copy
+
+
+def _counter_rows(d):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            rows.extend(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit("no counter_collection.csv under " + d)
+    return rows
+
+
+def _per_dispatch(rows, counter, match):
+    """Mean over dispatches of kernels whose name contains `match` of the
+    counter (summed over its instances within one dispatch)."""
+    per = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter or match not in r.get("Kernel_Name", ""):
+            continue
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    if not per:
+        raise SystemExit("no %s rows for kernels matching %r" % (counter, match))
+    return float(np.mean(list(per.values()))), len(per)
+
+
+def write_traffic(fetch_dir, write_dir):
+    """FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; each is scaled by
+    the ratio of known bytes to the counter's reading for the copy kernel."""
+    f_spmm, nf = _per_dispatch(_counter_rows(fetch_dir), "FETCH_SIZE", "k_spmm")
+    w_spmm, nw = _per_dispatch(_counter_rows(write_dir), "WRITE_SIZE", "k_spmm")
+    f_copy, _ = _per_dispatch(_counter_rows(fetch_dir), "FETCH_SIZE", "neg")
+    w_copy, _ = _per_dispatch(_counter_rows(write_dir), "WRITE_SIZE", "neg")
+    fetch_scale = COPY_BYTES / (f_copy * 1024.0)
+    write_scale = COPY_BYTES / (w_copy * 1024.0)
+    rd = f_spmm * 1024.0 * fetch_scale
+    wr = w_spmm * 1024.0 * write_scale
+    import synthgen
+    w = synthgen.WORKLOADS[WORKLOAD]
+    H = load_matrix(w)
+    alg = spmm_bytes(H.n, H.nnz, w.nvec, 4, 4)
+    rec = {"kernel": "k_spmm (float32 values and vectors, 8 vectors)", "workload": WORKLOAD,
+           "spmm_source_hash": source_hash("spmm.hip"),
+           "fetch_kib_per_launch": f_spmm, "write_kib_per_launch": w_spmm,
+           "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
+           "fetch_scale": fetch_scale, "write_scale": write_scale,
+           "hbm_read_bytes_per_launch": rd, "hbm_write_bytes_per_launch": wr,
+           "hbm_bytes_per_launch": rd + wr, "alg_bytes_per_launch": alg,
+           "traffic_over_alg": (rd + wr) / alg, "dispatches": [nf, nw]}
+    path = os.path.join(ROOT, "profiles", "spmm_mid_n2e6_traffic.json")
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
+def kernels_only(torch, bbl, Hd, b, iters=10):
+    V = torch.randn((Hd.n, b), dtype=torch.float32, device="cuda")
+    W = torch.empty_like(V)
+    for _ in range(iters):
+        bbl.spmm(Hd, V, W)
+    Xb = torch.randn((50, Hd.n, b), dtype=torch.float32, device="cuda")
+    Y = torch.randn((Hd.n, b), dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        bbl.gram(Xb, 50, b, Y)
+    a = torch.randn(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    c = torch.empty_like(a)
+    for _ in range(iters):
+        torch.neg(a, out=c)
+    torch.cuda.synchronize()
+    log("kernels-only done")
+
+
 def time_kernel(torch, fn, iters):
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -138,7 +223,14 @@ def main():
     ap.add_argument("--random-arm", action="store_true",
                     help="also solve once from a random pivot and report its counts")
     ap.add_argument("--spmm-iters", type=int, default=20)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="run the SpMM, gram and calibration copy only (counter runs)")
+    ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the SpMM HBM traffic record from two rocprofv3 --pmc runs")
     args = ap.parse_args()
+    if args.traffic:
+        write_traffic(*args.traffic)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the hot path has no multi-GPU build "
               "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
@@ -156,13 +248,17 @@ def main():
     Hd = bbl.DeviceCSR.from_host(H, "float32")
     torch.cuda.synchronize()
     b, k = w.nvec, w.k
+    if args.kernels_only:
+        kernels_only(torch, bbl, Hd, b)
+        return
 
     ws_l = torch.empty(bbl.lanczos_workspace_bytes(H.n, b, k, w.m_max, bbl.BBL_F32),
                        dtype=torch.uint8, device="cuda")
 
     def step():
         P, pst = bbl.bootstrap_pivot(Hd, w.n_trunc, b, w.tol, m_max=w.m_max, seed=w.seed)
-        r = bbl.block_lanczos(Hd, P, k, w.tol, m_max=w.m_max, seed=w.seed, workspace=ws_l)
+        r = bbl.block_lanczos(Hd, P, k, w.tol, m_max=w.m_max, seed=w.seed, workspace=ws_l,
+                              time_spmm=True)
         return P, pst, r
 
     for i in range(args.warmup):
@@ -170,23 +266,29 @@ def main():
         log("warmup %d: iters=%d converged=%s" % (i, r.stats["iters"], r.converged))
     torch.cuda.synchronize()
     times = []
+    spmm_ms, spmm_n = 0.0, 0
     for i in range(args.steps):
         torch.cuda.synchronize()
         t = time.perf_counter()
         P, pst, r = step()
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t)
+        spmm_ms += r.stats["spmm_ms"]
+        spmm_n += r.stats["spmm_timed"]
         log("step %d: %.3f s iters=%d pivot_iters=%d converged=%s" %
             (i, times[-1], r.stats["iters"], pst["iters"], r.converged))
     tts = float(np.mean(times))
 
-    # dominant kernel: the SpMM, timed alone with HIP events on the current stream
+    # roofline kernel: the SpMM launches of the timed solves (HIP event pairs on
+    # the solver's stream), algorithmic bytes per launch / mean launch time
+    alg = spmm_bytes(H.n, H.nnz, b, 4, 4)
+    t_live = spmm_ms / 1e3 / max(spmm_n, 1)
+    achieved = alg / t_live
+    traffic = read_traffic(source_hash("spmm.hip"))
+    # the same kernel alone, back to back, for comparison
     V = torch.randn((H.n, b), dtype=torch.float32, device="cuda")
     W = torch.empty_like(V)
     t_spmm = time_kernel(torch, lambda: bbl.spmm(Hd, V, W), args.spmm_iters)
-    alg = spmm_bytes(H.n, H.nnz, b, 4, 4)
-    achieved = alg / t_spmm
-    traffic = read_traffic(source_hash("spmm.hip"))
 
     # reorthogonalisation gram on FP64 matrix cores: V_{1:j}^T W' at j = 50
     j = 50
@@ -203,9 +305,9 @@ def main():
                       "eigvals": [float(x) for x in r.eigvals],
                       "max_resid_over_hnorm": float(np.max(r.residuals) / r.stats["hnorm_est"]),
                       "converged": bool(r.converged)},
-        "spmm": {"ms": t_spmm * 1e3, "alg_GBps": achieved / 1e9,
-                 "frac_hbm_peak": achieved / HBM_PEAK,
-                 "time_per_op_ns": t_spmm / (H.nnz * b) * 1e9},
+        "spmm": {"in_solve_ms_per_launch": t_live * 1e3, "in_solve_launches": spmm_n,
+                 "in_solve_share_of_tts": spmm_ms / 1e3 / max(sum(times), 1e-30),
+                 "isolated_ms": t_spmm * 1e3, "isolated_alg_GBps": alg / t_spmm / 1e9},
         "reorth_gram_j50": {"ms": t_gram * 1e3, "alg_GBps": gram_bytes / t_gram / 1e9,
                             "fp64_TFLOPs": gram_flops / t_gram / 1e12,
                             "frac_fp64_peak": gram_flops / t_gram / FP64_PEAK},
@@ -244,8 +346,8 @@ def main():
                    "n_trunc": w.n_trunc, "m_max": w.m_max, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK,
-                     "traffic": traffic, "kernel": "k_spmm<float,float,float,float,8,64>",
-                     "alg_bytes_per_launch": alg},
+                     "traffic": traffic, "kernel": "k_spmm<float,float,float,float,8,16>",
+                     "alg_bytes_per_launch": alg, "launch_ms": t_live * 1e3},
         "cpu_baseline": cpu,
         "details": extra,
     }

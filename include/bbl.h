@@ -62,12 +62,18 @@ typedef struct {
   int32_t basis_dtype;  /* storage and SpMM precision of the Krylov basis:
                            BBL_F32 (default for float32 H) or BBL_F64 */
   int32_t check_every;  /* solve the band matrix every this many blocks; 0 = auto */
-  int32_t reserved;     /* must be 0 */
+  int32_t flags;        /* bitwise OR of BBL_FLAG_* (default 0) */
   double defl_tau;      /* deflation threshold on singular values of the
                            residual block relative to max(sigma_max, ||H||)
                            (default 1e-12) */
   uint64_t seed;        /* key of random replacement directions (default 0) */
 } bbl_opts;
+
+/* Option flags.  BBL_FLAG_TIME_SPMM records a pair of HIP events on the
+   solver's stream around every product H V_j of the block recurrence and
+   reports their summed duration in bbl_stats.spmm_ms (costs two event
+   records per block). */
+#define BBL_FLAG_TIME_SPMM 1
 
 /* Counters of one solve and its wall time (host clock around the call). */
 typedef struct {
@@ -79,6 +85,10 @@ typedef struct {
   int32_t reorth_second_passes; /* blocks that needed a second Gram-Schmidt sweep */
   double hnorm_est;     /* largest |Ritz value| of the final band matrix */
   double t_total_ms;    /* wall time of the call */
+  double spmm_ms;       /* summed device time of the recurrence's products H V_j
+                           (BBL_FLAG_TIME_SPMM only, else 0) */
+  int32_t spmm_timed;   /* number of products in spmm_ms */
+  int32_t reserved;
 } bbl_stats;
 
 /* Message describing the last non-OK status on the calling thread. */

@@ -27,6 +27,7 @@ BBL_E_NOT_CONVERGED = -4
 BBL_E_BREAKDOWN = -5
 BBL_F32 = 1
 BBL_F64 = 2
+BBL_FLAG_TIME_SPMM = 1
 
 _STATUS = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "NOT_CONVERGED", -5: "BREAKDOWN"}
 
@@ -45,7 +46,7 @@ class _Csr(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("m_max", ctypes.c_int32), ("basis_dtype", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("defl_tau", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
@@ -53,7 +54,9 @@ class _Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("spmm_calls", ctypes.c_int32),
                 ("deflations", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("checks", ctypes.c_int32), ("reorth_second_passes", ctypes.c_int32),
-                ("hnorm_est", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+                ("hnorm_est", ctypes.c_double), ("t_total_ms", ctypes.c_double),
+                ("spmm_ms", ctypes.c_double), ("spmm_timed", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -159,8 +162,8 @@ class DeviceCSR:
                    torch.from_numpy(np.ascontiguousarray(val)).to(device))
 
 
-def _opts(m_max, basis_dtype, check_every, seed, defl_tau):
-    return _Opts(int(m_max), int(basis_dtype), int(check_every), 0, float(defl_tau),
+def _opts(m_max, basis_dtype, check_every, seed, defl_tau, flags=0):
+    return _Opts(int(m_max), int(basis_dtype), int(check_every), int(flags), float(defl_tau),
                  int(seed) & (2**64 - 1))
 
 
@@ -196,8 +199,10 @@ class LanczosResult:
 
 def block_lanczos(H: DeviceCSR, pivot, k: int, tol: float, *, m_max: int = 200,
                   basis_dtype=None, check_every: int = 0, seed: int = 0, defl_tau: float = 1e-12,
-                  workspace=None, want_vectors: bool = True) -> LanczosResult:
-    """Lowest k eigenpairs of H from the n x nvec float64 pivot block."""
+                  workspace=None, want_vectors: bool = True,
+                  time_spmm: bool = False) -> LanczosResult:
+    """Lowest k eigenpairs of H from the n x nvec float64 pivot block.
+    time_spmm: record device time of every product H V_j (stats spmm_ms)."""
     torch = _torch()
     assert pivot.dtype == torch.float64 and pivot.is_contiguous() and pivot.shape[0] == H.n
     nvec = pivot.shape[1]
@@ -214,7 +219,8 @@ def block_lanczos(H: DeviceCSR, pivot, k: int, tol: float, *, m_max: int = 200,
     X = torch.empty((H.n, k), dtype=torch.float64, device=pivot.device) if want_vectors else None
     st = _Stats()
     Hc = H._c()
-    o = _opts(m_max, basis_dtype, check_every, seed, defl_tau)
+    o = _opts(m_max, basis_dtype, check_every, seed, defl_tau,
+              BBL_FLAG_TIME_SPMM if time_spmm else 0)
     code = lib.bbl_block_lanczos(ctypes.byref(Hc), _ptr(pivot), nvec, k, tol, _ptr(workspace),
                                  workspace.numel(), ctypes.byref(o),
                                  eigvals.ctypes.data_as(ctypes.c_void_p), _ptr(X),

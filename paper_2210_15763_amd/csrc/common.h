@@ -38,6 +38,7 @@ inline void check_launch(const char *what) {
 
 constexpr int kMaxBlock = 32;    // largest supported block size / k
 constexpr int kWave = 64;
+constexpr int kXcds = 8;   // accelerator complex dies of an MI355X, each with its own L2
 
 // Capacity (doubles) of a partial-sum buffer for gram products with at most
 // Mmax columns of X and ny <= nyw columns of Y, including the reduction's

@@ -41,6 +41,7 @@ struct Opts {
   int m_max = 200;
   int basis_dtype = 0;  // 0: from H
   int check_every = 0;
+  int flags = 0;
   double tau = 1e-12;
   uint64_t seed = 0;
 };
@@ -51,6 +52,7 @@ Opts read_opts(const bbl_opts *o, int val_dtype) {
     if (o->m_max > 0) r.m_max = o->m_max;
     r.basis_dtype = o->basis_dtype;
     r.check_every = o->check_every;
+    r.flags = o->flags;
     if (o->defl_tau > 0) r.tau = o->defl_tau;
     r.seed = o->seed;
   }
@@ -105,6 +107,39 @@ void validate_csr(const bbl_csr *H) {
   BBL_REQUIRE(H->val_dtype == BBL_F32 || H->val_dtype == BBL_F64, "H.val_dtype must be F32/F64");
   BBL_REQUIRE(H->reserved == 0, "H.reserved must be 0");
 }
+
+// Optional device timing of the recurrence's products: one event pair per
+// block, read back once at the end of the solve.
+struct SpmmTimer {
+  std::vector<hipEvent_t> ev;
+  SpmmTimer(bool on, int m_max) {
+    if (!on) return;
+    ev.resize(2 * (size_t)m_max, nullptr);
+    for (auto &e : ev) BBL_HIP(hipEventCreate(&e));
+  }
+  ~SpmmTimer() {
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  void begin(int J, hipStream_t s) {
+    if (!ev.empty()) BBL_HIP(hipEventRecord(ev[2 * J], s));
+  }
+  void end(int J, hipStream_t s) {
+    if (!ev.empty()) BBL_HIP(hipEventRecord(ev[2 * J + 1], s));
+  }
+  void collect(int nblk, hipStream_t s, double *ms, int *count) {
+    *ms = 0.0;
+    *count = 0;
+    if (ev.empty()) return;
+    BBL_HIP(hipStreamSynchronize(s));
+    for (int J = 0; J < nblk; ++J) {
+      float t = 0.f;
+      BBL_HIP(hipEventElapsedTime(&t, ev[2 * J], ev[2 * J + 1]));
+      *ms += t;
+      ++*count;
+    }
+  }
+};
 
 struct Solver {
   const bbl_csr &H;
@@ -231,8 +266,8 @@ struct Solver {
 
   struct Result {
     bool converged = false;
-    int iters = 0, spmm_calls = 0, checks = 0;
-    double hnorm = 0.0;
+    int iters = 0, spmm_calls = 0, checks = 0, spmm_timed = 0;
+    double hnorm = 0.0, spmm_ms = 0.0;
     std::vector<double> theta, resid;
   };
 
@@ -293,8 +328,11 @@ struct Solver {
     int last_checked_nblk = 0;
     int next_check = 1;
     std::vector<double> hres(2 * kMaxBlock + 2);
+    SpmmTimer timer(o.flags & BBL_FLAG_TIME_SPMM, o.m_max);
     for (int J = 0; J < o.m_max; ++J) {
+      timer.begin(J, s);
       launch_spmm(H, slot(J), xd, W, xd, b, s);
+      timer.end(J, s);
       ++R.spmm_calls;
       gram(slot(J), xd, b, 1, 0, W, xd, b, Araw);
       launch_set_A(Araw, b, J, band, b, J > 0 ? Bstore + (size_t)(J - 1) * b * b : nullptr, C3,
@@ -346,6 +384,7 @@ struct Solver {
       }
     }
     (void)last_checked_nblk;
+    timer.collect(R.iters, s, &R.spmm_ms, &R.spmm_timed);
     return R;
   }
 };
@@ -414,6 +453,9 @@ int solve_impl(const bbl_csr *H, const double *pivot, int32_t nvec, int32_t k, d
     stats->hnorm_est = R.hnorm;
     stats->t_total_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    stats->spmm_ms = R.spmm_ms;
+    stats->spmm_timed = R.spmm_timed;
+    stats->reserved = 0;
   }
   return R.converged ? BBL_OK : BBL_E_NOT_CONVERGED;
 }

@@ -45,6 +45,17 @@ __device__ __forceinline__ T ldg_stream(const T *p) {
   return *p;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup w runs on
+// XCD w % 8), each XCD with its own L2.  The launch pads the grid to a
+// multiple of 8 and this remap hands XCD x the contiguous row range
+// [x G/8, (x+1) G/8) of blocks, so the workgroups resident on one XCD at a
+// time cover a few neighbouring sectors and their V-row gathers share that
+// XCD's L2 instead of every XCD caching every sector.
+__device__ __forceinline__ int64_t xcd_block(int64_t w) {
+  const int64_t per = gridDim.x / kXcds;
+  return (w % kXcds) * per + w / kXcds;
+}
+
 template <typename VT, typename XT, typename AT, typename YT, int B, int LPR>
 __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int64_t *__restrict__ rp,
                                               const int32_t *__restrict__ col,
@@ -53,7 +64,7 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int64_t *__restri
   constexpr int RPW = kWave / LPR;
   const int lane = threadIdx.x & (kWave - 1);
   const int sub = lane & (LPR - 1);
-  const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int64_t wave_id = xcd_block(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x / kWave);
   const int64_t row = wave_id * RPW + lane / LPR;
   AT acc[B];
 #pragma unroll
@@ -117,7 +128,7 @@ __global__ __launch_bounds__(256) void k_spmm_generic(int64_t n, const int64_t *
   constexpr int RPW = kWave / LPR;
   const int lane = threadIdx.x & (kWave - 1);
   const int sub = lane & (LPR - 1);
-  const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int64_t wave_id = xcd_block(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x / kWave);
   const int64_t row = wave_id * RPW + lane / LPR;
   AT acc[kMaxBlock];
 #pragma unroll
@@ -224,7 +235,7 @@ int pick_lpr(const bbl_csr &H) {
 template <typename VT, typename XT, typename AT, typename YT, int LPR>
 void spmm_dispatch_b(const bbl_csr &H, const XT *X, YT *Y, int nvec, hipStream_t s) {
   const int rows_per_wg = (256 / kWave) * (kWave / LPR);
-  const int64_t grid = ceil_div(H.n, rows_per_wg);
+  const int64_t grid = ceil_div(ceil_div(H.n, rows_per_wg), kXcds) * kXcds;
   const VT *val = static_cast<const VT *>(H.val);
 #define BBL_SPMM_CASE(BV)                                                                        \
   case BV:                                                                                       \

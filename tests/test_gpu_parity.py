@@ -108,7 +108,8 @@ def test_spmm_bitwise_reproducible(torch, bbl):
 # ------------------------------------------------------- tall-skinny products
 @pytest.mark.parametrize("bx,nblk,ny,xf32", [(8, 3, 8, True), (16, 2, 16, True), (4, 5, 4, False),
                                              (10, 3, 10, True), (8, 1, 20, False),
-                                             (8, 7, 8, False)])
+                                             (8, 7, 8, False), (8, 9, 8, True), (8, 37, 8, True),
+                                             (8, 1, 8, True), (8, 1, 8, False), (4, 1, 4, True)])
 def test_gram_and_update_match_numpy(torch, bbl, bx, nblk, ny, xf32):
     note("gram/update bx=%d nblk=%d ny=%d f32=%s" % (bx, nblk, ny, xf32))
     rng = np.random.default_rng(bx * 100 + nblk)
@@ -223,6 +224,19 @@ def test_small_fp64_workload_matches_oracle(torch, bbl):
     r2 = bbl.block_lanczos(Hd, dev(torch, Pref), w.k, w.tol, m_max=w.m_max, check_every=1)
     assert abs(r2.stats["iters"] - ro.iters) <= 1, (r2.stats["iters"], ro.iters)
     np.testing.assert_allclose(r2.eigvals, ro.eigvals, rtol=1e-10)
+
+
+def test_spmm_timing_flag_times_every_block_and_changes_nothing(torch, bbl):
+    note("BBL_FLAG_TIME_SPMM")
+    w = synthgen.WORKLOADS["small_fp64_n2e4"]
+    H = w.generate()
+    Hd = bbl.DeviceCSR.from_host(H, "float64")
+    P = bbl.random_pivot(H.n, 4, synthgen.pivot_key(3))
+    a = bbl.block_lanczos(Hd, P, 4, 1e-8, m_max=300)
+    t = bbl.block_lanczos(Hd, P, 4, 1e-8, m_max=300, time_spmm=True)
+    assert a.stats["spmm_timed"] == 0 and a.stats["spmm_ms"] == 0.0
+    assert t.stats["spmm_timed"] == t.stats["iters"] and t.stats["spmm_ms"] > 0
+    assert np.array_equal(a.eigvals, t.eigvals) and a.stats["iters"] == t.stats["iters"]
 
 
 def test_random_pivot_finds_same_eigenvalues(torch, bbl):
