@@ -14,8 +14,11 @@ large-dimension eigenvalue problems" (arXiv 2210.15763):
 * ``scalar_lanczos``  -- the single-vector method (Algorithm "Lanczos method").
 * ``bootstrap_pivot`` -- the pivot block built from eigenvectors of a
                          truncated leading block (Methods, last paragraphs).
-* ``mlp``             -- a float64 reference of the learned pivot proposer's
-                         network (not in the paper; see that module).
+* ``pivot``           -- a float64 reference of the learned pivot proposer:
+                         its per-row features (one-hop extension of truncated
+                         eigenvectors plus Rayleigh-Ritz), the network's
+                         forward/backward pass, Adam, Procrustes targets and
+                         the fallback rule (not in the paper; see that module).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU-baseline
 leg may import this package.  It shares no code with the HIP path; the only
