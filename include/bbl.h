@@ -207,6 +207,112 @@ int bbl_block_update(int64_t n, const void *X, int32_t xdtype, int32_t bx, int32
                      const double *C, int32_t ny, double alpha, const void *Yin, int32_t yindtype,
                      double beta, void *Yout, int32_t youtdtype, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned pivot proposer.  The paper's bootstrapped pivot comes from
+ * eigenvectors of a truncated leading block, and the Results discussion shows
+ * such a pivot can miss target states that live outside the truncation.  The
+ * paper does not describe a learned proposer; these entry points implement
+ * one (a per-row network fed by truncation-derived features), with the plain
+ * bootstrap block as the fallback.  Layouts: features bf16 [rows][28]
+ * (bfloat16 bit patterns), network outputs and targets float32 [rows][10],
+ * parameters float32 [38026] in the order W1 (128 x 28, row = output unit),
+ * b1, W2 (128 x 128), b2, W3 (128 x 128), b3, W4 (10 x 128), b4.  All
+ * pointers are device memory unless marked host; the caller owns them.
+ * ------------------------------------------------------------------------ */
+#define BBL_MLP_IN 28
+#define BBL_MLP_OUT 10
+#define BBL_MLP_PARAMS 38026
+
+/*
+ * Per-row features of H.  The lowest 20 eigenpairs of the leading block
+ * H[0:n_trunc, 0:n_trunc] (block Lanczos, block size 10, random pivot of key
+ * (opts->seed + 1) ^ 0x9E3779B97F4A7C15, tolerance tol) are extended one hop
+ * outside the truncation by first-order perturbation theory,
+ * y_ia = (H P)_ia / (theta_a - H_ii) with |denominator| clamped to >= 1; the
+ * 10 lowest Rayleigh-Ritz vectors of H on their span form P_D (unit columns,
+ * largest-magnitude entry positive).  Row i of the features holds
+ *   [0] (H_ii - mean) / std over the diagonal (population std),
+ *   [1..16] sin, cos of 2 pi f s / S, f = 1..8, sector s = i / sector_size of
+ *       S = ceil(n / sector_size),
+ *   [17] nnz of row i / (nnz / n),
+ *   [18..27] sqrt(n) P_D[i][0..10).
+ *   feats    device n x 28 bfloat16 (round to nearest even)
+ *   feats32  optional device n x 28 float32 (the values before rounding)
+ *   p_d      optional device n x 10 float64: P_D
+ *   p_boot   optional device n x 10 float64: the lowest 10 truncated
+ *            eigenvectors, zero padded (the plain bootstrap block)
+ *   theta_d  optional host [10]: Ritz values of P_D
+ *   stats    optional host: statistics of the truncated solve
+ * n_trunc must be in 20..n; BBL_E_BREAKDOWN if the extended block is rank
+ * deficient.
+ */
+size_t bbl_features_workspace_size(const bbl_csr *H, int64_t n_trunc, int32_t m_max,
+                                   int32_t basis_dtype, void *stream);
+int bbl_pivot_features(const bbl_csr *H, int64_t n_trunc, int64_t sector_size, double tol,
+                       void *ws, size_t ws_bytes, const bbl_opts *opts, uint16_t *feats,
+                       float *feats32, double *p_d, double *p_boot, double *theta_d,
+                       bbl_stats *stats, void *stream);
+
+/*
+ * Training targets: T = sqrt(n) X Q in float32, Q the orthogonal polar factor
+ * of X^T P (the Procrustes rotation taking X closest to P; Schoenemann 1966).
+ * X, P device n x m float64 (m <= 32).  BBL_E_BREAKDOWN if X^T P is singular.
+ */
+size_t bbl_procrustes_workspace_size(int64_t n, int32_t m);
+int bbl_procrustes_targets(const double *X, const double *P, int64_t n, int32_t m, void *ws,
+                           size_t ws_bytes, float *targets, void *stream);
+
+/*
+ * Network 28 -> 128 -> 128 -> 128 -> 10 with ReLU after the first three
+ * layers; bfloat16 operands on matrix cores, float32 accumulation, float32
+ * parameters (rounded to bfloat16 on load), bfloat16 hidden activations.
+ * bbl_mlp_init: He-uniform weights (bound sqrt(6 / fan_in)) from Philox
+ *   counter (index, 0, 0, 11) under key `seed`, zero biases.
+ * bbl_mlp_forward: out = network(feats) for `rows` rows.
+ * bbl_mlp_grad: grad = d loss / d params and *loss (device float, may be
+ *   NULL) of loss = mean over rows x 10 outputs of (out - targets)^2;
+ *   deterministic (fixed-order partial sums).
+ * bbl_adam_step: Adam with bias correction at step >= 1 on `count` values.
+ * bbl_mlp_train_step: samples `batch` rows uniformly with replacement
+ *   (Philox counter (r, step, 0, 12) under sample_key, modulo dataset_rows),
+ *   computes the gradient on them and applies one Adam step (beta1 0.9,
+ *   beta2 0.999, eps 1e-8); *loss is the batch loss before the step.
+ */
+int bbl_mlp_init(float *params, uint64_t seed, void *stream);
+int bbl_mlp_forward(const float *params, const uint16_t *feats, int64_t rows, float *out,
+                    void *stream);
+size_t bbl_mlp_grad_workspace_size(int64_t rows);
+int bbl_mlp_grad(const float *params, const uint16_t *feats, const float *targets, int64_t rows,
+                 void *ws, size_t ws_bytes, float *grad, float *loss, void *stream);
+int bbl_adam_step(float *params, float *m, float *v, const float *grad, int64_t count,
+                  int32_t step, float lr, float beta1, float beta2, float eps, void *stream);
+size_t bbl_mlp_train_workspace_size(int64_t batch);
+int bbl_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t step, float lr,
+                       const uint16_t *feats, const float *targets, int64_t dataset_rows,
+                       int64_t batch, uint64_t sample_key, void *ws, size_t ws_bytes,
+                       float *loss, void *stream);
+
+/*
+ * Learned pivot block: features of H (as bbl_pivot_features), the network's
+ * first nvec outputs as the n x nvec block, then the fallback rule: the plain
+ * bootstrap block (lowest nvec truncated eigenvectors, zero padded) is used
+ * instead if the learned block has a non-finite entry, if a squared pivot of
+ * the Cholesky factor of its Gram matrix is not above 1e-8 of the largest
+ * diagonal entry, or if the sum of its k lowest Rayleigh-Ritz values is not
+ * below that of the bootstrap block.
+ *   nvec          1..10;  k  number of Ritz values compared (min(k, nvec))
+ *   pivot         device n x nvec float64 output (not orthonormalised)
+ *   used_fallback host, 1 if the bootstrap block was returned
+ *   rr_sums       host [2]: the two sums (learned, bootstrap), NaN when the
+ *                 learned block failed an earlier test
+ */
+size_t bbl_learned_pivot_workspace_size(const bbl_csr *H, int64_t n_trunc, int32_t nvec,
+                                        int32_t m_max, int32_t basis_dtype, void *stream);
+int bbl_learned_pivot(const bbl_csr *H, const float *params, int64_t n_trunc, int64_t sector_size,
+                      int32_t nvec, int32_t k, double tol, void *ws, size_t ws_bytes,
+                      const bbl_opts *opts, double *pivot, int32_t *used_fallback,
+                      double *rr_sums, bbl_stats *stats, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -170,6 +170,17 @@ def procrustes_targets(X: np.ndarray, PD: np.ndarray) -> np.ndarray:
 
 
 # ------------------------------------------------------------------ network
+def round_bf16(x) -> np.ndarray:
+    """Nearest bfloat16 value (8-bit significand, float32 exponent range),
+    ties to even, taken from the float32 bit pattern; NaN stays NaN."""
+    f = np.atleast_1d(np.asarray(x, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    r = (u & 0xFFFFFFFF).astype(np.uint32).view(np.float32).astype(np.float64)
+    r[np.isnan(f)] = np.nan
+    return r.reshape(np.shape(x))
+
+
 def unpack(params: np.ndarray):
     out, o = [], 0
     for s in SHAPES:
@@ -179,20 +190,33 @@ def unpack(params: np.ndarray):
     return out
 
 
-def forward(params: np.ndarray, F: np.ndarray):
-    """Activations [F, h1, h2, h3] and the output [rows][10]."""
+def _layers(params: np.ndarray, act: str):
     W1, b1, W2, b2, W3, b3, W4, b4 = unpack(params)
-    h1 = np.maximum(F @ W1.T + b1, 0.0)
-    h2 = np.maximum(h1 @ W2.T + b2, 0.0)
-    h3 = np.maximum(h2 @ W3.T + b3, 0.0)
+    if act == "bf16":
+        W1, W2, W3, W4 = (round_bf16(W) for W in (W1, W2, W3, W4))
+    return W1, b1, W2, b2, W3, b3, W4, b4
+
+
+def forward(params: np.ndarray, F: np.ndarray, act: str = "f64"):
+    """Activations [F, h1, h2, h3] and the output [rows][10].  act="bf16"
+    evaluates the network the way the matrix-core kernels do: weights and
+    hidden activations rounded to bfloat16, so every ReLU decision is taken on
+    the same values; the arithmetic itself stays float64."""
+    W1, b1, W2, b2, W3, b3, W4, b4 = _layers(params, act)
+    rnd = round_bf16 if act == "bf16" else (lambda x: x)
+    h1 = rnd(np.maximum(F @ W1.T + b1, 0.0))
+    h2 = rnd(np.maximum(h1 @ W2.T + b2, 0.0))
+    h3 = rnd(np.maximum(h2 @ W3.T + b3, 0.0))
     return [F, h1, h2, h3], h3 @ W4.T + b4
 
 
-def loss_and_grad(params: np.ndarray, F: np.ndarray, T: np.ndarray):
+def loss_and_grad(params: np.ndarray, F: np.ndarray, T: np.ndarray, act: str = "f64"):
     """Mean squared error over rows x outputs and its gradient (chain rule
-    through the four layers; ReLU derivative 1 where the activation > 0)."""
-    W1, b1, W2, b2, W3, b3, W4, b4 = unpack(params)
-    (h0, h1, h2, h3), out = forward(params, F)
+    through the four layers; ReLU derivative 1 where the activation > 0).
+    act as in forward(); with "bf16" the chain rule runs through the rounded
+    weights and activations of that forward pass."""
+    W1, b1, W2, b2, W3, b3, W4, b4 = _layers(params, act)
+    (h0, h1, h2, h3), out = forward(params, F, act)
     diff = out - T
     loss = float(np.mean(diff * diff))
     d4 = 2.0 * diff / diff.size

@@ -68,7 +68,14 @@ _lib = None
 EXPORTS = ("bbl_last_error", "bbl_version", "bbl_spmm", "bbl_lanczos_workspace_size",
            "bbl_block_lanczos", "bbl_bootstrap_workspace_size", "bbl_bootstrap_pivot",
            "bbl_random_pivot", "bbl_band_eig_workspace_size", "bbl_band_eig",
-           "bbl_gram_workspace_size", "bbl_gram", "bbl_block_update")
+           "bbl_gram_workspace_size", "bbl_gram", "bbl_block_update",
+           "bbl_features_workspace_size", "bbl_pivot_features", "bbl_procrustes_workspace_size",
+           "bbl_procrustes_targets", "bbl_mlp_init", "bbl_mlp_forward",
+           "bbl_mlp_grad_workspace_size", "bbl_mlp_grad", "bbl_adam_step",
+           "bbl_mlp_train_workspace_size", "bbl_mlp_train_step",
+           "bbl_learned_pivot_workspace_size", "bbl_learned_pivot")
+
+MLP_IN, MLP_OUT, MLP_PARAMS = 28, 10, 38026
 
 
 def load_library(path: str = LIB_PATH):
@@ -97,6 +104,22 @@ def load_library(path: str = LIB_PATH):
         "bbl_gram": (ctypes.c_int, [I64, P, I32, I32, I32, P, I32, I32, P, P, SZ, P]),
         "bbl_block_update": (ctypes.c_int, [I64, P, I32, I32, I32, P, I32, D, P, I32, D, P, I32,
                                             P]),
+        "bbl_features_workspace_size": (SZ, [P, I64, I32, I32, P]),
+        "bbl_pivot_features": (ctypes.c_int, [P, I64, I64, D, P, SZ, P, P, P, P, P, P, P, P]),
+        "bbl_procrustes_workspace_size": (SZ, [I64, I32]),
+        "bbl_procrustes_targets": (ctypes.c_int, [P, P, I64, I32, P, SZ, P, P]),
+        "bbl_mlp_init": (ctypes.c_int, [P, U64, P]),
+        "bbl_mlp_forward": (ctypes.c_int, [P, P, I64, P, P]),
+        "bbl_mlp_grad_workspace_size": (SZ, [I64]),
+        "bbl_mlp_grad": (ctypes.c_int, [P, P, P, I64, P, SZ, P, P, P]),
+        "bbl_adam_step": (ctypes.c_int, [P, P, P, P, I64, I32, ctypes.c_float, ctypes.c_float,
+                                         ctypes.c_float, ctypes.c_float, P]),
+        "bbl_mlp_train_workspace_size": (SZ, [I64]),
+        "bbl_mlp_train_step": (ctypes.c_int, [P, P, P, I32, ctypes.c_float, P, P, I64, I64, U64,
+                                              P, SZ, P, P]),
+        "bbl_learned_pivot_workspace_size": (SZ, [P, I64, I32, I32, I32, P]),
+        "bbl_learned_pivot": (ctypes.c_int, [P, P, I64, I64, I32, I32, D, P, SZ, P, P, P, P, P,
+                                             P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -307,3 +330,129 @@ def block_update(X, nblk: int, bx: int, C, alpha: float, Yin, beta: float, Yout)
         _dtype_code(Yin) if Yin is not None else BBL_F64, beta, _ptr(Yout), _dtype_code(Yout),
         _stream()))
     return Yout
+
+
+# ------------------------------------------------------------ learned pivot
+def _ws(nbytes, device):
+    torch = _torch()
+    if nbytes == 0:
+        raise BblError(BBL_E_INVALID, load_library().bbl_last_error().decode() or "bad sizes")
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def pivot_features(H: DeviceCSR, n_trunc: int, sector_size: int, tol: float, *, m_max: int = 200,
+                   seed: int = 0, basis_dtype=None, want_f32: bool = False):
+    """Per-row features (bf16 bit patterns as int16, n x 28), optionally their
+    float32 values, P_D, the plain bootstrap block of 10 and P_D's Ritz values."""
+    torch = _torch()
+    lib = load_library()
+    dev = H.row_ptr.device
+    if basis_dtype is None:
+        basis_dtype = _dtype_code(H.val)
+    Hc = H._c()
+    ws = _ws(lib.bbl_features_workspace_size(ctypes.byref(Hc), n_trunc, m_max, basis_dtype,
+                                             _stream()), dev)
+    F = torch.empty((H.n, MLP_IN), dtype=torch.int16, device=dev)
+    F32 = torch.empty((H.n, MLP_IN), dtype=torch.float32, device=dev) if want_f32 else None
+    PD = torch.empty((H.n, MLP_OUT), dtype=torch.float64, device=dev)
+    PB = torch.empty((H.n, MLP_OUT), dtype=torch.float64, device=dev)
+    th = np.zeros(MLP_OUT)
+    st = _Stats()
+    o = _opts(m_max, basis_dtype, 0, seed, 1e-12)
+    _check(lib.bbl_pivot_features(ctypes.byref(Hc), n_trunc, sector_size, tol, _ptr(ws),
+                                  ws.numel(), ctypes.byref(o), _ptr(F), _ptr(F32), _ptr(PD),
+                                  _ptr(PB), th.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st),
+                                  _stream()))
+    return {"feats": F, "feats32": F32, "p_d": PD, "p_boot": PB, "theta_d": th,
+            "stats": st.as_dict()}
+
+
+def procrustes_targets(X, P):
+    """float32 sqrt(n) X Q, Q the polar factor of X^T P (X, P: n x m float64)."""
+    torch = _torch()
+    lib = load_library()
+    n, m = X.shape
+    ws = _ws(lib.bbl_procrustes_workspace_size(n, m), X.device)
+    T = torch.empty((n, m), dtype=torch.float32, device=X.device)
+    _check(lib.bbl_procrustes_targets(_ptr(X), _ptr(P), n, m, _ptr(ws), ws.numel(), _ptr(T),
+                                      _stream()))
+    return T
+
+
+def mlp_init(seed: int, device="cuda"):
+    torch = _torch()
+    p = torch.empty(MLP_PARAMS, dtype=torch.float32, device=device)
+    _check(load_library().bbl_mlp_init(_ptr(p), int(seed) & (2**64 - 1), _stream()))
+    return p
+
+
+def mlp_forward(params, feats):
+    torch = _torch()
+    out = torch.empty((feats.shape[0], MLP_OUT), dtype=torch.float32, device=feats.device)
+    _check(load_library().bbl_mlp_forward(_ptr(params), _ptr(feats), feats.shape[0], _ptr(out),
+                                          _stream()))
+    return out
+
+
+def mlp_grad(params, feats, targets):
+    """(grad float32 [38026], loss float32 device scalar)."""
+    torch = _torch()
+    lib = load_library()
+    rows = feats.shape[0]
+    ws = _ws(lib.bbl_mlp_grad_workspace_size(rows), feats.device)
+    g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=feats.device)
+    loss = torch.empty(1, dtype=torch.float32, device=feats.device)
+    _check(lib.bbl_mlp_grad(_ptr(params), _ptr(feats), _ptr(targets), rows, _ptr(ws), ws.numel(),
+                            _ptr(g), _ptr(loss), _stream()))
+    return g, loss
+
+
+def adam_step(params, m, v, grad, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(load_library().bbl_adam_step(_ptr(params), _ptr(m), _ptr(v), _ptr(grad),
+                                        params.numel(), step, lr, beta1, beta2, eps, _stream()))
+
+
+class MlpTrainer:
+    """Adam state plus a reusable workspace for bbl_mlp_train_step."""
+
+    def __init__(self, params, batch: int, sample_key: int = 0):
+        torch = _torch()
+        self.params = params
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.batch = int(batch)
+        self.key = int(sample_key) & (2**64 - 1)
+        self.step_no = 0
+        self.ws = _ws(load_library().bbl_mlp_train_workspace_size(self.batch), params.device)
+        self.loss = torch.empty(1, dtype=torch.float32, device=params.device)
+
+    def step(self, feats, targets, lr: float):
+        self.step_no += 1
+        _check(load_library().bbl_mlp_train_step(
+            _ptr(self.params), _ptr(self.m), _ptr(self.v), self.step_no, lr, _ptr(feats),
+            _ptr(targets), feats.shape[0], self.batch, self.key, _ptr(self.ws), self.ws.numel(),
+            _ptr(self.loss), _stream()))
+        return self.loss
+
+
+def learned_pivot(H: DeviceCSR, params, n_trunc: int, sector_size: int, nvec: int, k: int,
+                  tol: float, *, m_max: int = 200, seed: int = 0, basis_dtype=None):
+    """(pivot n x nvec float64, info dict with used_fallback and rr_sums)."""
+    torch = _torch()
+    lib = load_library()
+    dev = H.row_ptr.device
+    if basis_dtype is None:
+        basis_dtype = _dtype_code(H.val)
+    Hc = H._c()
+    ws = _ws(lib.bbl_learned_pivot_workspace_size(ctypes.byref(Hc), n_trunc, nvec, m_max,
+                                                  basis_dtype, _stream()), dev)
+    P = torch.empty((H.n, nvec), dtype=torch.float64, device=dev)
+    fb = ctypes.c_int32(0)
+    sums = np.zeros(2)
+    st = _Stats()
+    o = _opts(m_max, basis_dtype, 0, seed, 1e-12)
+    _check(lib.bbl_learned_pivot(ctypes.byref(Hc), _ptr(params), n_trunc, sector_size, nvec, k,
+                                 tol, _ptr(ws), ws.numel(), ctypes.byref(o), _ptr(P),
+                                 ctypes.byref(fb), sums.ctypes.data_as(ctypes.c_void_p),
+                                 ctypes.byref(st), _stream()))
+    return P, {"used_fallback": bool(fb.value), "rr_sums": sums, "stats": st.as_dict()}

@@ -21,6 +21,7 @@
 
 #include "bandeig.h"
 #include "common.h"
+#include "driver.h"
 #include "pivot.h"
 #include "small.h"
 
@@ -37,28 +38,6 @@ constexpr int kHn2Slot = 200;          // dres slot: max |A_jj| seen so far (<= 
 
 size_t dsize(int dt) { return dt == BBL_F32 ? 4 : 8; }
 
-struct Opts {
-  int m_max = 200;
-  int basis_dtype = 0;  // 0: from H
-  int check_every = 0;
-  int flags = 0;
-  double tau = 1e-12;
-  uint64_t seed = 0;
-};
-
-Opts read_opts(const bbl_opts *o, int val_dtype) {
-  Opts r;
-  if (o) {
-    if (o->m_max > 0) r.m_max = o->m_max;
-    r.basis_dtype = o->basis_dtype;
-    r.check_every = o->check_every;
-    r.flags = o->flags;
-    if (o->defl_tau > 0) r.tau = o->defl_tau;
-    r.seed = o->seed;
-  }
-  if (r.basis_dtype == 0) r.basis_dtype = val_dtype;
-  return r;
-}
 
 struct Layout {
   size_t basis, W, Wp, X, partial, C, band, Bstore, mats, ints, dres, S, eig, norm, total;
@@ -98,15 +77,6 @@ Layout make_layout(int64_t n, int b, int k, int m_max, int bdt) {
   return L;
 }
 
-void validate_csr(const bbl_csr *H) {
-  BBL_REQUIRE(H != nullptr, "H is NULL");
-  BBL_REQUIRE(H->n >= 1, "H.n must be >= 1");
-  BBL_REQUIRE(H->n <= (int64_t)INT32_MAX, "H.n exceeds int32 column range");
-  BBL_REQUIRE(H->nnz >= 0, "H.nnz must be >= 0");
-  BBL_REQUIRE(H->row_ptr && (H->nnz == 0 || (H->col && H->val)), "H has NULL arrays");
-  BBL_REQUIRE(H->val_dtype == BBL_F32 || H->val_dtype == BBL_F64, "H.val_dtype must be F32/F64");
-  BBL_REQUIRE(H->reserved == 0, "H.reserved must be 0");
-}
 
 // Optional device timing of the recurrence's products: one event pair per
 // block, read back once at the end of the solve.
@@ -389,6 +359,59 @@ struct Solver {
   }
 };
 
+
+
+
+
+struct TruncLayout {
+  size_t rp, col, val, piv, inner, total;
+};
+
+TruncLayout trunc_layout(int64_t n_t, int64_t nnz_t, int b, int k, int m_max, int bdt, int vdt) {
+  TruncLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  L.rp = take((size_t)(n_t + 1) * 8);
+  L.col = take((size_t)std::max<int64_t>(nnz_t, 1) * 4);
+  L.val = take((size_t)std::max<int64_t>(nnz_t, 1) * dsize(vdt));
+  L.piv = take((size_t)n_t * b * 8);
+  L.inner = take(make_layout(n_t, b, k, m_max, bdt).total + 256);
+  L.total = off + 256;
+  return L;
+}
+
+}  // namespace
+
+Opts read_opts(const bbl_opts *o, int val_dtype) {
+  Opts r;
+  if (o) {
+    if (o->m_max > 0) r.m_max = o->m_max;
+    r.basis_dtype = o->basis_dtype;
+    r.check_every = o->check_every;
+    r.flags = o->flags;
+    if (o->defl_tau > 0) r.tau = o->defl_tau;
+    r.seed = o->seed;
+  }
+  if (r.basis_dtype == 0) r.basis_dtype = val_dtype;
+  return r;
+}
+
+
+void validate_csr(const bbl_csr *H) {
+  BBL_REQUIRE(H != nullptr, "H is NULL");
+  BBL_REQUIRE(H->n >= 1, "H.n must be >= 1");
+  BBL_REQUIRE(H->n <= (int64_t)INT32_MAX, "H.n exceeds int32 column range");
+  BBL_REQUIRE(H->nnz >= 0, "H.nnz must be >= 0");
+  BBL_REQUIRE(H->row_ptr && (H->nnz == 0 || (H->col && H->val)), "H has NULL arrays");
+  BBL_REQUIRE(H->val_dtype == BBL_F32 || H->val_dtype == BBL_F64, "H.val_dtype must be F32/F64");
+  BBL_REQUIRE(H->reserved == 0, "H.reserved must be 0");
+}
+
+
 int64_t read_row_ptr(const bbl_csr &H, int64_t i, hipStream_t s) {
   int64_t v = 0;
   BBL_HIP(hipMemcpyAsync(&v, H.row_ptr + i, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -396,22 +419,8 @@ int64_t read_row_ptr(const bbl_csr &H, int64_t i, hipStream_t s) {
   return v;
 }
 
-template <typename F>
-int guarded(F &&f) {
-  try {
-    return f();
-  } catch (const Error &e) {
-    set_error(e.msg);
-    return e.code;
-  } catch (const std::exception &e) {
-    set_error(e.what());
-    return BBL_E_INVALID;
-  } catch (...) {
-    set_error("unknown error");
-    return BBL_E_INVALID;
-  }
-}
 
+namespace {
 void check_solver_args(const bbl_csr *H, int nvec, int k, const Opts &o) {
   validate_csr(H);
   BBL_REQUIRE(nvec >= 1 && nvec <= kMaxBlock, "nvec must be in 1..32");
@@ -423,6 +432,7 @@ void check_solver_args(const bbl_csr *H, int nvec, int k, const Opts &o) {
               "a float32 basis needs float32 matrix values");
   BBL_REQUIRE((int64_t)o.m_max * nvec <= 8192, "m_max * nvec must be <= 8192");
 }
+}  // namespace
 
 int solve_impl(const bbl_csr *H, const double *pivot, int32_t nvec, int32_t k, double tol,
                void *ws, size_t ws_bytes, const Opts &o, double *eigvals, double *eigvecs,
@@ -460,28 +470,44 @@ int solve_impl(const bbl_csr *H, const double *pivot, int32_t nvec, int32_t k, d
   return R.converged ? BBL_OK : BBL_E_NOT_CONVERGED;
 }
 
-struct BootLayout {
-  size_t rp, col, val, piv, inner, total;
-};
-
-BootLayout boot_layout(int64_t n_t, int64_t nnz_t, int b, int m_max, int bdt, int vdt) {
-  BootLayout L{};
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    const size_t o = off;
-    off += align_up(bytes);
-    return o;
-  };
-  L.rp = take((size_t)(n_t + 1) * 8);
-  L.col = take((size_t)std::max<int64_t>(nnz_t, 1) * 4);
-  L.val = take((size_t)std::max<int64_t>(nnz_t, 1) * dsize(vdt));
-  L.piv = take((size_t)n_t * b * 8);
-  L.inner = take(make_layout(n_t, b, b, m_max, bdt).total + 256);
-  L.total = off + 256;
-  return L;
+size_t truncated_ws_bytes(const bbl_csr &H, int64_t n_t, int b, int k, const Opts &o,
+                          hipStream_t s) {
+  const int bdt = o.basis_dtype ? o.basis_dtype : H.val_dtype;
+  const int64_t nnz_t = read_row_ptr(H, n_t, s);
+  return trunc_layout(n_t, nnz_t, b, k, o.m_max, bdt, H.val_dtype).total;
 }
 
-}  // namespace
+int truncated_solve(const bbl_csr &H, int64_t n_t, int b, int k, double tol, const Opts &o,
+                    void *ws, size_t ws_bytes, double *eigvecs_t, double *theta,
+                    bbl_stats *stats, hipStream_t s) {
+  BBL_REQUIRE(n_t >= b && n_t >= k && n_t <= H.n, "truncation must be in max(nvec, k)..n");
+  const int bdt = o.basis_dtype ? o.basis_dtype : H.val_dtype;
+  const int64_t nnz_t = read_row_ptr(H, n_t, s);
+  const TruncLayout L = trunc_layout(n_t, nnz_t, b, k, o.m_max, bdt, H.val_dtype);
+  if (ws_bytes < L.total) throw Error{BBL_E_NOMEM, "truncated-solve workspace too small"};
+  char *base = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
+  int64_t *rp_t = reinterpret_cast<int64_t *>(base + L.rp);
+  int32_t *col_t = reinterpret_cast<int32_t *>(base + L.col);
+  void *val_t = base + L.val;
+  double *piv_t = reinterpret_cast<double *>(base + L.piv);
+  launch_slice_leading(H, n_t, rp_t, col_t, val_t, s);
+  bbl_csr Ht{};
+  Ht.n = n_t;
+  Ht.nnz = read_row_ptr(bbl_csr{n_t, 0, rp_t, nullptr, nullptr, BBL_F64, 0}, n_t, s);
+  Ht.row_ptr = rp_t;
+  Ht.col = col_t;
+  Ht.val = val_t;
+  Ht.val_dtype = H.val_dtype;
+  // random pivot of the truncated problem, key (seed + 1) ^ golden ratio
+  const uint64_t key = (o.seed + 1) ^ 0x9E3779B97F4A7C15ull;
+  launch_gauss(n_t, b, b, 0, key, 6, piv_t, nullptr, nullptr, s);
+  Opts oi = o;
+  oi.seed = o.seed + 1;
+  oi.basis_dtype = bdt;
+  return solve_impl(&Ht, piv_t, b, k, tol, base + L.inner, L.total - L.inner, oi, theta,
+                    eigvecs_t, nullptr, stats, s);
+}
+
 }  // namespace bbl
 
 using namespace bbl;
@@ -535,9 +561,10 @@ size_t bbl_bootstrap_workspace_size(const bbl_csr *H, int64_t n_trunc, int32_t n
     BBL_REQUIRE(nvec >= 1 && nvec <= kMaxBlock, "nvec must be in 1..32");
     BBL_REQUIRE(n_trunc >= nvec && n_trunc <= H->n, "n_trunc must be in nvec..n");
     BBL_REQUIRE(m_max >= 1, "m_max must be >= 1");
-    const int bdt = basis_dtype ? basis_dtype : H->val_dtype;
-    const int64_t nnz_t = read_row_ptr(*H, n_trunc, static_cast<hipStream_t>(stream));
-    r = boot_layout(n_trunc, nnz_t, nvec, m_max, bdt, H->val_dtype).total;
+    Opts o;
+    o.m_max = m_max;
+    o.basis_dtype = basis_dtype;
+    r = truncated_ws_bytes(*H, n_trunc, nvec, nvec, o, static_cast<hipStream_t>(stream));
     return (int)BBL_OK;
   });
   return st == BBL_OK ? r : 0;
@@ -552,31 +579,11 @@ int bbl_bootstrap_pivot(const bbl_csr *H, int64_t n_trunc, int32_t nvec, double 
     BBL_REQUIRE(nvec >= 1 && nvec <= kMaxBlock, "nvec must be in 1..32");
     BBL_REQUIRE(n_trunc >= nvec && n_trunc <= H->n, "n_trunc must be in nvec..n");
     BBL_REQUIRE(pivot && ws, "pivot/workspace is NULL");
-    Opts o = read_opts(opts, H->val_dtype);
-    const int64_t nnz_t = read_row_ptr(*H, n_trunc, s);
-    const BootLayout L = boot_layout(n_trunc, nnz_t, nvec, o.m_max, o.basis_dtype, H->val_dtype);
-    if (ws_bytes < L.total) throw Error{BBL_E_NOMEM, "bootstrap workspace too small"};
-    char *base = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
-    int64_t *rp_t = reinterpret_cast<int64_t *>(base + L.rp);
-    int32_t *col_t = reinterpret_cast<int32_t *>(base + L.col);
-    void *val_t = base + L.val;
-    double *piv_t = reinterpret_cast<double *>(base + L.piv);
-    launch_slice_leading(*H, n_trunc, rp_t, col_t, val_t, s);
-    bbl_csr Ht{};
-    Ht.n = n_trunc;
-    Ht.nnz = read_row_ptr(bbl_csr{n_trunc, 0, rp_t, nullptr, nullptr, BBL_F64, 0}, n_trunc, s);
-    Ht.row_ptr = rp_t;
-    Ht.col = col_t;
-    Ht.val = val_t;
-    Ht.val_dtype = H->val_dtype;
-    // random pivot of the truncated problem, key (seed + 1) ^ golden ratio
-    const uint64_t key = (o.seed + 1) ^ 0x9E3779B97F4A7C15ull;
-    launch_gauss(n_trunc, nvec, nvec, 0, key, 6, piv_t, nullptr, nullptr, s);
+    const Opts o = read_opts(opts, H->val_dtype);
     std::vector<double> ev(nvec);
-    Opts oi = o;
-    oi.seed = o.seed + 1;
-    const int st = solve_impl(&Ht, piv_t, nvec, nvec, tol, base + L.inner, L.total - L.inner, oi,
-                              ev.data(), pivot, nullptr, stats, s);
+    // the lowest nvec eigenvectors land in the first n_trunc rows of the pivot
+    const int st = truncated_solve(*H, n_trunc, nvec, nvec, tol, o, ws, ws_bytes, pivot,
+                                   ev.data(), stats, s);
     // zero padding: the truncated basis is a subset of the full one
     launch_fill(pivot + (size_t)n_trunc * nvec, (H->n - n_trunc) * nvec, 0.0, s);
     BBL_HIP(hipStreamSynchronize(s));

@@ -1,0 +1,247 @@
+"""Learned pivot proposer on the GPU against the float64 reference in
+oracle.pivot: features, the network's forward pass and gradient, Adam,
+Procrustes targets, training, and the fallback rule.
+
+Bars: features 1e-6 (float32 rounding) on the per-row columns and 1e-5 on the
+sqrt(n)-scaled amplitudes; bfloat16 features equal torch's round-to-nearest-
+even of the float32 ones bit for bit; network output within 2e-3 relative
+Frobenius error of the reference evaluated with the kernels' bfloat16 weights
+and activations (so both take the same ReLU decisions) and 2e-2 of the plain
+float64 network; gradients within 2e-2 per tensor of the former (bfloat16
+backpropagated errors); Adam and Procrustes within float32 rounding."""
+import numpy as np
+import pytest
+
+import synthgen
+import oracle
+from oracle import pivot as op
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print("[case] " + msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def bbl(torch):
+    import paper_2210_15763_amd as m
+    m.load_library()
+    return m
+
+
+def to_bf16(torch, a):
+    """float array -> (device int16 bf16 bit patterns, float64 host values)."""
+    t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16)
+    return t.view(torch.int16).cuda(), t.to(torch.float64).numpy()
+
+
+def bf16_values(torch, F):
+    return F.cpu().view(torch.bfloat16).to(torch.float64).numpy()
+
+
+def rel_fro(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("rows", [1, 63, 1000])
+def test_mlp_forward_matches_oracle(torch, bbl, rows):
+    note("mlp forward rows=%d" % rows)
+    p = bbl.mlp_init(3)
+    rng = np.random.default_rng(rows)
+    Fd, F = to_bf16(torch, rng.standard_normal((rows, 28)))
+    out = bbl.mlp_forward(p, Fd).cpu().numpy()
+    pn = p.double().cpu().numpy()
+    _, ref = op.forward(pn, F)
+    _, ref16 = op.forward(pn, F, act="bf16")
+    assert out.shape == (rows, 10)
+    assert rel_fro(out, ref16) <= 2e-3, rel_fro(out, ref16)
+    assert rel_fro(out, ref) <= 2e-2, rel_fro(out, ref)
+
+
+def test_mlp_init_is_he_uniform_and_deterministic(torch, bbl):
+    note("mlp init")
+    a = bbl.mlp_init(11).cpu().numpy()
+    b = bbl.mlp_init(11).cpu().numpy()
+    assert np.array_equal(a, b)
+    W1, b1, W2, b2, W3, b3, W4, b4 = op.unpack(a.astype(np.float64))
+    for W, fan in ((W1, 28), (W2, 128), (W3, 128), (W4, 128)):
+        bound = np.sqrt(6.0 / fan)
+        assert np.abs(W).max() <= bound and np.abs(W).max() > 0.95 * bound
+        assert abs(W.std() - bound / np.sqrt(3)) < 0.05 * bound
+    assert all(np.all(x == 0) for x in (b1, b2, b3, b4))
+
+
+@pytest.mark.parametrize("rows", [7, 333])
+def test_mlp_gradient_matches_oracle(torch, bbl, rows):
+    note("mlp gradient rows=%d" % rows)
+    p = bbl.mlp_init(5)
+    # nonzero biases so every bias gradient path is exercised
+    rng = np.random.default_rng(rows)
+    pn = p.cpu().numpy()
+    for o, c in ((3584, 128), (20096, 128), (36608, 128), (38016, 10)):
+        pn[o:o + c] = rng.uniform(-0.1, 0.1, c)
+    p = torch.from_numpy(pn).cuda()
+    Fd, F = to_bf16(torch, rng.standard_normal((rows, 28)))
+    T = rng.standard_normal((rows, 10)).astype(np.float32)
+    g, loss = bbl.mlp_grad(p, Fd, torch.from_numpy(T).cuda())
+    # ReLU decisions taken on the bf16 values the kernels use (the float64
+    # network flips a few of them, which moves W1's gradient by several % at
+    # a handful of rows)
+    lref, gref = op.loss_and_grad(pn.astype(np.float64), F, T.astype(np.float64), act="bf16")
+    assert abs(loss.item() - lref) <= 2e-2 * lref
+    gg = g.cpu().numpy().astype(np.float64)
+    o = 0
+    for shape in op.SHAPES:
+        c = int(np.prod(shape))
+        assert rel_fro(gg[o:o + c], gref[o:o + c]) <= 2e-2, (shape, rel_fro(gg[o:o + c], gref[o:o + c]))
+        o += c
+
+
+def test_mlp_gradient_is_deterministic(torch, bbl):
+    note("mlp gradient determinism")
+    p = bbl.mlp_init(8)
+    rng = np.random.default_rng(0)
+    Fd, _ = to_bf16(torch, rng.standard_normal((5000, 28)))
+    T = torch.from_numpy(rng.standard_normal((5000, 10)).astype(np.float32)).cuda()
+    a, la = bbl.mlp_grad(p, Fd, T)
+    b, lb = bbl.mlp_grad(p, Fd, T)
+    assert torch.equal(a, b) and torch.equal(la, lb)
+
+
+def test_adam_matches_oracle(torch, bbl):
+    note("adam")
+    rng = np.random.default_rng(1)
+    n = 1000
+    p = rng.standard_normal(n).astype(np.float32)
+    m = (rng.standard_normal(n) * 0.1).astype(np.float32)
+    v = (rng.random(n) * 0.01).astype(np.float32)
+    g = rng.standard_normal(n).astype(np.float32)
+    pd, md, vd = (torch.from_numpy(x.copy()).cuda() for x in (p, m, v))
+    bbl.adam_step(pd, md, vd, torch.from_numpy(g).cuda(), 3, 1e-3)
+    # the float32 values of the constants the kernel uses
+    b1, b2, lr, eps = (float(np.float32(x)) for x in (0.9, 0.999, 1e-3, 1e-8))
+    pr, mr, vr = op.adam_step(p.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
+                              g.astype(np.float64), 3, lr, b1, b2, eps)
+    np.testing.assert_allclose(md.cpu().numpy(), mr, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(vd.cpu().numpy(), vr, rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(pd.cpu().numpy(), pr, rtol=1e-6, atol=1e-6)
+
+
+def test_training_overfits_a_tiny_instance(torch, bbl):
+    note("training overfits 64 rows")
+    rng = np.random.default_rng(2)
+    Fd, _ = to_bf16(torch, rng.standard_normal((64, 28)))
+    T = torch.from_numpy(rng.standard_normal((64, 10)).astype(np.float32)).cuda()
+    p = bbl.mlp_init(4)
+    _, l0 = bbl.mlp_grad(p, Fd, T)
+    tr = bbl.MlpTrainer(p, batch=256, sample_key=9)
+    for _ in range(1500):
+        tr.step(Fd, T, 3e-3)
+    _, l1 = bbl.mlp_grad(p, Fd, T)
+    assert l1.item() < 5e-3 and l1.item() < 0.01 * l0.item(), (l0.item(), l1.item())
+
+
+def test_procrustes_targets_match_oracle(torch, bbl):
+    note("procrustes targets")
+    rng = np.random.default_rng(3)
+    n = 5003
+    X, _ = np.linalg.qr(rng.standard_normal((n, 10)))
+    Q0, _ = np.linalg.qr(rng.standard_normal((10, 10)))
+    P = X @ Q0 + 1e-3 * rng.standard_normal((n, 10))
+    T = bbl.procrustes_targets(torch.from_numpy(X).cuda(), torch.from_numpy(P).cuda()).cpu().numpy()
+    ref = op.procrustes_targets(X, P)
+    assert np.max(np.abs(T - ref)) <= 1e-6 * np.max(np.abs(ref)) + 1e-6
+
+
+def small_instance():
+    # n = 6000 FP64, 30 sectors of 200 rows, ~25 nnz/row; truncation 1000 rows
+    return synthgen.generate(6000, 200, 12, 0.7, 5), 1000, 200
+
+
+def test_features_match_oracle(torch, bbl):
+    note("features n=6000 n_t=1000 FP64")
+    H, n_t, R = small_instance()
+    Hd = bbl.DeviceCSR.from_host(H, "float64")
+    r = bbl.pivot_features(Hd, n_t, R, 1e-11, m_max=300, want_f32=True)
+    F_ref, PD_ref, Pb_ref = op.features(H, n_t, R)
+    F32 = r["feats32"].cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(F32[:, :18], F_ref[:, :18], rtol=0, atol=1e-6 * np.abs(F_ref[:, :18]).max())
+    np.testing.assert_allclose(F32[:, 18:], F_ref[:, 18:], rtol=0, atol=1e-5)
+    # bf16 features are the round-to-nearest-even images of the float32 ones
+    rne = r["feats32"].cpu().to(torch.bfloat16).view(torch.int16)
+    assert torch.equal(rne, r["feats"].cpu())
+    np.testing.assert_allclose(r["p_d"].cpu().numpy(), PD_ref, rtol=0, atol=1e-7)
+    _, th_d, _, _ = op.variant_d(H, n_t)
+    np.testing.assert_allclose(r["theta_d"], th_d, rtol=1e-10)
+    sv = np.linalg.svd(r["p_boot"].cpu().numpy().T @ Pb_ref, compute_uv=False)
+    assert sv.min() > 1 - 1e-9 and np.all(r["p_boot"].cpu().numpy()[n_t:] == 0)
+
+
+def identity_network(torch):
+    """Parameters whose output equals features 18..27 (the P_D amplitudes):
+    ReLU splits each into positive and negative parts, two identity layers
+    carry them, the last layer recombines them."""
+    W1 = np.zeros((128, 28))
+    W2 = np.zeros((128, 128))
+    W4 = np.zeros((10, 128))
+    for a in range(10):
+        W1[2 * a, 18 + a] = 1.0
+        W1[2 * a + 1, 18 + a] = -1.0
+        W4[a, 2 * a] = 1.0
+        W4[a, 2 * a + 1] = -1.0
+    for i in range(20):
+        W2[i, i] = 1.0
+    p = np.concatenate([W1.ravel(), np.zeros(128), W2.ravel(), np.zeros(128), W2.ravel(),
+                        np.zeros(128), W4.ravel(), np.zeros(10)]).astype(np.float32)
+    return torch.from_numpy(p).cuda()
+
+
+@pytest.mark.parametrize("case", ["identity", "random", "nan"])
+def test_learned_pivot_fallback_agrees_with_oracle(torch, bbl, case):
+    note("learned pivot fallback: %s" % case)
+    H, n_t, R = small_instance()
+    Hd = bbl.DeviceCSR.from_host(H, "float64")
+    if case == "identity":
+        params = identity_network(torch)
+    else:
+        params = bbl.mlp_init(1)
+        if case == "nan":
+            params[38016] = float("nan")     # output bias of the first column
+    nvec, k = 8, 8
+    P, info = bbl.learned_pivot(Hd, params, n_t, R, nvec, k, 1e-11, m_max=300)
+    feats = bbl.pivot_features(Hd, n_t, R, 1e-11, m_max=300)
+    P_learn = bbl.mlp_forward(params, feats["feats"]).double().cpu().numpy()[:, :nvec]
+    P_boot = feats["p_boot"].cpu().numpy()[:, :nvec]
+    P_ref, fb_ref, why, (sl, sb) = op.choose_pivot(H, P_learn, P_boot, k)
+    assert info["used_fallback"] == fb_ref, (why, info)
+    assert np.array_equal(P.cpu().numpy(), P_boot if fb_ref else P_learn)
+    np.testing.assert_allclose(info["rr_sums"][1], sb, rtol=1e-10)
+    if np.isfinite(sl):
+        np.testing.assert_allclose(info["rr_sums"][0], sl, rtol=1e-9)
+    if case == "identity":
+        assert not fb_ref        # variant D beats the plain truncation here
+    if case == "nan":
+        assert fb_ref and why == "nonfinite"
+
+
+def test_learned_pivot_solve_finds_the_bootstrap_eigenvalues(torch, bbl):
+    note("solve from the learned (identity-network) pivot")
+    H, n_t, R = small_instance()
+    Hd = bbl.DeviceCSR.from_host(H, "float64")
+    P, info = bbl.learned_pivot(Hd, identity_network(torch), n_t, R, 8, 8, 1e-11, m_max=300)
+    assert not info["used_fallback"]
+    r = bbl.block_lanczos(Hd, P, 8, 1e-9, m_max=300)
+    lam = np.linalg.eigvalsh(H.to_dense())[:8]
+    assert r.converged
+    np.testing.assert_allclose(r.eigvals, lam, rtol=1e-10)
+    Pb, _ = bbl.bootstrap_pivot(Hd, n_t, 8, 1e-11, m_max=300)
+    rb = bbl.block_lanczos(Hd, Pb, 8, 1e-9, m_max=300)
+    assert r.stats["iters"] <= rb.stats["iters"] + 2

@@ -174,6 +174,52 @@ def test_backward_matches_central_differences():
         assert abs(fd - g[i]) <= 1e-6 * max(abs(g).max(), 1e-12), (i, fd, g[i])
 
 
+def test_round_bf16_matches_torch():
+    import torch
+    rng = np.random.default_rng(9)
+    x = np.concatenate([rng.standard_normal(4000) * 10.0 ** rng.integers(-30, 30, 4000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.01171875, 3.4e38, -3.4e38, 1e-40,
+                         np.inf, -np.inf]]).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(op.round_bf16(x), ref)
+    assert np.isnan(op.round_bf16(np.float32("nan")))
+
+
+def test_bf16_forward_rounds_only_weights_and_activations():
+    rng = np.random.default_rng(10)
+    p = rng.standard_normal(op.N_PARAMS) * 0.1
+    F = op.round_bf16(rng.standard_normal((5, 28)))
+    acts, out = op.forward(p, F, act="bf16")
+    for h in acts[1:]:
+        assert np.array_equal(h, op.round_bf16(h))
+    # weights exactly representable in bf16: identical to the float64 network
+    # up to activation rounding
+    pr = p.copy()
+    for o, c in ((0, 3584), (3712, 16384), (20224, 16384), (36736, 1280)):
+        pr[o:o + c] = op.round_bf16(p[o:o + c])
+    _, out64 = op.forward(pr, F)
+    assert np.max(np.abs(out - out64)) < 2e-2 * np.max(np.abs(out64))
+    lf, gf = op.loss_and_grad(pr, F, np.zeros((5, 10)), act="bf16")
+    assert np.isfinite(lf) and gf.shape == (op.N_PARAMS,)
+
+
+def test_bf16_backward_matches_central_differences_of_its_forward():
+    # with weights already on the bf16 grid and tiny steps that keep every
+    # activation's rounding and every ReLU decision, the bf16 network is
+    # piecewise linear in the biases of the output layer
+    rng = np.random.default_rng(11)
+    p = rng.standard_normal(op.N_PARAMS) * 0.1
+    F = op.round_bf16(rng.standard_normal((6, 28)))
+    T = rng.standard_normal((6, 10))
+    _, g = op.loss_and_grad(p, F, T, act="bf16")
+    for i in range(op.N_PARAMS - 10, op.N_PARAMS):
+        e = np.zeros(op.N_PARAMS)
+        e[i] = 1e-6
+        fd = (op.loss_and_grad(p + e, F, T, act="bf16")[0] -
+              op.loss_and_grad(p - e, F, T, act="bf16")[0]) / 2e-6
+        assert abs(fd - g[i]) <= 1e-6 * abs(g).max()
+
+
 def test_adam_first_step_closed_form():
     rng = np.random.default_rng(5)
     p = rng.standard_normal(50)
