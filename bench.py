@@ -14,6 +14,11 @@ solves, each bracketed by HIP events that the library records on the solver's
 stream) and a "cpu_baseline" object (the FP64 CPU oracle timed on a bounded
 sample of the same solve on the host cores).
 
+--compare-pivots solves the held-out n = 5e6 instance (~300 nnz/row, b = k = 10,
+tol 1e-6, truncation 50,000 rows) from four pivots -- random, bootstrapped,
+the one-hop Rayleigh-Ritz block P_D alone, and the learned proposer with its
+fallback -- and prints one JSON line with the counts and times of each.
+
 Two helper modes serve the hardware-counter measurement of HBM traffic:
   --kernels-only       runs the SpMM, the reorthogonalisation gram and a plain
                        1 GiB elementwise copy a few times each (the program run
@@ -167,6 +172,66 @@ def kernels_only(torch, bbl, Hd, b, iters=10):
     log("kernels-only done")
 
 
+def compare_pivots(torch, bbl, weights, m_max):
+    import synthgen
+    w = synthgen.WORKLOADS["apply_n5e6"]
+    t0 = time.time()
+    H = load_matrix(w)
+    log("apply matrix n=%d nnz=%d ready in %.1f s" % (H.n, H.nnz, time.time() - t0))
+    Hd = bbl.DeviceCSR.from_host(H, "float32")
+    params = torch.from_numpy(np.load(weights, allow_pickle=False)).cuda()
+    b, k, R = w.nvec, w.k, w.R
+    arms = {}
+
+    def run(name, make):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        P, info = make()
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t
+        r = bbl.block_lanczos(Hd, P, k, w.tol, m_max=m_max, seed=w.seed)
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - t
+        arms[name] = dict(info, iters=r.stats["iters"], spmm_calls=r.stats["spmm_calls"],
+                          converged=bool(r.converged), pivot_s=tp, tts_s=tt,
+                          eigvals=[float(x) for x in r.eigvals],
+                          max_resid_over_hnorm=float(np.max(r.residuals) / r.stats["hnorm_est"]))
+        log("%s: iters=%d pivot %.2f s total %.2f s converged=%s %s" %
+            (name, r.stats["iters"], tp, tt, r.converged, info))
+
+    # full-width products of each pivot's construction, in b-wide SpMM units:
+    # the learned block needs H P and H Y at width 20 and two width-b checks
+    run("random", lambda: (bbl.random_pivot(H.n, b, synthgen.pivot_key(w.seed)),
+                           {"pivot_full_spmm": 0}))
+
+    def boot():
+        P, st = bbl.bootstrap_pivot(Hd, w.n_trunc, b, w.tol, m_max=m_max, seed=w.seed)
+        return P, {"pivot_full_spmm": 0, "truncated_iters": st["iters"]}
+    run("bootstrap", boot)
+
+    def variant_d():
+        f = bbl.pivot_features(Hd, w.n_trunc, R, w.tol, m_max=m_max, seed=w.seed)
+        return f["p_d"][:, :b].contiguous(), {"pivot_full_spmm": 4,
+                                              "truncated_iters": f["stats"]["iters"]}
+    run("variant_d", variant_d)
+
+    def learned():
+        P, info = bbl.learned_pivot(Hd, params, w.n_trunc, R, b, k, w.tol, m_max=m_max,
+                                    seed=w.seed)
+        return P, {"pivot_full_spmm": 6, "used_fallback": info["used_fallback"],
+                   "rr_sums": [float(x) for x in info["rr_sums"]],
+                   "truncated_iters": info["stats"]["iters"]}
+    run("learned", learned)
+    ref = np.array(arms["bootstrap"]["eigvals"])
+    for a in arms.values():
+        a["max_eig_rel_diff_vs_bootstrap"] = float(np.max(np.abs(np.array(a["eigvals"]) - ref) /
+                                                          np.abs(ref)))
+    print(json.dumps({"mode": "compare-pivots", "workload": "sectored symmetric CSR n=5e6, "
+                      "~300 nnz/row, FP32, b=k=10, tol=1e-6, truncation 50000 rows, seed 200",
+                      "n": H.n, "nnz": H.nnz, "m_max": m_max, "weights": os.path.basename(weights),
+                      "arms": arms}), flush=True)
+
+
 def time_kernel(torch, fn, iters):
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -227,6 +292,11 @@ def main():
                     help="run the SpMM, gram and calibration copy only (counter runs)")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the SpMM HBM traffic record from two rocprofv3 --pmc runs")
+    ap.add_argument("--compare-pivots", action="store_true",
+                    help="random / bootstrap / variant D / learned pivots on the n=5e6 instance")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2210_15763_amd", "weights",
+                                                      "pivot_mlp_sectored.npy"))
+    ap.add_argument("--compare-m-max", type=int, default=300)
     args = ap.parse_args()
     if args.traffic:
         write_traffic(*args.traffic)
@@ -240,6 +310,9 @@ def main():
     import synthgen
     import paper_2210_15763_amd as bbl
     bbl.load_library()
+    if args.compare_pivots:
+        compare_pivots(torch, bbl, args.weights, args.compare_m_max)
+        return
     w = synthgen.WORKLOADS[WORKLOAD]
     t0 = time.time()
     H = load_matrix(w)
