@@ -45,7 +45,14 @@ typedef enum {
 
 typedef enum { BBL_F32 = 1, BBL_F64 = 2 } bbl_dtype;
 
-/* Symmetric CSR matrix resident on the device. */
+/* Symmetric CSR matrix resident on the device.
+ * block_rows is an optional locality hint: when > 0, the rows come in aligned
+ * groups [g*block_rows, (g+1)*block_rows) (sectors of the basis, e.g. blocks of
+ * fixed quantum numbers) and most of a row's columns fall inside its own
+ * group.  The SpMM then stages each group's rows of V in LDS and gathers those
+ * columns from there; other columns are read from HBM as usual, so the result
+ * is the same for any value.  0 = no hint.  Used when the group's rows of V fit
+ * in 128 KB of LDS (block_rows * nvec * element size). */
 typedef struct {
   int64_t n;              /* dimension, >= 1 */
   int64_t nnz;            /* number of stored entries (row_ptr[n]) */
@@ -53,7 +60,7 @@ typedef struct {
   const int32_t *col;     /* device, nnz entries, ascending within each row */
   const void *val;        /* device, nnz entries of type val_dtype */
   int32_t val_dtype;      /* BBL_F32 or BBL_F64 */
-  int32_t reserved;       /* must be 0 */
+  int32_t block_rows;     /* locality hint (see above), >= 0 */
 } bbl_csr;
 
 /* Solver options; a NULL pointer selects the defaults shown. */

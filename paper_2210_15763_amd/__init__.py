@@ -41,7 +41,7 @@ class BblError(RuntimeError):
 class _Csr(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
                 ("col", ctypes.c_void_p), ("val", ctypes.c_void_p), ("val_dtype", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("block_rows", ctypes.c_int32)]
 
 
 class _Opts(ctypes.Structure):
@@ -166,6 +166,7 @@ class DeviceCSR:
     row_ptr: "object"
     col: "object"
     val: "object"
+    block_rows: int = 0   # locality hint: rows grouped in aligned sectors of this size
 
     @property
     def nnz(self):
@@ -173,16 +174,17 @@ class DeviceCSR:
 
     def _c(self):
         return _Csr(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
-                    self.val.data_ptr(), _dtype_code(self.val), 0)
+                    self.val.data_ptr(), _dtype_code(self.val), int(self.block_rows))
 
     @classmethod
-    def from_host(cls, H, dtype="float32", device="cuda"):
-        """Upload a host CSR (any object with n, row_ptr, col, val)."""
+    def from_host(cls, H, dtype="float32", device="cuda", block_rows: int = 0):
+        """Upload a host CSR (any object with n, row_ptr, col, val).  block_rows:
+        the locality hint of bbl_csr (aligned row groups holding most columns)."""
         torch = _torch()
         val = np.asarray(H.val, dtype=np.float32 if dtype in ("float32", "f32") else np.float64)
         return cls(int(H.n), torch.from_numpy(np.ascontiguousarray(H.row_ptr, np.int64)).to(device),
                    torch.from_numpy(np.ascontiguousarray(H.col, np.int32)).to(device),
-                   torch.from_numpy(np.ascontiguousarray(val)).to(device))
+                   torch.from_numpy(np.ascontiguousarray(val)).to(device), int(block_rows))
 
 
 def _opts(m_max, basis_dtype, check_every, seed, defl_tau, flags=0):

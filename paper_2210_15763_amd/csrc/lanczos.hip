@@ -408,7 +408,7 @@ void validate_csr(const bbl_csr *H) {
   BBL_REQUIRE(H->nnz >= 0, "H.nnz must be >= 0");
   BBL_REQUIRE(H->row_ptr && (H->nnz == 0 || (H->col && H->val)), "H has NULL arrays");
   BBL_REQUIRE(H->val_dtype == BBL_F32 || H->val_dtype == BBL_F64, "H.val_dtype must be F32/F64");
-  BBL_REQUIRE(H->reserved == 0, "H.reserved must be 0");
+  BBL_REQUIRE(H->block_rows >= 0, "H.block_rows must be >= 0");
 }
 
 
@@ -498,6 +498,7 @@ int truncated_solve(const bbl_csr &H, int64_t n_t, int b, int k, double tol, con
   Ht.col = col_t;
   Ht.val = val_t;
   Ht.val_dtype = H.val_dtype;
+  Ht.block_rows = H.block_rows;
   // random pivot of the truncated problem, key (seed + 1) ^ golden ratio
   const uint64_t key = (o.seed + 1) ^ 0x9E3779B97F4A7C15ull;
   launch_gauss(n_t, b, b, 0, key, 6, piv_t, nullptr, nullptr, s);

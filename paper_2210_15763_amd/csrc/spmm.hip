@@ -117,6 +117,106 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int64_t *__restri
   }
 }
 
+// Sector-staged variant for matrices whose rows come in aligned groups of G
+// rows holding most of their columns (bbl_csr.block_rows): one workgroup per
+// group copies the group's G rows of V into LDS with full-line loads, then
+// gathers in-group columns from LDS and the rest from HBM.  The random 32-byte
+// gathers otherwise each pull a 128-byte line through L2; staging turns the
+// in-group share of them into one streaming read of V.
+template <typename VT, typename XT, typename AT, typename YT, int B, int LPR>
+__global__ __launch_bounds__(512) void k_spmm_blk(int64_t n, int64_t G,
+                                                  const int64_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ col,
+                                                  const VT *__restrict__ val,
+                                                  const XT *__restrict__ X, YT *__restrict__ Y) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  XT *sX = reinterpret_cast<XT *>(smem_raw);
+  const int64_t r0 = xcd_block(blockIdx.x) * G;
+  if (r0 >= n) return;  // grid padding: the whole workgroup leaves
+  const int64_t r1 = min(n, r0 + G);
+  const uint64_t W = (uint64_t)(r1 - r0);
+  {
+    constexpr int bytes = (int)sizeof(XT) * B;
+    const unsigned char *src = reinterpret_cast<const unsigned char *>(X + r0 * B);
+    const int64_t total = (int64_t)W * bytes;
+    if constexpr (bytes % 16 == 0) {
+      for (int64_t i = threadIdx.x; i < total / 16; i += blockDim.x)
+        reinterpret_cast<uint4 *>(smem_raw)[i] = reinterpret_cast<const uint4 *>(src)[i];
+    } else if constexpr (bytes % 8 == 0) {
+      for (int64_t i = threadIdx.x; i < total / 8; i += blockDim.x)
+        reinterpret_cast<uint2 *>(smem_raw)[i] = reinterpret_cast<const uint2 *>(src)[i];
+    } else {
+      for (int64_t i = threadIdx.x; i < total / 4; i += blockDim.x)
+        reinterpret_cast<uint32_t *>(smem_raw)[i] = reinterpret_cast<const uint32_t *>(src)[i];
+    }
+  }
+  __syncthreads();
+  constexpr int RPW = kWave / LPR;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int sub = lane & (LPR - 1);
+  const int wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
+  // the loop bound is uniform per wave, so every lane joins the butterfly
+  for (int64_t base = r0 + (int64_t)wave * RPW; base < r1; base += (int64_t)nwaves * RPW) {
+    const int64_t row = base + lane / LPR;
+    AT acc[B];
+#pragma unroll
+    for (int a = 0; a < B; ++a) acc[a] = AT(0);
+    if (row < r1) {
+      const int64_t p0 = rp[row], p1 = rp[row + 1];
+      int64_t p = p0 + sub;
+      constexpr int UNR = 4;
+      for (; p + (UNR - 1) * LPR < p1; p += UNR * LPR) {
+        int c[UNR];
+        AT h[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          c[u] = ldg_stream(col + p + u * LPR);
+          h[u] = (AT)ldg_stream(val + p + u * LPR);
+        }
+        XT x[UNR][B];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const uint64_t off = (uint64_t)((int64_t)c[u] - r0);
+          if (off < W) RowIO<XT, B>::load(sX + off * B, x[u]);
+          else RowIO<XT, B>::load(X + (int64_t)c[u] * B, x[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+          for (int a = 0; a < B; ++a) acc[a] = fma(h[u], (AT)x[u][a], acc[a]);
+      }
+      for (; p < p1; p += LPR) {
+        const int c0 = ldg_stream(col + p);
+        const AT h0 = (AT)ldg_stream(val + p);
+        XT x0[B];
+        const uint64_t off = (uint64_t)((int64_t)c0 - r0);
+        if (off < W) RowIO<XT, B>::load(sX + off * B, x0);
+        else RowIO<XT, B>::load(X + (int64_t)c0 * B, x0);
+#pragma unroll
+        for (int a = 0; a < B; ++a) acc[a] = fma(h0, (AT)x0[a], acc[a]);
+      }
+    }
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) {
+#pragma unroll
+      for (int a = 0; a < B; ++a) acc[a] += __shfl_xor(acc[a], off, LPR);
+    }
+    if (row < r1) {
+#pragma unroll
+      for (int a0 = 0; a0 < B; a0 += LPR) {
+        AT v = acc[0];
+#pragma unroll
+        for (int a = 1; a < B; ++a)
+          if (a == a0 + sub) v = acc[a];
+        if (a0 + sub < B) Y[row * B + a0 + sub] = (YT)v;
+      }
+    }
+  }
+}
+
+constexpr size_t kBlkMaxLds = 128 * 1024;   // LDS bytes a staged group may use
+constexpr int kBlkThreads = 512;
+
 // Generic width (runtime nvec <= 32), used for block sizes without a
 // dedicated instantiation.
 template <typename VT, typename XT, typename AT, typename YT, int LPR>
@@ -234,6 +334,41 @@ int pick_lpr(const bbl_csr &H) {
 
 template <typename VT, typename XT, typename AT, typename YT, int LPR>
 void spmm_dispatch_b(const bbl_csr &H, const XT *X, YT *Y, int nvec, hipStream_t s) {
+  const VT *valp = static_cast<const VT *>(H.val);
+  const size_t lds = (size_t)H.block_rows * nvec * sizeof(XT);
+  if (H.block_rows > 0 && lds <= kBlkMaxLds &&
+      (nvec == 1 || nvec == 2 || nvec == 4 || nvec == 8 || nvec == 10 || nvec == 16)) {
+    const int64_t groups = ceil_div(H.n, H.block_rows);
+    const int64_t grid = ceil_div(groups, kXcds) * kXcds;
+#define BBL_BLK_CASE(BV)                                                                      \
+  case BV: {                                                                                  \
+    auto kern = k_spmm_blk<VT, XT, AT, YT, BV, LPR>;                                          \
+    if (lds > 65536) {                                                                        \
+      static bool attr_set = false;                                                           \
+      if (!attr_set) {                                                                        \
+        BBL_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),                     \
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,               \
+                                    (int)kBlkMaxLds));                                        \
+        attr_set = true;                                                                      \
+      }                                                                                       \
+    }                                                                                         \
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kBlkThreads), lds, s, H.n,            \
+                       (int64_t)H.block_rows, H.row_ptr, H.col, valp, X, Y);                  \
+    break;                                                                                    \
+  }
+    switch (nvec) {
+      BBL_BLK_CASE(1)
+      BBL_BLK_CASE(2)
+      BBL_BLK_CASE(4)
+      BBL_BLK_CASE(8)
+      BBL_BLK_CASE(10)
+      BBL_BLK_CASE(16)
+      default: break;
+    }
+#undef BBL_BLK_CASE
+    check_launch("k_spmm_blk");
+    return;
+  }
   const int rows_per_wg = (256 / kWave) * (kWave / LPR);
   const int64_t grid = ceil_div(ceil_div(H.n, rows_per_wg), kXcds) * kXcds;
   const VT *val = static_cast<const VT *>(H.val);

@@ -8,8 +8,9 @@ Recipe (instance s = 0 .. instances-1, all seeded):
     10 eigenvectors X; the features of H give P_D; the targets are
     sqrt(n) X Q, Q the Procrustes rotation of X onto P_D;
   * Adam (lr 1e-3, betas 0.9 / 0.999) on uniformly sampled batches for a
-    number of epochs over all rows; the last 10 % of instances are held out
-    and their loss is reported.
+    number of epochs over all rows; the last 10 % of instances are held out,
+    their loss is evaluated 40 times during training and the parameters with
+    the lowest held-out loss are kept (early stopping).
 
 Every step runs in libbbl.so's kernels (generation of the synthetic matrices
 aside, which is host code in ``synthgen``).  Usage:
@@ -56,6 +57,21 @@ def instance_shape(s: int):
 def generate(s: int):
     n, z, q = instance_shape(s)
     return synthgen.generate(n, SECTOR, q, 0.7, s)
+
+
+def identity_params(torch):
+    """Parameters whose output reproduces feature columns 18..27 (sqrt(n) P_D):
+    the held-out loss of this map is what the network has to beat."""
+    W1 = np.zeros((128, 28))
+    W2 = np.zeros((128, 128))
+    W4 = np.zeros((10, 128))
+    for a in range(10):
+        W1[2 * a, 18 + a], W1[2 * a + 1, 18 + a] = 1.0, -1.0
+        W4[a, 2 * a], W4[a, 2 * a + 1] = 1.0, -1.0
+    W2[np.arange(20), np.arange(20)] = 1.0
+    p = np.concatenate([W1.ravel(), np.zeros(128), W2.ravel(), np.zeros(128), W2.ravel(),
+                        np.zeros(128), W4.ravel(), np.zeros(10)]).astype(np.float32)
+    return torch.from_numpy(p).cuda()
 
 
 def build_instance(torch, H, m_max: int):
@@ -122,30 +138,36 @@ def main():
     params = bbl.mlp_init(args.seed)
     tr = bbl.MlpTrainer(params, args.batch, sample_key=synthgen.pivot_key(args.seed + 7))
 
-    def val_loss():
+    def val_loss(p=None):
         tot, cnt = 0.0, 0
         for a in range(0, Fva.shape[0], 1 << 20):
             Fb, Tb = Fva[a:a + (1 << 20)], Tva[a:a + (1 << 20)]
-            _, l = bbl.mlp_grad(params, Fb, Tb)
+            _, l = bbl.mlp_grad(params if p is None else p, Fb, Tb)
             tot += l.item() * Fb.shape[0]
             cnt += Fb.shape[0]
         return tot / cnt
 
+    ident = val_loss(identity_params(torch))
     hist = [{"step": 0, "val_loss": val_loss()}]
-    log("initial held-out loss %.4f" % hist[0]["val_loss"])
+    log("initial held-out loss %.4f; the P_D amplitudes alone: %.4f" % (hist[0]["val_loss"], ident))
+    best = (hist[0]["val_loss"], 0, params.clone())
     t1 = time.time()
-    report = max(1, steps // 20)
+    report = max(1, steps // 40)
     for i in range(1, steps + 1):
         loss = tr.step(Ftr, Ttr, args.lr)
         if i % report == 0 or i == steps:
             hist.append({"step": i, "batch_loss": loss.item(), "val_loss": val_loss()})
+            if hist[-1]["val_loss"] < best[0]:
+                best = (hist[-1]["val_loss"], i, params.clone())
             log("step %d/%d batch loss %.4f held-out %.4f (%.1f s)" %
                 (i, steps, hist[-1]["batch_loss"], hist[-1]["val_loss"], time.time() - t1))
+    log("kept step %d (held-out loss %.4f)" % (best[1], best[0]))
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
-    np.save(args.out, params.cpu().numpy().astype(np.float32), allow_pickle=False)
+    np.save(args.out, best[2].cpu().numpy().astype(np.float32), allow_pickle=False)
     rec = {"instances": args.instances, "held_out": n_val, "epochs": args.epochs,
            "batch": args.batch, "lr": args.lr, "steps": steps, "train_rows": rows,
            "train_seconds": time.time() - t1, "data_seconds": t1 - t0, "history": hist,
+           "kept_step": best[1], "kept_val_loss": best[0], "identity_val_loss": ident,
            "instances_meta": meta}
     with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
         json.dump(rec, f, indent=1)

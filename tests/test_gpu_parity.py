@@ -75,6 +75,31 @@ def test_spmm_matches_oracle_within_dot_product_bound(torch, bbl, nvec, prec):
     assert np.all(np.abs(W - ref) <= bound), np.max(np.abs(W - ref) / bound)
 
 
+@pytest.mark.parametrize("nvec,block_rows,prec", [(8, 400, "f32"), (8, 400, "f64"), (1, 400, "f32"),
+                                                   (4, 333, "f32"), (10, 400, "f64"),
+                                                   (16, 2048, "f32"), (16, 4096, "f32"),
+                                                   (3, 400, "f32"), (8, 50000, "f32")])
+def test_spmm_sector_staging_is_bitwise_identical(torch, bbl, nvec, block_rows, prec):
+    """The locality hint only changes where in-group rows of V are read from:
+    same lanes, same order, so the product equals the unhinted one bit for bit
+    (16 x 4096 float32 rows exceed the LDS budget and take the plain kernel;
+    nvec 3 has no staged instantiation)."""
+    note("spmm block_rows=%d nvec=%d %s" % (block_rows, nvec, prec))
+    H = synthgen.generate(20000, 400, 20, 0.7, 11)
+    dt = "float32" if prec == "f32" else "float64"
+    V = synthgen.gaussian_block(H.n, nvec, 5)
+    Vd = dev(torch, V.astype(np.float32) if prec == "f32" else V)
+    a = bbl.spmm(bbl.DeviceCSR.from_host(H, dt), Vd).cpu().numpy()
+    b = bbl.spmm(bbl.DeviceCSR.from_host(H, dt, block_rows=block_rows), Vd).cpu().numpy()
+    assert np.array_equal(a, b)
+    Href = H.as_float32_values() if prec == "f32" else H
+    Vr = V.astype(np.float32).astype(np.float64) if prec == "f32" else V
+    u = U32 if prec == "f32" else U64
+    z = np.diff(H.row_ptr)[:, None]
+    bound = gamma(z + 2, u) * oracle.spmm_abs(Href, Vr) + 1e-300
+    assert np.all(np.abs(b - oracle.spmm(Href, Vr)) <= bound)
+
+
 def test_spmm_ragged_rows_and_empty_rows(torch, bbl):
     note("spmm ragged/empty rows")
     rng = np.random.default_rng(0)
