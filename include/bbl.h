@@ -63,6 +63,31 @@ typedef struct {
   int32_t block_rows;     /* locality hint (see above), >= 0 */
 } bbl_csr;
 
+/* Prepared form of a matrix with a block_rows hint for the SpMM of the block
+ * recurrence (built by bbl_spmm_plan_build; all pointers are device memory
+ * inside the caller's plan buffer, except row_ptr, which is H's).  For every
+ * aligned row group the plan names up to four column blocks of block_rows
+ * columns -- the group's own and the partner blocks holding most of its
+ * other entries -- and every row's entries are reordered: entries inside
+ * those blocks first, stored as an LDS row index slot*block_rows + offset,
+ * then the others with their global column.  The planned SpMM stages the
+ * blocks' rows of V in LDS once per group.  The same sums are formed in a
+ * different order, so results agree with bbl_spmm to rounding, not bitwise. */
+typedef struct {
+  int64_t n, nnz;
+  int32_t block_rows;     /* rows (and columns) per group */
+  int32_t slots;          /* column blocks staged per group, 1..4 */
+  int32_t nvec;           /* block width the plan serves */
+  int32_t vec_dtype;      /* vector element type it serves */
+  int32_t val_dtype;      /* matrix value type */
+  int32_t reserved;
+  const int64_t *row_ptr; /* H.row_ptr (not copied; H must outlive the plan) */
+  const int32_t *blocks;  /* [groups][slots] staged block ids, -1 = none */
+  const int32_t *n_local; /* [n] entries of the row inside staged blocks */
+  const int32_t *col;     /* [nnz] reordered column / LDS row indices */
+  const void *val;        /* [nnz] reordered values */
+} bbl_spmm_plan;
+
 /* Solver options; a NULL pointer selects the defaults shown. */
 typedef struct {
   int32_t m_max;        /* block iteration cap (default 200) */
@@ -74,6 +99,9 @@ typedef struct {
                            residual block relative to max(sigma_max, ||H||)
                            (default 1e-12) */
   uint64_t seed;        /* key of random replacement directions (default 0) */
+  const bbl_spmm_plan *spmm_plan; /* optional plan of H for the recurrence's SpMM
+                           (its nvec and vec_dtype must equal the solve's block
+                           width and basis type); NULL = plain CSR kernel */
 } bbl_opts;
 
 /* Option flags.  BBL_FLAG_TIME_SPMM records a pair of HIP events on the
@@ -117,6 +145,25 @@ const char *bbl_version(void);
  */
 int bbl_spmm(const bbl_csr *H, const void *V, void *W, int32_t nvec, int32_t vec_dtype,
              void *stream);
+
+/*
+ * Planned SpMM: the same product for a matrix with the block_rows locality
+ * hint, from its prepared form.  bbl_spmm_plan_size returns the device bytes
+ * a plan of (H, nvec, vec_dtype) needs, or 0 when no plan can be made
+ * (block_rows == 0, nvec not in {1, 2, 4, 8, 10, 16}, or one column block of
+ * V -- block_rows * nvec elements -- larger than 128 KB).
+ * bbl_spmm_plan_build fills `mem` (device, caller-owned, `bytes` >= the size)
+ * with two kernels on the stream and the host struct *plan; H must stay
+ * unchanged while the plan is used.  bbl_spmm_planned: W = H V for row-major
+ * n x plan->nvec blocks of plan->vec_dtype (no overlap); float32 values need
+ * float32 vectors, float64 values float64 vectors.
+ * Errors: BBL_E_INVALID (no plan possible, NULL pointers, mismatched types),
+ * BBL_E_NOMEM (bytes too small), BBL_E_HIP.
+ */
+size_t bbl_spmm_plan_size(const bbl_csr *H, int32_t nvec, int32_t vec_dtype);
+int bbl_spmm_plan_build(const bbl_csr *H, int32_t nvec, int32_t vec_dtype, void *mem,
+                        size_t bytes, bbl_spmm_plan *plan, void *stream);
+int bbl_spmm_planned(const bbl_spmm_plan *plan, const void *V, void *W, void *stream);
 
 /*
  * Workspace bytes needed by bbl_block_lanczos for dimension n, block size

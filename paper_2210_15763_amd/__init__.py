@@ -47,7 +47,16 @@ class _Csr(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("m_max", ctypes.c_int32), ("basis_dtype", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("defl_tau", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("defl_tau", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("spmm_plan", ctypes.c_void_p)]
+
+
+class _Plan(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("block_rows", ctypes.c_int32),
+                ("slots", ctypes.c_int32), ("nvec", ctypes.c_int32), ("vec_dtype", ctypes.c_int32),
+                ("val_dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("row_ptr", ctypes.c_void_p), ("blocks", ctypes.c_void_p),
+                ("n_local", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
 
 
 class _Stats(ctypes.Structure):
@@ -73,7 +82,8 @@ EXPORTS = ("bbl_last_error", "bbl_version", "bbl_spmm", "bbl_lanczos_workspace_s
            "bbl_procrustes_targets", "bbl_mlp_init", "bbl_mlp_forward",
            "bbl_mlp_grad_workspace_size", "bbl_mlp_grad", "bbl_adam_step",
            "bbl_mlp_train_workspace_size", "bbl_mlp_train_step",
-           "bbl_learned_pivot_workspace_size", "bbl_learned_pivot")
+           "bbl_learned_pivot_workspace_size", "bbl_learned_pivot", "bbl_spmm_plan_size",
+           "bbl_spmm_plan_build", "bbl_spmm_planned")
 
 MLP_IN, MLP_OUT, MLP_PARAMS = 28, 10, 38026
 
@@ -104,6 +114,9 @@ def load_library(path: str = LIB_PATH):
         "bbl_gram": (ctypes.c_int, [I64, P, I32, I32, I32, P, I32, I32, P, P, SZ, P]),
         "bbl_block_update": (ctypes.c_int, [I64, P, I32, I32, I32, P, I32, D, P, I32, D, P, I32,
                                             P]),
+        "bbl_spmm_plan_size": (SZ, [P, I32, I32]),
+        "bbl_spmm_plan_build": (ctypes.c_int, [P, I32, I32, P, SZ, P, P]),
+        "bbl_spmm_planned": (ctypes.c_int, [P, P, P, P]),
         "bbl_features_workspace_size": (SZ, [P, I64, I32, I32, P]),
         "bbl_pivot_features": (ctypes.c_int, [P, I64, I64, D, P, SZ, P, P, P, P, P, P, P, P]),
         "bbl_procrustes_workspace_size": (SZ, [I64, I32]),
@@ -187,9 +200,46 @@ class DeviceCSR:
                    torch.from_numpy(np.ascontiguousarray(val)).to(device), int(block_rows))
 
 
-def _opts(m_max, basis_dtype, check_every, seed, defl_tau, flags=0):
+def _opts(m_max, basis_dtype, check_every, seed, defl_tau, flags=0, plan=None):
     return _Opts(int(m_max), int(basis_dtype), int(check_every), int(flags), float(defl_tau),
-                 int(seed) & (2**64 - 1))
+                 int(seed) & (2**64 - 1),
+                 ctypes.cast(ctypes.pointer(plan.c), ctypes.c_void_p) if plan is not None else None)
+
+
+class SpmmPlan:
+    """Prepared form of a block_rows-hinted matrix for the planned SpMM (keeps
+    its device buffer and the matrix it was built from alive)."""
+
+    def __init__(self, H: "DeviceCSR", nvec: int, vec_dtype: int):
+        torch = _torch()
+        lib = load_library()
+        Hc = H._c()
+        need = lib.bbl_spmm_plan_size(ctypes.byref(Hc), nvec, vec_dtype)
+        if need == 0:
+            raise BblError(BBL_E_INVALID, "no SpMM plan possible for this matrix / block width")
+        self.H = H
+        self.mem = torch.empty(need, dtype=torch.uint8, device=H.row_ptr.device)
+        self.c = _Plan()
+        _check(lib.bbl_spmm_plan_build(ctypes.byref(Hc), nvec, vec_dtype, _ptr(self.mem), need,
+                                       ctypes.byref(self.c), _stream()))
+
+    @property
+    def slots(self):
+        return self.c.slots
+
+
+def spmm_plan(H: "DeviceCSR", nvec: int, dtype=None) -> SpmmPlan:
+    return SpmmPlan(H, nvec, _dtype_code(H.val) if dtype is None else dtype)
+
+
+def spmm_planned(plan: SpmmPlan, V, W=None):
+    """W = H V through the plan (V row-major n x plan.nvec)."""
+    torch = _torch()
+    assert V.is_contiguous() and V.shape == (plan.c.n, plan.c.nvec)
+    if W is None:
+        W = torch.empty_like(V)
+    _check(load_library().bbl_spmm_planned(ctypes.byref(plan.c), _ptr(V), _ptr(W), _stream()))
+    return W
 
 
 def spmm(H: DeviceCSR, V, W=None):
@@ -225,7 +275,7 @@ class LanczosResult:
 def block_lanczos(H: DeviceCSR, pivot, k: int, tol: float, *, m_max: int = 200,
                   basis_dtype=None, check_every: int = 0, seed: int = 0, defl_tau: float = 1e-12,
                   workspace=None, want_vectors: bool = True,
-                  time_spmm: bool = False) -> LanczosResult:
+                  time_spmm: bool = False, spmm_plan: "SpmmPlan" = None) -> LanczosResult:
     """Lowest k eigenpairs of H from the n x nvec float64 pivot block.
     time_spmm: record device time of every product H V_j (stats spmm_ms)."""
     torch = _torch()
@@ -245,7 +295,7 @@ def block_lanczos(H: DeviceCSR, pivot, k: int, tol: float, *, m_max: int = 200,
     st = _Stats()
     Hc = H._c()
     o = _opts(m_max, basis_dtype, check_every, seed, defl_tau,
-              BBL_FLAG_TIME_SPMM if time_spmm else 0)
+              BBL_FLAG_TIME_SPMM if time_spmm else 0, spmm_plan)
     code = lib.bbl_block_lanczos(ctypes.byref(Hc), _ptr(pivot), nvec, k, tol, _ptr(workspace),
                                  workspace.numel(), ctypes.byref(o),
                                  eigvals.ctypes.data_as(ctypes.c_void_p), _ptr(X),

@@ -60,6 +60,14 @@ inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 // SpMM: Y = H X (templated on value/vector/accumulator types inside).
 void launch_spmm(const bbl_csr &H, const void *X, int xdtype, void *Y, int ydtype, int nvec,
                  hipStream_t s);
+// Planned SpMM (rows reordered per aligned group, partner blocks staged in LDS).
+constexpr int kPlanMaxSlots = 4;                 // column blocks staged per group
+constexpr size_t kPlanLds = 128 * 1024;          // LDS bytes they may take
+int spmm_plan_slots(const bbl_csr &H, int nvec, int vec_dtype);
+size_t spmm_plan_bytes(const bbl_csr &H, int nvec, int vec_dtype);
+void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_t bytes,
+                     bbl_spmm_plan *P, hipStream_t s);
+void launch_spmm_planned(const bbl_spmm_plan &P, const void *X, void *Y, hipStream_t s);
 // Explicit residual: partial[g][c] = sum over the rows of group g of
 // ((H X)_{r,c} - theta_c X_{r,c})^2, float64 accumulation.  Returns the number
 // of partial rows written.

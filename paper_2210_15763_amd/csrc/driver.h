@@ -16,6 +16,7 @@ struct Opts {
   int flags = 0;
   double tau = 1e-12;
   uint64_t seed = 0;
+  const bbl_spmm_plan *plan = nullptr;
 };
 
 Opts read_opts(const bbl_opts *o, int val_dtype);

@@ -301,7 +301,8 @@ struct Solver {
     SpmmTimer timer(o.flags & BBL_FLAG_TIME_SPMM, o.m_max);
     for (int J = 0; J < o.m_max; ++J) {
       timer.begin(J, s);
-      launch_spmm(H, slot(J), xd, W, xd, b, s);
+      if (o.plan) launch_spmm_planned(*o.plan, slot(J), W, s);
+      else launch_spmm(H, slot(J), xd, W, xd, b, s);
       timer.end(J, s);
       ++R.spmm_calls;
       gram(slot(J), xd, b, 1, 0, W, xd, b, Araw);
@@ -393,6 +394,7 @@ Opts read_opts(const bbl_opts *o, int val_dtype) {
     r.basis_dtype = o->basis_dtype;
     r.check_every = o->check_every;
     r.flags = o->flags;
+    r.plan = o->spmm_plan;
     if (o->defl_tau > 0) r.tau = o->defl_tau;
     r.seed = o->seed;
   }
@@ -431,6 +433,13 @@ void check_solver_args(const bbl_csr *H, int nvec, int k, const Opts &o) {
   BBL_REQUIRE(!(o.basis_dtype == BBL_F32 && H->val_dtype == BBL_F64),
               "a float32 basis needs float32 matrix values");
   BBL_REQUIRE((int64_t)o.m_max * nvec <= 8192, "m_max * nvec must be <= 8192");
+  if (o.plan) {
+    BBL_REQUIRE(o.plan->n == H->n && o.plan->nnz == H->nnz && o.plan->row_ptr == H->row_ptr,
+                "spmm_plan was built for another matrix");
+    BBL_REQUIRE(o.plan->nvec == nvec && o.plan->vec_dtype == o.basis_dtype &&
+                    o.plan->val_dtype == H->val_dtype,
+                "spmm_plan nvec / vec_dtype must equal the block width and basis type");
+  }
 }
 }  // namespace
 
@@ -505,6 +514,7 @@ int truncated_solve(const bbl_csr &H, int64_t n_t, int b, int k, double tol, con
   Opts oi = o;
   oi.seed = o.seed + 1;
   oi.basis_dtype = bdt;
+  oi.plan = nullptr;  // the plan describes H, not its leading block
   return solve_impl(&Ht, piv_t, b, k, tol, base + L.inner, L.total - L.inner, oi, theta,
                     eigvecs_t, nullptr, stats, s);
 }
@@ -530,6 +540,41 @@ int bbl_spmm(const bbl_csr *H, const void *V, void *W, int32_t nvec, int32_t vec
     BBL_REQUIRE(!(vec_dtype == BBL_F32 && H->val_dtype == BBL_F64),
                 "float32 vectors need float32 matrix values");
     launch_spmm(*H, V, vec_dtype, W, vec_dtype, nvec, static_cast<hipStream_t>(stream));
+    return (int)BBL_OK;
+  });
+}
+
+size_t bbl_spmm_plan_size(const bbl_csr *H, int32_t nvec, int32_t vec_dtype) {
+  size_t r = 0;
+  const int st = guarded([&] {
+    validate_csr(H);
+    BBL_REQUIRE(vec_dtype == BBL_F32 || vec_dtype == BBL_F64, "vec_dtype must be F32/F64");
+    r = spmm_plan_bytes(*H, nvec, vec_dtype);
+    return (int)BBL_OK;
+  });
+  return st == BBL_OK ? r : 0;
+}
+
+int bbl_spmm_plan_build(const bbl_csr *H, int32_t nvec, int32_t vec_dtype, void *mem,
+                        size_t bytes, bbl_spmm_plan *plan, void *stream) {
+  return guarded([&] {
+    validate_csr(H);
+    BBL_REQUIRE(mem && plan, "mem/plan is NULL");
+    BBL_REQUIRE(vec_dtype == BBL_F32 || vec_dtype == BBL_F64, "vec_dtype must be F32/F64");
+    BBL_REQUIRE(vec_dtype == H->val_dtype, "plan: vector and value types must match");
+    build_spmm_plan(*H, nvec, vec_dtype, mem, bytes, plan, static_cast<hipStream_t>(stream));
+    return (int)BBL_OK;
+  });
+}
+
+int bbl_spmm_planned(const bbl_spmm_plan *plan, const void *V, void *W, void *stream) {
+  return guarded([&] {
+    BBL_REQUIRE(plan && V && W, "NULL argument");
+    BBL_REQUIRE(V != W, "V and W must not overlap");
+    BBL_REQUIRE(plan->block_rows > 0 && plan->slots >= 1 && plan->slots <= kPlanMaxSlots &&
+                    plan->blocks && plan->n_local && plan->col && plan->row_ptr,
+                "plan is not initialised");
+    launch_spmm_planned(*plan, V, W, static_cast<hipStream_t>(stream));
     return (int)BBL_OK;
   });
 }

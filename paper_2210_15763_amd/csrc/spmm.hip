@@ -117,106 +117,6 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int64_t *__restri
   }
 }
 
-// Sector-staged variant for matrices whose rows come in aligned groups of G
-// rows holding most of their columns (bbl_csr.block_rows): one workgroup per
-// group copies the group's G rows of V into LDS with full-line loads, then
-// gathers in-group columns from LDS and the rest from HBM.  The random 32-byte
-// gathers otherwise each pull a 128-byte line through L2; staging turns the
-// in-group share of them into one streaming read of V.
-template <typename VT, typename XT, typename AT, typename YT, int B, int LPR>
-__global__ __launch_bounds__(512) void k_spmm_blk(int64_t n, int64_t G,
-                                                  const int64_t *__restrict__ rp,
-                                                  const int32_t *__restrict__ col,
-                                                  const VT *__restrict__ val,
-                                                  const XT *__restrict__ X, YT *__restrict__ Y) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  XT *sX = reinterpret_cast<XT *>(smem_raw);
-  const int64_t r0 = xcd_block(blockIdx.x) * G;
-  if (r0 >= n) return;  // grid padding: the whole workgroup leaves
-  const int64_t r1 = min(n, r0 + G);
-  const uint64_t W = (uint64_t)(r1 - r0);
-  {
-    constexpr int bytes = (int)sizeof(XT) * B;
-    const unsigned char *src = reinterpret_cast<const unsigned char *>(X + r0 * B);
-    const int64_t total = (int64_t)W * bytes;
-    if constexpr (bytes % 16 == 0) {
-      for (int64_t i = threadIdx.x; i < total / 16; i += blockDim.x)
-        reinterpret_cast<uint4 *>(smem_raw)[i] = reinterpret_cast<const uint4 *>(src)[i];
-    } else if constexpr (bytes % 8 == 0) {
-      for (int64_t i = threadIdx.x; i < total / 8; i += blockDim.x)
-        reinterpret_cast<uint2 *>(smem_raw)[i] = reinterpret_cast<const uint2 *>(src)[i];
-    } else {
-      for (int64_t i = threadIdx.x; i < total / 4; i += blockDim.x)
-        reinterpret_cast<uint32_t *>(smem_raw)[i] = reinterpret_cast<const uint32_t *>(src)[i];
-    }
-  }
-  __syncthreads();
-  constexpr int RPW = kWave / LPR;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int sub = lane & (LPR - 1);
-  const int wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
-  // the loop bound is uniform per wave, so every lane joins the butterfly
-  for (int64_t base = r0 + (int64_t)wave * RPW; base < r1; base += (int64_t)nwaves * RPW) {
-    const int64_t row = base + lane / LPR;
-    AT acc[B];
-#pragma unroll
-    for (int a = 0; a < B; ++a) acc[a] = AT(0);
-    if (row < r1) {
-      const int64_t p0 = rp[row], p1 = rp[row + 1];
-      int64_t p = p0 + sub;
-      constexpr int UNR = 4;
-      for (; p + (UNR - 1) * LPR < p1; p += UNR * LPR) {
-        int c[UNR];
-        AT h[UNR];
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          c[u] = ldg_stream(col + p + u * LPR);
-          h[u] = (AT)ldg_stream(val + p + u * LPR);
-        }
-        XT x[UNR][B];
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          const uint64_t off = (uint64_t)((int64_t)c[u] - r0);
-          if (off < W) RowIO<XT, B>::load(sX + off * B, x[u]);
-          else RowIO<XT, B>::load(X + (int64_t)c[u] * B, x[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < UNR; ++u)
-#pragma unroll
-          for (int a = 0; a < B; ++a) acc[a] = fma(h[u], (AT)x[u][a], acc[a]);
-      }
-      for (; p < p1; p += LPR) {
-        const int c0 = ldg_stream(col + p);
-        const AT h0 = (AT)ldg_stream(val + p);
-        XT x0[B];
-        const uint64_t off = (uint64_t)((int64_t)c0 - r0);
-        if (off < W) RowIO<XT, B>::load(sX + off * B, x0);
-        else RowIO<XT, B>::load(X + (int64_t)c0 * B, x0);
-#pragma unroll
-        for (int a = 0; a < B; ++a) acc[a] = fma(h0, (AT)x0[a], acc[a]);
-      }
-    }
-#pragma unroll
-    for (int off = LPR / 2; off > 0; off >>= 1) {
-#pragma unroll
-      for (int a = 0; a < B; ++a) acc[a] += __shfl_xor(acc[a], off, LPR);
-    }
-    if (row < r1) {
-#pragma unroll
-      for (int a0 = 0; a0 < B; a0 += LPR) {
-        AT v = acc[0];
-#pragma unroll
-        for (int a = 1; a < B; ++a)
-          if (a == a0 + sub) v = acc[a];
-        if (a0 + sub < B) Y[row * B + a0 + sub] = (YT)v;
-      }
-    }
-  }
-}
-
-constexpr size_t kBlkMaxLds = 128 * 1024;   // LDS bytes a staged group may use
-constexpr int kBlkThreads = 512;
-
 // Generic width (runtime nvec <= 32), used for block sizes without a
 // dedicated instantiation.
 template <typename VT, typename XT, typename AT, typename YT, int LPR>
@@ -334,41 +234,6 @@ int pick_lpr(const bbl_csr &H) {
 
 template <typename VT, typename XT, typename AT, typename YT, int LPR>
 void spmm_dispatch_b(const bbl_csr &H, const XT *X, YT *Y, int nvec, hipStream_t s) {
-  const VT *valp = static_cast<const VT *>(H.val);
-  const size_t lds = (size_t)H.block_rows * nvec * sizeof(XT);
-  if (H.block_rows > 0 && lds <= kBlkMaxLds &&
-      (nvec == 1 || nvec == 2 || nvec == 4 || nvec == 8 || nvec == 10 || nvec == 16)) {
-    const int64_t groups = ceil_div(H.n, H.block_rows);
-    const int64_t grid = ceil_div(groups, kXcds) * kXcds;
-#define BBL_BLK_CASE(BV)                                                                      \
-  case BV: {                                                                                  \
-    auto kern = k_spmm_blk<VT, XT, AT, YT, BV, LPR>;                                          \
-    if (lds > 65536) {                                                                        \
-      static bool attr_set = false;                                                           \
-      if (!attr_set) {                                                                        \
-        BBL_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),                     \
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,               \
-                                    (int)kBlkMaxLds));                                        \
-        attr_set = true;                                                                      \
-      }                                                                                       \
-    }                                                                                         \
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kBlkThreads), lds, s, H.n,            \
-                       (int64_t)H.block_rows, H.row_ptr, H.col, valp, X, Y);                  \
-    break;                                                                                    \
-  }
-    switch (nvec) {
-      BBL_BLK_CASE(1)
-      BBL_BLK_CASE(2)
-      BBL_BLK_CASE(4)
-      BBL_BLK_CASE(8)
-      BBL_BLK_CASE(10)
-      BBL_BLK_CASE(16)
-      default: break;
-    }
-#undef BBL_BLK_CASE
-    check_launch("k_spmm_blk");
-    return;
-  }
   const int rows_per_wg = (256 / kWave) * (kWave / LPR);
   const int64_t grid = ceil_div(ceil_div(H.n, rows_per_wg), kXcds) * kXcds;
   const VT *val = static_cast<const VT *>(H.val);
@@ -398,6 +263,268 @@ void spmm_dispatch(const bbl_csr &H, const XT *X, YT *Y, int nvec, hipStream_t s
     case 16: spmm_dispatch_b<VT, XT, AT, YT, 16>(H, X, Y, nvec, s); break;
     case 32: spmm_dispatch_b<VT, XT, AT, YT, 32>(H, X, Y, nvec, s); break;
     default: spmm_dispatch_b<VT, XT, AT, YT, 64>(H, X, Y, nvec, s); break;
+  }
+}
+
+// ------------------------------------------------------------ planned SpMM
+// Prepared form of a matrix whose rows come in aligned groups of G rows
+// (bbl_csr.block_rows).  For every group the plan names up to four column
+// blocks -- its own and the partner blocks holding most of its other entries
+// -- and reorders each row: entries inside those blocks first, stored as an
+// LDS row index slot*G + (col - block start), then the others with their
+// global column.  The fused kernel stages the blocks' rows of V in LDS once
+// per group and, per row, issues the global gathers of the remote entries
+// before it walks the local ones through LDS, so the long-latency gathers
+// overlap the LDS work.
+
+constexpr int kPlanHash = 1024;
+
+// blocks[g][0] = g; blocks[g][1..slots) = the other column blocks with the
+// most entries in group g (ties to the smaller block id), -1 when fewer exist
+__global__ __launch_bounds__(256) void k_plan_blocks(int64_t n, int64_t G, int slots,
+                                                     const int64_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ col,
+                                                     int32_t *__restrict__ blocks) {
+  __shared__ int keys[kPlanHash];
+  __shared__ int cnts[kPlanHash];
+  const int64_t g = blockIdx.x;
+  const int64_t r0 = g * G, r1 = min(n, r0 + G);
+  for (int i = threadIdx.x; i < kPlanHash; i += blockDim.x) {
+    keys[i] = -1;
+    cnts[i] = 0;
+  }
+  __syncthreads();
+  const int64_t p0 = rp[r0], p1 = rp[r1];
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    const int b = (int)((int64_t)col[p] / G);
+    if (b == (int)g) continue;
+    unsigned h = ((unsigned)b * 2654435761u) >> 22;
+    for (int probe = 0; probe < kPlanHash; ++probe) {
+      const int k = atomicCAS(&keys[h], -1, b);
+      if (k == -1 || k == b) {
+        atomicAdd(&cnts[h], 1);
+        break;
+      }
+      h = (h + 1) & (kPlanHash - 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    blocks[g * slots] = (int32_t)g;
+    for (int sl = 1; sl < slots; ++sl) {
+      int best = -1, bi = -1, bc = 0;
+      for (int i = 0; i < kPlanHash; ++i) {
+        const int k = keys[i], c = cnts[i];
+        if (k < 0 || c <= 0) continue;
+        if (c > bc || (c == bc && k < best)) {
+          bc = c;
+          best = k;
+          bi = i;
+        }
+      }
+      if (bi >= 0) cnts[bi] = 0;
+      blocks[g * slots + sl] = best;
+    }
+  }
+}
+
+// Reorders every row: entries in a staged block first (as slot*G + offset),
+// the rest after them (global columns, in reverse order); n_local = count.
+template <typename VT>
+__global__ void k_plan_rows(int64_t n, int64_t G, int slots, const int64_t *__restrict__ rp,
+                            const int32_t *__restrict__ col, const VT *__restrict__ val,
+                            const int32_t *__restrict__ blocks, int32_t *__restrict__ n_local,
+                            int32_t *__restrict__ col2, VT *__restrict__ val2) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  const int64_t g = row / G;
+  int64_t base[kPlanMaxSlots];
+#pragma unroll
+  for (int k = 0; k < kPlanMaxSlots; ++k) {
+    const int b = k < slots ? blocks[g * slots + k] : -1;
+    base[k] = b >= 0 ? (int64_t)b * G : -((int64_t)1 << 62);
+  }
+  const int64_t p0 = rp[row], p1 = rp[row + 1];
+  int64_t il = p0, ir = p1 - 1;
+  for (int64_t p = p0; p < p1; ++p) {
+    const int32_t c = col[p];
+    const VT v = val[p];
+    int loc = -1;
+#pragma unroll
+    for (int k = kPlanMaxSlots - 1; k >= 0; --k) {
+      const int64_t o = (int64_t)c - base[k];
+      if (o >= 0 && o < G) loc = (int)(k * G + o);
+    }
+    if (loc >= 0) {
+      col2[il] = loc;
+      val2[il] = v;
+      ++il;
+    } else {
+      col2[ir] = c;
+      val2[ir] = v;
+      --ir;
+    }
+  }
+  n_local[row] = (int32_t)(il - p0);
+}
+
+template <typename VT, typename XT, typename AT, typename YT, int B, int LPR>
+__global__ __launch_bounds__(1024) void k_spmm_planned(int64_t n, int64_t G, int slots, int parts,
+                                                       const int64_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ n_local,
+                                                       const int32_t *__restrict__ col2,
+                                                       const VT *__restrict__ val2,
+                                                       const int32_t *__restrict__ blocks,
+                                                       const XT *__restrict__ X,
+                                                       YT *__restrict__ Y) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  XT *sX = reinterpret_cast<XT *>(smem_raw);
+  // `parts` workgroups share a group (each stages its blocks, takes a slice of
+  // its rows); they are consecutive in the XCD-aware order, so they run on one
+  // XCD together and the group's partner data is read from HBM once per L2
+  const int64_t L = xcd_block(blockIdx.x);
+  const int64_t g = L / parts, part = L % parts;
+  const int64_t gr0 = g * G;
+  if (gr0 >= n) return;  // grid padding: the whole workgroup leaves
+  const int64_t slice = (G + parts - 1) / parts;
+  const int64_t r0 = gr0 + part * slice;
+  const int64_t r1 = min(min(n, gr0 + G), r0 + slice);
+  if (r0 >= r1) return;
+  for (int k = 0; k < slots; ++k) {
+    const int b = blocks[g * slots + k];
+    if (b < 0) continue;
+    const int64_t b0 = (int64_t)b * G, b1 = min(n, b0 + G);
+    constexpr int bytes = (int)sizeof(XT) * B;
+    const unsigned char *src = reinterpret_cast<const unsigned char *>(X + b0 * B);
+    unsigned char *dst = smem_raw + (size_t)k * G * bytes;
+    const int64_t total = (b1 - b0) * bytes;
+    if constexpr (bytes % 16 == 0) {
+      for (int64_t i = threadIdx.x; i < total / 16; i += blockDim.x)
+        reinterpret_cast<uint4 *>(dst)[i] = reinterpret_cast<const uint4 *>(src)[i];
+    } else if constexpr (bytes % 8 == 0) {
+      for (int64_t i = threadIdx.x; i < total / 8; i += blockDim.x)
+        reinterpret_cast<uint2 *>(dst)[i] = reinterpret_cast<const uint2 *>(src)[i];
+    } else {
+      for (int64_t i = threadIdx.x; i < total / 4; i += blockDim.x)
+        reinterpret_cast<uint32_t *>(dst)[i] = reinterpret_cast<const uint32_t *>(src)[i];
+    }
+  }
+  __syncthreads();
+  constexpr int RPW = kWave / LPR;
+  constexpr int UL = 8, UR = 4;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int sub = lane & (LPR - 1);
+  const int wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
+  // the loop bound is uniform per wave, so every lane joins the butterfly
+  for (int64_t base = r0 + (int64_t)wave * RPW; base < r1; base += (int64_t)nwaves * RPW) {
+    const int64_t row = base + lane / LPR;
+    AT acc[B];
+#pragma unroll
+    for (int a = 0; a < B; ++a) acc[a] = AT(0);
+    if (row < r1) {
+      const int64_t p0 = rp[row], p1 = rp[row + 1];
+      const int64_t pl = p0 + n_local[row];
+      int64_t ql = p0 + sub, qr = pl + sub;
+      while (ql < pl || qr < p1) {
+        int lc[UL], rc[UR];
+        AT lh[UL], rh[UR];
+#pragma unroll
+        for (int u = 0; u < UL; ++u) {
+          const int64_t pp = ql + u * LPR;
+          lc[u] = 0;
+          lh[u] = AT(0);
+          if (pp < pl) {
+            lc[u] = col2[pp];
+            lh[u] = (AT)val2[pp];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+          const int64_t pp = qr + u * LPR;
+          rc[u] = 0;
+          rh[u] = AT(0);
+          if (pp < p1) {
+            rc[u] = col2[pp];
+            rh[u] = (AT)val2[pp];
+          }
+        }
+        // remote gathers first; their latency overlaps the LDS walk below
+        XT rx[UR][B];
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+#pragma unroll
+          for (int a = 0; a < B; ++a) rx[u][a] = XT(0);
+          if (qr + u * LPR < p1) RowIO<XT, B>::load(X + (int64_t)rc[u] * B, rx[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < UL; ++u) {
+          if (ql + u * LPR < pl) {
+            XT lx[B];
+            RowIO<XT, B>::load(sX + (int64_t)lc[u] * B, lx);
+#pragma unroll
+            for (int a = 0; a < B; ++a) acc[a] = fma(lh[u], (AT)lx[a], acc[a]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UR; ++u)
+#pragma unroll
+          for (int a = 0; a < B; ++a) acc[a] = fma(rh[u], (AT)rx[u][a], acc[a]);
+        ql += UL * LPR;
+        qr += UR * LPR;
+      }
+    }
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) {
+#pragma unroll
+      for (int a = 0; a < B; ++a) acc[a] += __shfl_xor(acc[a], off, LPR);
+    }
+    if (row < r1) {
+#pragma unroll
+      for (int a0 = 0; a0 < B; a0 += LPR) {
+        AT v = acc[0];
+#pragma unroll
+        for (int a = 1; a < B; ++a)
+          if (a == a0 + sub) v = acc[a];
+        if (a0 + sub < B) Y[row * B + a0 + sub] = (YT)v;
+      }
+    }
+  }
+}
+
+constexpr int kPlanThreads = 1024;
+constexpr int kPlanParts = 4;   // workgroups per row group
+
+template <typename VT, typename XT, int BV>
+void planned_launch(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s) {
+  auto kern = k_spmm_planned<VT, XT, XT, XT, BV, 16>;
+  const size_t lds = (size_t)P.slots * P.block_rows * BV * sizeof(XT);
+  if (lds > 65536) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      BBL_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPlanLds));
+      attr_set = true;
+    }
+  }
+  const int parts = (int)std::min<int64_t>(kPlanParts, ceil_div(P.block_rows, 64));
+  const int64_t groups = ceil_div(P.n, P.block_rows);
+  const int64_t grid = ceil_div(groups * parts, kXcds) * kXcds;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPlanThreads), lds, s, P.n,
+                     (int64_t)P.block_rows, P.slots, parts, P.row_ptr, P.n_local, P.col,
+                     static_cast<const VT *>(P.val), P.blocks, X, Y);
+  check_launch("k_spmm_planned");
+}
+
+template <typename VT, typename XT>
+void planned_dispatch(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s) {
+  switch (P.nvec) {
+    case 1: planned_launch<VT, XT, 1>(P, X, Y, s); break;
+    case 2: planned_launch<VT, XT, 2>(P, X, Y, s); break;
+    case 4: planned_launch<VT, XT, 4>(P, X, Y, s); break;
+    case 8: planned_launch<VT, XT, 8>(P, X, Y, s); break;
+    case 10: planned_launch<VT, XT, 10>(P, X, Y, s); break;
+    case 16: planned_launch<VT, XT, 16>(P, X, Y, s); break;
+    default: throw Error{BBL_E_INVALID, "planned SpMM: unsupported nvec"};
   }
 }
 
@@ -441,6 +568,84 @@ int launch_residual_spmm(const bbl_csr &H, const double *X, int nvec, const doub
 #undef BBL_RES
   check_launch("k_residual");
   return grid;
+}
+
+
+int spmm_plan_slots(const bbl_csr &H, int nvec, int vec_dtype) {
+  if (H.block_rows <= 0) return 0;
+  if (!(nvec == 1 || nvec == 2 || nvec == 4 || nvec == 8 || nvec == 10 || nvec == 16)) return 0;
+  const size_t per = (size_t)H.block_rows * nvec * (vec_dtype == BBL_F32 ? 4 : 8);
+  return (int)std::min<size_t>(kPlanMaxSlots, kPlanLds / per);
+}
+
+size_t spmm_plan_bytes(const bbl_csr &H, int nvec, int vec_dtype) {
+  const int slots = spmm_plan_slots(H, nvec, vec_dtype);
+  if (slots < 1) return 0;
+  const int64_t groups = ceil_div(H.n, H.block_rows);
+  const size_t sv = H.val_dtype == BBL_F32 ? 4 : 8;
+  return align_up((size_t)groups * slots * 4) + align_up((size_t)H.n * 4) +
+         align_up((size_t)std::max<int64_t>(H.nnz, 1) * 4) +
+         align_up((size_t)std::max<int64_t>(H.nnz, 1) * sv) + 256;
+}
+
+void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_t bytes,
+                     bbl_spmm_plan *P, hipStream_t s) {
+  const int slots = spmm_plan_slots(H, nvec, vec_dtype);
+  if (slots < 1)
+    throw Error{BBL_E_INVALID, "no plan: block_rows must be > 0, nvec in {1,2,4,8,10,16} and "
+                               "one block of V must fit in 128 KB of LDS"};
+  if (bytes < spmm_plan_bytes(H, nvec, vec_dtype)) throw Error{BBL_E_NOMEM, "plan memory too small"};
+  const int64_t groups = ceil_div(H.n, H.block_rows);
+  const size_t sv = H.val_dtype == BBL_F32 ? 4 : 8;
+  char *base = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(mem), 256));
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    char *p = base + off;
+    off += align_up(b);
+    return p;
+  };
+  int32_t *blocks = reinterpret_cast<int32_t *>(take((size_t)groups * slots * 4));
+  int32_t *n_local = reinterpret_cast<int32_t *>(take((size_t)H.n * 4));
+  int32_t *col2 = reinterpret_cast<int32_t *>(take((size_t)std::max<int64_t>(H.nnz, 1) * 4));
+  void *val2 = take((size_t)std::max<int64_t>(H.nnz, 1) * sv);
+  hipLaunchKernelGGL(k_plan_blocks, dim3((unsigned)groups), dim3(256), 0, s, H.n,
+                     (int64_t)H.block_rows, slots, H.row_ptr, H.col, blocks);
+  const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(H.n, 256));
+  if (H.val_dtype == BBL_F32)
+    hipLaunchKernelGGL((k_plan_rows<float>), dim3(grid), dim3(256), 0, s, H.n,
+                       (int64_t)H.block_rows, slots, H.row_ptr, H.col,
+                       static_cast<const float *>(H.val), blocks, n_local, col2,
+                       static_cast<float *>(val2));
+  else
+    hipLaunchKernelGGL((k_plan_rows<double>), dim3(grid), dim3(256), 0, s, H.n,
+                       (int64_t)H.block_rows, slots, H.row_ptr, H.col,
+                       static_cast<const double *>(H.val), blocks, n_local, col2,
+                       static_cast<double *>(val2));
+  check_launch("spmm plan");
+  P->n = H.n;
+  P->nnz = H.nnz;
+  P->block_rows = H.block_rows;
+  P->slots = slots;
+  P->nvec = nvec;
+  P->vec_dtype = vec_dtype;
+  P->val_dtype = H.val_dtype;
+  P->reserved = 0;
+  P->row_ptr = H.row_ptr;
+  P->blocks = blocks;
+  P->n_local = n_local;
+  P->col = col2;
+  P->val = val2;
+}
+
+void launch_spmm_planned(const bbl_spmm_plan &P, const void *X, void *Y, hipStream_t s) {
+  if (P.n == 0) return;
+  if (P.val_dtype == BBL_F32 && P.vec_dtype == BBL_F32)
+    planned_dispatch<float, float>(P, static_cast<const float *>(X), static_cast<float *>(Y), s);
+  else if (P.val_dtype == BBL_F64 && P.vec_dtype == BBL_F64)
+    planned_dispatch<double, double>(P, static_cast<const double *>(X), static_cast<double *>(Y),
+                                     s);
+  else
+    throw Error{BBL_E_INVALID, "planned SpMM: values and vectors must share float32 or float64"};
 }
 
 }  // namespace bbl

@@ -228,13 +228,13 @@ __device__ __forceinline__ Vec<T, N> vload(const T *p) {
 // Gram over 8-wide FP32 basis blocks on v_mfma_f64_4x4x4f64 (four independent
 // 4x4x4 products per instruction; operand layout: block g = (l % 16) / 4,
 // A[i][k] at lane 16k + 4g + i, B[k][j] at lane 16k + 4g + j, D[i][j] at lane
-// 16i + 4g + j).  K runs over rows.  A lane (k, g, e) loads ONE float4 of row
-// r0 + k -- wide columns c0 + 16*ht + 4e .. +3 (ht = g / 2, inside one block
-// row) -- and feeds its four components to four MFMAs q = 0..3; in MFMA q,
-// block g computes the 4x4 tile with X columns c0 + 16*ht + 4i + q and Y
-// columns 4*jt + j (jt = g % 2).  So one load instruction reads four whole
-// 128-byte lines (rows r0..r0+3 of four basis blocks) and the MFMAs carry no
-// padding.  Each wave keeps CG groups of 32 columns, U row groups in flight.
+// 16i + 4g + j).  K runs over rows.  Lane (k, g, e) loads ONE float4 of row
+// r0 + k: X columns c0 + 16g + 4e .. +3 (inside one 8-wide block row), so one
+// load instruction reads four whole 128-byte lines (rows r0..r0+3 of eight
+// basis blocks) and no X element is loaded twice.  Its four components feed
+// four MFMA pairs q = 0..3; in pair q, block g computes the 4x4 tiles of X
+// columns c0 + 16g + 4i + q against Y columns 0..3 and 4..7.  Each wave covers
+// 64*CG columns and keeps U row groups of four in flight.
 template <int CG, int U>
 __global__ __launch_bounds__(64) void k_gram_mfma8(int64_t n, const float *__restrict__ X, int M,
                                                    int64_t xstride, const double *__restrict__ Y,
@@ -243,33 +243,32 @@ __global__ __launch_bounds__(64) void k_gram_mfma8(int64_t n, const float *__res
   if (when && *when == 0) return;
   const int l = threadIdx.x;
   const int k = l >> 4, g = (l & 15) >> 2, e = l & 3;
-  const int ht = g >> 1, jt = g & 1;
-  const int c00 = blockIdx.y * (32 * CG);
-  // per column group: address of this lane's float4 in row 0, validity
+  const int c00 = blockIdx.y * (64 * CG);
   int64_t xo[CG];
   bool ok[CG];
 #pragma unroll
   for (int c = 0; c < CG; ++c) {
-    const int col = c00 + 32 * c + 16 * ht + 4 * e;  // first of 4 wide columns
+    const int col = c00 + 64 * c + 16 * g + 4 * e;  // first of 4 columns
     ok[c] = col < M;
     const int blk = col >> 3, a = col & 7;
     xo[c] = (int64_t)blk * xstride + a;
   }
-  double acc[CG][4];
+  double acc[CG][4][2];
 #pragma unroll
   for (int c = 0; c < CG; ++c)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[c][q] = 0.0;
+    for (int q = 0; q < 4; ++q) acc[c][q][0] = acc[c][q][1] = 0.0;
   const int64_t r0 = (int64_t)blockIdx.x * chunk;
   const int64_t r1 = min(n, r0 + chunk);
   for (int64_t rb = r0; rb < r1; rb += 4 * U) {
-    double y[U];
+    double y0[U], y1[U];
     float4 x[U][CG];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t r = rb + 4 * u + k;
       const bool rok = r < r1;
-      y[u] = rok ? Y[r * 8 + 4 * jt + e] : 0.0;
+      y0[u] = rok ? Y[r * 8 + e] : 0.0;
+      y1[u] = rok ? Y[r * 8 + 4 + e] : 0.0;
 #pragma unroll
       for (int c = 0; c < CG; ++c)
         x[u][c] = (rok && ok[c]) ? *reinterpret_cast<const float4 *>(X + xo[c] + r * 8)
@@ -279,21 +278,27 @@ __global__ __launch_bounds__(64) void k_gram_mfma8(int64_t n, const float *__res
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int c = 0; c < CG; ++c) {
-        acc[c][0] = __builtin_amdgcn_mfma_f64_4x4x4f64((double)x[u][c].x, y[u], acc[c][0], 0, 0, 0);
-        acc[c][1] = __builtin_amdgcn_mfma_f64_4x4x4f64((double)x[u][c].y, y[u], acc[c][1], 0, 0, 0);
-        acc[c][2] = __builtin_amdgcn_mfma_f64_4x4x4f64((double)x[u][c].z, y[u], acc[c][2], 0, 0, 0);
-        acc[c][3] = __builtin_amdgcn_mfma_f64_4x4x4f64((double)x[u][c].w, y[u], acc[c][3], 0, 0, 0);
+        const double xs[4] = {(double)x[u][c].x, (double)x[u][c].y, (double)x[u][c].z,
+                              (double)x[u][c].w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          acc[c][q][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(xs[q], y0[u], acc[c][q][0], 0, 0, 0);
+          acc[c][q][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(xs[q], y1[u], acc[c][q][1], 0, 0, 0);
+        }
       }
   }
-  // D lane l = 16i + 4g + j holds tile (g, q): X column c0 + 16ht + 4i + q,
-  // Y column 4jt + j, with i = k (l >> 4) and j = e (l & 3)
+  // D lane l = 16i + 4g + j holds tile (g, q) element (i, j): X column
+  // c0 + 16g + 4i + q with i = k (l >> 4), Y column j or 4 + j with j = e
   double *out = partial + (int64_t)blockIdx.x * M * 8;
 #pragma unroll
   for (int c = 0; c < CG; ++c)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int m = c00 + 32 * c + 16 * ht + 4 * k + q;
-      if (m < M) out[(int64_t)m * 8 + 4 * jt + e] = acc[c][q];
+      const int m = c00 + 64 * c + 16 * g + 4 * k + q;
+      if (m < M) {
+        out[(int64_t)m * 8 + e] = acc[c][q][0];
+        out[(int64_t)m * 8 + 4 + e] = acc[c][q][1];
+      }
     }
 }
 
@@ -539,12 +544,12 @@ int gram_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const 
     return (int)(grid * 4);
   }
   if (bx == 8 && ny == 8 && f32 && std::is_same<YT, double>::value && nblk >= 2) {
-    // 64 basis columns per one-wave workgroup, about 14k workgroups (measured
-    // on MI355X at n = 2e6, 50 blocks: 4.2 TB/s, against 2.3 TB/s for the
-    // VALU kernel with ~2k workgroups)
-    constexpr int CG = 2, U = 2;
-    const int gy = (M + 32 * CG - 1) / (32 * CG);
-    int64_t gx = std::max<int64_t>(1, std::min<int64_t>(14336 / gy + 1, ceil_div(n, 256)));
+    // 64 basis columns per one-wave workgroup, ~1000 row chunks (measured on
+    // MI355X at n = 2e6, 50 blocks: 4.9 TB/s, against 2.3 TB/s for the VALU
+    // kernel with ~2k workgroups)
+    constexpr int CG = 1, U = 2;
+    const int gy = (M + 64 * CG - 1) / (64 * CG);
+    int64_t gx = std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(n, 256)));
     gx = std::min<int64_t>(gx, std::max(1, max_partials));
     int64_t chunk = ceil_div(ceil_div(n, gx), 4 * U) * (4 * U);
     gx = ceil_div(n, chunk);

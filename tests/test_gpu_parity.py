@@ -76,28 +76,53 @@ def test_spmm_matches_oracle_within_dot_product_bound(torch, bbl, nvec, prec):
 
 
 @pytest.mark.parametrize("nvec,block_rows,prec", [(8, 400, "f32"), (8, 400, "f64"), (1, 400, "f32"),
-                                                   (4, 333, "f32"), (10, 400, "f64"),
-                                                   (16, 2048, "f32"), (16, 4096, "f32"),
-                                                   (3, 400, "f32"), (8, 50000, "f32")])
-def test_spmm_sector_staging_is_bitwise_identical(torch, bbl, nvec, block_rows, prec):
-    """The locality hint only changes where in-group rows of V are read from:
-    same lanes, same order, so the product equals the unhinted one bit for bit
-    (16 x 4096 float32 rows exceed the LDS budget and take the plain kernel;
-    nvec 3 has no staged instantiation)."""
-    note("spmm block_rows=%d nvec=%d %s" % (block_rows, nvec, prec))
+                                                   (4, 333, "f32"), (10, 400, "f32"),
+                                                   (16, 400, "f32"), (2, 400, "f64"),
+                                                   (16, 400, "f64"), (8, 3000, "f32"),
+                                                   (1, 25000, "f32")])
+def test_planned_spmm_matches_oracle(torch, bbl, nvec, block_rows, prec):
+    """Rows reordered per group, partner blocks staged in LDS: the same sums
+    in another order, so the dot-product bound holds entry by entry (groups
+    of 333 rows straddle the generator's 400-row sectors; 3000-row groups
+    leave a ragged last group; 25000 rows make one group larger than n)."""
+    note("planned spmm block_rows=%d nvec=%d %s" % (block_rows, nvec, prec))
     H = synthgen.generate(20000, 400, 20, 0.7, 11)
     dt = "float32" if prec == "f32" else "float64"
+    Hd = bbl.DeviceCSR.from_host(H, dt, block_rows=block_rows)
+    plan = bbl.spmm_plan(Hd, nvec)
+    per_block = block_rows * nvec * (4 if prec == "f32" else 8)
+    assert plan.slots == min(4, 128 * 1024 // per_block)
     V = synthgen.gaussian_block(H.n, nvec, 5)
     Vd = dev(torch, V.astype(np.float32) if prec == "f32" else V)
-    a = bbl.spmm(bbl.DeviceCSR.from_host(H, dt), Vd).cpu().numpy()
-    b = bbl.spmm(bbl.DeviceCSR.from_host(H, dt, block_rows=block_rows), Vd).cpu().numpy()
-    assert np.array_equal(a, b)
+    W = bbl.spmm_planned(plan, Vd).double().cpu().numpy()
+    W2 = bbl.spmm_planned(plan, Vd).double().cpu().numpy()
+    assert np.array_equal(W, W2)
     Href = H.as_float32_values() if prec == "f32" else H
     Vr = V.astype(np.float32).astype(np.float64) if prec == "f32" else V
     u = U32 if prec == "f32" else U64
     z = np.diff(H.row_ptr)[:, None]
     bound = gamma(z + 2, u) * oracle.spmm_abs(Href, Vr) + 1e-300
-    assert np.all(np.abs(b - oracle.spmm(Href, Vr)) <= bound)
+    assert np.all(np.abs(W - oracle.spmm(Href, Vr)) <= bound)
+
+
+def test_spmm_plan_layout_and_errors(torch, bbl):
+    note("spmm plan layout")
+    H = synthgen.generate(12000, 400, 20, 0.7, 3)
+    Hd = bbl.DeviceCSR.from_host(H, "float32", block_rows=400)
+    plan = bbl.spmm_plan(Hd, 8)
+    # n_local sits in the plan buffer right after the block table
+    off = plan.c.n_local - plan.mem.data_ptr()
+    assert off == ((plan.mem.data_ptr() + 255) // 256 * 256 - plan.mem.data_ptr()
+                   + -(-(30 * plan.slots * 4) // 256) * 256)
+    nl = plan.mem[off:off + 4 * H.n].view(torch.int32).cpu().numpy()
+    lens = np.diff(H.row_ptr)
+    assert np.all(nl >= 0) and np.all(nl <= lens)
+    # own sector (70 % of draws) plus the three busiest partners
+    assert nl.sum() / lens.sum() > 0.75
+    with pytest.raises(bbl.BblError):
+        bbl.spmm_plan(bbl.DeviceCSR.from_host(H, "float32"), 8)          # no hint
+    with pytest.raises(bbl.BblError):
+        bbl.spmm_plan(Hd, 3)                                             # no kernel width 3
 
 
 def test_spmm_ragged_rows_and_empty_rows(torch, bbl):
@@ -295,6 +320,16 @@ def test_fp32_path_matches_oracle_on_rounded_matrix(torch, bbl):
     Hd64 = bbl.DeviceCSR.from_host(H32, "float64")
     r64 = bbl.block_lanczos(Hd64, P, 10, 1e-6, m_max=200)
     np.testing.assert_allclose(r.eigvals, r64.eigvals, rtol=1e-5)
+    # the recurrence through the planned SpMM (sectors of 1000 rows)
+    Hp = bbl.DeviceCSR.from_host(H, "float32", block_rows=1000)
+    plan = bbl.spmm_plan(Hp, 8)
+    rp = bbl.block_lanczos(Hp, P, 10, 1e-6, m_max=200, spmm_plan=plan)
+    assert rp.converged
+    np.testing.assert_allclose(rp.eigvals, ro.eigvals, rtol=1e-5)
+    res_p = oracle.ritz_residuals(H32, rp.eigvecs.cpu().numpy(), rp.eigvals)
+    assert np.all(res_p <= 1e-6 * rp.stats["hnorm_est"])
+    with pytest.raises(bbl.BblError):       # a plan for another block width
+        bbl.block_lanczos(Hp, P[:, :4].contiguous(), 4, 1e-6, m_max=50, spmm_plan=plan)
 
 
 def test_exact_eigenvector_pivot_deflates_and_converges_at_once(torch, bbl):
