@@ -119,6 +119,97 @@ __global__ __launch_bounds__(64) void k_sturm(const double *__restrict__ Tb, int
   if (threadIdx.x == 0) counts[blockIdx.x] = c;
 }
 
+// Register-window Sturm counts for a compile-time bandwidth KD: one shift per
+// lane, 64 shifts per wave.  The (KD+1) x (KD+1) trailing window of the
+// partially factored T - sigma I is held as its lower triangle in registers,
+// indexed by circular slots; the row loop is unrolled by KD + 1 so that every
+// slot index is a compile-time constant.  Band rows are the same for all lanes
+// (uniform loads).  Same arithmetic as ldl_sweep, so the counts agree with it.
+constexpr int tri(int a, int b) { return a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a; }
+
+// Steps M..KD of one unrolled group of W = KD + 1 rows, slot indices static.
+template <int KD, int M>
+__device__ __forceinline__ void sturm_steps(const double *__restrict__ Tb, int N, int k0,
+                                            double sigma, double pivmin, double (&R)[(KD + 1) * (KD + 2) / 2],
+                                            int &cnt) {
+  if constexpr (M <= KD) {
+    constexpr int W = KD + 1;
+    const int k = k0 + M;
+    if (k < N) {
+      // relative row i of the window lives in slot (M + i) % W
+      double d = R[tri(M, M)];
+      if (fabs(d) < pivmin) d = -pivmin;
+      cnt += d < 0.0 ? 1 : 0;
+      const double inv = 1.0 / d;
+#pragma unroll
+      for (int i = 1; i <= KD; ++i) {
+        const int si = (M + i) % W;
+        const double li = R[tri(si, M)];
+#pragma unroll
+        for (int j = 1; j <= i; ++j) {
+          const int sj = (M + j) % W;
+          R[tri(si, sj)] -= li * R[tri(sj, M)] * inv;
+        }
+      }
+      // row k + W enters in the freed slot M: T[k+W][k+W-t], t = 0..KD
+      const int nr = k + W;
+#pragma unroll
+      for (int t = 0; t <= KD; ++t) {
+        double v = 0.0;
+        if (nr < N) {
+          v = Tb[(int64_t)nr * W + t];
+          if (t == 0) v -= sigma;
+        }
+        R[tri(M, (M + W - t) % W)] = v;
+      }
+      sturm_steps<KD, M + 1>(Tb, N, k0, sigma, pivmin, R, cnt);
+    }
+  }
+}
+
+template <int KD>
+__global__ __launch_bounds__(64) void k_sturm_reg(const double *__restrict__ Tb, int N,
+                                                  const double *__restrict__ shifts, int nshift,
+                                                  int *__restrict__ counts, double pivmin) {
+  constexpr int W = KD + 1;
+  constexpr int NP = W * (W + 1) / 2;
+  const int id = blockIdx.x * 64 + threadIdx.x;
+  const double sigma = id < nshift ? shifts[id] : 0.0;
+  double R[NP];
+#pragma unroll
+  for (int r = 0; r < W; ++r)
+#pragma unroll
+    for (int c = 0; c <= r; ++c) {
+      double v = 0.0;
+      if (r < N) {
+        v = Tb[(int64_t)r * W + (r - c)];
+        if (r == c) v -= sigma;
+      }
+      R[tri(r, c)] = v;
+    }
+  int cnt = 0;
+  for (int k0 = 0; k0 < N; k0 += W) {
+    sturm_steps<KD, 0>(Tb, N, k0, sigma, pivmin, R, cnt);
+  }
+  if (id < nshift) counts[id] = cnt;
+}
+
+void sturm_counts(const double *Tb, int N, int kd, const double *shifts, int nshift, int *counts,
+                  double pivmin, size_t smem_generic, hipStream_t s) {
+  const unsigned waves = (unsigned)((nshift + 63) / 64);
+  switch (kd) {
+    case 1: hipLaunchKernelGGL(k_sturm_reg<1>, dim3(waves), dim3(64), 0, s, Tb, N, shifts, nshift, counts, pivmin); break;
+    case 2: hipLaunchKernelGGL(k_sturm_reg<2>, dim3(waves), dim3(64), 0, s, Tb, N, shifts, nshift, counts, pivmin); break;
+    case 4: hipLaunchKernelGGL(k_sturm_reg<4>, dim3(waves), dim3(64), 0, s, Tb, N, shifts, nshift, counts, pivmin); break;
+    case 8: hipLaunchKernelGGL(k_sturm_reg<8>, dim3(waves), dim3(64), 0, s, Tb, N, shifts, nshift, counts, pivmin); break;
+    case 10: hipLaunchKernelGGL(k_sturm_reg<10>, dim3(waves), dim3(64), 0, s, Tb, N, shifts, nshift, counts, pivmin); break;
+    default:
+      hipLaunchKernelGGL(k_sturm, dim3(nshift), dim3(64), smem_generic, s, Tb, N, kd, shifts,
+                         counts, pivmin);
+  }
+  check_launch("k_sturm");
+}
+
 // Gershgorin interval of T: out[0] = lower bound, out[1] = upper bound.
 __global__ __launch_bounds__(256) void k_gersh(const double *__restrict__ Tb, int N, int kd,
                                                double *out) {
@@ -440,16 +531,12 @@ void band_eigensolve(const double *band, int N, int kd, int k, void *ws, const B
   hipLaunchKernelGGL(k_bisect_init, dim3(4), dim3(256), 0, s, gersh, kShifts1, sh_a, brk, NT);
   check_launch("k_bisect_init");
   const size_t smem_s = (size_t)((kdd + 1) * (kdd + 1) + kChunk * (kdd + 1)) * sizeof(double);
-  hipLaunchKernelGGL(k_sturm, dim3(kShifts1), dim3(64), smem_s, s, band, N, kdd, sh_a, counts,
-                     pivmin);
-  check_launch("k_sturm");
+  sturm_counts(band, N, kdd, sh_a, kShifts1, counts, pivmin, smem_s, s);
   hipLaunchKernelGGL(k_bisect_update, dim3(1), dim3(256), 0, s, 1, sh_a, counts, kShifts1, N, k,
                      brk, kShiftsT, sh_b);
   check_launch("k_bisect_update");
   for (int r = 1; r < kRounds; ++r) {
-    hipLaunchKernelGGL(k_sturm, dim3(NT * kShiftsT), dim3(64), smem_s, s, band, N, kdd, sh_b,
-                       counts, pivmin);
-    check_launch("k_sturm");
+    sturm_counts(band, N, kdd, sh_b, NT * kShiftsT, counts, pivmin, smem_s, s);
     const bool last = (r == kRounds - 1);
     hipLaunchKernelGGL(k_bisect_update, dim3(1), dim3(256), 0, s, 0, sh_b, counts, kShiftsT, N,
                        k, brk, kShiftsT, last ? nullptr : sh_a);

@@ -328,15 +328,21 @@ __global__ __launch_bounds__(256) void k_plan_blocks(int64_t n, int64_t G, int s
   }
 }
 
-// Reorders every row: entries in a staged block first (as slot*G + offset),
-// the rest after them (global columns, in reverse order); n_local = count.
+// Reorders every row (one wave per row): entries in a staged block first, in
+// their original order, as slot*G + offset; the others after them with their
+// global column, in their original order; n_local = count of the first kind.
 template <typename VT>
-__global__ void k_plan_rows(int64_t n, int64_t G, int slots, const int64_t *__restrict__ rp,
-                            const int32_t *__restrict__ col, const VT *__restrict__ val,
-                            const int32_t *__restrict__ blocks, int32_t *__restrict__ n_local,
-                            int32_t *__restrict__ col2, VT *__restrict__ val2) {
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= n) return;
+__global__ __launch_bounds__(256) void k_plan_rows(int64_t n, int64_t G, int slots,
+                                                   const int64_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ col,
+                                                   const VT *__restrict__ val,
+                                                   const int32_t *__restrict__ blocks,
+                                                   int32_t *__restrict__ n_local,
+                                                   int32_t *__restrict__ col2,
+                                                   VT *__restrict__ val2) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;  // uniform per wave
+  const int lane = threadIdx.x & 63;
   const int64_t g = row / G;
   int64_t base[kPlanMaxSlots];
 #pragma unroll
@@ -344,28 +350,42 @@ __global__ void k_plan_rows(int64_t n, int64_t G, int slots, const int64_t *__re
     const int b = k < slots ? blocks[g * slots + k] : -1;
     base[k] = b >= 0 ? (int64_t)b * G : -((int64_t)1 << 62);
   }
-  const int64_t p0 = rp[row], p1 = rp[row + 1];
-  int64_t il = p0, ir = p1 - 1;
-  for (int64_t p = p0; p < p1; ++p) {
-    const int32_t c = col[p];
-    const VT v = val[p];
+  auto local_index = [&](int32_t c) {
     int loc = -1;
 #pragma unroll
     for (int k = kPlanMaxSlots - 1; k >= 0; --k) {
       const int64_t o = (int64_t)c - base[k];
       if (o >= 0 && o < G) loc = (int)(k * G + o);
     }
-    if (loc >= 0) {
-      col2[il] = loc;
-      val2[il] = v;
-      ++il;
-    } else {
-      col2[ir] = c;
-      val2[ir] = v;
-      --ir;
-    }
+    return loc;
+  };
+  const int64_t p0 = rp[row], p1 = rp[row + 1];
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int nl = 0;
+  for (int64_t p = p0 + lane; p - lane < p1; p += 64) {
+    const bool isl = p < p1 && local_index(col[p]) >= 0;
+    nl += __popcll(__ballot(isl));
   }
-  n_local[row] = (int32_t)(il - p0);
+  int il = 0, ir = 0;
+  for (int64_t p = p0 + lane; p - lane < p1; p += 64) {
+    const bool in = p < p1;
+    const int32_t c = in ? col[p] : 0;
+    const int loc = in ? local_index(c) : -1;
+    const bool isl = in && loc >= 0;
+    const uint64_t ml = __ballot(isl), mr = __ballot(in && !isl);
+    if (isl) {
+      const int64_t q = p0 + il + __popcll(ml & below);
+      col2[q] = loc;
+      val2[q] = val[p];
+    } else if (in) {
+      const int64_t q = p0 + nl + ir + __popcll(mr & below);
+      col2[q] = c;
+      val2[q] = val[p];
+    }
+    il += __popcll(ml);
+    ir += __popcll(mr);
+  }
+  if (lane == 0) n_local[row] = nl;
 }
 
 template <typename VT, typename XT, typename AT, typename YT, int B, int LPR>
@@ -610,7 +630,7 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
   void *val2 = take((size_t)std::max<int64_t>(H.nnz, 1) * sv);
   hipLaunchKernelGGL(k_plan_blocks, dim3((unsigned)groups), dim3(256), 0, s, H.n,
                      (int64_t)H.block_rows, slots, H.row_ptr, H.col, blocks);
-  const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(H.n, 256));
+  const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(H.n, 4));
   if (H.val_dtype == BBL_F32)
     hipLaunchKernelGGL((k_plan_rows<float>), dim3(grid), dim3(256), 0, s, H.n,
                        (int64_t)H.block_rows, slots, H.row_ptr, H.col,
