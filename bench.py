@@ -387,6 +387,8 @@ def main():
 
     extra = {
         "bootstrap": {"iters": r.stats["iters"], "spmm_calls": r.stats["spmm_calls"],
+                      "checks": r.stats["checks"], "deflations": r.stats["deflations"],
+                      "reorth_second_passes": r.stats["reorth_second_passes"],
                       "vector_equiv_iters": r.stats["iters"] * b,
                       "pivot_iters": pst["iters"], "pivot_spmm_calls": pst["spmm_calls"],
                       "eigvals": [float(x) for x in r.eigvals],

@@ -279,6 +279,27 @@ void spmm_dispatch(const bbl_csr &H, const XT *X, YT *Y, int nvec, hipStream_t s
 
 constexpr int kPlanHash = 1024;
 
+// four consecutive values from a 16-byte aligned (float) / 32-byte aligned
+// (double) address
+template <typename T>
+struct Quad {
+  T v[4];
+};
+template <typename T>
+__device__ __forceinline__ Quad<T> load_quad(const T *__restrict__ p) {
+  Quad<T> q;
+  if constexpr (sizeof(T) == 4) {
+    const uint4 u = *reinterpret_cast<const uint4 *>(p);
+    __builtin_memcpy(q.v, &u, 16);
+  } else {
+    const uint4 *w = reinterpret_cast<const uint4 *>(p);
+    const uint4 u0 = w[0], u1 = w[1];
+    __builtin_memcpy(q.v, &u0, 16);
+    __builtin_memcpy(q.v + 2, &u1, 16);
+  }
+  return q;
+}
+
 // blocks[g][0] = g; blocks[g][1..slots) = the other column blocks with the
 // most entries in group g (ties to the smaller block id), -1 when fewer exist
 __global__ __launch_bounds__(256) void k_plan_blocks(int64_t n, int64_t G, int slots,
@@ -431,10 +452,13 @@ __global__ __launch_bounds__(1024) void k_spmm_planned(int64_t n, int64_t G, int
   }
   __syncthreads();
   constexpr int RPW = kWave / LPR;
-  constexpr int UL = 8, UR = 4;
   const int lane = threadIdx.x & (kWave - 1);
   const int sub = lane & (LPR - 1);
   const int wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
+  // Each lane takes four consecutive entries per chunk (one 16-byte load of
+  // indices and one of values; chunks start at multiples of four entries, the
+  // plan pads its arrays so the last load stays inside them).
+  constexpr int CH = 4 * LPR;
   // the loop bound is uniform per wave, so every lane joins the butterfly
   for (int64_t base = r0 + (int64_t)wave * RPW; base < r1; base += (int64_t)nwaves * RPW) {
     const int64_t row = base + lane / LPR;
@@ -444,53 +468,55 @@ __global__ __launch_bounds__(1024) void k_spmm_planned(int64_t n, int64_t G, int
     if (row < r1) {
       const int64_t p0 = rp[row], p1 = rp[row + 1];
       const int64_t pl = p0 + n_local[row];
-      int64_t ql = p0 + sub, qr = pl + sub;
-      while (ql < pl || qr < p1) {
-        int lc[UL], rc[UR];
-        AT lh[UL], rh[UR];
+      int64_t qr = (pl & ~(int64_t)3) + 4 * sub;   // remote chunk cursor
+      int64_t ql = (p0 & ~(int64_t)3) + 4 * sub;   // local chunk cursor
+      while (qr < p1 || ql < pl) {
+        // remote entries of this chunk: indices, values, then the gathers
+        XT rx[4][B];
+        AT rh[4];
+        {
+          int4 c4 = make_int4(0, 0, 0, 0);
+          Quad<VT> v4;
 #pragma unroll
-        for (int u = 0; u < UL; ++u) {
-          const int64_t pp = ql + u * LPR;
-          lc[u] = 0;
-          lh[u] = AT(0);
-          if (pp < pl) {
-            lc[u] = col2[pp];
-            lh[u] = (AT)val2[pp];
+          for (int e = 0; e < 4; ++e) v4.v[e] = VT(0);
+          if (qr < p1) {
+            c4 = *reinterpret_cast<const int4 *>(col2 + qr);
+            v4 = load_quad(val2 + qr);
+          }
+          const int cc[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t pe = qr + e;
+            const bool ok = pe >= pl && pe < p1;
+            rh[e] = ok ? (AT)v4.v[e] : AT(0);
+#pragma unroll
+            for (int a = 0; a < B; ++a) rx[e][a] = XT(0);
+            if (ok) RowIO<XT, B>::load(X + (int64_t)cc[e] * B, rx[e]);
+          }
+        }
+        // local entries: LDS gathers while the remote ones are in flight
+        if (ql < pl) {
+          const int4 c4 = *reinterpret_cast<const int4 *>(col2 + ql);
+          const Quad<VT> v4 = load_quad(val2 + ql);
+          const int cc[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t pe = ql + e;
+            if (pe >= p0 && pe < pl) {
+              XT lx[B];
+              RowIO<XT, B>::load(sX + (int64_t)cc[e] * B, lx);
+              const AT h = (AT)v4.v[e];
+#pragma unroll
+              for (int a = 0; a < B; ++a) acc[a] = fma(h, (AT)lx[a], acc[a]);
+            }
           }
         }
 #pragma unroll
-        for (int u = 0; u < UR; ++u) {
-          const int64_t pp = qr + u * LPR;
-          rc[u] = 0;
-          rh[u] = AT(0);
-          if (pp < p1) {
-            rc[u] = col2[pp];
-            rh[u] = (AT)val2[pp];
-          }
-        }
-        // remote gathers first; their latency overlaps the LDS walk below
-        XT rx[UR][B];
+        for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int u = 0; u < UR; ++u) {
-#pragma unroll
-          for (int a = 0; a < B; ++a) rx[u][a] = XT(0);
-          if (qr + u * LPR < p1) RowIO<XT, B>::load(X + (int64_t)rc[u] * B, rx[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < UL; ++u) {
-          if (ql + u * LPR < pl) {
-            XT lx[B];
-            RowIO<XT, B>::load(sX + (int64_t)lc[u] * B, lx);
-#pragma unroll
-            for (int a = 0; a < B; ++a) acc[a] = fma(lh[u], (AT)lx[a], acc[a]);
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < UR; ++u)
-#pragma unroll
-          for (int a = 0; a < B; ++a) acc[a] = fma(rh[u], (AT)rx[u][a], acc[a]);
-        ql += UL * LPR;
-        qr += UR * LPR;
+          for (int a = 0; a < B; ++a) acc[a] = fma(rh[e], (AT)rx[e][a], acc[a]);
+        qr += CH;
+        ql += CH;
       }
     }
 #pragma unroll
@@ -603,9 +629,9 @@ size_t spmm_plan_bytes(const bbl_csr &H, int nvec, int vec_dtype) {
   if (slots < 1) return 0;
   const int64_t groups = ceil_div(H.n, H.block_rows);
   const size_t sv = H.val_dtype == BBL_F32 ? 4 : 8;
+  // index and value arrays padded by 4 entries for the 16-byte chunk loads
   return align_up((size_t)groups * slots * 4) + align_up((size_t)H.n * 4) +
-         align_up((size_t)std::max<int64_t>(H.nnz, 1) * 4) +
-         align_up((size_t)std::max<int64_t>(H.nnz, 1) * sv) + 256;
+         align_up((size_t)(H.nnz + 4) * 4) + align_up((size_t)(H.nnz + 4) * sv) + 256;
 }
 
 void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_t bytes,
@@ -626,8 +652,8 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
   };
   int32_t *blocks = reinterpret_cast<int32_t *>(take((size_t)groups * slots * 4));
   int32_t *n_local = reinterpret_cast<int32_t *>(take((size_t)H.n * 4));
-  int32_t *col2 = reinterpret_cast<int32_t *>(take((size_t)std::max<int64_t>(H.nnz, 1) * 4));
-  void *val2 = take((size_t)std::max<int64_t>(H.nnz, 1) * sv);
+  int32_t *col2 = reinterpret_cast<int32_t *>(take((size_t)(H.nnz + 4) * 4));
+  void *val2 = take((size_t)(H.nnz + 4) * sv);
   hipLaunchKernelGGL(k_plan_blocks, dim3((unsigned)groups), dim3(256), 0, s, H.n,
                      (int64_t)H.block_rows, slots, H.row_ptr, H.col, blocks);
   const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(H.n, 4));
