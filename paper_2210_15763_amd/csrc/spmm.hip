@@ -56,6 +56,27 @@ __device__ __forceinline__ int64_t xcd_block(int64_t w) {
   return (w % kXcds) * per + w / kXcds;
 }
 
+// four consecutive values from a 16-byte aligned (float) / 32-byte aligned
+// (double) address
+template <typename T>
+struct Quad {
+  T v[4];
+};
+template <typename T>
+__device__ __forceinline__ Quad<T> load_quad(const T *__restrict__ p) {
+  Quad<T> q;
+  if constexpr (sizeof(T) == 4) {
+    const uint4 u = *reinterpret_cast<const uint4 *>(p);
+    __builtin_memcpy(q.v, &u, 16);
+  } else {
+    const uint4 *w = reinterpret_cast<const uint4 *>(p);
+    const uint4 u0 = w[0], u1 = w[1];
+    __builtin_memcpy(q.v, &u0, 16);
+    __builtin_memcpy(q.v + 2, &u1, 16);
+  }
+  return q;
+}
+
 template <typename VT, typename XT, typename AT, typename YT, int B, int LPR>
 __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int64_t *__restrict__ rp,
                                               const int32_t *__restrict__ col,
@@ -279,26 +300,7 @@ void spmm_dispatch(const bbl_csr &H, const XT *X, YT *Y, int nvec, hipStream_t s
 
 constexpr int kPlanHash = 1024;
 
-// four consecutive values from a 16-byte aligned (float) / 32-byte aligned
-// (double) address
-template <typename T>
-struct Quad {
-  T v[4];
-};
-template <typename T>
-__device__ __forceinline__ Quad<T> load_quad(const T *__restrict__ p) {
-  Quad<T> q;
-  if constexpr (sizeof(T) == 4) {
-    const uint4 u = *reinterpret_cast<const uint4 *>(p);
-    __builtin_memcpy(q.v, &u, 16);
-  } else {
-    const uint4 *w = reinterpret_cast<const uint4 *>(p);
-    const uint4 u0 = w[0], u1 = w[1];
-    __builtin_memcpy(q.v, &u0, 16);
-    __builtin_memcpy(q.v + 2, &u1, 16);
-  }
-  return q;
-}
+
 
 // blocks[g][0] = g; blocks[g][1..slots) = the other column blocks with the
 // most entries in group g (ties to the smaller block id), -1 when fewer exist

@@ -145,6 +145,28 @@ def test_spmm_ragged_rows_and_empty_rows(torch, bbl):
     assert np.all(W[lens == 0] == 0.0)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_spmm_unaligned_arrays(torch, bbl, prec):
+    """Column and value arrays that do not start on a 16-byte boundary (views
+    one element into a larger buffer): the plain kernel loads them per entry."""
+    note("spmm unaligned col/val %s" % prec)
+    H = synthgen.generate(6000, 400, 20, 0.7, 13)
+    dt = np.float32 if prec == "f32" else np.float64
+    colb = torch.from_numpy(np.concatenate([[0], H.col]).astype(np.int32)).cuda()
+    valb = torch.from_numpy(np.concatenate([[0.0], H.val]).astype(dt)).cuda()
+    Hd = bbl.DeviceCSR(H.n, torch.from_numpy(np.asarray(H.row_ptr, np.int64)).cuda(), colb[1:],
+                       valb[1:])
+    assert Hd.col.data_ptr() % 16 != 0
+    V = synthgen.gaussian_block(H.n, 8, 2)
+    Vd = dev(torch, V.astype(dt))
+    W = bbl.spmm(Hd, Vd).double().cpu().numpy()
+    Href = H.as_float32_values() if prec == "f32" else H
+    Vr = V.astype(dt).astype(np.float64)
+    u = U32 if prec == "f32" else U64
+    bound = gamma(np.diff(H.row_ptr)[:, None] + 2, u) * oracle.spmm_abs(Href, Vr) + 1e-300
+    assert np.all(np.abs(W - oracle.spmm(Href, Vr)) <= bound)
+
+
 def test_spmm_bitwise_reproducible(torch, bbl):
     note("spmm reproducibility")
     H = synthgen.generate(40000, 1000, 50, 0.7, 3)
