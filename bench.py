@@ -195,6 +195,7 @@ def compare_pivots(torch, bbl, weights, m_max):
         r = bbl.block_lanczos(Hd, P, k, w.tol, m_max=m_max, seed=w.seed, spmm_plan=plan)
         torch.cuda.synchronize()
         tt = time.perf_counter() - t
+        info = dict(info, overlap=pivot_overlap(bbl, r.eigvecs, P))
         arms[name] = dict(info, iters=r.stats["iters"], spmm_calls=r.stats["spmm_calls"],
                           converged=bool(r.converged), pivot_s=tp, tts_s=tt,
                           eigvals=[float(x) for x in r.eigvals],
@@ -233,6 +234,45 @@ def compare_pivots(torch, bbl, weights, m_max):
                       "~300 nnz/row, FP32, b=k=10, tol=1e-6, truncation 50000 rows, seed 200",
                       "n": H.n, "nnz": H.nnz, "m_max": m_max, "weights": os.path.basename(weights),
                       "arms": arms}), flush=True)
+
+
+def pivot_overlap(bbl, X, P):
+    """Singular values of X^T Q with Q an orthonormal basis of span(P): the
+    cosines of the principal angles between the converged eigenvectors and
+    the pivot block (products on the GPU, the k x b factors on the host)."""
+    M = bbl.gram(X, 1, X.shape[1], P).cpu().numpy()          # X^T P
+    G = bbl.gram(P, 1, P.shape[1], P).cpu().numpy()          # P^T P
+    lam, U = np.linalg.eigh(0.5 * (G + G.T))
+    keep = lam > 1e-12 * lam.max()
+    Wh = U[:, keep] / np.sqrt(lam[keep])
+    return [float(x) for x in np.linalg.svd(M @ Wh, compute_uv=False)]
+
+
+def spmm_block_sweep(torch, bbl, H, R):
+    """SpMM time per operation (one matrix element times one vector) for
+    block widths 1..16, plain CSR kernel and planned kernel (the GPU analogue
+    of the paper's block-size tables)."""
+    Hp = bbl.DeviceCSR.from_host(H, "float32")
+    Hb = bbl.DeviceCSR.from_host(H, "float32", block_rows=R)
+    out = {}
+    for b in (1, 2, 4, 8, 16):
+        V = torch.randn((H.n, b), dtype=torch.float32, device="cuda")
+        W = torch.empty_like(V)
+        t_plain = time_kernel(torch, lambda: bbl.spmm(Hp, V, W), 10)
+        rec = {"plain_ms": t_plain * 1e3, "plain_ns_per_op": t_plain / (H.nnz * b) * 1e9,
+               "plain_alg_GBps": spmm_bytes(H.n, H.nnz, b, 4, 4) / t_plain / 1e9}
+        try:
+            plan = bbl.spmm_plan(Hb, b)
+            t_pl = time_kernel(torch, lambda: bbl.spmm_planned(plan, V, W), 10)
+            rec.update({"planned_ms": t_pl * 1e3, "planned_ns_per_op": t_pl / (H.nnz * b) * 1e9,
+                        "planned_alg_GBps": spmm_bytes(H.n, H.nnz, b, 4, 4) / t_pl / 1e9,
+                        "plan_slots": plan.slots})
+            del plan
+        except bbl.BblError:
+            pass
+        out[str(b)] = rec
+        log("b=%d %s" % (b, json.dumps(rec)))
+    return out
 
 
 def time_kernel(torch, fn, iters):
@@ -300,6 +340,11 @@ def main():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2210_15763_amd", "weights",
                                                       "pivot_mlp_sectored.npy"))
     ap.add_argument("--compare-m-max", type=int, default=300)
+    ap.add_argument("--spmm-sweep", action="store_true",
+                    help="SpMM time per operation for block widths 1..16 (plain and planned)")
+    ap.add_argument("--single-vector-arm", action="store_true",
+                    help="also solve with block size 1 (the single-vector method) from a "
+                         "random start and report vector-equivalent iterations")
     args = ap.parse_args()
     if args.traffic:
         write_traffic(*args.traffic)
@@ -403,11 +448,25 @@ def main():
                             "fp64_TFLOPs": gram_flops / t_gram / 1e12,
                             "frac_fp64_peak": gram_flops / t_gram / FP64_PEAK},
     }
+    if args.spmm_sweep:
+        extra["spmm_block_sweep"] = spmm_block_sweep(torch, bbl, H, w.R)
+    if args.single_vector_arm:
+        p1 = bbl.random_pivot(H.n, 1, synthgen.pivot_key(w.seed))
+        plan1 = bbl.spmm_plan(Hd, 1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r1 = bbl.block_lanczos(Hd, p1, k, w.tol, m_max=3000, seed=w.seed, spmm_plan=plan1)
+        torch.cuda.synchronize()
+        extra["single_vector"] = {"iters": r1.stats["iters"], "vector_equiv_iters": r1.stats["iters"],
+                                  "tts_s": time.perf_counter() - t, "converged": bool(r1.converged),
+                                  "max_eig_rel_diff_vs_bootstrap":
+                                      float(np.max(np.abs(r1.eigvals - r.eigvals) / np.abs(r.eigvals)))}
+        log("single-vector: %s" % json.dumps(extra["single_vector"]))
     if args.random_arm:
         Pr = bbl.random_pivot(H.n, b, synthgen.pivot_key(w.seed))
         torch.cuda.synchronize()
         t = time.perf_counter()
-        rr = bbl.block_lanczos(Hd, Pr, k, w.tol, m_max=w.m_max, seed=w.seed)
+        rr = bbl.block_lanczos(Hd, Pr, k, w.tol, m_max=w.m_max, seed=w.seed, spmm_plan=step.plan)
         torch.cuda.synchronize()
         extra["random"] = {"iters": rr.stats["iters"], "spmm_calls": rr.stats["spmm_calls"],
                            "tts_s": time.perf_counter() - t, "converged": bool(rr.converged),
