@@ -61,8 +61,8 @@ inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 void launch_spmm(const bbl_csr &H, const void *X, int xdtype, void *Y, int ydtype, int nvec,
                  hipStream_t s);
 // Planned SpMM (rows reordered per aligned group, partner blocks staged in LDS).
-constexpr int kPlanMaxSlots = 4;                 // column blocks staged per group
-constexpr size_t kPlanLds = 128 * 1024;          // LDS bytes they may take
+constexpr int kPlanMaxSlots = 5;                 // column blocks staged per group
+constexpr size_t kPlanLds = 160 * 1024;          // LDS bytes they may take (all of it)
 int spmm_plan_slots(const bbl_csr &H, int nvec, int vec_dtype);
 size_t spmm_plan_bytes(const bbl_csr &H, int nvec, int vec_dtype);
 void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_t bytes,

@@ -540,7 +540,7 @@ __global__ __launch_bounds__(1024) void k_spmm_planned(int64_t n, int64_t G, int
 }
 
 constexpr int kPlanThreads = 1024;
-constexpr int kPlanParts = 4;   // workgroups per row group
+constexpr int kPlanParts = 2;   // workgroups per row group
 
 template <typename VT, typename XT, int BV>
 void planned_launch(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s) {
