@@ -112,8 +112,11 @@ typedef struct {
 
 /* Counters of one solve and its wall time (host clock around the call). */
 typedef struct {
-  int32_t iters;        /* block iterations (products H V_j) */
-  int32_t spmm_calls;   /* all products with H, explicit residual checks included */
+  int32_t iters;        /* blocks of the Krylov space the returned pairs come
+                           from (the recurrence may have built one more block
+                           while the last check ran beside it) */
+  int32_t spmm_calls;   /* all products with H, explicit residual checks and
+                           the block built beside the last check included */
   int32_t deflations;   /* columns replaced because of (near) rank loss */
   int32_t converged;    /* 1 if every wanted pair met the tolerance */
   int32_t checks;       /* band-matrix eigensolves */

@@ -12,8 +12,12 @@
 //   every few blocks: lowest Ritz pairs of the band matrix, residual
 //   estimates ||B_J s_last||; when all pass, Ritz vectors and the explicit
 //   FP64 residual decide convergence.
-// Every step runs in HIP kernels on the caller's stream; the host only
-// sequences launches and reads 2k+1 doubles per convergence check.
+// Every step runs in HIP kernels.  The recurrence runs on the caller's stream;
+// the band eigensolve of a check runs on a second stream of the solver,
+// concurrently with the next block of the recurrence, and its result is read
+// by the host after that block has been queued (one block later, always at
+// the same point of the sequence, so the run is deterministic).  The host
+// only sequences launches and reads 2k+3 numbers per check.
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -40,7 +44,7 @@ size_t dsize(int dt) { return dt == BBL_F32 ? 4 : 8; }
 
 
 struct Layout {
-  size_t basis, W, Wp, X, partial, C, band, Bstore, mats, ints, dres, S, eig, norm, total;
+  size_t basis, W, Wp, X, partial, C, band, Bstore, mats, ints, dres, chk, S, eig, norm, total;
   size_t partial_doubles;
   BandEigLayout el;
 };
@@ -69,6 +73,7 @@ Layout make_layout(int64_t n, int b, int k, int m_max, int bdt) {
   L.mats = take((size_t)16 * kMaxBlock * kMaxBlock * 8);
   L.ints = take(256 * sizeof(int));
   L.dres = take(256 * 8);
+  L.chk = take(256 * 8);
   L.S = take((size_t)m_max * b * k * 8);
   L.el = band_eig_layout(m_max * b, b, k);
   L.eig = take(L.el.bytes);
@@ -111,6 +116,34 @@ struct SpmmTimer {
   }
 };
 
+// The second stream of the overlapped convergence checks, its events and a
+// pinned host buffer for the check results.  Non-blocking, so that it never
+// synchronises implicitly with a legacy default stream of the caller.
+struct CheckStream {
+  hipStream_t cs = nullptr;
+  hipEvent_t ready = nullptr, done = nullptr;
+  double *host = nullptr;
+  hipError_t err = hipSuccess;
+  static constexpr int kHostDoubles = 2 * kMaxBlock + 8;
+  CheckStream() {
+    err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    if (err == hipSuccess)
+      err = hipHostMalloc(reinterpret_cast<void **>(&host), kHostDoubles * sizeof(double),
+                          hipHostMallocDefault);
+  }
+  ~CheckStream() {
+    if (cs) (void)hipStreamSynchronize(cs);
+    if (host) (void)hipHostFree(host);
+    if (ready) (void)hipEventDestroy(ready);
+    if (done) (void)hipEventDestroy(done);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+  CheckStream(const CheckStream &) = delete;
+  CheckStream &operator=(const CheckStream &) = delete;
+};
+
 struct Solver {
   const bbl_csr &H;
   int64_t n;
@@ -125,7 +158,7 @@ struct Solver {
   // regions
   char *basis;
   void *W;
-  double *Wp, *X, *partial, *C, *band, *Bstore, *S, *dres;
+  double *Wp, *X, *partial, *C, *band, *Bstore, *S, *dres, *chk;
   double *Araw, *C3, *O, *C0, *QB, *RB, *O2, *Rinv, *G0, *G1;
   int *ints;
   int *mask, *flag, *breakdown, *ndefl, *flag2, *n_second, *chol_fail;
@@ -150,6 +183,7 @@ struct Solver {
     Bstore = reinterpret_cast<double *>(ws + L.Bstore);
     S = reinterpret_cast<double *>(ws + L.S);
     dres = reinterpret_cast<double *>(ws + L.dres);
+    chk = reinterpret_cast<double *>(ws + L.chk);
     double *m = reinterpret_cast<double *>(ws + L.mats);
     const int sq = kMaxBlock * kMaxBlock;
     Araw = m;
@@ -236,7 +270,7 @@ struct Solver {
 
   struct Result {
     bool converged = false;
-    int iters = 0, spmm_calls = 0, checks = 0, spmm_timed = 0;
+    int iters = 0, built = 0, spmm_calls = 0, checks = 0, spmm_timed = 0;
     double hnorm = 0.0, spmm_ms = 0.0;
     std::vector<double> theta, resid;
   };
@@ -267,13 +301,14 @@ struct Solver {
   int prev_nblk_ = 0;
   double prev_log_rho_ = 0.0;
 
-  // Ritz vectors of the last eigensolve into Xout (n x k), normalised;
-  // returns explicit residual norms.
+  // Ritz vectors of the last (completed) check into Xout (n x k), normalised;
+  // returns their explicit residual norms ||H x - theta x|| with the check's
+  // Ritz values theta = chk[0..kk).
   std::vector<double> ritz_and_residual(int nblk, int kk, double *Xout) {
     launch_update(n, basis, xd, b, nblk, slot_stride(), S, kk, 1.0, nullptr, BBL_F64, 0.0, Xout,
                   BBL_F64, s);
     launch_normalize_columns(n, kk, Xout, reinterpret_cast<double *>(normws), kMaxPartialRows, s);
-    const int P = launch_residual_spmm(H, Xout, kk, dres, partial, kMaxPartialRows, s);
+    const int P = launch_residual_spmm(H, Xout, kk, chk, partial, kMaxPartialRows, s);
     double *r2 = dres + 128;
     launch_reduce(partial, P, 1, kk, r2, s);
     std::vector<double> h(kk);
@@ -283,8 +318,66 @@ struct Solver {
     return h;
   }
 
+  // A check of the first nblk blocks: the band eigensolve on the check
+  // stream once the recurrence has produced B_{nblk-1}.  chk[0..2kk] receives
+  // the Ritz values, residual estimates and ||T||_est, chk[64] (as int) the
+  // QR breakdown flag as of this point; both are copied to pinned memory.
+  void launch_check(CheckStream &cq, int nblk, int kk) {
+    int *flag_copy = reinterpret_cast<int *>(chk + 64);
+    BBL_HIP(hipMemcpyAsync(flag_copy, breakdown, sizeof(int), hipMemcpyDeviceToDevice, s));
+    BBL_HIP(hipEventRecord(cq.ready, s));
+    BBL_HIP(hipStreamWaitEvent(cq.cs, cq.ready, 0));
+    const double *BJ = Bstore + (size_t)(nblk - 1) * b * b;
+    band_eigensolve(band, nblk * b, b, kk, eigws, L.el, BJ, b, S, chk, cq.cs);
+    BBL_HIP(hipMemcpyAsync(cq.host, chk, (2 * kk + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                           cq.cs));
+    BBL_HIP(hipMemcpyAsync(cq.host + 2 * kMaxBlock + 4, flag_copy, sizeof(int),
+                           hipMemcpyDeviceToHost, cq.cs));
+    BBL_HIP(hipEventRecord(cq.done, cq.cs));
+  }
+
+  // Reads the results of the check of nblk blocks (waiting for it if needed),
+  // schedules the next one and, when the estimates pass (or `final`), forms
+  // the Ritz vectors and their explicit residuals.  True when converged.
+  bool consume_check(CheckStream &cq, int nblk, int kk, bool final, double *hnorm_dev,
+                     double *Xout, Result &R) {
+    BBL_HIP(hipEventSynchronize(cq.done));
+    const double *hres = cq.host;
+    int flag = 0;
+    std::memcpy(&flag, cq.host + 2 * kMaxBlock + 4, sizeof(int));
+    if (flag) throw Error{BBL_E_BREAKDOWN, "block QR lost rank beyond deflation repair"};
+    // ||H||_est for the block QRs queued from now on
+    BBL_HIP(hipMemcpyAsync(hnorm_dev, chk + 2 * kk, sizeof(double), hipMemcpyDeviceToDevice, s));
+    R.hnorm = hres[2 * kk];
+    bool est_ok = true;
+    double rho_max = 0.0;
+    for (int i = 0; i < kk; ++i) {
+      est_ok &= (hres[kk + i] <= tol * R.hnorm);
+      rho_max = std::max(rho_max, hres[kk + i]);
+    }
+    next_check = next_check_after(nblk, rho_max, tol * R.hnorm);
+    const bool exhausted = (int64_t)nblk * b >= n;
+    if (!(exhausted || (kk == k && est_ok) || final)) return false;
+    BBL_HIP(hipStreamWaitEvent(s, cq.done, 0));  // S of this check
+    std::vector<double> r = ritz_and_residual(nblk, kk, Xout);
+    ++R.spmm_calls;
+    bool ok = kk == k || exhausted;
+    for (int i = 0; i < kk; ++i) ok &= (r[i] <= tol * R.hnorm);
+    R.theta.assign(hres, hres + kk);
+    R.resid = r;
+    R.iters = nblk;  // the returned pairs come from the first nblk blocks
+    if (ok || exhausted) {
+      R.converged = true;
+      return true;
+    }
+    return false;
+  }
+  int next_check = 1;
+
   Result run(const double *pivot, double *eigvecs_out) {
     Result R;
+    CheckStream cq;
+    if (cq.err != hipSuccess) throw Error{BBL_E_HIP, std::string("check stream: ") + hipGetErrorString(cq.err)};
     // zero the band matrix, the B store, counters and results
     launch_fill(band, (int64_t)(o.m_max * b + b) * (b + 1), 0.0, s);
     launch_fill(Bstore, (int64_t)(o.m_max + 1) * b * b, 0.0, s);
@@ -295,9 +388,8 @@ struct Solver {
     BBL_HIP(hipMemcpyAsync(Wp, pivot, (size_t)n * b * 8, hipMemcpyDeviceToDevice, s));
     block_qr(0, 0, Bstore + (size_t)o.m_max * b * b, hnorm_dev);
     double *Xout = eigvecs_out ? eigvecs_out : X;
-    int last_checked_nblk = 0;
-    int next_check = 1;
-    std::vector<double> hres(2 * kMaxBlock + 2);
+    next_check = 1;
+    int pending = 0, pending_kk = 0;  // blocks and pairs of the check in flight
     SpmmTimer timer(o.flags & BBL_FLAG_TIME_SPMM, o.m_max);
     for (int J = 0; J < o.m_max; ++J) {
       timer.begin(J, s);
@@ -315,47 +407,29 @@ struct Solver {
       double *BJ = Bstore + (size_t)J * b * b;
       block_qr(J + 1, J + 1, BJ, hnorm_dev);
       launch_set_B(BJ, b, J, band, b, o.m_max * b, s);
-      R.iters = J + 1;
+      R.iters = R.built = J + 1;
+      // the check launched after the previous block ran beside this one
+      if (pending) {
+        const int nb = pending;
+        pending = 0;
+        if (consume_check(cq, nb, pending_kk, false, hnorm_dev, Xout, R)) break;
+      }
       const int N = (J + 1) * b;
       const bool exhausted = (int64_t)N >= n;
       const bool last = (J == o.m_max - 1);
       if (N < k && !exhausted) continue;
       if (!(exhausted || last || J + 1 >= next_check)) continue;
       const int kk = std::min(k, N);
-      band_eigensolve(band, N, b, kk, eigws, L.el, BJ, b, S, dres, s);
+      launch_check(cq, J + 1, kk);
       ++R.checks;
-      // keep ||H||_est at a fixed slot for the next QR (res[2kk] -> dres[2k])
-      BBL_HIP(hipMemcpyAsync(hres.data(), dres, (2 * kk + 1) * sizeof(double),
-                             hipMemcpyDeviceToHost, s));
-      int hflags[2];
-      BBL_HIP(hipMemcpyAsync(hflags, breakdown, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-      BBL_HIP(hipStreamSynchronize(s));
-      if (hflags[0]) throw Error{BBL_E_BREAKDOWN, "block QR lost rank beyond deflation repair"};
-      if (kk < k) BBL_HIP(hipMemcpyAsync(hnorm_dev, dres + 2 * kk, 8, hipMemcpyDeviceToDevice, s));
-      R.hnorm = hres[2 * kk];
-      last_checked_nblk = J + 1;
-      bool est_ok = true;
-      double rho_max = 0.0;
-      for (int i = 0; i < kk; ++i) {
-        est_ok &= (hres[kk + i] <= tol * R.hnorm);
-        rho_max = std::max(rho_max, hres[kk + i]);
+      if (exhausted || last) {  // nothing left to overlap with
+        consume_check(cq, J + 1, kk, true, hnorm_dev, Xout, R);
+        break;
       }
-      next_check = next_check_after(J + 1, rho_max, tol * R.hnorm);
-      if (exhausted || (kk == k && est_ok) || last) {
-        std::vector<double> r = ritz_and_residual(J + 1, kk, Xout);
-        ++R.spmm_calls;
-        bool ok = kk == k || exhausted;
-        for (int i = 0; i < kk; ++i) ok &= (r[i] <= tol * R.hnorm);
-        R.theta.assign(hres.begin(), hres.begin() + kk);
-        R.resid = r;
-        if (ok || exhausted) {
-          R.converged = true;
-          break;
-        }
-      }
+      pending = J + 1;
+      pending_kk = kk;
     }
-    (void)last_checked_nblk;
-    timer.collect(R.iters, s, &R.spmm_ms, &R.spmm_timed);
+    timer.collect(R.built, s, &R.spmm_ms, &R.spmm_timed);
     return R;
   }
 };

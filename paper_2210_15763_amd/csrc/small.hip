@@ -149,8 +149,8 @@ __global__ __launch_bounds__(64) void k_chol_try(const double *__restrict__ O, i
 }
 
 // Second pass: O2 = Y^T Y = R2^T R2.  Writes R2^{-1} (upper, row-major) and
-// Bout = R2 RB (upper triangular).  breakdown = 1 if O2 is not positive
-// definite to working precision.
+// Bout = R2 RB (upper triangular).  breakdown is set to 1 (and never cleared)
+// if O2 is not positive definite to working precision.
 __global__ __launch_bounds__(64) void k_chol_finish(const double *__restrict__ O2, int b,
                                                     const double *__restrict__ RB, double *Rinv,
                                                     double *Bout, int *breakdown) {
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(64) void k_chol_finish(const double *__restrict__ O
         Ri[r * b + c] = -x / R[r * b + r];
       }
     }
-    *breakdown = bad;
+    if (bad) *breakdown = 1;  // sticky until the solve ends
   }
   __syncthreads();
   for (int i = t; i < b * b; i += blockDim.x) {
