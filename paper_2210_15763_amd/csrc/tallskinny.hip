@@ -18,6 +18,7 @@
 // (the accumulator's four 64-bit elements are rows strided by 4; checked
 // against numpy by the gram/update parity tests)
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 
 #include "common.h"
@@ -111,15 +112,31 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, const XT *__restrict__ 
   }
 }
 
+// Sum of partial[p0..p1)[idx] in a fixed order: eight interleaved running
+// sums (p = p0 + u mod 8) so that eight loads are in flight at a time, then
+// a fixed pairwise combination.
+__device__ __forceinline__ double sum_strided(const double *__restrict__ partial, int p0, int p1,
+                                              int MN, int idx) {
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const double *q = partial + (int64_t)p0 * MN + idx;
+  int p = p0;
+  for (; p + 8 <= p1; p += 8, q += (int64_t)8 * MN) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += q[(int64_t)u * MN];
+  }
+#pragma unroll
+  for (int u = 0; u < 7; ++u)
+    if (p + u < p1) a[u] += q[(int64_t)u * MN];
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
 __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partial, int P,
                                                 int MN, double *__restrict__ out,
                                                 const int *__restrict__ when) {
   if (when && *when == 0) return;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= MN) return;
-  double s = 0.0;
-  for (int p = 0; p < P; ++p) s += partial[(int64_t)p * MN + idx];
-  out[idx] = s;
+  out[idx] = sum_strided(partial, 0, P, MN, idx);
 }
 
 // Yout[r][c] = beta*Yin[r][c] + alpha*sum_m X[r][m] C[m][c].  One wave per
@@ -235,15 +252,25 @@ __device__ __forceinline__ Vec<T, N> vload(const T *p) {
 // four MFMA pairs q = 0..3; in pair q, block g computes the 4x4 tiles of X
 // columns c0 + 16g + 4i + q against Y columns 0..3 and 4..7.  Each wave covers
 // 64*CG columns and keeps U row groups of four in flight.
+//
+// Workgroup order: the gy column groups of one row chunk share that chunk of
+// Y, so they are given workgroup ids congruent modulo 8 (the same XCD, whose
+// L2 then serves Y to all of them) and close in dispatch order.  Linear id i:
+// super-block i / (8 gy) holds row chunks 8 sb .. 8 sb + 7, inside it
+// column group (i % (8 gy)) / 8 and row chunk 8 sb + i % 8.
 template <int CG, int U>
 __global__ __launch_bounds__(64) void k_gram_mfma8(int64_t n, const float *__restrict__ X, int M,
                                                    int64_t xstride, const double *__restrict__ Y,
-                                                   int64_t chunk, double *__restrict__ partial,
+                                                   int64_t chunk, int gx, int gy,
+                                                   double *__restrict__ partial,
                                                    const int *__restrict__ when) {
   if (when && *when == 0) return;
+  const int sb = blockIdx.x / (8 * gy), rem = blockIdx.x % (8 * gy);
+  const int cy = rem / 8, cx = sb * 8 + rem % 8;
+  if (cx >= gx) return;
   const int l = threadIdx.x;
   const int k = l >> 4, g = (l & 15) >> 2, e = l & 3;
-  const int c00 = blockIdx.y * (64 * CG);
+  const int c00 = cy * (64 * CG);
   int64_t xo[CG];
   bool ok[CG];
 #pragma unroll
@@ -258,7 +285,7 @@ __global__ __launch_bounds__(64) void k_gram_mfma8(int64_t n, const float *__res
   for (int c = 0; c < CG; ++c)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[c][q][0] = acc[c][q][1] = 0.0;
-  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r0 = (int64_t)cx * chunk;
   const int64_t r1 = min(n, r0 + chunk);
   for (int64_t rb = r0; rb < r1; rb += 4 * U) {
     double y0[U], y1[U];
@@ -289,7 +316,7 @@ __global__ __launch_bounds__(64) void k_gram_mfma8(int64_t n, const float *__res
   }
   // D lane l = 16i + 4g + j holds tile (g, q) element (i, j): X column
   // c0 + 16g + 4i + q with i = k (l >> 4), Y column j or 4 + j with j = e
-  double *out = partial + (int64_t)blockIdx.x * M * 8;
+  double *out = partial + (int64_t)cx * M * 8;
 #pragma unroll
   for (int c = 0; c < CG; ++c)
 #pragma unroll
@@ -473,9 +500,7 @@ __global__ __launch_bounds__(256) void k_reduce1(const double *__restrict__ part
   const int sidx = blockIdx.y;
   if (idx >= MN) return;
   const int p0 = (int)((int64_t)P * sidx / S), p1 = (int)((int64_t)P * (sidx + 1) / S);
-  double s = 0.0;
-  for (int p = p0; p < p1; ++p) s += partial[(int64_t)p * MN + idx];
-  tmp[(int64_t)sidx * MN + idx] = s;
+  tmp[(int64_t)sidx * MN + idx] = sum_strided(partial, p0, p1, MN, idx);
 }
 
 __global__ void k_fill(double *p, int64_t count, double v) {
@@ -544,17 +569,21 @@ int gram_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const 
     return (int)(grid * 4);
   }
   if (bx == 8 && ny == 8 && f32 && std::is_same<YT, double>::value && nblk >= 2) {
-    // 64 basis columns per one-wave workgroup, ~1000 row chunks (measured on
-    // MI355X at n = 2e6, 50 blocks: 4.9 TB/s, against 2.3 TB/s for the VALU
-    // kernel with ~2k workgroups)
+    // 64 basis columns per one-wave workgroup; about 6k workgroups in all, so
+    // that the whole grid is resident at once (measured on MI355X at n = 2e6:
+    // 45, 90 and 181 blocks run fastest with 1024, 512 and 256 row chunks,
+    // 5.1-5.3 TB/s)
     constexpr int CG = 1, U = 2;
     const int gy = (M + 64 * CG - 1) / (64 * CG);
-    int64_t gx = std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(n, 256)));
+    int64_t gx = std::min<int64_t>(1024, ceil_div(6144, gy));
+    gx = std::max<int64_t>(1, std::min<int64_t>(gx, ceil_div(n, 256)));
     gx = std::min<int64_t>(gx, std::max(1, max_partials));
     int64_t chunk = ceil_div(ceil_div(n, gx), 4 * U) * (4 * U);
     gx = ceil_div(n, chunk);
-    hipLaunchKernelGGL((k_gram_mfma8<CG, U>), dim3((unsigned)gx, gy), dim3(64), 0, s, n,
-                       (const float *)X, M, xstride, (const double *)Y, chunk, partial, when);
+    const int64_t grid = ceil_div(gx, 8) * 8 * gy;
+    hipLaunchKernelGGL((k_gram_mfma8<CG, U>), dim3((unsigned)grid), dim3(64), 0, s, n,
+                       (const float *)X, M, xstride, (const double *)Y, chunk, (int)gx, gy,
+                       partial, when);
     check_launch("k_gram_mfma8");
     return (int)gx;
   }
@@ -585,12 +614,12 @@ int gram_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const 
   return (int)gx;
 }
 
-template <typename XT, typename YIT, typename YOT, int B>
+template <typename XT, typename YIT, typename YOT, int B, int NY = B>
 void update_valu(int64_t n, const XT *X, int nblk, int64_t xstride, const double *C, double alpha,
                  const YIT *Yin, double beta, YOT *Yout, const int *when, hipStream_t s) {
   constexpr int RPL = 2;
   const int64_t grid = ceil_div(n, 256 * RPL);
-  hipLaunchKernelGGL((k_update_v<XT, YIT, YOT, B, B, RPL>), dim3((unsigned)grid), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_update_v<XT, YIT, YOT, B, NY, RPL>), dim3((unsigned)grid), dim3(256), 0, s,
                      n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when);
   check_launch("k_update_v");
 }
@@ -600,6 +629,10 @@ void update_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, con
                   int ny, double alpha, const YIT *Yin, double beta, YOT *Yout, const int *when,
                   hipStream_t s) {
   const int M = nblk * bx;
+  if (bx == 8 && ny == 10) {  // Ritz vectors of b = 8 blocks, k = 10
+    update_valu<XT, YIT, YOT, 8, 10>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, s);
+    return;
+  }
   if (ny == bx) {
     switch (bx) {
       case 4: update_valu<XT, YIT, YOT, 4>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, s); return;
@@ -651,8 +684,10 @@ void launch_reduce_when(const double *partial, int P, int M, int ny, double *out
                         const int *when, hipStream_t s) {
   const int MN = M * ny;
   // stage 1 writes S partial sums behind the P partials (the caller's partial
-  // buffer holds (P + S) * MN doubles), stage 2 sums them in order
-  const int S = std::max(1, std::min(P / 8, std::max(1, 8192 / ((MN + 255) / 256))));
+  // buffer holds (P + S) * MN doubles), stage 2 sums them in order.  S ~ sqrt(P)
+  // balances the serial length of the two stages.
+  const int S_room = std::max(1, 8192 / ((MN + 255) / 256));
+  const int S = std::max(1, std::min({P / 8, S_room, (int)std::ceil(std::sqrt((double)P))}));
   if (S > 1) {
     double *tmp = const_cast<double *>(partial) + (size_t)P * MN;
     hipLaunchKernelGGL(k_reduce1, dim3((MN + 255) / 256, S), dim3(256), 0, s, partial, P, MN, S,

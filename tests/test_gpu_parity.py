@@ -181,7 +181,8 @@ def test_spmm_bitwise_reproducible(torch, bbl):
 @pytest.mark.parametrize("bx,nblk,ny,xf32", [(8, 3, 8, True), (16, 2, 16, True), (4, 5, 4, False),
                                              (10, 3, 10, True), (8, 1, 20, False),
                                              (8, 7, 8, False), (8, 9, 8, True), (8, 37, 8, True),
-                                             (8, 1, 8, True), (8, 1, 8, False), (4, 1, 4, True)])
+                                             (8, 1, 8, True), (8, 1, 8, False), (4, 1, 4, True),
+                                             (8, 23, 10, True), (8, 4, 10, False)])
 def test_gram_and_update_match_numpy(torch, bbl, bx, nblk, ny, xf32):
     note("gram/update bx=%d nblk=%d ny=%d f32=%s" % (bx, nblk, ny, xf32))
     rng = np.random.default_rng(bx * 100 + nblk)
