@@ -66,26 +66,30 @@ typedef struct {
 /* Prepared form of a matrix with a block_rows hint for the SpMM of the block
  * recurrence (built by bbl_spmm_plan_build; all pointers are device memory
  * inside the caller's plan buffer, except row_ptr, which is H's).  For every
- * aligned row group the plan names up to four column blocks of block_rows
+ * aligned row group the plan names up to five column blocks of block_rows
  * columns -- the group's own and the partner blocks holding most of its
  * other entries -- and every row's entries are reordered: entries inside
  * those blocks first, stored as an LDS row index slot*block_rows + offset,
- * then the others with their global column.  The planned SpMM stages the
+ * then the others with their global column.  When every LDS row index fits
+ * in 16 bits the plan also keeps them as uint16 (lcol), which the planned
+ * SpMM streams instead of the 32-bit ones.  The planned SpMM stages the
  * blocks' rows of V in LDS once per group.  The same sums are formed in a
  * different order, so results agree with bbl_spmm to rounding, not bitwise. */
 typedef struct {
   int64_t n, nnz;
   int32_t block_rows;     /* rows (and columns) per group */
-  int32_t slots;          /* column blocks staged per group, 1..4 */
+  int32_t slots;          /* column blocks staged per group, 1..5 */
   int32_t nvec;           /* block width the plan serves */
   int32_t vec_dtype;      /* vector element type it serves */
   int32_t val_dtype;      /* matrix value type */
-  int32_t reserved;
+  int32_t local16;        /* 1 if lcol is present (slots*block_rows <= 65536) */
   const int64_t *row_ptr; /* H.row_ptr (not copied; H must outlive the plan) */
   const int32_t *blocks;  /* [groups][slots] staged block ids, -1 = none */
   const int32_t *n_local; /* [n] entries of the row inside staged blocks */
   const int32_t *col;     /* [nnz] reordered column / LDS row indices */
   const void *val;        /* [nnz] reordered values */
+  const uint16_t *lcol;   /* [nnz] LDS row index of the staged entries (their
+                             positions in col; others unspecified), or NULL */
 } bbl_spmm_plan;
 
 /* Solver options; a NULL pointer selects the defaults shown. */

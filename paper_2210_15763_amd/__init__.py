@@ -54,9 +54,10 @@ class _Opts(ctypes.Structure):
 class _Plan(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("block_rows", ctypes.c_int32),
                 ("slots", ctypes.c_int32), ("nvec", ctypes.c_int32), ("vec_dtype", ctypes.c_int32),
-                ("val_dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("val_dtype", ctypes.c_int32), ("local16", ctypes.c_int32),
                 ("row_ptr", ctypes.c_void_p), ("blocks", ctypes.c_void_p),
-                ("n_local", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+                ("n_local", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("lcol", ctypes.c_void_p)]
 
 
 class _Stats(ctypes.Structure):

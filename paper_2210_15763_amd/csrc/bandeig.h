@@ -6,7 +6,7 @@
 namespace bbl {
 
 struct BandEigLayout {
-  size_t gersh, shifts_a, shifts_b, counts, brk, Lscr, Dscr, X, TX, bytes;
+  size_t gersh, shifts_a, shifts_b, counts, brk, Lscr, Dscr, X, TX, flag, bytes;
 };
 
 // Workspace layout for N x N band matrices of half-bandwidth kd, k pairs.

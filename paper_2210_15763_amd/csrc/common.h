@@ -107,5 +107,13 @@ void launch_reduce_when(const double *partial, int P, int M, int ny, double *out
 void launch_update_when(int64_t n, const void *X, int xdtype, int bx, int nblk, int64_t xstride,
                         const double *C, int ny, double alpha, const void *Yin, int yindtype,
                         double beta, void *Yout, int youtdtype, const int *when, hipStream_t s);
+// The update above, also leaving the Gram partials of Yout (as stored) in
+// gpart[p][a][c], p < the returned count, for launch_reduce_when(.., ny, ny);
+// returns 0 when this shape has no fused Gram or gcap_doubles is too small
+// (then only the update ran).
+int launch_update_gram_when(int64_t n, const void *X, int xdtype, int bx, int nblk,
+                            int64_t xstride, const double *C, int ny, double alpha,
+                            const void *Yin, int yindtype, double beta, void *Yout, int youtdtype,
+                            double *gpart, size_t gcap_doubles, const int *when, hipStream_t s);
 
 }  // namespace bbl

@@ -12,6 +12,12 @@
 //   every few blocks: lowest Ritz pairs of the band matrix, residual
 //   estimates ||B_J s_last||; when all pass, Ritz vectors and the explicit
 //   FP64 residual decide convergence.
+// A block first runs a fast path: one Gram-Schmidt sweep and a Cholesky QR.
+// Whether it needed the second sweep (the DGKS norm test) or the spectral
+// factor with deflation is recorded on the device and read by the host once
+// the next block is queued; such a block (rare: none on the benchmark
+// matrices) is then redone on the full path, which decides both branches on
+// the device, and the blocks queued after it are discarded.
 // Every step runs in HIP kernels.  The recurrence runs on the caller's stream;
 // the band eigensolve of a check runs on a second stream of the solver,
 // concurrently with the next block of the recurrence, and its result is read
@@ -39,6 +45,7 @@ namespace {
 constexpr int kMaxPartialRows = 4096;   // residual / column-statistics partials
 constexpr uint32_t kTagDeflation = 7;
 constexpr int kHn2Slot = 200;          // dres slot: max |A_jj| seen so far (<= ||H||)
+constexpr int kHn2Snap = 202;          // dres slots 202, 203: kHn2Slot at the start of block J (J % 2)
 
 size_t dsize(int dt) { return dt == BBL_F32 ? 4 : 8; }
 
@@ -119,16 +126,23 @@ struct SpmmTimer {
 // The second stream of the overlapped convergence checks, its events and a
 // pinned host buffer for the check results.  Non-blocking, so that it never
 // synchronises implicitly with a legacy default stream of the caller.
+// The pinned buffer also receives, per block of the fast path, its rare-branch
+// flags (slot J % 2: ints flag2, -, chol_fail at kIterFlags + 4 (J % 2)) and
+// `fev[J % 2]` marks their arrival.
+constexpr int kIterFlags = 2 * (2 * kMaxBlock + 8);  // int offset in the pinned buffer
+
 struct CheckStream {
   hipStream_t cs = nullptr;
-  hipEvent_t ready = nullptr, done = nullptr;
+  hipEvent_t ready = nullptr, done = nullptr, fev[2] = {nullptr, nullptr};
   double *host = nullptr;
   hipError_t err = hipSuccess;
-  static constexpr int kHostDoubles = 2 * kMaxBlock + 8;
+  static constexpr int kHostDoubles = 2 * kMaxBlock + 16;
   CheckStream() {
     err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (err == hipSuccess) err = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
     if (err == hipSuccess) err = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    for (int i = 0; i < 2 && err == hipSuccess; ++i)
+      err = hipEventCreateWithFlags(&fev[i], hipEventDisableTiming);
     if (err == hipSuccess)
       err = hipHostMalloc(reinterpret_cast<void **>(&host), kHostDoubles * sizeof(double),
                           hipHostMallocDefault);
@@ -138,8 +152,11 @@ struct CheckStream {
     if (host) (void)hipHostFree(host);
     if (ready) (void)hipEventDestroy(ready);
     if (done) (void)hipEventDestroy(done);
+    for (auto e : fev)
+      if (e) (void)hipEventDestroy(e);
     if (cs) (void)hipStreamDestroy(cs);
   }
+  int *iter_flags(int J) { return reinterpret_cast<int *>(host) + kIterFlags + 4 * (J % 2); }
   CheckStream(const CheckStream &) = delete;
   CheckStream &operator=(const CheckStream &) = delete;
 };
@@ -224,6 +241,29 @@ struct Solver {
     launch_reduce_when(partial, P, M, ny, out, when, s);
   }
 
+  // Yout = beta Yin + alpha X C (b x b C) and G = Yout^T Yout, the latter
+  // from the update's own partials where it can produce them.
+  void update_gram(const void *Xp, int xdt, int nblk, int64_t xstride, const double *Cm,
+                   double alpha, const void *Yin, int yindt, double beta, double *Yout, double *G,
+                   const int *when) {
+    const int P = launch_update_gram_when(n, Xp, xdt, b, nblk, xstride, Cm, b, alpha, Yin, yindt,
+                                          beta, Yout, BBL_F64, partial, L.partial_doubles, when, s);
+    if (P > 0) launch_reduce_when(partial, P, b, b, G, when, s);
+    else gram(Yout, BBL_F64, b, 1, 0, Yout, BBL_F64, b, G, when);
+  }
+
+  // Full reorthogonalisation of W' (whose Gram G0 is known) against the
+  // stored blocks, leaving G1 = W'^T W' of the result: one classical
+  // Gram-Schmidt sweep, and a second one decided on the device when the
+  // first removed a large part of some column (norm ratio below 1/sqrt(2)).
+  void reorth_recurrence(int nb, double *Y) {
+    gram(basis, xd, b, nb, slot_stride(), Y, BBL_F64, b, C);
+    update_gram(basis, xd, nb, slot_stride(), C, -1.0, Y, BBL_F64, 1.0, Y, G1, nullptr);
+    launch_reorth_check(G0, G1, b, 0.5, nullptr, flag2, n_second, s);
+    gram(basis, xd, b, nb, slot_stride(), Y, BBL_F64, b, C, flag2);
+    update_gram(basis, xd, nb, slot_stride(), C, -1.0, Y, BBL_F64, 1.0, Y, G1, flag2);
+  }
+
   // One classical Gram-Schmidt sweep: W' -= V_{0:nb-1} (V^T W').
   void cgs_pass(int nb, double *Y, const int *when) {
     gram(basis, xd, b, nb, slot_stride(), Y, BBL_F64, b, C, when);
@@ -231,37 +271,29 @@ struct Solver {
                        BBL_F64, when, s);
   }
 
-  // Full reorthogonalisation against the stored blocks.  always_twice: two
-  // sweeps unconditionally (fresh random directions); otherwise the second
-  // sweep runs only when the first removed a large part of some column
-  // (norm ratio below 1/sqrt(2)), decided on the device.
-  void reorth(int nb, double *Y, const int *when = nullptr, bool always_twice = false) {
-    if (always_twice) {
-      cgs_pass(nb, Y, when);
-      cgs_pass(nb, Y, when);
-      return;
-    }
-    gram(Y, BBL_F64, b, 1, 0, Y, BBL_F64, b, G0);
+  // Two unconditional sweeps (fresh random directions after a deflation).
+  void reorth_twice(int nb, double *Y, const int *when) {
     cgs_pass(nb, Y, when);
-    gram(Y, BBL_F64, b, 1, 0, Y, BBL_F64, b, G1);
-    launch_reorth_check(G0, G1, b, 0.5, when, flag2, n_second, s);
-    cgs_pass(nb, Y, flag2);
+    cgs_pass(nb, Y, when);
   }
 
   // Block QR of Wp into basis slot `dest`; Bout = B (upper triangular).
-  void block_qr(int nbasis, int dest, double *Bout, const double *hnorm_dev) {
-    gram(Wp, BBL_F64, b, 1, 0, Wp, BBL_F64, b, O);
-    launch_chol_try(O, b, o.tau, hnorm_dev, dres + kHn2Slot, C0, QB, RB, mask, flag, chol_fail, s);
-    launch_svqb_prepare(O, b, o.tau, hnorm_dev, dres + kHn2Slot, C0, QB, RB, mask, flag, ndefl,
+  // Oknown: Wp^T Wp if the caller has it (else it is formed here).
+  void block_qr(int nbasis, int dest, double *Bout, const double *hnorm_dev,
+                const double *Oknown = nullptr) {
+    if (!Oknown) gram(Wp, BBL_F64, b, 1, 0, Wp, BBL_F64, b, O);
+    const double *Ov = Oknown ? Oknown : O;
+    launch_chol_try(Ov, b, o.tau, hnorm_dev, dres + kHn2Slot, C0, QB, RB, mask, flag, chol_fail,
+                    s);
+    launch_svqb_prepare(Ov, b, o.tau, hnorm_dev, dres + kHn2Slot, C0, QB, RB, mask, flag, ndefl,
                         chol_fail, s);
-    launch_update(n, Wp, BBL_F64, b, 1, 0, C0, b, 1.0, nullptr, BBL_F64, 0.0, Wp, BBL_F64, s);
+    // Wp C0 and its Gram O2 (final unless a column was deflated)
+    update_gram(Wp, BBL_F64, 1, 0, C0, 1.0, nullptr, BBL_F64, 0.0, Wp, O2, nullptr);
     // deflated columns: fresh random directions, orthogonal to the basis
     const uint64_t key = (o.seed ^ 0x9E3779B97F4A7C15ull) + 0x5DEECE66Dull * (uint64_t)(qr_calls + 1);
     launch_gauss(n, b, b, 0, key, kTagDeflation, Wp, mask, flag, s);
-    if (nbasis > 0) reorth(nbasis, Wp, flag, true);
-    launch_update_when(n, Wp, BBL_F64, b, 1, 0, QB, b, 1.0, nullptr, BBL_F64, 0.0, Wp, BBL_F64,
-                       flag, s);
-    gram(Wp, BBL_F64, b, 1, 0, Wp, BBL_F64, b, O2);
+    if (nbasis > 0) reorth_twice(nbasis, Wp, flag);
+    update_gram(Wp, BBL_F64, 1, 0, QB, 1.0, nullptr, BBL_F64, 0.0, Wp, O2, flag);
     launch_chol_finish(O2, b, RB, Rinv, Bout, breakdown, s);
     launch_update(n, Wp, BBL_F64, b, 1, 0, Rinv, b, 1.0, nullptr, BBL_F64, 0.0, slot(dest), xd,
                   s);
@@ -374,6 +406,57 @@ struct Solver {
   }
   int next_check = 1;
 
+  // Block QR of the fast path: the Cholesky factorisation only (its failure,
+  // which the full path repairs with the spectral factor and deflation, is
+  // recorded in chol_fail and makes the host redo the block).
+  void block_qr_fast(int dest, double *Bout, const double *hnorm_dev, const double *Ov) {
+    launch_chol_try(Ov, b, o.tau, hnorm_dev, dres + kHn2Slot, C0, QB, RB, mask, flag, chol_fail,
+                    s);
+    update_gram(Wp, BBL_F64, 1, 0, C0, 1.0, nullptr, BBL_F64, 0.0, Wp, O2, nullptr);
+    launch_chol_finish(O2, b, RB, Rinv, Bout, breakdown, s);
+    launch_update(n, Wp, BBL_F64, b, 1, 0, Rinv, b, 1.0, nullptr, BBL_F64, 0.0, slot(dest), xd,
+                  s);
+    ++qr_calls;
+  }
+
+  // Block J of the recurrence.  fast: the common path only -- one
+  // Gram-Schmidt sweep and a Cholesky QR; whether the block needed a second
+  // sweep (flag2) or a deflation repair (chol_fail) is copied to pinned
+  // memory and read by the host one block later, and such a block is then
+  // redone on the full path, which decides those branches on the device.
+  void iterate(int J, bool fast, const double *hnorm_dev, SpmmTimer &timer, CheckStream &cq,
+               Result &R) {
+    if (fast)  // max |A_jj| as of this block's start, restored if it is redone
+      BBL_HIP(hipMemcpyAsync(dres + kHn2Snap + J % 2, dres + kHn2Slot, sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    timer.begin(J, s);
+    if (o.plan) launch_spmm_planned(*o.plan, slot(J), W, s);
+    else launch_spmm(H, slot(J), xd, W, xd, b, s);
+    timer.end(J, s);
+    ++R.spmm_calls;
+    gram(slot(J), xd, b, 1, 0, W, xd, b, Araw);
+    launch_set_A(Araw, b, J, band, b, J > 0 ? Bstore + (size_t)(J - 1) * b * b : nullptr, C3,
+                 dres + kHn2Slot, s);
+    const int nb3 = J > 0 ? 2 : 1;
+    update_gram(slot(J > 0 ? J - 1 : 0), xd, nb3, slot_stride(), C3, -1.0, W, xd, 1.0, Wp, G0,
+                nullptr);
+    double *BJ = Bstore + (size_t)J * b * b;
+    if (fast) {
+      gram(basis, xd, b, J + 1, slot_stride(), Wp, BBL_F64, b, C);
+      update_gram(basis, xd, J + 1, slot_stride(), C, -1.0, Wp, BBL_F64, 1.0, Wp, G1, nullptr);
+      launch_reorth_check(G0, G1, b, 0.5, nullptr, flag2, nullptr, s);
+      block_qr_fast(J + 1, BJ, hnorm_dev, G1);
+    } else {
+      reorth_recurrence(J + 1, Wp);
+      block_qr(J + 1, J + 1, BJ, hnorm_dev, G1);
+    }
+    launch_set_B(BJ, b, J, band, b, o.m_max * b, s);
+    if (fast) {  // flag2, n_second, chol_fail -> pinned slot J % 2
+      BBL_HIP(hipMemcpyAsync(cq.iter_flags(J), flag2, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+      BBL_HIP(hipEventRecord(cq.fev[J % 2], s));
+    }
+  }
+
   Result run(const double *pivot, double *eigvecs_out) {
     Result R;
     CheckStream cq;
@@ -390,24 +473,44 @@ struct Solver {
     double *Xout = eigvecs_out ? eigvecs_out : X;
     next_check = 1;
     int pending = 0, pending_kk = 0;  // blocks and pairs of the check in flight
+    int unverified = -1;              // fast block whose flags are not read yet
+    int qr_snap[2] = {0, 0};          // qr_calls at the start of block J (J % 2)
+    bool redo = false;
     SpmmTimer timer(o.flags & BBL_FLAG_TIME_SPMM, o.m_max);
-    for (int J = 0; J < o.m_max; ++J) {
-      timer.begin(J, s);
-      if (o.plan) launch_spmm_planned(*o.plan, slot(J), W, s);
-      else launch_spmm(H, slot(J), xd, W, xd, b, s);
-      timer.end(J, s);
-      ++R.spmm_calls;
-      gram(slot(J), xd, b, 1, 0, W, xd, b, Araw);
-      launch_set_A(Araw, b, J, band, b, J > 0 ? Bstore + (size_t)(J - 1) * b * b : nullptr, C3,
-                   dres + kHn2Slot, s);
-      const int nb3 = J > 0 ? 2 : 1;
-      launch_update(n, slot(J > 0 ? J - 1 : 0), xd, b, nb3, slot_stride(), C3, b, -1.0, W, xd,
-                    1.0, Wp, BBL_F64, s);
-      reorth(J + 1, Wp);
-      double *BJ = Bstore + (size_t)J * b * b;
-      block_qr(J + 1, J + 1, BJ, hnorm_dev);
-      launch_set_B(BJ, b, J, band, b, o.m_max * b, s);
-      R.iters = R.built = J + 1;
+    // Reads the flags of fast block U (waiting for it); if it needed a rare
+    // branch, discards what followed it and returns true: block U is redone
+    // on the full path.
+    auto needs_redo = [&](int U) {
+      BBL_HIP(hipEventSynchronize(cq.fev[U % 2]));
+      const int *f = cq.iter_flags(U);
+      if (!f[0] && !f[2]) return false;
+      if (pending) {  // its band matrix contains the discarded blocks
+        BBL_HIP(hipStreamSynchronize(cq.cs));
+        pending = 0;
+      }
+      BBL_HIP(hipMemcpyAsync(dres + kHn2Slot, dres + kHn2Snap + U % 2, sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+      // the breakdown flag is sticky; a block that is redone did not count
+      BBL_HIP(hipMemcpyAsync(breakdown, ints + 127, sizeof(int), hipMemcpyDeviceToDevice, s));
+      qr_calls = qr_snap[U % 2];
+      return true;
+    };
+    int J = 0;
+    while (J < o.m_max) {
+      const bool fast = !redo;
+      redo = false;
+      qr_snap[J % 2] = qr_calls;
+      iterate(J, fast, hnorm_dev, timer, cq, R);
+      R.iters = J + 1;
+      R.built = std::max(R.built, J + 1);
+      // the previous fast block, complete once this one is queued
+      if (unverified >= 0 && needs_redo(unverified)) {
+        J = unverified;
+        unverified = -1;
+        redo = true;
+        continue;
+      }
+      unverified = fast ? J : -1;
       // the check launched after the previous block ran beside this one
       if (pending) {
         const int nb = pending;
@@ -417,17 +520,27 @@ struct Solver {
       const int N = (J + 1) * b;
       const bool exhausted = (int64_t)N >= n;
       const bool last = (J == o.m_max - 1);
-      if (N < k && !exhausted) continue;
-      if (!(exhausted || last || J + 1 >= next_check)) continue;
+      if ((N < k && !exhausted) || !(exhausted || last || J + 1 >= next_check)) {
+        ++J;
+        continue;
+      }
       const int kk = std::min(k, N);
       launch_check(cq, J + 1, kk);
       ++R.checks;
-      if (exhausted || last) {  // nothing left to overlap with
+      pending = J + 1;
+      pending_kk = kk;
+      if (exhausted || last) {  // nothing left to overlap with: read it now
+        if (unverified >= 0 && needs_redo(unverified)) {
+          J = unverified;
+          unverified = -1;
+          redo = true;
+          continue;
+        }
+        pending = 0;
         consume_check(cq, J + 1, kk, true, hnorm_dev, Xout, R);
         break;
       }
-      pending = J + 1;
-      pending_kk = kk;
+      ++J;
     }
     timer.collect(R.built, s, &R.spmm_ms, &R.spmm_timed);
     return R;

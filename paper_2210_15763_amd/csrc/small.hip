@@ -125,13 +125,16 @@ __global__ __launch_bounds__(64) void k_chol_try(const double *__restrict__ O, i
                                                  const double *hnorm_ptr, const double *hn2_ptr,
                                                  double *C0, double *QB, double *RB, int *mask,
                                                  int *flag, int *fail) {
-  __shared__ double R[kMaxBlock * kMaxBlock], Ri[kMaxBlock * kMaxBlock];
+  __shared__ double R[kMaxBlock * kMaxBlock], Ri[kMaxBlock * kMaxBlock], Os[kMaxBlock * kMaxBlock];
   __shared__ int ok;
   const int t = threadIdx.x;
+  // the serial factorisation reads its input from LDS, not global memory
+  for (int i = t; i < b * b; i += blockDim.x) Os[i] = O[i];
+  __syncthreads();
   if (t == 0) {
     double dmax = 0.0;
-    for (int i = 0; i < b; ++i) dmax = fmax(dmax, O[i * b + i]);
-    const double pmin = chol_upper(O, b, R, Ri);
+    for (int i = 0; i < b; ++i) dmax = fmax(dmax, Os[i * b + i]);
+    const double pmin = chol_upper(Os, b, R, Ri);
     const double hn = fmax(hnorm_ptr ? *hnorm_ptr : 0.0, hn2_ptr ? *hn2_ptr : 0.0);
     const double scale = tau * fmax(sqrt(fmax(dmax, 0.0)), hn);
     ok = (dmax > 0.0 && pmin > 1e-14 * dmax && pmin > scale * scale) ? 1 : 0;
@@ -154,15 +157,19 @@ __global__ __launch_bounds__(64) void k_chol_try(const double *__restrict__ O, i
 __global__ __launch_bounds__(64) void k_chol_finish(const double *__restrict__ O2, int b,
                                                     const double *__restrict__ RB, double *Rinv,
                                                     double *Bout, int *breakdown) {
-  __shared__ double R[kMaxBlock * kMaxBlock], Ri[kMaxBlock * kMaxBlock];
+  __shared__ double R[kMaxBlock * kMaxBlock], Ri[kMaxBlock * kMaxBlock], Os[kMaxBlock * kMaxBlock];
   const int t = threadIdx.x;
+  // the serial factorisation reads its input from LDS, not global memory
+  for (int i = t; i < b * b; i += blockDim.x) Os[i] = O2[i];
+  __syncthreads();
+  const double *O2l = Os;
   if (t == 0) {
     int bad = 0;
     double dmax = 0.0;
-    for (int i = 0; i < b; ++i) dmax = fmax(dmax, O2[i * b + i]);
+    for (int i = 0; i < b; ++i) dmax = fmax(dmax, O2l[i * b + i]);
     for (int i = 0; i < b * b; ++i) R[i] = 0.0;
     for (int j = 0; j < b; ++j) {
-      double s = 0.5 * (O2[j * b + j] + O2[j * b + j]);
+      double s = 0.5 * (O2l[j * b + j] + O2l[j * b + j]);
       for (int k = 0; k < j; ++k) s -= R[k * b + j] * R[k * b + j];
       if (!(s > 1e-28 * dmax) || !(dmax > 0.0)) {
         bad = 1;
@@ -171,7 +178,7 @@ __global__ __launch_bounds__(64) void k_chol_finish(const double *__restrict__ O
       const double rjj = sqrt(s);
       R[j * b + j] = rjj;
       for (int c = j + 1; c < b; ++c) {
-        double x = 0.5 * (O2[j * b + c] + O2[c * b + j]);
+        double x = 0.5 * (O2l[j * b + c] + O2l[c * b + j]);
         for (int k = 0; k < j; ++k) x -= R[k * b + j] * R[k * b + c];
         R[j * b + c] = x / rjj;
       }
@@ -336,7 +343,7 @@ void launch_chol_try(const double *O, int b, double tau, const double *hnorm_ptr
                      int *flag, int *fail, hipStream_t s) {
   hipLaunchKernelGGL(k_chol_try, dim3(1), dim3(64), 0, s, O, b, tau, hnorm_ptr, hn2_ptr, C0, QB,
                      RB, mask, flag, fail);
-  check_launch("k_svqb_prepare");
+  check_launch("k_chol_try");
 }
 
 void launch_chol_finish(const double *O2, int b, const double *RB, double *Rinv, double *Bout,

@@ -362,7 +362,8 @@ __global__ __launch_bounds__(256) void k_plan_rows(int64_t n, int64_t G, int slo
                                                    const int32_t *__restrict__ blocks,
                                                    int32_t *__restrict__ n_local,
                                                    int32_t *__restrict__ col2,
-                                                   VT *__restrict__ val2) {
+                                                   VT *__restrict__ val2,
+                                                   uint16_t *__restrict__ lcol) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;  // uniform per wave
   const int lane = threadIdx.x & 63;
@@ -400,6 +401,7 @@ __global__ __launch_bounds__(256) void k_plan_rows(int64_t n, int64_t G, int slo
       const int64_t q = p0 + il + __popcll(ml & below);
       col2[q] = loc;
       val2[q] = val[p];
+      if (lcol) lcol[q] = (uint16_t)loc;
     } else if (in) {
       const int64_t q = p0 + nl + ir + __popcll(mr & below);
       col2[q] = c;
@@ -411,12 +413,13 @@ __global__ __launch_bounds__(256) void k_plan_rows(int64_t n, int64_t G, int slo
   if (lane == 0) n_local[row] = nl;
 }
 
-template <typename VT, typename XT, typename AT, typename YT, int B, int LPR>
+template <typename VT, typename XT, typename AT, typename YT, int B, int LPR, bool LC16>
 __global__ __launch_bounds__(1024) void k_spmm_planned(int64_t n, int64_t G, int slots, int parts,
                                                        const int64_t *__restrict__ rp,
                                                        const int32_t *__restrict__ n_local,
                                                        const int32_t *__restrict__ col2,
                                                        const VT *__restrict__ val2,
+                                                       const uint16_t *__restrict__ lcol,
                                                        const int32_t *__restrict__ blocks,
                                                        const XT *__restrict__ X,
                                                        YT *__restrict__ Y) {
@@ -498,9 +501,21 @@ __global__ __launch_bounds__(1024) void k_spmm_planned(int64_t n, int64_t G, int
         }
         // local entries: LDS gathers while the remote ones are in flight
         if (ql < pl) {
-          const int4 c4 = *reinterpret_cast<const int4 *>(col2 + ql);
+          int cc[4];
+          if constexpr (LC16) {  // four 16-bit LDS indices in one 8-byte load
+            const uint2 c2 = *reinterpret_cast<const uint2 *>(lcol + ql);
+            cc[0] = (int)(c2.x & 0xffffu);
+            cc[1] = (int)(c2.x >> 16);
+            cc[2] = (int)(c2.y & 0xffffu);
+            cc[3] = (int)(c2.y >> 16);
+          } else {
+            const int4 c4 = *reinterpret_cast<const int4 *>(col2 + ql);
+            cc[0] = c4.x;
+            cc[1] = c4.y;
+            cc[2] = c4.z;
+            cc[3] = c4.w;
+          }
           const Quad<VT> v4 = load_quad(val2 + ql);
-          const int cc[4] = {c4.x, c4.y, c4.z, c4.w};
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int64_t pe = ql + e;
@@ -542,9 +557,9 @@ __global__ __launch_bounds__(1024) void k_spmm_planned(int64_t n, int64_t G, int
 constexpr int kPlanThreads = 1024;
 constexpr int kPlanParts = 2;   // workgroups per row group
 
-template <typename VT, typename XT, int BV>
-void planned_launch(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s) {
-  auto kern = k_spmm_planned<VT, XT, XT, XT, BV, 16>;
+template <typename VT, typename XT, int BV, bool LC16>
+void planned_launch_t(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s) {
+  auto kern = k_spmm_planned<VT, XT, XT, XT, BV, 16, LC16>;
   const size_t lds = (size_t)P.slots * P.block_rows * BV * sizeof(XT);
   if (lds > 65536) {
     static bool attr_set = false;
@@ -559,8 +574,14 @@ void planned_launch(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s) {
   const int64_t grid = ceil_div(groups * parts, kXcds) * kXcds;
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPlanThreads), lds, s, P.n,
                      (int64_t)P.block_rows, P.slots, parts, P.row_ptr, P.n_local, P.col,
-                     static_cast<const VT *>(P.val), P.blocks, X, Y);
+                     static_cast<const VT *>(P.val), P.lcol, P.blocks, X, Y);
   check_launch("k_spmm_planned");
+}
+
+template <typename VT, typename XT, int BV>
+void planned_launch(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s) {
+  if (P.local16 && P.lcol) planned_launch_t<VT, XT, BV, true>(P, X, Y, s);
+  else planned_launch_t<VT, XT, BV, false>(P, X, Y, s);
 }
 
 template <typename VT, typename XT>
@@ -626,14 +647,20 @@ int spmm_plan_slots(const bbl_csr &H, int nvec, int vec_dtype) {
   return (int)std::min<size_t>(kPlanMaxSlots, kPlanLds / per);
 }
 
+// LDS row indices slot*G + offset all fit in 16 bits
+bool plan_local16(const bbl_csr &H, int slots) {
+  return (int64_t)slots * H.block_rows <= 65536;
+}
+
 size_t spmm_plan_bytes(const bbl_csr &H, int nvec, int vec_dtype) {
   const int slots = spmm_plan_slots(H, nvec, vec_dtype);
   if (slots < 1) return 0;
   const int64_t groups = ceil_div(H.n, H.block_rows);
   const size_t sv = H.val_dtype == BBL_F32 ? 4 : 8;
-  // index and value arrays padded by 4 entries for the 16-byte chunk loads
+  // index and value arrays padded by 4 entries for the chunk loads
   return align_up((size_t)groups * slots * 4) + align_up((size_t)H.n * 4) +
-         align_up((size_t)(H.nnz + 4) * 4) + align_up((size_t)(H.nnz + 4) * sv) + 256;
+         align_up((size_t)(H.nnz + 4) * 4) + align_up((size_t)(H.nnz + 4) * sv) +
+         (plan_local16(H, slots) ? align_up((size_t)(H.nnz + 4) * 2) : 0) + 256;
 }
 
 void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_t bytes,
@@ -641,7 +668,7 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
   const int slots = spmm_plan_slots(H, nvec, vec_dtype);
   if (slots < 1)
     throw Error{BBL_E_INVALID, "no plan: block_rows must be > 0, nvec in {1,2,4,8,10,16} and "
-                               "one block of V must fit in 128 KB of LDS"};
+                               "one block of V must fit in 160 KB of LDS"};
   if (bytes < spmm_plan_bytes(H, nvec, vec_dtype)) throw Error{BBL_E_NOMEM, "plan memory too small"};
   const int64_t groups = ceil_div(H.n, H.block_rows);
   const size_t sv = H.val_dtype == BBL_F32 ? 4 : 8;
@@ -656,6 +683,8 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
   int32_t *n_local = reinterpret_cast<int32_t *>(take((size_t)H.n * 4));
   int32_t *col2 = reinterpret_cast<int32_t *>(take((size_t)(H.nnz + 4) * 4));
   void *val2 = take((size_t)(H.nnz + 4) * sv);
+  const bool l16 = plan_local16(H, slots);
+  uint16_t *lcol = l16 ? reinterpret_cast<uint16_t *>(take((size_t)(H.nnz + 4) * 2)) : nullptr;
   hipLaunchKernelGGL(k_plan_blocks, dim3((unsigned)groups), dim3(256), 0, s, H.n,
                      (int64_t)H.block_rows, slots, H.row_ptr, H.col, blocks);
   const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(H.n, 4));
@@ -663,12 +692,12 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
     hipLaunchKernelGGL((k_plan_rows<float>), dim3(grid), dim3(256), 0, s, H.n,
                        (int64_t)H.block_rows, slots, H.row_ptr, H.col,
                        static_cast<const float *>(H.val), blocks, n_local, col2,
-                       static_cast<float *>(val2));
+                       static_cast<float *>(val2), lcol);
   else
     hipLaunchKernelGGL((k_plan_rows<double>), dim3(grid), dim3(256), 0, s, H.n,
                        (int64_t)H.block_rows, slots, H.row_ptr, H.col,
                        static_cast<const double *>(H.val), blocks, n_local, col2,
-                       static_cast<double *>(val2));
+                       static_cast<double *>(val2), lcol);
   check_launch("spmm plan");
   P->n = H.n;
   P->nnz = H.nnz;
@@ -677,12 +706,13 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
   P->nvec = nvec;
   P->vec_dtype = vec_dtype;
   P->val_dtype = H.val_dtype;
-  P->reserved = 0;
+  P->local16 = l16 ? 1 : 0;
   P->row_ptr = H.row_ptr;
   P->blocks = blocks;
   P->n_local = n_local;
   P->col = col2;
   P->val = val2;
+  P->lcol = lcol;
 }
 
 void launch_spmm_planned(const bbl_spmm_plan &P, const void *X, void *Y, hipStream_t s) {

@@ -439,11 +439,20 @@ __global__ __launch_bounds__(64) void k_gram_v(int64_t n, const XT *__restrict__
 
 // Yout[r][j] = beta*Yin[r][j] + alpha*sum_m X[r][m] C[m][j], X blocks of width
 // BX, one row per lane (RPL rows per lane, 256-row stride), C rows scalar.
-template <typename XT, typename YIT, typename YOT, int BX, int NY, int RPL>
+//
+// GRAM: also the Gram matrix of the rows this workgroup wrote,
+// gpart[blockIdx.x][a][c] = sum_r Yout[r][a] Yout[r][c] (the values as
+// stored), which saves a separate pass over Yout when the next step needs
+// Yout^T Yout.  Each 256-row tile of output goes through LDS; thread
+// (e, s) sums entry e over the tile rows s, s + S, ... and the S slices
+// are added in a fixed order, so the result is deterministic and the main
+// loop keeps its register budget (occupancy).
+template <typename XT, typename YIT, typename YOT, int BX, int NY, int RPL, bool GRAM>
 __global__ __launch_bounds__(256) void k_update_v(int64_t n, const XT *X, int nblk,
                                                   int64_t xstride, const double *__restrict__ C,
                                                   double alpha, const YIT *Yin, double beta,
-                                                  YOT *Yout, const int *__restrict__ when) {
+                                                  YOT *Yout, const int *__restrict__ when,
+                                                  double *__restrict__ gpart) {
   if (when && *when == 0) return;
   const int64_t base = (int64_t)blockIdx.x * 256 * RPL + threadIdx.x;
   double acc[RPL][NY];
@@ -472,21 +481,63 @@ __global__ __launch_bounds__(256) void k_update_v(int64_t n, const XT *X, int nb
       }
     }
   }
+  constexpr int NP = NY * (NY + 1) / 2;
+  constexpr int S = (256 / NP) > 0 ? 256 / NP : 1;  // slices per Gram entry
+  static_assert(NP <= 256, "Gram epilogue: too many entries");
+  __shared__ double tile[GRAM ? 256 : 1][GRAM ? NY : 1];
+  __shared__ double red[GRAM ? 256 : 1];
+  const int t = threadIdx.x;
+  int ga = 0, gc = 0;  // Gram entry (a <= c) of this thread
+  if (GRAM && t < NP * S) {
+    const int e = t / S;
+    while ((gc + 1) * (gc + 2) / 2 <= e) ++gc;
+    ga = e - gc * (gc + 1) / 2;
+  }
+  double gsum = 0.0;
 #pragma unroll
   for (int u = 0; u < RPL; ++u) {
     const int64_t r = base + (int64_t)u * 256;
-    if (r >= n) continue;
-    YOT o[NY];
-    if (beta != 0.0) {
-      const Vec<YIT, NY> yi = vload<YIT, NY>(Yin + r * NY);
+    double ov[NY];
 #pragma unroll
-      for (int j = 0; j < NY; ++j) o[j] = (YOT)fma(beta, (double)yi.v[j], alpha * acc[u][j]);
-    } else {
+    for (int j = 0; j < NY; ++j) ov[j] = 0.0;
+    if (r < n) {
+      YOT o[NY];
+      if (beta != 0.0) {
+        const Vec<YIT, NY> yi = vload<YIT, NY>(Yin + r * NY);
 #pragma unroll
-      for (int j = 0; j < NY; ++j) o[j] = (YOT)(alpha * acc[u][j]);
+        for (int j = 0; j < NY; ++j) o[j] = (YOT)fma(beta, (double)yi.v[j], alpha * acc[u][j]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < NY; ++j) o[j] = (YOT)(alpha * acc[u][j]);
+      }
+#pragma unroll
+      for (int j = 0; j < NY; ++j) {
+        Yout[r * NY + j] = o[j];
+        ov[j] = (double)o[j];
+      }
     }
+    if constexpr (GRAM) {
+      __syncthreads();  // the previous tile is consumed
 #pragma unroll
-    for (int j = 0; j < NY; ++j) Yout[r * NY + j] = o[j];
+      for (int j = 0; j < NY; ++j) tile[t][j] = ov[j];
+      __syncthreads();
+      if (t < NP * S)
+        for (int q = t % S; q < 256; q += S) gsum = fma(tile[q][ga], tile[q][gc], gsum);
+    }
+  }
+  if constexpr (GRAM) {
+    red[t] = gsum;
+    __syncthreads();
+    if (t < NP) {
+      int c = 0;
+      while ((c + 1) * (c + 2) / 2 <= t) ++c;
+      const int a = t - c * (c + 1) / 2;
+      double v = 0.0;
+      for (int q = 0; q < S; ++q) v += red[t * S + q];
+      double *out = gpart + (int64_t)blockIdx.x * NY * NY;
+      out[a * NY + c] = v;
+      out[c * NY + a] = v;
+    }
   }
 }
 
@@ -614,31 +665,42 @@ int gram_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const 
   return (int)gx;
 }
 
+constexpr int kUpdRPL = 2;  // rows per lane of k_update_v (256-row stride)
+
 template <typename XT, typename YIT, typename YOT, int B, int NY = B>
 void update_valu(int64_t n, const XT *X, int nblk, int64_t xstride, const double *C, double alpha,
-                 const YIT *Yin, double beta, YOT *Yout, const int *when, hipStream_t s) {
-  constexpr int RPL = 2;
-  const int64_t grid = ceil_div(n, 256 * RPL);
-  hipLaunchKernelGGL((k_update_v<XT, YIT, YOT, B, NY, RPL>), dim3((unsigned)grid), dim3(256), 0, s,
-                     n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when);
+                 const YIT *Yin, double beta, YOT *Yout, const int *when, double *gpart,
+                 hipStream_t s) {
+  const int64_t grid = ceil_div(n, 256 * kUpdRPL);
+  if (gpart)
+    hipLaunchKernelGGL((k_update_v<XT, YIT, YOT, B, NY, kUpdRPL, true>), dim3((unsigned)grid),
+                       dim3(256), 0, s, n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when,
+                       gpart);
+  else
+    hipLaunchKernelGGL((k_update_v<XT, YIT, YOT, B, NY, kUpdRPL, false>), dim3((unsigned)grid),
+                       dim3(256), 0, s, n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when,
+                       gpart);
   check_launch("k_update_v");
 }
 
+// gpart: where the Gram partials of Yout may go (nullptr: none wanted).
+// Returns the number of partials written, 0 if this shape has no fused Gram.
 template <typename XT, typename YIT, typename YOT>
-void update_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const double *C,
-                  int ny, double alpha, const YIT *Yin, double beta, YOT *Yout, const int *when,
-                  hipStream_t s) {
+int update_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const double *C,
+                 int ny, double alpha, const YIT *Yin, double beta, YOT *Yout, const int *when,
+                 double *gpart, hipStream_t s) {
   const int M = nblk * bx;
+  const int P = (int)ceil_div(n, 256 * kUpdRPL);
   if (bx == 8 && ny == 10) {  // Ritz vectors of b = 8 blocks, k = 10
-    update_valu<XT, YIT, YOT, 8, 10>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, s);
-    return;
+    update_valu<XT, YIT, YOT, 8, 10>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s);
+    return gpart ? P : 0;
   }
   if (ny == bx) {
     switch (bx) {
-      case 4: update_valu<XT, YIT, YOT, 4>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, s); return;
-      case 8: update_valu<XT, YIT, YOT, 8>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, s); return;
-      case 10: update_valu<XT, YIT, YOT, 10>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, s); return;
-      case 16: update_valu<XT, YIT, YOT, 16>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, s); return;
+      case 4: update_valu<XT, YIT, YOT, 4>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s); return gpart ? P : 0;
+      case 8: update_valu<XT, YIT, YOT, 8>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s); return gpart ? P : 0;
+      case 10: update_valu<XT, YIT, YOT, 10>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s); return gpart ? P : 0;
+      case 16: update_valu<XT, YIT, YOT, 16>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s); return gpart ? P : 0;
       default: break;
     }
   }
@@ -650,6 +712,7 @@ void update_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, con
     hipLaunchKernelGGL((k_update<XT, YIT, YOT, 2>), dim3((unsigned)grid), dim3(256), 0, s, n, X,
                        bx, M, xstride, C, ny, alpha, Yin, beta, Yout, when);
   check_launch("k_update");
+  return 0;
 }
 
 }  // namespace
@@ -705,18 +768,21 @@ void launch_reduce(const double *partial, int P, int M, int ny, double *out, hip
   launch_reduce_when(partial, P, M, ny, out, nullptr, s);
 }
 
-void launch_update_when(int64_t n, const void *X, int xdtype, int bx, int nblk, int64_t xstride,
-                        const double *C, int ny, double alpha, const void *Yin, int yindtype,
-                        double beta, void *Yout, int youtdtype, const int *when,
-                        hipStream_t s) {
-  if (n <= 0) return;
+int launch_update_gram_when(int64_t n, const void *X, int xdtype, int bx, int nblk,
+                            int64_t xstride, const double *C, int ny, double alpha,
+                            const void *Yin, int yindtype, double beta, void *Yout, int youtdtype,
+                            double *gpart, size_t gcap_doubles, const int *when, hipStream_t s) {
+  if (n <= 0) return 0;
   if (nblk <= 0) {  // empty product: Yout = beta * Yin
     BBL_REQUIRE(false, "update: empty X");
   }
+  // room for the partials and the reduction's stage-1 sums behind them
+  const int64_t P = ceil_div(n, 256 * kUpdRPL);
+  if (gpart && (size_t)(P + P / 8 + 64) * ny * ny > gcap_doubles) gpart = nullptr;
   const bool xf = xdtype == BBL_F32, yif = yindtype == BBL_F32, yof = youtdtype == BBL_F32;
 #define BBL_UPD(XT, YIT, YOT)                                                                 \
-  update_typed(n, (const XT *)X, bx, nblk, xstride, C, ny, alpha, (const YIT *)Yin, beta,     \
-               (YOT *)Yout, when, s)
+  return update_typed(n, (const XT *)X, bx, nblk, xstride, C, ny, alpha, (const YIT *)Yin,    \
+                      beta, (YOT *)Yout, when, gpart, s)
   if (xf && yif && yof) BBL_UPD(float, float, float);
   else if (xf && yif && !yof) BBL_UPD(float, float, double);
   else if (xf && !yif && yof) BBL_UPD(float, double, float);
@@ -726,6 +792,14 @@ void launch_update_when(int64_t n, const void *X, int xdtype, int bx, int nblk, 
   else if (!xf && !yif && yof) BBL_UPD(double, double, float);
   else BBL_UPD(double, double, double);
 #undef BBL_UPD
+}
+
+void launch_update_when(int64_t n, const void *X, int xdtype, int bx, int nblk, int64_t xstride,
+                        const double *C, int ny, double alpha, const void *Yin, int yindtype,
+                        double beta, void *Yout, int youtdtype, const int *when,
+                        hipStream_t s) {
+  (void)launch_update_gram_when(n, X, xdtype, bx, nblk, xstride, C, ny, alpha, Yin, yindtype,
+                                beta, Yout, youtdtype, nullptr, 0, when, s);
 }
 
 void launch_update(int64_t n, const void *X, int xdtype, int bx, int nblk, int64_t xstride,

@@ -119,6 +119,18 @@ def test_spmm_plan_layout_and_errors(torch, bbl):
     assert np.all(nl >= 0) and np.all(nl <= lens)
     # own sector (70 % of draws) plus the three busiest partners
     assert nl.sum() / lens.sum() > 0.75
+    # the 16-bit copy of the LDS row indices matches the 32-bit one on every
+    # staged entry (the first n_local entries of each row)
+    assert plan.c.local16 == 1
+    oc = plan.c.col - plan.mem.data_ptr()
+    ol = plan.c.lcol - plan.mem.data_ptr()
+    col2 = plan.mem[oc:oc + 4 * H.nnz].view(torch.int32).cpu().numpy()
+    lcol = plan.mem[ol:ol + 2 * H.nnz].view(torch.int16).cpu().numpy().view(np.uint16)
+    rows = np.repeat(np.arange(H.n), lens)
+    staged = np.arange(H.nnz) - np.asarray(H.row_ptr)[rows] < nl[rows]
+    assert staged.sum() == nl.sum()
+    assert np.array_equal(lcol[staged].astype(np.int64), col2[staged].astype(np.int64))
+    assert np.all(col2[staged] < plan.slots * 400)
     with pytest.raises(bbl.BblError):
         bbl.spmm_plan(bbl.DeviceCSR.from_host(H, "float32"), 8)          # no hint
     with pytest.raises(bbl.BblError):
@@ -236,6 +248,29 @@ def test_band_eig_matches_dense_eigh(torch, bbl, N, kd, k):
     Sg = Sg.cpu().numpy()
     assert np.max(np.linalg.norm(T @ Sg - Sg * theta, axis=0)) <= 1e-11 * nrm
     assert np.max(np.abs(Sg.T @ Sg - np.eye(k))) <= 1e-12
+
+
+@pytest.mark.parametrize("kd", [4, 6])
+def test_band_eig_double_eigenvalues(torch, bbl, kd):
+    """T = diag(B, B): every eigenvalue twice.  Inverse iteration at equal
+    shifts must still give an orthonormal basis of each 2-d eigenspace."""
+    note("band eig with doubled spectrum kd=%d" % kd)
+    rng = np.random.default_rng(11 + kd)
+    m = 150
+    B = np.zeros((m, m))
+    for d in range(kd + 1):
+        v = rng.standard_normal(m - d)
+        B += np.diag(v, -d) + (np.diag(v, d) if d else 0)
+    T = np.zeros((2 * m, 2 * m))
+    T[:m, :m] = B
+    T[m:, m:] = B
+    lam = np.linalg.eigvalsh(T)
+    theta, Sg, top = bbl.band_eig(dev(torch, band_from_dense(T, kd)), 2 * m, kd, 10)
+    nrm = max(abs(lam[0]), abs(lam[-1]))
+    np.testing.assert_allclose(theta, lam[:10], rtol=0, atol=1e-12 * nrm)
+    Sg = Sg.cpu().numpy()
+    assert np.max(np.abs(Sg.T @ Sg - np.eye(10))) <= 1e-12
+    assert np.max(np.linalg.norm(T @ Sg - Sg * theta, axis=0)) <= 1e-11 * nrm
 
 
 def test_band_eig_on_lanczos_band_matrix(torch, bbl):
@@ -367,6 +402,40 @@ def test_exact_eigenvector_pivot_deflates_and_converges_at_once(torch, bbl):
     assert r.converged and r.stats["iters"] == 1
     assert r.stats["deflations"] == 4
     np.testing.assert_allclose(r.eigvals, lam[:4], rtol=1e-12)
+
+
+def test_exhausted_invariant_subspace_takes_the_full_path(torch, bbl):
+    """A pivot inside a 12-dimensional invariant subspace: the third block's
+    W' is rounding noise inside the basis span, so that block needs the
+    second Gram-Schmidt sweep and a full deflation -- the branches the fast
+    path leaves to a redo on the full path."""
+    note("exhausted invariant subspace n=412 b=4")
+    A = synthgen.generate(12, 12, 4, 0.7, 5).to_dense() + 100.0 * np.eye(12)
+    Bm = synthgen.generate(400, 100, 10, 0.7, 6).to_dense()
+    D = np.zeros((412, 412))
+    D[:12, :12] = A
+    D[12:, 12:] = Bm
+    rp = [0]
+    cols, vals = [], []
+    for i in range(412):
+        nz = np.nonzero(D[i])[0]
+        cols.append(nz)
+        vals.append(D[i, nz])
+        rp.append(rp[-1] + len(nz))
+    H = synthgen.CSR(412, np.array(rp, np.int64), np.concatenate(cols).astype(np.int32),
+                     np.concatenate(vals))
+    P = np.zeros((412, 4))
+    P[:12] = synthgen.gaussian_block(12, 4, 3)
+    r = bbl.block_lanczos(bbl.DeviceCSR.from_host(H, "float64"), dev(torch, P), 4, 1e-10,
+                          m_max=50)
+    # the Krylov space of the pivot is the invariant subspace: its pairs are
+    # exact (the coupling to the deflated block vanishes), as in the oracle
+    ref = oracle.block_lanczos(H, P, 4, 1e-10, 50)
+    assert ref.converged and ref.iters == 3 and ref.deflations == 4
+    assert r.converged and r.stats["iters"] == ref.iters
+    assert r.stats["deflations"] == ref.deflations
+    assert r.stats["reorth_second_passes"] >= 1
+    np.testing.assert_allclose(r.eigvals, np.linalg.eigvalsh(A)[:4], rtol=1e-12)
 
 
 def test_rank_deficient_pivot_is_repaired(torch, bbl):
