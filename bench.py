@@ -506,7 +506,7 @@ def main():
                    "n_trunc": w.n_trunc, "m_max": w.m_max, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK,
-                     "traffic": traffic, "kernel": "k_spmm_planned<float,float,float,float,8,16>",
+                     "traffic": traffic, "kernel": "k_spmm_planned<float,float,float,float,8,16,true>",
                      "alg_bytes_per_launch": alg, "launch_ms": t_live * 1e3},
         "cpu_baseline": cpu,
         "details": extra,

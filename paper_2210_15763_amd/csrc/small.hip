@@ -114,6 +114,59 @@ __device__ double chol_upper(const double *O, int b, double *R, double *Ri) {
   return pmin;
 }
 
+// The same factorisation in registers for a compile-time B (one thread):
+// R[a][c] (a <= c) at trR(c, a), R^{-1} likewise.  thr: a pivot that is not
+// above it is replaced by 1 and counted in nbad.  Returns the smallest pivot.
+__host__ __device__ constexpr int trR(int c, int a) { return c * (c + 1) / 2 + a; }
+
+template <int B>
+__device__ __forceinline__ double chol_reg(const double *O, double thr, double (&R)[B * (B + 1) / 2],
+                                           double (&Ri)[B * (B + 1) / 2], int &nbad) {
+  double pmin = 1e308;
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    double sj = O[j * B + j];
+#pragma unroll
+    for (int m = 0; m < j; ++m) sj = fma(-R[trR(j, m)], R[trR(j, m)], sj);
+    pmin = fmin(pmin, sj);
+    if (!(sj > thr)) {
+      ++nbad;
+      sj = 1.0;
+    }
+    const double rjj = sqrt(sj);
+    R[trR(j, j)] = rjj;
+#pragma unroll
+    for (int c = j + 1; c < B; ++c) {
+      double x = 0.5 * (O[j * B + c] + O[c * B + j]);
+#pragma unroll
+      for (int m = 0; m < j; ++m) x = fma(-R[trR(j, m)], R[trR(c, m)], x);
+      R[trR(c, j)] = x / rjj;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < B; ++c) {
+    Ri[trR(c, c)] = 1.0 / R[trR(c, c)];
+#pragma unroll
+    for (int aa = 0; aa < c; ++aa) {
+      const int r = c - 1 - aa;
+      double x = 0.0;
+#pragma unroll
+      for (int m = r + 1; m <= c; ++m) x = fma(R[trR(m, r)], Ri[trR(c, m)], x);
+      Ri[trR(c, r)] = -x / R[trR(r, r)];
+    }
+  }
+  return pmin;
+}
+
+// Unpacks the register triangles into row-major LDS matrices (zero below).
+template <int B>
+__device__ __forceinline__ void unpack_upper(const double (&T)[B * (B + 1) / 2], double *M) {
+#pragma unroll
+  for (int r = 0; r < B; ++r)
+#pragma unroll
+    for (int c = 0; c < B; ++c) M[r * B + c] = c >= r ? T[trR(c, r)] : 0.0;
+}
+
 // First factorisation of the overlap by Cholesky (CholQR).  Accepted when the
 // overlap is safely positive definite: every pivot above 1e-14 * max O_ii
 // (condition number of W' below ~1e7, where the Cholesky polish pass restores
@@ -121,6 +174,8 @@ __device__ double chol_upper(const double *O, int b, double *R, double *Ri) {
 // is negligible -- the deflation test of the spectral factorisation).  On
 // success C0 = R^{-1}, RB = R, QB = I, no deflation; otherwise fail = 1 and the
 // spectral factorisation (k_svqb_prepare, gated by fail) takes over.
+// BC > 0: compile-time block width (b == BC), factorised in registers.
+template <int BC>
 __global__ __launch_bounds__(64) void k_chol_try(const double *__restrict__ O, int b, double tau,
                                                  const double *hnorm_ptr, const double *hn2_ptr,
                                                  double *C0, double *QB, double *RB, int *mask,
@@ -134,7 +189,16 @@ __global__ __launch_bounds__(64) void k_chol_try(const double *__restrict__ O, i
   if (t == 0) {
     double dmax = 0.0;
     for (int i = 0; i < b; ++i) dmax = fmax(dmax, Os[i * b + i]);
-    const double pmin = chol_upper(Os, b, R, Ri);
+    double pmin;
+    if constexpr (BC > 0) {
+      double Rr[BC * (BC + 1) / 2], Rir[BC * (BC + 1) / 2];
+      int nbad = 0;
+      pmin = chol_reg<BC>(Os, 0.0, Rr, Rir, nbad);
+      unpack_upper<BC>(Rr, R);
+      unpack_upper<BC>(Rir, Ri);
+    } else {
+      pmin = chol_upper(Os, b, R, Ri);
+    }
     const double hn = fmax(hnorm_ptr ? *hnorm_ptr : 0.0, hn2_ptr ? *hn2_ptr : 0.0);
     const double scale = tau * fmax(sqrt(fmax(dmax, 0.0)), hn);
     ok = (dmax > 0.0 && pmin > 1e-14 * dmax && pmin > scale * scale) ? 1 : 0;
@@ -154,6 +218,7 @@ __global__ __launch_bounds__(64) void k_chol_try(const double *__restrict__ O, i
 // Second pass: O2 = Y^T Y = R2^T R2.  Writes R2^{-1} (upper, row-major) and
 // Bout = R2 RB (upper triangular).  breakdown is set to 1 (and never cleared)
 // if O2 is not positive definite to working precision.
+template <int BC>
 __global__ __launch_bounds__(64) void k_chol_finish(const double *__restrict__ O2, int b,
                                                     const double *__restrict__ RB, double *Rinv,
                                                     double *Bout, int *breakdown) {
@@ -163,7 +228,19 @@ __global__ __launch_bounds__(64) void k_chol_finish(const double *__restrict__ O
   for (int i = t; i < b * b; i += blockDim.x) Os[i] = O2[i];
   __syncthreads();
   const double *O2l = Os;
-  if (t == 0) {
+  if (BC > 0 && t == 0) {
+    double dmax = 0.0;
+    for (int i = 0; i < b; ++i) dmax = fmax(dmax, O2l[i * b + i]);
+    double Rr[(BC > 0 ? BC : 1) * ((BC > 0 ? BC : 1) + 1) / 2];
+    double Rir[(BC > 0 ? BC : 1) * ((BC > 0 ? BC : 1) + 1) / 2];
+    int nbad = 0;
+    if constexpr (BC > 0) {
+      chol_reg<BC>(O2l, 1e-28 * dmax, Rr, Rir, nbad);
+      unpack_upper<BC>(Rr, R);
+      unpack_upper<BC>(Rir, Ri);
+    }
+    if (nbad || !(dmax > 0.0)) *breakdown = 1;  // sticky until the solve ends
+  } else if (BC == 0 && t == 0) {
     int bad = 0;
     double dmax = 0.0;
     for (int i = 0; i < b; ++i) dmax = fmax(dmax, O2l[i * b + i]);
@@ -341,14 +418,29 @@ void launch_svqb_prepare(const double *O, int b, double tau, const double *hnorm
 void launch_chol_try(const double *O, int b, double tau, const double *hnorm_ptr,
                      const double *hn2_ptr, double *C0, double *QB, double *RB, int *mask,
                      int *flag, int *fail, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_try, dim3(1), dim3(64), 0, s, O, b, tau, hnorm_ptr, hn2_ptr, C0, QB,
-                     RB, mask, flag, fail);
+  if (b == 8)
+    hipLaunchKernelGGL(k_chol_try<8>, dim3(1), dim3(64), 0, s, O, b, tau, hnorm_ptr, hn2_ptr, C0,
+                       QB, RB, mask, flag, fail);
+  else if (b == 10)
+    hipLaunchKernelGGL(k_chol_try<10>, dim3(1), dim3(64), 0, s, O, b, tau, hnorm_ptr, hn2_ptr, C0,
+                       QB, RB, mask, flag, fail);
+  else
+    hipLaunchKernelGGL(k_chol_try<0>, dim3(1), dim3(64), 0, s, O, b, tau, hnorm_ptr, hn2_ptr, C0,
+                       QB, RB, mask, flag, fail);
   check_launch("k_chol_try");
 }
 
 void launch_chol_finish(const double *O2, int b, const double *RB, double *Rinv, double *Bout,
                         int *breakdown, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_finish, dim3(1), dim3(64), 0, s, O2, b, RB, Rinv, Bout, breakdown);
+  if (b == 8)
+    hipLaunchKernelGGL(k_chol_finish<8>, dim3(1), dim3(64), 0, s, O2, b, RB, Rinv, Bout,
+                       breakdown);
+  else if (b == 10)
+    hipLaunchKernelGGL(k_chol_finish<10>, dim3(1), dim3(64), 0, s, O2, b, RB, Rinv, Bout,
+                       breakdown);
+  else
+    hipLaunchKernelGGL(k_chol_finish<0>, dim3(1), dim3(64), 0, s, O2, b, RB, Rinv, Bout,
+                       breakdown);
   check_launch("k_chol_finish");
 }
 
