@@ -823,17 +823,18 @@ __global__ __launch_bounds__(64) void k_rr_fast(const double *__restrict__ Tb, i
   }
 }
 
-// Multisection.  Register-window bandwidths: 16384 shifts per round (256
-// one-wave workgroups, a quarter of the SIMDs, so that an overlapped check
-// leaves most of the chip to the recurrence) and four rounds; the first
-// round spreads the shifts over the Gershgorin interval, later rounds give
-// each target its own run of shifts / (k + 1), rounded down to whole waves.
-// That narrows every bracket by at least 16385 * 449^3 ~ 1.5e12 (k <= 32).
-// Other bandwidths (one workgroup per shift): 2048 shifts and six rounds,
-// at least 2049 * 65^5 ~ 2.4e12.  Inverse iteration and Rayleigh-Ritz then
-// refine the pairs.
-constexpr int kShiftsReg = 16384, kRoundsReg = 4;
-constexpr int kShiftsLds = 2048, kRoundsLds = 6;
+// Multisection.  Register-window bandwidths: 8192 shifts per round (128
+// one-wave workgroups, an eighth of the SIMDs, so that an overlapped check
+// leaves most of the chip to the recurrence); other bandwidths (one
+// workgroup per shift): 2048.  The first round spreads the shifts over the
+// Gershgorin interval, later rounds give each target its own run of
+// shifts / (k + 1), rounded down to whole waves.  Rounds continue until every
+// bracket has narrowed by at least kNarrow (four rounds for k = 10 on the
+// register path: 8193 * 705^3 ~ 2.9e12).  Inverse iteration and Rayleigh-Ritz
+// then refine the pairs.
+constexpr int kShiftsReg = 8192;
+constexpr int kShiftsLds = 2048;
+constexpr double kNarrow = 2e12;
 constexpr int kInvIters = 2;
 // dynamic LDS of the one-wave kernels that stage an N x k block (vectors of
 // the inverse iteration, the Rayleigh-Ritz basis)
@@ -907,8 +908,9 @@ void band_eigensolve(const double *band, int N, int kd, int k, void *ws, const B
   hipLaunchKernelGGL(k_gersh, dim3(1), dim3(256), 0, s, band, N, kdd, gersh);
   const bool regk = reg_bandwidth(kdd);
   const int nsh = regk ? kShiftsReg : kShiftsLds;
-  const int rounds = regk ? kRoundsReg : kRoundsLds;
   const int SP = shifts_per_target(nsh, NT);
+  int rounds = 1;
+  for (double f = nsh + 1.0; f < kNarrow; f *= SP + 1.0) ++rounds;
   hipLaunchKernelGGL(k_bisect_init, dim3(16), dim3(256), 0, s, gersh, nsh, sh_a, brk, NT);
   check_launch("k_bisect_init");
   const size_t smem_s = (size_t)((kdd + 1) * (kdd + 1) + kChunk * (kdd + 1)) * sizeof(double);
