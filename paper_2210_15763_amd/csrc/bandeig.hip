@@ -414,7 +414,8 @@ __global__ __launch_bounds__(64) void k_invit(const double *__restrict__ Tb, int
 // group (its multipliers, inverse pivots and entering x values) are issued
 // before its arithmetic, so that one memory latency is exposed per group
 // rather than per row.  Stores z_j = y_j / d_j in place of x_j.
-template <int KD>
+// FULL: rows j0 .. j0 + 2 KD - 1 all exist, so no clamping or selects.
+template <int KD, bool FULL>
 __device__ __forceinline__ void fwd_group(const double *__restrict__ L,
                                           const double *__restrict__ Dinv, int ls, double *X,
                                           int ldx, int N, int j0, double (&q)[KD]) {
@@ -424,8 +425,8 @@ __device__ __forceinline__ void fwd_group(const double *__restrict__ L,
 #pragma unroll
   for (int m = 0; m < KD; ++m) {
     const int j = j0 + m;
-    const bool in = j < N, nin = j + KD < N;
-    const int jc = min(j, N - 1), jnc = min(j + KD, N - 1);
+    const bool in = FULL || j < N, nin = FULL || j + KD < N;
+    const int jc = FULL ? j : min(j, N - 1), jnc = FULL ? j + KD : min(j + KD, N - 1);
 #pragma unroll
     for (int r = 0; r < KD; ++r) {
       const double v = L[((int64_t)jc * KD + r) * ls];
@@ -442,7 +443,7 @@ __device__ __forceinline__ void fwd_group(const double *__restrict__ L,
 #pragma unroll
     for (int r = 1; r < KD; ++r) q[(m + r) % KD] = fma(-Lg[m][r - 1], y, q[(m + r) % KD]);
     q[m] = fma(-Lg[m][KD - 1], y, xn[m]);
-    if (j0 + m < N) X[(int64_t)(j0 + m) * ldx] = y * dv[m];
+    if (FULL || j0 + m < N) X[(int64_t)(j0 + m) * ldx] = y * dv[m];
   }
 }
 
@@ -450,15 +451,16 @@ __device__ __forceinline__ void fwd_group(const double *__restrict__ L,
 // x_i = z_i - sum_r l_{i+r,i} x_{i+r}.  wv holds x_{i+1..i+KD}; the slot of
 // x_m is (m - i0 - 1) mod KD.  Loads of the group first, as above.
 // Accumulates ||x||^2 in row order.
-template <int KD>
+// FULL: rows i0 - KD + 1 .. i0 all exist.
+template <int KD, bool FULL>
 __device__ __forceinline__ void bwd_group(const double *__restrict__ L, int ls, double *X,
                                           int ldx, int i0, double (&wv)[KD], double &nrm2) {
   double Lg[KD][KD], zg[KD];
 #pragma unroll
   for (int m = 0; m < KD; ++m) {
     const int i = i0 - m;
-    const bool in = i >= 0;
-    const int ic = max(i, 0);
+    const bool in = FULL || i >= 0;
+    const int ic = FULL ? i : max(i, 0);
 #pragma unroll
     for (int r = 0; r < KD; ++r) {
       const double v = L[((int64_t)ic * KD + r) * ls];
@@ -469,7 +471,7 @@ __device__ __forceinline__ void bwd_group(const double *__restrict__ L, int ls, 
   }
 #pragma unroll
   for (int m = 0; m < KD; ++m) {
-    if (i0 - m < 0) break;
+    if (!FULL && i0 - m < 0) break;
     double a0 = 0.0, a1 = 0.0;
 #pragma unroll
     for (int r = 1; r <= KD; ++r) {
@@ -516,14 +518,20 @@ __global__ __launch_bounds__(64) void k_invit_reg(const double *__restrict__ Tb,
     double q[KD];
 #pragma unroll
     for (int r = 0; r < KD; ++r) q[r] = r < N ? x[(int64_t)r * k] : 0.0;
+    int j0 = 0;
 #pragma unroll 1
-    for (int j0 = 0; j0 < N; j0 += KD) fwd_group<KD>(L, Dinv, k, x, k, N, j0, q);
+    for (; j0 + 2 * KD <= N; j0 += KD) fwd_group<KD, true>(L, Dinv, k, x, k, N, j0, q);
+#pragma unroll 1
+    for (; j0 < N; j0 += KD) fwd_group<KD, false>(L, Dinv, k, x, k, N, j0, q);
     double wv[KD];
 #pragma unroll
     for (int r = 0; r < KD; ++r) wv[r] = 0.0;
     double nrm2 = 0.0;
+    int i0 = N - 1;
 #pragma unroll 1
-    for (int i0 = N - 1; i0 >= 0; i0 -= KD) bwd_group<KD>(L, k, x, k, i0, wv, nrm2);
+    for (; i0 - KD + 1 >= 0; i0 -= KD) bwd_group<KD, true>(L, k, x, k, i0, wv, nrm2);
+#pragma unroll 1
+    for (; i0 >= 0; i0 -= KD) bwd_group<KD, false>(L, k, x, k, i0, wv, nrm2);
     const double sc = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 1.0;
     for (int i = 0; i < N; ++i) x[(int64_t)i * k] *= sc;
   }
