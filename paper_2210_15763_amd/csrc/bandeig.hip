@@ -129,6 +129,18 @@ __global__ __launch_bounds__(64) void k_sturm(const double *__restrict__ Tb, int
 // R[k+i][k+j] -= w_i R[k+j][k]; the same arithmetic as ldl_sweep.
 constexpr int tri(int a, int b) { return a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a; }
 
+// 1/d from the hardware reciprocal estimate and two Newton steps
+// r <- r + r (1 - d r): full double precision for the LDL^T multipliers at a
+// third of the dependent instructions of the IEEE division sequence, which
+// sits on the critical path of every row.
+__device__ __forceinline__ double newton_inv(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Steps M..KD of one unrolled group of W = KD + 1 rows, slot indices static.
 // STORE: multipliers l_{k+i,k} to L[(k*KD + i-1) * ls] and 1/d to
 // Dinv[k * ls] (a tiny pivot keeps its sign there); otherwise a tiny pivot
@@ -158,7 +170,7 @@ __device__ __forceinline__ void ldl_steps(const double *__restrict__ Tb, int N, 
       double d = R[tri(M, M)];
       if (fabs(d) < pivmin) d = (STORE && d > 0.0) ? pivmin : -pivmin;
       cnt += d < 0.0 ? 1 : 0;
-      const double inv = 1.0 / d;
+      const double inv = newton_inv(d);
       double w[KD + 1];
 #pragma unroll
       for (int i = 1; i <= KD; ++i) w[i] = R[tri((M + i) % W, M)] * inv;
