@@ -498,57 +498,75 @@ __device__ __forceinline__ void bwd_group(const double *__restrict__ L, int ls, 
   }
 }
 
-// Inverse iteration for a compile-time bandwidth, one lane per target tg < k:
-// the lane factors T - theta I (theta = bracket midpoint) with the register
-// window, keeping its multipliers and inverse pivots in scratch (interleaved
-// over the k lanes, so that every load and store of the wave is contiguous),
-// then runs niter solves L D L^T x <- x from a hashed start, normalising
-// after each.  Column tg of X (row-major N x k) is the lane's vector.
-// SX: the vectors live in dynamic LDS (N k doubles) during the solves and are
-// copied to X at the end; the solves then issue no global stores, whose
-// completion the waits for their global loads would otherwise include.
-template <int KD, bool SX>
+// Inverse iteration for a compile-time bandwidth at the bracket midpoint
+// theta of target tg < k: factor T - theta I with the register window,
+// keeping the multipliers and inverse pivots, then run niter solves
+// L D L^T x <- x from a hashed start, normalising after each.  Column tg of
+// X (row-major N x k) receives the vector.  Three placements:
+//   MODE 0: one lane per target, factors in global scratch (interleaved over
+//           the k lanes, so every load and store of the wave is contiguous),
+//           vectors in X;
+//   MODE 1: as 0 but the vectors in dynamic LDS (N k doubles), copied to X
+//           at the end;
+//   MODE 2: one workgroup per target (its first lane works): factors and
+//           vector in dynamic LDS (N (KD + 2) doubles), so the solves never
+//           wait on global memory, whose latency grows under the load of the
+//           recurrence running beside a check.
+template <int KD, int MODE>
 __global__ __launch_bounds__(64) void k_invit_reg(const double *__restrict__ Tb, int N,
                                                   const double *__restrict__ brk, int k,
                                                   double pivmin, double *Lscr, double *Dscr,
                                                   double *X, int niter) {
   constexpr int W = KD + 1;
-  extern __shared__ double sX[];
-  const int tg = blockIdx.x * 64 + threadIdx.x;
-  if (tg >= k) return;
+  extern __shared__ double smem_inv[];
+  const int tg = MODE == 2 ? (int)blockIdx.x : (int)(blockIdx.x * 64 + threadIdx.x);
+  if (tg >= k || (MODE == 2 && threadIdx.x != 0)) return;
   const double theta = 0.5 * (brk[2 * tg] + brk[2 * tg + 1]);
-  double *L = Lscr + tg;     // l_{j+r,j} at L[(j*KD + r-1) * k]
-  double *Dinv = Dscr + tg;  // 1/d_j at Dinv[j * k]
+  // l_{j+r,j} at L[(j*KD + r-1) * ls], 1/d_j at Dinv[j * ls], x_j at x[j * lx]
+  double *L, *Dinv, *x;
+  int ls, lx;
+  if constexpr (MODE == 2) {
+    L = smem_inv;
+    Dinv = smem_inv + (size_t)N * KD;
+    x = Dinv + N;
+    ls = 1;
+    lx = 1;
+  } else {
+    L = Lscr + tg;
+    Dinv = Dscr + tg;
+    x = (MODE == 1 ? smem_inv : X) + tg;
+    ls = k;
+    lx = k;
+  }
   double R[W * (W + 1) / 2];
   ldl_window_init<KD>(Tb, N, theta, R);
   int cnt = 0;
-  ldl_sweep_reg<KD, true>(Tb, N, theta, pivmin, R, cnt, L, Dinv, k);
-  double *x = (SX ? sX : X) + tg;
+  ldl_sweep_reg<KD, true>(Tb, N, theta, pivmin, R, cnt, L, Dinv, ls);
   for (int i = 0; i < N; ++i)
-    x[(int64_t)i * k] = hash_unit((uint32_t)(i * 40503u + tg * 2654435761u + 7u));
+    x[(int64_t)i * lx] = hash_unit((uint32_t)(i * 40503u + tg * 2654435761u + 7u));
   for (int it = 0; it < niter; ++it) {
     double q[KD];
 #pragma unroll
-    for (int r = 0; r < KD; ++r) q[r] = r < N ? x[(int64_t)r * k] : 0.0;
+    for (int r = 0; r < KD; ++r) q[r] = r < N ? x[(int64_t)r * lx] : 0.0;
     int j0 = 0;
 #pragma unroll 1
-    for (; j0 + 2 * KD <= N; j0 += KD) fwd_group<KD, true>(L, Dinv, k, x, k, N, j0, q);
+    for (; j0 + 2 * KD <= N; j0 += KD) fwd_group<KD, true>(L, Dinv, ls, x, lx, N, j0, q);
 #pragma unroll 1
-    for (; j0 < N; j0 += KD) fwd_group<KD, false>(L, Dinv, k, x, k, N, j0, q);
+    for (; j0 < N; j0 += KD) fwd_group<KD, false>(L, Dinv, ls, x, lx, N, j0, q);
     double wv[KD];
 #pragma unroll
     for (int r = 0; r < KD; ++r) wv[r] = 0.0;
     double nrm2 = 0.0;
     int i0 = N - 1;
 #pragma unroll 1
-    for (; i0 - KD + 1 >= 0; i0 -= KD) bwd_group<KD, true>(L, k, x, k, i0, wv, nrm2);
+    for (; i0 - KD + 1 >= 0; i0 -= KD) bwd_group<KD, true>(L, ls, x, lx, i0, wv, nrm2);
 #pragma unroll 1
-    for (; i0 >= 0; i0 -= KD) bwd_group<KD, false>(L, k, x, k, i0, wv, nrm2);
+    for (; i0 >= 0; i0 -= KD) bwd_group<KD, false>(L, ls, x, lx, i0, wv, nrm2);
     const double sc = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 1.0;
-    for (int i = 0; i < N; ++i) x[(int64_t)i * k] *= sc;
+    for (int i = 0; i < N; ++i) x[(int64_t)i * lx] *= sc;
   }
-  if (SX)
-    for (int i = 0; i < N; ++i) X[(int64_t)i * k + tg] = x[(int64_t)i * k];
+  if (MODE != 0)
+    for (int i = 0; i < N; ++i) X[(int64_t)i * k + tg] = x[(int64_t)i * lx];
 }
 
 __device__ double wg_sum(double v, double *red) {
@@ -863,22 +881,32 @@ constexpr size_t kRrLds = 150 * 1024;
 bool reg_bandwidth(int kd) { return kd == 1 || kd == 2 || kd == 4 || kd == 8 || kd == 10; }
 int shifts_per_target(int nsh, int NT) { return std::max(64, (nsh / NT) / 64 * 64); }
 
-template <int KD>
-void invit_reg_launch(bool sx, size_t xbytes, const double *band, int N, const double *brk, int k,
-                      double *Lscr, double *Dscr, double *X, hipStream_t s) {
-  if (sx) {
+template <int KD, int MODE>
+void invit_reg_mode(size_t smem, int grid, const double *band, int N, const double *brk, int k,
+                    double *Lscr, double *Dscr, double *X, hipStream_t s) {
+  if (smem > 65536) {
     static bool attr = false;  // per process: the kernel's LDS limit
     if (!attr) {
-      BBL_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_invit_reg<KD, true>),
+      BBL_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_invit_reg<KD, MODE>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRrLds));
       attr = true;
     }
-    hipLaunchKernelGGL((k_invit_reg<KD, true>), dim3(1), dim3(64), xbytes, s, band, N, brk, k,
-                       1e-200, Lscr, Dscr, X, kInvIters);
-  } else {
-    hipLaunchKernelGGL((k_invit_reg<KD, false>), dim3(1), dim3(64), 0, s, band, N, brk, k, 1e-200,
-                       Lscr, Dscr, X, kInvIters);
   }
+  hipLaunchKernelGGL((k_invit_reg<KD, MODE>), dim3(grid), dim3(64), smem, s, band, N, brk, k,
+                     1e-200, Lscr, Dscr, X, kInvIters);
+}
+
+template <int KD>
+void invit_reg_launch(const double *band, int N, const double *brk, int k, double *Lscr,
+                      double *Dscr, double *X, hipStream_t s) {
+  const size_t per_target = (size_t)N * (KD + 2) * sizeof(double);
+  const size_t xbytes = (size_t)N * k * sizeof(double);
+  if (per_target <= kRrLds)
+    invit_reg_mode<KD, 2>(per_target, k, band, N, brk, k, Lscr, Dscr, X, s);
+  else if (xbytes <= kRrLds)
+    invit_reg_mode<KD, 1>(xbytes, 1, band, N, brk, k, Lscr, Dscr, X, s);
+  else
+    invit_reg_mode<KD, 0>(0, 1, band, N, brk, k, Lscr, Dscr, X, s);
 }
 
 }  // namespace
@@ -949,14 +977,12 @@ void band_eigensolve(const double *band, int N, int kd, int k, void *ws, const B
   // inverse iteration: register-window kernel for the common bandwidths,
   // else the LDS-window kernel (x staged in LDS)
   if (regk) {
-    const size_t xbytes = (size_t)N * k * sizeof(double);
-    const bool sx = xbytes <= kRrLds;
     switch (kdd) {
-      case 1: invit_reg_launch<1>(sx, xbytes, band, N, brk, k, Lscr, Dscr, X, s); break;
-      case 2: invit_reg_launch<2>(sx, xbytes, band, N, brk, k, Lscr, Dscr, X, s); break;
-      case 4: invit_reg_launch<4>(sx, xbytes, band, N, brk, k, Lscr, Dscr, X, s); break;
-      case 8: invit_reg_launch<8>(sx, xbytes, band, N, brk, k, Lscr, Dscr, X, s); break;
-      default: invit_reg_launch<10>(sx, xbytes, band, N, brk, k, Lscr, Dscr, X, s); break;
+      case 1: invit_reg_launch<1>(band, N, brk, k, Lscr, Dscr, X, s); break;
+      case 2: invit_reg_launch<2>(band, N, brk, k, Lscr, Dscr, X, s); break;
+      case 4: invit_reg_launch<4>(band, N, brk, k, Lscr, Dscr, X, s); break;
+      case 8: invit_reg_launch<8>(band, N, brk, k, Lscr, Dscr, X, s); break;
+      default: invit_reg_launch<10>(band, N, brk, k, Lscr, Dscr, X, s); break;
     }
     check_launch("k_invit_reg");
   } else {
