@@ -447,7 +447,10 @@ __global__ __launch_bounds__(64) void k_gram_v(int64_t n, const XT *__restrict__
 // (e, s) sums entry e over the tile rows s, s + S, ... and the S slices
 // are added in a fixed order, so the result is deterministic and the main
 // loop keeps its register budget (occupancy).
-template <typename XT, typename YIT, typename YOT, int BX, int NY, int RPL, bool GRAM>
+//
+// PF > 1: the loads of PF blocks are issued before their products (for short
+// grids, where each lane's walk over the blocks is latency-bound).
+template <typename XT, typename YIT, typename YOT, int BX, int NY, int RPL, bool GRAM, int PF>
 __global__ __launch_bounds__(256) void k_update_v(int64_t n, const XT *X, int nblk,
                                                   int64_t xstride, const double *__restrict__ C,
                                                   double alpha, const YIT *Yin, double beta,
@@ -460,7 +463,36 @@ __global__ __launch_bounds__(256) void k_update_v(int64_t n, const XT *X, int nb
   for (int u = 0; u < RPL; ++u)
 #pragma unroll
     for (int j = 0; j < NY; ++j) acc[u][j] = 0.0;
-  for (int blk = 0; blk < nblk; ++blk) {
+  int blk0 = 0;
+  if constexpr (PF > 1) {
+    for (; blk0 + PF <= nblk; blk0 += PF) {
+      Vec<XT, BX> xp[PF][RPL];
+#pragma unroll
+      for (int p = 0; p < PF; ++p)
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+          const int64_t r = base + (int64_t)u * 256;
+          if (r < n) xp[p][u] = vload<XT, BX>(X + (int64_t)(blk0 + p) * xstride + r * BX);
+          else
+#pragma unroll
+            for (int c = 0; c < BX; ++c) xp[p][u].v[c] = XT(0);
+        }
+#pragma unroll
+      for (int p = 0; p < PF; ++p) {
+        const double *cb = C + (int64_t)(blk0 + p) * BX * NY;
+#pragma unroll
+        for (int a = 0; a < BX; ++a) {
+#pragma unroll
+          for (int j = 0; j < NY; ++j) {
+            const double cv = cb[a * NY + j];
+#pragma unroll
+            for (int u = 0; u < RPL; ++u) acc[u][j] = fma((double)xp[p][u].v[a], cv, acc[u][j]);
+          }
+        }
+      }
+    }
+  }
+  for (int blk = blk0; blk < nblk; ++blk) {
     Vec<XT, BX> xv[RPL];
 #pragma unroll
     for (int u = 0; u < RPL; ++u) {
@@ -672,14 +704,19 @@ void update_valu(int64_t n, const XT *X, int nblk, int64_t xstride, const double
                  const YIT *Yin, double beta, YOT *Yout, const int *when, double *gpart,
                  hipStream_t s) {
   const int64_t grid = ceil_div(n, 256 * kUpdRPL);
-  if (gpart)
-    hipLaunchKernelGGL((k_update_v<XT, YIT, YOT, B, NY, kUpdRPL, true>), dim3((unsigned)grid),
-                       dim3(256), 0, s, n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when,
-                       gpart);
-  else
-    hipLaunchKernelGGL((k_update_v<XT, YIT, YOT, B, NY, kUpdRPL, false>), dim3((unsigned)grid),
-                       dim3(256), 0, s, n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when,
-                       gpart);
+  // a short grid (few rows) walks many blocks per lane: prefetch four at a time
+  const bool pf = grid < 512 && nblk >= 8;
+#define BBL_UPDV(G, PF)                                                                        \
+  hipLaunchKernelGGL((k_update_v<XT, YIT, YOT, B, NY, kUpdRPL, G, PF>), dim3((unsigned)grid),    \
+                     dim3(256), 0, s, n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart)
+  if (gpart) {
+    if (pf) BBL_UPDV(true, 4);
+    else BBL_UPDV(true, 1);
+  } else {
+    if (pf) BBL_UPDV(false, 4);
+    else BBL_UPDV(false, 1);
+  }
+#undef BBL_UPDV
   check_launch("k_update_v");
 }
 
@@ -749,8 +786,10 @@ void launch_reduce_when(const double *partial, int P, int M, int ny, double *out
   // stage 1 writes S partial sums behind the P partials (the caller's partial
   // buffer holds (P + S) * MN doubles), stage 2 sums them in order.  S ~ sqrt(P)
   // balances the serial length of the two stages.
+  // (a few partials: one stage, one launch)
   const int S_room = std::max(1, 8192 / ((MN + 255) / 256));
-  const int S = std::max(1, std::min({P / 8, S_room, (int)std::ceil(std::sqrt((double)P))}));
+  const int S = P <= 32 ? 1
+                        : std::max(1, std::min({P / 8, S_room, (int)std::ceil(std::sqrt((double)P))}));
   if (S > 1) {
     double *tmp = const_cast<double *>(partial) + (size_t)P * MN;
     hipLaunchKernelGGL(k_reduce1, dim3((MN + 255) / 256, S), dim3(256), 0, s, partial, P, MN, S,
