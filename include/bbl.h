@@ -117,10 +117,10 @@ typedef struct {
 /* Counters of one solve and its wall time (host clock around the call). */
 typedef struct {
   int32_t iters;        /* blocks of the Krylov space the returned pairs come
-                           from (the recurrence may have built one more block
+                           from (the recurrence may have built up to two more
                            while the last check ran beside it) */
   int32_t spmm_calls;   /* all products with H, explicit residual checks and
-                           the block built beside the last check included */
+                           the blocks built beside the last check included */
   int32_t deflations;   /* columns replaced because of (near) rank loss */
   int32_t converged;    /* 1 if every wanted pair met the tolerance */
   int32_t checks;       /* band-matrix eigensolves */

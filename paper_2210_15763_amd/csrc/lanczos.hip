@@ -14,17 +14,19 @@
 //   FP64 residual decide convergence.
 // A block first runs a fast path: one Gram-Schmidt sweep and a Cholesky QR.
 // Whether it needed the second sweep (the DGKS norm test) or the spectral
-// factor with deflation is recorded on the device and read by the host once
-// the next block is queued; such a block (rare: none on the benchmark
-// matrices) is then redone on the full path, which decides both branches on
-// the device, and the blocks queued after it are discarded.
+// factor with deflation is recorded on the device and read by the host two
+// blocks later (the queue keeps two blocks ahead of the host); such a block
+// (rare: none on the benchmark matrices) is then redone on the full path,
+// which decides both branches on the device, and the blocks queued after it
+// are discarded.
 // Every step runs in HIP kernels.  The recurrence runs on the caller's stream;
 // the band eigensolve of a check runs on a second stream of the solver,
-// concurrently with the next block of the recurrence, and its result is read
-// by the host after that block has been queued (one block later, always at
-// the same point of the sequence, so the run is deterministic).  The host
-// only sequences launches and reads 2k+3 numbers per check.
+// concurrently with the recurrence, and its result is read by the host once
+// the block it ends with has been verified (two blocks later, always at the
+// same point of the sequence, so the run is deterministic).  The host only
+// sequences launches and reads 2k+3 numbers per check and 3 per block.
 #include <chrono>
+#include <deque>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -45,7 +47,7 @@ namespace {
 constexpr int kMaxPartialRows = 4096;   // residual / column-statistics partials
 constexpr uint32_t kTagDeflation = 7;
 constexpr int kHn2Slot = 200;          // dres slot: max |A_jj| seen so far (<= ||H||)
-constexpr int kHn2Snap = 202;          // dres slots 202, 203: kHn2Slot at the start of block J (J % 2)
+constexpr int kHn2Snap = 202;          // dres slots 202..205: kHn2Slot at the start of block J (J % 4)
 
 size_t dsize(int dt) { return dt == BBL_F32 ? 4 : 8; }
 
@@ -127,13 +129,15 @@ struct SpmmTimer {
 // pinned host buffer for the check results.  Non-blocking, so that it never
 // synchronises implicitly with a legacy default stream of the caller.
 // The pinned buffer also receives, per block of the fast path, its rare-branch
-// flags (slot J % 2: ints flag2, -, chol_fail at kIterFlags + 4 (J % 2)) and
-// `fev[J % 2]` marks their arrival.
+// flags (slot J % kRing: ints flag2, -, chol_fail at kIterFlags + 4 (J % kRing))
+// and `fev[J % kRing]` marks their arrival.  The host reads a block's flags
+// kLag blocks later, so kRing > kLag slots are in use at a time.
+constexpr int kLag = 2, kRing = 4;
 constexpr int kIterFlags = 2 * (2 * kMaxBlock + 8);  // int offset in the pinned buffer
 
 struct CheckStream {
   hipStream_t cs = nullptr;
-  hipEvent_t ready = nullptr, done = nullptr, fev[2] = {nullptr, nullptr};
+  hipEvent_t ready = nullptr, done = nullptr, fev[kRing] = {};
   double *host = nullptr;
   hipError_t err = hipSuccess;
   static constexpr int kHostDoubles = 2 * kMaxBlock + 16;
@@ -141,7 +145,7 @@ struct CheckStream {
     err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (err == hipSuccess) err = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
     if (err == hipSuccess) err = hipEventCreateWithFlags(&done, hipEventDisableTiming);
-    for (int i = 0; i < 2 && err == hipSuccess; ++i)
+    for (int i = 0; i < kRing && err == hipSuccess; ++i)
       err = hipEventCreateWithFlags(&fev[i], hipEventDisableTiming);
     if (err == hipSuccess)
       err = hipHostMalloc(reinterpret_cast<void **>(&host), kHostDoubles * sizeof(double),
@@ -156,7 +160,7 @@ struct CheckStream {
       if (e) (void)hipEventDestroy(e);
     if (cs) (void)hipStreamDestroy(cs);
   }
-  int *iter_flags(int J) { return reinterpret_cast<int *>(host) + kIterFlags + 4 * (J % 2); }
+  int *iter_flags(int J) { return reinterpret_cast<int *>(host) + kIterFlags + 4 * (J % kRing); }
   CheckStream(const CheckStream &) = delete;
   CheckStream &operator=(const CheckStream &) = delete;
 };
@@ -427,7 +431,7 @@ struct Solver {
   void iterate(int J, bool fast, const double *hnorm_dev, SpmmTimer &timer, CheckStream &cq,
                Result &R) {
     if (fast)  // max |A_jj| as of this block's start, restored if it is redone
-      BBL_HIP(hipMemcpyAsync(dres + kHn2Snap + J % 2, dres + kHn2Slot, sizeof(double),
+      BBL_HIP(hipMemcpyAsync(dres + kHn2Snap + J % kRing, dres + kHn2Slot, sizeof(double),
                              hipMemcpyDeviceToDevice, s));
     timer.begin(J, s);
     if (o.plan) launch_spmm_planned(*o.plan, slot(J), W, s);
@@ -451,9 +455,9 @@ struct Solver {
       block_qr(J + 1, J + 1, BJ, hnorm_dev, G1);
     }
     launch_set_B(BJ, b, J, band, b, o.m_max * b, s);
-    if (fast) {  // flag2, n_second, chol_fail -> pinned slot J % 2
+    if (fast) {  // flag2, n_second, chol_fail -> pinned slot J % kRing
       BBL_HIP(hipMemcpyAsync(cq.iter_flags(J), flag2, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
-      BBL_HIP(hipEventRecord(cq.fev[J % 2], s));
+      BBL_HIP(hipEventRecord(cq.fev[J % kRing], s));
     }
   }
 
@@ -473,46 +477,54 @@ struct Solver {
     double *Xout = eigvecs_out ? eigvecs_out : X;
     next_check = 1;
     int pending = 0, pending_kk = 0;  // blocks and pairs of the check in flight
-    int unverified = -1;              // fast block whose flags are not read yet
-    int qr_snap[2] = {0, 0};          // qr_calls at the start of block J (J % 2)
+    std::deque<int> unverified;       // fast blocks whose flags are not read yet
+    int qr_snap[kRing] = {};          // qr_calls at the start of block J (J % kRing)
     bool redo = false;
     SpmmTimer timer(o.flags & BBL_FLAG_TIME_SPMM, o.m_max);
-    // Reads the flags of fast block U (waiting for it); if it needed a rare
-    // branch, discards what followed it and returns true: block U is redone
-    // on the full path.
-    auto needs_redo = [&](int U) {
-      BBL_HIP(hipEventSynchronize(cq.fev[U % 2]));
-      const int *f = cq.iter_flags(U);
-      if (!f[0] && !f[2]) return false;
-      if (pending) {  // its band matrix contains the discarded blocks
-        BBL_HIP(hipStreamSynchronize(cq.cs));
-        pending = 0;
+    // Reads the flags of the unverified fast blocks up to `upto`, oldest
+    // first (waiting for them).  At the first that needed a rare branch,
+    // discards what followed it and returns it: that block is redone on the
+    // full path.  Otherwise returns -1.
+    auto verify = [&](int upto) {
+      while (!unverified.empty() && unverified.front() <= upto) {
+        const int U = unverified.front();
+        unverified.pop_front();
+        BBL_HIP(hipEventSynchronize(cq.fev[U % kRing]));
+        const int *f = cq.iter_flags(U);
+        if (!f[0] && !f[2]) continue;
+        unverified.clear();
+        if (pending) {  // its band matrix may contain discarded blocks
+          BBL_HIP(hipStreamSynchronize(cq.cs));
+          pending = 0;
+        }
+        BBL_HIP(hipMemcpyAsync(dres + kHn2Slot, dres + kHn2Snap + U % kRing, sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
+        // the breakdown flag is sticky; a block that is redone did not count
+        BBL_HIP(hipMemcpyAsync(breakdown, ints + 127, sizeof(int), hipMemcpyDeviceToDevice, s));
+        qr_calls = qr_snap[U % kRing];
+        return U;
       }
-      BBL_HIP(hipMemcpyAsync(dres + kHn2Slot, dres + kHn2Snap + U % 2, sizeof(double),
-                             hipMemcpyDeviceToDevice, s));
-      // the breakdown flag is sticky; a block that is redone did not count
-      BBL_HIP(hipMemcpyAsync(breakdown, ints + 127, sizeof(int), hipMemcpyDeviceToDevice, s));
-      qr_calls = qr_snap[U % 2];
-      return true;
+      return -1;
     };
     int J = 0;
     while (J < o.m_max) {
       const bool fast = !redo;
       redo = false;
-      qr_snap[J % 2] = qr_calls;
+      qr_snap[J % kRing] = qr_calls;
       iterate(J, fast, hnorm_dev, timer, cq, R);
       R.iters = J + 1;
       R.built = std::max(R.built, J + 1);
-      // the previous fast block, complete once this one is queued
-      if (unverified >= 0 && needs_redo(unverified)) {
-        J = unverified;
-        unverified = -1;
+      if (fast) unverified.push_back(J);
+      // blocks kLag behind are read now: the queue still holds kLag blocks
+      const int U = verify(J - kLag);
+      if (U >= 0) {
+        J = U;
         redo = true;
         continue;
       }
-      unverified = fast ? J : -1;
-      // the check launched after the previous block ran beside this one
-      if (pending) {
+      // the pending check, once the block it ends with is verified
+      const int ok_upto = unverified.empty() ? J : unverified.front() - 1;
+      if (pending && pending - 1 <= ok_upto) {
         const int nb = pending;
         pending = 0;
         if (consume_check(cq, nb, pending_kk, false, hnorm_dev, Xout, R)) break;
@@ -520,25 +532,30 @@ struct Solver {
       const int N = (J + 1) * b;
       const bool exhausted = (int64_t)N >= n;
       const bool last = (J == o.m_max - 1);
-      if ((N < k && !exhausted) || !(exhausted || last || J + 1 >= next_check)) {
-        ++J;
-        continue;
-      }
       const int kk = std::min(k, N);
-      launch_check(cq, J + 1, kk);
-      ++R.checks;
-      pending = J + 1;
-      pending_kk = kk;
-      if (exhausted || last) {  // nothing left to overlap with: read it now
-        if (unverified >= 0 && needs_redo(unverified)) {
-          J = unverified;
-          unverified = -1;
+      if (exhausted || last) {  // nothing left to overlap with: verify all, read now
+        const int V = verify(J);
+        if (V >= 0) {
+          J = V;
           redo = true;
           continue;
         }
-        pending = 0;
+        if (pending) {
+          const int nb = pending;
+          pending = 0;
+          if (consume_check(cq, nb, pending_kk, false, hnorm_dev, Xout, R)) break;
+        }
+        launch_check(cq, J + 1, kk);
+        ++R.checks;
         consume_check(cq, J + 1, kk, true, hnorm_dev, Xout, R);
         break;
+      }
+      // one check in flight at a time; a due check waits for the slot
+      if (N >= k && J + 1 >= next_check && !pending) {
+        launch_check(cq, J + 1, kk);
+        ++R.checks;
+        pending = J + 1;
+        pending_kk = kk;
       }
       ++J;
     }
