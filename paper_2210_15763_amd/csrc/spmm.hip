@@ -177,6 +177,73 @@ __global__ __launch_bounds__(256) void k_spmm_generic(int64_t n, const int64_t *
   }
 }
 
+// The same residual for a compile-time vector count NV: each gather reads a
+// row of X with 16-byte loads, and workgroup w takes a contiguous run of rows
+// (XCD-aware order, so the XCD's L2 serves neighbouring rows' gathers).
+template <typename VT, int LPR, int NV>
+__global__ __launch_bounds__(256) void k_residual_t(int64_t n, const int64_t *__restrict__ rp,
+                                                    const int32_t *__restrict__ col,
+                                                    const VT *__restrict__ val,
+                                                    const double *__restrict__ X,
+                                                    const double *__restrict__ theta,
+                                                    int64_t chunk, double *__restrict__ partial) {
+  constexpr int RPW = kWave / LPR;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int sub = lane & (LPR - 1);
+  const int wave = threadIdx.x / kWave;
+  __shared__ double red[4][NV];
+  double sq[NV];
+#pragma unroll
+  for (int a = 0; a < NV; ++a) sq[a] = 0.0;
+  const int64_t w = xcd_block(blockIdx.x);
+  const int64_t r0 = w * chunk, r1 = min(n, r0 + chunk);
+  for (int64_t base = r0 + (int64_t)wave * RPW; base < r1; base += 4 * RPW) {
+    const int64_t row = base + lane / LPR;
+    double acc[NV];
+#pragma unroll
+    for (int a = 0; a < NV; ++a) acc[a] = 0.0;
+    if (row < r1) {
+      const int64_t q1 = rp[row + 1];
+      for (int64_t p = rp[row] + sub; p < q1; p += LPR) {
+        const double h = (double)val[p];
+        double x[NV];
+        RowIO<double, NV>::load(X + (int64_t)col[p] * NV, x);
+#pragma unroll
+        for (int a = 0; a < NV; ++a) acc[a] = fma(h, x[a], acc[a]);
+      }
+    }
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) {
+#pragma unroll
+      for (int a = 0; a < NV; ++a) acc[a] += __shfl_xor(acc[a], off, LPR);
+    }
+    if (row < r1 && sub == 0) {
+      double xr[NV];
+      RowIO<double, NV>::load(X + row * NV, xr);
+#pragma unroll
+      for (int a = 0; a < NV; ++a) {
+        const double r = acc[a] - theta[a] * xr[a];
+        sq[a] = fma(r, r, sq[a]);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = LPR; off < kWave; off <<= 1) {
+#pragma unroll
+    for (int a = 0; a < NV; ++a) sq[a] += __shfl_xor(sq[a], off, kWave);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int a = 0; a < NV; ++a) red[wave][a] = sq[a];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NV) {
+    const double v = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                     (red[2][threadIdx.x] + red[3][threadIdx.x]);
+    partial[w * NV + threadIdx.x] = v;
+  }
+}
+
 // Explicit FP64 residual: per workgroup g, partial[g][c] = sum over its rows of
 // ((H X)_{r,c} - theta_c X_{r,c})^2.  Grid-stride over rows, fixed order.
 template <typename VT, int LPR>
@@ -616,9 +683,42 @@ void launch_spmm(const bbl_csr &H, const void *X, int xdtype, void *Y, int ydtyp
   }
 }
 
+template <int NV>
+int residual_t(const bbl_csr &H, const double *X, const double *theta, double *partial,
+               int max_partials, int lpr, hipStream_t s) {
+  // whole multiple of 8 workgroups (XCD order), each a contiguous run of rows
+  int64_t grid = std::min<int64_t>(max_partials, std::max<int64_t>(8, ceil_div(H.n, 512)));
+  grid = std::max<int64_t>(8, grid / 8 * 8);
+  const int64_t chunk = ceil_div(H.n, grid);
+#define BBL_REST(VT, L)                                                                       \
+  hipLaunchKernelGGL((k_residual_t<VT, L, NV>), dim3((unsigned)grid), dim3(256), 0, s, H.n,    \
+                     H.row_ptr, H.col, static_cast<const VT *>(H.val), X, theta, chunk, partial)
+  if (H.val_dtype == BBL_F32) {
+    if (lpr == 16) BBL_REST(float, 16);
+    else if (lpr == 32) BBL_REST(float, 32);
+    else BBL_REST(float, 64);
+  } else {
+    if (lpr == 16) BBL_REST(double, 16);
+    else if (lpr == 32) BBL_REST(double, 32);
+    else BBL_REST(double, 64);
+  }
+#undef BBL_REST
+  check_launch("k_residual_t");
+  return (int)grid;
+}
+
 int launch_residual_spmm(const bbl_csr &H, const double *X, int nvec, const double *theta,
                          double *partial, int max_partials, hipStream_t s) {
   const int lpr = pick_lpr(H);
+  if (max_partials >= 8) {
+    switch (nvec) {
+      case 4: return residual_t<4>(H, X, theta, partial, max_partials, lpr, s);
+      case 8: return residual_t<8>(H, X, theta, partial, max_partials, lpr, s);
+      case 10: return residual_t<10>(H, X, theta, partial, max_partials, lpr, s);
+      case 16: return residual_t<16>(H, X, theta, partial, max_partials, lpr, s);
+      default: break;
+    }
+  }
   const int rows_per_wg = (256 / kWave) * (kWave / lpr);
   int grid = (int)std::min<int64_t>(ceil_div(H.n, rows_per_wg), max_partials);
   if (grid < 1) grid = 1;
