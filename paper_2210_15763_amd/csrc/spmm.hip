@@ -686,8 +686,9 @@ void launch_spmm(const bbl_csr &H, const void *X, int xdtype, void *Y, int ydtyp
 template <int NV>
 int residual_t(const bbl_csr &H, const double *X, const double *theta, double *partial,
                int max_partials, int lpr, hipStream_t s) {
-  // whole multiple of 8 workgroups (XCD order), each a contiguous run of rows
-  int64_t grid = std::min<int64_t>(max_partials, std::max<int64_t>(8, ceil_div(H.n, 512)));
+  // whole multiple of 8 workgroups (XCD order), each a contiguous run of at
+  // least 64 rows
+  int64_t grid = std::min<int64_t>(max_partials, std::max<int64_t>(8, ceil_div(H.n, 64)));
   grid = std::max<int64_t>(8, grid / 8 * 8);
   const int64_t chunk = ceil_div(H.n, grid);
 #define BBL_REST(VT, L)                                                                       \
