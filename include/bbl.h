@@ -90,6 +90,10 @@ typedef struct {
   const void *val;        /* [nnz] reordered values */
   const uint16_t *lcol;   /* [nnz] LDS row index of the staged entries (their
                              positions in col; others unspecified), or NULL */
+  const int32_t *rdesc;   /* [n][4] per row: first entry, first remote entry and
+                             end, as offsets from the group's first entry rounded
+                             down to a multiple of 8 (valid when nnz < 2^31); 4th
+                             unused */
 } bbl_spmm_plan;
 
 /* Solver options; a NULL pointer selects the defaults shown. */

@@ -57,7 +57,7 @@ class _Plan(ctypes.Structure):
                 ("val_dtype", ctypes.c_int32), ("local16", ctypes.c_int32),
                 ("row_ptr", ctypes.c_void_p), ("blocks", ctypes.c_void_p),
                 ("n_local", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
-                ("lcol", ctypes.c_void_p)]
+                ("lcol", ctypes.c_void_p), ("rdesc", ctypes.c_void_p)]
 
 
 class _Stats(ctypes.Structure):

@@ -8,6 +8,8 @@
 // whole row of V for that column with vector loads, and accumulates nvec
 // partial sums; a butterfly over the LPR lanes finishes the row.  Rows are
 // independent, no atomics, so results are bitwise reproducible.
+#include <type_traits>
+
 #include "common.h"
 
 namespace bbl {
@@ -430,7 +432,8 @@ __global__ __launch_bounds__(256) void k_plan_rows(int64_t n, int64_t G, int slo
                                                    int32_t *__restrict__ n_local,
                                                    int32_t *__restrict__ col2,
                                                    VT *__restrict__ val2,
-                                                   uint16_t *__restrict__ lcol) {
+                                                   uint16_t *__restrict__ lcol,
+                                                   int32_t *__restrict__ rdesc) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;  // uniform per wave
   const int lane = threadIdx.x & 63;
@@ -477,7 +480,14 @@ __global__ __launch_bounds__(256) void k_plan_rows(int64_t n, int64_t G, int slo
     il += __popcll(ml);
     ir += __popcll(mr);
   }
-  if (lane == 0) n_local[row] = nl;
+  if (lane == 0) {
+    n_local[row] = nl;
+    if (rdesc) {
+      const int64_t gb = rp[g * G] & ~(int64_t)7;
+      const int4 d = make_int4((int)(p0 - gb), (int)(p0 + nl - gb), (int)(p1 - gb), 0);
+      *reinterpret_cast<int4 *>(rdesc + 4 * row) = d;
+    }
+  }
 }
 
 template <typename VT, typename XT, typename AT, typename YT, int B, int LPR, bool LC16>
@@ -621,6 +631,273 @@ __global__ __launch_bounds__(1024) void k_spmm_planned(int64_t n, int64_t G, int
   }
 }
 
+// Software-pipelined variant for FP32 plans with 16-bit staged indices.
+// Each 16-lane row group walks its rows in steps of 128 staged entries (eight
+// per lane: one 16-byte load of indices, two of values) and 32 remote entries
+// (two per lane); the index and value loads of the following step -- of the
+// next row when this one ends -- are issued before this step's LDS reads and
+// FMAs, so one step of the CSR stream is always in flight behind the
+// arithmetic.  Entries outside a lane's part of the row read an all-zero LDS
+// row kept after the staged blocks with a zero weight, so the LDS reads carry
+// no branches.
+constexpr int kPipeLE = 8;    // staged entries per lane and step
+constexpr int kPipeRE = 2;    // remote entries per lane and step
+constexpr int kPipeLPR = 16;  // lanes per row
+
+struct PipeStage {
+  uint4 lc;                  // eight 16-bit LDS row indices
+  float lv[kPipeLE];
+  int rc[kPipeRE];
+  float rv[kPipeRE];
+  int llo, lhi, rlo, rhi;    // valid entries e: llo <= e < lhi (staged), rlo <= e < rhi (remote)
+};
+
+// Loads the lane's share of one step: staged entries [ql, ql + 8) and remote
+// entries [qr, qr + 2) of a row whose staged entries are [p0, pl) and remote
+// ones [pl, p1).  Positions are relative to a base that is a multiple of 8,
+// ql a multiple of 8 and qr of 2, so the loads are aligned; the plan pads its
+// arrays by 8 entries.  Every lane issues the same five loads whether or not
+// its entries exist (those without any read position 0 and are masked by the
+// ranges), so the number of loads in flight is the same on every path.
+__device__ __forceinline__ void pipe_load(PipeStage &st, const uint16_t *__restrict__ lcol,
+                                          const float *__restrict__ val2,
+                                          const int32_t *__restrict__ col2, int ql, int qr,
+                                          int p0, int pl, int p1) {
+  st.llo = p0 - ql;
+  st.lhi = pl - ql;
+  st.rlo = pl - qr;
+  st.rhi = p1 - qr;
+  const int lq = st.lhi > 0 ? ql : 0;
+  const int rq = st.rhi > 0 ? qr : 0;
+  st.lc = *reinterpret_cast<const uint4 *>(lcol + lq);
+  const uint4 a = reinterpret_cast<const uint4 *>(val2 + lq)[0];
+  const uint4 b = reinterpret_cast<const uint4 *>(val2 + lq)[1];
+  __builtin_memcpy(st.lv, &a, 16);
+  __builtin_memcpy(st.lv + 4, &b, 16);
+  const uint2 c = *reinterpret_cast<const uint2 *>(col2 + rq);
+  const float2 v = *reinterpret_cast<const float2 *>(val2 + rq);
+  st.rc[0] = (int)c.x;
+  st.rc[1] = (int)c.y;
+  st.rv[0] = v.x;
+  st.rv[1] = v.y;
+}
+
+__device__ __forceinline__ int pipe_lidx(const uint4 &c, int e) {
+  const unsigned w = e < 2 ? c.x : e < 4 ? c.y : e < 6 ? c.z : c.w;
+  return (int)((e & 1) ? (w >> 16) : (w & 0xffffu));
+}
+
+// Row positions come from the plan's per-row descriptors (32-bit offsets from
+// the group's first entry rounded down to a multiple of 8).
+template <int B>
+__global__ __launch_bounds__(1024) void k_spmm_planned_pipe(int64_t n, int64_t G, int slots,
+                                                            int parts,
+                                                            const int64_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ col2,
+                                                            const float *__restrict__ val2,
+                                                            const uint16_t *__restrict__ lcol,
+                                                            const int32_t *__restrict__ rdesc,
+                                                            const int32_t *__restrict__ blocks,
+                                                            const float *__restrict__ X,
+                                                            float *__restrict__ Y) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const float *sX = reinterpret_cast<const float *>(smem_raw);
+  const int64_t L = xcd_block(blockIdx.x);
+  const int64_t g = L / parts, part = L % parts;
+  const int64_t gr0 = g * G;
+  if (gr0 >= n) return;  // grid padding: the whole workgroup leaves
+  const int64_t slice = (G + parts - 1) / parts;
+  const int64_t r0 = gr0 + part * slice;
+  const int nr = (int)(min(min(n, gr0 + G), r0 + slice) - r0);
+  if (nr <= 0) return;
+  constexpr int LPR = kPipeLPR, RPW = kWave / LPR;
+  constexpr int LCH = kPipeLE * LPR, RCH = kPipeRE * LPR;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int sub = lane & (LPR - 1);
+  const int wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
+  const int stride = nwaves * RPW;
+  const int zrow = slots * (int)G;  // the all-zero LDS row
+  const int64_t base = rp[gr0] & ~(int64_t)(kPipeLE - 1);
+  const uint16_t *lc_b = lcol + base;
+  const float *v_b = val2 + base;
+  const int32_t *c_b = col2 + base;
+  const int4 *desc = reinterpret_cast<const int4 *>(rdesc) + r0;
+
+  // this row group's first row (relative to r0) and the descriptor of its second
+  int row = wave * RPW + lane / LPR;
+  int nrow = row + stride;
+  const int4 d0 = desc[row < nr ? row : 0];
+  int4 dn = desc[nrow < nr ? nrow : 0];
+  int pl = d0.y, p1 = d0.z;
+  int qlb = d0.x & ~(kPipeLE - 1), qrb = pl & ~(kPipeRE - 1);
+  PipeStage cur;
+  pipe_load(cur, lc_b, v_b, c_b, qlb + kPipeLE * sub, qrb + kPipeRE * sub, d0.x, pl, p1);
+
+  // stage the column blocks: every load of the fill first, then the writes
+  {
+    constexpr int bytes = (int)sizeof(float) * B;
+    constexpr int piece = bytes % 16 == 0 ? 16 : bytes % 8 == 0 ? 8 : 4;
+    using P = unsigned __attribute__((ext_vector_type(piece / 4)));
+    constexpr int kMaxJ = (int)((kPlanLds / piece + 1023) / 1024);
+    const int per_slot = (int)(G * bytes / piece);
+    const int total = slots * per_slot;
+    P tmp[kMaxJ];
+    int dst[kMaxJ];
+#pragma unroll
+    for (int j = 0; j < kMaxJ; ++j) {
+      const int item = (int)threadIdx.x + j * 1024;
+      dst[j] = -1;
+      if (item < total) {
+        const int k = item / per_slot, off = item - k * per_slot;
+        const int bk = blocks[g * slots + k];
+        if (bk >= 0 && (int64_t)bk * G * bytes / piece + off < n * bytes / piece) {
+          tmp[j] = reinterpret_cast<const P *>(X + (int64_t)bk * G * B)[off];
+          dst[j] = item;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxJ; ++j)
+      if (dst[j] >= 0) reinterpret_cast<P *>(smem_raw)[dst[j]] = tmp[j];
+    if (threadIdx.x < B) reinterpret_cast<float *>(smem_raw)[(int64_t)zrow * B + threadIdx.x] = 0.0f;
+  }
+  __syncthreads();
+  if (row >= nr) return;  // no rows for this group of lanes (no barrier follows)
+
+  float acc[B];
+#pragma unroll
+  for (int a = 0; a < B; ++a) acc[a] = 0.0f;
+  // A finished row's sums, stored at the start of the following step: a store
+  // issued after the step's loads would have to complete before the next
+  // step's first wait.
+  constexpr int NO = B == 8 ? 1 : B;
+  float out[NO];
+  float *yp = nullptr;
+  // One step on the entries in `cur`, loading the following step into `nxt`;
+  // false once the group has no rows left.  The loop below alternates the two
+  // buffers so that no load result is copied between registers (a copy would
+  // wait for the load).  Per step, in issue order: the pending store, the
+  // remote gathers, the five loads of the next step and the next descriptor;
+  // the gathers are consumed last, so their wait leaves the later loads in
+  // flight.
+  auto step = [&](const PipeStage &cur, PipeStage &nxt) __attribute__((always_inline)) {
+    // everything the previous step loaded (this step's entries and the next
+    // descriptor) is needed now; waiting here, before the pending store, keeps
+    // that store out of the wait
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    // where the next step starts: the rest of this row, else the group's next row
+    const bool last = qlb + LCH >= pl && qrb + RCH >= p1;
+    const bool more = !last || nrow < nr;
+    int sp0 = 0, spl = pl, sp1 = p1, sqlb = qlb + LCH, sqrb = qrb + RCH;
+    if (last) {
+      sp0 = dn.x;
+      spl = dn.y;
+      sp1 = dn.z;
+      sqlb = dn.x & ~(kPipeLE - 1);
+      sqrb = dn.y & ~(kPipeRE - 1);
+    }
+    if (!more) sp0 = spl = sp1 = sqlb = sqrb = 0;  // nothing left: empty ranges
+    if (yp) {
+      if constexpr (B == 8) {
+        if ((sub & 1) == 0) yp[sub >> 1] = out[0];
+      } else {
+#pragma unroll
+        for (int a = 0; a < B; ++a)
+          if (a % LPR == sub) yp[a] = out[a];
+      }
+      yp = nullptr;
+    }
+    // remote gathers of this step
+    float rx[kPipeRE][B];
+#pragma unroll
+    for (int e = 0; e < kPipeRE; ++e) {
+#pragma unroll
+      for (int a = 0; a < B; ++a) rx[e][a] = 0.0f;
+      if (cur.rlo <= e && e < cur.rhi) RowIO<float, B>::load(X + (int64_t)cur.rc[e] * B, rx[e]);
+    }
+    pipe_load(nxt, lc_b, v_b, c_b, sqlb + kPipeLE * sub, sqrb + kPipeRE * sub, sp0, spl, sp1);
+    // the descriptor of the row after the one the next step works on
+    {
+      const int r = last ? nrow + stride : nrow;
+      dn = desc[r < nr ? r : 0];
+    }
+    // staged entries, four LDS rows at a time
+#pragma unroll
+    for (int hf = 0; hf < kPipeLE; hf += 4) {
+      float lx[4][B];
+      float h[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const bool ok = cur.llo <= hf + e && hf + e < cur.lhi;
+        const int idx = ok ? pipe_lidx(cur.lc, hf + e) : zrow;
+        h[e] = ok ? cur.lv[hf + e] : 0.0f;
+        RowIO<float, B>::load(sX + idx * B, lx[e]);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int a = 0; a < B; ++a) acc[a] = fmaf(h[e], lx[e][a], acc[a]);
+    }
+#pragma unroll
+    for (int e = 0; e < kPipeRE; ++e) {
+      const float h = (cur.rlo <= e && e < cur.rhi) ? cur.rv[e] : 0.0f;
+#pragma unroll
+      for (int a = 0; a < B; ++a) acc[a] = fmaf(h, rx[e][a], acc[a]);
+    }
+    if (last) {
+      yp = Y + (r0 + row) * B;
+      if constexpr (B == 8) {
+        // halving exchange: afterwards lanes sub and sub ^ 1 hold component sub >> 1
+        const bool h8 = sub & 8, h4 = sub & 4, h2 = sub & 2;
+        float k4[4], k2[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float send = h8 ? acc[i] : acc[i + 4];
+          const float keep = h8 ? acc[i + 4] : acc[i];
+          k4[i] = keep + __shfl_xor(send, 8, LPR);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const float send = h4 ? k4[i] : k4[i + 2];
+          const float keep = h4 ? k4[i + 2] : k4[i];
+          k2[i] = keep + __shfl_xor(send, 4, LPR);
+        }
+        const float send = h2 ? k2[0] : k2[1];
+        float k1 = (h2 ? k2[1] : k2[0]) + __shfl_xor(send, 2, LPR);
+        out[0] = k1 + __shfl_xor(k1, 1, LPR);
+      } else {
+#pragma unroll
+        for (int off = LPR / 2; off > 0; off >>= 1) {
+#pragma unroll
+          for (int a = 0; a < B; ++a) acc[a] += __shfl_xor(acc[a], off, LPR);
+        }
+#pragma unroll
+        for (int a = 0; a < B; ++a) out[a] = acc[a];
+      }
+#pragma unroll
+      for (int a = 0; a < B; ++a) acc[a] = 0.0f;
+      row = nrow;
+      nrow += stride;
+    }
+    pl = spl;
+    p1 = sp1;
+    qlb = sqlb;
+    qrb = sqrb;
+    return more;
+  };
+  PipeStage alt;
+  while (step(cur, alt) && step(alt, cur)) {
+  }
+  // the last row's sums
+  if constexpr (B == 8) {
+    if ((sub & 1) == 0) yp[sub >> 1] = out[0];
+  } else {
+#pragma unroll
+    for (int a = 0; a < B; ++a)
+      if (a % LPR == sub) yp[a] = out[a];
+  }
+}
+
 constexpr int kPlanThreads = 1024;
 constexpr int kPlanParts = 2;   // workgroups per row group
 
@@ -645,8 +922,37 @@ void planned_launch_t(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s)
   check_launch("k_spmm_planned");
 }
 
+template <int BV>
+void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, hipStream_t s) {
+  auto kern = k_spmm_planned_pipe<BV>;
+  const size_t lds = ((size_t)P.slots * P.block_rows + 1) * BV * sizeof(float);
+  static bool attr_set = false;
+  if (!attr_set) {
+    BBL_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPlanLds));
+    attr_set = true;
+  }
+  const int parts = (int)std::min<int64_t>(kPlanParts, ceil_div(P.block_rows, 64));
+  const int64_t groups = ceil_div(P.n, P.block_rows);
+  const int64_t grid = ceil_div(groups * parts, kXcds) * kXcds;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPlanThreads), lds, s, P.n,
+                     (int64_t)P.block_rows, P.slots, parts, P.row_ptr, P.col,
+                     static_cast<const float *>(P.val), P.lcol, P.rdesc, P.blocks, X, Y);
+  check_launch("k_spmm_planned_pipe");
+}
+
 template <typename VT, typename XT, int BV>
 void planned_launch(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s) {
+  if constexpr (std::is_same<VT, float>::value && std::is_same<XT, float>::value &&
+                (BV == 4 || BV == 8)) {
+    // the pipelined kernel also keeps one all-zero row of V in LDS and takes
+    // 32-bit entry offsets
+    if (P.local16 && P.lcol && P.rdesc &&
+        ((size_t)P.slots * P.block_rows + 1) * BV * sizeof(float) <= kPlanLds) {
+      planned_launch_pipe<BV>(P, X, Y, s);
+      return;
+    }
+  }
   if (P.local16 && P.lcol) planned_launch_t<VT, XT, BV, true>(P, X, Y, s);
   else planned_launch_t<VT, XT, BV, false>(P, X, Y, s);
 }
@@ -753,15 +1059,19 @@ bool plan_local16(const bbl_csr &H, int slots) {
   return (int64_t)slots * H.block_rows <= 65536;
 }
 
+// per-row 32-bit entry offsets from the group's first entry
+bool plan_desc(const bbl_csr &H) { return H.nnz < ((int64_t)1 << 31) - 64; }
+
 size_t spmm_plan_bytes(const bbl_csr &H, int nvec, int vec_dtype) {
   const int slots = spmm_plan_slots(H, nvec, vec_dtype);
   if (slots < 1) return 0;
   const int64_t groups = ceil_div(H.n, H.block_rows);
   const size_t sv = H.val_dtype == BBL_F32 ? 4 : 8;
-  // index and value arrays padded by 4 entries for the chunk loads
+  // index and value arrays padded by 8 entries for the chunk loads
   return align_up((size_t)groups * slots * 4) + align_up((size_t)H.n * 4) +
-         align_up((size_t)(H.nnz + 4) * 4) + align_up((size_t)(H.nnz + 4) * sv) +
-         (plan_local16(H, slots) ? align_up((size_t)(H.nnz + 4) * 2) : 0) + 256;
+         align_up((size_t)(H.nnz + 8) * 4) + align_up((size_t)(H.nnz + 8) * sv) +
+         (plan_local16(H, slots) ? align_up((size_t)(H.nnz + 8) * 2) : 0) +
+         (plan_desc(H) ? align_up((size_t)H.n * 16) : 0) + 256;
 }
 
 void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_t bytes,
@@ -782,10 +1092,11 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
   };
   int32_t *blocks = reinterpret_cast<int32_t *>(take((size_t)groups * slots * 4));
   int32_t *n_local = reinterpret_cast<int32_t *>(take((size_t)H.n * 4));
-  int32_t *col2 = reinterpret_cast<int32_t *>(take((size_t)(H.nnz + 4) * 4));
-  void *val2 = take((size_t)(H.nnz + 4) * sv);
+  int32_t *col2 = reinterpret_cast<int32_t *>(take((size_t)(H.nnz + 8) * 4));
+  void *val2 = take((size_t)(H.nnz + 8) * sv);
   const bool l16 = plan_local16(H, slots);
-  uint16_t *lcol = l16 ? reinterpret_cast<uint16_t *>(take((size_t)(H.nnz + 4) * 2)) : nullptr;
+  uint16_t *lcol = l16 ? reinterpret_cast<uint16_t *>(take((size_t)(H.nnz + 8) * 2)) : nullptr;
+  int32_t *rdesc = plan_desc(H) ? reinterpret_cast<int32_t *>(take((size_t)H.n * 16)) : nullptr;
   hipLaunchKernelGGL(k_plan_blocks, dim3((unsigned)groups), dim3(256), 0, s, H.n,
                      (int64_t)H.block_rows, slots, H.row_ptr, H.col, blocks);
   const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(H.n, 4));
@@ -793,12 +1104,12 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
     hipLaunchKernelGGL((k_plan_rows<float>), dim3(grid), dim3(256), 0, s, H.n,
                        (int64_t)H.block_rows, slots, H.row_ptr, H.col,
                        static_cast<const float *>(H.val), blocks, n_local, col2,
-                       static_cast<float *>(val2), lcol);
+                       static_cast<float *>(val2), lcol, rdesc);
   else
     hipLaunchKernelGGL((k_plan_rows<double>), dim3(grid), dim3(256), 0, s, H.n,
                        (int64_t)H.block_rows, slots, H.row_ptr, H.col,
                        static_cast<const double *>(H.val), blocks, n_local, col2,
-                       static_cast<double *>(val2), lcol);
+                       static_cast<double *>(val2), lcol, rdesc);
   check_launch("spmm plan");
   P->n = H.n;
   P->nnz = H.nnz;
@@ -814,6 +1125,7 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
   P->col = col2;
   P->val = val2;
   P->lcol = lcol;
+  P->rdesc = rdesc;
 }
 
 void launch_spmm_planned(const bbl_spmm_plan &P, const void *X, void *Y, hipStream_t s) {

@@ -75,18 +75,22 @@ def test_spmm_matches_oracle_within_dot_product_bound(torch, bbl, nvec, prec):
     assert np.all(np.abs(W - ref) <= bound), np.max(np.abs(W - ref) / bound)
 
 
-@pytest.mark.parametrize("nvec,block_rows,prec", [(8, 400, "f32"), (8, 400, "f64"), (1, 400, "f32"),
-                                                   (4, 333, "f32"), (10, 400, "f32"),
-                                                   (16, 400, "f32"), (2, 400, "f64"),
-                                                   (16, 400, "f64"), (8, 3000, "f32"),
-                                                   (1, 25000, "f32")])
-def test_planned_spmm_matches_oracle(torch, bbl, nvec, block_rows, prec):
+@pytest.mark.parametrize("nvec,block_rows,prec,q,p", [
+    (8, 400, "f32", 20, 0.7), (8, 400, "f64", 20, 0.7), (1, 400, "f32", 20, 0.7),
+    (4, 333, "f32", 20, 0.7), (10, 400, "f32", 20, 0.7), (16, 400, "f32", 20, 0.7),
+    (2, 400, "f64", 20, 0.7), (16, 400, "f64", 20, 0.7), (8, 3000, "f32", 20, 0.7),
+    (1, 25000, "f32", 20, 0.7),
+    # long rows (~285 entries: several steps of staged entries per row) and
+    # rows with most entries outside the staged blocks (several remote steps)
+    (8, 400, "f32", 150, 0.7), (8, 400, "f32", 150, 0.1), (4, 400, "f32", 150, 0.3),
+    (8, 1000, "f32", 105, 0.7)])
+def test_planned_spmm_matches_oracle(torch, bbl, nvec, block_rows, prec, q, p):
     """Rows reordered per group, partner blocks staged in LDS: the same sums
     in another order, so the dot-product bound holds entry by entry (groups
     of 333 rows straddle the generator's 400-row sectors; 3000-row groups
     leave a ragged last group; 25000 rows make one group larger than n)."""
-    note("planned spmm block_rows=%d nvec=%d %s" % (block_rows, nvec, prec))
-    H = synthgen.generate(20000, 400, 20, 0.7, 11)
+    note("planned spmm block_rows=%d nvec=%d %s q=%d p=%.1f" % (block_rows, nvec, prec, q, p))
+    H = synthgen.generate(20000, 400 if block_rows != 1000 else 1000, q, p, 11)
     dt = "float32" if prec == "f32" else "float64"
     Hd = bbl.DeviceCSR.from_host(H, dt, block_rows=block_rows)
     plan = bbl.spmm_plan(Hd, nvec)
@@ -131,10 +135,46 @@ def test_spmm_plan_layout_and_errors(torch, bbl):
     assert staged.sum() == nl.sum()
     assert np.array_equal(lcol[staged].astype(np.int64), col2[staged].astype(np.int64))
     assert np.all(col2[staged] < plan.slots * 400)
+    # per-row descriptors: first entry, first remote entry, end, relative to
+    # the row group's first entry rounded down to a multiple of 8
+    od = plan.c.rdesc - plan.mem.data_ptr()
+    d = plan.mem[od:od + 16 * H.n].view(torch.int32).cpu().numpy().reshape(-1, 4).astype(np.int64)
+    rp = np.asarray(H.row_ptr)
+    gb = rp[(np.arange(H.n) // 400) * 400] & ~7
+    assert np.array_equal(d[:, 0], rp[:-1] - gb)
+    assert np.array_equal(d[:, 1], rp[:-1] + nl - gb)
+    assert np.array_equal(d[:, 2], rp[1:] - gb)
     with pytest.raises(bbl.BblError):
         bbl.spmm_plan(bbl.DeviceCSR.from_host(H, "float32"), 8)          # no hint
     with pytest.raises(bbl.BblError):
         bbl.spmm_plan(Hd, 3)                                             # no kernel width 3
+
+
+def test_planned_spmm_ignores_rows_of_v_it_does_not_use(torch, bbl):
+    """Lanes without an entry of their own must not pick up values of V: with
+    an infinite row of V, exactly the rows of H that reference it are not
+    finite, and every other row keeps its dot-product bound."""
+    note("planned spmm with an infinite row of V")
+    H = synthgen.generate(20000, 400, 60, 0.7, 12)
+    Hd = bbl.DeviceCSR.from_host(H, "float32", block_rows=400)
+    plan = bbl.spmm_plan(Hd, 8)
+    V = synthgen.gaussian_block(H.n, 8, 6).astype(np.float32)
+    bad = [0, 401, 19999]
+    V[bad] = np.inf
+    W = bbl.spmm_planned(plan, dev(torch, V)).double().cpu().numpy()
+    rows = np.repeat(np.arange(H.n), np.diff(H.row_ptr))
+    touched = np.zeros(H.n, bool)
+    touched[rows[np.isin(np.asarray(H.col), bad)]] = True
+    assert touched.sum() > 0 and (~touched).sum() > 0
+    assert not np.any(np.isfinite(W[touched]).all(axis=1))
+    ok = ~touched
+    assert np.all(np.isfinite(W[ok]))
+    Vr = V.astype(np.float64)
+    Vr[bad] = 0.0
+    Href = H.as_float32_values()
+    z = np.diff(H.row_ptr)[:, None]
+    bound = gamma(z + 2, U32) * oracle.spmm_abs(Href, Vr) + 1e-300
+    assert np.all((np.abs(W - oracle.spmm(Href, Vr)) <= bound)[ok])
 
 
 def test_spmm_ragged_rows_and_empty_rows(torch, bbl):
