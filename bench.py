@@ -141,8 +141,9 @@ def write_traffic(fetch_dir, write_dir):
     w = synthgen.WORKLOADS[WORKLOAD]
     H = load_matrix(w)
     alg = spmm_bytes(H.n, H.nnz, w.nvec, 4, 4)
-    rec = {"kernel": "k_spmm_planned (float32 values and vectors, 8 vectors, sectors of 1000 "
-                     "rows, partner blocks staged in LDS)", "workload": WORKLOAD,
+    rec = {"kernel": "k_spmm_planned_pipe<8> (float32 values and vectors, 8 vectors, sectors "
+                     "of 1000 rows, partner blocks staged in LDS, software-pipelined)",
+           "workload": WORKLOAD,
            "spmm_source_hash": source_hash("spmm.hip"),
            "fetch_kib_per_launch": f_spmm, "write_kib_per_launch": w_spmm,
            "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
@@ -506,7 +507,7 @@ def main():
                    "n_trunc": w.n_trunc, "m_max": w.m_max, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK,
-                     "traffic": traffic, "kernel": "k_spmm_planned<float,float,float,float,8,16,true>",
+                     "traffic": traffic, "kernel": "k_spmm_planned_pipe<8>",
                      "alg_bytes_per_launch": alg, "launch_ms": t_live * 1e3},
         "cpu_baseline": cpu,
         "details": extra,

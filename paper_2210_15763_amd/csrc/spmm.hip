@@ -674,12 +674,33 @@ __device__ __forceinline__ void pipe_load(PipeStage &st, const uint16_t *__restr
   const uint4 b = reinterpret_cast<const uint4 *>(val2 + lq)[1];
   __builtin_memcpy(st.lv, &a, 16);
   __builtin_memcpy(st.lv + 4, &b, 16);
-  const uint2 c = *reinterpret_cast<const uint2 *>(col2 + rq);
-  const float2 v = *reinterpret_cast<const float2 *>(val2 + rq);
-  st.rc[0] = (int)c.x;
-  st.rc[1] = (int)c.y;
-  st.rv[0] = v.x;
-  st.rv[1] = v.y;
+  if constexpr (kPipeRE == 2) {
+    const uint2 c = *reinterpret_cast<const uint2 *>(col2 + rq);
+    const float2 v = *reinterpret_cast<const float2 *>(val2 + rq);
+    __builtin_memcpy(st.rc, &c, 8);
+    __builtin_memcpy(st.rv, &v, 8);
+  } else {
+    const uint4 c = *reinterpret_cast<const uint4 *>(col2 + rq);
+    const float4 v = *reinterpret_cast<const float4 *>(val2 + rq);
+    __builtin_memcpy(st.rc, &c, 16);
+    __builtin_memcpy(st.rv, &v, 16);
+  }
+}
+
+// Row loads of the pipelined kernel.  For B = 8 odd lanes keep their sums
+// rotated by four components (v[a] holds component (a + 4) % 8): the first
+// 16-byte half they read is the row's second, so the lanes of one LDS read
+// spread over twice as many bank positions.  The row reduction undoes it.
+template <int B>
+__device__ __forceinline__ void pipe_row(const float *p, int par, float (&v)[B]) {
+  if constexpr (B == 8) {
+    const float4 a = *reinterpret_cast<const float4 *>(p + 4 * par);
+    const float4 b = *reinterpret_cast<const float4 *>(p + 4 - 4 * par);
+    __builtin_memcpy(v, &a, 16);
+    __builtin_memcpy(v + 4, &b, 16);
+  } else {
+    RowIO<float, B>::load(p, v);
+  }
 }
 
 __device__ __forceinline__ int pipe_lidx(const uint4 &c, int e) {
@@ -717,6 +738,7 @@ __global__ __launch_bounds__(1024) void k_spmm_planned_pipe(int64_t n, int64_t G
   const int wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
   const int stride = nwaves * RPW;
   const int zrow = slots * (int)G;  // the all-zero LDS row
+  const int par = B == 8 ? (sub & 1) : 0;
   const int64_t base = rp[gr0] & ~(int64_t)(kPipeLE - 1);
   const uint16_t *lc_b = lcol + base;
   const float *v_b = val2 + base;
@@ -813,7 +835,7 @@ __global__ __launch_bounds__(1024) void k_spmm_planned_pipe(int64_t n, int64_t G
     for (int e = 0; e < kPipeRE; ++e) {
 #pragma unroll
       for (int a = 0; a < B; ++a) rx[e][a] = 0.0f;
-      if (cur.rlo <= e && e < cur.rhi) RowIO<float, B>::load(X + (int64_t)cur.rc[e] * B, rx[e]);
+      if (cur.rlo <= e && e < cur.rhi) pipe_row<B>(X + (int64_t)cur.rc[e] * B, par, rx[e]);
     }
     pipe_load(nxt, lc_b, v_b, c_b, sqlb + kPipeLE * sub, sqrb + kPipeRE * sub, sp0, spl, sp1);
     // the descriptor of the row after the one the next step works on
@@ -831,7 +853,7 @@ __global__ __launch_bounds__(1024) void k_spmm_planned_pipe(int64_t n, int64_t G
         const bool ok = cur.llo <= hf + e && hf + e < cur.lhi;
         const int idx = ok ? pipe_lidx(cur.lc, hf + e) : zrow;
         h[e] = ok ? cur.lv[hf + e] : 0.0f;
-        RowIO<float, B>::load(sX + idx * B, lx[e]);
+        pipe_row<B>(sX + idx * B, par, lx[e]);
       }
 #pragma unroll
       for (int e = 0; e < 4; ++e)
@@ -847,7 +869,8 @@ __global__ __launch_bounds__(1024) void k_spmm_planned_pipe(int64_t n, int64_t G
     if (last) {
       yp = Y + (r0 + row) * B;
       if constexpr (B == 8) {
-        // halving exchange: afterwards lanes sub and sub ^ 1 hold component sub >> 1
+        // halving exchange between lanes of equal parity: afterwards lane sub
+        // holds (rotated) component (sub >> 1) & 7
         const bool h8 = sub & 8, h4 = sub & 4, h2 = sub & 2;
         float k4[4], k2[2];
 #pragma unroll
@@ -864,7 +887,8 @@ __global__ __launch_bounds__(1024) void k_spmm_planned_pipe(int64_t n, int64_t G
         }
         const float send = h2 ? k2[0] : k2[1];
         float k1 = (h2 ? k2[1] : k2[0]) + __shfl_xor(send, 2, LPR);
-        out[0] = k1 + __shfl_xor(k1, 1, LPR);
+        // even lane sub and odd lane sub ^ 9 now hold the same component
+        out[0] = k1 + __shfl_xor(k1, 9, LPR);
       } else {
 #pragma unroll
         for (int off = LPR / 2; off > 0; off >>= 1) {
