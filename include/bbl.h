@@ -67,13 +67,16 @@ typedef struct {
  * recurrence (built by bbl_spmm_plan_build; all pointers are device memory
  * inside the caller's plan buffer, except row_ptr, which is H's).  For every
  * aligned row group the plan names up to five column blocks of block_rows
- * columns -- the group's own and the partner blocks holding most of its
- * other entries -- and every row's entries are reordered: entries inside
+ * columns (set A) -- the group's own and the partner blocks holding most of
+ * its other entries -- and every row's entries are reordered: entries inside
  * those blocks first, stored as an LDS row index slot*block_rows + offset,
  * then the others with their global column.  When every LDS row index fits
- * in 16 bits the plan also keeps them as uint16 (lcol), which the planned
- * SpMM streams instead of the 32-bit ones.  The planned SpMM stages the
- * blocks' rows of V in LDS once per group.  The same sums are formed in a
+ * in 16 bits and nnz < 2^31 the plan also names the next five busiest blocks
+ * (set B), places each row's set-B entries right after its set-A entries,
+ * keeps the LDS index of set-A and set-B entries within their set as uint16
+ * (lcol) and per-row entry ranges (rdesc); the FP32 planned SpMM then runs in
+ * two passes, set A and then set B (plus the remaining entries, gathered),
+ * each set staged in LDS once per group.  The same sums are formed in a
  * different order, so results agree with bbl_spmm to rounding, not bitwise. */
 typedef struct {
   int64_t n, nnz;
@@ -84,16 +87,18 @@ typedef struct {
   int32_t val_dtype;      /* matrix value type */
   int32_t local16;        /* 1 if lcol is present (slots*block_rows <= 65536) */
   const int64_t *row_ptr; /* H.row_ptr (not copied; H must outlive the plan) */
-  const int32_t *blocks;  /* [groups][slots] staged block ids, -1 = none */
+  const int32_t *blocks;  /* [groups][slots] staged block ids (set A), or
+                             [groups][2 slots] (set A, then set B) when lcol
+                             and rdesc are present; -1 = none */
   const int32_t *n_local; /* [n] entries of the row inside staged blocks */
   const int32_t *col;     /* [nnz] reordered column / LDS row indices */
   const void *val;        /* [nnz] reordered values */
-  const uint16_t *lcol;   /* [nnz] LDS row index of the staged entries (their
-                             positions in col; others unspecified), or NULL */
-  const int32_t *rdesc;   /* [n][4] per row: first entry, first remote entry and
-                             end, as offsets from the group's first entry rounded
-                             down to a multiple of 8 (valid when nnz < 2^31); 4th
-                             unused */
+  const uint16_t *lcol;   /* [nnz] LDS row index within its set of every set-A
+                             and set-B entry (others unspecified), or NULL */
+  const int32_t *rdesc;   /* [n][4] per row: first entry, first set-B entry,
+                             first remaining entry and end, as offsets from the
+                             group's first entry rounded down to a multiple of 8;
+                             present with lcol when nnz < 2^31, else NULL */
 } bbl_spmm_plan;
 
 /* Solver options; a NULL pointer selects the defaults shown. */

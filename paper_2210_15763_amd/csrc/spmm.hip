@@ -371,9 +371,10 @@ constexpr int kPlanHash = 1024;
 
 
 
-// blocks[g][0] = g; blocks[g][1..slots) = the other column blocks with the
-// most entries in group g (ties to the smaller block id), -1 when fewer exist
-__global__ __launch_bounds__(256) void k_plan_blocks(int64_t n, int64_t G, int slots,
+// blocks[g][0] = g; blocks[g][1..width) = the other column blocks with the
+// most entries in group g, busiest first (ties to the smaller block id), -1
+// when fewer exist
+__global__ __launch_bounds__(256) void k_plan_blocks(int64_t n, int64_t G, int width,
                                                      const int64_t *__restrict__ rp,
                                                      const int32_t *__restrict__ col,
                                                      int32_t *__restrict__ blocks) {
@@ -402,8 +403,8 @@ __global__ __launch_bounds__(256) void k_plan_blocks(int64_t n, int64_t G, int s
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    blocks[g * slots] = (int32_t)g;
-    for (int sl = 1; sl < slots; ++sl) {
+    blocks[g * width] = (int32_t)g;
+    for (int sl = 1; sl < width; ++sl) {
       int best = -1, bi = -1, bc = 0;
       for (int i = 0; i < kPlanHash; ++i) {
         const int k = keys[i], c = cnts[i];
@@ -415,16 +416,21 @@ __global__ __launch_bounds__(256) void k_plan_blocks(int64_t n, int64_t G, int s
         }
       }
       if (bi >= 0) cnts[bi] = 0;
-      blocks[g * slots + sl] = best;
+      blocks[g * width + sl] = best;
     }
   }
 }
 
-// Reorders every row (one wave per row): entries in a staged block first, in
-// their original order, as slot*G + offset; the others after them with their
-// global column, in their original order; n_local = count of the first kind.
+// Reorders every row (one wave per row), each kind in the original order:
+// entries in a set-A block (blocks[g][0..slots)) first, as slot*G + offset;
+// then entries in a set-B block (blocks[g][slots..width), present when width
+// = 2 slots) and then the rest, both with their global column in col2.
+// n_local = count of the first kind.  lcol (if present) holds the LDS index
+// of set-A and set-B entries within their set (slot*G + offset); rdesc (if
+// present) the row's {first entry, first set-B entry, first remote entry,
+// end} as offsets from its group's first entry rounded down to a multiple of 8.
 template <typename VT>
-__global__ __launch_bounds__(256) void k_plan_rows(int64_t n, int64_t G, int slots,
+__global__ __launch_bounds__(256) void k_plan_rows(int64_t n, int64_t G, int slots, int width,
                                                    const int64_t *__restrict__ rp,
                                                    const int32_t *__restrict__ col,
                                                    const VT *__restrict__ val,
@@ -438,60 +444,69 @@ __global__ __launch_bounds__(256) void k_plan_rows(int64_t n, int64_t G, int slo
   if (row >= n) return;  // uniform per wave
   const int lane = threadIdx.x & 63;
   const int64_t g = row / G;
-  int64_t base[kPlanMaxSlots];
+  int64_t base[2 * kPlanMaxSlots];
 #pragma unroll
-  for (int k = 0; k < kPlanMaxSlots; ++k) {
-    const int b = k < slots ? blocks[g * slots + k] : -1;
+  for (int k = 0; k < 2 * kPlanMaxSlots; ++k) {
+    const int b = k < width ? blocks[g * width + k] : -1;
     base[k] = b >= 0 ? (int64_t)b * G : -((int64_t)1 << 62);
   }
-  auto local_index = [&](int32_t c) {
-    int loc = -1;
+  // kind (0: set A, 1: set B, 2: remote) and LDS index within the set
+  auto classify = [&](int32_t c, int &loc) {
+    int kind = 2;
+    loc = -1;
 #pragma unroll
-    for (int k = kPlanMaxSlots - 1; k >= 0; --k) {
+    for (int k = 2 * kPlanMaxSlots - 1; k >= 0; --k) {
       const int64_t o = (int64_t)c - base[k];
-      if (o >= 0 && o < G) loc = (int)(k * G + o);
+      if (o >= 0 && o < G) {
+        kind = k < slots ? 0 : 1;
+        loc = (int)((k < slots ? k : k - slots) * G + o);
+      }
     }
-    return loc;
+    return kind;
   };
   const int64_t p0 = rp[row], p1 = rp[row + 1];
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  int nl = 0;
+  int na = 0, nb = 0;
   for (int64_t p = p0 + lane; p - lane < p1; p += 64) {
-    const bool isl = p < p1 && local_index(col[p]) >= 0;
-    nl += __popcll(__ballot(isl));
+    int loc;
+    const int kind = p < p1 ? classify(col[p], loc) : 3;
+    na += __popcll(__ballot(kind == 0));
+    nb += __popcll(__ballot(kind == 1));
   }
-  int il = 0, ir = 0;
+  int ia = 0, ib = 0, ir = 0;
   for (int64_t p = p0 + lane; p - lane < p1; p += 64) {
     const bool in = p < p1;
     const int32_t c = in ? col[p] : 0;
-    const int loc = in ? local_index(c) : -1;
-    const bool isl = in && loc >= 0;
-    const uint64_t ml = __ballot(isl), mr = __ballot(in && !isl);
-    if (isl) {
-      const int64_t q = p0 + il + __popcll(ml & below);
-      col2[q] = loc;
+    int loc = -1;
+    const int kind = in ? classify(c, loc) : 3;
+    const uint64_t ma = __ballot(kind == 0), mb = __ballot(kind == 1), mr = __ballot(kind == 2);
+    int64_t q = -1;
+    if (kind == 0) q = p0 + ia + __popcll(ma & below);
+    else if (kind == 1) q = p0 + na + ib + __popcll(mb & below);
+    else if (kind == 2) q = p0 + na + nb + ir + __popcll(mr & below);
+    if (q >= 0) {
+      col2[q] = kind == 0 ? loc : c;
       val2[q] = val[p];
-      if (lcol) lcol[q] = (uint16_t)loc;
-    } else if (in) {
-      const int64_t q = p0 + nl + ir + __popcll(mr & below);
-      col2[q] = c;
-      val2[q] = val[p];
+      if (lcol && kind < 2) lcol[q] = (uint16_t)loc;
     }
-    il += __popcll(ml);
+    ia += __popcll(ma);
+    ib += __popcll(mb);
     ir += __popcll(mr);
   }
   if (lane == 0) {
-    n_local[row] = nl;
+    n_local[row] = na;
     if (rdesc) {
       const int64_t gb = rp[g * G] & ~(int64_t)7;
-      const int4 d = make_int4((int)(p0 - gb), (int)(p0 + nl - gb), (int)(p1 - gb), 0);
+      const int4 d = make_int4((int)(p0 - gb), (int)(p0 + na - gb), (int)(p0 + na + nb - gb),
+                               (int)(p1 - gb));
       *reinterpret_cast<int4 *>(rdesc + 4 * row) = d;
     }
   }
 }
 
 template <typename VT, typename XT, typename AT, typename YT, int B, int LPR, bool LC16>
-__global__ __launch_bounds__(1024) void k_spmm_planned(int64_t n, int64_t G, int slots, int parts,
+__global__ __launch_bounds__(1024) void k_spmm_planned(int64_t n, int64_t G, int slots, int width,
+                                                       int parts,
                                                        const int64_t *__restrict__ rp,
                                                        const int32_t *__restrict__ n_local,
                                                        const int32_t *__restrict__ col2,
@@ -514,7 +529,7 @@ __global__ __launch_bounds__(1024) void k_spmm_planned(int64_t n, int64_t G, int
   const int64_t r1 = min(min(n, gr0 + G), r0 + slice);
   if (r0 >= r1) return;
   for (int k = 0; k < slots; ++k) {
-    const int b = blocks[g * slots + k];
+    const int b = blocks[g * width + k];
     if (b < 0) continue;
     const int64_t b0 = (int64_t)b * G, b1 = min(n, b0 + G);
     constexpr int bytes = (int)sizeof(XT) * B;
@@ -631,66 +646,89 @@ __global__ __launch_bounds__(1024) void k_spmm_planned(int64_t n, int64_t G, int
   }
 }
 
-// Software-pipelined variant for FP32 plans with 16-bit staged indices.
-// Each 16-lane row group walks its rows in steps of 128 staged entries (eight
-// per lane: one 16-byte load of indices, two of values) and 32 remote entries
-// (two per lane); the index and value loads of the following step -- of the
-// next row when this one ends -- are issued before this step's LDS reads and
-// FMAs, so one step of the CSR stream is always in flight behind the
-// arithmetic.  Entries outside a lane's part of the row read an all-zero LDS
-// row kept after the staged blocks with a zero weight, so the LDS reads carry
-// no branches.
+// Two-pass planned SpMM for FP32 plans with 16-bit LDS indices and row
+// descriptors.  The plan names two sets of column blocks per row group: set
+// A (the group's own block and its busiest partners) and set B (the next
+// busiest), and orders every row's entries: set A, set B, then the rest
+// ("remote").  Pass 1 stages set A in LDS and streams each row's set-A
+// entries, writing the row sums; pass 2 stages set B, streams the set-B
+// entries, gathers the few remote rows of V from global memory and adds its
+// sums to pass 1's.  On sectored matrices the two sets hold nearly every
+// entry, so rows of V are read from LDS rather than gathered one by one
+// through the vector caches.
+//
+// Both passes run the same software pipeline.  LPR lanes share a row and
+// walk it in steps of 8 * LPR staged entries (eight per lane: one 16-byte
+// load of indices, two of values) and, in pass 2, 2 * LPR remote entries;
+// the loads of the following step -- of the group's next row when this one
+// ends -- are issued before this step's LDS reads and FMAs, so one step of
+// the CSR stream is always in flight behind the arithmetic.  Entries outside
+// a lane's part of the row read an all-zero LDS row kept after the staged
+// blocks, with a zero weight, so the LDS reads carry no branches.
 constexpr int kPipeLE = 8;    // staged entries per lane and step
-constexpr int kPipeRE = 2;    // remote entries per lane and step
-constexpr int kPipeLPR = 16;  // lanes per row
+constexpr int kPipeRE = 2;    // remote entries per lane and step (pass 2)
 
+template <int B, int LPR, bool P2>
 struct PipeStage {
-  uint4 lc;                  // eight 16-bit LDS row indices
+  static constexpr int NO = B / LPR > 0 ? B / LPR : 1;  // sums per lane after the reduction
+  uint4 lc;                     // eight 16-bit LDS row indices
   float lv[kPipeLE];
-  int rc[kPipeRE];
-  float rv[kPipeRE];
-  int llo, lhi, rlo, rhi;    // valid entries e: llo <= e < lhi (staged), rlo <= e < rhi (remote)
+  int rc[P2 ? kPipeRE : 1];
+  float rv[P2 ? kPipeRE : 1];
+  float yp[P2 ? NO : 1];        // pass 1's sums of the row (pass 2)
+  int llo, lhi, rlo, rhi;       // valid entries e: llo <= e < lhi (staged), rlo <= e < rhi (remote)
 };
 
 // Loads the lane's share of one step: staged entries [ql, ql + 8) and remote
 // entries [qr, qr + 2) of a row whose staged entries are [p0, pl) and remote
-// ones [pl, p1).  Positions are relative to a base that is a multiple of 8,
-// ql a multiple of 8 and qr of 2, so the loads are aligned; the plan pads its
-// arrays by 8 entries.  Every lane issues the same five loads whether or not
-// its entries exist (those without any read position 0 and are masked by the
-// ranges), so the number of loads in flight is the same on every path.
-__device__ __forceinline__ void pipe_load(PipeStage &st, const uint16_t *__restrict__ lcol,
+// ones [pl, p1), and in pass 2 that row's pass-1 sums.  Positions are
+// relative to a base that is a multiple of 8, ql a multiple of 8 and qr of 2,
+// so the loads are aligned; the plan pads its arrays by 8 entries.  Every
+// lane issues the same loads whether or not its entries exist (those without
+// any read position 0 and are masked by the ranges), so the number of loads
+// in flight is the same on every path.
+template <int B, int LPR, bool P2>
+__device__ __forceinline__ void pipe_load(PipeStage<B, LPR, P2> &st,
+                                          const uint16_t *__restrict__ lcol,
                                           const float *__restrict__ val2,
                                           const int32_t *__restrict__ col2, int ql, int qr,
-                                          int p0, int pl, int p1) {
+                                          int p0, int pl, int p1, const float *yrow) {
   st.llo = p0 - ql;
   st.lhi = pl - ql;
-  st.rlo = pl - qr;
-  st.rhi = p1 - qr;
   const int lq = st.lhi > 0 ? ql : 0;
-  const int rq = st.rhi > 0 ? qr : 0;
   st.lc = *reinterpret_cast<const uint4 *>(lcol + lq);
   const uint4 a = reinterpret_cast<const uint4 *>(val2 + lq)[0];
   const uint4 b = reinterpret_cast<const uint4 *>(val2 + lq)[1];
   __builtin_memcpy(st.lv, &a, 16);
   __builtin_memcpy(st.lv + 4, &b, 16);
-  if constexpr (kPipeRE == 2) {
+  if constexpr (P2) {
+    st.rlo = pl - qr;
+    st.rhi = p1 - qr;
+    const int rq = st.rhi > 0 ? qr : 0;
     const uint2 c = *reinterpret_cast<const uint2 *>(col2 + rq);
     const float2 v = *reinterpret_cast<const float2 *>(val2 + rq);
     __builtin_memcpy(st.rc, &c, 8);
     __builtin_memcpy(st.rv, &v, 8);
+    constexpr int NO = PipeStage<B, LPR, P2>::NO;
+    if constexpr (NO == 2) {
+      const float2 y = *reinterpret_cast<const float2 *>(yrow);
+      st.yp[0] = y.x;
+      st.yp[1] = y.y;
+    } else {
+#pragma unroll
+      for (int i = 0; i < NO; ++i) st.yp[i] = yrow[i];
+    }
   } else {
-    const uint4 c = *reinterpret_cast<const uint4 *>(col2 + rq);
-    const float4 v = *reinterpret_cast<const float4 *>(val2 + rq);
-    __builtin_memcpy(st.rc, &c, 16);
-    __builtin_memcpy(st.rv, &v, 16);
+    st.rlo = 0;
+    st.rhi = 0;
   }
 }
 
-// Row loads of the pipelined kernel.  For B = 8 odd lanes keep their sums
-// rotated by four components (v[a] holds component (a + 4) % 8): the first
-// 16-byte half they read is the row's second, so the lanes of one LDS read
-// spread over twice as many bank positions.  The row reduction undoes it.
+// Row loads of the pipelined kernel.  With par = 1 (odd lanes of pass 1 at
+// B = 8) the lane keeps its sums rotated by four components (v[a] holds
+// component (a + 4) % 8): the first 16-byte half it reads is the row's
+// second, so the lanes of one LDS read spread over twice as many bank
+// positions.  The row reduction undoes it.
 template <int B>
 __device__ __forceinline__ void pipe_row(const float *p, int par, float (&v)[B]) {
   if constexpr (B == 8) {
@@ -708,19 +746,24 @@ __device__ __forceinline__ int pipe_lidx(const uint4 &c, int e) {
   return (int)((e & 1) ? (w >> 16) : (w & 0xffffu));
 }
 
-// Row positions come from the plan's per-row descriptors (32-bit offsets from
-// the group's first entry rounded down to a multiple of 8).
-template <int B>
-__global__ __launch_bounds__(1024) void k_spmm_planned_pipe(int64_t n, int64_t G, int slots,
-                                                            int parts,
-                                                            const int64_t *__restrict__ rp,
-                                                            const int32_t *__restrict__ col2,
-                                                            const float *__restrict__ val2,
-                                                            const uint16_t *__restrict__ lcol,
-                                                            const int32_t *__restrict__ rdesc,
-                                                            const int32_t *__restrict__ blocks,
-                                                            const float *__restrict__ X,
-                                                            float *__restrict__ Y) {
+// Pass 1 (P2 = false) or pass 2 (P2 = true) over the row groups; `blocks`
+// has `width` = 2 slots entries per group (set A, then set B).  Row positions
+// come from the plan's descriptors {first entry, first set-B entry, first
+// remote entry, end} (32-bit offsets from the group's first entry rounded
+// down to a multiple of 8).
+template <int B, int LPR, bool P2>
+__global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int slots, int parts,
+                                                    const int64_t *__restrict__ rp,
+                                                    const int32_t *__restrict__ col2,
+                                                    const float *__restrict__ val2,
+                                                    const uint16_t *__restrict__ lcol,
+                                                    const int32_t *__restrict__ rdesc,
+                                                    const int32_t *__restrict__ blocks,
+                                                    const float *__restrict__ X,
+                                                    float *__restrict__ Y) {
+  static_assert(!P2 || B >= LPR, "pass 2 keeps whole components per lane");
+  using Stage = PipeStage<B, LPR, P2>;
+  constexpr int NO = Stage::NO;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const float *sX = reinterpret_cast<const float *>(smem_raw);
   const int64_t L = xcd_block(blockIdx.x);
@@ -731,31 +774,48 @@ __global__ __launch_bounds__(1024) void k_spmm_planned_pipe(int64_t n, int64_t G
   const int64_t r0 = gr0 + part * slice;
   const int nr = (int)(min(min(n, gr0 + G), r0 + slice) - r0);
   if (nr <= 0) return;
-  constexpr int LPR = kPipeLPR, RPW = kWave / LPR;
+  constexpr int RPW = kWave / LPR;
   constexpr int LCH = kPipeLE * LPR, RCH = kPipeRE * LPR;
   const int lane = threadIdx.x & (kWave - 1);
   const int sub = lane & (LPR - 1);
   const int wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
   const int stride = nwaves * RPW;
   const int zrow = slots * (int)G;  // the all-zero LDS row
-  const int par = B == 8 ? (sub & 1) : 0;
+  const int par = (B == 8 && LPR == 16) ? (sub & 1) : 0;
+  const int cb = NO * sub;          // first of the lane's sums after the reduction (B >= LPR)
   const int64_t base = rp[gr0] & ~(int64_t)(kPipeLE - 1);
   const uint16_t *lc_b = lcol + base;
   const float *v_b = val2 + base;
   const int32_t *c_b = col2 + base;
   const int4 *desc = reinterpret_cast<const int4 *>(rdesc) + r0;
+  float *Yw = Y + r0 * B;
+  // the row's staged and remote ranges in this pass
+  auto ranges = [&](const int4 &d, int &p0, int &pl, int &p1) {
+    if constexpr (P2) {
+      p0 = d.y;
+      pl = d.z;
+      p1 = d.w;
+    } else {
+      p0 = d.x;
+      pl = d.y;
+      p1 = d.y;
+    }
+  };
+  auto yrow = [&](int r) { return Yw + (int64_t)(r < nr ? r : 0) * B + (B >= LPR ? cb : 0); };
 
   // this row group's first row (relative to r0) and the descriptor of its second
   int row = wave * RPW + lane / LPR;
   int nrow = row + stride;
   const int4 d0 = desc[row < nr ? row : 0];
   int4 dn = desc[nrow < nr ? nrow : 0];
-  int pl = d0.y, p1 = d0.z;
-  int qlb = d0.x & ~(kPipeLE - 1), qrb = pl & ~(kPipeRE - 1);
-  PipeStage cur;
-  pipe_load(cur, lc_b, v_b, c_b, qlb + kPipeLE * sub, qrb + kPipeRE * sub, d0.x, pl, p1);
+  int p0, pl, p1;
+  ranges(d0, p0, pl, p1);
+  int qlb = p0 & ~(kPipeLE - 1), qrb = pl & ~(kPipeRE - 1);
+  Stage cur;
+  pipe_load<B, LPR, P2>(cur, lc_b, v_b, c_b, qlb + kPipeLE * sub, qrb + kPipeRE * sub, p0, pl, p1,
+                        yrow(row));
 
-  // stage the column blocks: every load of the fill first, then the writes
+  // stage the set's column blocks: every load of the fill first, then the writes
   {
     constexpr int bytes = (int)sizeof(float) * B;
     constexpr int piece = bytes % 16 == 0 ? 16 : bytes % 8 == 0 ? 8 : 4;
@@ -763,6 +823,7 @@ __global__ __launch_bounds__(1024) void k_spmm_planned_pipe(int64_t n, int64_t G
     constexpr int kMaxJ = (int)((kPlanLds / piece + 1023) / 1024);
     const int per_slot = (int)(G * bytes / piece);
     const int total = slots * per_slot;
+    const int32_t *bl = blocks + g * (2 * slots) + (P2 ? slots : 0);
     P tmp[kMaxJ];
     int dst[kMaxJ];
 #pragma unroll
@@ -771,7 +832,7 @@ __global__ __launch_bounds__(1024) void k_spmm_planned_pipe(int64_t n, int64_t G
       dst[j] = -1;
       if (item < total) {
         const int k = item / per_slot, off = item - k * per_slot;
-        const int bk = blocks[g * slots + k];
+        const int bk = bl[k];
         if (bk >= 0 && (int64_t)bk * G * bytes / piece + off < n * bytes / piece) {
           tmp[j] = reinterpret_cast<const P *>(X + (int64_t)bk * G * B)[off];
           dst[j] = item;
@@ -792,83 +853,112 @@ __global__ __launch_bounds__(1024) void k_spmm_planned_pipe(int64_t n, int64_t G
   // A finished row's sums, stored at the start of the following step: a store
   // issued after the step's loads would have to complete before the next
   // step's first wait.
-  constexpr int NO = B == 8 ? 1 : B;
-  float out[NO];
+  constexpr int NOUT = (B == 8 && LPR == 16) ? 1 : (B >= LPR ? NO : B);
+  float out[NOUT];
   float *yp = nullptr;
+  auto store_out = [&]() __attribute__((always_inline)) {
+    if constexpr (B == 8 && LPR == 16) {
+      if ((sub & 1) == 0) yp[sub >> 1] = out[0];
+    } else if constexpr (B >= LPR) {
+      if constexpr (NO == 2) {
+        *reinterpret_cast<float2 *>(yp + cb) = make_float2(out[0], out[1]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < NO; ++i) yp[cb + i] = out[i];
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < B; ++a)
+        if (a % LPR == sub) yp[a] = out[a];
+    }
+  };
+  float rx[P2 ? kPipeRE : 1][B], rh[P2 ? kPipeRE : 1];  // remote rows in flight (pass 2)
+  bool rpend = false;
   // One step on the entries in `cur`, loading the following step into `nxt`;
   // false once the group has no rows left.  The loop below alternates the two
   // buffers so that no load result is copied between registers (a copy would
   // wait for the load).  Per step, in issue order: the pending store, the
-  // remote gathers, the five loads of the next step and the next descriptor;
-  // the gathers are consumed last, so their wait leaves the later loads in
-  // flight.
-  auto step = [&](const PipeStage &cur, PipeStage &nxt) __attribute__((always_inline)) {
+  // remote gathers, the loads of the next step and the next descriptor.
+  auto step = [&](const Stage &cur, Stage &nxt) __attribute__((always_inline)) {
     // everything the previous step loaded (this step's entries and the next
     // descriptor) is needed now; waiting here, before the pending store, keeps
     // that store out of the wait
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     // where the next step starts: the rest of this row, else the group's next row
-    const bool last = qlb + LCH >= pl && qrb + RCH >= p1;
+    const bool last = qlb + LCH >= pl && (!P2 || qrb + RCH >= p1);
     const bool more = !last || nrow < nr;
     int sp0 = 0, spl = pl, sp1 = p1, sqlb = qlb + LCH, sqrb = qrb + RCH;
+    int srow = row;
     if (last) {
-      sp0 = dn.x;
-      spl = dn.y;
-      sp1 = dn.z;
-      sqlb = dn.x & ~(kPipeLE - 1);
-      sqrb = dn.y & ~(kPipeRE - 1);
+      ranges(dn, sp0, spl, sp1);
+      sqlb = sp0 & ~(kPipeLE - 1);
+      sqrb = spl & ~(kPipeRE - 1);
+      srow = nrow;
     }
     if (!more) sp0 = spl = sp1 = sqlb = sqrb = 0;  // nothing left: empty ranges
     if (yp) {
-      if constexpr (B == 8) {
-        if ((sub & 1) == 0) yp[sub >> 1] = out[0];
-      } else {
-#pragma unroll
-        for (int a = 0; a < B; ++a)
-          if (a % LPR == sub) yp[a] = out[a];
-      }
+      store_out();
       yp = nullptr;
     }
-    // remote gathers of this step
-    float rx[kPipeRE][B];
+    if constexpr (P2) {
+      // remote products gathered by the previous step of this row: that
+      // step's later loads have arrived, so these have too
+      if (rpend) {
 #pragma unroll
-    for (int e = 0; e < kPipeRE; ++e) {
+        for (int e = 0; e < kPipeRE; ++e)
 #pragma unroll
-      for (int a = 0; a < B; ++a) rx[e][a] = 0.0f;
-      if (cur.rlo <= e && e < cur.rhi) pipe_row<B>(X + (int64_t)cur.rc[e] * B, par, rx[e]);
+          for (int a = 0; a < B; ++a) acc[a] = fmaf(rh[e], rx[e][a], acc[a]);
+      }
+      // remote gathers of this step, multiplied in at the start of the row's
+      // next step (or at the end of this one if it is the row's last)
+      rpend = cur.rhi > 0;
+#pragma unroll
+      for (int e = 0; e < kPipeRE; ++e) {
+        const bool ok = cur.rlo <= e && e < cur.rhi;
+        rh[e] = ok ? cur.rv[e] : 0.0f;
+#pragma unroll
+        for (int a = 0; a < B; ++a) rx[e][a] = 0.0f;
+        if (ok) pipe_row<B>(X + (int64_t)cur.rc[e] * B, par, rx[e]);
+      }
     }
-    pipe_load(nxt, lc_b, v_b, c_b, sqlb + kPipeLE * sub, sqrb + kPipeRE * sub, sp0, spl, sp1);
+    pipe_load<B, LPR, P2>(nxt, lc_b, v_b, c_b, sqlb + kPipeLE * sub, sqrb + kPipeRE * sub, sp0,
+                          spl, sp1, yrow(srow));
     // the descriptor of the row after the one the next step works on
     {
       const int r = last ? nrow + stride : nrow;
       dn = desc[r < nr ? r : 0];
     }
-    // staged entries, four LDS rows at a time
+    // staged entries, LG LDS rows at a time (fewer in pass 2, whose remote
+    // rows take registers)
+    constexpr int LG = P2 ? 2 : 4;
 #pragma unroll
-    for (int hf = 0; hf < kPipeLE; hf += 4) {
-      float lx[4][B];
-      float h[4];
+    for (int hf = 0; hf < kPipeLE; hf += LG) {
+      float lx[LG][B];
+      float h[LG];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < LG; ++e) {
         const bool ok = cur.llo <= hf + e && hf + e < cur.lhi;
         const int idx = ok ? pipe_lidx(cur.lc, hf + e) : zrow;
         h[e] = ok ? cur.lv[hf + e] : 0.0f;
         pipe_row<B>(sX + idx * B, par, lx[e]);
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+      for (int e = 0; e < LG; ++e)
 #pragma unroll
         for (int a = 0; a < B; ++a) acc[a] = fmaf(h[e], lx[e][a], acc[a]);
     }
-#pragma unroll
-    for (int e = 0; e < kPipeRE; ++e) {
-      const float h = (cur.rlo <= e && e < cur.rhi) ? cur.rv[e] : 0.0f;
-#pragma unroll
-      for (int a = 0; a < B; ++a) acc[a] = fmaf(h, rx[e][a], acc[a]);
-    }
     if (last) {
-      yp = Y + (r0 + row) * B;
-      if constexpr (B == 8) {
+      if constexpr (P2) {
+        if (rpend) {
+#pragma unroll
+          for (int e = 0; e < kPipeRE; ++e)
+#pragma unroll
+            for (int a = 0; a < B; ++a) acc[a] = fmaf(rh[e], rx[e][a], acc[a]);
+          rpend = false;
+        }
+      }
+      yp = Yw + (int64_t)row * B;
+      if constexpr (B == 8 && LPR == 16) {
         // halving exchange between lanes of equal parity: afterwards lane sub
         // holds (rotated) component (sub >> 1) & 7
         const bool h8 = sub & 8, h4 = sub & 4, h2 = sub & 2;
@@ -889,7 +979,27 @@ __global__ __launch_bounds__(1024) void k_spmm_planned_pipe(int64_t n, int64_t G
         float k1 = (h2 ? k2[1] : k2[0]) + __shfl_xor(send, 2, LPR);
         // even lane sub and odd lane sub ^ 9 now hold the same component
         out[0] = k1 + __shfl_xor(k1, 9, LPR);
+        if constexpr (P2) out[0] += cur.yp[0];
+      } else if constexpr (B >= LPR) {
+        // halving exchange: each round keeps the half of the sums selected by
+        // one bit of sub, so lane sub ends with components [NO sub, NO sub + NO)
+        float v[B];
+#pragma unroll
+        for (int a = 0; a < B; ++a) v[a] = acc[a];
+#pragma unroll
+        for (int off = LPR / 2, K = B; off > 0; off >>= 1, K >>= 1) {
+          const bool up = sub & off;
+#pragma unroll
+          for (int i = 0; i < K / 2; ++i) {
+            const float send = up ? v[i] : v[i + K / 2];
+            const float keep = up ? v[i + K / 2] : v[i];
+            v[i] = keep + __shfl_xor(send, off, LPR);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < NO; ++i) out[i] = v[i] + (P2 ? cur.yp[i] : 0.0f);
       } else {
+        static_assert(!P2, "pass 2 needs B >= LPR");
 #pragma unroll
         for (int off = LPR / 2; off > 0; off >>= 1) {
 #pragma unroll
@@ -909,21 +1019,18 @@ __global__ __launch_bounds__(1024) void k_spmm_planned_pipe(int64_t n, int64_t G
     qrb = sqrb;
     return more;
   };
-  PipeStage alt;
+  Stage alt;
   while (step(cur, alt) && step(alt, cur)) {
   }
-  // the last row's sums
-  if constexpr (B == 8) {
-    if ((sub & 1) == 0) yp[sub >> 1] = out[0];
-  } else {
-#pragma unroll
-    for (int a = 0; a < B; ++a)
-      if (a % LPR == sub) yp[a] = out[a];
-  }
+  store_out();  // the last row's sums
 }
 
 constexpr int kPlanThreads = 1024;
 constexpr int kPlanParts = 2;   // workgroups per row group
+
+// entries per group of the block table: a second set (for the two-pass
+// kernel) whenever the plan has 16-bit LDS indices and row descriptors
+int plan_width(const bbl_spmm_plan &P) { return P.lcol && P.rdesc ? 2 * P.slots : P.slots; }
 
 template <typename VT, typename XT, int BV, bool LC16>
 void planned_launch_t(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s) {
@@ -941,14 +1048,14 @@ void planned_launch_t(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s)
   const int64_t groups = ceil_div(P.n, P.block_rows);
   const int64_t grid = ceil_div(groups * parts, kXcds) * kXcds;
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPlanThreads), lds, s, P.n,
-                     (int64_t)P.block_rows, P.slots, parts, P.row_ptr, P.n_local, P.col,
-                     static_cast<const VT *>(P.val), P.lcol, P.blocks, X, Y);
+                     (int64_t)P.block_rows, P.slots, plan_width(P), parts, P.row_ptr, P.n_local,
+                     P.col, static_cast<const VT *>(P.val), P.lcol, P.blocks, X, Y);
   check_launch("k_spmm_planned");
 }
 
-template <int BV>
-void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, hipStream_t s) {
-  auto kern = k_spmm_planned_pipe<BV>;
+template <int BV, int LPR, bool P2>
+void pipe_pass(const bbl_spmm_plan &P, int parts, const float *X, float *Y, hipStream_t s) {
+  auto kern = k_spmm_pipe<BV, LPR, P2>;
   const size_t lds = ((size_t)P.slots * P.block_rows + 1) * BV * sizeof(float);
   static bool attr_set = false;
   if (!attr_set) {
@@ -956,13 +1063,21 @@ void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, hipSt
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPlanLds));
     attr_set = true;
   }
-  const int parts = (int)std::min<int64_t>(kPlanParts, ceil_div(P.block_rows, 64));
   const int64_t groups = ceil_div(P.n, P.block_rows);
   const int64_t grid = ceil_div(groups * parts, kXcds) * kXcds;
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPlanThreads), lds, s, P.n,
                      (int64_t)P.block_rows, P.slots, parts, P.row_ptr, P.col,
                      static_cast<const float *>(P.val), P.lcol, P.rdesc, P.blocks, X, Y);
-  check_launch("k_spmm_planned_pipe");
+  check_launch(P2 ? "k_spmm_pipe (pass 2)" : "k_spmm_pipe (pass 1)");
+}
+
+// Pass 1 takes most entries per row (16 lanes per row, two workgroups per
+// group); pass 2 the few left (4 lanes per row, one workgroup per group).
+template <int BV>
+void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, hipStream_t s) {
+  const int parts = (int)std::min<int64_t>(kPlanParts, ceil_div(P.block_rows, 64));
+  pipe_pass<BV, 16, false>(P, parts, X, Y, s);
+  pipe_pass<BV, 4, true>(P, 1, X, Y, s);
 }
 
 template <typename VT, typename XT, int BV>
@@ -1092,10 +1207,11 @@ size_t spmm_plan_bytes(const bbl_csr &H, int nvec, int vec_dtype) {
   const int64_t groups = ceil_div(H.n, H.block_rows);
   const size_t sv = H.val_dtype == BBL_F32 ? 4 : 8;
   // index and value arrays padded by 8 entries for the chunk loads
-  return align_up((size_t)groups * slots * 4) + align_up((size_t)H.n * 4) +
+  const int width = plan_local16(H, slots) && plan_desc(H) ? 2 * slots : slots;
+  return align_up((size_t)groups * width * 4) + align_up((size_t)H.n * 4) +
          align_up((size_t)(H.nnz + 8) * 4) + align_up((size_t)(H.nnz + 8) * sv) +
          (plan_local16(H, slots) ? align_up((size_t)(H.nnz + 8) * 2) : 0) +
-         (plan_desc(H) ? align_up((size_t)H.n * 16) : 0) + 256;
+         (plan_local16(H, slots) && plan_desc(H) ? align_up((size_t)H.n * 16) : 0) + 256;
 }
 
 void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_t bytes,
@@ -1114,24 +1230,26 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
     off += align_up(b);
     return p;
   };
-  int32_t *blocks = reinterpret_cast<int32_t *>(take((size_t)groups * slots * 4));
+  const int width = plan_local16(H, slots) && plan_desc(H) ? 2 * slots : slots;
+  int32_t *blocks = reinterpret_cast<int32_t *>(take((size_t)groups * width * 4));
   int32_t *n_local = reinterpret_cast<int32_t *>(take((size_t)H.n * 4));
   int32_t *col2 = reinterpret_cast<int32_t *>(take((size_t)(H.nnz + 8) * 4));
   void *val2 = take((size_t)(H.nnz + 8) * sv);
   const bool l16 = plan_local16(H, slots);
   uint16_t *lcol = l16 ? reinterpret_cast<uint16_t *>(take((size_t)(H.nnz + 8) * 2)) : nullptr;
-  int32_t *rdesc = plan_desc(H) ? reinterpret_cast<int32_t *>(take((size_t)H.n * 16)) : nullptr;
+  int32_t *rdesc = l16 && plan_desc(H) ? reinterpret_cast<int32_t *>(take((size_t)H.n * 16))
+                                        : nullptr;
   hipLaunchKernelGGL(k_plan_blocks, dim3((unsigned)groups), dim3(256), 0, s, H.n,
-                     (int64_t)H.block_rows, slots, H.row_ptr, H.col, blocks);
+                     (int64_t)H.block_rows, width, H.row_ptr, H.col, blocks);
   const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(H.n, 4));
   if (H.val_dtype == BBL_F32)
     hipLaunchKernelGGL((k_plan_rows<float>), dim3(grid), dim3(256), 0, s, H.n,
-                       (int64_t)H.block_rows, slots, H.row_ptr, H.col,
+                       (int64_t)H.block_rows, slots, width, H.row_ptr, H.col,
                        static_cast<const float *>(H.val), blocks, n_local, col2,
                        static_cast<float *>(val2), lcol, rdesc);
   else
     hipLaunchKernelGGL((k_plan_rows<double>), dim3(grid), dim3(256), 0, s, H.n,
-                       (int64_t)H.block_rows, slots, H.row_ptr, H.col,
+                       (int64_t)H.block_rows, slots, width, H.row_ptr, H.col,
                        static_cast<const double *>(H.val), blocks, n_local, col2,
                        static_cast<double *>(val2), lcol, rdesc);
   check_launch("spmm plan");

@@ -117,7 +117,7 @@ def test_spmm_plan_layout_and_errors(torch, bbl):
     # n_local sits in the plan buffer right after the block table
     off = plan.c.n_local - plan.mem.data_ptr()
     assert off == ((plan.mem.data_ptr() + 255) // 256 * 256 - plan.mem.data_ptr()
-                   + -(-(30 * plan.slots * 4) // 256) * 256)
+                   + -(-(30 * 2 * plan.slots * 4) // 256) * 256)
     nl = plan.mem[off:off + 4 * H.n].view(torch.int32).cpu().numpy()
     lens = np.diff(H.row_ptr)
     assert np.all(nl >= 0) and np.all(nl <= lens)
@@ -135,15 +135,50 @@ def test_spmm_plan_layout_and_errors(torch, bbl):
     assert staged.sum() == nl.sum()
     assert np.array_equal(lcol[staged].astype(np.int64), col2[staged].astype(np.int64))
     assert np.all(col2[staged] < plan.slots * 400)
-    # per-row descriptors: first entry, first remote entry, end, relative to
-    # the row group's first entry rounded down to a multiple of 8
+    # block table: per group its own block, then the other blocks by entry
+    # count (set A: the first `slots`, set B: the next `slots`)
+    ob = plan.c.blocks - plan.mem.data_ptr()
+    S = plan.slots
+    blk = plan.mem[ob:ob + 4 * 30 * 2 * S].view(torch.int32).cpu().numpy().reshape(30, 2 * S)
+    cb = np.asarray(H.col) // 400
+    for g in (0, 7, 29):
+        m = rows // 400 == g
+        cnt = np.bincount(cb[m], minlength=30)
+        assert blk[g, 0] == g
+        others = blk[g, 1:][blk[g, 1:] >= 0]
+        assert len(set(others.tolist())) == len(others) and g not in others
+        c = cnt[others]
+        assert np.all(np.diff(c) <= 0) and np.all(c > 0)
+        rest = np.setdiff1d(np.nonzero(cnt)[0], np.concatenate([[g], others]))
+        assert len(rest) == 0 or cnt[rest].max() <= c.min()
+    # per-row descriptors: first entry, first set-B entry, first remaining
+    # entry, end, relative to the row group's first entry rounded down to 8
     od = plan.c.rdesc - plan.mem.data_ptr()
     d = plan.mem[od:od + 16 * H.n].view(torch.int32).cpu().numpy().reshape(-1, 4).astype(np.int64)
     rp = np.asarray(H.row_ptr)
     gb = rp[(np.arange(H.n) // 400) * 400] & ~7
     assert np.array_equal(d[:, 0], rp[:-1] - gb)
     assert np.array_equal(d[:, 1], rp[:-1] + nl - gb)
-    assert np.array_equal(d[:, 2], rp[1:] - gb)
+    assert np.array_equal(d[:, 3], rp[1:] - gb)
+    assert np.all(d[:, 1] <= d[:, 2]) and np.all(d[:, 2] <= d[:, 3])
+    # set-B entries: global columns in col, in-set LDS rows in lcol, in order;
+    # the rest: global columns outside both sets
+    pos = np.arange(H.nnz) - gb[rows]
+    inb = (pos >= d[rows, 1]) & (pos < d[rows, 2])
+    rem = pos >= d[rows, 2]
+    setb = blk[rows // 400, S:]
+    gcol = col2.astype(np.int64)
+    okb = (gcol[inb][:, None] // 400 == setb[inb]).any(axis=1)
+    assert okb.all()
+    k = np.argmax(gcol[inb][:, None] // 400 == setb[inb], axis=1)
+    assert np.array_equal(lcol[inb].astype(np.int64), k * 400 + gcol[inb] % 400)
+    allb = blk[rows // 400]
+    assert not (gcol[rem][:, None] // 400 == allb[rem]).any()
+    # the (row, column) pairs outside set A are those of H
+    ocol = np.asarray(H.col).astype(np.int64)
+    nota = ~(ocol[:, None] // 400 == blk[rows // 400, :S]).any(axis=1)
+    assert np.array_equal(np.sort(rows[nota] * H.n + ocol[nota]),
+                          np.sort(rows[inb | rem] * H.n + gcol[inb | rem]))
     with pytest.raises(bbl.BblError):
         bbl.spmm_plan(bbl.DeviceCSR.from_host(H, "float32"), 8)          # no hint
     with pytest.raises(bbl.BblError):
