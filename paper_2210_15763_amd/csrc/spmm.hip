@@ -1071,12 +1071,12 @@ void pipe_pass(const bbl_spmm_plan &P, int parts, const float *X, float *Y, hipS
   check_launch(P2 ? "k_spmm_pipe (pass 2)" : "k_spmm_pipe (pass 1)");
 }
 
-// Pass 1 takes most entries per row (16 lanes per row, two workgroups per
-// group); pass 2 the few left (4 lanes per row, one workgroup per group).
+// Pass 1 takes most entries per row (16 lanes per row), pass 2 the few left
+// (4 lanes per row); one workgroup per group in both, so each set is staged
+// once per group.
 template <int BV>
 void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, hipStream_t s) {
-  const int parts = (int)std::min<int64_t>(kPlanParts, ceil_div(P.block_rows, 64));
-  pipe_pass<BV, 16, false>(P, parts, X, Y, s);
+  pipe_pass<BV, 16, false>(P, 1, X, Y, s);
   pipe_pass<BV, 4, true>(P, 1, X, Y, s);
 }
 
