@@ -658,32 +658,37 @@ __global__ __launch_bounds__(1024) void k_spmm_planned(int64_t n, int64_t G, int
 // through the vector caches.
 //
 // Both passes run the same software pipeline.  LPR lanes share a row and
-// walk it in steps of 8 * LPR staged entries (eight per lane: one 16-byte
-// load of indices, two of values) and, in pass 2, 2 * LPR remote entries;
-// the loads of the following step -- of the group's next row when this one
-// ends -- are issued before this step's LDS reads and FMAs, so one step of
-// the CSR stream is always in flight behind the arithmetic.  Entries outside
-// a lane's part of the row read an all-zero LDS row kept after the staged
-// blocks, with a zero weight, so the LDS reads carry no branches.
-constexpr int kPipeLE = 8;    // staged entries per lane and step
+// walk it in steps of LE * LPR staged entries (LE per lane, 16 in pass 1 and
+// 8 in pass 2, loaded 16 bytes at a time) and, in pass 2, 2 * LPR remote
+// entries; the loads of the following step -- of the group's next row when
+// this one ends -- are issued before this step's LDS reads and FMAs, so one
+// step of the CSR stream is always in flight behind the arithmetic.  Entries
+// outside a lane's part of the row read an all-zero LDS row kept after the
+// staged blocks, with a zero weight, so the LDS reads carry no branches.
 constexpr int kPipeRE = 2;    // remote entries per lane and step (pass 2)
+
+// staged entries per lane and step: sixteen in pass 1 (two 16-byte loads of
+// indices, four of values), eight in pass 2
+template <bool P2>
+constexpr int pipe_le() { return P2 ? 8 : 16; }
 
 template <int B, int LPR, bool P2>
 struct PipeStage {
   static constexpr int NO = B / LPR > 0 ? B / LPR : 1;  // sums per lane after the reduction
-  uint4 lc;                     // eight 16-bit LDS row indices
-  float lv[kPipeLE];
+  static constexpr int LE = pipe_le<P2>();
+  uint4 lc[LE / 8];             // 16-bit LDS row indices
+  float lv[LE];
   int rc[P2 ? kPipeRE : 1];
   float rv[P2 ? kPipeRE : 1];
   float yp[P2 ? NO : 1];        // pass 1's sums of the row (pass 2)
   int llo, lhi, rlo, rhi;       // valid entries e: llo <= e < lhi (staged), rlo <= e < rhi (remote)
 };
 
-// Loads the lane's share of one step: staged entries [ql, ql + 8) and remote
-// entries [qr, qr + 2) of a row whose staged entries are [p0, pl) and remote
-// ones [pl, p1), and in pass 2 that row's pass-1 sums.  Positions are
-// relative to a base that is a multiple of 8, ql a multiple of 8 and qr of 2,
-// so the loads are aligned; the plan pads its arrays by 8 entries.  Every
+// Loads the lane's share of one step: staged entries [ql, ql + LE) and
+// remote entries [qr, qr + 2) of a row whose staged entries are [p0, pl) and
+// remote ones [pl, p1), and in pass 2 that row's pass-1 sums.  Positions are
+// relative to a base that is a multiple of 8, ql a multiple of LE and qr of
+// 2, so the loads are aligned; the plan pads its arrays by 16 entries.  Every
 // lane issues the same loads whether or not its entries exist (those without
 // any read position 0 and are masked by the ranges), so the number of loads
 // in flight is the same on every path.
@@ -693,14 +698,17 @@ __device__ __forceinline__ void pipe_load(PipeStage<B, LPR, P2> &st,
                                           const float *__restrict__ val2,
                                           const int32_t *__restrict__ col2, int ql, int qr,
                                           int p0, int pl, int p1, const float *yrow) {
+  constexpr int LE = PipeStage<B, LPR, P2>::LE;
   st.llo = p0 - ql;
   st.lhi = pl - ql;
   const int lq = st.lhi > 0 ? ql : 0;
-  st.lc = *reinterpret_cast<const uint4 *>(lcol + lq);
-  const uint4 a = reinterpret_cast<const uint4 *>(val2 + lq)[0];
-  const uint4 b = reinterpret_cast<const uint4 *>(val2 + lq)[1];
-  __builtin_memcpy(st.lv, &a, 16);
-  __builtin_memcpy(st.lv + 4, &b, 16);
+#pragma unroll
+  for (int i = 0; i < LE / 8; ++i) st.lc[i] = reinterpret_cast<const uint4 *>(lcol + lq)[i];
+#pragma unroll
+  for (int i = 0; i < LE / 4; ++i) {
+    const uint4 a = reinterpret_cast<const uint4 *>(val2 + lq)[i];
+    __builtin_memcpy(st.lv + 4 * i, &a, 16);
+  }
   if constexpr (P2) {
     st.rlo = pl - qr;
     st.rhi = p1 - qr;
@@ -741,9 +749,12 @@ __device__ __forceinline__ void pipe_row(const float *p, int par, float (&v)[B])
   }
 }
 
-__device__ __forceinline__ int pipe_lidx(const uint4 &c, int e) {
-  const unsigned w = e < 2 ? c.x : e < 4 ? c.y : e < 6 ? c.z : c.w;
-  return (int)((e & 1) ? (w >> 16) : (w & 0xffffu));
+template <int N>
+__device__ __forceinline__ int pipe_lidx(const uint4 (&c)[N], int e) {
+  const uint4 &q = c[e / 8];
+  const int f = e % 8;
+  const unsigned w = f < 2 ? q.x : f < 4 ? q.y : f < 6 ? q.z : q.w;
+  return (int)((f & 1) ? (w >> 16) : (w & 0xffffu));
 }
 
 // Pass 1 (P2 = false) or pass 2 (P2 = true) over the row groups; `blocks`
@@ -775,7 +786,8 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
   const int nr = (int)(min(min(n, gr0 + G), r0 + slice) - r0);
   if (nr <= 0) return;
   constexpr int RPW = kWave / LPR;
-  constexpr int LCH = kPipeLE * LPR, RCH = kPipeRE * LPR;
+  constexpr int LE = Stage::LE;
+  constexpr int LCH = LE * LPR, RCH = kPipeRE * LPR;
   const int lane = threadIdx.x & (kWave - 1);
   const int sub = lane & (LPR - 1);
   const int wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
@@ -783,7 +795,7 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
   const int zrow = slots * (int)G;  // the all-zero LDS row
   const int par = (B == 8 && LPR == 16) ? (sub & 1) : 0;
   const int cb = NO * sub;          // first of the lane's sums after the reduction (B >= LPR)
-  const int64_t base = rp[gr0] & ~(int64_t)(kPipeLE - 1);
+  const int64_t base = rp[gr0] & ~(int64_t)7;
   const uint16_t *lc_b = lcol + base;
   const float *v_b = val2 + base;
   const int32_t *c_b = col2 + base;
@@ -810,9 +822,9 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
   int4 dn = desc[nrow < nr ? nrow : 0];
   int p0, pl, p1;
   ranges(d0, p0, pl, p1);
-  int qlb = p0 & ~(kPipeLE - 1), qrb = pl & ~(kPipeRE - 1);
+  int qlb = p0 & ~(LE - 1), qrb = pl & ~(kPipeRE - 1);
   Stage cur;
-  pipe_load<B, LPR, P2>(cur, lc_b, v_b, c_b, qlb + kPipeLE * sub, qrb + kPipeRE * sub, p0, pl, p1,
+  pipe_load<B, LPR, P2>(cur, lc_b, v_b, c_b, qlb + LE * sub, qrb + kPipeRE * sub, p0, pl, p1,
                         yrow(row));
 
   // stage the set's column blocks: every load of the fill first, then the writes
@@ -891,7 +903,7 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
     int srow = row;
     if (last) {
       ranges(dn, sp0, spl, sp1);
-      sqlb = sp0 & ~(kPipeLE - 1);
+      sqlb = sp0 & ~(LE - 1);
       sqrb = spl & ~(kPipeRE - 1);
       srow = nrow;
     }
@@ -921,7 +933,7 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
         if (ok) pipe_row<B>(X + (int64_t)cur.rc[e] * B, par, rx[e]);
       }
     }
-    pipe_load<B, LPR, P2>(nxt, lc_b, v_b, c_b, sqlb + kPipeLE * sub, sqrb + kPipeRE * sub, sp0,
+    pipe_load<B, LPR, P2>(nxt, lc_b, v_b, c_b, sqlb + LE * sub, sqrb + kPipeRE * sub, sp0,
                           spl, sp1, yrow(srow));
     // the descriptor of the row after the one the next step works on
     {
@@ -932,7 +944,7 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
     // rows take registers)
     constexpr int LG = P2 ? 2 : 4;
 #pragma unroll
-    for (int hf = 0; hf < kPipeLE; hf += LG) {
+    for (int hf = 0; hf < LE; hf += LG) {
       float lx[LG][B];
       float h[LG];
 #pragma unroll
@@ -1206,11 +1218,11 @@ size_t spmm_plan_bytes(const bbl_csr &H, int nvec, int vec_dtype) {
   if (slots < 1) return 0;
   const int64_t groups = ceil_div(H.n, H.block_rows);
   const size_t sv = H.val_dtype == BBL_F32 ? 4 : 8;
-  // index and value arrays padded by 8 entries for the chunk loads
+  // index and value arrays padded by 16 entries for the chunk loads
   const int width = plan_local16(H, slots) && plan_desc(H) ? 2 * slots : slots;
   return align_up((size_t)groups * width * 4) + align_up((size_t)H.n * 4) +
-         align_up((size_t)(H.nnz + 8) * 4) + align_up((size_t)(H.nnz + 8) * sv) +
-         (plan_local16(H, slots) ? align_up((size_t)(H.nnz + 8) * 2) : 0) +
+         align_up((size_t)(H.nnz + 16) * 4) + align_up((size_t)(H.nnz + 16) * sv) +
+         (plan_local16(H, slots) ? align_up((size_t)(H.nnz + 16) * 2) : 0) +
          (plan_local16(H, slots) && plan_desc(H) ? align_up((size_t)H.n * 16) : 0) + 256;
 }
 
@@ -1233,10 +1245,10 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
   const int width = plan_local16(H, slots) && plan_desc(H) ? 2 * slots : slots;
   int32_t *blocks = reinterpret_cast<int32_t *>(take((size_t)groups * width * 4));
   int32_t *n_local = reinterpret_cast<int32_t *>(take((size_t)H.n * 4));
-  int32_t *col2 = reinterpret_cast<int32_t *>(take((size_t)(H.nnz + 8) * 4));
-  void *val2 = take((size_t)(H.nnz + 8) * sv);
+  int32_t *col2 = reinterpret_cast<int32_t *>(take((size_t)(H.nnz + 16) * 4));
+  void *val2 = take((size_t)(H.nnz + 16) * sv);
   const bool l16 = plan_local16(H, slots);
-  uint16_t *lcol = l16 ? reinterpret_cast<uint16_t *>(take((size_t)(H.nnz + 8) * 2)) : nullptr;
+  uint16_t *lcol = l16 ? reinterpret_cast<uint16_t *>(take((size_t)(H.nnz + 16) * 2)) : nullptr;
   int32_t *rdesc = l16 && plan_desc(H) ? reinterpret_cast<int32_t *>(take((size_t)H.n * 16))
                                         : nullptr;
   hipLaunchKernelGGL(k_plan_blocks, dim3((unsigned)groups), dim3(256), 0, s, H.n,
