@@ -650,55 +650,83 @@ __global__ __launch_bounds__(1024) void k_spmm_planned(int64_t n, int64_t G, int
 // descriptors.  The plan names two sets of column blocks per row group: set
 // A (the group's own block and its busiest partners) and set B (the next
 // busiest), and orders every row's entries: set A, set B, then the rest
-// ("remote").  Pass 1 stages set A in LDS and streams each row's set-A
-// entries, writing the row sums; pass 2 stages set B, streams the set-B
-// entries, gathers the few remote rows of V from global memory and adds its
-// sums to pass 1's.  On sectored matrices the two sets hold nearly every
-// entry, so rows of V are read from LDS rather than gathered one by one
-// through the vector caches.
+// ("remote").  Pass 1 stages set A in LDS, streams each row's set-A entries,
+// gathers its few remote rows of V from global memory and writes the row
+// sums; pass 2 stages set B, streams the set-B entries and adds its sums to
+// pass 1's.  On sectored matrices the two sets hold nearly every entry, so
+// rows of V are read from LDS rather than gathered one by one through the
+// vector caches.
 //
 // Both passes run the same software pipeline.  LPR lanes share a row and
-// walk it in steps of LE * LPR staged entries (LE per lane, 16 in pass 1 and
-// 8 in pass 2, loaded 16 bytes at a time) and, in pass 2, 2 * LPR remote
-// entries; the loads of the following step -- of the group's next row when
-// this one ends -- are issued before this step's LDS reads and FMAs, so one
-// step of the CSR stream is always in flight behind the arithmetic.  Entries
-// outside a lane's part of the row read an all-zero LDS row kept after the
-// staged blocks, with a zero weight, so the LDS reads carry no branches.
-constexpr int kPipeRE = 2;    // remote entries per lane and step (pass 2)
+// walk it in steps of LE * LPR staged entries (LE per lane, loaded 16 bytes
+// at a time) and, in pass 1, 2 * LPR remote entries; the loads of the
+// following step -- of the group's next row when this one ends -- are issued
+// before this step's LDS reads and FMAs, so one step of the CSR stream is
+// always in flight behind the arithmetic.  Entries outside a lane's part of
+// the row read an all-zero LDS row kept after the staged blocks, with a zero
+// weight, so the LDS reads carry no branches.
+constexpr int kPipeRE = 2;    // remote entries per lane and step (pass 1)
 
-// staged entries per lane and step: sixteen in pass 1 (two 16-byte loads of
-// indices, four of values), eight in pass 2
+// lanes per row and staged entries per lane and step: pass 1 takes ~90 % of
+// each row's entries, pass 2 ~10 %
 template <bool P2>
-constexpr int pipe_le() { return P2 ? 8 : 16; }
+constexpr int pipe_lpr() { return P2 ? 2 : 16; }
+template <bool P2>
+constexpr int pipe_le() { return P2 ? 16 : 8; }
 
-template <int B, int LPR, bool P2>
+template <int B, bool P2>
 struct PipeStage {
+  static constexpr int LPR = pipe_lpr<P2>();
   static constexpr int NO = B / LPR > 0 ? B / LPR : 1;  // sums per lane after the reduction
   static constexpr int LE = pipe_le<P2>();
   uint4 lc[LE / 8];             // 16-bit LDS row indices
   float lv[LE];
-  int rc[P2 ? kPipeRE : 1];
-  float rv[P2 ? kPipeRE : 1];
+  int rc[P2 ? 1 : kPipeRE];     // remote entries (pass 1)
+  float rv[P2 ? 1 : kPipeRE];
   float yp[P2 ? NO : 1];        // pass 1's sums of the row (pass 2)
   int llo, lhi, rlo, rhi;       // valid entries e: llo <= e < lhi (staged), rlo <= e < rhi (remote)
 };
 
-// Loads the lane's share of one step: staged entries [ql, ql + LE) and
-// remote entries [qr, qr + 2) of a row whose staged entries are [p0, pl) and
-// remote ones [pl, p1), and in pass 2 that row's pass-1 sums.  Positions are
-// relative to a base that is a multiple of 8, ql a multiple of LE and qr of
-// 2, so the loads are aligned; the plan pads its arrays by 16 entries.  Every
-// lane issues the same loads whether or not its entries exist (those without
-// any read position 0 and are masked by the ranges), so the number of loads
-// in flight is the same on every path.
-template <int B, int LPR, bool P2>
-__device__ __forceinline__ void pipe_load(PipeStage<B, LPR, P2> &st,
-                                          const uint16_t *__restrict__ lcol,
+// NO consecutive floats from a 4 * NO-byte aligned address
+template <int NO>
+__device__ __forceinline__ void pipe_vload(const float *p, float (&v)[NO]) {
+  if constexpr (NO == 4) {
+    const float4 y = *reinterpret_cast<const float4 *>(p);
+    v[0] = y.x, v[1] = y.y, v[2] = y.z, v[3] = y.w;
+  } else if constexpr (NO == 2) {
+    const float2 y = *reinterpret_cast<const float2 *>(p);
+    v[0] = y.x, v[1] = y.y;
+  } else {
+#pragma unroll
+    for (int i = 0; i < NO; ++i) v[i] = p[i];
+  }
+}
+template <int NO>
+__device__ __forceinline__ void pipe_vstore(float *p, const float (&v)[NO]) {
+  if constexpr (NO == 4) {
+    *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (NO == 2) {
+    *reinterpret_cast<float2 *>(p) = make_float2(v[0], v[1]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < NO; ++i) p[i] = v[i];
+  }
+}
+
+// Loads the lane's share of one step: staged entries [ql, ql + LE) of a row
+// whose staged entries are [p0, pl), in pass 1 remote entries [qr, qr + 2)
+// of its remote range [q0, q1), in pass 2 the row's pass-1 sums.  Positions
+// are relative to a base that is a multiple of 8, ql a multiple of LE and qr
+// of 2, so the loads are aligned; the plan pads its arrays by 16 entries.
+// Every lane issues the same loads whether or not its entries exist (those
+// without any read position 0 and are masked by the ranges), so the number
+// of loads in flight is the same on every path.
+template <int B, bool P2>
+__device__ __forceinline__ void pipe_load(PipeStage<B, P2> &st, const uint16_t *__restrict__ lcol,
                                           const float *__restrict__ val2,
                                           const int32_t *__restrict__ col2, int ql, int qr,
-                                          int p0, int pl, int p1, const float *yrow) {
-  constexpr int LE = PipeStage<B, LPR, P2>::LE;
+                                          int p0, int pl, int q0, int q1, const float *yrow) {
+  constexpr int LE = PipeStage<B, P2>::LE;
   st.llo = p0 - ql;
   st.lhi = pl - ql;
   const int lq = st.lhi > 0 ? ql : 0;
@@ -710,25 +738,17 @@ __device__ __forceinline__ void pipe_load(PipeStage<B, LPR, P2> &st,
     __builtin_memcpy(st.lv + 4 * i, &a, 16);
   }
   if constexpr (P2) {
-    st.rlo = pl - qr;
-    st.rhi = p1 - qr;
+    st.rlo = 0;
+    st.rhi = 0;
+    pipe_vload<PipeStage<B, P2>::NO>(yrow, st.yp);
+  } else {
+    st.rlo = q0 - qr;
+    st.rhi = q1 - qr;
     const int rq = st.rhi > 0 ? qr : 0;
     const uint2 c = *reinterpret_cast<const uint2 *>(col2 + rq);
     const float2 v = *reinterpret_cast<const float2 *>(val2 + rq);
     __builtin_memcpy(st.rc, &c, 8);
     __builtin_memcpy(st.rv, &v, 8);
-    constexpr int NO = PipeStage<B, LPR, P2>::NO;
-    if constexpr (NO == 2) {
-      const float2 y = *reinterpret_cast<const float2 *>(yrow);
-      st.yp[0] = y.x;
-      st.yp[1] = y.y;
-    } else {
-#pragma unroll
-      for (int i = 0; i < NO; ++i) st.yp[i] = yrow[i];
-    }
-  } else {
-    st.rlo = 0;
-    st.rhi = 0;
   }
 }
 
@@ -762,7 +782,7 @@ __device__ __forceinline__ int pipe_lidx(const uint4 (&c)[N], int e) {
 // come from the plan's descriptors {first entry, first set-B entry, first
 // remote entry, end} (32-bit offsets from the group's first entry rounded
 // down to a multiple of 8).
-template <int B, int LPR, bool P2>
+template <int B, bool P2>
 __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int slots, int parts,
                                                     const int64_t *__restrict__ rp,
                                                     const int32_t *__restrict__ col2,
@@ -772,9 +792,9 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
                                                     const int32_t *__restrict__ blocks,
                                                     const float *__restrict__ X,
                                                     float *__restrict__ Y) {
+  using Stage = PipeStage<B, P2>;
+  constexpr int LPR = Stage::LPR, NO = Stage::NO, LE = Stage::LE;
   static_assert(!P2 || B >= LPR, "pass 2 keeps whole components per lane");
-  using Stage = PipeStage<B, LPR, P2>;
-  constexpr int NO = Stage::NO;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const float *sX = reinterpret_cast<const float *>(smem_raw);
   const int64_t L = xcd_block(blockIdx.x);
@@ -786,7 +806,6 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
   const int nr = (int)(min(min(n, gr0 + G), r0 + slice) - r0);
   if (nr <= 0) return;
   constexpr int RPW = kWave / LPR;
-  constexpr int LE = Stage::LE;
   constexpr int LCH = LE * LPR, RCH = kPipeRE * LPR;
   const int lane = threadIdx.x & (kWave - 1);
   const int sub = lane & (LPR - 1);
@@ -801,16 +820,17 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
   const int32_t *c_b = col2 + base;
   const int4 *desc = reinterpret_cast<const int4 *>(rdesc) + r0;
   float *Yw = Y + r0 * B;
-  // the row's staged and remote ranges in this pass
-  auto ranges = [&](const int4 &d, int &p0, int &pl, int &p1) {
+  // the row's staged range [p0, pl) and remote range [q0, q1) in this pass
+  auto ranges = [&](const int4 &d, int &p0, int &pl, int &q0, int &q1) {
     if constexpr (P2) {
       p0 = d.y;
       pl = d.z;
-      p1 = d.w;
+      q0 = q1 = d.z;
     } else {
       p0 = d.x;
       pl = d.y;
-      p1 = d.y;
+      q0 = d.z;
+      q1 = d.w;
     }
   };
   auto yrow = [&](int r) { return Yw + (int64_t)(r < nr ? r : 0) * B + (B >= LPR ? cb : 0); };
@@ -820,12 +840,12 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
   int nrow = row + stride;
   const int4 d0 = desc[row < nr ? row : 0];
   int4 dn = desc[nrow < nr ? nrow : 0];
-  int p0, pl, p1;
-  ranges(d0, p0, pl, p1);
-  int qlb = p0 & ~(LE - 1), qrb = pl & ~(kPipeRE - 1);
+  int p0, pl, q0, q1;
+  ranges(d0, p0, pl, q0, q1);
+  int qlb = p0 & ~(LE - 1), qrb = q0 & ~(kPipeRE - 1);
   Stage cur;
-  pipe_load<B, LPR, P2>(cur, lc_b, v_b, c_b, qlb + LE * sub, qrb + kPipeRE * sub, p0, pl, p1,
-                        yrow(row));
+  pipe_load<B, P2>(cur, lc_b, v_b, c_b, qlb + LE * sub, qrb + kPipeRE * sub, p0, pl, q0, q1,
+                   yrow(row));
 
   // stage the set's column blocks: every load of the fill first, then the writes
   {
@@ -872,19 +892,14 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
     if constexpr (B == 8 && LPR == 16) {
       if ((sub & 1) == 0) yp[sub >> 1] = out[0];
     } else if constexpr (B >= LPR) {
-      if constexpr (NO == 2) {
-        *reinterpret_cast<float2 *>(yp + cb) = make_float2(out[0], out[1]);
-      } else {
-#pragma unroll
-        for (int i = 0; i < NO; ++i) yp[cb + i] = out[i];
-      }
+      pipe_vstore<NO>(yp + cb, out);
     } else {
 #pragma unroll
       for (int a = 0; a < B; ++a)
         if (a % LPR == sub) yp[a] = out[a];
     }
   };
-  float rx[P2 ? kPipeRE : 1][B], rh[P2 ? kPipeRE : 1];  // remote rows in flight (pass 2)
+  float rx[P2 ? 1 : kPipeRE][B], rh[P2 ? 1 : kPipeRE];  // remote rows in flight (pass 1)
   bool rpend = false;
   // One step on the entries in `cur`, loading the following step into `nxt`;
   // false once the group has no rows left.  The loop below alternates the two
@@ -897,22 +912,22 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
     // that store out of the wait
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     // where the next step starts: the rest of this row, else the group's next row
-    const bool last = qlb + LCH >= pl && (!P2 || qrb + RCH >= p1);
+    const bool last = qlb + LCH >= pl && (P2 || qrb + RCH >= q1);
     const bool more = !last || nrow < nr;
-    int sp0 = 0, spl = pl, sp1 = p1, sqlb = qlb + LCH, sqrb = qrb + RCH;
+    int sp0 = 0, spl = pl, sq0 = q0, sq1 = q1, sqlb = qlb + LCH, sqrb = qrb + RCH;
     int srow = row;
     if (last) {
-      ranges(dn, sp0, spl, sp1);
+      ranges(dn, sp0, spl, sq0, sq1);
       sqlb = sp0 & ~(LE - 1);
-      sqrb = spl & ~(kPipeRE - 1);
+      sqrb = sq0 & ~(kPipeRE - 1);
       srow = nrow;
     }
-    if (!more) sp0 = spl = sp1 = sqlb = sqrb = 0;  // nothing left: empty ranges
+    if (!more) sp0 = spl = sq0 = sq1 = sqlb = sqrb = 0;  // nothing left: empty ranges
     if (yp) {
       store_out();
       yp = nullptr;
     }
-    if constexpr (P2) {
+    if constexpr (!P2) {
       // remote products gathered by the previous step of this row: that
       // step's later loads have arrived, so these have too
       if (rpend) {
@@ -923,7 +938,7 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
       }
       // remote gathers of this step, multiplied in at the start of the row's
       // next step (or at the end of this one if it is the row's last)
-      rpend = cur.rhi > 0;
+      rpend = cur.rhi > 0 && cur.rlo < kPipeRE;
 #pragma unroll
       for (int e = 0; e < kPipeRE; ++e) {
         const bool ok = cur.rlo <= e && e < cur.rhi;
@@ -933,15 +948,15 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
         if (ok) pipe_row<B>(X + (int64_t)cur.rc[e] * B, par, rx[e]);
       }
     }
-    pipe_load<B, LPR, P2>(nxt, lc_b, v_b, c_b, sqlb + LE * sub, sqrb + kPipeRE * sub, sp0,
-                          spl, sp1, yrow(srow));
+    pipe_load<B, P2>(nxt, lc_b, v_b, c_b, sqlb + LE * sub, sqrb + kPipeRE * sub, sp0, spl, sq0,
+                     sq1, yrow(srow));
     // the descriptor of the row after the one the next step works on
     {
       const int r = last ? nrow + stride : nrow;
       dn = desc[r < nr ? r : 0];
     }
-    // staged entries, LG LDS rows at a time (fewer in pass 2, whose remote
-    // rows take registers)
+    // staged entries, LG LDS rows at a time (fewer in pass 2, whose lanes hold
+    // more sums and stage data)
     constexpr int LG = P2 ? 2 : 4;
 #pragma unroll
     for (int hf = 0; hf < LE; hf += LG) {
@@ -960,7 +975,7 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
         for (int a = 0; a < B; ++a) acc[a] = fmaf(h[e], lx[e][a], acc[a]);
     }
     if (last) {
-      if constexpr (P2) {
+      if constexpr (!P2) {
         if (rpend) {
 #pragma unroll
           for (int e = 0; e < kPipeRE; ++e)
@@ -991,7 +1006,6 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
         float k1 = (h2 ? k2[1] : k2[0]) + __shfl_xor(send, 2, LPR);
         // even lane sub and odd lane sub ^ 9 now hold the same component
         out[0] = k1 + __shfl_xor(k1, 9, LPR);
-        if constexpr (P2) out[0] += cur.yp[0];
       } else if constexpr (B >= LPR) {
         // halving exchange: each round keeps the half of the sums selected by
         // one bit of sub, so lane sub ends with components [NO sub, NO sub + NO)
@@ -1026,7 +1040,8 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
       nrow += stride;
     }
     pl = spl;
-    p1 = sp1;
+    q0 = sq0;
+    q1 = sq1;
     qlb = sqlb;
     qrb = sqrb;
     return more;
@@ -1065,9 +1080,9 @@ void planned_launch_t(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s)
   check_launch("k_spmm_planned");
 }
 
-template <int BV, int LPR, bool P2>
+template <int BV, bool P2>
 void pipe_pass(const bbl_spmm_plan &P, int parts, const float *X, float *Y, hipStream_t s) {
-  auto kern = k_spmm_pipe<BV, LPR, P2>;
+  auto kern = k_spmm_pipe<BV, P2>;
   const size_t lds = ((size_t)P.slots * P.block_rows + 1) * BV * sizeof(float);
   static bool attr_set = false;
   if (!attr_set) {
@@ -1083,13 +1098,13 @@ void pipe_pass(const bbl_spmm_plan &P, int parts, const float *X, float *Y, hipS
   check_launch(P2 ? "k_spmm_pipe (pass 2)" : "k_spmm_pipe (pass 1)");
 }
 
-// Pass 1 takes most entries per row (16 lanes per row), pass 2 the few left
-// (4 lanes per row); one workgroup per group in both, so each set is staged
-// once per group.
+// Pass 1 takes most entries per row (16 lanes per row), pass 2 the set-B
+// tenth (2 lanes per row); one workgroup per group in both, so each set is
+// staged once per group.
 template <int BV>
 void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, hipStream_t s) {
-  pipe_pass<BV, 16, false>(P, 1, X, Y, s);
-  pipe_pass<BV, 4, true>(P, 1, X, Y, s);
+  pipe_pass<BV, false>(P, 1, X, Y, s);
+  pipe_pass<BV, true>(P, 1, X, Y, s);
 }
 
 template <typename VT, typename XT, int BV>
