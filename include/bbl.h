@@ -99,6 +99,14 @@ typedef struct {
                              first remaining entry and end, as offsets from the
                              group's first entry rounded down to a multiple of 8;
                              present with lcol when nnz < 2^31, else NULL */
+  /* A dense copy of the set-B entries (present with rdesc, else NULL), read
+   * by the second pass of the FP32 SpMM: each group's rows in order with no
+   * gaps. */
+  const int64_t *bgroup;  /* [groups + 1] first copy entry of each group's rows */
+  const int32_t *brow;    /* [n][2] first and end copy entry of each row, relative
+                             to its group's first rounded down to a multiple of 8 */
+  const uint16_t *blcol;  /* [nnz + 16] LDS index within set B of each copied entry */
+  const void *bval;       /* [nnz + 16] its value (val_dtype) */
 } bbl_spmm_plan;
 
 /* Solver options; a NULL pointer selects the defaults shown. */

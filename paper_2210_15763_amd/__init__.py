@@ -57,7 +57,9 @@ class _Plan(ctypes.Structure):
                 ("val_dtype", ctypes.c_int32), ("local16", ctypes.c_int32),
                 ("row_ptr", ctypes.c_void_p), ("blocks", ctypes.c_void_p),
                 ("n_local", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
-                ("lcol", ctypes.c_void_p), ("rdesc", ctypes.c_void_p)]
+                ("lcol", ctypes.c_void_p), ("rdesc", ctypes.c_void_p),
+                ("bgroup", ctypes.c_void_p), ("brow", ctypes.c_void_p),
+                ("blcol", ctypes.c_void_p), ("bval", ctypes.c_void_p)]
 
 
 class _Stats(ctypes.Structure):

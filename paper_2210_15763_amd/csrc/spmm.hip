@@ -428,7 +428,8 @@ __global__ __launch_bounds__(256) void k_plan_blocks(int64_t n, int64_t G, int w
 // n_local = count of the first kind.  lcol (if present) holds the LDS index
 // of set-A and set-B entries within their set (slot*G + offset); rdesc (if
 // present) the row's {first entry, first set-B entry, first remote entry,
-// end} as offsets from its group's first entry rounded down to a multiple of 8.
+// end} as offsets from its group's first entry rounded down to a multiple of
+// 8; bcount[2 row + 1] (if present) its number of set-B entries.
 template <typename VT>
 __global__ __launch_bounds__(256) void k_plan_rows(int64_t n, int64_t G, int slots, int width,
                                                    const int64_t *__restrict__ rp,
@@ -439,7 +440,8 @@ __global__ __launch_bounds__(256) void k_plan_rows(int64_t n, int64_t G, int slo
                                                    int32_t *__restrict__ col2,
                                                    VT *__restrict__ val2,
                                                    uint16_t *__restrict__ lcol,
-                                                   int32_t *__restrict__ rdesc) {
+                                                   int32_t *__restrict__ rdesc,
+                                                   int32_t *__restrict__ bcount) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;  // uniform per wave
   const int lane = threadIdx.x & 63;
@@ -495,12 +497,98 @@ __global__ __launch_bounds__(256) void k_plan_rows(int64_t n, int64_t G, int slo
   }
   if (lane == 0) {
     n_local[row] = na;
+    if (bcount) bcount[2 * row + 1] = nb;
     if (rdesc) {
       const int64_t gb = rp[g * G] & ~(int64_t)7;
       const int4 d = make_int4((int)(p0 - gb), (int)(p0 + na - gb), (int)(p0 + na + nb - gb),
                                (int)(p1 - gb));
       *reinterpret_cast<int4 *>(rdesc + 4 * row) = d;
     }
+  }
+}
+
+// Dense copy of the set-B entries, rows in order, for the second pass.
+// k_plan_bgroup (one workgroup per group): brow[2 r] = set-B entries of the
+// group's rows before r, bgroup[g + 1] = the group's total.  k_plan_gscan
+// (one workgroup): bgroup[g] = first copy entry of group g.  k_plan_bfill
+// (one wave per row): copies the row's set-B LDS indices and values and
+// leaves brow[r] = {first, end} relative to bgroup[g] rounded down to 8.
+__global__ __launch_bounds__(256) void k_plan_bgroup(int64_t n, int64_t G,
+                                                     int32_t *__restrict__ brow,
+                                                     int64_t *__restrict__ bgroup) {
+  __shared__ int64_t part[256];
+  const int64_t g = blockIdx.x;
+  const int64_t r0 = g * G, r1 = min(n, r0 + G);
+  const int t = threadIdx.x;
+  const int64_t per = (r1 - r0 + 255) / 256;
+  const int64_t a0 = r0 + t * per, a1 = min(r1, a0 + per);
+  int64_t sum = 0;
+  for (int64_t r = a0; r < a1; ++r) sum += brow[2 * r + 1];
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int64_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t run = t > 0 ? part[t - 1] : 0;
+  for (int64_t r = a0; r < a1; ++r) {
+    const int c = brow[2 * r + 1];
+    brow[2 * r] = (int)run;
+    run += c;
+  }
+  if (t == 255) bgroup[g + 1] = part[255];
+  if (g == 0 && t == 0) bgroup[0] = 0;
+}
+
+__global__ __launch_bounds__(1024) void k_plan_gscan(int64_t *__restrict__ a, int64_t m) {
+  // inclusive scan of a[1..m] in place
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (m + 1023) / 1024;
+  const int64_t b0 = 1 + t * per, b1 = min(m + 1, b0 + per);
+  int64_t sum = 0;
+  for (int64_t i = b0; i < b1; ++i) sum += a[i];
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int64_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t run = t > 0 ? part[t - 1] : 0;
+  for (int64_t i = b0; i < b1; ++i) {
+    run += a[i];
+    a[i] = run;
+  }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_plan_bfill(int64_t n, int64_t G,
+                                                    const int64_t *__restrict__ rp,
+                                                    const int32_t *__restrict__ n_local,
+                                                    const uint16_t *__restrict__ lcol,
+                                                    const VT *__restrict__ val2,
+                                                    const int64_t *__restrict__ bgroup,
+                                                    int32_t *__restrict__ brow,
+                                                    uint16_t *__restrict__ blcol,
+                                                    VT *__restrict__ bval) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;  // uniform per wave
+  const int lane = threadIdx.x & 63;
+  const int64_t g = row / G;
+  const int64_t src = rp[row] + n_local[row];
+  const int cnt = brow[2 * row + 1];
+  const int64_t dst = bgroup[g] + brow[2 * row];
+  for (int i = lane; i < cnt; i += 64) {
+    blcol[dst + i] = lcol[src + i];
+    bval[dst + i] = val2[src + i];
+  }
+  if (lane == 0) {
+    const int64_t gb = bgroup[g] & ~(int64_t)7;
+    *reinterpret_cast<int2 *>(brow + 2 * row) = make_int2((int)(dst - gb), (int)(dst + cnt - gb));
   }
 }
 
@@ -778,13 +866,17 @@ __device__ __forceinline__ int pipe_lidx(const uint4 (&c)[N], int e) {
 }
 
 // Pass 1 (P2 = false) or pass 2 (P2 = true) over the row groups; `blocks`
-// has `width` = 2 slots entries per group (set A, then set B).  Row positions
-// come from the plan's descriptors {first entry, first set-B entry, first
-// remote entry, end} (32-bit offsets from the group's first entry rounded
-// down to a multiple of 8).
+// has 2 slots entries per group (set A, then set B).  Row positions are
+// 32-bit offsets from the group's first entry rounded down to a multiple of
+// 8: pass 1's descriptors are {first entry, first set-B entry, first remote
+// entry, end}, pass 2's {first, end} of the row in the set-B copy.
+//
+// Pass 1 streams the plan's reordered arrays (rows at H's row offsets, base
+// = rp, descriptors rdesc [n][4]); pass 2 the dense copy of the set-B entries
+// (base = the plan's per-group offsets into it, descriptors [n][2]).
 template <int B, bool P2>
 __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int slots, int parts,
-                                                    const int64_t *__restrict__ rp,
+                                                    const int64_t *__restrict__ bases,
                                                     const int32_t *__restrict__ col2,
                                                     const float *__restrict__ val2,
                                                     const uint16_t *__restrict__ lcol,
@@ -792,6 +884,7 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
                                                     const int32_t *__restrict__ blocks,
                                                     const float *__restrict__ X,
                                                     float *__restrict__ Y) {
+  using Desc = typename std::conditional<P2, int2, int4>::type;
   using Stage = PipeStage<B, P2>;
   constexpr int LPR = Stage::LPR, NO = Stage::NO, LE = Stage::LE;
   static_assert(!P2 || B >= LPR, "pass 2 keeps whole components per lane");
@@ -814,18 +907,18 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
   const int zrow = slots * (int)G;  // the all-zero LDS row
   const int par = (B == 8 && LPR == 16) ? (sub & 1) : 0;
   const int cb = NO * sub;          // first of the lane's sums after the reduction (B >= LPR)
-  const int64_t base = rp[gr0] & ~(int64_t)7;
+  const int64_t base = bases[P2 ? g : gr0] & ~(int64_t)7;
   const uint16_t *lc_b = lcol + base;
   const float *v_b = val2 + base;
-  const int32_t *c_b = col2 + base;
-  const int4 *desc = reinterpret_cast<const int4 *>(rdesc) + r0;
+  const int32_t *c_b = P2 ? col2 : col2 + base;  // pass 2 has no remote entries
+  const Desc *desc = reinterpret_cast<const Desc *>(rdesc) + r0;
   float *Yw = Y + r0 * B;
   // the row's staged range [p0, pl) and remote range [q0, q1) in this pass
-  auto ranges = [&](const int4 &d, int &p0, int &pl, int &q0, int &q1) {
+  auto ranges = [&](const Desc &d, int &p0, int &pl, int &q0, int &q1) {
     if constexpr (P2) {
-      p0 = d.y;
-      pl = d.z;
-      q0 = q1 = d.z;
+      p0 = d.x;
+      pl = d.y;
+      q0 = q1 = d.y;
     } else {
       p0 = d.x;
       pl = d.y;
@@ -838,8 +931,8 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
   // this row group's first row (relative to r0) and the descriptor of its second
   int row = wave * RPW + lane / LPR;
   int nrow = row + stride;
-  const int4 d0 = desc[row < nr ? row : 0];
-  int4 dn = desc[nrow < nr ? nrow : 0];
+  const Desc d0 = desc[row < nr ? row : 0];
+  Desc dn = desc[nrow < nr ? nrow : 0];
   int p0, pl, q0, q1;
   ranges(d0, p0, pl, q0, q1);
   int qlb = p0 & ~(LE - 1), qrb = q0 & ~(kPipeRE - 1);
@@ -1092,9 +1185,14 @@ void pipe_pass(const bbl_spmm_plan &P, int parts, const float *X, float *Y, hipS
   }
   const int64_t groups = ceil_div(P.n, P.block_rows);
   const int64_t grid = ceil_div(groups * parts, kXcds) * kXcds;
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPlanThreads), lds, s, P.n,
-                     (int64_t)P.block_rows, P.slots, parts, P.row_ptr, P.col,
-                     static_cast<const float *>(P.val), P.lcol, P.rdesc, P.blocks, X, Y);
+  if (P2)
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPlanThreads), lds, s, P.n,
+                       (int64_t)P.block_rows, P.slots, parts, P.bgroup, P.col,
+                       static_cast<const float *>(P.bval), P.blcol, P.brow, P.blocks, X, Y);
+  else
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPlanThreads), lds, s, P.n,
+                       (int64_t)P.block_rows, P.slots, parts, P.row_ptr, P.col,
+                       static_cast<const float *>(P.val), P.lcol, P.rdesc, P.blocks, X, Y);
   check_launch(P2 ? "k_spmm_pipe (pass 2)" : "k_spmm_pipe (pass 1)");
 }
 
@@ -1113,7 +1211,7 @@ void planned_launch(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s) {
                 (BV == 4 || BV == 8)) {
     // the pipelined kernel also keeps one all-zero row of V in LDS and takes
     // 32-bit entry offsets
-    if (P.local16 && P.lcol && P.rdesc &&
+    if (P.local16 && P.lcol && P.rdesc && P.brow &&
         ((size_t)P.slots * P.block_rows + 1) * BV * sizeof(float) <= kPlanLds) {
       planned_launch_pipe<BV>(P, X, Y, s);
       return;
@@ -1238,7 +1336,12 @@ size_t spmm_plan_bytes(const bbl_csr &H, int nvec, int vec_dtype) {
   return align_up((size_t)groups * width * 4) + align_up((size_t)H.n * 4) +
          align_up((size_t)(H.nnz + 16) * 4) + align_up((size_t)(H.nnz + 16) * sv) +
          (plan_local16(H, slots) ? align_up((size_t)(H.nnz + 16) * 2) : 0) +
-         (plan_local16(H, slots) && plan_desc(H) ? align_up((size_t)H.n * 16) : 0) + 256;
+         (plan_local16(H, slots) && plan_desc(H)
+              ? align_up((size_t)H.n * 16) + align_up((size_t)H.n * 8) +
+                    align_up((size_t)(groups + 1) * 8) + align_up((size_t)(H.nnz + 16) * 2) +
+                    align_up((size_t)(H.nnz + 16) * sv)
+              : 0) +
+         256;
 }
 
 void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_t bytes,
@@ -1264,8 +1367,12 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
   void *val2 = take((size_t)(H.nnz + 16) * sv);
   const bool l16 = plan_local16(H, slots);
   uint16_t *lcol = l16 ? reinterpret_cast<uint16_t *>(take((size_t)(H.nnz + 16) * 2)) : nullptr;
-  int32_t *rdesc = l16 && plan_desc(H) ? reinterpret_cast<int32_t *>(take((size_t)H.n * 16))
-                                        : nullptr;
+  const bool two = l16 && plan_desc(H);
+  int32_t *rdesc = two ? reinterpret_cast<int32_t *>(take((size_t)H.n * 16)) : nullptr;
+  int32_t *brow = two ? reinterpret_cast<int32_t *>(take((size_t)H.n * 8)) : nullptr;
+  int64_t *bgroup = two ? reinterpret_cast<int64_t *>(take((size_t)(groups + 1) * 8)) : nullptr;
+  uint16_t *blcol = two ? reinterpret_cast<uint16_t *>(take((size_t)(H.nnz + 16) * 2)) : nullptr;
+  void *bval = two ? take((size_t)(H.nnz + 16) * sv) : nullptr;
   hipLaunchKernelGGL(k_plan_blocks, dim3((unsigned)groups), dim3(256), 0, s, H.n,
                      (int64_t)H.block_rows, width, H.row_ptr, H.col, blocks);
   const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(H.n, 4));
@@ -1273,12 +1380,27 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
     hipLaunchKernelGGL((k_plan_rows<float>), dim3(grid), dim3(256), 0, s, H.n,
                        (int64_t)H.block_rows, slots, width, H.row_ptr, H.col,
                        static_cast<const float *>(H.val), blocks, n_local, col2,
-                       static_cast<float *>(val2), lcol, rdesc);
+                       static_cast<float *>(val2), lcol, rdesc, brow);
   else
     hipLaunchKernelGGL((k_plan_rows<double>), dim3(grid), dim3(256), 0, s, H.n,
                        (int64_t)H.block_rows, slots, width, H.row_ptr, H.col,
                        static_cast<const double *>(H.val), blocks, n_local, col2,
-                       static_cast<double *>(val2), lcol, rdesc);
+                       static_cast<double *>(val2), lcol, rdesc, brow);
+  if (two) {
+    hipLaunchKernelGGL(k_plan_bgroup, dim3((unsigned)groups), dim3(256), 0, s, H.n,
+                       (int64_t)H.block_rows, brow, bgroup);
+    hipLaunchKernelGGL(k_plan_gscan, dim3(1), dim3(1024), 0, s, bgroup, groups);
+    if (H.val_dtype == BBL_F32)
+      hipLaunchKernelGGL((k_plan_bfill<float>), dim3(grid), dim3(256), 0, s, H.n,
+                         (int64_t)H.block_rows, H.row_ptr, n_local, lcol,
+                         static_cast<const float *>(val2), bgroup, brow, blcol,
+                         static_cast<float *>(bval));
+    else
+      hipLaunchKernelGGL((k_plan_bfill<double>), dim3(grid), dim3(256), 0, s, H.n,
+                         (int64_t)H.block_rows, H.row_ptr, n_local, lcol,
+                         static_cast<const double *>(val2), bgroup, brow, blcol,
+                         static_cast<double *>(bval));
+  }
   check_launch("spmm plan");
   P->n = H.n;
   P->nnz = H.nnz;
@@ -1295,6 +1417,10 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
   P->val = val2;
   P->lcol = lcol;
   P->rdesc = rdesc;
+  P->bgroup = bgroup;
+  P->brow = brow;
+  P->blcol = blcol;
+  P->bval = bval;
 }
 
 void launch_spmm_planned(const bbl_spmm_plan &P, const void *X, void *Y, hipStream_t s) {

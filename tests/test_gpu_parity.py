@@ -174,6 +174,25 @@ def test_spmm_plan_layout_and_errors(torch, bbl):
     assert np.array_equal(lcol[inb].astype(np.int64), k * 400 + gcol[inb] % 400)
     allb = blk[rows // 400]
     assert not (gcol[rem][:, None] // 400 == allb[rem]).any()
+    # the dense copy of the set-B entries: each group's rows in order, no gaps
+    G = 400
+    ogr = plan.c.bgroup - plan.mem.data_ptr()
+    bg = plan.mem[ogr:ogr + 8 * 31].view(torch.int64).cpu().numpy()
+    obr = plan.c.brow - plan.mem.data_ptr()
+    br = plan.mem[obr:obr + 8 * H.n].view(torch.int32).cpu().numpy().reshape(-1, 2).astype(np.int64)
+    nbr = d[:, 2] - d[:, 1]
+    assert bg[0] == 0 and np.array_equal(np.diff(bg), np.add.reduceat(nbr, np.arange(0, H.n, G)))
+    first = (bg[np.arange(H.n) // G] & ~7) + br[:, 0]
+    assert np.array_equal(br[:, 1] - br[:, 0], nbr)
+    assert np.array_equal(first[1:][nbr[:-1] >= 0], (first + nbr)[:-1])
+    obl = plan.c.blcol - plan.mem.data_ptr()
+    obv = plan.c.bval - plan.mem.data_ptr()
+    nb_all = int(bg[-1])
+    bl = plan.mem[obl:obl + 2 * nb_all].view(torch.int16).cpu().numpy().view(np.uint16)
+    ov = plan.c.val - plan.mem.data_ptr()
+    val2 = plan.mem[ov:ov + 4 * H.nnz].view(torch.float32).cpu().numpy()
+    bv = plan.mem[obv:obv + 4 * nb_all].view(torch.float32).cpu().numpy()
+    assert np.array_equal(bl, lcol[inb]) and np.array_equal(bv, val2[inb])
     # the (row, column) pairs outside set A are those of H
     ocol = np.asarray(H.col).astype(np.int64)
     nota = ~(ocol[:, None] // 400 == blk[rows // 400, :S]).any(axis=1)
