@@ -734,29 +734,28 @@ __global__ __launch_bounds__(1024) void k_spmm_planned(int64_t n, int64_t G, int
   }
 }
 
-// Two-pass planned SpMM for FP32 plans with 16-bit LDS indices and row
+// Three-pass planned SpMM for FP32 plans with 16-bit LDS indices and row
 // descriptors.  The plan names two sets of column blocks per row group: set
 // A (the group's own block and its busiest partners) and set B (the next
-// busiest), and orders every row's entries: set A, set B, then the rest
-// ("remote").  Pass 1 stages set A in LDS, streams each row's set-A entries,
-// gathers its few remote rows of V from global memory and writes the row
-// sums; pass 2 stages set B, streams the set-B entries and adds its sums to
-// pass 1's.  On sectored matrices the two sets hold nearly every entry, so
-// rows of V are read from LDS rather than gathered one by one through the
-// vector caches.
+// busiest), and orders every row's entries: set A, set B, then the rest.
+// Pass 1 stages set A in LDS and streams each row's set-A entries, writing
+// the row sums; pass 2 stages set B, streams a dense copy of the set-B
+// entries and adds its sums; pass 3 gathers the rows of V the few remaining
+// entries need from global memory and adds theirs.  On sectored matrices the
+// two sets hold nearly every entry, so rows of V are read from LDS rather
+// than gathered one by one through the vector caches, and the pipelined
+// passes carry no gather path.
 //
-// Both passes run the same software pipeline.  LPR lanes share a row and
-// walk it in steps of LE * LPR staged entries (LE per lane, loaded 16 bytes
-// at a time) and, in pass 1, 2 * LPR remote entries; the loads of the
-// following step -- of the group's next row when this one ends -- are issued
-// before this step's LDS reads and FMAs, so one step of the CSR stream is
-// always in flight behind the arithmetic.  Entries outside a lane's part of
-// the row read an all-zero LDS row kept after the staged blocks, with a zero
-// weight, so the LDS reads carry no branches.
-constexpr int kPipeRE = 2;    // remote entries per lane and step (pass 1)
+// Passes 1 and 2 run the same software pipeline.  LPR lanes share a row and
+// walk it in steps of LE * LPR entries (LE per lane, loaded 16 bytes at a
+// time); the loads of the following step -- of the group's next row when
+// this one ends -- are issued before this step's LDS reads and FMAs, so one
+// step of the stream is always in flight behind the arithmetic.  Entries
+// outside a lane's part of the row read an all-zero LDS row kept after the
+// staged blocks, with a zero weight, so the LDS reads carry no branches.
 
-// lanes per row and staged entries per lane and step: pass 1 takes ~90 % of
-// each row's entries, pass 2 ~10 %
+// lanes per row and entries per lane and step: pass 1 takes ~90 % of each
+// row's entries, pass 2 ~10 %
 template <bool P2>
 constexpr int pipe_lpr() { return P2 ? 2 : 16; }
 template <bool P2>
@@ -769,10 +768,8 @@ struct PipeStage {
   static constexpr int LE = pipe_le<P2>();
   uint4 lc[LE / 8];             // 16-bit LDS row indices
   float lv[LE];
-  int rc[P2 ? 1 : kPipeRE];     // remote entries (pass 1)
-  float rv[P2 ? 1 : kPipeRE];
-  float yp[P2 ? NO : 1];        // pass 1's sums of the row (pass 2)
-  int llo, lhi, rlo, rhi;       // valid entries e: llo <= e < lhi (staged), rlo <= e < rhi (remote)
+  float yp[P2 ? NO : 1];        // the row's sums so far (pass 2)
+  int llo, lhi;                 // valid entries e: llo <= e < lhi
 };
 
 // NO consecutive floats from a 4 * NO-byte aligned address
@@ -801,19 +798,17 @@ __device__ __forceinline__ void pipe_vstore(float *p, const float (&v)[NO]) {
   }
 }
 
-// Loads the lane's share of one step: staged entries [ql, ql + LE) of a row
-// whose staged entries are [p0, pl), in pass 1 remote entries [qr, qr + 2)
-// of its remote range [q0, q1), in pass 2 the row's pass-1 sums.  Positions
-// are relative to a base that is a multiple of 8, ql a multiple of LE and qr
-// of 2, so the loads are aligned; the plan pads its arrays by 16 entries.
-// Every lane issues the same loads whether or not its entries exist (those
-// without any read position 0 and are masked by the ranges), so the number
-// of loads in flight is the same on every path.
+// Loads the lane's share of one step: entries [ql, ql + LE) of a row whose
+// entries in this pass are [p0, pl), and in pass 2 the row's sums so far.
+// Positions are relative to a base that is a multiple of 8 and ql is a
+// multiple of LE, so the loads are aligned; the plan pads its arrays by 16
+// entries.  Every lane issues the same loads whether or not its entries exist
+// (those without any read position 0 and are masked by the range), so the
+// number of loads in flight is the same on every path.
 template <int B, bool P2>
 __device__ __forceinline__ void pipe_load(PipeStage<B, P2> &st, const uint16_t *__restrict__ lcol,
-                                          const float *__restrict__ val2,
-                                          const int32_t *__restrict__ col2, int ql, int qr,
-                                          int p0, int pl, int q0, int q1, const float *yrow) {
+                                          const float *__restrict__ val, int ql, int p0, int pl,
+                                          const float *yrow) {
   constexpr int LE = PipeStage<B, P2>::LE;
   st.llo = p0 - ql;
   st.lhi = pl - ql;
@@ -822,29 +817,17 @@ __device__ __forceinline__ void pipe_load(PipeStage<B, P2> &st, const uint16_t *
   for (int i = 0; i < LE / 8; ++i) st.lc[i] = reinterpret_cast<const uint4 *>(lcol + lq)[i];
 #pragma unroll
   for (int i = 0; i < LE / 4; ++i) {
-    const uint4 a = reinterpret_cast<const uint4 *>(val2 + lq)[i];
+    const uint4 a = reinterpret_cast<const uint4 *>(val + lq)[i];
     __builtin_memcpy(st.lv + 4 * i, &a, 16);
   }
-  if constexpr (P2) {
-    st.rlo = 0;
-    st.rhi = 0;
-    pipe_vload<PipeStage<B, P2>::NO>(yrow, st.yp);
-  } else {
-    st.rlo = q0 - qr;
-    st.rhi = q1 - qr;
-    const int rq = st.rhi > 0 ? qr : 0;
-    const uint2 c = *reinterpret_cast<const uint2 *>(col2 + rq);
-    const float2 v = *reinterpret_cast<const float2 *>(val2 + rq);
-    __builtin_memcpy(st.rc, &c, 8);
-    __builtin_memcpy(st.rv, &v, 8);
-  }
+  if constexpr (P2) pipe_vload<PipeStage<B, P2>::NO>(yrow, st.yp);
 }
 
-// Row loads of the pipelined kernel.  With par = 1 (odd lanes of pass 1 at
-// B = 8) the lane keeps its sums rotated by four components (v[a] holds
-// component (a + 4) % 8): the first 16-byte half it reads is the row's
-// second, so the lanes of one LDS read spread over twice as many bank
-// positions.  The row reduction undoes it.
+// Row loads from LDS.  With par = 1 (odd lanes of pass 1 at B = 8) the lane
+// keeps its sums rotated by four components (v[a] holds component
+// (a + 4) % 8): the first 16-byte half it reads is the row's second, so the
+// lanes of one LDS read spread over twice as many bank positions.  The row
+// reduction undoes it.
 template <int B>
 __device__ __forceinline__ void pipe_row(const float *p, int par, float (&v)[B]) {
   if constexpr (B == 8) {
@@ -866,19 +849,16 @@ __device__ __forceinline__ int pipe_lidx(const uint4 (&c)[N], int e) {
 }
 
 // Pass 1 (P2 = false) or pass 2 (P2 = true) over the row groups; `blocks`
-// has 2 slots entries per group (set A, then set B).  Row positions are
-// 32-bit offsets from the group's first entry rounded down to a multiple of
-// 8: pass 1's descriptors are {first entry, first set-B entry, first remote
-// entry, end}, pass 2's {first, end} of the row in the set-B copy.
-//
-// Pass 1 streams the plan's reordered arrays (rows at H's row offsets, base
-// = rp, descriptors rdesc [n][4]); pass 2 the dense copy of the set-B entries
-// (base = the plan's per-group offsets into it, descriptors [n][2]).
+// has 2 slots entries per group (set A, then set B).  Pass 1 streams the
+// plan's reordered arrays (rows at H's row offsets; bases = rp; descriptors
+// [n][4], of which it uses {first entry, first set-B entry}); pass 2 the
+// dense copy of the set-B entries (bases = the plan's per-group offsets into
+// it; descriptors [n][2] = {first, end}).  Row positions are 32-bit offsets
+// from the group's first entry rounded down to a multiple of 8.
 template <int B, bool P2>
-__global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int slots, int parts,
+__global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int slots,
                                                     const int64_t *__restrict__ bases,
-                                                    const int32_t *__restrict__ col2,
-                                                    const float *__restrict__ val2,
+                                                    const float *__restrict__ val,
                                                     const uint16_t *__restrict__ lcol,
                                                     const int32_t *__restrict__ rdesc,
                                                     const int32_t *__restrict__ blocks,
@@ -890,16 +870,12 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
   static_assert(!P2 || B >= LPR, "pass 2 keeps whole components per lane");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const float *sX = reinterpret_cast<const float *>(smem_raw);
-  const int64_t L = xcd_block(blockIdx.x);
-  const int64_t g = L / parts, part = L % parts;
-  const int64_t gr0 = g * G;
-  if (gr0 >= n) return;  // grid padding: the whole workgroup leaves
-  const int64_t slice = (G + parts - 1) / parts;
-  const int64_t r0 = gr0 + part * slice;
-  const int nr = (int)(min(min(n, gr0 + G), r0 + slice) - r0);
-  if (nr <= 0) return;
+  const int64_t g = xcd_block(blockIdx.x);
+  const int64_t r0 = g * G;
+  if (r0 >= n) return;  // grid padding: the whole workgroup leaves
+  const int nr = (int)(min(n, r0 + G) - r0);
   constexpr int RPW = kWave / LPR;
-  constexpr int LCH = LE * LPR, RCH = kPipeRE * LPR;
+  constexpr int LCH = LE * LPR;
   const int lane = threadIdx.x & (kWave - 1);
   const int sub = lane & (LPR - 1);
   const int wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
@@ -907,25 +883,11 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
   const int zrow = slots * (int)G;  // the all-zero LDS row
   const int par = (B == 8 && LPR == 16) ? (sub & 1) : 0;
   const int cb = NO * sub;          // first of the lane's sums after the reduction (B >= LPR)
-  const int64_t base = bases[P2 ? g : gr0] & ~(int64_t)7;
+  const int64_t base = bases[P2 ? g : r0] & ~(int64_t)7;
   const uint16_t *lc_b = lcol + base;
-  const float *v_b = val2 + base;
-  const int32_t *c_b = P2 ? col2 : col2 + base;  // pass 2 has no remote entries
+  const float *v_b = val + base;
   const Desc *desc = reinterpret_cast<const Desc *>(rdesc) + r0;
   float *Yw = Y + r0 * B;
-  // the row's staged range [p0, pl) and remote range [q0, q1) in this pass
-  auto ranges = [&](const Desc &d, int &p0, int &pl, int &q0, int &q1) {
-    if constexpr (P2) {
-      p0 = d.x;
-      pl = d.y;
-      q0 = q1 = d.y;
-    } else {
-      p0 = d.x;
-      pl = d.y;
-      q0 = d.z;
-      q1 = d.w;
-    }
-  };
   auto yrow = [&](int r) { return Yw + (int64_t)(r < nr ? r : 0) * B + (B >= LPR ? cb : 0); };
 
   // this row group's first row (relative to r0) and the descriptor of its second
@@ -933,12 +895,10 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
   int nrow = row + stride;
   const Desc d0 = desc[row < nr ? row : 0];
   Desc dn = desc[nrow < nr ? nrow : 0];
-  int p0, pl, q0, q1;
-  ranges(d0, p0, pl, q0, q1);
-  int qlb = p0 & ~(LE - 1), qrb = q0 & ~(kPipeRE - 1);
+  int pl = d0.y;
+  int qlb = d0.x & ~(LE - 1);
   Stage cur;
-  pipe_load<B, P2>(cur, lc_b, v_b, c_b, qlb + LE * sub, qrb + kPipeRE * sub, p0, pl, q0, q1,
-                   yrow(row));
+  pipe_load<B, P2>(cur, lc_b, v_b, qlb + LE * sub, d0.x, pl, yrow(row));
 
   // stage the set's column blocks: every load of the fill first, then the writes
   {
@@ -992,64 +952,40 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
         if (a % LPR == sub) yp[a] = out[a];
     }
   };
-  float rx[P2 ? 1 : kPipeRE][B], rh[P2 ? 1 : kPipeRE];  // remote rows in flight (pass 1)
-  bool rpend = false;
   // One step on the entries in `cur`, loading the following step into `nxt`;
   // false once the group has no rows left.  The loop below alternates the two
   // buffers so that no load result is copied between registers (a copy would
   // wait for the load).  Per step, in issue order: the pending store, the
-  // remote gathers, the loads of the next step and the next descriptor.
+  // loads of the next step and the next descriptor.
   auto step = [&](const Stage &cur, Stage &nxt) __attribute__((always_inline)) {
     // everything the previous step loaded (this step's entries and the next
     // descriptor) is needed now; waiting here, before the pending store, keeps
     // that store out of the wait
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     // where the next step starts: the rest of this row, else the group's next row
-    const bool last = qlb + LCH >= pl && (P2 || qrb + RCH >= q1);
+    const bool last = qlb + LCH >= pl;
     const bool more = !last || nrow < nr;
-    int sp0 = 0, spl = pl, sq0 = q0, sq1 = q1, sqlb = qlb + LCH, sqrb = qrb + RCH;
+    int sp0 = 0, spl = pl, sqlb = qlb + LCH;
     int srow = row;
     if (last) {
-      ranges(dn, sp0, spl, sq0, sq1);
+      sp0 = dn.x;
+      spl = dn.y;
       sqlb = sp0 & ~(LE - 1);
-      sqrb = sq0 & ~(kPipeRE - 1);
       srow = nrow;
     }
-    if (!more) sp0 = spl = sq0 = sq1 = sqlb = sqrb = 0;  // nothing left: empty ranges
+    if (!more) sp0 = spl = sqlb = 0;  // nothing left: an empty range
     if (yp) {
       store_out();
       yp = nullptr;
     }
-    if constexpr (!P2) {
-      // remote products gathered by the previous step of this row: that
-      // step's later loads have arrived, so these have too
-      if (rpend) {
-#pragma unroll
-        for (int e = 0; e < kPipeRE; ++e)
-#pragma unroll
-          for (int a = 0; a < B; ++a) acc[a] = fmaf(rh[e], rx[e][a], acc[a]);
-      }
-      // remote gathers of this step, multiplied in at the start of the row's
-      // next step (or at the end of this one if it is the row's last)
-      rpend = cur.rhi > 0 && cur.rlo < kPipeRE;
-#pragma unroll
-      for (int e = 0; e < kPipeRE; ++e) {
-        const bool ok = cur.rlo <= e && e < cur.rhi;
-        rh[e] = ok ? cur.rv[e] : 0.0f;
-#pragma unroll
-        for (int a = 0; a < B; ++a) rx[e][a] = 0.0f;
-        if (ok) pipe_row<B>(X + (int64_t)cur.rc[e] * B, par, rx[e]);
-      }
-    }
-    pipe_load<B, P2>(nxt, lc_b, v_b, c_b, sqlb + LE * sub, sqrb + kPipeRE * sub, sp0, spl, sq0,
-                     sq1, yrow(srow));
+    pipe_load<B, P2>(nxt, lc_b, v_b, sqlb + LE * sub, sp0, spl, yrow(srow));
     // the descriptor of the row after the one the next step works on
     {
       const int r = last ? nrow + stride : nrow;
       dn = desc[r < nr ? r : 0];
     }
-    // staged entries, LG LDS rows at a time (fewer in pass 2, whose lanes hold
-    // more sums and stage data)
+    // the step's entries, LG LDS rows at a time (fewer in pass 2, whose lanes
+    // hold more entries and sums)
     constexpr int LG = P2 ? 2 : 4;
 #pragma unroll
     for (int hf = 0; hf < LE; hf += LG) {
@@ -1068,15 +1004,6 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
         for (int a = 0; a < B; ++a) acc[a] = fmaf(h[e], lx[e][a], acc[a]);
     }
     if (last) {
-      if constexpr (!P2) {
-        if (rpend) {
-#pragma unroll
-          for (int e = 0; e < kPipeRE; ++e)
-#pragma unroll
-            for (int a = 0; a < B; ++a) acc[a] = fmaf(rh[e], rx[e][a], acc[a]);
-          rpend = false;
-        }
-      }
       yp = Yw + (int64_t)row * B;
       if constexpr (B == 8 && LPR == 16) {
         // halving exchange between lanes of equal parity: afterwards lane sub
@@ -1133,16 +1060,53 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
       nrow += stride;
     }
     pl = spl;
-    q0 = sq0;
-    q1 = sq1;
     qlb = sqlb;
-    qrb = sqrb;
     return more;
   };
   Stage alt;
   while (step(cur, alt) && step(alt, cur)) {
   }
   store_out();  // the last row's sums
+}
+
+// Pass 3: one lane per row adds the products of the row's remaining entries
+// (outside both staged sets, read in place from the plan's arrays at
+// descriptor offsets {.z, .w}), gathering those rows of V.
+template <int B>
+__global__ __launch_bounds__(256) void k_spmm_rest(int64_t n, int64_t G,
+                                                   const int64_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ rdesc,
+                                                   const int32_t *__restrict__ col2,
+                                                   const float *__restrict__ val2,
+                                                   const float *__restrict__ X,
+                                                   float *__restrict__ Y) {
+  const int64_t row = (int64_t)xcd_block(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  const int4 d = reinterpret_cast<const int4 *>(rdesc)[row];
+  if (d.z >= d.w) return;
+  const int64_t base = rp[(row / G) * G] & ~(int64_t)7;
+  float acc[B];
+#pragma unroll
+  for (int a = 0; a < B; ++a) acc[a] = 0.0f;
+  for (int64_t q = base + d.z; q < base + d.w; ++q) {
+    float x[B];
+    RowIO<float, B>::load(X + (int64_t)col2[q] * B, x);
+    const float h = val2[q];
+#pragma unroll
+    for (int a = 0; a < B; ++a) acc[a] = fmaf(h, x[a], acc[a]);
+  }
+  float y[B];
+  RowIO<float, B>::load(Y + row * B, y);
+#pragma unroll
+  for (int a = 0; a < B; ++a) y[a] += acc[a];
+  if constexpr ((int)sizeof(float) * B % 16 == 0) {
+#pragma unroll
+    for (int i = 0; i < B / 4; ++i)
+      reinterpret_cast<float4 *>(Y + row * B)[i] = make_float4(y[4 * i], y[4 * i + 1], y[4 * i + 2], y[4 * i + 3]);
+  } else {
+#pragma unroll
+    for (int a = 0; a < B; ++a) Y[row * B + a] = y[a];
+  }
 }
 
 constexpr int kPlanThreads = 1024;
@@ -1174,7 +1138,7 @@ void planned_launch_t(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s)
 }
 
 template <int BV, bool P2>
-void pipe_pass(const bbl_spmm_plan &P, int parts, const float *X, float *Y, hipStream_t s) {
+void pipe_pass(const bbl_spmm_plan &P, const float *X, float *Y, hipStream_t s) {
   auto kern = k_spmm_pipe<BV, P2>;
   const size_t lds = ((size_t)P.slots * P.block_rows + 1) * BV * sizeof(float);
   static bool attr_set = false;
@@ -1184,25 +1148,30 @@ void pipe_pass(const bbl_spmm_plan &P, int parts, const float *X, float *Y, hipS
     attr_set = true;
   }
   const int64_t groups = ceil_div(P.n, P.block_rows);
-  const int64_t grid = ceil_div(groups * parts, kXcds) * kXcds;
+  const int64_t grid = ceil_div(groups, kXcds) * kXcds;
   if (P2)
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPlanThreads), lds, s, P.n,
-                       (int64_t)P.block_rows, P.slots, parts, P.bgroup, P.col,
+                       (int64_t)P.block_rows, P.slots, P.bgroup,
                        static_cast<const float *>(P.bval), P.blcol, P.brow, P.blocks, X, Y);
   else
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPlanThreads), lds, s, P.n,
-                       (int64_t)P.block_rows, P.slots, parts, P.row_ptr, P.col,
+                       (int64_t)P.block_rows, P.slots, P.row_ptr,
                        static_cast<const float *>(P.val), P.lcol, P.rdesc, P.blocks, X, Y);
   check_launch(P2 ? "k_spmm_pipe (pass 2)" : "k_spmm_pipe (pass 1)");
 }
 
 // Pass 1 takes most entries per row (16 lanes per row), pass 2 the set-B
-// tenth (2 lanes per row); one workgroup per group in both, so each set is
-// staged once per group.
+// tenth (2 lanes per row), one workgroup per group in both so each set is
+// staged once per group; pass 3 the rest, one lane per row.
 template <int BV>
 void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, hipStream_t s) {
-  pipe_pass<BV, false>(P, 1, X, Y, s);
-  pipe_pass<BV, true>(P, 1, X, Y, s);
+  pipe_pass<BV, false>(P, X, Y, s);
+  pipe_pass<BV, true>(P, X, Y, s);
+  const int64_t grid = ceil_div(ceil_div(P.n, 256), kXcds) * kXcds;
+  hipLaunchKernelGGL((k_spmm_rest<BV>), dim3((unsigned)grid), dim3(256), 0, s, P.n,
+                     (int64_t)P.block_rows, P.row_ptr, P.rdesc, P.col,
+                     static_cast<const float *>(P.val), X, Y);
+  check_launch("k_spmm_rest");
 }
 
 template <typename VT, typename XT, int BV>
