@@ -107,6 +107,11 @@ typedef struct {
                              to its group's first rounded down to a multiple of 8 */
   const uint16_t *blcol;  /* [nnz + 16] LDS index within set B of each copied entry */
   const void *bval;       /* [nnz + 16] its value (val_dtype) */
+  /* The rows with entries outside both sets (present with rdesc): group g's
+   * are rlist[rgroup[g] .. rgroup[g + 1]), each {row, count, first entry as
+   * two 32-bit words (low, high)}; their entries are the row's last. */
+  const int64_t *rgroup;  /* [groups + 1] */
+  const int32_t *rlist;   /* [n][4] */
 } bbl_spmm_plan;
 
 /* Solver options; a NULL pointer selects the defaults shown. */

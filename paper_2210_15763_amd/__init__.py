@@ -59,7 +59,8 @@ class _Plan(ctypes.Structure):
                 ("n_local", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
                 ("lcol", ctypes.c_void_p), ("rdesc", ctypes.c_void_p),
                 ("bgroup", ctypes.c_void_p), ("brow", ctypes.c_void_p),
-                ("blcol", ctypes.c_void_p), ("bval", ctypes.c_void_p)]
+                ("blcol", ctypes.c_void_p), ("bval", ctypes.c_void_p),
+                ("rgroup", ctypes.c_void_p), ("rlist", ctypes.c_void_p)]
 
 
 class _Stats(ctypes.Structure):

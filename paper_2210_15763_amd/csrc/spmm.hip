@@ -507,23 +507,25 @@ __global__ __launch_bounds__(256) void k_plan_rows(int64_t n, int64_t G, int slo
   }
 }
 
-// Dense copy of the set-B entries, rows in order, for the second pass.
+// Dense copy of the set-B entries, rows in order, for the second pass, and
+// the list of rows with entries outside both sets, for the third.  (See the
+// kernels' own comments.)
 // k_plan_bgroup (one workgroup per group): brow[2 r] = set-B entries of the
 // group's rows before r, bgroup[g + 1] = the group's total.  k_plan_gscan
 // (one workgroup): bgroup[g] = first copy entry of group g.  k_plan_bfill
 // (one wave per row): copies the row's set-B LDS indices and values and
 // leaves brow[r] = {first, end} relative to bgroup[g] rounded down to 8.
-__global__ __launch_bounds__(256) void k_plan_bgroup(int64_t n, int64_t G,
-                                                     int32_t *__restrict__ brow,
-                                                     int64_t *__restrict__ bgroup) {
-  __shared__ int64_t part[256];
-  const int64_t g = blockIdx.x;
-  const int64_t r0 = g * G, r1 = min(n, r0 + G);
+// Exclusive prefix over the group's rows of f(r) by one 256-thread
+// workgroup: each thread takes a contiguous run of rows; returns the group
+// total to every thread and calls put(r, prefix) for each row.
+template <typename F, typename Put>
+__device__ __forceinline__ int64_t group_scan(int64_t r0, int64_t r1, int64_t *part, F f,
+                                              Put put) {
   const int t = threadIdx.x;
   const int64_t per = (r1 - r0 + 255) / 256;
   const int64_t a0 = r0 + t * per, a1 = min(r1, a0 + per);
   int64_t sum = 0;
-  for (int64_t r = a0; r < a1; ++r) sum += brow[2 * r + 1];
+  for (int64_t r = a0; r < a1; ++r) sum += f(r);
   part[t] = sum;
   __syncthreads();
   for (int off = 1; off < 256; off <<= 1) {
@@ -534,12 +536,38 @@ __global__ __launch_bounds__(256) void k_plan_bgroup(int64_t n, int64_t G,
   }
   int64_t run = t > 0 ? part[t - 1] : 0;
   for (int64_t r = a0; r < a1; ++r) {
-    const int c = brow[2 * r + 1];
-    brow[2 * r] = (int)run;
+    const int64_t c = f(r);
+    put(r, run);
     run += c;
   }
-  if (t == 255) bgroup[g + 1] = part[255];
-  if (g == 0 && t == 0) bgroup[0] = 0;
+  const int64_t total = part[255];
+  __syncthreads();
+  return total;
+}
+
+// Also: rpos[r] = index of row r among the group's rows with entries outside
+// both sets (-1 if it has none), rgroup[g + 1] = their number.
+__global__ __launch_bounds__(256) void k_plan_bgroup(int64_t n, int64_t G,
+                                                     const int32_t *__restrict__ rdesc,
+                                                     int32_t *__restrict__ brow,
+                                                     int64_t *__restrict__ bgroup,
+                                                     int32_t *__restrict__ rpos,
+                                                     int64_t *__restrict__ rgroup) {
+  __shared__ int64_t part[256];
+  const int64_t g = blockIdx.x;
+  const int64_t r0 = g * G, r1 = min(n, r0 + G);
+  const int64_t nb = group_scan(
+      r0, r1, part, [&](int64_t r) { return (int64_t)brow[2 * r + 1]; },
+      [&](int64_t r, int64_t pre) { brow[2 * r] = (int)pre; });
+  auto has_rest = [&](int64_t r) { return (int64_t)(rdesc[4 * r + 3] > rdesc[4 * r + 2]); };
+  const int64_t nrest = group_scan(r0, r1, part, has_rest, [&](int64_t r, int64_t pre) {
+    rpos[r] = has_rest(r) ? (int)pre : -1;
+  });
+  if (threadIdx.x == 0) {
+    bgroup[g + 1] = nb;
+    rgroup[g + 1] = nrest;
+    if (g == 0) bgroup[0] = rgroup[0] = 0;
+  }
 }
 
 __global__ __launch_bounds__(1024) void k_plan_gscan(int64_t *__restrict__ a, int64_t m) {
@@ -574,7 +602,11 @@ __global__ __launch_bounds__(256) void k_plan_bfill(int64_t n, int64_t G,
                                                     const int64_t *__restrict__ bgroup,
                                                     int32_t *__restrict__ brow,
                                                     uint16_t *__restrict__ blcol,
-                                                    VT *__restrict__ bval) {
+                                                    VT *__restrict__ bval,
+                                                    const int32_t *__restrict__ rdesc,
+                                                    const int32_t *__restrict__ rpos,
+                                                    const int64_t *__restrict__ rgroup,
+                                                    int4 *__restrict__ rlist) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;  // uniform per wave
   const int lane = threadIdx.x & 63;
@@ -589,6 +621,13 @@ __global__ __launch_bounds__(256) void k_plan_bfill(int64_t n, int64_t G,
   if (lane == 0) {
     const int64_t gb = bgroup[g] & ~(int64_t)7;
     *reinterpret_cast<int2 *>(brow + 2 * row) = make_int2((int)(dst - gb), (int)(dst + cnt - gb));
+    if (rpos[row] >= 0) {
+      // {row, count, first entry (64-bit, low and high word)}
+      const int64_t first = (rp[g * G] & ~(int64_t)7) + rdesc[4 * row + 2];
+      rlist[rgroup[g] + rpos[row]] =
+          make_int4((int)row, rdesc[4 * row + 3] - rdesc[4 * row + 2], (int)(uint32_t)first,
+                    (int)(first >> 32));
+    }
   }
 }
 
@@ -1069,43 +1108,47 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
   store_out();  // the last row's sums
 }
 
-// Pass 3: one lane per row adds the products of the row's remaining entries
-// (outside both staged sets, read in place from the plan's arrays at
-// descriptor offsets {.z, .w}), gathering those rows of V.
+// Pass 3: one lane per listed row (rows with entries outside both staged
+// sets, {row, count, first entry}; the list's length is rgroup[groups]) adds
+// the products of those entries, read in place from the plan's arrays,
+// gathering the rows of V they need.  A grid-stride loop covers any length.
 template <int B>
-__global__ __launch_bounds__(256) void k_spmm_rest(int64_t n, int64_t G,
-                                                   const int64_t *__restrict__ rp,
-                                                   const int32_t *__restrict__ rdesc,
+__global__ __launch_bounds__(256) void k_spmm_rest(const int64_t *__restrict__ rgroup,
+                                                   int64_t groups,
+                                                   const int4 *__restrict__ rlist,
                                                    const int32_t *__restrict__ col2,
                                                    const float *__restrict__ val2,
                                                    const float *__restrict__ X,
                                                    float *__restrict__ Y) {
-  const int64_t row = (int64_t)xcd_block(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (row >= n) return;
-  const int4 d = reinterpret_cast<const int4 *>(rdesc)[row];
-  if (d.z >= d.w) return;
-  const int64_t base = rp[(row / G) * G] & ~(int64_t)7;
-  float acc[B];
+  const int64_t total = rgroup[groups];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int4 d = rlist[i];
+    const int64_t row = d.x;
+    const int64_t first = (int64_t)(uint32_t)d.z | ((int64_t)d.w << 32);
+    float y[B];
+    RowIO<float, B>::load(Y + row * B, y);
+    float acc[B];
 #pragma unroll
-  for (int a = 0; a < B; ++a) acc[a] = 0.0f;
-  for (int64_t q = base + d.z; q < base + d.w; ++q) {
-    float x[B];
-    RowIO<float, B>::load(X + (int64_t)col2[q] * B, x);
-    const float h = val2[q];
+    for (int a = 0; a < B; ++a) acc[a] = 0.0f;
+    for (int64_t q = first; q < first + d.y; ++q) {
+      float x[B];
+      RowIO<float, B>::load(X + (int64_t)col2[q] * B, x);
+      const float h = val2[q];
 #pragma unroll
-    for (int a = 0; a < B; ++a) acc[a] = fmaf(h, x[a], acc[a]);
-  }
-  float y[B];
-  RowIO<float, B>::load(Y + row * B, y);
+      for (int a = 0; a < B; ++a) acc[a] = fmaf(h, x[a], acc[a]);
+    }
 #pragma unroll
-  for (int a = 0; a < B; ++a) y[a] += acc[a];
-  if constexpr ((int)sizeof(float) * B % 16 == 0) {
+    for (int a = 0; a < B; ++a) y[a] += acc[a];
+    if constexpr ((int)sizeof(float) * B % 16 == 0) {
 #pragma unroll
-    for (int i = 0; i < B / 4; ++i)
-      reinterpret_cast<float4 *>(Y + row * B)[i] = make_float4(y[4 * i], y[4 * i + 1], y[4 * i + 2], y[4 * i + 3]);
-  } else {
+      for (int k = 0; k < B / 4; ++k)
+        reinterpret_cast<float4 *>(Y + row * B)[k] =
+            make_float4(y[4 * k], y[4 * k + 1], y[4 * k + 2], y[4 * k + 3]);
+    } else {
 #pragma unroll
-    for (int a = 0; a < B; ++a) Y[row * B + a] = y[a];
+      for (int a = 0; a < B; ++a) Y[row * B + a] = y[a];
+    }
   }
 }
 
@@ -1167,9 +1210,12 @@ template <int BV>
 void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, hipStream_t s) {
   pipe_pass<BV, false>(P, X, Y, s);
   pipe_pass<BV, true>(P, X, Y, s);
-  const int64_t grid = ceil_div(ceil_div(P.n, 256), kXcds) * kXcds;
-  hipLaunchKernelGGL((k_spmm_rest<BV>), dim3((unsigned)grid), dim3(256), 0, s, P.n,
-                     (int64_t)P.block_rows, P.row_ptr, P.rdesc, P.col,
+  // the list's length is on the device: a grid of at most 2048 workgroups
+  // strides over it
+  const int64_t groups = ceil_div(P.n, P.block_rows);
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(2048, ceil_div(P.n, 256)));
+  hipLaunchKernelGGL((k_spmm_rest<BV>), dim3((unsigned)grid), dim3(256), 0, s, P.rgroup, groups,
+                     reinterpret_cast<const int4 *>(P.rlist), P.col,
                      static_cast<const float *>(P.val), X, Y);
   check_launch("k_spmm_rest");
 }
@@ -1180,7 +1226,7 @@ void planned_launch(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s) {
                 (BV == 4 || BV == 8)) {
     // the pipelined kernel also keeps one all-zero row of V in LDS and takes
     // 32-bit entry offsets
-    if (P.local16 && P.lcol && P.rdesc && P.brow &&
+    if (P.local16 && P.lcol && P.rdesc && P.brow && P.rlist &&
         ((size_t)P.slots * P.block_rows + 1) * BV * sizeof(float) <= kPlanLds) {
       planned_launch_pipe<BV>(P, X, Y, s);
       return;
@@ -1308,7 +1354,8 @@ size_t spmm_plan_bytes(const bbl_csr &H, int nvec, int vec_dtype) {
          (plan_local16(H, slots) && plan_desc(H)
               ? align_up((size_t)H.n * 16) + align_up((size_t)H.n * 8) +
                     align_up((size_t)(groups + 1) * 8) + align_up((size_t)(H.nnz + 16) * 2) +
-                    align_up((size_t)(H.nnz + 16) * sv)
+                    align_up((size_t)(H.nnz + 16) * sv) + align_up((size_t)H.n * 4) +
+                    align_up((size_t)(groups + 1) * 8) + align_up((size_t)H.n * 16)
               : 0) +
          256;
 }
@@ -1342,6 +1389,9 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
   int64_t *bgroup = two ? reinterpret_cast<int64_t *>(take((size_t)(groups + 1) * 8)) : nullptr;
   uint16_t *blcol = two ? reinterpret_cast<uint16_t *>(take((size_t)(H.nnz + 16) * 2)) : nullptr;
   void *bval = two ? take((size_t)(H.nnz + 16) * sv) : nullptr;
+  int32_t *rpos = two ? reinterpret_cast<int32_t *>(take((size_t)H.n * 4)) : nullptr;
+  int64_t *rgroup = two ? reinterpret_cast<int64_t *>(take((size_t)(groups + 1) * 8)) : nullptr;
+  int32_t *rlist = two ? reinterpret_cast<int32_t *>(take((size_t)H.n * 16)) : nullptr;
   hipLaunchKernelGGL(k_plan_blocks, dim3((unsigned)groups), dim3(256), 0, s, H.n,
                      (int64_t)H.block_rows, width, H.row_ptr, H.col, blocks);
   const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(H.n, 4));
@@ -1357,18 +1407,21 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
                        static_cast<double *>(val2), lcol, rdesc, brow);
   if (two) {
     hipLaunchKernelGGL(k_plan_bgroup, dim3((unsigned)groups), dim3(256), 0, s, H.n,
-                       (int64_t)H.block_rows, brow, bgroup);
+                       (int64_t)H.block_rows, rdesc, brow, bgroup, rpos, rgroup);
     hipLaunchKernelGGL(k_plan_gscan, dim3(1), dim3(1024), 0, s, bgroup, groups);
+    hipLaunchKernelGGL(k_plan_gscan, dim3(1), dim3(1024), 0, s, rgroup, groups);
     if (H.val_dtype == BBL_F32)
       hipLaunchKernelGGL((k_plan_bfill<float>), dim3(grid), dim3(256), 0, s, H.n,
                          (int64_t)H.block_rows, H.row_ptr, n_local, lcol,
                          static_cast<const float *>(val2), bgroup, brow, blcol,
-                         static_cast<float *>(bval));
+                         static_cast<float *>(bval), rdesc, rpos, rgroup,
+                         reinterpret_cast<int4 *>(rlist));
     else
       hipLaunchKernelGGL((k_plan_bfill<double>), dim3(grid), dim3(256), 0, s, H.n,
                          (int64_t)H.block_rows, H.row_ptr, n_local, lcol,
                          static_cast<const double *>(val2), bgroup, brow, blcol,
-                         static_cast<double *>(bval));
+                         static_cast<double *>(bval), rdesc, rpos, rgroup,
+                         reinterpret_cast<int4 *>(rlist));
   }
   check_launch("spmm plan");
   P->n = H.n;
@@ -1390,6 +1443,8 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
   P->brow = brow;
   P->blcol = blcol;
   P->bval = bval;
+  P->rgroup = rgroup;
+  P->rlist = rlist;
 }
 
 void launch_spmm_planned(const bbl_spmm_plan &P, const void *X, void *Y, hipStream_t s) {

@@ -193,6 +193,18 @@ def test_spmm_plan_layout_and_errors(torch, bbl):
     val2 = plan.mem[ov:ov + 4 * H.nnz].view(torch.float32).cpu().numpy()
     bv = plan.mem[obv:obv + 4 * nb_all].view(torch.float32).cpu().numpy()
     assert np.array_equal(bl, lcol[inb]) and np.array_equal(bv, val2[inb])
+    # the list of rows with entries outside both sets: {row, count, first}
+    org = plan.c.rgroup - plan.mem.data_ptr()
+    rg = plan.mem[org:org + 8 * 31].view(torch.int64).cpu().numpy()
+    has = d[:, 3] > d[:, 2]
+    assert rg[0] == 0 and np.array_equal(np.diff(rg), np.add.reduceat(has.astype(np.int64), np.arange(0, H.n, G)))
+    orl = plan.c.rlist - plan.mem.data_ptr()
+    rl = plan.mem[orl:orl + 16 * int(rg[-1])].view(torch.int32).cpu().numpy().reshape(-1, 4)
+    want = np.nonzero(has)[0]
+    assert np.array_equal(rl[:, 0], want)
+    assert np.array_equal(rl[:, 1], (d[want, 3] - d[want, 2]))
+    firsts = (rl[:, 2].astype(np.int64) & 0xffffffff) | (rl[:, 3].astype(np.int64) << 32)
+    assert np.array_equal(firsts, gb[want] + d[want, 2])
     # the (row, column) pairs outside set A are those of H
     ocol = np.asarray(H.col).astype(np.int64)
     nota = ~(ocol[:, None] // 400 == blk[rows // 400, :S]).any(axis=1)
