@@ -99,10 +99,15 @@ typedef struct {
                              first remaining entry and end, as offsets from the
                              group's first entry rounded down to a multiple of 8;
                              present with lcol when nnz < 2^31, else NULL */
-  /* A dense copy of the set-B entries (present with rdesc, else NULL), read
-   * by the second pass of the FP32 SpMM: each group's rows in order with no
-   * gaps. */
-  const int64_t *bgroup;  /* [groups + 1] first copy entry of each group's rows */
+  /* Dense copies of the set-A and set-B entries (present with rdesc, else
+   * NULL), read by the first and second passes of the FP32 SpMM: each
+   * group's rows in order with no gaps. */
+  const int64_t *agroup;  /* [groups + 1] first set-A copy entry of each group's rows */
+  const int32_t *arow;    /* [n][2] first and end set-A copy entry of each row, relative
+                             to its group's first rounded down to a multiple of 8 */
+  const uint16_t *alcol;  /* [nnz + 16] LDS index within set A of each copied entry */
+  const void *aval;       /* [nnz + 16] its value (val_dtype) */
+  const int64_t *bgroup;  /* [groups + 1] first set-B copy entry of each group's rows */
   const int32_t *brow;    /* [n][2] first and end copy entry of each row, relative
                              to its group's first rounded down to a multiple of 8 */
   const uint16_t *blcol;  /* [nnz + 16] LDS index within set B of each copied entry */

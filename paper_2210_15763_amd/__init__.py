@@ -58,6 +58,8 @@ class _Plan(ctypes.Structure):
                 ("row_ptr", ctypes.c_void_p), ("blocks", ctypes.c_void_p),
                 ("n_local", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
                 ("lcol", ctypes.c_void_p), ("rdesc", ctypes.c_void_p),
+                ("agroup", ctypes.c_void_p), ("arow", ctypes.c_void_p),
+                ("alcol", ctypes.c_void_p), ("aval", ctypes.c_void_p),
                 ("bgroup", ctypes.c_void_p), ("brow", ctypes.c_void_p),
                 ("blcol", ctypes.c_void_p), ("bval", ctypes.c_void_p),
                 ("rgroup", ctypes.c_void_p), ("rlist", ctypes.c_void_p)]

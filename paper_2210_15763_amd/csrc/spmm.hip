@@ -507,14 +507,15 @@ __global__ __launch_bounds__(256) void k_plan_rows(int64_t n, int64_t G, int slo
   }
 }
 
-// Dense copy of the set-B entries, rows in order, for the second pass, and
-// the list of rows with entries outside both sets, for the third.  (See the
-// kernels' own comments.)
-// k_plan_bgroup (one workgroup per group): brow[2 r] = set-B entries of the
-// group's rows before r, bgroup[g + 1] = the group's total.  k_plan_gscan
-// (one workgroup): bgroup[g] = first copy entry of group g.  k_plan_bfill
-// (one wave per row): copies the row's set-B LDS indices and values and
-// leaves brow[r] = {first, end} relative to bgroup[g] rounded down to 8.
+// Dense copies of the set-A and set-B entries, rows in order, for the first
+// and second passes, and the list of rows with entries outside both sets,
+// for the third.  (See the kernels' own comments.)
+// k_plan_bgroup (one workgroup per group): arow[2 r] / brow[2 r] = set-A /
+// set-B entries of the group's rows before r, agroup[g + 1] / bgroup[g + 1] =
+// the group's totals.  k_plan_gscan (one workgroup): agroup[g] / bgroup[g] =
+// first copy entry of group g.  k_plan_bfill (one wave per row): copies the
+// row's LDS indices and values of both sets and leaves arow[r] / brow[r] =
+// {first, end} relative to agroup[g] / bgroup[g] rounded down to 8.
 // Exclusive prefix over the group's rows of f(r) by one 256-thread
 // workgroup: each thread takes a contiguous run of rows; returns the group
 // total to every thread and calls put(r, prefix) for each row.
@@ -549,6 +550,9 @@ __device__ __forceinline__ int64_t group_scan(int64_t r0, int64_t r1, int64_t *p
 // both sets (-1 if it has none), rgroup[g + 1] = their number.
 __global__ __launch_bounds__(256) void k_plan_bgroup(int64_t n, int64_t G,
                                                      const int32_t *__restrict__ rdesc,
+                                                     const int32_t *__restrict__ n_local,
+                                                     int32_t *__restrict__ arow,
+                                                     int64_t *__restrict__ agroup,
                                                      int32_t *__restrict__ brow,
                                                      int64_t *__restrict__ bgroup,
                                                      int32_t *__restrict__ rpos,
@@ -556,6 +560,9 @@ __global__ __launch_bounds__(256) void k_plan_bgroup(int64_t n, int64_t G,
   __shared__ int64_t part[256];
   const int64_t g = blockIdx.x;
   const int64_t r0 = g * G, r1 = min(n, r0 + G);
+  const int64_t na = group_scan(
+      r0, r1, part, [&](int64_t r) { return (int64_t)n_local[r]; },
+      [&](int64_t r, int64_t pre) { arow[2 * r] = (int)pre; });
   const int64_t nb = group_scan(
       r0, r1, part, [&](int64_t r) { return (int64_t)brow[2 * r + 1]; },
       [&](int64_t r, int64_t pre) { brow[2 * r] = (int)pre; });
@@ -564,9 +571,10 @@ __global__ __launch_bounds__(256) void k_plan_bgroup(int64_t n, int64_t G,
     rpos[r] = has_rest(r) ? (int)pre : -1;
   });
   if (threadIdx.x == 0) {
+    agroup[g + 1] = na;
     bgroup[g + 1] = nb;
     rgroup[g + 1] = nrest;
-    if (g == 0) bgroup[0] = rgroup[0] = 0;
+    if (g == 0) agroup[0] = bgroup[0] = rgroup[0] = 0;
   }
 }
 
@@ -599,6 +607,10 @@ __global__ __launch_bounds__(256) void k_plan_bfill(int64_t n, int64_t G,
                                                     const int32_t *__restrict__ n_local,
                                                     const uint16_t *__restrict__ lcol,
                                                     const VT *__restrict__ val2,
+                                                    const int64_t *__restrict__ agroup,
+                                                    int32_t *__restrict__ arow,
+                                                    uint16_t *__restrict__ alcol,
+                                                    VT *__restrict__ aval,
                                                     const int64_t *__restrict__ bgroup,
                                                     int32_t *__restrict__ brow,
                                                     uint16_t *__restrict__ blcol,
@@ -611,7 +623,13 @@ __global__ __launch_bounds__(256) void k_plan_bfill(int64_t n, int64_t G,
   if (row >= n) return;  // uniform per wave
   const int lane = threadIdx.x & 63;
   const int64_t g = row / G;
-  const int64_t src = rp[row] + n_local[row];
+  const int na = n_local[row];
+  const int64_t asrc = rp[row], adst = agroup[g] + arow[2 * row];
+  for (int i = lane; i < na; i += 64) {
+    alcol[adst + i] = lcol[asrc + i];
+    aval[adst + i] = val2[asrc + i];
+  }
+  const int64_t src = asrc + na;
   const int cnt = brow[2 * row + 1];
   const int64_t dst = bgroup[g] + brow[2 * row];
   for (int i = lane; i < cnt; i += 64) {
@@ -619,6 +637,8 @@ __global__ __launch_bounds__(256) void k_plan_bfill(int64_t n, int64_t G,
     bval[dst + i] = val2[src + i];
   }
   if (lane == 0) {
+    const int64_t ga = agroup[g] & ~(int64_t)7;
+    *reinterpret_cast<int2 *>(arow + 2 * row) = make_int2((int)(adst - ga), (int)(adst + na - ga));
     const int64_t gb = bgroup[g] & ~(int64_t)7;
     *reinterpret_cast<int2 *>(brow + 2 * row) = make_int2((int)(dst - gb), (int)(dst + cnt - gb));
     if (rpos[row] >= 0) {
@@ -888,12 +908,10 @@ __device__ __forceinline__ int pipe_lidx(const uint4 (&c)[N], int e) {
 }
 
 // Pass 1 (P2 = false) or pass 2 (P2 = true) over the row groups; `blocks`
-// has 2 slots entries per group (set A, then set B).  Pass 1 streams the
-// plan's reordered arrays (rows at H's row offsets; bases = rp; descriptors
-// [n][4], of which it uses {first entry, first set-B entry}); pass 2 the
-// dense copy of the set-B entries (bases = the plan's per-group offsets into
-// it; descriptors [n][2] = {first, end}).  Row positions are 32-bit offsets
-// from the group's first entry rounded down to a multiple of 8.
+// has 2 slots entries per group (set A, then set B).  Each pass streams the
+// plan's dense copy of its set's entries: bases = the per-group offsets into
+// it, descriptors [n][2] = {first, end} of each row as 32-bit offsets from
+// its group's first entry rounded down to a multiple of 8.
 template <int B, bool P2>
 __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int slots,
                                                     const int64_t *__restrict__ bases,
@@ -903,7 +921,7 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
                                                     const int32_t *__restrict__ blocks,
                                                     const float *__restrict__ X,
                                                     float *__restrict__ Y) {
-  using Desc = typename std::conditional<P2, int2, int4>::type;
+  using Desc = int2;
   using Stage = PipeStage<B, P2>;
   constexpr int LPR = Stage::LPR, NO = Stage::NO, LE = Stage::LE;
   static_assert(!P2 || B >= LPR, "pass 2 keeps whole components per lane");
@@ -922,7 +940,7 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
   const int zrow = slots * (int)G;  // the all-zero LDS row
   const int par = (B == 8 && LPR == 16) ? (sub & 1) : 0;
   const int cb = NO * sub;          // first of the lane's sums after the reduction (B >= LPR)
-  const int64_t base = bases[P2 ? g : r0] & ~(int64_t)7;
+  const int64_t base = bases[g] & ~(int64_t)7;
   const uint16_t *lc_b = lcol + base;
   const float *v_b = val + base;
   const Desc *desc = reinterpret_cast<const Desc *>(rdesc) + r0;
@@ -1198,8 +1216,8 @@ void pipe_pass(const bbl_spmm_plan &P, const float *X, float *Y, hipStream_t s) 
                        static_cast<const float *>(P.bval), P.blcol, P.brow, P.blocks, X, Y);
   else
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPlanThreads), lds, s, P.n,
-                       (int64_t)P.block_rows, P.slots, P.row_ptr,
-                       static_cast<const float *>(P.val), P.lcol, P.rdesc, P.blocks, X, Y);
+                       (int64_t)P.block_rows, P.slots, P.agroup,
+                       static_cast<const float *>(P.aval), P.alcol, P.arow, P.blocks, X, Y);
   check_launch(P2 ? "k_spmm_pipe (pass 2)" : "k_spmm_pipe (pass 1)");
 }
 
@@ -1226,7 +1244,7 @@ void planned_launch(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s) {
                 (BV == 4 || BV == 8)) {
     // the pipelined kernel also keeps one all-zero row of V in LDS and takes
     // 32-bit entry offsets
-    if (P.local16 && P.lcol && P.rdesc && P.brow && P.rlist &&
+    if (P.local16 && P.lcol && P.rdesc && P.arow && P.brow && P.rlist &&
         ((size_t)P.slots * P.block_rows + 1) * BV * sizeof(float) <= kPlanLds) {
       planned_launch_pipe<BV>(P, X, Y, s);
       return;
@@ -1355,7 +1373,9 @@ size_t spmm_plan_bytes(const bbl_csr &H, int nvec, int vec_dtype) {
               ? align_up((size_t)H.n * 16) + align_up((size_t)H.n * 8) +
                     align_up((size_t)(groups + 1) * 8) + align_up((size_t)(H.nnz + 16) * 2) +
                     align_up((size_t)(H.nnz + 16) * sv) + align_up((size_t)H.n * 4) +
-                    align_up((size_t)(groups + 1) * 8) + align_up((size_t)H.n * 16)
+                    align_up((size_t)(groups + 1) * 8) + align_up((size_t)H.n * 16) +
+                    align_up((size_t)H.n * 8) + align_up((size_t)(groups + 1) * 8) +
+                    align_up((size_t)(H.nnz + 16) * 2) + align_up((size_t)(H.nnz + 16) * sv)
               : 0) +
          256;
 }
@@ -1385,6 +1405,10 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
   uint16_t *lcol = l16 ? reinterpret_cast<uint16_t *>(take((size_t)(H.nnz + 16) * 2)) : nullptr;
   const bool two = l16 && plan_desc(H);
   int32_t *rdesc = two ? reinterpret_cast<int32_t *>(take((size_t)H.n * 16)) : nullptr;
+  int32_t *arow = two ? reinterpret_cast<int32_t *>(take((size_t)H.n * 8)) : nullptr;
+  int64_t *agroup = two ? reinterpret_cast<int64_t *>(take((size_t)(groups + 1) * 8)) : nullptr;
+  uint16_t *alcol = two ? reinterpret_cast<uint16_t *>(take((size_t)(H.nnz + 16) * 2)) : nullptr;
+  void *aval = two ? take((size_t)(H.nnz + 16) * sv) : nullptr;
   int32_t *brow = two ? reinterpret_cast<int32_t *>(take((size_t)H.n * 8)) : nullptr;
   int64_t *bgroup = two ? reinterpret_cast<int64_t *>(take((size_t)(groups + 1) * 8)) : nullptr;
   uint16_t *blcol = two ? reinterpret_cast<uint16_t *>(take((size_t)(H.nnz + 16) * 2)) : nullptr;
@@ -1407,19 +1431,23 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
                        static_cast<double *>(val2), lcol, rdesc, brow);
   if (two) {
     hipLaunchKernelGGL(k_plan_bgroup, dim3((unsigned)groups), dim3(256), 0, s, H.n,
-                       (int64_t)H.block_rows, rdesc, brow, bgroup, rpos, rgroup);
+                       (int64_t)H.block_rows, rdesc, n_local, arow, agroup, brow, bgroup, rpos,
+                       rgroup);
+    hipLaunchKernelGGL(k_plan_gscan, dim3(1), dim3(1024), 0, s, agroup, groups);
     hipLaunchKernelGGL(k_plan_gscan, dim3(1), dim3(1024), 0, s, bgroup, groups);
     hipLaunchKernelGGL(k_plan_gscan, dim3(1), dim3(1024), 0, s, rgroup, groups);
     if (H.val_dtype == BBL_F32)
       hipLaunchKernelGGL((k_plan_bfill<float>), dim3(grid), dim3(256), 0, s, H.n,
                          (int64_t)H.block_rows, H.row_ptr, n_local, lcol,
-                         static_cast<const float *>(val2), bgroup, brow, blcol,
+                         static_cast<const float *>(val2), agroup, arow, alcol,
+                         static_cast<float *>(aval), bgroup, brow, blcol,
                          static_cast<float *>(bval), rdesc, rpos, rgroup,
                          reinterpret_cast<int4 *>(rlist));
     else
       hipLaunchKernelGGL((k_plan_bfill<double>), dim3(grid), dim3(256), 0, s, H.n,
                          (int64_t)H.block_rows, H.row_ptr, n_local, lcol,
-                         static_cast<const double *>(val2), bgroup, brow, blcol,
+                         static_cast<const double *>(val2), agroup, arow, alcol,
+                         static_cast<double *>(aval), bgroup, brow, blcol,
                          static_cast<double *>(bval), rdesc, rpos, rgroup,
                          reinterpret_cast<int4 *>(rlist));
   }
@@ -1439,6 +1467,10 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
   P->val = val2;
   P->lcol = lcol;
   P->rdesc = rdesc;
+  P->agroup = agroup;
+  P->arow = arow;
+  P->alcol = alcol;
+  P->aval = aval;
   P->bgroup = bgroup;
   P->brow = brow;
   P->blcol = blcol;

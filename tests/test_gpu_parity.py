@@ -193,6 +193,21 @@ def test_spmm_plan_layout_and_errors(torch, bbl):
     val2 = plan.mem[ov:ov + 4 * H.nnz].view(torch.float32).cpu().numpy()
     bv = plan.mem[obv:obv + 4 * nb_all].view(torch.float32).cpu().numpy()
     assert np.array_equal(bl, lcol[inb]) and np.array_equal(bv, val2[inb])
+    # the dense copy of the set-A entries, likewise
+    oag = plan.c.agroup - plan.mem.data_ptr()
+    ag = plan.mem[oag:oag + 8 * 31].view(torch.int64).cpu().numpy()
+    oar = plan.c.arow - plan.mem.data_ptr()
+    ar = plan.mem[oar:oar + 8 * H.n].view(torch.int32).cpu().numpy().reshape(-1, 2).astype(np.int64)
+    assert ag[0] == 0 and np.array_equal(np.diff(ag), np.add.reduceat(nl.astype(np.int64), np.arange(0, H.n, G)))
+    assert np.array_equal(ar[:, 1] - ar[:, 0], nl)
+    afirst = (ag[np.arange(H.n) // G] & ~7) + ar[:, 0]
+    assert np.array_equal(afirst[1:], (afirst + nl)[:-1])
+    na_all = int(ag[-1])
+    oal = plan.c.alcol - plan.mem.data_ptr()
+    oav = plan.c.aval - plan.mem.data_ptr()
+    al = plan.mem[oal:oal + 2 * na_all].view(torch.int16).cpu().numpy().view(np.uint16)
+    av = plan.mem[oav:oav + 4 * na_all].view(torch.float32).cpu().numpy()
+    assert np.array_equal(al, lcol[staged]) and np.array_equal(av, val2[staged])
     # the list of rows with entries outside both sets: {row, count, first}
     org = plan.c.rgroup - plan.mem.data_ptr()
     rg = plan.mem[org:org + 8 * 31].view(torch.int64).cpu().numpy()
