@@ -655,10 +655,11 @@ int gram_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const 
     // 64 basis columns per one-wave workgroup; about 6k workgroups in all, so
     // that the whole grid is resident at once (measured on MI355X at n = 2e6:
     // 45, 90 and 181 blocks run fastest with 1024, 512 and 256 row chunks,
-    // 5.1-5.3 TB/s)
+    // 5.1-5.3 TB/s; 20 blocks with 2048 chunks, 4.8 TB/s against 3.6 with
+    // 1024)
     constexpr int CG = 1, U = 2;
     const int gy = (M + 64 * CG - 1) / (64 * CG);
-    int64_t gx = std::min<int64_t>(1024, ceil_div(6144, gy));
+    int64_t gx = std::min<int64_t>(2048, ceil_div(6144, gy));
     gx = std::max<int64_t>(1, std::min<int64_t>(gx, ceil_div(n, 256)));
     gx = std::min<int64_t>(gx, std::max(1, max_partials));
     int64_t chunk = ceil_div(ceil_div(n, gx), 4 * U) * (4 * U);
