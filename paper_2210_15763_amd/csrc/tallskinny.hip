@@ -573,6 +573,47 @@ __global__ __launch_bounds__(256) void k_update_v(int64_t n, const XT *X, int nb
   }
 }
 
+// Update for short row counts (a truncated problem): Yout = beta Yin +
+// alpha X C with the basis blocks split over the eight waves of a workgroup
+// (wave w takes blocks w, w + 8, ...; C stays wave-uniform) and one row per
+// lane, so the grid holds eight times as many waves as one row per lane over
+// all blocks would; the eight partial sums of each row are added in LDS in
+// fixed order, thread t finishing component t / 64 of row t % 64.
+template <typename XT, typename YIT, typename YOT, int BX, int NY>
+__global__ __launch_bounds__(512) void k_update_w8(int64_t n, const XT *X, int nblk,
+                                                   int64_t xstride, const double *__restrict__ C,
+                                                   double alpha, const YIT *Yin, double beta,
+                                                   YOT *Yout, const int *__restrict__ when) {
+  static_assert(NY <= 8, "one component per wave");
+  if (when && *when == 0) return;
+  __shared__ double part[8][64][NY];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t r = (int64_t)blockIdx.x * 64 + lane;
+  double acc[NY];
+#pragma unroll
+  for (int j = 0; j < NY; ++j) acc[j] = 0.0;
+  if (r < n) {
+    for (int blk = w; blk < nblk; blk += 8) {
+      const Vec<XT, BX> xv = vload<XT, BX>(X + (int64_t)blk * xstride + r * BX);
+      const double *cb = C + (int64_t)blk * BX * NY;
+#pragma unroll
+      for (int a = 0; a < BX; ++a)
+#pragma unroll
+        for (int j = 0; j < NY; ++j) acc[j] = fma((double)xv.v[a], cb[a * NY + j], acc[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NY; ++j) part[w][lane][j] = acc[j];
+  __syncthreads();
+  if (w < NY && r < n) {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v += part[q][lane][w];
+    const double o = beta != 0.0 ? fma(beta, (double)Yin[r * NY + w], alpha * v) : alpha * v;
+    Yout[r * NY + w] = (YOT)o;
+  }
+}
+
 // Two-stage fixed-order reduction of partial[P][MN]: stage 1 sums S
 // contiguous ranges of p, stage 2 sums the S results.
 __global__ __launch_bounds__(256) void k_reduce1(const double *__restrict__ partial, int P, int MN,
@@ -705,7 +746,17 @@ void update_valu(int64_t n, const XT *X, int nblk, int64_t xstride, const double
                  const YIT *Yin, double beta, YOT *Yout, const int *when, double *gpart,
                  hipStream_t s) {
   const int64_t grid = ceil_div(n, 256 * kUpdRPL);
-  // a short grid (few rows) walks many blocks per lane: prefetch four at a time
+  // a short grid (few rows) with many blocks: split the blocks over waves
+  // (no fused Gram then); a short grid with a few blocks: prefetch four at a
+  // time
+  if (grid < 512 && nblk >= 16 && NY <= 8) {
+    if constexpr (NY <= 8) {
+      hipLaunchKernelGGL((k_update_w8<XT, YIT, YOT, B, NY>), dim3((unsigned)ceil_div(n, 64)),
+                         dim3(512), 0, s, n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when);
+      check_launch("k_update_w8");
+      return;
+    }
+  }
   const bool pf = grid < 512 && nblk >= 8;
 #define BBL_UPDV(G, PF)                                                                        \
   hipLaunchKernelGGL((k_update_v<XT, YIT, YOT, B, NY, kUpdRPL, G, PF>), dim3((unsigned)grid),    \
@@ -733,10 +784,12 @@ int update_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, cons
     update_valu<XT, YIT, YOT, 8, 10>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s);
     return gpart ? P : 0;
   }
+  // the wave-split kernel (short grids, many blocks) leaves no Gram partials
+  const bool split = P < 512 && nblk >= 16 && ny <= 8;
   if (ny == bx) {
     switch (bx) {
-      case 4: update_valu<XT, YIT, YOT, 4>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s); return gpart ? P : 0;
-      case 8: update_valu<XT, YIT, YOT, 8>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s); return gpart ? P : 0;
+      case 4: update_valu<XT, YIT, YOT, 4>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s); return gpart && !split ? P : 0;
+      case 8: update_valu<XT, YIT, YOT, 8>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s); return gpart && !split ? P : 0;
       case 10: update_valu<XT, YIT, YOT, 10>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s); return gpart ? P : 0;
       case 16: update_valu<XT, YIT, YOT, 16>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s); return gpart ? P : 0;
       default: break;

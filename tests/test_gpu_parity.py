@@ -315,8 +315,10 @@ def test_spmm_bitwise_reproducible(torch, bbl):
                                              (10, 3, 10, True), (8, 1, 20, False),
                                              (8, 7, 8, False), (8, 9, 8, True), (8, 37, 8, True),
                                              (8, 1, 8, True), (8, 1, 8, False), (4, 1, 4, True),
-                                             (8, 23, 10, True), (8, 4, 10, False)])
+                                             (8, 23, 10, True), (8, 4, 10, False),
+                                             (4, 20, 4, False)])
 def test_gram_and_update_match_numpy(torch, bbl, bx, nblk, ny, xf32):
+    """(5003 rows with 16 or more blocks take the wave-split update.)"""
     note("gram/update bx=%d nblk=%d ny=%d f32=%s" % (bx, nblk, ny, xf32))
     rng = np.random.default_rng(bx * 100 + nblk)
     n = 5003  # several tiles plus a ragged tail
