@@ -1149,12 +1149,30 @@ __global__ __launch_bounds__(256) void k_spmm_rest(const int64_t *__restrict__ r
     float acc[B];
 #pragma unroll
     for (int a = 0; a < B; ++a) acc[a] = 0.0f;
-    for (int64_t q = first; q < first + d.y; ++q) {
-      float x[B];
-      RowIO<float, B>::load(X + (int64_t)col2[q] * B, x);
-      const float h = val2[q];
+    // eight entries at a time: their index and value loads, then their
+    // gathers, all in flight together (rows with many remaining entries would
+    // otherwise wait out one gather after another)
+    constexpr int U = 8;
+    for (int64_t q0 = first; q0 < first + d.y; q0 += U) {
+      int c[U];
+      float h[U];
 #pragma unroll
-      for (int a = 0; a < B; ++a) acc[a] = fmaf(h, x[a], acc[a]);
+      for (int e = 0; e < U; ++e) {
+        const bool ok = q0 + e < first + d.y;
+        c[e] = ok ? col2[q0 + e] : 0;
+        h[e] = ok ? val2[q0 + e] : 0.0f;
+      }
+      float x[U][B];
+#pragma unroll
+      for (int e = 0; e < U; ++e) {
+#pragma unroll
+        for (int a = 0; a < B; ++a) x[e][a] = 0.0f;
+        if (q0 + e < first + d.y) RowIO<float, B>::load(X + (int64_t)c[e] * B, x[e]);
+      }
+#pragma unroll
+      for (int e = 0; e < U; ++e)
+#pragma unroll
+        for (int a = 0; a < B; ++a) acc[a] = fmaf(h[e], x[e][a], acc[a]);
     }
 #pragma unroll
     for (int a = 0; a < B; ++a) y[a] += acc[a];
