@@ -1259,7 +1259,7 @@ void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, hipSt
 template <typename VT, typename XT, int BV>
 void planned_launch(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s) {
   if constexpr (std::is_same<VT, float>::value && std::is_same<XT, float>::value &&
-                (BV == 4 || BV == 8)) {
+                (BV == 4 || BV == 8 || BV == 10)) {
     // the pipelined kernel also keeps one all-zero row of V in LDS and takes
     // 32-bit entry offsets
     if (P.local16 && P.lcol && P.rdesc && P.arow && P.brow && P.rlist &&
