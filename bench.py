@@ -126,13 +126,13 @@ def _per_dispatch(rows, counter, match):
     return float(np.mean(list(per.values()))), len(per)
 
 
-SPMM_PASSES = ("k_spmm_pipe<8, false>", "k_spmm_pipe<8, true>", "k_spmm_rest<8>")
+SPMM_PASSES = ("k_spmm_pipe12<8>", "k_spmm_rest<8>")
 
 
 def write_traffic(fetch_dir, write_dir):
     """FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; each is scaled by
     the ratio of known bytes to the counter's reading for the copy kernel.  One
-    planned SpMM is three dispatches (its passes): their means are added."""
+    planned SpMM is two dispatches (passes 1-2 fused, pass 3): their means are added."""
     fr, wr_ = _counter_rows(fetch_dir), _counter_rows(write_dir)
     fp = [_per_dispatch(fr, "FETCH_SIZE", k) for k in SPMM_PASSES]
     wp = [_per_dispatch(wr_, "WRITE_SIZE", k) for k in SPMM_PASSES]
@@ -148,8 +148,8 @@ def write_traffic(fetch_dir, write_dir):
     w = synthgen.WORKLOADS[WORKLOAD]
     H = load_matrix(w)
     alg = spmm_bytes(H.n, H.nnz, w.nvec, 4, 4)
-    rec = {"kernel": "k_spmm_pipe<8,false> + k_spmm_pipe<8,true> + k_spmm_rest<8> (the three "
-                     "passes of one planned SpMM: float32 values and vectors, 8 vectors, sectors "
+    rec = {"kernel": "k_spmm_pipe12<8> + k_spmm_rest<8> (one planned SpMM: passes 1 and 2 in "
+                     "one kernel, then pass 3; float32 values and vectors, 8 vectors, sectors "
                      "of 1000 rows, two sets of column blocks staged in LDS, the rest gathered)",
            "workload": WORKLOAD, "per_pass_fetch_kib": [x[0] for x in fp],
            "per_pass_write_kib": [x[0] for x in wp],
@@ -516,7 +516,7 @@ def main():
                    "n_trunc": w.n_trunc, "m_max": w.m_max, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK,
-                     "traffic": traffic, "kernel": "k_spmm_pipe<8,false> + k_spmm_pipe<8,true> + k_spmm_rest<8>",
+                     "traffic": traffic, "kernel": "k_spmm_pipe12<8> + k_spmm_rest<8>",
                      "alg_bytes_per_launch": alg, "launch_ms": t_live * 1e3},
         "cpu_baseline": cpu,
         "details": extra,

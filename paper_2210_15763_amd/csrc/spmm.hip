@@ -912,24 +912,23 @@ __device__ __forceinline__ int pipe_lidx(const uint4 (&c)[N], int e) {
 // plan's dense copy of its set's entries: bases = the per-group offsets into
 // it, descriptors [n][2] = {first, end} of each row as 32-bit offsets from
 // its group's first entry rounded down to a multiple of 8.
+// One pass over group g, run by the whole workgroup (every thread calls it:
+// it holds a barrier).
 template <int B, bool P2>
-__global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int slots,
-                                                    const int64_t *__restrict__ bases,
-                                                    const float *__restrict__ val,
-                                                    const uint16_t *__restrict__ lcol,
-                                                    const int32_t *__restrict__ rdesc,
-                                                    const int32_t *__restrict__ blocks,
-                                                    const float *__restrict__ X,
-                                                    float *__restrict__ Y) {
+__device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int slots,
+                                         const int64_t *__restrict__ bases,
+                                         const float *__restrict__ val,
+                                         const uint16_t *__restrict__ lcol,
+                                         const int32_t *__restrict__ rdesc,
+                                         const int32_t *__restrict__ blocks,
+                                         const float *__restrict__ X, float *__restrict__ Y,
+                                         unsigned char *smem_raw) {
   using Desc = int2;
   using Stage = PipeStage<B, P2>;
   constexpr int LPR = Stage::LPR, NO = Stage::NO, LE = Stage::LE;
   static_assert(!P2 || B >= LPR, "pass 2 keeps whole components per lane");
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   const float *sX = reinterpret_cast<const float *>(smem_raw);
-  const int64_t g = xcd_block(blockIdx.x);
   const int64_t r0 = g * G;
-  if (r0 >= n) return;  // grid padding: the whole workgroup leaves
   const int nr = (int)(min(n, r0 + G) - r0);
   constexpr int RPW = kWave / LPR;
   constexpr int LCH = LE * LPR;
@@ -987,7 +986,7 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
     if (threadIdx.x < B) reinterpret_cast<float *>(smem_raw)[(int64_t)zrow * B + threadIdx.x] = 0.0f;
   }
   __syncthreads();
-  if (row >= nr) return;  // no rows for this group of lanes (no barrier follows)
+  if (row >= nr) return;  // no rows for this group of lanes
 
   float acc[B];
 #pragma unroll
@@ -1126,6 +1125,31 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe(int64_t n, int64_t G, int sl
   store_out();  // the last row's sums
 }
 
+// Passes 1 and 2 of one group in one workgroup: pass 2 stages set B over set A
+// once every thread is past pass 1, and reads pass 1's row sums back while
+// they are still in the L2.
+template <int B>
+__global__ __launch_bounds__(1024) void k_spmm_pipe12(int64_t n, int64_t G, int slots,
+                                                      const int64_t *__restrict__ abases,
+                                                      const float *__restrict__ aval,
+                                                      const uint16_t *__restrict__ alcol,
+                                                      const int32_t *__restrict__ arow,
+                                                      const int64_t *__restrict__ bbases,
+                                                      const float *__restrict__ bval,
+                                                      const uint16_t *__restrict__ blcol,
+                                                      const int32_t *__restrict__ brow,
+                                                      const int32_t *__restrict__ blocks,
+                                                      const float *__restrict__ X,
+                                                      float *__restrict__ Y) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int64_t g = xcd_block(blockIdx.x);
+  if (g * G >= n) return;  // grid padding: the whole workgroup leaves
+  pipe_run<B, false>(g, n, G, slots, abases, aval, alcol, arow, blocks, X, Y, smem_raw);
+  // pass 1's row sums written and its LDS reads done, workgroup-wide
+  __syncthreads();
+  pipe_run<B, true>(g, n, G, slots, bbases, bval, blcol, brow, blocks, X, Y, smem_raw);
+}
+
 // Pass 3: one lane per listed row (rows with entries outside both staged
 // sets, {row, count, first entry}; the list's length is rgroup[groups]) adds
 // the products of those entries, read in place from the plan's arrays,
@@ -1216,9 +1240,12 @@ void planned_launch_t(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s)
   check_launch("k_spmm_planned");
 }
 
-template <int BV, bool P2>
-void pipe_pass(const bbl_spmm_plan &P, const float *X, float *Y, hipStream_t s) {
-  auto kern = k_spmm_pipe<BV, P2>;
+// Passes 1 and 2 in one workgroup per group (pass 1: 16 lanes per row over
+// set A; pass 2: 2 lanes per row over set B), then pass 3 for the rest, one
+// lane per listed row.
+template <int BV>
+void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, hipStream_t s) {
+  auto kern = k_spmm_pipe12<BV>;
   const size_t lds = ((size_t)P.slots * P.block_rows + 1) * BV * sizeof(float);
   static bool attr_set = false;
   if (!attr_set) {
@@ -1227,28 +1254,13 @@ void pipe_pass(const bbl_spmm_plan &P, const float *X, float *Y, hipStream_t s) 
     attr_set = true;
   }
   const int64_t groups = ceil_div(P.n, P.block_rows);
-  const int64_t grid = ceil_div(groups, kXcds) * kXcds;
-  if (P2)
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPlanThreads), lds, s, P.n,
-                       (int64_t)P.block_rows, P.slots, P.bgroup,
-                       static_cast<const float *>(P.bval), P.blcol, P.brow, P.blocks, X, Y);
-  else
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPlanThreads), lds, s, P.n,
-                       (int64_t)P.block_rows, P.slots, P.agroup,
-                       static_cast<const float *>(P.aval), P.alcol, P.arow, P.blocks, X, Y);
-  check_launch(P2 ? "k_spmm_pipe (pass 2)" : "k_spmm_pipe (pass 1)");
-}
-
-// Pass 1 takes most entries per row (16 lanes per row), pass 2 the set-B
-// tenth (2 lanes per row), one workgroup per group in both so each set is
-// staged once per group; pass 3 the rest, one lane per row.
-template <int BV>
-void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, hipStream_t s) {
-  pipe_pass<BV, false>(P, X, Y, s);
-  pipe_pass<BV, true>(P, X, Y, s);
+  hipLaunchKernelGGL(kern, dim3((unsigned)(ceil_div(groups, kXcds) * kXcds)), dim3(kPlanThreads),
+                     lds, s, P.n, (int64_t)P.block_rows, P.slots, P.agroup,
+                     static_cast<const float *>(P.aval), P.alcol, P.arow, P.bgroup,
+                     static_cast<const float *>(P.bval), P.blcol, P.brow, P.blocks, X, Y);
+  check_launch("k_spmm_pipe12");
   // the list's length is on the device: a grid of at most 2048 workgroups
   // strides over it
-  const int64_t groups = ceil_div(P.n, P.block_rows);
   const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(2048, ceil_div(P.n, 256)));
   hipLaunchKernelGGL((k_spmm_rest<BV>), dim3((unsigned)grid), dim3(256), 0, s, P.rgroup, groups,
                      reinterpret_cast<const int4 *>(P.rlist), P.col,
