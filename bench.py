@@ -75,6 +75,31 @@ def spmm_bytes(n, nnz, b, sv, sx):
     return nnz * (sv + 4) + 8 * (n + 1) + 2 * n * b * sx
 
 
+def solve_bytes(n, nnz, b, k, iters, extra_spmm, second_passes):
+    """HBM bytes the phases of one block Lanczos solve move at least (FP32
+    matrix values and basis, FP64 W' and Ritz vectors), block by block:
+    SpMM; A_j gram (V_j and W); three-term update (W, V_{j-1:j} in, W' out);
+    Gram-Schmidt gram and update over the j + 1 stored blocks (W' read, and
+    read and written); Cholesky QR (W' read and written, then read, V_{j+1}
+    written).  Then the Ritz vectors (basis read, X written, normalised in
+    place) and the FP64 residual (matrix once, X read twice), plus the
+    second Gram-Schmidt sweeps and any SpMM calls beyond one per block."""
+    blk = n * b * 4      # one FP32 basis block
+    wp = n * b * 8       # W' in FP64
+    sp = spmm_bytes(n, nnz, b, 4, 4)
+    tot = 0.0
+    for j in range(iters):
+        tot += sp + 2 * blk + (blk + min(j + 1, 2) * blk + wp)
+        tot += ((j + 1) * blk + wp) + ((j + 1) * blk + 2 * wp)
+        tot += 3 * wp + blk
+    jm = iters / 2.0
+    tot += second_passes * (2 * (jm + 1) * blk + 3 * wp)
+    tot += extra_spmm * sp
+    tot += iters * blk + n * k * 8 + 2 * n * k * 8
+    tot += nnz * 8 + 8 * (n + 1) + 2 * n * k * 8
+    return tot
+
+
 def source_hash(*names):
     h = hashlib.sha256()
     for nm in names:
@@ -467,6 +492,17 @@ def main():
                             "fp64_TFLOPs": gram_flops / t_gram / 1e12,
                             "frac_fp64_peak": gram_flops / t_gram / FP64_PEAK},
     }
+    # the roofline time to solution: bytes every phase that ran must move at
+    # least, over the 8 TB/s peak (the truncated pivot solve included)
+    rp = np.asarray(H.row_ptr)
+    nt = w.n_trunc
+    nnz_t = int(np.count_nonzero(np.asarray(H.col[:rp[nt]]) < nt))
+    by_main = solve_bytes(H.n, H.nnz, b, k, r.stats["iters"],
+                          r.stats["spmm_calls"] - r.stats["iters"], r.stats["reorth_second_passes"])
+    by_piv = solve_bytes(nt, nnz_t, b, b, pst["iters"], pst["spmm_calls"] - pst["iters"], 0)
+    extra["roofline_tts"] = {"s": (by_main + by_piv) / HBM_PEAK, "bytes": by_main + by_piv,
+                             "main_solve_bytes": by_main, "pivot_solve_bytes": by_piv,
+                             "measured_over_roofline": tts / ((by_main + by_piv) / HBM_PEAK)}
     if args.spmm_sweep:
         extra["spmm_block_sweep"] = spmm_block_sweep(torch, bbl, H, w.R)
     if args.single_vector_arm:
