@@ -71,13 +71,17 @@ typedef struct {
  * its other entries -- and every row's entries are reordered: entries inside
  * those blocks first, stored as an LDS row index slot*block_rows + offset,
  * then the others with their global column.  When every LDS row index fits
- * in 16 bits and nnz < 2^31 the plan also names the next five busiest blocks
- * (set B), places each row's set-B entries right after its set-A entries,
- * keeps the LDS index of set-A and set-B entries within their set as uint16
- * (lcol) and per-row entry ranges (rdesc); the FP32 planned SpMM then runs in
- * two passes, set A and then set B (plus the remaining entries, gathered),
- * each set staged in LDS once per group.  The same sums are formed in a
- * different order, so results agree with bbl_spmm to rounding, not bitwise. */
+ * in 16 bits and nnz < 2^31 the plan also names the next busiest blocks (set
+ * B, as many as set A), places each row's set-B entries right after its set-A
+ * entries, keeps the LDS index of set-A and set-B entries within their set as
+ * uint16 (lcol), per-row entry ranges (rdesc), dense copies of the set-A and
+ * set-B entries and the list of rows with entries outside both sets.  The
+ * FP32 planned SpMM at nvec 4, 8 or 10 then runs one workgroup per group
+ * over set A and then set B, each staged in LDS, and a last pass over the
+ * listed rows that gathers the rows of V their remaining entries need.
+ * Otherwise one pass stages set A and gathers the rest.  The same sums are
+ * formed in a different order, so results agree with bbl_spmm to rounding,
+ * not bitwise. */
 typedef struct {
   int64_t n, nnz;
   int32_t block_rows;     /* rows (and columns) per group */

@@ -83,7 +83,7 @@ def test_spmm_matches_oracle_within_dot_product_bound(torch, bbl, nvec, prec):
     # long rows (~285 entries: several steps of staged entries per row) and
     # rows with most entries outside the staged blocks (several remote steps)
     (8, 400, "f32", 150, 0.7), (8, 400, "f32", 150, 0.1), (4, 400, "f32", 150, 0.3),
-    (8, 1000, "f32", 105, 0.7)])
+    (8, 1000, "f32", 105, 0.7), (10, 1000, "f32", 105, 0.7)])
 def test_planned_spmm_matches_oracle(torch, bbl, nvec, block_rows, prec, q, p):
     """Rows reordered per group, partner blocks staged in LDS: the same sums
     in another order, so the dot-product bound holds entry by entry (groups
