@@ -907,13 +907,69 @@ __device__ __forceinline__ int pipe_lidx(const uint4 (&c)[N], int e) {
   return (int)((f & 1) ? (w >> 16) : (w & 0xffffu));
 }
 
+// A workgroup's copy of `slots` column blocks of V into LDS (slot k at
+// k G rows), in pieces of 4, 8 or 16 bytes, piece item = thread + 1024 j:
+// issue() loads this thread's pieces J0 .. J0 + NJ - 1 into registers,
+// commit() writes them; every load is in flight before the first write.
+template <int B>
+constexpr int stage_pieces() {
+  constexpr int bytes = (int)sizeof(float) * B;
+  constexpr int piece = bytes % 16 == 0 ? 16 : bytes % 8 == 0 ? 8 : 4;
+  return (int)((kPlanLds / piece + 1023) / 1024);
+}
+template <int B, int J0 = 0, int NJ = stage_pieces<B>()>
+struct StageFill {
+  static constexpr int bytes = (int)sizeof(float) * B;
+  static constexpr int piece = bytes % 16 == 0 ? 16 : bytes % 8 == 0 ? 8 : 4;
+  using P = unsigned __attribute__((ext_vector_type(piece / 4)));
+  static_assert(NJ <= 64, "one bit per piece");
+  P tmp[NJ];
+  uint64_t keep;  // bit j: piece j is written
+  // Every load is unconditional (out-of-range pieces read the last piece of
+  // V and are not written), so all pieces are in flight before the first
+  // wait.  1 <= slots <= kPlanMaxSlots.
+  __device__ __forceinline__ void issue(int64_t n, int64_t G, int slots,
+                                        const int32_t *__restrict__ bl,
+                                        const float *__restrict__ X) {
+    const int per_slot = (int)(G * bytes / piece);
+    const int total = slots * per_slot;
+    const int64_t last = n * bytes / piece - 1;
+    // opaque to the compiler, so that the piece positions are computed here
+    // and not shared with (and held live until) another fill
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    // the set's block numbers are the same for the whole workgroup
+    int bs[kPlanMaxSlots];
+#pragma unroll
+    for (int k = 0; k < kPlanMaxSlots; ++k) bs[k] = bl[min(k, slots - 1)];
+    keep = 0;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int item = tid + (J0 + j) * 1024;
+      const int k = item / per_slot, off = item - k * per_slot;
+      int bk = bs[0];
+#pragma unroll
+      for (int q = 1; q < kPlanMaxSlots; ++q) bk = k == q ? bs[q] : bk;
+      const int64_t at = (int64_t)max(bk, 0) * per_slot + off;
+      tmp[j] = reinterpret_cast<const P *>(X)[min(at, last)];
+      if (item < total && bk >= 0 && at <= last) keep |= uint64_t(1) << j;
+    }
+  }
+  __device__ __forceinline__ void commit(unsigned char *smem_raw) const {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+      if ((keep >> j) & 1) reinterpret_cast<P *>(smem_raw)[threadIdx.x + (J0 + j) * 1024] = tmp[j];
+  }
+};
+
 // Pass 1 (P2 = false) or pass 2 (P2 = true) over the row groups; `blocks`
 // has 2 slots entries per group (set A, then set B).  Each pass streams the
 // plan's dense copy of its set's entries: bases = the per-group offsets into
 // it, descriptors [n][2] = {first, end} of each row as 32-bit offsets from
 // its group's first entry rounded down to a multiple of 8.
 // One pass over group g, run by the whole workgroup (every thread calls it:
-// it holds a barrier).
+// it holds a barrier).  pre: the set's blocks already loaded by this thread
+// (nullptr: loaded here).
 template <int B, bool P2>
 __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int slots,
                                          const int64_t *__restrict__ bases,
@@ -922,7 +978,8 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
                                          const int32_t *__restrict__ rdesc,
                                          const int32_t *__restrict__ blocks,
                                          const float *__restrict__ X, float *__restrict__ Y,
-                                         unsigned char *smem_raw) {
+                                         unsigned char *smem_raw,
+                                         const StageFill<B> *pre = nullptr) {
   using Desc = int2;
   using Stage = PipeStage<B, P2>;
   constexpr int LPR = Stage::LPR, NO = Stage::NO, LE = Stage::LE;
@@ -956,35 +1013,29 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
   Stage cur;
   pipe_load<B, P2>(cur, lc_b, v_b, qlb + LE * sub, d0.x, pl, yrow(row));
 
-  // stage the set's column blocks: every load of the fill first, then the writes
-  {
-    constexpr int bytes = (int)sizeof(float) * B;
-    constexpr int piece = bytes % 16 == 0 ? 16 : bytes % 8 == 0 ? 8 : 4;
-    using P = unsigned __attribute__((ext_vector_type(piece / 4)));
-    constexpr int kMaxJ = (int)((kPlanLds / piece + 1023) / 1024);
-    const int per_slot = (int)(G * bytes / piece);
-    const int total = slots * per_slot;
+  // stage the set's column blocks (loaded here unless the caller loaded them
+  // already), then the all-zero row
+  if (pre) {
+    pre->commit(smem_raw);
+  } else {
+    // in two halves where the whole would not fit in registers beside the
+    // first stage
     const int32_t *bl = blocks + g * (2 * slots) + (P2 ? slots : 0);
-    P tmp[kMaxJ];
-    int dst[kMaxJ];
-#pragma unroll
-    for (int j = 0; j < kMaxJ; ++j) {
-      const int item = (int)threadIdx.x + j * 1024;
-      dst[j] = -1;
-      if (item < total) {
-        const int k = item / per_slot, off = item - k * per_slot;
-        const int bk = bl[k];
-        if (bk >= 0 && (int64_t)bk * G * bytes / piece + off < n * bytes / piece) {
-          tmp[j] = reinterpret_cast<const P *>(X + (int64_t)bk * G * B)[off];
-          dst[j] = item;
-        }
-      }
+    constexpr int kAll = stage_pieces<B>(), kHalf = (kAll + 1) / 2;
+    if constexpr (kAll <= 10) {
+      StageFill<B> fill;
+      fill.issue(n, G, slots, bl, X);
+      fill.commit(smem_raw);
+    } else {
+      StageFill<B, 0, kHalf> f0;
+      f0.issue(n, G, slots, bl, X);
+      f0.commit(smem_raw);
+      StageFill<B, kHalf, kAll - kHalf> f1;
+      f1.issue(n, G, slots, bl, X);
+      f1.commit(smem_raw);
     }
-#pragma unroll
-    for (int j = 0; j < kMaxJ; ++j)
-      if (dst[j] >= 0) reinterpret_cast<P *>(smem_raw)[dst[j]] = tmp[j];
-    if (threadIdx.x < B) reinterpret_cast<float *>(smem_raw)[(int64_t)zrow * B + threadIdx.x] = 0.0f;
   }
+  if (threadIdx.x < B) reinterpret_cast<float *>(smem_raw)[(int64_t)zrow * B + threadIdx.x] = 0.0f;
   __syncthreads();
   if (row >= nr) return;  // no rows for this group of lanes
 
@@ -1125,9 +1176,10 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
   store_out();  // the last row's sums
 }
 
-// Passes 1 and 2 of one group in one workgroup: pass 2 stages set B over set A
-// once every thread is past pass 1, and reads pass 1's row sums back while
-// they are still in the L2.
+// Passes 1 and 2 of one group in one workgroup: each thread loads its share
+// of set B as soon as its pass-1 rows are done, pass 2 writes set B over set
+// A in LDS once every thread is past pass 1, and reads pass 1's row sums back
+// while they are still in the L2.
 template <int B>
 __global__ __launch_bounds__(1024) void k_spmm_pipe12(int64_t n, int64_t G, int slots,
                                                       const int64_t *__restrict__ abases,
@@ -1145,9 +1197,16 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe12(int64_t n, int64_t G, int 
   const int64_t g = xcd_block(blockIdx.x);
   if (g * G >= n) return;  // grid padding: the whole workgroup leaves
   pipe_run<B, false>(g, n, G, slots, abases, aval, alcol, arow, blocks, X, Y, smem_raw);
+  // set B's blocks are loaded while the rest of the workgroup finishes pass 1
+  // (where 16-byte pieces keep the held loads within the register budget of
+  // 1024 threads; otherwise pass 2 loads them after the barrier)
+  constexpr bool kEarly = StageFill<B>::piece == 16;
+  StageFill<B> fill;
+  if (kEarly) fill.issue(n, G, slots, blocks + g * (2 * slots) + slots, X);
   // pass 1's row sums written and its LDS reads done, workgroup-wide
   __syncthreads();
-  pipe_run<B, true>(g, n, G, slots, bbases, bval, blcol, brow, blocks, X, Y, smem_raw);
+  pipe_run<B, true>(g, n, G, slots, bbases, bval, blcol, brow, blocks, X, Y, smem_raw,
+                    kEarly ? &fill : nullptr);
 }
 
 // Pass 3: one lane per listed row (rows with entries outside both staged
