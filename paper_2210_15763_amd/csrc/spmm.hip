@@ -1209,10 +1209,14 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe12(int64_t n, int64_t G, int 
                     kEarly ? &fill : nullptr);
 }
 
-// Pass 3: one lane per listed row (rows with entries outside both staged
-// sets, {row, count, first entry}; the list's length is rgroup[groups]) adds
-// the products of those entries, read in place from the plan's arrays,
-// gathering the rows of V they need.  A grid-stride loop covers any length.
+// Pass 3: kRestLanes lanes per listed row (rows with entries outside both
+// staged sets, {row, count, first entry}; the list's length is
+// rgroup[groups]).  Lane s takes the row's entries s, s + L, s + 2L, ..., U
+// of them in flight per round, read in place from the plan's arrays, and
+// gathers the rows of V they need; a butterfly adds the lanes' sums (every
+// lane ends with the same, fixed-order total) and lane s adds components
+// s, s + L, ... to the row of W.  A grid-stride loop covers any length.
+constexpr int kRestLanes = 8;
 template <int B>
 __global__ __launch_bounds__(256) void k_spmm_rest(const int64_t *__restrict__ rgroup,
                                                    int64_t groups,
@@ -1221,52 +1225,53 @@ __global__ __launch_bounds__(256) void k_spmm_rest(const int64_t *__restrict__ r
                                                    const float *__restrict__ val2,
                                                    const float *__restrict__ X,
                                                    float *__restrict__ Y) {
+  constexpr int L = kRestLanes, U = 4, NC = (B + L - 1) / L;
   const int64_t total = rgroup[groups];
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  const int s = (int)(threadIdx.x & (L - 1));
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / L);
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / L; i < total; i += stride) {
     const int4 d = rlist[i];
     const int64_t row = d.x;
+    const int cnt = d.y;
     const int64_t first = (int64_t)(uint32_t)d.z | ((int64_t)d.w << 32);
-    float y[B];
-    RowIO<float, B>::load(Y + row * B, y);
+    float y[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) y[k] = s + k * L < B ? Y[row * B + s + k * L] : 0.0f;
     float acc[B];
 #pragma unroll
     for (int a = 0; a < B; ++a) acc[a] = 0.0f;
-    // eight entries at a time: their index and value loads, then their
-    // gathers, all in flight together (rows with many remaining entries would
-    // otherwise wait out one gather after another)
-    constexpr int U = 8;
-    for (int64_t q0 = first; q0 < first + d.y; q0 += U) {
+    // the same trip count on all L lanes of the row; every load is issued
+    // (past the row's end a lane reloads its last entry and drops the product)
+    for (int t0 = 0; t0 < cnt; t0 += L * U) {
       int c[U];
       float h[U];
 #pragma unroll
-      for (int e = 0; e < U; ++e) {
-        const bool ok = q0 + e < first + d.y;
-        c[e] = ok ? col2[q0 + e] : 0;
-        h[e] = ok ? val2[q0 + e] : 0.0f;
+      for (int u = 0; u < U; ++u) {
+        const int64_t q = first + min(t0 + s + L * u, cnt - 1);
+        c[u] = col2[q];
+        h[u] = val2[q];
       }
       float x[U][B];
 #pragma unroll
-      for (int e = 0; e < U; ++e) {
+      for (int u = 0; u < U; ++u) RowIO<float, B>::load(X + (int64_t)c[u] * B, x[u]);
 #pragma unroll
-        for (int a = 0; a < B; ++a) x[e][a] = 0.0f;
-        if (q0 + e < first + d.y) RowIO<float, B>::load(X + (int64_t)c[e] * B, x[e]);
+      for (int u = 0; u < U; ++u) {
+        const bool ok = t0 + s + L * u < cnt;
+#pragma unroll
+        for (int a = 0; a < B; ++a) acc[a] = fmaf(h[u], ok ? x[u][a] : 0.0f, acc[a]);
       }
-#pragma unroll
-      for (int e = 0; e < U; ++e)
-#pragma unroll
-        for (int a = 0; a < B; ++a) acc[a] = fmaf(h[e], x[e][a], acc[a]);
     }
 #pragma unroll
-    for (int a = 0; a < B; ++a) y[a] += acc[a];
-    if constexpr ((int)sizeof(float) * B % 16 == 0) {
+    for (int m = 1; m < L; m <<= 1)
 #pragma unroll
-      for (int k = 0; k < B / 4; ++k)
-        reinterpret_cast<float4 *>(Y + row * B)[k] =
-            make_float4(y[4 * k], y[4 * k + 1], y[4 * k + 2], y[4 * k + 3]);
-    } else {
+      for (int a = 0; a < B; ++a) acc[a] += __shfl_xor(acc[a], m, L);
 #pragma unroll
-      for (int a = 0; a < B; ++a) Y[row * B + a] = y[a];
+    for (int k = 0; k < NC; ++k) {
+      const int a = s + k * L;
+      float v = 0.0f;
+#pragma unroll
+      for (int a2 = 0; a2 < B; ++a2) v = a2 == a ? acc[a2] : v;
+      if (a < B) Y[row * B + a] = y[k] + v;
     }
   }
 }
@@ -1318,9 +1323,10 @@ void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, hipSt
                      static_cast<const float *>(P.aval), P.alcol, P.arow, P.bgroup,
                      static_cast<const float *>(P.bval), P.blcol, P.brow, P.blocks, X, Y);
   check_launch("k_spmm_pipe12");
-  // the list's length is on the device: a grid of at most 2048 workgroups
-  // strides over it
-  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(2048, ceil_div(P.n, 256)));
+  // the list's length is on the device: a grid of at most 4096 workgroups
+  // (32 rows each) strides over it
+  const int64_t grid =
+      std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(P.n * kRestLanes, 256)));
   hipLaunchKernelGGL((k_spmm_rest<BV>), dim3((unsigned)grid), dim3(256), 0, s, P.rgroup, groups,
                      reinterpret_cast<const int4 *>(P.rlist), P.col,
                      static_cast<const float *>(P.val), X, Y);
