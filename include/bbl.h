@@ -78,8 +78,10 @@ typedef struct {
  * set-B entries and the list of rows with entries outside both sets.  The
  * FP32 planned SpMM at nvec 4, 8 or 10 then runs one workgroup per group
  * over set A and then set B, each staged in LDS, and a last pass over the
- * listed rows that gathers the rows of V their remaining entries need.
- * Otherwise one pass stages set A and gathers the rest.  The same sums are
+ * listed rows that gathers the rows of V their remaining entries need; at
+ * nvec 16 it does so twice, for columns 0-7 and 8-15 (the slot count is
+ * then sized for 8 columns).  Otherwise one pass stages set A and gathers
+ * the rest.  The same sums are
  * formed in a different order, so results agree with bbl_spmm to rounding,
  * not bitwise. */
 typedef struct {

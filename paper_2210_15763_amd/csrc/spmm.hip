@@ -907,8 +907,9 @@ __device__ __forceinline__ int pipe_lidx(const uint4 (&c)[N], int e) {
   return (int)((f & 1) ? (w >> 16) : (w & 0xffffu));
 }
 
-// A workgroup's copy of `slots` column blocks of V into LDS (slot k at
-// k G rows), in pieces of 4, 8 or 16 bytes, piece item = thread + 1024 j:
+// A workgroup's copy of `slots` column blocks of V (B columns of rows `ld`
+// floats apart) into LDS (slot k at k G rows of B), in pieces of 4, 8 or 16
+// bytes, piece item = thread + 1024 j:
 // issue() loads this thread's pieces J0 .. J0 + NJ - 1 into registers,
 // commit() writes them; every load is in flight before the first write.
 template <int B>
@@ -925,15 +926,15 @@ struct StageFill {
   static_assert(NJ <= 64, "one bit per piece");
   P tmp[NJ];
   uint64_t keep;  // bit j: piece j is written
-  // Every load is unconditional (out-of-range pieces read the last piece of
-  // V and are not written), so all pieces are in flight before the first
+  // Every load is unconditional (out-of-range pieces read from the last row
+  // of V and are not written), so all pieces are in flight before the first
   // wait.  1 <= slots <= kPlanMaxSlots.
   __device__ __forceinline__ void issue(int64_t n, int64_t G, int slots,
                                         const int32_t *__restrict__ bl,
-                                        const float *__restrict__ X) {
-    const int per_slot = (int)(G * bytes / piece);
+                                        const float *__restrict__ X, int ld) {
+    constexpr int ppr = bytes / piece;  // pieces per row
+    const int per_slot = (int)G * ppr;
     const int total = slots * per_slot;
-    const int64_t last = n * bytes / piece - 1;
     // opaque to the compiler, so that the piece positions are computed here
     // and not shared with (and held live until) another fill
     int tid = (int)threadIdx.x;
@@ -950,9 +951,10 @@ struct StageFill {
       int bk = bs[0];
 #pragma unroll
       for (int q = 1; q < kPlanMaxSlots; ++q) bk = k == q ? bs[q] : bk;
-      const int64_t at = (int64_t)max(bk, 0) * per_slot + off;
-      tmp[j] = reinterpret_cast<const P *>(X)[min(at, last)];
-      if (item < total && bk >= 0 && at <= last) keep |= uint64_t(1) << j;
+      const int rin = off / ppr;
+      const int64_t r = (int64_t)max(bk, 0) * G + rin;
+      tmp[j] = *reinterpret_cast<const P *>(X + min(r, n - 1) * ld + (off - rin * ppr) * (piece / 4));
+      if (item < total && bk >= 0 && r < n) keep |= uint64_t(1) << j;
     }
   }
   __device__ __forceinline__ void commit(unsigned char *smem_raw) const {
@@ -978,7 +980,7 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
                                          const int32_t *__restrict__ rdesc,
                                          const int32_t *__restrict__ blocks,
                                          const float *__restrict__ X, float *__restrict__ Y,
-                                         unsigned char *smem_raw,
+                                         unsigned char *smem_raw, int ld,
                                          const StageFill<B> *pre = nullptr) {
   using Desc = int2;
   using Stage = PipeStage<B, P2>;
@@ -1000,8 +1002,8 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
   const uint16_t *lc_b = lcol + base;
   const float *v_b = val + base;
   const Desc *desc = reinterpret_cast<const Desc *>(rdesc) + r0;
-  float *Yw = Y + r0 * B;
-  auto yrow = [&](int r) { return Yw + (int64_t)(r < nr ? r : 0) * B + (B >= LPR ? cb : 0); };
+  float *Yw = Y + r0 * ld;
+  auto yrow = [&](int r) { return Yw + (int64_t)(r < nr ? r : 0) * ld + (B >= LPR ? cb : 0); };
 
   // this row group's first row (relative to r0) and the descriptor of its second
   int row = wave * RPW + lane / LPR;
@@ -1024,14 +1026,14 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
     constexpr int kAll = stage_pieces<B>(), kHalf = (kAll + 1) / 2;
     if constexpr (kAll <= 10) {
       StageFill<B> fill;
-      fill.issue(n, G, slots, bl, X);
+      fill.issue(n, G, slots, bl, X, ld);
       fill.commit(smem_raw);
     } else {
       StageFill<B, 0, kHalf> f0;
-      f0.issue(n, G, slots, bl, X);
+      f0.issue(n, G, slots, bl, X, ld);
       f0.commit(smem_raw);
       StageFill<B, kHalf, kAll - kHalf> f1;
-      f1.issue(n, G, slots, bl, X);
+      f1.issue(n, G, slots, bl, X, ld);
       f1.commit(smem_raw);
     }
   }
@@ -1111,7 +1113,7 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
         for (int a = 0; a < B; ++a) acc[a] = fmaf(h[e], lx[e][a], acc[a]);
     }
     if (last) {
-      yp = Yw + (int64_t)row * B;
+      yp = Yw + (int64_t)row * ld;
       if constexpr (B == 8 && LPR == 16) {
         // halving exchange between lanes of equal parity: afterwards lane sub
         // holds (rotated) component (sub >> 1) & 7
@@ -1180,7 +1182,7 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
 // of set B as soon as its pass-1 rows are done, pass 2 writes set B over set
 // A in LDS once every thread is past pass 1, and reads pass 1's row sums back
 // while they are still in the L2.
-template <int B>
+template <int B, bool S>
 __global__ __launch_bounds__(1024) void k_spmm_pipe12(int64_t n, int64_t G, int slots,
                                                       const int64_t *__restrict__ abases,
                                                       const float *__restrict__ aval,
@@ -1192,20 +1194,21 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe12(int64_t n, int64_t G, int 
                                                       const int32_t *__restrict__ brow,
                                                       const int32_t *__restrict__ blocks,
                                                       const float *__restrict__ X,
-                                                      float *__restrict__ Y) {
+                                                      float *__restrict__ Y, int ld_arg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int ld = S ? ld_arg : B;  // row stride of V and W (S: strided halves)
   const int64_t g = xcd_block(blockIdx.x);
   if (g * G >= n) return;  // grid padding: the whole workgroup leaves
-  pipe_run<B, false>(g, n, G, slots, abases, aval, alcol, arow, blocks, X, Y, smem_raw);
+  pipe_run<B, false>(g, n, G, slots, abases, aval, alcol, arow, blocks, X, Y, smem_raw, ld);
   // set B's blocks are loaded while the rest of the workgroup finishes pass 1
   // (where 16-byte pieces keep the held loads within the register budget of
   // 1024 threads; otherwise pass 2 loads them after the barrier)
   constexpr bool kEarly = StageFill<B>::piece == 16;
   StageFill<B> fill;
-  if (kEarly) fill.issue(n, G, slots, blocks + g * (2 * slots) + slots, X);
+  if (kEarly) fill.issue(n, G, slots, blocks + g * (2 * slots) + slots, X, ld);
   // pass 1's row sums written and its LDS reads done, workgroup-wide
   __syncthreads();
-  pipe_run<B, true>(g, n, G, slots, bbases, bval, blcol, brow, blocks, X, Y, smem_raw,
+  pipe_run<B, true>(g, n, G, slots, bbases, bval, blcol, brow, blocks, X, Y, smem_raw, ld,
                     kEarly ? &fill : nullptr);
 }
 
@@ -1217,15 +1220,16 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe12(int64_t n, int64_t G, int 
 // lane ends with the same, fixed-order total) and lane s adds components
 // s, s + L, ... to the row of W.  A grid-stride loop covers any length.
 constexpr int kRestLanes = 8;
-template <int B>
+template <int B, bool S>
 __global__ __launch_bounds__(256) void k_spmm_rest(const int64_t *__restrict__ rgroup,
                                                    int64_t groups,
                                                    const int4 *__restrict__ rlist,
                                                    const int32_t *__restrict__ col2,
                                                    const float *__restrict__ val2,
                                                    const float *__restrict__ X,
-                                                   float *__restrict__ Y) {
+                                                   float *__restrict__ Y, int ld_arg) {
   constexpr int L = kRestLanes, U = 4, NC = (B + L - 1) / L;
+  const int ld = S ? ld_arg : B;  // row stride of V and W (S: strided halves)
   const int64_t total = rgroup[groups];
   const int s = (int)(threadIdx.x & (L - 1));
   const int64_t stride = (int64_t)gridDim.x * (blockDim.x / L);
@@ -1236,7 +1240,7 @@ __global__ __launch_bounds__(256) void k_spmm_rest(const int64_t *__restrict__ r
     const int64_t first = (int64_t)(uint32_t)d.z | ((int64_t)d.w << 32);
     float y[NC];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) y[k] = s + k * L < B ? Y[row * B + s + k * L] : 0.0f;
+    for (int k = 0; k < NC; ++k) y[k] = s + k * L < B ? Y[row * ld + s + k * L] : 0.0f;
     float acc[B];
 #pragma unroll
     for (int a = 0; a < B; ++a) acc[a] = 0.0f;
@@ -1253,7 +1257,7 @@ __global__ __launch_bounds__(256) void k_spmm_rest(const int64_t *__restrict__ r
       }
       float x[U][B];
 #pragma unroll
-      for (int u = 0; u < U; ++u) RowIO<float, B>::load(X + (int64_t)c[u] * B, x[u]);
+      for (int u = 0; u < U; ++u) RowIO<float, B>::load(X + (int64_t)c[u] * ld, x[u]);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const bool ok = t0 + s + L * u < cnt;
@@ -1271,7 +1275,7 @@ __global__ __launch_bounds__(256) void k_spmm_rest(const int64_t *__restrict__ r
       float v = 0.0f;
 #pragma unroll
       for (int a2 = 0; a2 < B; ++a2) v = a2 == a ? acc[a2] : v;
-      if (a < B) Y[row * B + a] = y[k] + v;
+      if (a < B) Y[row * ld + a] = y[k] + v;
     }
   }
 }
@@ -1304,12 +1308,19 @@ void planned_launch_t(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s)
   check_launch("k_spmm_planned");
 }
 
+// Whether a plan can run through the pipelined kernels at BK vectors per
+// pass: 16-bit LDS indices, the per-row descriptors and dense copies, and
+// the staged sets plus the all-zero row within the LDS.
+bool plan_pipe_ok(bool local16, bool copies, int slots, int64_t block_rows, int BK) {
+  return local16 && copies && ((size_t)slots * block_rows + 1) * BK * sizeof(float) <= kPlanLds;
+}
+
 // Passes 1 and 2 in one workgroup per group (pass 1: 16 lanes per row over
 // set A; pass 2: 2 lanes per row over set B), then pass 3 for the rest, one
 // lane per listed row.
-template <int BV>
-void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, hipStream_t s) {
-  auto kern = k_spmm_pipe12<BV>;
+template <int BV, bool S>
+void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, int ld, hipStream_t s) {
+  auto kern = k_spmm_pipe12<BV, S>;
   const size_t lds = ((size_t)P.slots * P.block_rows + 1) * BV * sizeof(float);
   static bool attr_set = false;
   if (!attr_set) {
@@ -1321,29 +1332,34 @@ void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, hipSt
   hipLaunchKernelGGL(kern, dim3((unsigned)(ceil_div(groups, kXcds) * kXcds)), dim3(kPlanThreads),
                      lds, s, P.n, (int64_t)P.block_rows, P.slots, P.agroup,
                      static_cast<const float *>(P.aval), P.alcol, P.arow, P.bgroup,
-                     static_cast<const float *>(P.bval), P.blcol, P.brow, P.blocks, X, Y);
+                     static_cast<const float *>(P.bval), P.blcol, P.brow, P.blocks, X, Y, ld);
   check_launch("k_spmm_pipe12");
   // the list's length is on the device: a grid of at most 4096 workgroups
   // (32 rows each) strides over it
   const int64_t grid =
       std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(P.n * kRestLanes, 256)));
-  hipLaunchKernelGGL((k_spmm_rest<BV>), dim3((unsigned)grid), dim3(256), 0, s, P.rgroup, groups,
+  hipLaunchKernelGGL((k_spmm_rest<BV, S>), dim3((unsigned)grid), dim3(256), 0, s, P.rgroup, groups,
                      reinterpret_cast<const int4 *>(P.rlist), P.col,
-                     static_cast<const float *>(P.val), X, Y);
+                     static_cast<const float *>(P.val), X, Y, ld);
   check_launch("k_spmm_rest");
 }
 
 template <typename VT, typename XT, int BV>
 void planned_launch(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s) {
   if constexpr (std::is_same<VT, float>::value && std::is_same<XT, float>::value &&
-                (BV == 4 || BV == 8 || BV == 10)) {
+                (BV == 4 || BV == 8 || BV == 10 || BV == 16)) {
     // the pipelined kernel also keeps one all-zero row of V in LDS and takes
-    // 32-bit entry offsets
-    if (P.local16 && P.lcol && P.rdesc && P.arow && P.brow && P.rlist &&
-        ((size_t)P.slots * P.block_rows + 1) * BV * sizeof(float) <= kPlanLds) {
-      planned_launch_pipe<BV>(P, X, Y, s);
+    // 32-bit entry offsets; 16 vectors go through it as two halves of 8
+    constexpr int BK = BV == 16 ? 8 : BV;
+    if (plan_pipe_ok(P.local16 && P.lcol, P.rdesc && P.arow && P.brow && P.rlist, P.slots,
+                     P.block_rows, BK)) {
+      planned_launch_pipe<BK, BV != BK>(P, X, Y, BV, s);
+      if constexpr (BV == 16) planned_launch_pipe<BK, true>(P, X + 8, Y + 8, BV, s);
       return;
     }
+    if constexpr (BV == 16)
+      BBL_REQUIRE((size_t)P.slots * P.block_rows * BV * sizeof(float) <= kPlanLds,
+                  "planned SpMM: plan built for the two-half kernel cannot run here");
   }
   if (P.local16 && P.lcol) planned_launch_t<VT, XT, BV, true>(P, X, Y, s);
   else planned_launch_t<VT, XT, BV, false>(P, X, Y, s);
@@ -1439,13 +1455,6 @@ int launch_residual_spmm(const bbl_csr &H, const double *X, int nvec, const doub
 }
 
 
-int spmm_plan_slots(const bbl_csr &H, int nvec, int vec_dtype) {
-  if (H.block_rows <= 0) return 0;
-  if (!(nvec == 1 || nvec == 2 || nvec == 4 || nvec == 8 || nvec == 10 || nvec == 16)) return 0;
-  const size_t per = (size_t)H.block_rows * nvec * (vec_dtype == BBL_F32 ? 4 : 8);
-  return (int)std::min<size_t>(kPlanMaxSlots, kPlanLds / per);
-}
-
 // LDS row indices slot*G + offset all fit in 16 bits
 bool plan_local16(const bbl_csr &H, int slots) {
   return (int64_t)slots * H.block_rows <= 65536;
@@ -1453,6 +1462,19 @@ bool plan_local16(const bbl_csr &H, int slots) {
 
 // per-row 32-bit entry offsets from the group's first entry
 bool plan_desc(const bbl_csr &H) { return H.nnz < ((int64_t)1 << 31) - 64; }
+
+int spmm_plan_slots(const bbl_csr &H, int nvec, int vec_dtype) {
+  if (H.block_rows <= 0) return 0;
+  if (!(nvec == 1 || nvec == 2 || nvec == 4 || nvec == 8 || nvec == 10 || nvec == 16)) return 0;
+  if (nvec == 16 && vec_dtype == BBL_F32 && H.val_dtype == BBL_F32 && plan_desc(H)) {
+    // FP32, 16 vectors: the pipelined kernels take the columns in two halves
+    // of 8, so a slot holds 8 columns of a block (beside the all-zero row)
+    const int s8 = (int)std::min<int64_t>(kPlanMaxSlots, ((int64_t)kPlanLds / 32 - 1) / H.block_rows);
+    if (s8 >= 1 && plan_pipe_ok(plan_local16(H, s8), true, s8, H.block_rows, 8)) return s8;
+  }
+  const size_t per = (size_t)H.block_rows * nvec * (vec_dtype == BBL_F32 ? 4 : 8);
+  return (int)std::min<size_t>(kPlanMaxSlots, kPlanLds / per);
+}
 
 size_t spmm_plan_bytes(const bbl_csr &H, int nvec, int vec_dtype) {
   const int slots = spmm_plan_slots(H, nvec, vec_dtype);

@@ -83,7 +83,8 @@ def test_spmm_matches_oracle_within_dot_product_bound(torch, bbl, nvec, prec):
     # long rows (~285 entries: several steps of staged entries per row) and
     # rows with most entries outside the staged blocks (several remote steps)
     (8, 400, "f32", 150, 0.7), (8, 400, "f32", 150, 0.1), (4, 400, "f32", 150, 0.3),
-    (8, 1000, "f32", 105, 0.7), (10, 1000, "f32", 105, 0.7)])
+    (8, 1000, "f32", 105, 0.7), (10, 1000, "f32", 105, 0.7),
+    (16, 1000, "f32", 105, 0.7), (16, 333, "f32", 150, 0.3)])
 def test_planned_spmm_matches_oracle(torch, bbl, nvec, block_rows, prec, q, p):
     """Rows reordered per group, partner blocks staged in LDS: the same sums
     in another order, so the dot-product bound holds entry by entry (groups
@@ -95,7 +96,13 @@ def test_planned_spmm_matches_oracle(torch, bbl, nvec, block_rows, prec, q, p):
     Hd = bbl.DeviceCSR.from_host(H, dt, block_rows=block_rows)
     plan = bbl.spmm_plan(Hd, nvec)
     per_block = block_rows * nvec * (4 if prec == "f32" else 8)
-    assert plan.slots == min(5, 160 * 1024 // per_block)
+    expect = min(5, 160 * 1024 // per_block)
+    if nvec == 16 and prec == "f32":
+        # two 8-column passes: a slot holds 8 columns, beside the zero row
+        s8 = min(5, (160 * 1024 // 32 - 1) // block_rows)
+        if s8 >= 1 and s8 * block_rows <= 65536:
+            expect = s8
+    assert plan.slots == expect
     V = synthgen.gaussian_block(H.n, nvec, 5)
     Vd = dev(torch, V.astype(np.float32) if prec == "f32" else V)
     W = bbl.spmm_planned(plan, Vd).double().cpu().numpy()
