@@ -523,6 +523,25 @@ def test_fp32_path_matches_oracle_on_rounded_matrix(torch, bbl):
         bbl.block_lanczos(Hp, P[:, :4].contiguous(), 4, 1e-6, m_max=50, spmm_plan=plan)
 
 
+def test_planned_solve_at_sixteen_vectors(torch, bbl):
+    """b = 16 through the planned SpMM's two 8-column passes: residuals of the
+    converged pairs recomputed on the host in FP64, and the same eigenvalues
+    (within the residual bound) as the solve through the plain CSR kernel."""
+    note("planned solve b=16")
+    H = synthgen.generate(20000, 1000, 105, 0.7, 12)
+    Hp = bbl.DeviceCSR.from_host(H, "float32", block_rows=1000)
+    plan = bbl.spmm_plan(Hp, 16)
+    assert plan.slots == 5
+    P = bbl.random_pivot(H.n, 16, synthgen.pivot_key(3))
+    rp = bbl.block_lanczos(Hp, P, 10, 1e-6, m_max=120, spmm_plan=plan)
+    r = bbl.block_lanczos(Hp, P, 10, 1e-6, m_max=120)
+    assert rp.converged and r.converged, (rp.stats, r.stats)
+    hn = rp.stats["hnorm_est"]
+    np.testing.assert_allclose(rp.eigvals, r.eigvals, rtol=0, atol=2e-6 * hn)
+    res = oracle.ritz_residuals(H.as_float32_values(), rp.eigvecs.cpu().numpy(), rp.eigvals)
+    assert np.all(res <= 1e-6 * hn), res / hn
+
+
 def test_exact_eigenvector_pivot_deflates_and_converges_at_once(torch, bbl):
     note("exact-eigenvector pivot")
     H = synthgen.generate(1600, 400, 20, 0.7, 6)
