@@ -205,13 +205,29 @@ __global__ __launch_bounds__(256) void k_residual_t(int64_t n, const int64_t *__
 #pragma unroll
     for (int a = 0; a < NV; ++a) acc[a] = 0.0;
     if (row < r1) {
+      // U entries per lane in flight: their index and value loads, then their
+      // gathers (past the row's end a lane reloads its first entry of the
+      // step and drops the product)
+      constexpr int U = NV <= 4 ? 4 : NV <= 8 ? 3 : 2;
       const int64_t q1 = rp[row + 1];
-      for (int64_t p = rp[row] + sub; p < q1; p += LPR) {
-        const double h = (double)val[p];
-        double x[NV];
-        RowIO<double, NV>::load(X + (int64_t)col[p] * NV, x);
+      for (int64_t p = rp[row] + sub; p < q1; p += U * LPR) {
+        double h[U];
+        int32_t c[U];
 #pragma unroll
-        for (int a = 0; a < NV; ++a) acc[a] = fma(h, x[a], acc[a]);
+        for (int u = 0; u < U; ++u) {
+          const int64_t pu = p + u * LPR < q1 ? p + u * LPR : p;
+          h[u] = (double)val[pu];
+          c[u] = col[pu];
+        }
+        double x[U][NV];
+#pragma unroll
+        for (int u = 0; u < U; ++u) RowIO<double, NV>::load(X + (int64_t)c[u] * NV, x[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const bool ok = p + u * LPR < q1;
+#pragma unroll
+          for (int a = 0; a < NV; ++a) acc[a] = fma(h[u], ok ? x[u][a] : 0.0, acc[a]);
+        }
       }
     }
 #pragma unroll
