@@ -677,7 +677,8 @@ int gram_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const 
   const int M = nblk * bx;
   constexpr bool f32 = sizeof(XT) == 4;
   if (nblk == 1 && ny == bx && (bx == 4 || bx == 8)) {
-    // one block: rows across lanes, 1024 waves at most
+    // one block: rows across lanes, 1024 waves at most (4096 ran slower at
+    // n = 2e6: 36 against 30 us)
     const int64_t waves = std::max<int64_t>(1, std::min<int64_t>({(int64_t)max_partials - 4, (int64_t)1024,
                                                                     ceil_div(n, 1024)}));
     const int64_t rpw = ceil_div(ceil_div(n, waves), 64) * 64;
@@ -840,9 +841,9 @@ void launch_reduce_when(const double *partial, int P, int M, int ny, double *out
   // stage 1 writes S partial sums behind the P partials (the caller's partial
   // buffer holds (P + S) * MN doubles), stage 2 sums them in order.  S ~ sqrt(P)
   // balances the serial length of the two stages.
-  // (a few partials: one stage, one launch)
+  // (up to 64 partials: one stage, one launch)
   const int S_room = std::max(1, 8192 / ((MN + 255) / 256));
-  const int S = P <= 32 ? 1
+  const int S = P <= 64 ? 1
                         : std::max(1, std::min({P / 8, S_room, (int)std::ceil(std::sqrt((double)P))}));
   if (S > 1) {
     double *tmp = const_cast<double *>(partial) + (size_t)P * MN;
