@@ -76,6 +76,29 @@ def test_null_and_bad_arguments_are_rejected_without_a_device():
                                 None) == bbl.BBL_E_INVALID
 
 
+def test_plan_size_follows_the_slot_rule_without_a_device():
+    """No plan without the block_rows hint or for an unsupported width; a
+    16-vector FP32 plan has the slots, and so the bytes, of an 8-vector one
+    (the pipelined kernels take it as two 8-column halves), while a
+    16-vector FP64 plan stages fewer blocks than an 8-vector FP64 one."""
+    lib = bbl.load_library()
+    n, nnz = 20000, 2_000_000
+
+    def size(dtype, block_rows, nvec, vdt):
+        H = bbl._Csr(n, nnz, 1, 1, 1, dtype, block_rows)
+        return lib.bbl_spmm_plan_size(ctypes.byref(H), nvec, vdt)
+
+    assert size(bbl.BBL_F32, 0, 8, bbl.BBL_F32) == 0
+    assert size(bbl.BBL_F32, 1000, 3, bbl.BBL_F32) == 0
+    s8, s16 = size(bbl.BBL_F32, 1000, 8, bbl.BBL_F32), size(bbl.BBL_F32, 1000, 16, bbl.BBL_F32)
+    assert s8 > 0 and s16 == s8
+    # FP64: 2 slots at 8 vectors (64 KB blocks), 1 at 16 (128 KB): the block
+    # table shrinks by groups * 2 * (2 - 1) * 4 bytes (alignment aside)
+    d8, d16 = size(bbl.BBL_F64, 1000, 8, bbl.BBL_F64), size(bbl.BBL_F64, 1000, 16, bbl.BBL_F64)
+    assert d8 > d16 > 0
+    assert 0 < d8 - d16 <= 20 * 2 * 4 + 256
+
+
 def test_binding_fails_loudly_without_the_library(tmp_path):
     saved = bbl._lib
     bbl._lib = None
