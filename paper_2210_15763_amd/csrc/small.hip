@@ -358,24 +358,48 @@ __global__ __launch_bounds__(256) void k_colstats(int64_t n, int k, const double
   }
 }
 
-// factor[c] = sign(x[argmax|x|, c]) / ||x_c||
-__global__ void k_colfinish(int P, int k, const double *sumsq, const double *amax,
-                            const int64_t *aidx, const double *__restrict__ X, double *factor) {
-  const int c = threadIdx.x;
-  if (c >= k) return;
-  double sq = 0.0, am = -1.0;
-  int64_t ix = 0;
-  for (int p = 0; p < P; ++p) {
-    sq += sumsq[(int64_t)p * k + c];
-    const double a2 = amax[(int64_t)p * k + c];
-    const int64_t i2 = aidx[(int64_t)p * k + c];
-    if (a2 > am || (a2 == am && i2 < ix)) {
-      am = a2;
-      ix = i2;
+// factor[c] = sign(x[argmax|x|, c]) / ||x_c||.  One workgroup: per column,
+// the threads stride over the P partials, then a fixed-order tree combines
+// them (the largest |x| wins, ties to the lowest row index, as in k_colstats).
+__global__ __launch_bounds__(256) void k_colfinish(int P, int k, const double *sumsq,
+                                                   const double *amax, const int64_t *aidx,
+                                                   const double *__restrict__ X, double *factor) {
+  __shared__ double s_sq[256], s_am[256];
+  __shared__ int64_t s_ix[256];
+  for (int c = 0; c < k; ++c) {
+    double sq = 0.0, am = -1.0;
+    int64_t ix = 0;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+      sq += sumsq[(int64_t)p * k + c];
+      const double a2 = amax[(int64_t)p * k + c];
+      const int64_t i2 = aidx[(int64_t)p * k + c];
+      if (a2 > am || (a2 == am && i2 < ix)) {
+        am = a2;
+        ix = i2;
+      }
     }
+    s_sq[threadIdx.x] = sq;
+    s_am[threadIdx.x] = am;
+    s_ix[threadIdx.x] = ix;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        s_sq[threadIdx.x] += s_sq[threadIdx.x + w];
+        const double a2 = s_am[threadIdx.x + w];
+        const int64_t i2 = s_ix[threadIdx.x + w];
+        if (a2 > s_am[threadIdx.x] || (a2 == s_am[threadIdx.x] && i2 < s_ix[threadIdx.x])) {
+          s_am[threadIdx.x] = a2;
+          s_ix[threadIdx.x] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const double sgn = X[s_ix[0] * k + c] < 0.0 ? -1.0 : 1.0;
+      factor[c] = s_sq[0] > 0.0 ? sgn / sqrt(s_sq[0]) : 1.0;
+    }
+    __syncthreads();
   }
-  const double sgn = X[ix * k + c] < 0.0 ? -1.0 : 1.0;
-  factor[c] = sq > 0.0 ? sgn / sqrt(sq) : 1.0;
 }
 
 __global__ void k_colscale(int64_t n, int k, double *X, const double *factor) {
@@ -465,7 +489,7 @@ void launch_normalize_columns(int64_t n, int k, double *X, double *scratch, int 
   double *factor = reinterpret_cast<double *>(aidx + (size_t)P * k);
   hipLaunchKernelGGL(k_colstats, dim3(P), dim3(256), 0, s, n, k, X, sumsq, amax, aidx);
   check_launch("k_colstats");
-  hipLaunchKernelGGL(k_colfinish, dim3(1), dim3(64), 0, s, P, k, sumsq, amax, aidx, X, factor);
+  hipLaunchKernelGGL(k_colfinish, dim3(1), dim3(256), 0, s, P, k, sumsq, amax, aidx, X, factor);
   check_launch("k_colfinish");
   const int64_t grid = std::min<int64_t>(4096, ceil_div(n * k, 256));
   hipLaunchKernelGGL(k_colscale, dim3((unsigned)grid), dim3(256), 0, s, n, k, X, factor);
