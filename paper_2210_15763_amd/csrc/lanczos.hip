@@ -358,6 +358,23 @@ struct Solver {
   // stream once the recurrence has produced B_{nblk-1}.  chk[0..2kk] receives
   // the Ritz values, residual estimates and ||T||_est, chk[64] (as int) the
   // QR breakdown flag as of this point; both are copied to pinned memory.
+  // A check due at the end of a block is armed there and launched right
+  // after the next block's SpMM is queued, so that it runs beside that block's
+  // tall-skinny products instead of holding compute units the SpMM needs (a
+  // planned-SpMM workgroup takes a whole CU's LDS).  It reads only band rows
+  // of blocks that are complete.
+  int armed_nblk_ = 0, armed_kk_ = 0;
+  void arm_check(int nblk, int kk) {
+    armed_nblk_ = nblk;
+    armed_kk_ = kk;
+  }
+  void fire_armed(CheckStream &cq) {
+    if (!armed_nblk_) return;
+    const int nb = armed_nblk_, kk = armed_kk_;
+    armed_nblk_ = 0;
+    launch_check(cq, nb, kk);
+  }
+
   void launch_check(CheckStream &cq, int nblk, int kk) {
     int *flag_copy = reinterpret_cast<int *>(chk + 64);
     BBL_HIP(hipMemcpyAsync(flag_copy, breakdown, sizeof(int), hipMemcpyDeviceToDevice, s));
@@ -377,6 +394,7 @@ struct Solver {
   // the Ritz vectors and their explicit residuals.  True when converged.
   bool consume_check(CheckStream &cq, int nblk, int kk, bool final, double *hnorm_dev,
                      double *Xout, Result &R) {
+    fire_armed(cq);  // (a check is always launched before it is read)
     BBL_HIP(hipEventSynchronize(cq.done));
     const double *hres = cq.host;
     int flag = 0;
@@ -438,6 +456,7 @@ struct Solver {
     else launch_spmm(H, slot(J), xd, W, xd, b, s);
     timer.end(J, s);
     ++R.spmm_calls;
+    fire_armed(cq);
     gram(slot(J), xd, b, 1, 0, W, xd, b, Araw);
     launch_set_A(Araw, b, J, band, b, J > 0 ? Bstore + (size_t)(J - 1) * b * b : nullptr, C3,
                  dres + kHn2Slot, s);
@@ -494,6 +513,7 @@ struct Solver {
         if (!f[0] && !f[2]) continue;
         unverified.clear();
         if (pending) {  // its band matrix may contain discarded blocks
+          armed_nblk_ = 0;
           BBL_HIP(hipStreamSynchronize(cq.cs));
           pending = 0;
         }
@@ -552,7 +572,7 @@ struct Solver {
       }
       // one check in flight at a time; a due check waits for the slot
       if (N >= k && J + 1 >= next_check && !pending) {
-        launch_check(cq, J + 1, kk);
+        arm_check(J + 1, kk);
         ++R.checks;
         pending = J + 1;
         pending_kk = kk;
