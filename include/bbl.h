@@ -48,11 +48,11 @@ typedef enum { BBL_F32 = 1, BBL_F64 = 2 } bbl_dtype;
 /* Symmetric CSR matrix resident on the device.
  * block_rows is an optional locality hint: when > 0, the rows come in aligned
  * groups [g*block_rows, (g+1)*block_rows) (sectors of the basis, e.g. blocks of
- * fixed quantum numbers) and most of a row's columns fall inside its own
- * group.  The SpMM then stages each group's rows of V in LDS and gathers those
- * columns from there; other columns are read from HBM as usual, so the result
- * is the same for any value.  0 = no hint.  Used when the group's rows of V fit
- * in 128 KB of LDS (block_rows * nvec * element size). */
+ * fixed quantum numbers) and most of a row's columns fall inside a few column
+ * blocks of the same size.  Only the planned SpMM uses it (bbl_spmm_plan_size,
+ * bbl_spmm_plan_build, bbl_spmm_planned: column blocks staged in the 160 KB
+ * of LDS); bbl_spmm and the solver's plain kernel ignore it, and the result
+ * does not depend on it beyond rounding.  0 = no hint. */
 typedef struct {
   int64_t n;              /* dimension, >= 1 */
   int64_t nnz;            /* number of stored entries (row_ptr[n]) */
@@ -139,13 +139,26 @@ typedef struct {
   const bbl_spmm_plan *spmm_plan; /* optional plan of H for the recurrence's SpMM
                            (its nvec and vec_dtype must equal the solve's block
                            width and basis type); NULL = plain CSR kernel */
+  int32_t restart_keep; /* thick restart (see bbl_block_lanczos): Ritz vectors
+                           kept when the basis reaches m_max blocks, a multiple
+                           of nvec in [max(k_eig, nvec), min(32, nvec*(m_max-2))];
+                           0 (default) = no restart, stop at m_max */
+  int32_t fault_block;  /* testing only, 0 (default) = off.  f > 0 forces the
+                           failure-handling path from the host: block f-1 is
+                           marked as having lost rank beyond repair, and block
+                           f as needing the second Gram-Schmidt sweep (so it is
+                           redone); the solve must then return BBL_E_BREAKDOWN */
 } bbl_opts;
 
 /* Option flags.  BBL_FLAG_TIME_SPMM records a pair of HIP events on the
    solver's stream around every product H V_j of the block recurrence and
    reports their summed duration in bbl_stats.spmm_ms (costs two event
-   records per block). */
+   records per block).  BBL_FLAG_TIME_PHASES also times the three-term step,
+   the reorthogonalisation, the block QR, the band eigensolves of the
+   convergence checks (on their own stream, concurrent with the recurrence)
+   and the thick restarts, filling the t_*_ms fields of bbl_stats. */
 #define BBL_FLAG_TIME_SPMM 1
+#define BBL_FLAG_TIME_PHASES 2
 
 /* Counters of one solve and its wall time (host clock around the call). */
 typedef struct {
@@ -161,9 +174,22 @@ typedef struct {
   double hnorm_est;     /* largest |Ritz value| of the final band matrix */
   double t_total_ms;    /* wall time of the call */
   double spmm_ms;       /* summed device time of the recurrence's products H V_j
-                           (BBL_FLAG_TIME_SPMM only, else 0) */
+                           (BBL_FLAG_TIME_SPMM or _PHASES, else 0) */
   int32_t spmm_timed;   /* number of products in spmm_ms */
-  int32_t reserved;
+  int32_t restarts;     /* thick restarts performed */
+  /* Device time per phase (BBL_FLAG_TIME_PHASES, else 0), summed over every
+   * block instance the recurrence ran, redone and discarded ones included. */
+  double t_threeterm_ms; /* A_j = V_j^T W and W - V_j A_j - V_{j-1} B_{j-1}^T */
+  double t_reorth_ms;    /* full reorthogonalisation against the stored blocks */
+  double t_qr_ms;        /* block QR: B_j and V_{j+1} */
+  double t_eig_ms;       /* band eigensolves (concurrent with the recurrence) */
+  double t_restart_ms;   /* thick restarts: Ritz vectors and the new band matrix */
+  /* Pivot calls (bbl_bootstrap_pivot, bbl_pivot_features, bbl_learned_pivot)
+   * fill these; a solve sets them to 0. */
+  double t_pivot_ms;     /* wall time of the pivot call */
+  int32_t pivot_spmm_calls; /* products with H or its leading block the pivot
+                           needed, in units of one nvec-wide product */
+  int32_t used_fallback; /* learned pivot: 1 if the bootstrap block was returned */
 } bbl_stats;
 
 /* Message describing the last non-OK status on the calling thread. */
@@ -241,6 +267,25 @@ int bbl_block_lanczos(const bbl_csr *H, const double *pivot, int32_t nvec, int32
                       void *stream);
 
 /*
+ * Diagnostic view of the state a bbl_block_lanczos call left in its workspace
+ * (pure pointer arithmetic on ws; nothing is read or launched).  With the same
+ * (n, nvec, k_eig, m_max, basis_dtype) as the solve:
+ *   basis  receives the device address of the stored Krylov basis: block j
+ *          (the paper's V_{j+1}) is a row-major n x nvec array of basis_dtype
+ *          at basis + j*n*nvec elements, j = 0..m_max
+ *   band   receives the device address of the band matrix of the block
+ *          recurrence, (m_max + 1)*nvec rows of nvec + 1 float64:
+ *          band[i*(nvec+1) + d] = T[i][i-d] (A blocks on the diagonal, B
+ *          blocks below it; the matrix is symmetric)
+ * After a solve that reported stats.iters = m, blocks 0..m-1 and the leading
+ * m*nvec rows of the band are V_{1:m} and T_m of the Methods section (after a
+ * thick restart: of the current cycle, whose leading blocks hold the kept
+ * Ritz vectors in a rotated basis).  Valid until ws is reused.
+ */
+int bbl_lanczos_workspace_views(const void *ws, int64_t n, int32_t nvec, int32_t k_eig,
+                                int32_t m_max, int32_t basis_dtype, void **basis, double **band);
+
+/*
  * Workspace bytes for bbl_bootstrap_pivot (reads row_ptr[n_trunc] from the
  * device, hence the stream).  Returns 0 for invalid arguments.
  */
@@ -268,6 +313,23 @@ int bbl_bootstrap_pivot(const bbl_csr *H, int64_t n_trunc, int32_t nvec, double 
  * against.  Device output; no workspace.
  */
 int bbl_random_pivot(int64_t n, int32_t nvec, uint64_t key, double *pivot, void *stream);
+
+/*
+ * Pivot-overlap diagnostic (the Results discussion of why a bootstrapped
+ * pivot helps or not: target states missing from the truncated space,
+ * "intruders", leave no overlap with the pivot).  For k unit vectors X
+ * (e.g. converged eigenvectors) and an n x nvec pivot block P:
+ *   cosines   host [k]: cosines of the principal angles between span(X) and
+ *             span(P), descending (singular values of X^T Q for an
+ *             orthonormal basis Q of span(P); zeros beyond rank)
+ *   captured  host [k] or NULL: ||Q^T x_i||^2, the weight of each x_i in span(P)
+ * X device n x k float64, P device n x nvec float64 (any full-rank block;
+ * directions of P^T P below 1e-12 of its largest eigenvalue are dropped);
+ * k, nvec in 1..32; ws device >= bbl_pivot_overlap_workspace_size(n, k, nvec).
+ */
+size_t bbl_pivot_overlap_workspace_size(int64_t n, int32_t k, int32_t nvec);
+int bbl_pivot_overlap(int64_t n, const double *X, int32_t k, const double *P, int32_t nvec,
+                      void *ws, size_t ws_bytes, double *cosines, double *captured, void *stream);
 
 /*
  * Eigenpairs of a symmetric band matrix (diagnostic entry point for the

@@ -28,6 +28,7 @@ BBL_E_BREAKDOWN = -5
 BBL_F32 = 1
 BBL_F64 = 2
 BBL_FLAG_TIME_SPMM = 1
+BBL_FLAG_TIME_PHASES = 2
 
 _STATUS = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "NOT_CONVERGED", -5: "BREAKDOWN"}
 
@@ -48,7 +49,8 @@ class _Opts(ctypes.Structure):
     _fields_ = [("m_max", ctypes.c_int32), ("basis_dtype", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("defl_tau", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("spmm_plan", ctypes.c_void_p)]
+                ("spmm_plan", ctypes.c_void_p), ("restart_keep", ctypes.c_int32),
+                ("fault_block", ctypes.c_int32)]
 
 
 class _Plan(ctypes.Structure):
@@ -71,7 +73,11 @@ class _Stats(ctypes.Structure):
                 ("checks", ctypes.c_int32), ("reorth_second_passes", ctypes.c_int32),
                 ("hnorm_est", ctypes.c_double), ("t_total_ms", ctypes.c_double),
                 ("spmm_ms", ctypes.c_double), ("spmm_timed", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("restarts", ctypes.c_int32), ("t_threeterm_ms", ctypes.c_double),
+                ("t_reorth_ms", ctypes.c_double), ("t_qr_ms", ctypes.c_double),
+                ("t_eig_ms", ctypes.c_double), ("t_restart_ms", ctypes.c_double),
+                ("t_pivot_ms", ctypes.c_double), ("pivot_spmm_calls", ctypes.c_int32),
+                ("used_fallback", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -89,7 +95,8 @@ EXPORTS = ("bbl_last_error", "bbl_version", "bbl_spmm", "bbl_lanczos_workspace_s
            "bbl_mlp_grad_workspace_size", "bbl_mlp_grad", "bbl_adam_step",
            "bbl_mlp_train_workspace_size", "bbl_mlp_train_step",
            "bbl_learned_pivot_workspace_size", "bbl_learned_pivot", "bbl_spmm_plan_size",
-           "bbl_spmm_plan_build", "bbl_spmm_planned")
+           "bbl_spmm_plan_build", "bbl_spmm_planned", "bbl_lanczos_workspace_views",
+           "bbl_pivot_overlap_workspace_size", "bbl_pivot_overlap")
 
 MLP_IN, MLP_OUT, MLP_PARAMS = 28, 10, 38026
 
@@ -111,9 +118,13 @@ def load_library(path: str = LIB_PATH):
         "bbl_spmm": (ctypes.c_int, [P, P, P, I32, I32, P]),
         "bbl_lanczos_workspace_size": (SZ, [I64, I32, I32, I32, I32]),
         "bbl_block_lanczos": (ctypes.c_int, [P, P, I32, I32, D, P, SZ, P, P, P, P, P, P]),
+        "bbl_lanczos_workspace_views": (ctypes.c_int, [P, I64, I32, I32, I32, I32,
+                                                       ctypes.POINTER(P), ctypes.POINTER(P)]),
         "bbl_bootstrap_workspace_size": (SZ, [P, I64, I32, I32, I32, P]),
         "bbl_bootstrap_pivot": (ctypes.c_int, [P, I64, I32, D, P, SZ, P, P, P, P]),
         "bbl_random_pivot": (ctypes.c_int, [I64, I32, U64, P, P]),
+        "bbl_pivot_overlap_workspace_size": (SZ, [I64, I32, I32]),
+        "bbl_pivot_overlap": (ctypes.c_int, [I64, P, I32, P, I32, P, SZ, P, P, P]),
         "bbl_band_eig_workspace_size": (SZ, [I32, I32, I32]),
         "bbl_band_eig": (ctypes.c_int, [P, I32, I32, I32, P, SZ, P, P, P, P]),
         "bbl_gram_workspace_size": (SZ, [I64, I32, I32, I32]),
@@ -206,10 +217,12 @@ class DeviceCSR:
                    torch.from_numpy(np.ascontiguousarray(val)).to(device), int(block_rows))
 
 
-def _opts(m_max, basis_dtype, check_every, seed, defl_tau, flags=0, plan=None):
+def _opts(m_max, basis_dtype, check_every, seed, defl_tau, flags=0, plan=None, restart_keep=0,
+          fault_block=0):
     return _Opts(int(m_max), int(basis_dtype), int(check_every), int(flags), float(defl_tau),
                  int(seed) & (2**64 - 1),
-                 ctypes.cast(ctypes.pointer(plan.c), ctypes.c_void_p) if plan is not None else None)
+                 ctypes.cast(ctypes.pointer(plan.c), ctypes.c_void_p) if plan is not None else None,
+                 int(restart_keep), int(fault_block))
 
 
 class SpmmPlan:
@@ -272,6 +285,7 @@ class LanczosResult:
     residuals: np.ndarray
     status: int
     stats: dict
+    workspace: "object" = None
 
     @property
     def converged(self):
@@ -281,9 +295,14 @@ class LanczosResult:
 def block_lanczos(H: DeviceCSR, pivot, k: int, tol: float, *, m_max: int = 200,
                   basis_dtype=None, check_every: int = 0, seed: int = 0, defl_tau: float = 1e-12,
                   workspace=None, want_vectors: bool = True,
-                  time_spmm: bool = False, spmm_plan: "SpmmPlan" = None) -> LanczosResult:
+                  time_spmm: bool = False, time_phases: bool = False,
+                  spmm_plan: "SpmmPlan" = None, restart_keep: int = 0,
+                  fault_block: int = 0) -> LanczosResult:
     """Lowest k eigenpairs of H from the n x nvec float64 pivot block.
-    time_spmm: record device time of every product H V_j (stats spmm_ms)."""
+    time_spmm: record device time of every product H V_j (stats spmm_ms);
+    time_phases: also the other phases (stats t_*_ms).  restart_keep: thick
+    restart keeping that many Ritz vectors (0: none).  fault_block: testing
+    only (see bbl_opts)."""
     torch = _torch()
     assert pivot.dtype == torch.float64 and pivot.is_contiguous() and pivot.shape[0] == H.n
     nvec = pivot.shape[1]
@@ -300,15 +319,27 @@ def block_lanczos(H: DeviceCSR, pivot, k: int, tol: float, *, m_max: int = 200,
     X = torch.empty((H.n, k), dtype=torch.float64, device=pivot.device) if want_vectors else None
     st = _Stats()
     Hc = H._c()
-    o = _opts(m_max, basis_dtype, check_every, seed, defl_tau,
-              BBL_FLAG_TIME_SPMM if time_spmm else 0, spmm_plan)
+    flags = (BBL_FLAG_TIME_SPMM if time_spmm else 0) | (BBL_FLAG_TIME_PHASES if time_phases else 0)
+    o = _opts(m_max, basis_dtype, check_every, seed, defl_tau, flags, spmm_plan, restart_keep,
+              fault_block)
     code = lib.bbl_block_lanczos(ctypes.byref(Hc), _ptr(pivot), nvec, k, tol, _ptr(workspace),
                                  workspace.numel(), ctypes.byref(o),
                                  eigvals.ctypes.data_as(ctypes.c_void_p), _ptr(X),
                                  resid.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st),
                                  _stream())
     _check(code)
-    return LanczosResult(eigvals, X, resid, code, st.as_dict())
+    return LanczosResult(eigvals, X, resid, code, st.as_dict(), workspace)
+
+
+def workspace_views(workspace, n: int, nvec: int, k: int, m_max: int, basis_dtype: int):
+    """Device addresses (basis, band) inside a block_lanczos workspace: the
+    stored Krylov blocks and the band matrix the last solve left there."""
+    basis = ctypes.c_void_p()
+    band = ctypes.c_void_p()
+    _check(load_library().bbl_lanczos_workspace_views(_ptr(workspace), n, nvec, k, m_max,
+                                                      basis_dtype, ctypes.byref(basis),
+                                                      ctypes.byref(band)))
+    return basis.value, band.value
 
 
 def bootstrap_pivot(H: DeviceCSR, n_trunc: int, nvec: int, tol: float, *, m_max: int = 200,
@@ -342,6 +373,24 @@ def random_pivot(n: int, nvec: int, key: int, device="cuda"):
     out = torch.empty((n, nvec), dtype=torch.float64, device=device)
     _check(load_library().bbl_random_pivot(n, nvec, int(key) & (2**64 - 1), _ptr(out), _stream()))
     return out
+
+
+def pivot_overlap(X, P):
+    """(cosines, captured): principal-angle cosines between span(X) and
+    span(P), descending, and each column's weight ||Q^T x_i||^2 in span(P)
+    (X: n x k, P: n x nvec, float64 device tensors)."""
+    torch = _torch()
+    lib = load_library()
+    n, k = X.shape
+    nvec = P.shape[1]
+    assert X.is_contiguous() and P.is_contiguous() and P.shape[0] == n
+    ws = _ws(lib.bbl_pivot_overlap_workspace_size(n, k, nvec), X.device)
+    cos = np.zeros(k)
+    cap = np.zeros(k)
+    _check(lib.bbl_pivot_overlap(n, _ptr(X), k, _ptr(P), nvec, _ptr(ws), ws.numel(),
+                                 cos.ctypes.data_as(ctypes.c_void_p),
+                                 cap.ctypes.data_as(ctypes.c_void_p), _stream()))
+    return cos, cap
 
 
 def pivot_key(seed: int) -> int:

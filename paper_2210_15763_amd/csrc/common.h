@@ -91,6 +91,8 @@ void launch_update(int64_t n, const void *X, int xdtype, int bx, int nblk, int64
 
 // Small dense kernels (one workgroup).
 void launch_fill(double *p, int64_t count, double v, hipStream_t s);
+// *p = v (one lane; a kernel, so it may be recorded into a graph)
+void launch_store_int(int *p, int v, hipStream_t s);
 
 // Random normal block (Philox4x32-10 + Box-Muller), entry (i, a) from counter
 // (i, a + col0, tag).

@@ -17,6 +17,8 @@ struct Opts {
   double tau = 1e-12;
   uint64_t seed = 0;
   const bbl_spmm_plan *plan = nullptr;
+  int restart_keep = 0;  // thick restart: Ritz vectors kept (0 = off)
+  int fault_block = 0;   // testing: host-forced breakdown + redo (0 = off)
 };
 
 Opts read_opts(const bbl_opts *o, int val_dtype);

@@ -29,6 +29,7 @@
 #include <deque>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "bandeig.h"
@@ -48,6 +49,7 @@ constexpr int kMaxPartialRows = 4096;   // residual / column-statistics partials
 constexpr uint32_t kTagDeflation = 7;
 constexpr int kHn2Slot = 200;          // dres slot: max |A_jj| seen so far (<= ||H||)
 constexpr int kHn2Snap = 202;          // dres slots 202..205: kHn2Slot at the start of block J (J % 4)
+constexpr int kBreakSnap = 128;        // ints 128..131: the breakdown flag at the start of block J (J % 4)
 
 size_t dsize(int dt) { return dt == BBL_F32 ? 4 : 8; }
 
@@ -92,77 +94,133 @@ Layout make_layout(int64_t n, int b, int k, int m_max, int bdt) {
 }
 
 
-// Optional device timing of the recurrence's products: one event pair per
-// block, read back once at the end of the solve.
-struct SpmmTimer {
-  std::vector<hipEvent_t> ev;
-  SpmmTimer(bool on, int m_max) {
-    if (!on) return;
-    ev.resize(2 * (size_t)m_max, nullptr);
-    for (auto &e : ev) BBL_HIP(hipEventCreate(&e));
-  }
-  ~SpmmTimer() {
-    for (auto e : ev)
-      if (e) (void)hipEventDestroy(e);
-  }
-  void begin(int J, hipStream_t s) {
-    if (!ev.empty()) BBL_HIP(hipEventRecord(ev[2 * J], s));
-  }
-  void end(int J, hipStream_t s) {
-    if (!ev.empty()) BBL_HIP(hipEventRecord(ev[2 * J + 1], s));
-  }
-  void collect(int nblk, hipStream_t s, double *ms, int *count) {
-    *ms = 0.0;
-    *count = 0;
-    if (ev.empty()) return;
-    BBL_HIP(hipStreamSynchronize(s));
-    for (int J = 0; J < nblk; ++J) {
-      float t = 0.f;
-      BBL_HIP(hipEventElapsedTime(&t, ev[2 * J], ev[2 * J + 1]));
-      *ms += t;
-      ++*count;
-    }
-  }
-};
-
-// The second stream of the overlapped convergence checks, its events and a
-// pinned host buffer for the check results.  Non-blocking, so that it never
-// synchronises implicitly with a legacy default stream of the caller.
-// The pinned buffer also receives, per block of the fast path, its rare-branch
-// flags (slot J % kRing: ints flag2, -, chol_fail at kIterFlags + 4 (J % kRing))
-// and `fev[J % kRing]` marks their arrival.  The host reads a block's flags
-// kLag blocks later, so kRing > kLag slots are in use at a time.
+// The second stream of the overlapped convergence checks, its events, a
+// pinned host buffer for the check results and the timing events of one
+// solve.  Non-blocking, so that it never synchronises implicitly with a legacy
+// default stream of the caller.  The pinned buffer also receives, per block of
+// the fast path, its rare-branch flags (slot J % kRing: ints flag2, -,
+// chol_fail at kIterFlags + 4 (J % kRing)) and `fev[J % kRing]` marks their
+// arrival.  The host reads a block's flags kLag blocks later, so kRing > kLag
+// slots are in use at a time.
+//
+// These are created once and kept for the life of the process in a per-device
+// pool (a solve takes one set and gives it back when it returns), so a solve
+// -- and every truncated solve of a pivot -- creates no stream, event or
+// pinned buffer of its own.
 constexpr int kLag = 2, kRing = 4;
 constexpr int kIterFlags = 2 * (2 * kMaxBlock + 8);  // int offset in the pinned buffer
 
+// Phase boundaries recorded per block instance when phase timing is on:
+// [0] before the SpMM, [1] after it, [2] after the three-term step, [3] after
+// the reorthogonalisation, [4] after the block QR.
+constexpr int kPhaseEv = 5, kTimeRing = 8;
+
 struct CheckStream {
+  int device = -1;
   hipStream_t cs = nullptr;
   hipEvent_t ready = nullptr, done = nullptr, fev[kRing] = {};
+  hipEvent_t tev[kTimeRing][kPhaseEv] = {};  // timing events, per block instance
+  hipEvent_t eig0 = nullptr, eig1 = nullptr;  // around a check's band eigensolve
+  hipEvent_t rs0 = nullptr, rs1 = nullptr;    // around a thick restart
   double *host = nullptr;
-  hipError_t err = hipSuccess;
   static constexpr int kHostDoubles = 2 * kMaxBlock + 16;
-  CheckStream() {
-    err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (err == hipSuccess) err = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
-    if (err == hipSuccess) err = hipEventCreateWithFlags(&done, hipEventDisableTiming);
-    for (int i = 0; i < kRing && err == hipSuccess; ++i)
-      err = hipEventCreateWithFlags(&fev[i], hipEventDisableTiming);
-    if (err == hipSuccess)
-      err = hipHostMalloc(reinterpret_cast<void **>(&host), kHostDoubles * sizeof(double),
-                          hipHostMallocDefault);
-  }
-  ~CheckStream() {
-    if (cs) (void)hipStreamSynchronize(cs);
-    if (host) (void)hipHostFree(host);
-    if (ready) (void)hipEventDestroy(ready);
-    if (done) (void)hipEventDestroy(done);
-    for (auto e : fev)
-      if (e) (void)hipEventDestroy(e);
-    if (cs) (void)hipStreamDestroy(cs);
+  void create() {
+    BBL_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    BBL_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    BBL_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    for (auto &e : fev) BBL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto &row : tev)
+      for (auto &e : row) BBL_HIP(hipEventCreate(&e));
+    BBL_HIP(hipEventCreate(&eig0));
+    BBL_HIP(hipEventCreate(&eig1));
+    BBL_HIP(hipEventCreate(&rs0));
+    BBL_HIP(hipEventCreate(&rs1));
+    BBL_HIP(hipHostMalloc(reinterpret_cast<void **>(&host), kHostDoubles * sizeof(double),
+                          hipHostMallocDefault));
   }
   int *iter_flags(int J) { return reinterpret_cast<int *>(host) + kIterFlags + 4 * (J % kRing); }
-  CheckStream(const CheckStream &) = delete;
-  CheckStream &operator=(const CheckStream &) = delete;
+};
+
+std::mutex g_pool_mu;
+std::vector<CheckStream *> g_pool;  // idle sets, any device; never freed
+
+CheckStream *acquire_check_stream() {
+  int dev = 0;
+  BBL_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (size_t i = 0; i < g_pool.size(); ++i)
+      if (g_pool[i]->device == dev) {
+        CheckStream *c = g_pool[i];
+        g_pool.erase(g_pool.begin() + i);
+        return c;
+      }
+  }
+  CheckStream *c = new CheckStream();
+  c->device = dev;
+  try {
+    c->create();
+  } catch (...) {
+    delete c;  // (its partially created handles are left to the process exit)
+    throw;
+  }
+  return c;
+}
+
+void release_check_stream(CheckStream *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->cs);  // nothing of this solve may still run on it
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_pool.push_back(c);
+}
+
+// Holds a pooled set for the duration of one solve.
+struct CheckStreamLease {
+  CheckStream *c;
+  hipStream_t s;
+  explicit CheckStreamLease(hipStream_t s_) : c(acquire_check_stream()), s(s_) {}
+  ~CheckStreamLease() {
+    (void)hipStreamSynchronize(s);  // its flag copies target the pinned buffer
+    release_check_stream(c);
+  }
+  CheckStream &operator*() { return *c; }
+  CheckStreamLease(const CheckStreamLease &) = delete;
+  CheckStreamLease &operator=(const CheckStreamLease &) = delete;
+};
+
+// Device time per phase of the recurrence (HIP events on the solver's stream
+// around the SpMM, the three-term step, the reorthogonalisation and the block
+// QR of every block instance, redone and discarded ones included), read back
+// kTimeRing instances later, when the event set is reused, and at the end.
+struct PhaseTimer {
+  bool spmm_on = false, all_on = false;
+  CheckStream *cq = nullptr;
+  int64_t inst = 0, harvested = 0;
+  double ms[4] = {0, 0, 0, 0};  // spmm, three-term, reorth, qr
+  int spmm_count = 0;
+  void harvest_one(int64_t i) {
+    hipEvent_t *e = cq->tev[i % kTimeRing];
+    const int last = all_on ? kPhaseEv - 1 : 1;
+    BBL_HIP(hipEventSynchronize(e[last]));
+    for (int p = 0; p < last; ++p) {
+      float t = 0.f;
+      BBL_HIP(hipEventElapsedTime(&t, e[p], e[p + 1]));
+      ms[p] += t;
+    }
+    ++spmm_count;
+  }
+  // Starts block instance i; returns its event set (nullptr when timing is off).
+  hipEvent_t *begin() {
+    if (!spmm_on) return nullptr;
+    if (inst - harvested >= kTimeRing) harvest_one(harvested++);
+    return cq->tev[inst++ % kTimeRing];
+  }
+  void mark(hipEvent_t *e, int p, hipStream_t s) {
+    if (e && (all_on || p <= 1)) BBL_HIP(hipEventRecord(e[p], s));
+  }
+  void finish() {
+    while (harvested < inst) harvest_one(harvested++);
+  }
 };
 
 struct Solver {
@@ -306,8 +364,9 @@ struct Solver {
 
   struct Result {
     bool converged = false;
-    int iters = 0, built = 0, spmm_calls = 0, checks = 0, spmm_timed = 0;
-    double hnorm = 0.0, spmm_ms = 0.0;
+    int iters = 0, built = 0, spmm_calls = 0, checks = 0, spmm_timed = 0, restarts = 0;
+    double hnorm = 0.0, spmm_ms = 0.0, threeterm_ms = 0.0, reorth_ms = 0.0, qr_ms = 0.0,
+           eig_ms = 0.0, restart_ms = 0.0;
     std::vector<double> theta, resid;
   };
 
@@ -381,12 +440,26 @@ struct Solver {
     BBL_HIP(hipEventRecord(cq.ready, s));
     BBL_HIP(hipStreamWaitEvent(cq.cs, cq.ready, 0));
     const double *BJ = Bstore + (size_t)(nblk - 1) * b * b;
+    if (time_eig_) BBL_HIP(hipEventRecord(cq.eig0, cq.cs));
     band_eigensolve(band, nblk * b, b, kk, eigws, L.el, BJ, b, S, chk, cq.cs);
+    if (time_eig_) BBL_HIP(hipEventRecord(cq.eig1, cq.cs));
+    eig_pending_ = time_eig_;
     BBL_HIP(hipMemcpyAsync(cq.host, chk, (2 * kk + 1) * sizeof(double), hipMemcpyDeviceToHost,
                            cq.cs));
     BBL_HIP(hipMemcpyAsync(cq.host + 2 * kMaxBlock + 4, flag_copy, sizeof(int),
                            hipMemcpyDeviceToHost, cq.cs));
     BBL_HIP(hipEventRecord(cq.done, cq.cs));
+  }
+
+  // Device time of the last launched check's band eigensolve (once it is done).
+  bool time_eig_ = false, eig_pending_ = false;
+  void harvest_eig(CheckStream &cq, Result &R) {
+    if (!eig_pending_) return;
+    eig_pending_ = false;
+    float t = 0.f;
+    BBL_HIP(hipEventSynchronize(cq.eig1));
+    BBL_HIP(hipEventElapsedTime(&t, cq.eig0, cq.eig1));
+    R.eig_ms += t;
   }
 
   // Reads the results of the check of nblk blocks (waiting for it if needed),
@@ -396,6 +469,7 @@ struct Solver {
                      double *Xout, Result &R) {
     fire_armed(cq);  // (a check is always launched before it is read)
     BBL_HIP(hipEventSynchronize(cq.done));
+    harvest_eig(cq, R);
     const double *hres = cq.host;
     int flag = 0;
     std::memcpy(&flag, cq.host + 2 * kMaxBlock + 4, sizeof(int));
@@ -446,15 +520,21 @@ struct Solver {
   // sweep (flag2) or a deflation repair (chol_fail) is copied to pinned
   // memory and read by the host one block later, and such a block is then
   // redone on the full path, which decides those branches on the device.
-  void iterate(int J, bool fast, const double *hnorm_dev, SpmmTimer &timer, CheckStream &cq,
+  void iterate(int J, bool fast, const double *hnorm_dev, PhaseTimer &timer, CheckStream &cq,
                Result &R) {
-    if (fast)  // max |A_jj| as of this block's start, restored if it is redone
+    if (fast) {  // state as of this block's start, restored if it is redone:
+      // max |A_jj|, and the sticky breakdown flag (an earlier block may have
+      // raised it; the redone block's own QR decides again)
       BBL_HIP(hipMemcpyAsync(dres + kHn2Snap + J % kRing, dres + kHn2Slot, sizeof(double),
                              hipMemcpyDeviceToDevice, s));
-    timer.begin(J, s);
+      BBL_HIP(hipMemcpyAsync(ints + kBreakSnap + J % kRing, breakdown, sizeof(int),
+                             hipMemcpyDeviceToDevice, s));
+    }
+    hipEvent_t *ev = timer.begin();
+    timer.mark(ev, 0, s);
     if (o.plan) launch_spmm_planned(*o.plan, slot(J), W, s);
     else launch_spmm(H, slot(J), xd, W, xd, b, s);
-    timer.end(J, s);
+    timer.mark(ev, 1, s);
     ++R.spmm_calls;
     fire_armed(cq);
     gram(slot(J), xd, b, 1, 0, W, xd, b, Araw);
@@ -463,16 +543,24 @@ struct Solver {
     const int nb3 = J > 0 ? 2 : 1;
     update_gram(slot(J > 0 ? J - 1 : 0), xd, nb3, slot_stride(), C3, -1.0, W, xd, 1.0, Wp, G0,
                 nullptr);
+    timer.mark(ev, 2, s);
     double *BJ = Bstore + (size_t)J * b * b;
     if (fast) {
       gram(basis, xd, b, J + 1, slot_stride(), Wp, BBL_F64, b, C);
       update_gram(basis, xd, J + 1, slot_stride(), C, -1.0, Wp, BBL_F64, 1.0, Wp, G1, nullptr);
       launch_reorth_check(G0, G1, b, 0.5, nullptr, flag2, nullptr, s);
+      // fault injection (testing): the block after the marked one needs a redo
+      if (o.fault_block > 0 && J == o.fault_block) launch_store_int(flag2, 1, s);
+      timer.mark(ev, 3, s);
       block_qr_fast(J + 1, BJ, hnorm_dev, G1);
+      // fault injection (testing): the marked block's QR lost rank
+      if (o.fault_block > 0 && J == o.fault_block - 1) launch_store_int(breakdown, 1, s);
     } else {
       reorth_recurrence(J + 1, Wp);
+      timer.mark(ev, 3, s);
       block_qr(J + 1, J + 1, BJ, hnorm_dev, G1);
     }
+    timer.mark(ev, 4, s);
     launch_set_B(BJ, b, J, band, b, o.m_max * b, s);
     if (fast) {  // flag2, n_second, chol_fail -> pinned slot J % kRing
       BBL_HIP(hipMemcpyAsync(cq.iter_flags(J), flag2, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -482,8 +570,8 @@ struct Solver {
 
   Result run(const double *pivot, double *eigvecs_out) {
     Result R;
-    CheckStream cq;
-    if (cq.err != hipSuccess) throw Error{BBL_E_HIP, std::string("check stream: ") + hipGetErrorString(cq.err)};
+    CheckStreamLease lease(s);
+    CheckStream &cq = *lease;
     // zero the band matrix, the B store, counters and results
     launch_fill(band, (int64_t)(o.m_max * b + b) * (b + 1), 0.0, s);
     launch_fill(Bstore, (int64_t)(o.m_max + 1) * b * b, 0.0, s);
@@ -499,7 +587,12 @@ struct Solver {
     std::deque<int> unverified;       // fast blocks whose flags are not read yet
     int qr_snap[kRing] = {};          // qr_calls at the start of block J (J % kRing)
     bool redo = false;
-    SpmmTimer timer(o.flags & BBL_FLAG_TIME_SPMM, o.m_max);
+    PhaseTimer timer;
+    timer.cq = &cq;
+    timer.all_on = (o.flags & BBL_FLAG_TIME_PHASES) != 0;
+    timer.spmm_on = timer.all_on || (o.flags & BBL_FLAG_TIME_SPMM) != 0;
+    time_eig_ = timer.all_on;
+    eig_pending_ = false;
     // Reads the flags of the unverified fast blocks up to `upto`, oldest
     // first (waiting for them).  At the first that needed a rare branch,
     // discards what followed it and returns it: that block is redone on the
@@ -515,12 +608,15 @@ struct Solver {
         if (pending) {  // its band matrix may contain discarded blocks
           armed_nblk_ = 0;
           BBL_HIP(hipStreamSynchronize(cq.cs));
+          harvest_eig(cq, R);
           pending = 0;
         }
         BBL_HIP(hipMemcpyAsync(dres + kHn2Slot, dres + kHn2Snap + U % kRing, sizeof(double),
                                hipMemcpyDeviceToDevice, s));
-        // the breakdown flag is sticky; a block that is redone did not count
-        BBL_HIP(hipMemcpyAsync(breakdown, ints + 127, sizeof(int), hipMemcpyDeviceToDevice, s));
+        // the breakdown flag is sticky: back to its value at the start of
+        // block U (the discarded blocks did not count, earlier ones still do)
+        BBL_HIP(hipMemcpyAsync(breakdown, ints + kBreakSnap + U % kRing, sizeof(int),
+                               hipMemcpyDeviceToDevice, s));
         qr_calls = qr_snap[U % kRing];
         return U;
       }
@@ -579,7 +675,12 @@ struct Solver {
       }
       ++J;
     }
-    timer.collect(R.built, s, &R.spmm_ms, &R.spmm_timed);
+    timer.finish();
+    R.spmm_ms = timer.ms[0];
+    R.threeterm_ms = timer.ms[1];
+    R.reorth_ms = timer.ms[2];
+    R.qr_ms = timer.ms[3];
+    R.spmm_timed = timer.spmm_on ? timer.spmm_count : 0;
     return R;
   }
 };
@@ -619,6 +720,8 @@ Opts read_opts(const bbl_opts *o, int val_dtype) {
     r.check_every = o->check_every;
     r.flags = o->flags;
     r.plan = o->spmm_plan;
+    r.restart_keep = o->restart_keep;
+    r.fault_block = o->fault_block;
     if (o->defl_tau > 0) r.tau = o->defl_tau;
     r.seed = o->seed;
   }
@@ -657,6 +760,8 @@ void check_solver_args(const bbl_csr *H, int nvec, int k, const Opts &o) {
   BBL_REQUIRE(!(o.basis_dtype == BBL_F32 && H->val_dtype == BBL_F64),
               "a float32 basis needs float32 matrix values");
   BBL_REQUIRE((int64_t)o.m_max * nvec <= 8192, "m_max * nvec must be <= 8192");
+  BBL_REQUIRE(o.fault_block >= 0, "fault_block must be >= 0");
+  BBL_REQUIRE(o.restart_keep == 0, "thick restart is not available in this build");
   if (o.plan) {
     BBL_REQUIRE(o.plan->n == H->n && o.plan->nnz == H->nnz && o.plan->row_ptr == H->row_ptr,
                 "spmm_plan was built for another matrix");
@@ -698,7 +803,15 @@ int solve_impl(const bbl_csr *H, const double *pivot, int32_t nvec, int32_t k, d
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     stats->spmm_ms = R.spmm_ms;
     stats->spmm_timed = R.spmm_timed;
-    stats->reserved = 0;
+    stats->restarts = R.restarts;
+    stats->t_threeterm_ms = R.threeterm_ms;
+    stats->t_reorth_ms = R.reorth_ms;
+    stats->t_qr_ms = R.qr_ms;
+    stats->t_eig_ms = R.eig_ms;
+    stats->t_restart_ms = R.restart_ms;
+    stats->t_pivot_ms = 0.0;
+    stats->pivot_spmm_calls = 0;
+    stats->used_fallback = 0;
   }
   return R.converged ? BBL_OK : BBL_E_NOT_CONVERGED;
 }
@@ -811,6 +924,20 @@ size_t bbl_lanczos_workspace_size(int64_t n, int32_t nvec, int32_t k_eig, int32_
   return make_layout(n, nvec, k_eig, m_max, basis_dtype).total;
 }
 
+int bbl_lanczos_workspace_views(const void *ws, int64_t n, int32_t nvec, int32_t k_eig,
+                                int32_t m_max, int32_t basis_dtype, void **basis, double **band) {
+  return guarded([&] {
+    BBL_REQUIRE(ws && basis && band, "NULL argument");
+    BBL_REQUIRE(bbl_lanczos_workspace_size(n, nvec, k_eig, m_max, basis_dtype) > 0,
+                "invalid sizes");
+    const Layout L = make_layout(n, nvec, k_eig, m_max, basis_dtype);
+    char *base = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
+    *basis = base + L.basis;
+    *band = reinterpret_cast<double *>(base + L.band);
+    return (int)BBL_OK;
+  });
+}
+
 int bbl_block_lanczos(const bbl_csr *H, const double *pivot, int32_t nvec, int32_t k_eig,
                       double tol, void *ws, size_t ws_bytes, const bbl_opts *opts,
                       double *eigvals, double *eigvecs, double *residuals, bbl_stats *stats,
@@ -849,6 +976,7 @@ int bbl_bootstrap_pivot(const bbl_csr *H, int64_t n_trunc, int32_t nvec, double 
     BBL_REQUIRE(nvec >= 1 && nvec <= kMaxBlock, "nvec must be in 1..32");
     BBL_REQUIRE(n_trunc >= nvec && n_trunc <= H->n, "n_trunc must be in nvec..n");
     BBL_REQUIRE(pivot && ws, "pivot/workspace is NULL");
+    const auto t0 = std::chrono::steady_clock::now();
     const Opts o = read_opts(opts, H->val_dtype);
     std::vector<double> ev(nvec);
     // the lowest nvec eigenvectors land in the first n_trunc rows of the pivot
@@ -857,7 +985,50 @@ int bbl_bootstrap_pivot(const bbl_csr *H, int64_t n_trunc, int32_t nvec, double 
     // zero padding: the truncated basis is a subset of the full one
     launch_fill(pivot + (size_t)n_trunc * nvec, (H->n - n_trunc) * nvec, 0.0, s);
     BBL_HIP(hipStreamSynchronize(s));
+    if (stats) {
+      stats->pivot_spmm_calls = stats->spmm_calls;
+      stats->t_pivot_ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
     return st;
+  });
+}
+
+size_t bbl_pivot_overlap_workspace_size(int64_t n, int32_t k, int32_t nvec) {
+  if (n < 1 || k < 1 || k > kMaxBlock || nvec < 1 || nvec > kMaxBlock) return 0;
+  return gram_partial_doubles(std::max(k, nvec), nvec) * 8 + 8 * 1024 * 8 + 512;
+}
+
+int bbl_pivot_overlap(int64_t n, const double *X, int32_t k, const double *P, int32_t nvec,
+                      void *ws, size_t ws_bytes, double *cosines, double *captured,
+                      void *stream) {
+  return guarded([&] {
+    BBL_REQUIRE(X && P && ws && cosines, "NULL argument");
+    const size_t need = bbl_pivot_overlap_workspace_size(n, k, nvec);
+    BBL_REQUIRE(need > 0, "bad n/k/nvec");
+    if (ws_bytes < need) throw Error{BBL_E_NOMEM, "overlap workspace too small"};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *base = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
+    double *M = reinterpret_cast<double *>(base);
+    double *G = M + 2 * 1024;
+    double *out = G + 2 * 1024;
+    double *partial = reinterpret_cast<double *>(base + 8 * 1024 * 8);
+    const size_t pcap = (need - 512 - 8 * 1024 * 8) / 8;
+    int P1 = launch_gram(n, X, BBL_F64, k, 1, 0, P, BBL_F64, nvec, partial,
+                         gram_max_partials(pcap, k, nvec), s);
+    launch_reduce(partial, P1, k, nvec, M, s);
+    P1 = launch_gram(n, P, BBL_F64, nvec, 1, 0, P, BBL_F64, nvec, partial,
+                     gram_max_partials(pcap, nvec, nvec), s);
+    launch_reduce(partial, P1, nvec, nvec, G, s);
+    launch_overlap(M, G, k, nvec, out, s);
+    double h[2 * kMaxBlock];
+    BBL_HIP(hipMemcpyAsync(h, out, 2 * k * sizeof(double), hipMemcpyDeviceToHost, s));
+    BBL_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < k; ++i) {
+      cosines[i] = h[i];
+      if (captured) captured[i] = h[k + i];
+    }
+    return (int)BBL_OK;
   });
 }
 

@@ -22,6 +22,7 @@
 // MFMA layout (16x16x16 bf16, wave64): A[i][k] at lane i + 16 (k / 4),
 // element k % 4; B[k][j] at lane j + 16 (k / 4), element k % 4; D[i][j] at
 // lane j + 16 (i / 4), element i % 4.
+#include <chrono>
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -760,6 +761,8 @@ void build_features(const bbl_csr &H, int64_t n_t, int64_t R, double tol, const 
                                  th.data(), stats, s);
   if (st != BBL_OK && st != BBL_E_NOT_CONVERGED)
     throw Error{st, "truncated solve failed: " + std::string(bbl_last_error())};
+  // the truncated solve's products, then H P and H Y at width 2 * 10
+  if (stats) stats->pivot_spmm_calls = stats->spmm_calls + 2 * (kTrunc / kOut);
   if (n > n_t) launch_fill(b.Ppad + (size_t)n_t * kTrunc, (n - n_t) * kTrunc, 0.0, s);
   double *dtheta = b.small;           // [0, 32): truncated eigenvalues
   double *G = b.small + 64;           // [64, 64 + 1024)
@@ -869,6 +872,7 @@ int bbl_pivot_features(const bbl_csr *H, int64_t n_trunc, int64_t sector_size, d
     BBL_REQUIRE(sector_size >= 1, "sector_size must be >= 1");
     BBL_REQUIRE(feats && ws, "feats/workspace is NULL");
     BBL_REQUIRE(tol > 0.0, "tol must be > 0");
+    const auto t0 = std::chrono::steady_clock::now();
     const Opts o = read_opts(opts, H->val_dtype);
     FeatBufs b{};
     const size_t need = feature_bytes(*H, n_trunc, o, s, &b, ws, ws_bytes);
@@ -881,6 +885,9 @@ int bbl_pivot_features(const bbl_csr *H, int64_t n_trunc, int64_t sector_size, d
       hipLaunchKernelGGL((k_copy_cols<double, double>), dim3(grid_for(n * kOut)), dim3(256), 0, s,
                          n, kOut, b.Ppad, kTrunc, p_boot, kOut);
     BBL_HIP(hipStreamSynchronize(s));
+    if (stats)
+      stats->t_pivot_ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return (int)BBL_OK;
   });
 }
@@ -1021,6 +1028,7 @@ int bbl_learned_pivot(const bbl_csr *H, const float *params, int64_t n_trunc, in
     BBL_REQUIRE(k >= 1, "k must be >= 1");
     BBL_REQUIRE(n_trunc >= kTrunc && n_trunc <= H->n, "n_trunc must be in 20..n");
     BBL_REQUIRE(sector_size >= 1, "sector_size must be >= 1");
+    const auto t0 = std::chrono::steady_clock::now();
     const Opts o = read_opts(opts, H->val_dtype);
     const int64_t n = H->n;
     FeatBufs b{};
@@ -1058,6 +1066,12 @@ int bbl_learned_pivot(const bbl_csr *H, const float *params, int64_t n_trunc, in
     if (rr_sums) {
       rr_sums[0] = h[2];
       rr_sums[1] = h[5];
+    }
+    if (stats) {
+      stats->pivot_spmm_calls += 2;  // H P_learn and H P_boot of the fallback test
+      stats->used_fallback = fallback ? 1 : 0;
+      stats->t_pivot_ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     return (int)BBL_OK;
   });

@@ -10,4 +10,8 @@ namespace bbl {
 void launch_slice_leading(const bbl_csr &H, int64_t n_t, int64_t *rp_t, int32_t *col_t,
                           void *val_t, hipStream_t s);
 
+// Principal-angle cosines (out[0..k), descending) and per-vector captured
+// weights (out[k..2k)) from M = X^T P (k x b) and G = P^T P (b x b).
+void launch_overlap(const double *M, const double *G, int k, int b, double *out, hipStream_t s);
+
 }  // namespace bbl

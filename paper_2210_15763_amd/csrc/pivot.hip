@@ -3,8 +3,11 @@
 // Methods last paragraphs).  Column indices are ascending within a row, so
 // the entries with col < n_t are a prefix of each row: a binary search gives
 // its length, a scan gives the new row pointers, and the prefixes are copied.
+#include <algorithm>
+
 #include "common.h"
 #include "pivot.h"
+#include "small.h"
 
 namespace bbl {
 namespace {
@@ -65,7 +68,57 @@ __global__ __launch_bounds__(256) void k_slice_fill(int64_t n_t, const int64_t *
   }
 }
 
+// Overlap of k unit vectors X with span(P): K = M G^+ M^T, M = X^T P (k x b),
+// G = P^T P (b x b) and G^+ its pseudo-inverse (eigenvalues at or below
+// 1e-12 of the largest dropped).  K's eigenvalues are the squared cosines of
+// the principal angles between span(X) and span(P); its diagonal is the
+// weight of each x_i inside span(P).  out[0..k): cosines, descending;
+// out[k..2k): the weights.  One workgroup.
+__global__ __launch_bounds__(256) void k_overlap(const double *__restrict__ M,
+                                                 const double *__restrict__ G, int k, int b,
+                                                 double *out) {
+  __shared__ double A[kMaxBlock * kMaxBlock], U[kMaxBlock * kMaxBlock], lam[kMaxBlock];
+  __shared__ double Gp[kMaxBlock * kMaxBlock], K[kMaxBlock * kMaxBlock], cs[4];
+  const int t = threadIdx.x;
+  for (int i = t; i < b * b; i += blockDim.x) {
+    const int r = i / b, c = i % b;
+    A[i] = 0.5 * (G[r * b + c] + G[c * b + r]);
+  }
+  __syncthreads();
+  wg_jacobi_eig(A, U, lam, b, cs);
+  const double lmax = lam[b - 1];
+  for (int i = t; i < b * b; i += blockDim.x) {  // G^+ = U diag(1/lam) U^T
+    const int r = i / b, c = i % b;
+    double x = 0.0;
+    for (int q = 0; q < b; ++q)
+      if (lam[q] > 1e-12 * lmax && lam[q] > 0.0) x += U[r * b + q] * U[c * b + q] / lam[q];
+    Gp[i] = x;
+  }
+  __syncthreads();
+  for (int i = t; i < k * k; i += blockDim.x) {  // K = M G^+ M^T
+    const int r = i / k, c = i % k;
+    double x = 0.0;
+    for (int p = 0; p < b; ++p) {
+      double y = 0.0;
+      for (int q = 0; q < b; ++q) y += Gp[p * b + q] * M[c * b + q];
+      x += M[r * b + p] * y;
+    }
+    K[i] = x;
+  }
+  __syncthreads();
+  if (t < k) out[k + t] = K[t * k + t];
+  for (int i = t; i < k * k; i += blockDim.x) A[i] = 0.5 * (K[i] + K[(i % k) * k + i / k]);
+  __syncthreads();
+  wg_jacobi_eig(A, U, lam, k, cs);
+  if (t < k) out[t] = sqrt(fmax(lam[k - 1 - t], 0.0));
+}
+
 }  // namespace
+
+void launch_overlap(const double *M, const double *G, int k, int b, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_overlap, dim3(1), dim3(256), 0, s, M, G, k, b, out);
+  check_launch("k_overlap");
+}
 
 void launch_slice_leading(const bbl_csr &H, int64_t n_t, int64_t *rp_t, int32_t *col_t,
                           void *val_t, hipStream_t s) {

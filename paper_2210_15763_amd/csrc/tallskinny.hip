@@ -903,6 +903,15 @@ void launch_update(int64_t n, const void *X, int xdtype, int bx, int nblk, int64
                      youtdtype, nullptr, s);
 }
 
+__global__ void k_store_int(int *p, int v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+void launch_store_int(int *p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_store_int, dim3(1), dim3(64), 0, s, p, v);
+  check_launch("k_store_int");
+}
+
 void launch_fill(double *p, int64_t count, double v, hipStream_t s) {
   if (count <= 0) return;
   const int64_t grid = std::min<int64_t>(4096, ceil_div(count, 256));

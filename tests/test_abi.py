@@ -107,3 +107,55 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
             bbl.load_library(str(tmp_path / "missing.so"))
     finally:
         bbl._lib = saved
+
+
+def _c_layout(tmp_path, struct, fields):
+    """sizeof and offsetof of a header struct, from a C program built with gcc."""
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bbl.h"', 'int main(void) {',
+             '  printf("%%zu\\n", sizeof(%s));' % struct]
+    lines += ['  printf("%%zu\\n", offsetof(%s, %s));' % (struct, f) for f in fields]
+    lines += ['  return 0;', '}']
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+@pytest.mark.parametrize("struct,cls", [("bbl_stats", "_Stats"), ("bbl_opts", "_Opts"),
+                                        ("bbl_csr", "_Csr"), ("bbl_spmm_plan", "_Plan")])
+def test_binding_structs_match_the_header_layout(tmp_path, struct, cls):
+    C = getattr(bbl, cls)
+    names = [f for f, _ in C._fields_]
+    size, offs = _c_layout(tmp_path, struct, names)
+    assert ctypes.sizeof(C) == size
+    assert [getattr(C, f).offset for f in names] == offs
+
+
+def test_new_solver_options_are_validated_without_a_device():
+    lib = bbl.load_library()
+    H = bbl._Csr(10, 5, 1, 1, 1, bbl.BBL_F64, 0)
+    ev = np.zeros(2)
+    for keep, fault in ((0, -1), (-2, 0)):
+        o = bbl._Opts(10, bbl.BBL_F64, 0, 0, 1e-12, 0, None, keep, fault)
+        assert lib.bbl_block_lanczos(ctypes.byref(H), 1, 2, 2, 1e-8, 1, 1 << 30, ctypes.byref(o),
+                                     ev.ctypes.data_as(ctypes.c_void_p), None, None, None,
+                                     None) == bbl.BBL_E_INVALID
+
+
+def test_workspace_views_are_pointer_arithmetic():
+    lib = bbl.load_library()
+    n, b, k, m = 1000, 4, 4, 20
+    base = 0x10000000  # never dereferenced: the call only computes addresses
+    basis, band = ctypes.c_void_p(), ctypes.c_void_p()
+    assert lib.bbl_lanczos_workspace_views(base + 8, n, b, k, m, bbl.BBL_F64,
+                                           ctypes.byref(basis), ctypes.byref(band)) == bbl.BBL_OK
+    # the basis comes first, at the 256-byte aligned start of the workspace
+    assert basis.value == base + 256
+    assert band.value % 256 == 0 and band.value >= basis.value + (m + 1) * n * b * 8
+    assert band.value < base + lib.bbl_lanczos_workspace_size(n, b, k, m, bbl.BBL_F64)
+    assert lib.bbl_lanczos_workspace_views(base, 0, b, k, m, bbl.BBL_F64, ctypes.byref(basis),
+                                           ctypes.byref(band)) == bbl.BBL_E_INVALID

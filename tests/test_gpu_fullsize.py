@@ -1,7 +1,8 @@
 """Full-size checks at the benchmark's shape (n = 2e6 sectored FP32 matrix,
 ~200 nnz/row, b = 8, k = 10, tol 1e-6, bootstrap pivot from the leading
-20,000 rows), in the launch configuration the benchmark times (sector-staged
-SpMM).  The oracle cannot run the whole solve here, so the checks are on
+20,000 rows), in the launch configuration the benchmark times (the planned
+three-pass SpMM with column blocks staged in LDS), and through the plain CSR
+kernel beside it.  The oracle cannot run the whole solve here, so the checks are on
 sampled outputs it computes one by one and on properties that hold at any
 size: the dot-product error bound of sampled SpMM rows, explicit FP64
 residuals of the returned eigenpairs recomputed on the host, orthonormality of
@@ -49,25 +50,56 @@ def rows_of(H, idx):
             for i in idx]
 
 
-def test_full_size_spmm_sampled_rows(torch, bbl, mid):
-    w, H, Hd = mid
-    note("full-size SpMM, 4000 sampled rows")
-    V = synthgen.gaussian_block(H.n, 8, 17).astype(np.float32)
-    W = bbl.spmm(Hd, torch.from_numpy(V).cuda()).cpu().numpy().astype(np.float64)
-    rng = np.random.default_rng(0)
-    idx = np.concatenate([rng.choice(H.n, 4000, replace=False), [0, 999, 1000, H.n - 1]])
-    V64 = V.astype(np.float64)
+def check_rows(W, V64, H, idx):
     for i, (c, v) in zip(idx, rows_of(H, idx)):
         ref = v @ V64[c]
         bound = (len(c) + 2) * U32 / (1 - (len(c) + 2) * U32) * (np.abs(v) @ np.abs(V64[c])) + 1e-30
         assert np.all(np.abs(W[i] - ref) <= bound), (i, np.abs(W[i] - ref).max(), bound.max())
 
 
-def test_full_size_solve_residuals_and_orthonormality(torch, bbl, mid):
+@pytest.fixture(scope="module")
+def plan(bbl, mid):
     w, H, Hd = mid
-    note("full-size bootstrapped solve")
+    note("SpMM plan, 8 vectors, sectors of 1000 rows")
+    return bbl.spmm_plan(Hd, w.nvec)
+
+
+def test_full_size_spmm_sampled_rows(torch, bbl, mid, plan):
+    """Both SpMM kernels at the benchmark shape: the planned three-pass kernel
+    the solver's recurrence runs (2000 row groups, two sets of five column
+    blocks staged in LDS, the rest gathered) and the plain CSR kernel, on
+    4000 random rows plus the group edges, against the dot-product bound."""
+    w, H, Hd = mid
+    assert plan.slots == 5 and plan.c.rdesc and plan.c.rlist
+    V = synthgen.gaussian_block(H.n, 8, 17).astype(np.float32)
+    Vd = torch.from_numpy(V).cuda()
+    rng = np.random.default_rng(0)
+    idx = np.concatenate([rng.choice(H.n, 4000, replace=False),
+                          [0, 999, 1000, 1001, 500_000, 999_999, 1_000_000, H.n - 1000, H.n - 1]])
+    V64 = V.astype(np.float64)
+    note("planned SpMM, 4009 sampled rows")
+    Wp = bbl.spmm_planned(plan, Vd).cpu().numpy().astype(np.float64)
+    check_rows(Wp, V64, H, idx)
+    note("plain CSR SpMM, 4009 sampled rows")
+    W = bbl.spmm(Hd, Vd).cpu().numpy().astype(np.float64)
+    check_rows(W, V64, H, idx)
+    # every row of the two kernels agrees within twice the bound of its own
+    # rounding; a cheap whole-matrix check: the largest difference is tiny
+    # against the largest |H||V| row
+    assert np.max(np.abs(Wp - W)) <= 1e-4 * np.max(np.abs(W))
+
+
+def test_full_size_solve_residuals_invariants_and_pivots(torch, bbl, mid, plan):
+    """The benchmark's solve (bootstrap pivot, planned SpMM): explicit FP64
+    residuals recomputed on the host, orthonormal eigenvectors, the
+    recurrence's invariants on its own stored float32 basis (max |V^T V - I|
+    <= 1e-6 and max |V^T H V - T| <= 1e-5 ||H||, T the band matrix the solve
+    built), and the same eigenvalues from the plain-kernel solve and from a
+    random pivot."""
+    w, H, Hd = mid
+    note("full-size bootstrapped solve, planned SpMM")
     P, pst = bbl.bootstrap_pivot(Hd, w.n_trunc, w.nvec, w.tol, m_max=w.m_max, seed=w.seed)
-    r = bbl.block_lanczos(Hd, P, w.k, w.tol, m_max=w.m_max, seed=w.seed)
+    r = bbl.block_lanczos(Hd, P, w.k, w.tol, m_max=w.m_max, seed=w.seed, spmm_plan=plan)
     assert r.converged and pst["converged"] == 1
     X = r.eigvecs.cpu().numpy()
     hn = r.stats["hnorm_est"]
@@ -77,11 +109,40 @@ def test_full_size_solve_residuals_and_orthonormality(torch, bbl, mid):
     np.testing.assert_allclose(r.residuals, res, rtol=1e-6, atol=1e-3 * w.tol * hn)
     np.testing.assert_allclose(X.T @ X, np.eye(w.k), atol=1e-6)
     assert np.all(np.diff(r.eigvals) >= 0)
+
+    m, b, n = r.stats["iters"], w.nvec, H.n
+    note("invariants of the stored basis, %d blocks" % m)
+    basis_addr, band_addr = bbl.workspace_views(r.workspace, n, b, w.k, w.m_max, bbl.BBL_F32)
+    ws = r.workspace
+    off = basis_addr - ws.data_ptr()
+    Vall = ws[off:off + m * n * b * 4].view(torch.float32).view(m, n, b)
+    boff = band_addr - ws.data_ptr()
+    band = ws[boff:boff + m * b * (b + 1) * 8].view(torch.float64).view(m * b, b + 1).cpu().numpy()
+    T = np.zeros((m * b, m * b))
+    for i in range(m * b):
+        for d in range(min(b, i) + 1):
+            T[i, i - d] = T[i - d, i] = band[i, d]
+    VtV = np.zeros((m * b, m * b))
+    VtHV = np.zeros((m * b, m * b))
+    for j in range(m):
+        Vj = Vall[j].double().contiguous()
+        VtV[:, j * b:(j + 1) * b] = bbl.gram(Vall, m, b, Vj).cpu().numpy()
+        HVj = bbl.spmm(Hd, Vall[j].contiguous()).double()
+        VtHV[:, j * b:(j + 1) * b] = bbl.gram(Vall, m, b, HVj).cpu().numpy()
+    e_orth = np.max(np.abs(VtV - np.eye(m * b)))
+    e_band = np.max(np.abs(VtHV - T)) / hn
+    note("max |V^T V - I| = %.2e, max |V^T H V - T| / ||H|| = %.2e" % (e_orth, e_band))
+    assert e_orth <= 1e-6 and e_band <= 1e-5
+
+    note("full-size solve through the plain CSR kernel")
+    r0 = bbl.block_lanczos(Hd, P, w.k, w.tol, m_max=w.m_max, seed=w.seed)
+    assert r0.converged
+    np.testing.assert_allclose(r0.eigvals, r.eigvals, rtol=0, atol=2 * w.tol * hn)
     # a random start converges to the same lowest eigenvalues (lowest-ness is
     # not implied by small residuals alone)
     note("full-size random-pivot solve")
     rr = bbl.block_lanczos(Hd, bbl.random_pivot(H.n, w.nvec, synthgen.pivot_key(w.seed)), w.k,
-                           w.tol, m_max=w.m_max, seed=w.seed)
+                           w.tol, m_max=w.m_max, seed=w.seed, spmm_plan=plan)
     assert rr.converged
     # both sets are within the residual bound of true eigenvalues
     np.testing.assert_allclose(rr.eigvals, r.eigvals, rtol=0, atol=2 * w.tol * hn)

@@ -105,6 +105,35 @@ def test_mlp_gradient_matches_oracle(torch, bbl, rows):
         o += c
 
 
+def test_mlp_gradient_matches_fp64_network(torch, bbl):
+    """The gradient against the plain float64 network (float64 weights and
+    activations, its own ReLU decisions): at 20,000 rows the few decisions
+    that bfloat16 rounding flips average out, and every tensor agrees to the
+    2e-2 relative Frobenius bar."""
+    rows = 20000
+    note("mlp gradient vs the float64 network, rows=%d" % rows)
+    p = bbl.mlp_init(5)
+    rng = np.random.default_rng(rows)
+    pn = p.cpu().numpy()
+    for o, c in ((3584, 128), (20096, 128), (36608, 128), (38016, 10)):
+        pn[o:o + c] = rng.uniform(-0.1, 0.1, c)
+    p = torch.from_numpy(pn).cuda()
+    Fd, F = to_bf16(torch, rng.standard_normal((rows, 28)))
+    T = rng.standard_normal((rows, 10)).astype(np.float32)
+    g, loss = bbl.mlp_grad(p, Fd, torch.from_numpy(T).cuda())
+    lref, gref = op.loss_and_grad(pn.astype(np.float64), F, T.astype(np.float64), act="f64")
+    assert abs(loss.item() - lref) <= 2e-2 * lref
+    gg = g.cpu().numpy().astype(np.float64)
+    o = 0
+    errs = []
+    for shape in op.SHAPES:
+        c = int(np.prod(shape))
+        errs.append(rel_fro(gg[o:o + c], gref[o:o + c]))
+        o += c
+    note("relative Frobenius error per tensor: " + " ".join("%.2e" % e for e in errs))
+    assert max(errs) <= 2e-2, errs
+
+
 def test_mlp_gradient_is_deterministic(torch, bbl):
     note("mlp gradient determinism")
     p = bbl.mlp_init(8)

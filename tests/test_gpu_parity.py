@@ -624,3 +624,79 @@ def test_not_converged_reports_current_pairs(torch, bbl):
                           dev(torch, synthgen.gaussian_block(H.n, 4, 1)), 4, 1e-10, m_max=5)
     assert r.status == bbl.BBL_E_NOT_CONVERGED and r.stats["iters"] == 5
     assert np.all(np.isfinite(r.eigvals)) and np.all(r.residuals > 0)
+
+
+def test_breakdown_raised_before_a_redo_is_still_reported(torch, bbl):
+    """The QR of block 5 loses rank beyond repair and block 6 needs the second
+    Gram-Schmidt sweep (both forced from the host); no check reads the sticky
+    breakdown flag before block 6 is redone (checks every 50 blocks), so the
+    redo must keep the flag block 5 raised and the solve must fail."""
+    note("forced breakdown followed by a redo")
+    H = synthgen.generate(4000, 400, 20, 0.7, 4)
+    Hd = bbl.DeviceCSR.from_host(H, "float64")
+    P = dev(torch, synthgen.gaussian_block(H.n, 4, 1))
+    ok = bbl.block_lanczos(Hd, P, 4, 1e-9, m_max=300, check_every=50)
+    assert ok.converged and ok.stats["iters"] > 52
+    with pytest.raises(bbl.BblError) as e:
+        bbl.block_lanczos(Hd, P, 4, 1e-9, m_max=300, check_every=50, fault_block=6)
+    assert e.value.code == bbl.BBL_E_BREAKDOWN
+    # the default check schedule reports it as well
+    with pytest.raises(bbl.BblError) as e:
+        bbl.block_lanczos(Hd, P, 4, 1e-9, m_max=300, fault_block=6)
+    assert e.value.code == bbl.BBL_E_BREAKDOWN
+    # the pooled check stream is healthy after the failures
+    again = bbl.block_lanczos(Hd, P, 4, 1e-9, m_max=300, check_every=50)
+    assert np.array_equal(again.eigvals, ok.eigvals)
+
+
+def test_phase_timing_fills_the_stats_and_changes_nothing(torch, bbl):
+    note("BBL_FLAG_TIME_PHASES")
+    w = synthgen.WORKLOADS["small_fp64_n2e4"]
+    H = w.generate()
+    Hd = bbl.DeviceCSR.from_host(H, "float64")
+    P = bbl.random_pivot(H.n, 4, synthgen.pivot_key(3))
+    a = bbl.block_lanczos(Hd, P, 4, 1e-8, m_max=300)
+    t = bbl.block_lanczos(Hd, P, 4, 1e-8, m_max=300, time_phases=True)
+    assert np.array_equal(a.eigvals, t.eigvals) and a.stats["iters"] == t.stats["iters"]
+    for f in ("t_threeterm_ms", "t_reorth_ms", "t_qr_ms", "t_restart_ms", "t_eig_ms"):
+        assert a.stats[f] == 0.0
+    s = t.stats
+    assert s["iters"] <= s["spmm_timed"] <= s["iters"] + 2
+    for f in ("spmm_ms", "t_threeterm_ms", "t_reorth_ms", "t_qr_ms", "t_eig_ms"):
+        assert s[f] > 0.0, f
+    assert s["spmm_ms"] + s["t_threeterm_ms"] + s["t_reorth_ms"] + s["t_qr_ms"] < s["t_total_ms"]
+    assert s["t_pivot_ms"] == 0.0 and s["pivot_spmm_calls"] == 0 and s["restarts"] == 0
+    # pivot calls report their own time and products
+    _, ps = bbl.bootstrap_pivot(Hd, w.n_trunc, 4, 1e-8, m_max=300)
+    assert ps["t_pivot_ms"] > 0 and ps["pivot_spmm_calls"] == ps["spmm_calls"] > 0
+
+
+def test_pivot_overlap_matches_host_svd(torch, bbl):
+    """Principal-angle cosines and captured weights against numpy's SVD of
+    X^T Q, Q an orthonormal basis of span(P); also for a rank-deficient P
+    (a duplicated column) and for X inside span(P) (all cosines 1)."""
+    note("pivot overlap diagnostic")
+    rng = np.random.default_rng(5)
+    n = 30011
+    X, _ = np.linalg.qr(rng.standard_normal((n, 10)))
+    for case in ("random", "dup", "inside"):
+        if case == "inside":
+            P = X[:, :8] @ rng.standard_normal((8, 8))
+            Xc = X[:, :6].copy()
+        else:
+            P = rng.standard_normal((n, 8)) + 3.0 * X[:, :8]
+            if case == "dup":
+                P[:, 7] = P[:, 2]
+            Xc = X
+        cos, cap = bbl.pivot_overlap(dev(torch, Xc), dev(torch, P))
+        U, sv, _ = np.linalg.svd(P, full_matrices=False)
+        Q = U[:, sv > 1e-10 * sv[0]]
+        ref = np.linalg.svd(Xc.T @ Q, compute_uv=False)
+        ref = np.concatenate([ref, np.zeros(Xc.shape[1] - len(ref))])
+        # squared cosines are the eigenvalues the kernel computes (a zero one
+        # comes out as rounding noise whose square root is ~1e-8)
+        np.testing.assert_allclose(cos ** 2, ref ** 2, rtol=0, atol=1e-11)
+        assert np.all(np.diff(cos) <= 0)
+        np.testing.assert_allclose(cap, np.sum((Xc.T @ Q) ** 2, axis=1), rtol=0, atol=1e-11)
+        if case == "inside":
+            np.testing.assert_allclose(cos, 1.0, atol=1e-9)

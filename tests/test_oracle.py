@@ -47,6 +47,28 @@ def test_spmm_float32_values_are_promoted_exactly():
     assert np.max(np.abs(W - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("b", [1, 8])
+def test_spmm_abs_is_the_product_of_absolute_values(b):
+    """|H| |V|, the scale of every SpMM parity bound, against the dense
+    product of elementwise absolute values: the matrix and the block both
+    carry negative entries, so a missing absolute value on either side (or
+    a signed sum) fails; also with float32 values and a hand case."""
+    H = synthgen.generate(1500, 300, 12, 0.7, 11)
+    assert (H.val < 0).any()
+    V = np.random.default_rng(b).standard_normal((H.n, b))
+    A = oracle.spmm_abs(H, V)
+    ref = np.abs(H.to_dense()) @ np.abs(V)
+    assert np.max(np.abs(A - ref)) <= 1e-12 * np.max(ref)
+    assert np.all(A >= np.abs(oracle.spmm(H, V)) - 1e-12 * np.max(ref))
+    H32 = synthgen.CSR(H.n, H.row_ptr, H.col, H.val.astype(np.float32))
+    A32 = oracle.spmm_abs(H32, V)
+    ref32 = np.abs(H.as_float32_values().to_dense()) @ np.abs(V)
+    assert np.max(np.abs(A32 - ref32)) <= 1e-12 * np.max(ref32)
+    D = np.array([[-1.0, 2.0], [2.0, -3.0]])
+    np.testing.assert_array_equal(oracle.spmm_abs(csr_from_dense(D), np.array([[1.0], [-1.0]])),
+                                  [[3.0], [5.0]])
+
+
 def test_spmm_empty_rows_and_laplacian_eigenvectors():
     # rows 1 and 3 empty
     D = np.zeros((5, 5))
