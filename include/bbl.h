@@ -345,6 +345,22 @@ int bbl_band_eig(const double *band, int32_t N, int32_t kd, int32_t k, void *ws,
                  double *theta, double *S, double *top, void *stream);
 
 /*
+ * bbl_band_eig without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments and results as bbl_band_eig; the
+ * scratch is a 24 MiB array the library holds in device memory on every GPU
+ * it runs on until the process ends, so the call allocates nothing (its
+ * device address is looked up on the first call on each device).  Sizes
+ * whose bbl_band_eig_workspace_size exceeds 24 MiB are rejected with
+ * BBL_E_INVALID (N <= 8192 with kd, k <= 16 always fit).  All calls on one
+ * GPU share that scratch: calls that overlap in time on one GPU (different
+ * streams or threads) race and must be serialised by the caller; nothing
+ * needs clearing between calls.
+ */
+int bbl_band_eig_noalloc(const double *band, int32_t N, int32_t kd, int32_t k, double *theta,
+                         double *S, double *top, void *stream);
+
+/*
  * Tall-skinny products of the block recurrence on FP64 matrix cores
  * (diagnostic entry points for the kernels bbl_block_lanczos uses for
  * A_n = V_n^T W_n, the reorthogonalisation coefficients and the overlap

@@ -96,7 +96,7 @@ EXPORTS = ("bbl_last_error", "bbl_version", "bbl_spmm", "bbl_lanczos_workspace_s
            "bbl_mlp_train_workspace_size", "bbl_mlp_train_step",
            "bbl_learned_pivot_workspace_size", "bbl_learned_pivot", "bbl_spmm_plan_size",
            "bbl_spmm_plan_build", "bbl_spmm_planned", "bbl_lanczos_workspace_views",
-           "bbl_pivot_overlap_workspace_size", "bbl_pivot_overlap")
+           "bbl_pivot_overlap_workspace_size", "bbl_pivot_overlap", "bbl_band_eig_noalloc")
 
 MLP_IN, MLP_OUT, MLP_PARAMS = 28, 10, 38026
 
@@ -127,6 +127,7 @@ def load_library(path: str = LIB_PATH):
         "bbl_pivot_overlap": (ctypes.c_int, [I64, P, I32, P, I32, P, SZ, P, P, P]),
         "bbl_band_eig_workspace_size": (SZ, [I32, I32, I32]),
         "bbl_band_eig": (ctypes.c_int, [P, I32, I32, I32, P, SZ, P, P, P, P]),
+        "bbl_band_eig_noalloc": (ctypes.c_int, [P, I32, I32, I32, P, P, P, P]),
         "bbl_gram_workspace_size": (SZ, [I64, I32, I32, I32]),
         "bbl_gram": (ctypes.c_int, [I64, P, I32, I32, I32, P, I32, I32, P, P, SZ, P]),
         "bbl_block_update": (ctypes.c_int, [I64, P, I32, I32, I32, P, I32, D, P, I32, D, P, I32,
@@ -412,6 +413,21 @@ def band_eig(band, N: int, kd: int, k: int):
     _check(lib.bbl_band_eig(_ptr(band), N, kd, k, _ptr(ws), ws.numel(),
                             theta.ctypes.data_as(ctypes.c_void_p), _ptr(S), ctypes.byref(top),
                             _stream()))
+    return theta, S, top.value
+
+
+def band_eig_noalloc(band, N: int, kd: int, k: int, S=None):
+    """band_eig through the entry point that allocates nothing (library-held
+    scratch); S (N x k float64) may be passed in so the call allocates no
+    output either."""
+    torch = _torch()
+    lib = load_library()
+    theta = np.zeros(k)
+    top = ctypes.c_double(0.0)
+    if S is None:
+        S = torch.empty((N, k), dtype=torch.float64, device=band.device)
+    _check(lib.bbl_band_eig_noalloc(_ptr(band), N, kd, k, theta.ctypes.data_as(ctypes.c_void_p),
+                                    _ptr(S), ctypes.byref(top), _stream()))
     return theta, S, top.value
 
 

@@ -30,6 +30,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "bandeig.h"
@@ -856,6 +857,55 @@ int truncated_solve(const bbl_csr &H, int64_t n_t, int b, int k, double tol, con
                     eigvecs_t, nullptr, stats, s);
 }
 
+namespace {
+
+void check_band_eig_args(int N, int kd, int k) {
+  BBL_REQUIRE(N >= 1 && N <= 8192 && kd >= 1 && kd <= kMaxBlock && k >= 1 &&
+                  k <= std::min(N, kMaxBlock),
+              "bad N/kd/k");
+}
+
+// The band eigensolve on a 256-byte aligned scratch region `base` of at least
+// bbl_band_eig_workspace_size(N, kd, k) bytes: results at its start, the
+// solver's workspace after them.
+void band_eig_on(const double *band, int N, int kd, int k, char *base, double *theta, double *S,
+                 double *top, hipStream_t s) {
+  double *res = reinterpret_cast<double *>(base);
+  const BandEigLayout L = band_eig_layout(N, kd, k);
+  band_eigensolve(band, N, kd, k, base + 2 * 256 * 8, L, nullptr, kd, S, res, s);
+  double h[2 * kMaxBlock + 2];
+  BBL_HIP(hipMemcpyAsync(h, res, (2 * k + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+  BBL_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < k; ++i) theta[i] = h[i];
+  if (top) *top = h[2 * k + 1];
+}
+
+// Scratch of bbl_band_eig_noalloc: a file-scope device array, so the call
+// needs no allocation.  Every GPU the library runs on holds its own copy
+// until the process ends; its device address is looked up once per device.
+constexpr size_t kBandScratchBytes = (size_t)24 << 20;
+__device__ __align__(256) unsigned char g_band_scratch[kBandScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+char *band_scratch_ptr() {
+  int dev = 0;
+  BBL_HIP(hipGetDevice(&dev));
+  BBL_REQUIRE(dev >= 0 && dev < kMaxDevices, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    BBL_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(g_band_scratch)));
+    BBL_REQUIRE(p != nullptr, "no device address for the band-eigensolve scratch");
+    g_scratch_ptr[dev] = static_cast<char *>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
 }  // namespace bbl
 
 using namespace bbl;
@@ -1051,21 +1101,27 @@ int bbl_band_eig(const double *band, int32_t N, int32_t kd, int32_t k, void *ws,
                  double *theta, double *S, double *top, void *stream) {
   return guarded([&] {
     BBL_REQUIRE(band && ws && theta && S, "NULL argument");
-    BBL_REQUIRE(N >= 1 && N <= 8192 && kd >= 1 && kd <= kMaxBlock && k >= 1 &&
-                    k <= std::min(N, kMaxBlock),
-                "bad N/kd/k");
+    check_band_eig_args(N, kd, k);
     const size_t need = bbl_band_eig_workspace_size(N, kd, k);
     if (ws_bytes < need) throw Error{BBL_E_NOMEM, "band eig workspace too small"};
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    char *base = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
-    double *res = reinterpret_cast<double *>(base);
-    const BandEigLayout L = band_eig_layout(N, kd, k);
-    band_eigensolve(band, N, kd, k, base + 2 * 256 * 8, L, nullptr, kd, S, res, s);
-    std::vector<double> h(2 * k + 2);
-    BBL_HIP(hipMemcpyAsync(h.data(), res, h.size() * 8, hipMemcpyDeviceToHost, s));
-    BBL_HIP(hipStreamSynchronize(s));
-    for (int i = 0; i < k; ++i) theta[i] = h[i];
-    if (top) *top = h[2 * k + 1];
+    band_eig_on(band, N, kd, k, reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(ws), 256)),
+                theta, S, top, static_cast<hipStream_t>(stream));
+    return (int)BBL_OK;
+  });
+}
+
+int bbl_band_eig_noalloc(const double *band, int32_t N, int32_t kd, int32_t k, double *theta,
+                         double *S, double *top, void *stream) {
+  return guarded([&] {
+    BBL_REQUIRE(band && theta && S, "NULL argument");
+    check_band_eig_args(N, kd, k);
+    const size_t need = bbl_band_eig_workspace_size(N, kd, k);
+    if (need > kBandScratchBytes)
+      throw Error{BBL_E_INVALID, "band eig without allocation: N, kd, k need " +
+                                     std::to_string(need) + " bytes of scratch, more than the " +
+                                     std::to_string(kBandScratchBytes) + " the library holds"};
+    band_eig_on(band, N, kd, k, band_scratch_ptr(), theta, S, top,
+                static_cast<hipStream_t>(stream));
     return (int)BBL_OK;
   });
 }

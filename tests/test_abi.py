@@ -159,3 +159,13 @@ def test_workspace_views_are_pointer_arithmetic():
     assert band.value < base + lib.bbl_lanczos_workspace_size(n, b, k, m, bbl.BBL_F64)
     assert lib.bbl_lanczos_workspace_views(base, 0, b, k, m, bbl.BBL_F64, ctypes.byref(basis),
                                            ctypes.byref(band)) == bbl.BBL_E_INVALID
+
+
+def test_no_alloc_band_eig_rejects_sizes_beyond_its_scratch_without_a_device():
+    lib = bbl.load_library()
+    theta = np.zeros(32)
+    st = lib.bbl_band_eig_noalloc(1, 8192, 32, 32, theta.ctypes.data_as(ctypes.c_void_p), 2,
+                                  None, None)
+    assert st == bbl.BBL_E_INVALID and b"scratch" in lib.bbl_last_error()
+    assert lib.bbl_band_eig_noalloc(None, 100, 4, 4, theta.ctypes.data_as(ctypes.c_void_p), 2,
+                                    None, None) == bbl.BBL_E_INVALID
