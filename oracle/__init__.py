@@ -11,6 +11,11 @@ large-dimension eigenvalue problems" (arXiv 2210.15763):
                          its spectral factorisation B_n, V_{n+1}, full
                          reorthogonalisation, and the band matrix solved by a
                          dense symmetric eigensolver (Methods).
+* ``block_lanczos_restarted`` -- the same recurrence with thick restart: at
+                         the block cap the lowest Ritz vectors and the
+                         residual block are kept and the recurrence
+                         continues on the arrowhead-bordered band matrix
+                         (the restarted method the paper cites, Wu & Simon).
 * ``scalar_lanczos``  -- the single-vector method (Algorithm "Lanczos method").
 * ``bootstrap_pivot`` -- the pivot block built from eigenvectors of a
                          truncated leading block (Methods, last paragraphs).
@@ -26,4 +31,4 @@ common dependency is the seeded input generator ``synthgen``.
 """
 from .spmm import spmm, spmm_abs, build_native  # noqa: F401
 from .lanczos import (block_lanczos, scalar_lanczos, bootstrap_pivot, svqb,  # noqa: F401
-                      ritz_residuals, LanczosResult)
+                      ritz_residuals, LanczosResult, block_lanczos_restarted)

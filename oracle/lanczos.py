@@ -51,6 +51,9 @@ class LanczosResult:
     B: list = field(default_factory=list, repr=False)
     V: list = field(default_factory=list, repr=False)
     W_prime: list = field(default_factory=list, repr=False)
+    restarts: int = 0
+    T: np.ndarray = field(default=None, repr=False)       # final projected matrix
+    basis: list = field(default_factory=list, repr=False)  # its basis: [Y,] V blocks
 
 
 def deflation_key(seed: int, j: int) -> int:
@@ -239,3 +242,133 @@ def bootstrap_pivot(H, n_t: int, b: int, *, tol: float = 1e-8, m_max: int = 400,
     P = np.zeros((H.n, b))
     P[:n_t] = Xt
     return P
+
+
+def block_lanczos_restarted(H, P: np.ndarray, k: int, tol: float, m_max: int, keep: int, *,
+                            max_restarts: int = 1000, defl_tau: float = 1e-12, seed: int = 0,
+                            spmm=_spmm, history: list = None) -> LanczosResult:
+    """Thick-restart block Lanczos (the restarted method the paper's
+    introduction and base-Lanczos subsection refer to: Wu & Simon's thick
+    restart, which keeps a reduced set of Ritz vectors), in block form.
+
+    The stored basis holds at most m_max blocks of b vectors.  A cycle runs
+    the block recurrence until it has m_max blocks; if the lowest k pairs have
+    not converged, the `keep` lowest Ritz vectors Y = V S[:, :keep] are kept
+    together with the residual block V_next (the next Lanczos block), which is
+    orthogonal to them.  On span{Y, V_next} H acts as the arrowhead matrix
+
+        [ Theta        Sigma^T ]      Theta = diag(lowest keep Ritz values),
+        [ Sigma        A       ]      Sigma = V_next^T H Y = B_last S[last block rows, :keep],
+
+    and the recurrence continues from V_next: its first residual block is
+    W' = H V_next - V_next A - Y Sigma^T, later ones the usual three-term
+    form, always fully reorthogonalised (twice) against Y and every stored
+    block.  Y counts as keep / b stored blocks.  The projected matrix of a
+    cycle is the arrowhead bordered block-tridiagonal matrix above, solved by
+    a dense symmetric eigensolver.  `history`, if given, receives the lowest
+    Ritz value after every block.
+
+    Returns the Ritz pairs of the final cycle; `iters` counts the block
+    iterations of all cycles, `restarts` the restarts, and `T`, `basis` hold
+    the final cycle's projected matrix and its basis ([Y] + Lanczos blocks).
+    """
+    n, b = P.shape
+    if keep % b or keep < max(k, b) or keep // b + 1 >= m_max:
+        raise ValueError("keep must be a multiple of b in [max(k, b), b (m_max - 2)]")
+    q = keep // b
+    V1, _, nd0 = svqb(np.array(P, dtype=np.float64), defl_tau, 0.0, [], deflation_key(seed, 0))
+    Y = None            # kept Ritz vectors of this cycle (n x keep), or None
+    theta_keep = None   # their Ritz values
+    Sigma = None        # V_next^T H Y (b x keep)
+    blocks = [V1]       # Lanczos blocks of this cycle
+    A, B = [], []
+    deflations = nd0
+    nspmm = 0
+    restarts = 0
+    it = 0
+    hnorm = 0.0
+
+    def projected():
+        Tb = band_matrix(A, B)
+        if Y is None:
+            return Tb
+        m = Tb.shape[0]
+        T = np.zeros((keep + m, keep + m))
+        T[:keep, :keep] = np.diag(theta_keep)
+        T[keep:keep + b, :keep] = Sigma
+        T[:keep, keep:keep + b] = Sigma.T
+        T[keep:, keep:] = Tb
+        return T
+
+    def ritz_vectors(S, kk):
+        X = np.zeros((n, kk))
+        off = 0
+        if Y is not None:
+            X += Y @ S[:keep, :kk]
+            off = keep
+        for i, Vi in enumerate(blocks[:len(A)]):
+            X += Vi @ S[off + i * b:off + (i + 1) * b, :kk]
+        return _normalise_signs(X)
+
+    while True:
+        it += 1
+        Vj = blocks[-1]
+        stored = ([Y] if Y is not None else []) + blocks
+        W = spmm(H, Vj)
+        nspmm += 1
+        Aj = Vj.T @ W
+        Aj = 0.5 * (Aj + Aj.T)
+        Wp = W - Vj @ Aj
+        if len(A) > 0:
+            Wp = Wp - blocks[-2] @ B[-1].T
+        elif Y is not None:
+            Wp = Wp - Y @ Sigma.T
+        Wp = _orthogonalise_against(Wp, stored)
+        A.append(Aj)
+        T = projected()
+        theta, S = np.linalg.eigh(T)
+        if history is not None:
+            history.append(theta[0])
+        hnorm = max(abs(theta[0]), abs(theta[-1]))
+        Vn, Bj, nd = svqb(Wp, defl_tau, hnorm, stored, deflation_key(seed, it))
+        deflations += nd
+        N = T.shape[0]
+        exhausted = N >= n
+        kk = min(k, N)
+        if N >= k or exhausted:
+            last = slice(N - b, N)
+            rho = np.linalg.norm(Bj @ S[last, :kk], axis=0)
+            if exhausted or np.all(rho <= tol * hnorm):
+                X = ritz_vectors(S, kk)
+                r = ritz_residuals(H, X, theta[:kk], spmm)
+                nspmm += 1
+                if exhausted or np.all(r <= tol * hnorm):
+                    return LanczosResult(theta[:kk], X, r, True, it, nspmm, hnorm, deflations,
+                                         theta, restarts=restarts, T=T,
+                                         basis=([Y] if Y is not None else []) + blocks[:len(A)])
+        cycle_blocks = (q if Y is not None else 0) + len(A)
+        if cycle_blocks < m_max:
+            B.append(Bj)
+            blocks.append(Vn)
+            continue
+        if restarts >= max_restarts:
+            X = ritz_vectors(S, kk)
+            r = ritz_residuals(H, X, theta[:kk], spmm)
+            return LanczosResult(theta[:kk], X, r, False, it, nspmm + 1, hnorm, deflations, theta,
+                                 restarts=restarts, T=T,
+                                 basis=([Y] if Y is not None else []) + blocks[:len(A)])
+        # thick restart: the keep lowest Ritz vectors and the residual block
+        Snew = S[:, :keep]
+        Ynew = np.zeros((n, keep))
+        off = 0
+        if Y is not None:
+            Ynew += Y @ Snew[:keep]
+            off = keep
+        for i, Vi in enumerate(blocks[:len(A)]):
+            Ynew += Vi @ Snew[off + i * b:off + (i + 1) * b]
+        Sigma = Bj @ Snew[N - b:N]
+        Y = Ynew
+        theta_keep = theta[:keep].copy()
+        blocks = [Vn]
+        A, B = [], []
+        restarts += 1

@@ -292,3 +292,95 @@ def test_full_truncation_pivot_converges_immediately():
     P = oracle.bootstrap_pivot(H, H.n, 4)
     res = oracle.block_lanczos(H, P, 4, 1e-10, 5)
     assert res.iters == 1 and res.converged
+
+
+# ------------------------------------------------------ thick restart pins
+from oracle.lanczos import block_lanczos_restarted  # noqa: E402
+
+
+@pytest.mark.parametrize("seed,b,keep,m_max", [(6, 4, 8, 8), (7, 4, 12, 10), (8, 2, 6, 12)])
+def test_thick_restart_matches_dense_eigh(seed, b, keep, m_max):
+    """A basis of at most m_max blocks forces many restarts; the converged
+    pairs are still the lowest eigenpairs of the dense matrix."""
+    H = synthgen.generate(1600, 400, 20, 0.7, seed)
+    lam, Xd = np.linalg.eigh(H.to_dense())
+    k = 4
+    res = block_lanczos_restarted(H, synthgen.gaussian_block(H.n, b, seed), k, 1e-10, m_max, keep)
+    assert res.converged and res.restarts >= 5
+    np.testing.assert_allclose(res.eigvals, lam[:k], rtol=1e-10)
+    assert np.all(res.residuals <= 1e-10 * res.hnorm)
+    sv = np.linalg.svd(Xd[:, :k].T @ res.eigvecs, compute_uv=False)
+    assert sv.min() > 1 - 1e-8
+
+
+def test_thick_restart_cycle_invariants():
+    """After restarts the cycle's basis [Y, V_1, ...] is orthonormal and H
+    acts on it as the arrowhead-bordered band matrix: Q^T Q = I and
+    Q^T H Q = T, with the kept Ritz values on T's leading diagonal, T's
+    leading keep x keep block diagonal and the Y-coupling only in the first
+    Lanczos block's rows (checked on a cycle that ran to the block cap)."""
+    H = synthgen.generate(2000, 400, 20, 0.7, 3)
+    b, keep, m_max = 4, 8, 9
+    res = block_lanczos_restarted(H, synthgen.gaussian_block(H.n, b, 1), 4, 1e-300, m_max, keep,
+                                  max_restarts=3)
+    assert not res.converged and res.restarts == 3
+    Q = np.hstack(res.basis)
+    T = res.T
+    assert Q.shape[1] == T.shape[0] == keep + (m_max - keep // b) * b
+    hn = np.max(np.abs(np.linalg.eigvalsh(T)))
+    assert np.max(np.abs(Q.T @ Q - np.eye(Q.shape[1]))) <= 1e-12
+    assert np.max(np.abs(Q.T @ oracle.spmm(H, Q) - T)) <= 1e-10 * hn
+    assert np.count_nonzero(T[:keep, :keep] - np.diag(np.diag(T[:keep, :keep]))) == 0
+    assert np.all(np.diff(np.diag(T)[:keep]) >= 0)
+    assert np.count_nonzero(T[keep + b:, :keep]) == 0
+    # the Y block holds Ritz vectors: each is an eigenvector of the previous
+    # cycle's projection, so ||H y - theta y|| equals its coupling column norm
+    Y = res.basis[0]
+    th = np.diag(T)[:keep]
+    r = np.linalg.norm(oracle.spmm(H, Y) - Y * th, axis=0)
+    np.testing.assert_allclose(r, np.linalg.norm(T[keep:keep + b, :keep], axis=0), rtol=1e-6,
+                               atol=1e-10 * hn)
+
+
+def test_thick_restart_ritz_values_never_increase():
+    """The kept Ritz vectors lie in every later search space, so the lowest
+    Ritz value is non-increasing across blocks and across restarts (Cauchy
+    interlacing), and it stays above the true lowest eigenvalue."""
+    H = synthgen.generate(1600, 400, 20, 0.7, 9)
+    lam0 = np.linalg.eigvalsh(H.to_dense())[0]
+    hist = []
+    res = block_lanczos_restarted(H, synthgen.gaussian_block(H.n, 4, 2), 4, 1e-10, 8, 8,
+                                  history=hist)
+    assert res.converged and res.restarts >= 3
+    h = np.array(hist)
+    assert np.all(np.diff(h) <= 1e-12 * abs(lam0))
+    assert np.all(h >= lam0 - 1e-10 * abs(lam0))
+
+
+def test_thick_restart_is_the_plain_method_when_no_restart_is_needed():
+    H = synthgen.generate(1600, 400, 20, 0.7, 6)
+    P = synthgen.gaussian_block(H.n, 4, 3)
+    a = oracle.block_lanczos(H, P, 4, 1e-10, 400)
+    r = block_lanczos_restarted(H, P, 4, 1e-10, 400, 8)
+    assert r.restarts == 0 and r.iters == a.iters
+    assert np.array_equal(r.eigvals, a.eigvals)
+
+
+def test_thick_restart_qdqt_known_spectrum():
+    n = 240
+    rng = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    d = np.concatenate([[-5.0, -4.0, -3.5, -3.0, -2.0, -1.0], np.linspace(0, 10, n - 6)])
+    D = 0.5 * ((Q * d) @ Q.T + ((Q * d) @ Q.T).T)
+    H = csr_from_dense(D)
+    res = block_lanczos_restarted(H, synthgen.gaussian_block(n, 4, 9), 6, 1e-11, 5, 8)
+    assert res.converged and res.restarts >= 1
+    np.testing.assert_allclose(res.eigvals, d[:6], rtol=0, atol=1e-11)
+
+
+def test_thick_restart_rejects_bad_keep():
+    H = synthgen.generate(400, 100, 10, 0.7, 1)
+    P = synthgen.gaussian_block(H.n, 4, 1)
+    for keep in (6, 2, 40):
+        with pytest.raises(ValueError):
+            block_lanczos_restarted(H, P, 4, 1e-8, 10, keep)
