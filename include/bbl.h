@@ -142,7 +142,9 @@ typedef struct {
   int32_t restart_keep; /* thick restart (see bbl_block_lanczos): Ritz vectors
                            kept when the basis reaches m_max blocks, a multiple
                            of nvec in [max(k_eig, nvec), min(32, nvec*(m_max-2))];
-                           0 (default) = no restart, stop at m_max */
+                           0 (default) = no restart, stop at m_max.  The pivot
+                           calls raise it to cover their own pair count. */
+  int32_t max_restarts; /* restarts before giving up (0 = default 100) */
   int32_t fault_block;  /* testing only, 0 (default) = off.  f > 0 forces the
                            failure-handling path from the host: block f-1 is
                            marked as having lost rank beyond repair, and block
@@ -162,9 +164,11 @@ typedef struct {
 
 /* Counters of one solve and its wall time (host clock around the call). */
 typedef struct {
-  int32_t iters;        /* blocks of the Krylov space the returned pairs come
-                           from (the recurrence may have built up to two more
-                           while the last check ran beside it) */
+  int32_t iters;        /* block iterations (products H V_j of the recurrence)
+                           that built the space the returned pairs come from,
+                           over all thick-restart cycles (the recurrence may
+                           have built up to two more while the last check ran
+                           beside it) */
   int32_t spmm_calls;   /* all products with H, explicit residual checks and
                            the blocks built beside the last check included */
   int32_t deflations;   /* columns replaced because of (near) rank loss */
@@ -190,6 +194,9 @@ typedef struct {
   int32_t pivot_spmm_calls; /* products with H or its leading block the pivot
                            needed, in units of one nvec-wide product */
   int32_t used_fallback; /* learned pivot: 1 if the bootstrap block was returned */
+  int32_t basis_blocks;  /* blocks of the basis the returned pairs come from
+                            (= iters without restart; see the workspace views) */
+  int32_t reserved;
 } bbl_stats;
 
 /* Message describing the last non-OK status on the calling thread. */
@@ -234,19 +241,30 @@ int bbl_spmm_planned(const bbl_spmm_plan *plan, const void *V, void *W, void *st
 
 /*
  * Workspace bytes needed by bbl_block_lanczos for dimension n, block size
- * nvec, k_eig wanted pairs, block cap m_max and basis precision basis_dtype.
- * Returns 0 for invalid arguments.
+ * nvec, k_eig wanted pairs, block cap m_max and basis precision basis_dtype,
+ * without restart; the _restart form for opts->restart_keep kept Ritz vectors
+ * (restart_keep / nvec more basis blocks).  Returns 0 for invalid arguments.
  */
 size_t bbl_lanczos_workspace_size(int64_t n, int32_t nvec, int32_t k_eig, int32_t m_max,
                                   int32_t basis_dtype);
+size_t bbl_lanczos_workspace_size_restart(int64_t n, int32_t nvec, int32_t k_eig, int32_t m_max,
+                                          int32_t basis_dtype, int32_t restart_keep);
 
 /*
- * Lowest k_eig eigenpairs of H by non-restarted block Lanczos (Methods): the
- * block recurrence H V_j = V_{j-1} B_{j-1}^T + V_j A_j + V_{j+1} B_j with
+ * Lowest k_eig eigenpairs of H by block Lanczos (Methods): the block
+ * recurrence H V_j = V_{j-1} B_{j-1}^T + V_j A_j + V_{j+1} B_j with
  * A_j = V_j^T H V_j, full reorthogonalisation of every new block against all
  * stored blocks, a block QR of the residual block giving B_j and V_{j+1}, and
  * the block-tridiagonal band matrix of the A's and B's solved for its lowest
- * Ritz pairs.
+ * Ritz pairs.  Non-restarted by default (the paper's runs); with
+ * opts->restart_keep = p > 0, thick restart (the restarted method the paper's
+ * introduction and base-Lanczos subsection cite, Wu & Simon): when the basis
+ * holds m_max blocks and the pairs have not converged, the p lowest Ritz
+ * vectors and the next Lanczos block are kept and the recurrence continues
+ * from that block; the projected matrix on the kept vectors is brought back
+ * to band form by rotating them (Householder reflectors on the small
+ * matrix), so every cycle runs the same kernels as a non-restarted solve.
+ * The workspace then comes from bbl_lanczos_workspace_size_restart.
  *   pivot    device n x nvec float64 starting block (any full-rank block;
  *            rank loss is repaired by deflation)
  *   nvec     block size, 1..32;  k_eig 1..min(n, 32, nvec * m_max)
@@ -258,8 +276,9 @@ size_t bbl_lanczos_workspace_size(int64_t n, int32_t nvec, int32_t k_eig, int32_
  *            largest-magnitude entry is positive (may be NULL)
  *   residuals host, k_eig explicit residual norms in float64 (may be NULL)
  *   stats    host (may be NULL)
- * Returns BBL_OK on convergence, BBL_E_NOT_CONVERGED at the cap (outputs hold
- * the current Ritz pairs and their true residuals), or an error.
+ * Returns BBL_OK on convergence, BBL_E_NOT_CONVERGED at the cap (after
+ * max_restarts restarts with restart; outputs hold the current Ritz pairs
+ * and their true residuals), or an error.
  */
 int bbl_block_lanczos(const bbl_csr *H, const double *pivot, int32_t nvec, int32_t k_eig,
                       double tol, void *ws, size_t ws_bytes, const bbl_opts *opts,
@@ -269,7 +288,7 @@ int bbl_block_lanczos(const bbl_csr *H, const double *pivot, int32_t nvec, int32
 /*
  * Diagnostic view of the state a bbl_block_lanczos call left in its workspace
  * (pure pointer arithmetic on ws; nothing is read or launched).  With the same
- * (n, nvec, k_eig, m_max, basis_dtype) as the solve:
+ * (n, nvec, k_eig, m_max, basis_dtype, restart_keep) as the solve:
  *   basis  receives the device address of the stored Krylov basis: block j
  *          (the paper's V_{j+1}) is a row-major n x nvec array of basis_dtype
  *          at basis + j*n*nvec elements, j = 0..m_max
@@ -277,13 +296,15 @@ int bbl_block_lanczos(const bbl_csr *H, const double *pivot, int32_t nvec, int32
  *          recurrence, (m_max + 1)*nvec rows of nvec + 1 float64:
  *          band[i*(nvec+1) + d] = T[i][i-d] (A blocks on the diagonal, B
  *          blocks below it; the matrix is symmetric)
- * After a solve that reported stats.iters = m, blocks 0..m-1 and the leading
- * m*nvec rows of the band are V_{1:m} and T_m of the Methods section (after a
- * thick restart: of the current cycle, whose leading blocks hold the kept
- * Ritz vectors in a rotated basis).  Valid until ws is reused.
+ * After a solve that reported stats.basis_blocks = m, blocks 0..m-1 and the
+ * leading m*nvec rows of the band are V_{1:m} and T_m of the Methods section
+ * (after a thick restart: of the final cycle, whose leading restart_keep/nvec
+ * blocks hold the kept Ritz vectors in a rotated basis that makes the
+ * projected matrix a band matrix again).  Valid until ws is reused.
  */
 int bbl_lanczos_workspace_views(const void *ws, int64_t n, int32_t nvec, int32_t k_eig,
-                                int32_t m_max, int32_t basis_dtype, void **basis, double **band);
+                                int32_t m_max, int32_t basis_dtype, int32_t restart_keep,
+                                void **basis, double **band);
 
 /*
  * Workspace bytes for bbl_bootstrap_pivot (reads row_ptr[n_trunc] from the

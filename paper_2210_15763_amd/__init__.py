@@ -50,7 +50,7 @@ class _Opts(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("defl_tau", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("spmm_plan", ctypes.c_void_p), ("restart_keep", ctypes.c_int32),
-                ("fault_block", ctypes.c_int32)]
+                ("max_restarts", ctypes.c_int32), ("fault_block", ctypes.c_int32)]
 
 
 class _Plan(ctypes.Structure):
@@ -77,7 +77,8 @@ class _Stats(ctypes.Structure):
                 ("t_reorth_ms", ctypes.c_double), ("t_qr_ms", ctypes.c_double),
                 ("t_eig_ms", ctypes.c_double), ("t_restart_ms", ctypes.c_double),
                 ("t_pivot_ms", ctypes.c_double), ("pivot_spmm_calls", ctypes.c_int32),
-                ("used_fallback", ctypes.c_int32)]
+                ("used_fallback", ctypes.c_int32), ("basis_blocks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -96,7 +97,8 @@ EXPORTS = ("bbl_last_error", "bbl_version", "bbl_spmm", "bbl_lanczos_workspace_s
            "bbl_mlp_train_workspace_size", "bbl_mlp_train_step",
            "bbl_learned_pivot_workspace_size", "bbl_learned_pivot", "bbl_spmm_plan_size",
            "bbl_spmm_plan_build", "bbl_spmm_planned", "bbl_lanczos_workspace_views",
-           "bbl_pivot_overlap_workspace_size", "bbl_pivot_overlap", "bbl_band_eig_noalloc")
+           "bbl_pivot_overlap_workspace_size", "bbl_pivot_overlap", "bbl_band_eig_noalloc",
+           "bbl_lanczos_workspace_size_restart")
 
 MLP_IN, MLP_OUT, MLP_PARAMS = 28, 10, 38026
 
@@ -118,8 +120,9 @@ def load_library(path: str = LIB_PATH):
         "bbl_spmm": (ctypes.c_int, [P, P, P, I32, I32, P]),
         "bbl_lanczos_workspace_size": (SZ, [I64, I32, I32, I32, I32]),
         "bbl_block_lanczos": (ctypes.c_int, [P, P, I32, I32, D, P, SZ, P, P, P, P, P, P]),
-        "bbl_lanczos_workspace_views": (ctypes.c_int, [P, I64, I32, I32, I32, I32,
+        "bbl_lanczos_workspace_views": (ctypes.c_int, [P, I64, I32, I32, I32, I32, I32,
                                                        ctypes.POINTER(P), ctypes.POINTER(P)]),
+        "bbl_lanczos_workspace_size_restart": (SZ, [I64, I32, I32, I32, I32, I32]),
         "bbl_bootstrap_workspace_size": (SZ, [P, I64, I32, I32, I32, P]),
         "bbl_bootstrap_pivot": (ctypes.c_int, [P, I64, I32, D, P, SZ, P, P, P, P]),
         "bbl_random_pivot": (ctypes.c_int, [I64, I32, U64, P, P]),
@@ -219,11 +222,11 @@ class DeviceCSR:
 
 
 def _opts(m_max, basis_dtype, check_every, seed, defl_tau, flags=0, plan=None, restart_keep=0,
-          fault_block=0):
+          fault_block=0, max_restarts=0):
     return _Opts(int(m_max), int(basis_dtype), int(check_every), int(flags), float(defl_tau),
                  int(seed) & (2**64 - 1),
                  ctypes.cast(ctypes.pointer(plan.c), ctypes.c_void_p) if plan is not None else None,
-                 int(restart_keep), int(fault_block))
+                 int(restart_keep), int(max_restarts), int(fault_block))
 
 
 class SpmmPlan:
@@ -275,8 +278,9 @@ def spmm(H: DeviceCSR, V, W=None):
     return W
 
 
-def lanczos_workspace_bytes(n, nvec, k, m_max, basis_dtype):
-    return int(load_library().bbl_lanczos_workspace_size(n, nvec, k, m_max, basis_dtype))
+def lanczos_workspace_bytes(n, nvec, k, m_max, basis_dtype, restart_keep=0):
+    return int(load_library().bbl_lanczos_workspace_size_restart(n, nvec, k, m_max, basis_dtype,
+                                                                 restart_keep))
 
 
 @dataclass
@@ -298,7 +302,7 @@ def block_lanczos(H: DeviceCSR, pivot, k: int, tol: float, *, m_max: int = 200,
                   workspace=None, want_vectors: bool = True,
                   time_spmm: bool = False, time_phases: bool = False,
                   spmm_plan: "SpmmPlan" = None, restart_keep: int = 0,
-                  fault_block: int = 0) -> LanczosResult:
+                  max_restarts: int = 0, fault_block: int = 0) -> LanczosResult:
     """Lowest k eigenpairs of H from the n x nvec float64 pivot block.
     time_spmm: record device time of every product H V_j (stats spmm_ms);
     time_phases: also the other phases (stats t_*_ms).  restart_keep: thick
@@ -310,7 +314,7 @@ def block_lanczos(H: DeviceCSR, pivot, k: int, tol: float, *, m_max: int = 200,
     if basis_dtype is None:
         basis_dtype = _dtype_code(H.val)
     lib = load_library()
-    need = lib.bbl_lanczos_workspace_size(H.n, nvec, k, m_max, basis_dtype)
+    need = lib.bbl_lanczos_workspace_size_restart(H.n, nvec, k, m_max, basis_dtype, restart_keep)
     if need == 0:
         raise BblError(BBL_E_INVALID, "invalid sizes for the workspace query")
     if workspace is None or workspace.numel() < need:
@@ -322,7 +326,7 @@ def block_lanczos(H: DeviceCSR, pivot, k: int, tol: float, *, m_max: int = 200,
     Hc = H._c()
     flags = (BBL_FLAG_TIME_SPMM if time_spmm else 0) | (BBL_FLAG_TIME_PHASES if time_phases else 0)
     o = _opts(m_max, basis_dtype, check_every, seed, defl_tau, flags, spmm_plan, restart_keep,
-              fault_block)
+              fault_block, max_restarts)
     code = lib.bbl_block_lanczos(ctypes.byref(Hc), _ptr(pivot), nvec, k, tol, _ptr(workspace),
                                  workspace.numel(), ctypes.byref(o),
                                  eigvals.ctypes.data_as(ctypes.c_void_p), _ptr(X),
@@ -332,19 +336,21 @@ def block_lanczos(H: DeviceCSR, pivot, k: int, tol: float, *, m_max: int = 200,
     return LanczosResult(eigvals, X, resid, code, st.as_dict(), workspace)
 
 
-def workspace_views(workspace, n: int, nvec: int, k: int, m_max: int, basis_dtype: int):
+def workspace_views(workspace, n: int, nvec: int, k: int, m_max: int, basis_dtype: int,
+                    restart_keep: int = 0):
     """Device addresses (basis, band) inside a block_lanczos workspace: the
     stored Krylov blocks and the band matrix the last solve left there."""
     basis = ctypes.c_void_p()
     band = ctypes.c_void_p()
     _check(load_library().bbl_lanczos_workspace_views(_ptr(workspace), n, nvec, k, m_max,
-                                                      basis_dtype, ctypes.byref(basis),
-                                                      ctypes.byref(band)))
+                                                      basis_dtype, restart_keep,
+                                                      ctypes.byref(basis), ctypes.byref(band)))
     return basis.value, band.value
 
 
 def bootstrap_pivot(H: DeviceCSR, n_trunc: int, nvec: int, tol: float, *, m_max: int = 200,
-                    basis_dtype=None, check_every: int = 0, seed: int = 0, workspace=None):
+                    basis_dtype=None, check_every: int = 0, seed: int = 0, workspace=None,
+                    restart_keep: int = 0):
     """Pivot block from the lowest nvec eigenvectors of H[0:n_trunc, 0:n_trunc],
     zero-padded to n rows.  Returns (pivot, stats of the truncated solve)."""
     torch = _torch()
@@ -360,7 +366,7 @@ def bootstrap_pivot(H: DeviceCSR, n_trunc: int, nvec: int, tol: float, *, m_max:
         workspace = torch.empty(need, dtype=torch.uint8, device=H.val.device)
     pivot = torch.empty((H.n, nvec), dtype=torch.float64, device=H.val.device)
     st = _Stats()
-    o = _opts(m_max, basis_dtype, check_every, seed, 1e-12)
+    o = _opts(m_max, basis_dtype, check_every, seed, 1e-12, restart_keep=restart_keep)
     code = lib.bbl_bootstrap_pivot(ctypes.byref(Hc), n_trunc, nvec, tol, _ptr(workspace),
                                    workspace.numel(), ctypes.byref(o), _ptr(pivot),
                                    ctypes.byref(st), _stream())
@@ -464,7 +470,8 @@ def _ws(nbytes, device):
 
 
 def pivot_features(H: DeviceCSR, n_trunc: int, sector_size: int, tol: float, *, m_max: int = 200,
-                   seed: int = 0, basis_dtype=None, want_f32: bool = False):
+                   seed: int = 0, basis_dtype=None, want_f32: bool = False,
+                   restart_keep: int = 0):
     """Per-row features (bf16 bit patterns as int16, n x 28), optionally their
     float32 values, P_D, the plain bootstrap block of 10 and P_D's Ritz values."""
     torch = _torch()
@@ -481,7 +488,7 @@ def pivot_features(H: DeviceCSR, n_trunc: int, sector_size: int, tol: float, *, 
     PB = torch.empty((H.n, MLP_OUT), dtype=torch.float64, device=dev)
     th = np.zeros(MLP_OUT)
     st = _Stats()
-    o = _opts(m_max, basis_dtype, 0, seed, 1e-12)
+    o = _opts(m_max, basis_dtype, 0, seed, 1e-12, restart_keep=restart_keep)
     _check(lib.bbl_pivot_features(ctypes.byref(Hc), n_trunc, sector_size, tol, _ptr(ws),
                                   ws.numel(), ctypes.byref(o), _ptr(F), _ptr(F32), _ptr(PD),
                                   _ptr(PB), th.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st),
@@ -559,7 +566,8 @@ class MlpTrainer:
 
 
 def learned_pivot(H: DeviceCSR, params, n_trunc: int, sector_size: int, nvec: int, k: int,
-                  tol: float, *, m_max: int = 200, seed: int = 0, basis_dtype=None):
+                  tol: float, *, m_max: int = 200, seed: int = 0, basis_dtype=None,
+                  restart_keep: int = 0):
     """(pivot n x nvec float64, info dict with used_fallback and rr_sums)."""
     torch = _torch()
     lib = load_library()
@@ -573,7 +581,7 @@ def learned_pivot(H: DeviceCSR, params, n_trunc: int, sector_size: int, nvec: in
     fb = ctypes.c_int32(0)
     sums = np.zeros(2)
     st = _Stats()
-    o = _opts(m_max, basis_dtype, 0, seed, 1e-12)
+    o = _opts(m_max, basis_dtype, 0, seed, 1e-12, restart_keep=restart_keep)
     _check(lib.bbl_learned_pivot(ctypes.byref(Hc), _ptr(params), n_trunc, sector_size, nvec, k,
                                  tol, _ptr(ws), ws.numel(), ctypes.byref(o), _ptr(P),
                                  ctypes.byref(fb), sums.ctypes.data_as(ctypes.c_void_p),

@@ -18,6 +18,7 @@ struct Opts {
   uint64_t seed = 0;
   const bbl_spmm_plan *plan = nullptr;
   int restart_keep = 0;  // thick restart: Ritz vectors kept (0 = off)
+  int max_restarts = 100;
   int fault_block = 0;   // testing: host-forced breakdown + redo (0 = off)
 };
 

@@ -56,12 +56,15 @@ size_t dsize(int dt) { return dt == BBL_F32 ? 4 : 8; }
 
 
 struct Layout {
-  size_t basis, W, Wp, X, partial, C, band, Bstore, mats, ints, dres, chk, S, eig, norm, total;
+  size_t basis, W, Wp, X, partial, C, band, Bstore, mats, ints, dres, chk, S, eig, norm, Sp, total;
   size_t partial_doubles;
   BandEigLayout el;
 };
 
-Layout make_layout(int64_t n, int b, int k, int m_max, int bdt) {
+// keep > 0: thick restart keeping `keep` Ritz vectors -- keep / b more basis
+// slots (the rotated Ritz vectors are formed there), eigenpairs and
+// coefficients for keep vectors.
+Layout make_layout(int64_t n, int b, int k, int m_max, int bdt, int keep = 0) {
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -72,7 +75,8 @@ Layout make_layout(int64_t n, int b, int k, int m_max, int bdt) {
   const size_t sx = dsize(bdt);
   const int64_t Mmax = (int64_t)(m_max + 1) * b;
   const int nyw = std::max(b, k);
-  L.basis = take((size_t)(m_max + 1) * n * b * sx);
+  const int kS = std::max(k, keep);  // eigenpairs of a band solve
+  L.basis = take((size_t)(m_max + 1 + keep / b) * n * b * sx);
   L.W = take((size_t)n * b * sx);
   L.Wp = take((size_t)n * b * 8);
   L.X = take((size_t)n * k * 8);
@@ -86,10 +90,11 @@ Layout make_layout(int64_t n, int b, int k, int m_max, int bdt) {
   L.ints = take(256 * sizeof(int));
   L.dres = take(256 * 8);
   L.chk = take(256 * 8);
-  L.S = take((size_t)m_max * b * k * 8);
-  L.el = band_eig_layout(m_max * b, b, k);
+  L.S = take((size_t)m_max * b * kS * 8);
+  L.el = band_eig_layout(m_max * b, b, kS);
   L.eig = take(L.el.bytes);
   L.norm = take(normalize_scratch_bytes(k, kMaxPartialRows));
+  L.Sp = take(keep > 0 ? ((size_t)m_max * b * keep + kMaxBlock * kMaxBlock) * 8 : 0);
   L.total = off + 256;
   return L;
 }
@@ -243,6 +248,7 @@ struct Solver {
   int *ints;
   int *mask, *flag, *breakdown, *ndefl, *flag2, *n_second, *chol_fail;
   void *eigws, *normws;
+  double *Sp = nullptr, *Qr = nullptr;  // thick restart: coefficients, rotation
   int qr_calls = 0;
 
   Solver(const bbl_csr &H_, int b_, int k_, double tol_, const Opts &o_, void *ws_, size_t bytes,
@@ -250,7 +256,7 @@ struct Solver {
       : H(H_), n(H_.n), b(b_), k(k_), tol(tol_), o(o_), s(s_) {
     xd = o.basis_dtype;
     sx = dsize(xd);
-    L = make_layout(n, b, k, o.m_max, xd);
+    L = make_layout(n, b, k, o.m_max, xd, o.restart_keep);
     if (bytes < L.total) throw Error{BBL_E_NOMEM, "workspace too small"};
     ws = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(ws_), 256));
     basis = ws + L.basis;
@@ -286,6 +292,8 @@ struct Solver {
     chol_fail = ints + 69;
     eigws = ws + L.eig;
     normws = ws + L.norm;
+    Sp = reinterpret_cast<double *>(ws + L.Sp);
+    Qr = Sp + (size_t)o.m_max * b * o.restart_keep;
   }
 
   char *slot(int J) const { return basis + (size_t)J * n * b * sx; }
@@ -366,6 +374,8 @@ struct Solver {
   struct Result {
     bool converged = false;
     int iters = 0, built = 0, spmm_calls = 0, checks = 0, spmm_timed = 0, restarts = 0;
+    int done_blocks = 0;  // block iterations of the cycles before the current one
+    int cycle_q = 0;      // blocks of kept Ritz vectors that open the current cycle
     double hnorm = 0.0, spmm_ms = 0.0, threeterm_ms = 0.0, reorth_ms = 0.0, qr_ms = 0.0,
            eig_ms = 0.0, restart_ms = 0.0;
     std::vector<double> theta, resid;
@@ -569,6 +579,42 @@ struct Solver {
     }
   }
 
+  // Thick restart after a cycle of nblk blocks (the next Lanczos block is in
+  // slot nblk, B_{nblk-1} in the B store): the lowest p = restart_keep Ritz
+  // pairs of the band matrix, the reduction of the arrowhead matrix they
+  // form with the next block back to a band matrix (rotating the Ritz
+  // vectors only), the rotated Ritz vectors Y' = V S_p Q formed in the spare
+  // slots past m_max and moved to slots 0..p/b-1, and the next block moved to
+  // slot p/b.  The recurrence then continues at block p/b unchanged: its
+  // three-term step couples to the last block of Y' through B_{p/b-1}.
+  void restart(int nblk, CheckStream &cq, Result &R) {
+    const int p = o.restart_keep, q = p / b, N = nblk * b;
+    double *rres = chk + 128;
+    const double *Blast = Bstore + (size_t)(nblk - 1) * b * b;
+    if (time_eig_) BBL_HIP(hipEventRecord(cq.rs0, s));
+    band_eigensolve(band, N, b, p, eigws, L.el, Blast, b, S, rres, s);
+    launch_restart_reduce(rres, S, p, (nblk - 1) * b, Blast, p, b, band, Bstore, Qr, s);
+    launch_restart_coeffs(S, p, N, Qr, p, b, Sp, s);
+    for (int j = 0; j < q; ++j)
+      launch_update(n, basis, xd, b, nblk, slot_stride(), Sp + (size_t)j * N * b, b, 1.0, nullptr,
+                    BBL_F64, 0.0, slot(o.m_max + 1 + j), xd, s);
+    BBL_HIP(hipMemcpyAsync(slot(q), slot(nblk), (size_t)n * b * sx, hipMemcpyDeviceToDevice, s));
+    BBL_HIP(hipMemcpyAsync(slot(0), slot(o.m_max + 1), (size_t)q * n * b * sx,
+                           hipMemcpyDeviceToDevice, s));
+    if (time_eig_) {
+      BBL_HIP(hipEventRecord(cq.rs1, s));
+      BBL_HIP(hipEventSynchronize(cq.rs1));
+      float t = 0.f;
+      BBL_HIP(hipEventElapsedTime(&t, cq.rs0, cq.rs1));
+      R.restart_ms += t;
+    }
+    R.done_blocks += nblk - R.cycle_q;
+    R.cycle_q = q;
+    ++R.restarts;
+    next_check = q + 1;
+    have_prev_ = false;
+  }
+
   Result run(const double *pivot, double *eigvecs_out) {
     Result R;
     CheckStreamLease lease(s);
@@ -664,8 +710,13 @@ struct Solver {
         }
         launch_check(cq, J + 1, kk);
         ++R.checks;
-        consume_check(cq, J + 1, kk, true, hnorm_dev, Xout, R);
-        break;
+        const bool can_restart =
+            o.restart_keep > 0 && !exhausted && R.restarts < o.max_restarts;
+        if (consume_check(cq, J + 1, kk, !can_restart, hnorm_dev, Xout, R) || !can_restart)
+          break;
+        restart(J + 1, cq, R);
+        J = o.restart_keep / b;
+        continue;
       }
       // one check in flight at a time; a due check waits for the slot
       if (N >= k && J + 1 >= next_check && !pending) {
@@ -677,6 +728,7 @@ struct Solver {
       ++J;
     }
     timer.finish();
+    R.done_blocks += R.iters - R.cycle_q;  // all block iterations of all cycles
     R.spmm_ms = timer.ms[0];
     R.threeterm_ms = timer.ms[1];
     R.reorth_ms = timer.ms[2];
@@ -689,6 +741,18 @@ struct Solver {
 
 
 
+
+// Kept Ritz vectors of a restarted truncated solve: the caller's restart_keep
+// raised to cover the k wanted pairs (a multiple of b); the truncated-solve
+// workspace always has room for the largest such value.
+int trunc_keep(int keep, int b, int k) {
+  if (keep <= 0) return 0;
+  return std::max(keep, (int)ceil_div(std::max(k, b), b) * b);
+}
+int trunc_keep_max(int b, int k) {
+  const int m = kMaxBlock / b * b;
+  return m >= std::max(k, b) ? m : 0;
+}
 
 struct TruncLayout {
   size_t rp, col, val, piv, inner, total;
@@ -706,7 +770,7 @@ TruncLayout trunc_layout(int64_t n_t, int64_t nnz_t, int b, int k, int m_max, in
   L.col = take((size_t)std::max<int64_t>(nnz_t, 1) * 4);
   L.val = take((size_t)std::max<int64_t>(nnz_t, 1) * dsize(vdt));
   L.piv = take((size_t)n_t * b * 8);
-  L.inner = take(make_layout(n_t, b, k, m_max, bdt).total + 256);
+  L.inner = take(make_layout(n_t, b, k, m_max, bdt, trunc_keep_max(b, k)).total + 256);
   L.total = off + 256;
   return L;
 }
@@ -722,6 +786,7 @@ Opts read_opts(const bbl_opts *o, int val_dtype) {
     r.flags = o->flags;
     r.plan = o->spmm_plan;
     r.restart_keep = o->restart_keep;
+    r.max_restarts = o->max_restarts > 0 ? o->max_restarts : r.max_restarts;
     r.fault_block = o->fault_block;
     if (o->defl_tau > 0) r.tau = o->defl_tau;
     r.seed = o->seed;
@@ -762,7 +827,12 @@ void check_solver_args(const bbl_csr *H, int nvec, int k, const Opts &o) {
               "a float32 basis needs float32 matrix values");
   BBL_REQUIRE((int64_t)o.m_max * nvec <= 8192, "m_max * nvec must be <= 8192");
   BBL_REQUIRE(o.fault_block >= 0, "fault_block must be >= 0");
-  BBL_REQUIRE(o.restart_keep == 0, "thick restart is not available in this build");
+  BBL_REQUIRE(o.max_restarts >= 0, "max_restarts must be >= 0");
+  if (o.restart_keep != 0)
+    BBL_REQUIRE(o.restart_keep % nvec == 0 && o.restart_keep >= std::max(k, nvec) &&
+                    o.restart_keep <= kMaxBlock && o.restart_keep / nvec + 1 < o.m_max,
+                "restart_keep must be a multiple of nvec in [max(k_eig, nvec), "
+                "min(32, nvec * (m_max - 2))]");
   if (o.plan) {
     BBL_REQUIRE(o.plan->n == H->n && o.plan->nnz == H->nnz && o.plan->row_ptr == H->row_ptr,
                 "spmm_plan was built for another matrix");
@@ -793,7 +863,8 @@ int solve_impl(const bbl_csr *H, const double *pivot, int32_t nvec, int32_t k, d
   BBL_HIP(hipStreamSynchronize(s));
   const int nd = cnt[0];
   if (stats) {
-    stats->iters = R.iters;
+    stats->iters = R.done_blocks;
+    stats->basis_blocks = R.iters;
     stats->spmm_calls = R.spmm_calls;
     stats->deflations = nd;
     stats->converged = R.converged ? 1 : 0;
@@ -853,6 +924,7 @@ int truncated_solve(const bbl_csr &H, int64_t n_t, int b, int k, double tol, con
   oi.seed = o.seed + 1;
   oi.basis_dtype = bdt;
   oi.plan = nullptr;  // the plan describes H, not its leading block
+  oi.restart_keep = trunc_keep(o.restart_keep, b, k);
   return solve_impl(&Ht, piv_t, b, k, tol, base + L.inner, L.total - L.inner, oi, theta,
                     eigvecs_t, nullptr, stats, s);
 }
@@ -971,16 +1043,26 @@ size_t bbl_lanczos_workspace_size(int64_t n, int32_t nvec, int32_t k_eig, int32_
   if (n < 1 || nvec < 1 || nvec > kMaxBlock || k_eig < 1 || k_eig > kMaxBlock || m_max < 1 ||
       (basis_dtype != BBL_F32 && basis_dtype != BBL_F64))
     return 0;
-  return make_layout(n, nvec, k_eig, m_max, basis_dtype).total;
+  return make_layout(n, nvec, k_eig, m_max, basis_dtype, 0).total;
+}
+
+size_t bbl_lanczos_workspace_size_restart(int64_t n, int32_t nvec, int32_t k_eig, int32_t m_max,
+                                          int32_t basis_dtype, int32_t restart_keep) {
+  if (bbl_lanczos_workspace_size(n, nvec, k_eig, m_max, basis_dtype) == 0 || restart_keep < 0 ||
+      restart_keep > kMaxBlock || restart_keep % nvec)
+    return 0;
+  return make_layout(n, nvec, k_eig, m_max, basis_dtype, restart_keep).total;
 }
 
 int bbl_lanczos_workspace_views(const void *ws, int64_t n, int32_t nvec, int32_t k_eig,
-                                int32_t m_max, int32_t basis_dtype, void **basis, double **band) {
+                                int32_t m_max, int32_t basis_dtype, int32_t restart_keep,
+                                void **basis, double **band) {
   return guarded([&] {
     BBL_REQUIRE(ws && basis && band, "NULL argument");
-    BBL_REQUIRE(bbl_lanczos_workspace_size(n, nvec, k_eig, m_max, basis_dtype) > 0,
+    BBL_REQUIRE(bbl_lanczos_workspace_size_restart(n, nvec, k_eig, m_max, basis_dtype,
+                                                   restart_keep) > 0,
                 "invalid sizes");
-    const Layout L = make_layout(n, nvec, k_eig, m_max, basis_dtype);
+    const Layout L = make_layout(n, nvec, k_eig, m_max, basis_dtype, restart_keep);
     char *base = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
     *basis = base + L.basis;
     *band = reinterpret_cast<double *>(base + L.band);

@@ -137,6 +137,14 @@ void launch_set_A(const double *Araw, int b, int J, double *band, int kd, const 
                   double *C3, double *hn2, hipStream_t s);
 void launch_set_B(const double *B, int b, int J, double *band, int kd, int nrows_max,
                   hipStream_t s);
+// Thick restart: band rows 0..p+b-1, Bstore[0..p/b) and the rotation Q
+// (p x p) of the kept Ritz vectors (theta, S[:, 0:p] with row stride ldS,
+// last block rows from row0, B_last), then Sp = S[:, 0:p] Q by column blocks.
+void launch_restart_reduce(const double *theta, const double *S, int ldS, int row0,
+                           const double *Blast, int p, int b, double *band, double *Bstore,
+                           double *Q, hipStream_t s);
+void launch_restart_coeffs(const double *S, int ldS, int Nr, const double *Q, int p, int b,
+                           double *Sp, hipStream_t s);
 void launch_normalize_columns(int64_t n, int k, double *X, double *scratch, int max_partials,
                               hipStream_t s);
 size_t normalize_scratch_bytes(int k, int max_partials);

@@ -422,6 +422,126 @@ __global__ void k_reorth_check(const double *G0, const double *G1, int b, double
   if (counter) *counter += need;
 }
 
+
+// Thick restart (Wu & Simon; the restarted method of the paper's introduction
+// and base-Lanczos subsection).  The lowest p Ritz vectors Y = V S_p of a
+// cycle and the next Lanczos block V_m span a space on which H acts as the
+// arrowhead matrix [[Theta, Sigma^T], [Sigma, A]] with Theta = diag(theta),
+// Sigma = B_last S_p[last block rows] (b x p).  This kernel rotates Y only,
+// Y' = Y Q, so that the matrix becomes a band matrix of bandwidth b again:
+// Householder reflectors applied from both sides reduce it column by column
+// with the index order reversed (V_m first, so the reflectors never touch
+// it).  Outputs: band rows 0..p+b-1 of the new cycle (row-major
+// band[i*(b+1)+d] = T[i][i-d]; the V_m diagonal block is left to the next
+// A), the b x b blocks B_j = T[(j+1)b.., jb..] (upper triangular) into
+// Bstore[0..p/b), and Q (p x p, row-major).  One workgroup; p + b <= 64.
+__global__ __launch_bounds__(256) void k_restart_reduce(const double *__restrict__ theta,
+                                                        const double *__restrict__ S, int ldS,
+                                                        int row0, const double *__restrict__ Blast,
+                                                        int p, int b, double *band,
+                                                        double *Bstore, double *Qout) {
+  constexpr int NM = 2 * kMaxBlock;
+  // G: the accumulated reflectors on the kept-vector indices b..N-1 (they
+  // are the identity on the first b), G[(a-b)*p + (c-b)]
+  __shared__ double M[NM * NM], G[kMaxBlock * kMaxBlock], v[NM], w[NM], pv[NM], sc[4];
+  const int t = threadIdx.x;
+  const int N = p + b;
+  // M in reversed order: index a <-> forward index N-1-a (V_m first)
+  for (int i = t; i < N * N; i += blockDim.x) {
+    const int a = i / N, c = i % N;
+    const int fi = N - 1 - a, fj = N - 1 - c;
+    double x = 0.0;
+    if (fi < p && fj < p) {
+      x = (fi == fj) ? theta[fi] : 0.0;
+    } else if (fi >= p && fj < p) {  // Sigma[fi - p][fj]
+      for (int q = 0; q < b; ++q) x += Blast[(fi - p) * b + q] * S[(size_t)(row0 + q) * ldS + fj];
+    } else if (fi < p && fj >= p) {
+      for (int q = 0; q < b; ++q) x += Blast[(fj - p) * b + q] * S[(size_t)(row0 + q) * ldS + fi];
+    }
+    M[i] = x;
+  }
+  for (int i = t; i < p * p; i += blockDim.x) G[i] = (i / p == i % p) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int c = 0; c + b + 1 < N; ++c) {
+    const int r0 = c + b;  // the reflector acts on indices r0..N-1
+    __syncthreads();       // every lane has read the previous step's sc
+    if (t == 0) {
+      double tail = 0.0;
+      for (int i = r0 + 1; i < N; ++i) tail += M[i * N + c] * M[i * N + c];
+      const double x0 = M[r0 * N + c];
+      if (tail == 0.0) {
+        sc[0] = 0.0;
+      } else {
+        const double nrm = sqrt(x0 * x0 + tail);
+        const double alpha = x0 >= 0.0 ? -nrm : nrm;
+        const double v0 = x0 - alpha;
+        sc[0] = 2.0 / (v0 * v0 + tail);
+        sc[1] = v0;
+      }
+    }
+    __syncthreads();
+    const double tau = sc[0];
+    if (tau == 0.0) continue;  // uniform: sc is shared
+    for (int i = t; i < N; i += blockDim.x)
+      v[i] = (i < r0) ? 0.0 : (i == r0 ? sc[1] : M[i * N + c]);
+    __syncthreads();
+    for (int i = t; i < N; i += blockDim.x) {  // p = tau M v, (G v)
+      double x = 0.0, y = 0.0;
+      for (int j = r0; j < N; ++j) {
+        x += M[i * N + j] * v[j];
+        if (i >= b) y += G[(i - b) * p + (j - b)] * v[j];
+      }
+      pv[i] = tau * x;
+      w[i] = y;
+    }
+    __syncthreads();
+    if (t == 0) {
+      double vp = 0.0;
+      for (int j = r0; j < N; ++j) vp += v[j] * pv[j];
+      sc[2] = 0.5 * tau * vp;
+    }
+    __syncthreads();
+    const double K = sc[2];
+    for (int i = t; i < N * N; i += blockDim.x) {  // M -= v q^T + q v^T
+      const int a = i / N, e = i % N;
+      const double qa = pv[a] - K * v[a], qe = pv[e] - K * v[e];
+      M[i] -= v[a] * qe + qa * v[e];
+    }
+    for (int i = t; i < p * p; i += blockDim.x) {  // G -= tau (G v) v^T
+      const int a = i / p + b, e = i % p + b;
+      G[i] -= tau * w[a] * v[e];
+    }
+    __syncthreads();
+  }
+  // forward order: T[i][j] = M[N-1-i][N-1-j], Q[l][i] = G[N-1-l][N-1-i]
+  for (int i = t; i < N * (b + 1); i += blockDim.x) {
+    const int r = i / (b + 1), d = i % (b + 1);
+    if (r - d >= 0) band[(size_t)r * (b + 1) + d] = M[(N - 1 - r) * N + (N - 1 - (r - d))];
+  }
+  const int q = p / b;
+  for (int i = t; i < q * b * b; i += blockDim.x) {
+    const int j = i / (b * b), r = (i / b) % b, c = i % b;
+    const int fi = (j + 1) * b + r, fj = j * b + c;
+    Bstore[i] = (c >= r) ? M[(N - 1 - fi) * N + (N - 1 - fj)] : 0.0;
+  }
+  for (int i = t; i < p * p; i += blockDim.x) {  // reversed index N-1-l = b + (p-1-l)
+    const int l = i / p, c = i % p;
+    Qout[i] = G[(p - 1 - l) * p + (p - 1 - c)];
+  }
+}
+
+// Sp = S[:, 0:p] Q as p / b column blocks of Nr x b (block j at Sp + j*Nr*b),
+// the coefficients of the rotated kept Ritz vectors in the cycle's basis.
+__global__ void k_restart_coeffs(const double *__restrict__ S, int ldS, int Nr,
+                                 const double *__restrict__ Q, int p, int b, double *Sp) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)Nr * p) return;
+  const int r = (int)(i / p), c = (int)(i % p);
+  double x = 0.0;
+  for (int l = 0; l < p; ++l) x += S[(size_t)r * ldS + l] * Q[l * p + c];
+  Sp[(size_t)(c / b) * Nr * b + (size_t)r * b + (c % b)] = x;
+}
+
 }  // namespace
 
 void launch_reorth_check(const double *G0, const double *G1, int b, double eta2, const int *outer,
@@ -478,6 +598,22 @@ void launch_set_B(const double *B, int b, int J, double *band, int kd, int nrows
                   hipStream_t s) {
   hipLaunchKernelGGL(k_set_B, dim3(1), dim3(256), 0, s, B, b, J, band, kd, nrows_max);
   check_launch("k_set_B");
+}
+
+void launch_restart_reduce(const double *theta, const double *S, int ldS, int row0,
+                           const double *Blast, int p, int b, double *band, double *Bstore,
+                           double *Q, hipStream_t s) {
+  hipLaunchKernelGGL(k_restart_reduce, dim3(1), dim3(256), 0, s, theta, S, ldS, row0, Blast, p, b,
+                     band, Bstore, Q);
+  check_launch("k_restart_reduce");
+}
+
+void launch_restart_coeffs(const double *S, int ldS, int Nr, const double *Q, int p, int b,
+                           double *Sp, hipStream_t s) {
+  const int64_t tot = (int64_t)Nr * p;
+  hipLaunchKernelGGL(k_restart_coeffs, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, S, ldS,
+                     Nr, Q, p, b, Sp);
+  check_launch("k_restart_coeffs");
 }
 
 void launch_normalize_columns(int64_t n, int k, double *X, double *scratch, int max_partials,

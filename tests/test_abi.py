@@ -138,10 +138,12 @@ def test_binding_structs_match_the_header_layout(tmp_path, struct, cls):
 def test_new_solver_options_are_validated_without_a_device():
     lib = bbl.load_library()
     H = bbl._Csr(10, 5, 1, 1, 1, bbl.BBL_F64, 0)
-    ev = np.zeros(2)
-    for keep, fault in ((0, -1), (-2, 0)):
-        o = bbl._Opts(10, bbl.BBL_F64, 0, 0, 1e-12, 0, None, keep, fault)
-        assert lib.bbl_block_lanczos(ctypes.byref(H), 1, 2, 2, 1e-8, 1, 1 << 30, ctypes.byref(o),
+    ev = np.zeros(4)
+    # bad fault block, negative keep, keep not a multiple of nvec, keep below
+    # k = 4, keep leaving no room for a new block (m_max 10, nvec 2: keep <= 16)
+    for keep, fault in ((0, -1), (-2, 0), (3, 0), (2, 0), (18, 0)):
+        o = bbl._Opts(10, bbl.BBL_F64, 0, 0, 1e-12, 0, None, keep, 0, fault)
+        assert lib.bbl_block_lanczos(ctypes.byref(H), 1, 2, 4, 1e-8, 1, 1 << 30, ctypes.byref(o),
                                      ev.ctypes.data_as(ctypes.c_void_p), None, None, None,
                                      None) == bbl.BBL_E_INVALID
 
@@ -151,14 +153,22 @@ def test_workspace_views_are_pointer_arithmetic():
     n, b, k, m = 1000, 4, 4, 20
     base = 0x10000000  # never dereferenced: the call only computes addresses
     basis, band = ctypes.c_void_p(), ctypes.c_void_p()
-    assert lib.bbl_lanczos_workspace_views(base + 8, n, b, k, m, bbl.BBL_F64,
+    assert lib.bbl_lanczos_workspace_views(base + 8, n, b, k, m, bbl.BBL_F64, 0,
                                            ctypes.byref(basis), ctypes.byref(band)) == bbl.BBL_OK
     # the basis comes first, at the 256-byte aligned start of the workspace
     assert basis.value == base + 256
     assert band.value % 256 == 0 and band.value >= basis.value + (m + 1) * n * b * 8
     assert band.value < base + lib.bbl_lanczos_workspace_size(n, b, k, m, bbl.BBL_F64)
-    assert lib.bbl_lanczos_workspace_views(base, 0, b, k, m, bbl.BBL_F64, ctypes.byref(basis),
+    assert lib.bbl_lanczos_workspace_views(base, 0, b, k, m, bbl.BBL_F64, 0, ctypes.byref(basis),
                                            ctypes.byref(band)) == bbl.BBL_E_INVALID
+    # with thick restart the basis has keep / b more blocks, so the band moves
+    b8 = ctypes.c_void_p()
+    assert lib.bbl_lanczos_workspace_views(base, n, b, k, m, bbl.BBL_F64, 8, ctypes.byref(basis),
+                                           ctypes.byref(b8)) == bbl.BBL_OK
+    assert b8.value >= basis.value + (m + 3) * n * b * 8
+    assert (lib.bbl_lanczos_workspace_size_restart(n, b, k, m, bbl.BBL_F64, 8) -
+            lib.bbl_lanczos_workspace_size(n, b, k, m, bbl.BBL_F64)) >= 2 * n * b * 8
+    assert lib.bbl_lanczos_workspace_size_restart(n, b, k, m, bbl.BBL_F64, 6) == 0
 
 
 def test_no_alloc_band_eig_rejects_sizes_beyond_its_scratch_without_a_device():

@@ -110,7 +110,8 @@ def test_full_size_solve_residuals_invariants_and_pivots(torch, bbl, mid, plan):
     np.testing.assert_allclose(X.T @ X, np.eye(w.k), atol=1e-6)
     assert np.all(np.diff(r.eigvals) >= 0)
 
-    m, b, n = r.stats["iters"], w.nvec, H.n
+    m, b, n = r.stats["basis_blocks"], w.nvec, H.n
+    assert m == r.stats["iters"]
     note("invariants of the stored basis, %d blocks" % m)
     basis_addr, band_addr = bbl.workspace_views(r.workspace, n, b, w.k, w.m_max, bbl.BBL_F32)
     ws = r.workspace

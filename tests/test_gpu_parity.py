@@ -700,3 +700,88 @@ def test_pivot_overlap_matches_host_svd(torch, bbl):
         np.testing.assert_allclose(cap, np.sum((Xc.T @ Q) ** 2, axis=1), rtol=0, atol=1e-11)
         if case == "inside":
             np.testing.assert_allclose(cos, 1.0, atol=1e-9)
+
+
+# ----------------------------------------------------------- thick restart
+@pytest.mark.parametrize("seed,b,keep,m_max", [(6, 4, 8, 8), (7, 4, 12, 10), (8, 2, 6, 12)])
+def test_thick_restart_matches_oracle_and_dense(torch, bbl, seed, b, keep, m_max):
+    """FP64: a basis capped at m_max blocks forces many restarts; eigenvalues
+    within 1e-10 of numpy's dense eigensolver and of the oracle's restarted
+    solve, explicit residuals recomputed on the host, and the final cycle's
+    stored basis satisfies V^T V = I and V^T H V = T (its band matrix)."""
+    note("thick restart n=1600 b=%d keep=%d m_max=%d" % (b, keep, m_max))
+    H = synthgen.generate(1600, 400, 20, 0.7, seed)
+    lam = np.linalg.eigvalsh(H.to_dense())
+    P = synthgen.gaussian_block(H.n, b, seed)
+    Hd = bbl.DeviceCSR.from_host(H, "float64")
+    r = bbl.block_lanczos(Hd, dev(torch, P), 4, 1e-10, m_max=m_max, restart_keep=keep)
+    ro = oracle.block_lanczos_restarted(H, P, 4, 1e-10, m_max, keep)
+    assert r.converged and ro.converged
+    assert r.stats["restarts"] >= 5, r.stats
+    np.testing.assert_allclose(r.eigvals, lam[:4], rtol=1e-10)
+    np.testing.assert_allclose(r.eigvals, ro.eigvals, rtol=1e-10)
+    X = r.eigvecs.cpu().numpy()
+    res = oracle.ritz_residuals(H, X, r.eigvals)
+    assert np.all(res <= 1e-10 * r.stats["hnorm_est"])
+    # restarts happen at the same cycle boundaries; the check schedule may
+    # end the last cycle a few blocks apart
+    assert abs(r.stats["restarts"] - ro.restarts) <= 1, (r.stats["restarts"], ro.restarts)
+    m = r.stats["basis_blocks"]
+    assert keep // b < m <= m_max
+    basis, band = bbl.workspace_views(r.workspace, H.n, b, 4, m_max, bbl.BBL_F64, keep)
+    ws = r.workspace
+    off = basis - ws.data_ptr()
+    V = ws[off:off + m * H.n * b * 8].view(torch.float64).view(m, H.n, b).cpu().numpy()
+    Q = np.concatenate([V[j] for j in range(m)], axis=1)
+    boff = band - ws.data_ptr()
+    bd = ws[boff:boff + m * b * (b + 1) * 8].view(torch.float64).view(m * b, b + 1).cpu().numpy()
+    T = np.zeros((m * b, m * b))
+    for i in range(m * b):
+        for d in range(min(b, i) + 1):
+            T[i, i - d] = T[i - d, i] = bd[i, d]
+    hn = r.stats["hnorm_est"]
+    assert np.max(np.abs(Q.T @ Q - np.eye(m * b))) <= 1e-12
+    assert np.max(np.abs(Q.T @ oracle.spmm(H, Q) - T)) <= 1e-10 * hn
+
+
+def test_thick_restart_fp32_planned_sixteen_vectors(torch, bbl):
+    """The C3 shape in small: FP32 values and basis, b = 16 through the
+    planned SpMM, k = 10, 12 stored blocks with 32 Ritz vectors kept."""
+    note("thick restart FP32 planned b=16 keep=32 m_max=12")
+    H = synthgen.generate(40000, 1000, 105, 0.7, 2)
+    Hp = bbl.DeviceCSR.from_host(H, "float32", block_rows=1000)
+    plan = bbl.spmm_plan(Hp, 16)
+    P = bbl.random_pivot(H.n, 16, synthgen.pivot_key(3))
+    r = bbl.block_lanczos(Hp, P, 10, 1e-6, m_max=12, restart_keep=32, spmm_plan=plan,
+                          time_phases=True)
+    assert r.converged and r.stats["restarts"] >= 2, r.stats
+    assert r.stats["t_restart_ms"] > 0
+    H32 = H.as_float32_values()
+    Pref = oracle.bootstrap_pivot(H32, 4000, 8)
+    ro = oracle.block_lanczos(H32, Pref, 10, 1e-6, 200)
+    np.testing.assert_allclose(r.eigvals, ro.eigvals, rtol=1e-5)
+    res = oracle.ritz_residuals(H32, r.eigvecs.cpu().numpy(), r.eigvals)
+    assert np.all(res <= 1e-6 * r.stats["hnorm_est"]), res / r.stats["hnorm_est"]
+
+
+def test_thick_restart_bootstrap_pivot_and_restart_cap(torch, bbl):
+    """The pivot's truncated solve restarts too (its pair count raises the
+    kept vectors), and a solve out of restarts reports its current pairs
+    with their true residuals."""
+    note("thick restart in the bootstrap pivot; restart cap")
+    w = synthgen.WORKLOADS["small_fp64_n2e4"]
+    H = w.generate()
+    Hd = bbl.DeviceCSR.from_host(H, "float64")
+    P, ps = bbl.bootstrap_pivot(Hd, w.n_trunc, 4, 1e-10, m_max=10, restart_keep=4)
+    assert ps["converged"] == 1 and ps["restarts"] >= 1
+    Pref = oracle.bootstrap_pivot(H, w.n_trunc, 4)
+    sv = np.linalg.svd(Pref.T @ P.cpu().numpy(), compute_uv=False)
+    assert sv.min() > 1 - 1e-9
+    r = bbl.block_lanczos(Hd, P, 4, 1e-8, m_max=12, restart_keep=8, max_restarts=2)
+    assert r.status == bbl.BBL_E_NOT_CONVERGED and r.stats["restarts"] == 2
+    X = r.eigvecs.cpu().numpy()
+    np.testing.assert_allclose(r.residuals, oracle.ritz_residuals(H, X, r.eigvals), rtol=1e-6)
+    ro = bbl.block_lanczos(Hd, P, 4, 1e-8, m_max=12, restart_keep=8)
+    assert ro.converged
+    np.testing.assert_allclose(ro.eigvals, oracle.block_lanczos(H, Pref, 4, 1e-8, 200).eigvals,
+                               rtol=1e-10)
