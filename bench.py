@@ -272,15 +272,113 @@ def compare_pivots(torch, bbl, weights, m_max):
 
 
 def pivot_overlap(bbl, X, P):
-    """Singular values of X^T Q with Q an orthonormal basis of span(P): the
-    cosines of the principal angles between the converged eigenvectors and
-    the pivot block (products on the GPU, the k x b factors on the host)."""
-    M = bbl.gram(X, 1, X.shape[1], P).cpu().numpy()          # X^T P
-    G = bbl.gram(P, 1, P.shape[1], P).cpu().numpy()          # P^T P
-    lam, U = np.linalg.eigh(0.5 * (G + G.T))
-    keep = lam > 1e-12 * lam.max()
-    Wh = U[:, keep] / np.sqrt(lam[keep])
-    return [float(x) for x in np.linalg.svd(M @ Wh, compute_uv=False)]
+    """Cosines of the principal angles between the converged eigenvectors
+    and the pivot block (the library's overlap diagnostic)."""
+    cos, _ = bbl.pivot_overlap(X.contiguous(), P.contiguous())
+    return [float(x) for x in cos]
+
+
+def parlett_bounds(theta, resid):
+    """Quadratic residual bound on the eigenvalue error of each Ritz value,
+    ||r_i||^2 / gap_i (Parlett, The Symmetric Eigenvalue Problem, Thm 11.7.1),
+    with gap_i taken from the neighbouring computed Ritz values (an estimate:
+    the true gap to the rest of the spectrum is not known without the
+    oracle)."""
+    th = np.asarray(theta, dtype=np.float64)
+    out = []
+    for i in range(len(th)):
+        others = np.delete(th, i)
+        gap = float(np.min(np.abs(others - th[i]))) if len(others) else float("inf")
+        out.append(float(resid[i]) ** 2 / gap if gap > 0 else float("inf"))
+    return out
+
+
+def reorth_flops(n, b, iters, basis_blocks, restarts, keep, m_max):
+    """FP64 flops of the Gram-Schmidt sweep (gram and update, 2 n M b each for
+    M = J b stored columns) over every block iteration the solve ran."""
+    q = keep // b if restarts else 0
+    Js = list(range(m_max)) if restarts else list(range(basis_blocks))
+    for c in range(restarts):
+        last = (c == restarts - 1)
+        Js += list(range(q, basis_blocks if last else m_max))
+    return sum(4.0 * n * (J + 1) * b * b for J in Js[:iters])
+
+
+def large_workload(torch, bbl, name, args):
+    """C3 (n = 2e7, ~400 nnz/row, b = 16, k = 10) or C5 (n = 1e8, ~50 nnz/row,
+    50/50 locality, b = k = 8): at most m_max = 40 stored FP32 blocks with
+    thick restart, bootstrapped pivot from the leading n_trunc rows.  One
+    timed solve (pivot + solve + Ritz vectors + FP64 residual, matrix
+    resident); residuals recomputed on the host in FP64 by the oracle's
+    product; eigenvalue accuracy certified by the quadratic residual bound."""
+    import synthgen
+    import oracle
+    w = synthgen.WORKLOADS[name]
+    b, k, keep = w.nvec, w.k, args.restart_keep
+    t0 = time.time()
+    H = w.generate(values="f32", verbose=True)
+    log("%s: n=%d nnz=%d (%.1f nnz/row) generated in %.1f s" % (name, H.n, H.nnz, H.nnz / H.n,
+                                                                 time.time() - t0))
+    t0 = time.time()
+    Hd = bbl.DeviceCSR.from_host(H, "float32", block_rows=w.R)
+    torch.cuda.synchronize()
+    log("uploaded in %.1f s" % (time.time() - t0))
+    ws = torch.empty(bbl.lanczos_workspace_bytes(H.n, b, k, w.m_max, bbl.BBL_F32, keep),
+                     dtype=torch.uint8, device="cuda")
+    log("workspace %.1f GB" % (ws.numel() / 1e9))
+    res = {}
+    for rep_i in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        P, pst = bbl.bootstrap_pivot(Hd, w.n_trunc, b, w.tol, m_max=w.m_max, seed=w.seed,
+                                     restart_keep=keep)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t
+        log("pivot: %.2f s, truncated iters %d restarts %d converged %d" %
+            (tp, pst["iters"], pst["restarts"], pst["converged"]))
+        r = bbl.block_lanczos(Hd, P, k, w.tol, m_max=w.m_max, seed=w.seed, workspace=ws,
+                              restart_keep=keep, time_phases=True)
+        torch.cuda.synchronize()
+        tts = time.perf_counter() - t
+        st = r.stats
+        log("solve %d: tts %.2f s iters %d restarts %d converged %s" %
+            (rep_i, tts, st["iters"], st["restarts"], r.converged))
+        res = {"tts_s": tts, "pivot_s": tp, "stats": st, "pivot_stats": pst, "r": r}
+    r, st = res["r"], res["stats"]
+    alg = spmm_bytes(H.n, H.nnz, b, 4, 4)
+    t_spmm = st["spmm_ms"] / 1e3 / max(st["spmm_timed"], 1)
+    log("host FP64 residuals ...")
+    t0 = time.time()
+    X = r.eigvecs.cpu().numpy()
+    hres = oracle.ritz_residuals(H, X, r.eigvals)
+    log("host residuals in %.1f s" % (time.time() - t0))
+    hn = st["hnorm_est"]
+    fl = reorth_flops(H.n, b, st["iters"], st["basis_blocks"], st["restarts"], keep, w.m_max)
+    out = {
+        "mode": "large", "workload": name,
+        "config": "sectored symmetric CSR n=%d, %.0f nnz/row, sectors of %d, p=%.1f, FP32 "
+                  "values and basis, b=%d, k=%d, tol=%g, <= %d stored blocks, thick restart "
+                  "keeping %d Ritz vectors, bootstrap from the leading %d rows" %
+                  (H.n, H.nnz / H.n, w.R, w.p, b, k, w.tol, w.m_max, keep, w.n_trunc),
+        "n": H.n, "nnz": H.nnz, "tts_s": res["tts_s"], "pivot_s": res["pivot_s"],
+        "converged": bool(r.converged), "iters": st["iters"], "restarts": st["restarts"],
+        "vector_equiv_iters": st["iters"] * b, "spmm_calls": st["spmm_calls"],
+        "pivot_iters": res["pivot_stats"]["iters"],
+        "pivot_spmm_calls": res["pivot_stats"]["pivot_spmm_calls"],
+        "eigvals": [float(x) for x in r.eigvals],
+        "resid_over_hnorm_device": [float(x) / hn for x in r.residuals],
+        "resid_over_hnorm_host_fp64": [float(x) / hn for x in hres],
+        "parlett_bound_abs": parlett_bounds(r.eigvals, hres),
+        "spmm": {"kernel": "plain CSR (k_spmm)", "alg_bytes_per_call": alg,
+                 "ms_per_call": t_spmm * 1e3, "alg_GBps": alg / t_spmm / 1e9,
+                 "frac_hbm_peak": alg / t_spmm / HBM_PEAK, "calls_timed": st["spmm_timed"]},
+        "phases_ms": {f: st[f] for f in ("spmm_ms", "t_threeterm_ms", "t_reorth_ms", "t_qr_ms",
+                                          "t_eig_ms", "t_restart_ms")},
+        "reorth_fp64": {"flops": fl, "TFLOPs": fl / (st["t_reorth_ms"] / 1e3) / 1e12,
+                        "frac_fp64_peak": fl / (st["t_reorth_ms"] / 1e3) / FP64_PEAK},
+        "device_GB": torch.cuda.max_memory_allocated() / 1e9,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def spmm_block_sweep(torch, bbl, H, R):
@@ -377,6 +475,11 @@ def main():
     ap.add_argument("--compare-m-max", type=int, default=300)
     ap.add_argument("--spmm-sweep", action="store_true",
                     help="SpMM time per operation for block widths 1..16 (plain and planned)")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="mid_n2e6 (the timed benchmark) or large_n2e7 / stress_n1e8 (one "
+                         "thick-restarted solve, reported on its own JSON line)")
+    ap.add_argument("--restart-keep", type=int, default=32,
+                    help="Ritz vectors kept by thick restart (large workloads)")
     ap.add_argument("--single-vector-arm", action="store_true",
                     help="also solve with block size 1 (the single-vector method) from a "
                          "random start and report vector-equivalent iterations")
@@ -395,6 +498,9 @@ def main():
     bbl.load_library()
     if args.compare_pivots:
         compare_pivots(torch, bbl, args.weights, args.compare_m_max)
+        return
+    if args.workload != WORKLOAD:
+        large_workload(torch, bbl, args.workload, args)
         return
     w = synthgen.WORKLOADS[WORKLOAD]
     t0 = time.time()

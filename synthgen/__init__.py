@@ -48,7 +48,7 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     lib.sg_generate.restype = ctypes.c_void_p
     lib.sg_generate.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
-                                ctypes.c_uint64, ctypes.c_int32]
+                                ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32]
     lib.sg_nnz.restype = ctypes.c_int64
     lib.sg_nnz.argtypes = [ctypes.c_void_p]
     lib.sg_export.restype = None
@@ -87,6 +87,8 @@ class CSR:
 
     @property
     def val32(self) -> np.ndarray:
+        if self.val.dtype == np.float32:
+            return self.val
         if self._val32 is None:
             self._val32 = self.val.astype(np.float32)
         return self._val32
@@ -104,10 +106,13 @@ class CSR:
         return D
 
 
-def generate(n: int, R: int, q: int, p: float, seed: int, threads: int = 0) -> CSR:
-    """Sectored symmetric matrix (see gen.cpp for the recipe)."""
+def generate(n: int, R: int, q: int, p: float, seed: int, threads: int = 0,
+             values: str = "f64", verbose: bool = False) -> CSR:
+    """Sectored symmetric matrix (see gen.cpp for the recipe).  values="f32"
+    keeps only the float32 rounding of the values (the largest instances:
+    no float64 copy is ever held); verbose prints a line per pass."""
     lib = _load()
-    h = lib.sg_generate(n, R, q, p, seed & (2**64 - 1), threads)
+    h = lib.sg_generate(n, R, q, p, seed & (2**64 - 1), threads, 1 if verbose else 0)
     if not h:
         raise ValueError("synthgen: bad arguments or out of memory "
                          f"(n={n}, R={R}, q={q}, p={p})")
@@ -115,10 +120,16 @@ def generate(n: int, R: int, q: int, p: float, seed: int, threads: int = 0) -> C
         nnz = lib.sg_nnz(h)
         row_ptr = np.empty(n + 1, np.int64)
         col = np.empty(nnz, np.int32)
-        val = np.empty(nnz, np.float64)
         diag = np.empty(n, np.float64)
         partners = np.empty(3 * (n // R), np.int32)
-        lib.sg_export(h, _ptr(row_ptr), _ptr(col), _ptr(val), None, _ptr(diag), _ptr(partners))
+        if values == "f32":
+            val = np.empty(nnz, np.float32)
+            lib.sg_export(h, _ptr(row_ptr), _ptr(col), None, _ptr(val), _ptr(diag),
+                          _ptr(partners))
+        else:
+            val = np.empty(nnz, np.float64)
+            lib.sg_export(h, _ptr(row_ptr), _ptr(col), _ptr(val), None, _ptr(diag),
+                          _ptr(partners))
     finally:
         lib.sg_free(h)
     return CSR(n, row_ptr, col, val, diag, partners, R)
@@ -164,8 +175,8 @@ class Workload:
     fp64_values: bool  # values stored in FP64 (else FP32)
     z_target: int
 
-    def generate(self, threads: int = 0) -> CSR:
-        return generate(self.n, self.R, self.q, self.p, self.seed, threads)
+    def generate(self, threads: int = 0, values: str = "f64", verbose: bool = False) -> CSR:
+        return generate(self.n, self.R, self.q, self.p, self.seed, threads, values, verbose)
 
 
 WORKLOADS = {
@@ -181,6 +192,9 @@ WORKLOADS = {
     # n = 5e6, ~300 nnz/row (held-out instance for the learned pivot), b = k = 10.
     "apply_n5e6": Workload("apply_n5e6", 5_000_000, 1_000, 162, 0.7, 200, 10, 10, 1e-6, 100,
                            50_000, False, 300),
+    # the large_n2e7 shape at n = 2e5 (a quick check of that code path)
+    "large_n2e5_check": Workload("large_n2e5_check", 200_000, 2_000, 210, 0.7, 0, 16, 10, 1e-6,
+                                 40, 20_000, False, 400),
     # n = 1e8, ~50 nnz/row, 50000 sectors of 2000, 50/50 split; b = k = 8.
     "stress_n1e8": Workload("stress_n1e8", 100_000_000, 2_000, 25, 0.5, 0, 8, 8, 1e-6, 40,
                             1_000_000, False, 50),

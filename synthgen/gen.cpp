@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -98,13 +99,23 @@ struct Params {
   int32_t q;
   double p;
   uint64_t seed;
+  int verbose;  // progress lines on stderr after each pass
 };
+
+double now_s() { return omp_get_wtime(); }
+void progress(const Params& P, const char* what, double t0) {
+  if (P.verbose) {
+    std::fprintf(stderr, "[synthgen] n=%lld: %s (%.1f s)\n", (long long)P.n, what, now_s() - t0);
+    std::fflush(stderr);
+  }
+}
 
 inline uint32_t umul_range(uint32_t w, uint64_t range) {  // floor(w * range / 2^32)
   return (uint32_t)(((uint64_t)w * range) >> 32);
 }
 
-// Column drawn by row i at draw t, or -1 when the draw is j == i.
+// Column drawn by row i at draw t, or -1 when the draw is j == i; its value
+// into *val unless val is NULL.
 inline int64_t draw_col(const Params& P, const int32_t* partners, int64_t i, int32_t t, double* val) {
   const int64_t s = i / P.R;
   const U4 w = draw(P.seed, (uint64_t)i, (uint32_t)t, TAG_DRAW_CHOICE);
@@ -117,15 +128,19 @@ inline int64_t draw_col(const Params& P, const int32_t* partners, int64_t i, int
   }
   const int64_t j = tgt * P.R + (int64_t)umul_range(w.v[2], (uint64_t)P.R);
   if (j == i) return -1;
-  *val = gauss(draw(P.seed, (uint64_t)i, (uint32_t)t, TAG_DRAW_VALUE));
+  if (val) *val = gauss(draw(P.seed, (uint64_t)i, (uint32_t)t, TAG_DRAW_VALUE));
   return j;
 }
 
+// The assembled matrix: row i's ucnt[i] entries (sorted, duplicates summed)
+// sit at tcol/tval[p0[i] ..] with gaps between rows; sg_export compacts them
+// straight into the caller's arrays, so the largest instances never hold a
+// second full copy.
 struct Matrix {
   int64_t n = 0, nnz = 0;
-  std::vector<int64_t> row_ptr;
-  std::vector<int32_t> col;
-  std::vector<double> val;
+  std::vector<int64_t> row_ptr, p0;
+  std::vector<int32_t> tcol;
+  std::vector<double> tval;
   std::vector<double> diag;
   std::vector<int32_t> partners;
 };
@@ -215,6 +230,7 @@ void make_partners(const Params& P, std::vector<int32_t>& partners) {
 }
 
 Matrix* build(const Params& P) {
+  const double t0 = now_s();
   Matrix* M = new Matrix();
   M->n = P.n;
   make_diag(P, M->diag);
@@ -229,22 +245,27 @@ Matrix* build(const Params& P) {
 #pragma omp parallel for schedule(dynamic, 1024)
   for (int64_t i = 0; i < n; ++i) {
     for (int32_t t = 0; t < P.q; ++t) {
-      double v;
-      const int64_t j = draw_col(P, partners, i, t, &v);
+      const int64_t j = draw_col(P, partners, i, t, nullptr);
       if (j < 0) continue;
       cnt[i].fetch_add(1, std::memory_order_relaxed);
       cnt[j].fetch_add(1, std::memory_order_relaxed);
     }
   }
-  std::vector<int64_t> c0(n), p0(n + 1);
+  progress(P, "draws counted", t0);
+  std::vector<int64_t> c0(n);
+  std::vector<int64_t>& p0 = M->p0;
+  p0.resize(n + 1);
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) c0[i] = cnt[i].load(std::memory_order_relaxed);
   exclusive_scan_i64(c0.data(), p0.data(), n);
+  { std::vector<int64_t>().swap(c0); }
   const int64_t tot = p0[n];
 
   // pass 2: fill (order within a row is arbitrary here; fixed by the sort)
-  std::vector<int32_t> tcol(tot);
-  std::vector<double> tval(tot);
+  std::vector<int32_t>& tcol = M->tcol;
+  std::vector<double>& tval = M->tval;
+  tcol.resize(tot);
+  tval.resize(tot);
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     tcol[p0[i]] = (int32_t)i;
@@ -266,6 +287,7 @@ Matrix* build(const Params& P) {
     }
   }
   { std::vector<std::atomic<int64_t>>().swap(cnt); }
+  progress(P, "draws placed", t0);
 
   // pass 3: per-row sort by (col, value), sum duplicates in that order
   std::vector<int64_t> ucnt(n);
@@ -294,13 +316,7 @@ Matrix* build(const Params& P) {
   M->row_ptr.resize(n + 1);
   exclusive_scan_i64(ucnt.data(), M->row_ptr.data(), n);
   M->nnz = M->row_ptr[n];
-  M->col.resize(M->nnz);
-  M->val.resize(M->nnz);
-#pragma omp parallel for schedule(dynamic, 1024)
-  for (int64_t i = 0; i < n; ++i) {
-    std::memcpy(&M->col[M->row_ptr[i]], &tcol[p0[i]], sizeof(int32_t) * ucnt[i]);
-    std::memcpy(&M->val[M->row_ptr[i]], &tval[p0[i]], sizeof(double) * ucnt[i]);
-  }
+  progress(P, "rows sorted and merged", t0);
   return M;
 }
 
@@ -309,11 +325,12 @@ Matrix* build(const Params& P) {
 extern "C" {
 
 // Builds the matrix; returns an opaque handle (NULL on bad arguments or OOM).
-void* sg_generate(int64_t n, int64_t R, int32_t q, double p, uint64_t seed, int32_t nthreads) {
+void* sg_generate(int64_t n, int64_t R, int32_t q, double p, uint64_t seed, int32_t nthreads,
+                  int32_t verbose) {
   if (n < 1 || R < 1 || n % R != 0 || q < 0 || p < 0.0 || p > 1.0) return nullptr;
   if (n > (int64_t)INT32_MAX) return nullptr;  // column indices are int32
   if (nthreads > 0) omp_set_num_threads(nthreads);
-  Params P{n, R, q, p, seed};
+  Params P{n, R, q, p, seed, verbose};
   try {
     return build(P);
   } catch (const std::bad_alloc&) {
@@ -328,12 +345,15 @@ int64_t sg_nnz(void* h) { return static_cast<Matrix*>(h)->nnz; }
 void sg_export(void* h, int64_t* row_ptr, int32_t* col, double* val, float* val32, double* diag,
                int32_t* partners) {
   Matrix* M = static_cast<Matrix*>(h);
-  if (row_ptr) std::memcpy(row_ptr, M->row_ptr.data(), sizeof(int64_t) * (M->n + 1));
-  if (col) std::memcpy(col, M->col.data(), sizeof(int32_t) * M->nnz);
-  if (val) std::memcpy(val, M->val.data(), sizeof(double) * M->nnz);
-  if (val32) {
-#pragma omp parallel for schedule(static)
-    for (int64_t k = 0; k < M->nnz; ++k) val32[k] = (float)M->val[k];
+  const int64_t n = M->n;
+  if (row_ptr) std::memcpy(row_ptr, M->row_ptr.data(), sizeof(int64_t) * (n + 1));
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t src = M->p0[i], dst = M->row_ptr[i], len = M->row_ptr[i + 1] - dst;
+    if (col) std::memcpy(col + dst, &M->tcol[src], sizeof(int32_t) * len);
+    if (val) std::memcpy(val + dst, &M->tval[src], sizeof(double) * len);
+    if (val32)
+      for (int64_t k = 0; k < len; ++k) val32[dst + k] = (float)M->tval[src + k];
   }
   if (diag) std::memcpy(diag, M->diag.data(), sizeof(double) * M->n);
   if (partners) std::memcpy(partners, M->partners.data(), sizeof(int32_t) * M->partners.size());

@@ -87,3 +87,11 @@ def test_gaussian_block_moments_and_determinism():
 def test_bad_arguments_rejected():
     with pytest.raises(ValueError):
         synthgen.generate(1001, 400, 5, 0.7, 0)  # n not a multiple of R
+
+
+def test_float32_export_is_the_rounding_of_the_float64_one():
+    a = synthgen.generate(20000, 400, 20, 0.7, 3)
+    b = synthgen.generate(20000, 400, 20, 0.7, 3, values="f32")
+    assert b.val.dtype == np.float32 and b.val32 is b.val
+    assert np.array_equal(a.row_ptr, b.row_ptr) and np.array_equal(a.col, b.col)
+    assert np.array_equal(a.val.astype(np.float32), b.val)
