@@ -37,6 +37,10 @@ import os
 import sys
 import time
 
+# the CPU baseline's OpenMP threads stay close to each other (set before any
+# OpenMP runtime starts)
+os.environ.setdefault("OMP_PROC_BIND", "close")
+
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -209,7 +213,7 @@ def kernels_only(torch, bbl, Hd, b, iters=10):
     log("kernels-only done")
 
 
-def compare_pivots(torch, bbl, weights, m_max):
+def compare_pivots(torch, bbl, weights, m_max, sweep=False):
     import synthgen
     w = synthgen.WORKLOADS["apply_n5e6"]
     t0 = time.time()
@@ -265,6 +269,8 @@ def compare_pivots(torch, bbl, weights, m_max):
     for a in arms.values():
         a["max_eig_rel_diff_vs_bootstrap"] = float(np.max(np.abs(np.array(a["eigvals"]) - ref) /
                                                           np.abs(ref)))
+    if sweep:
+        arms["spmm_block_sweep"] = spmm_block_sweep(torch, bbl, H, R, Hd)
     print(json.dumps({"mode": "compare-pivots", "workload": "sectored symmetric CSR n=5e6, "
                       "~300 nnz/row, FP32, b=k=10, tol=1e-6, truncation 50000 rows, seed 200",
                       "n": H.n, "nnz": H.nnz, "m_max": m_max, "weights": os.path.basename(weights),
@@ -276,6 +282,30 @@ def pivot_overlap(bbl, X, P):
     and the pivot block (the library's overlap diagnostic)."""
     cos, _ = bbl.pivot_overlap(X.contiguous(), P.contiguous())
     return [float(x) for x in cos]
+
+
+def independent_residuals(torch, Hd, X, theta, chunk=400_000_000):
+    """||H x_i - theta_i x_i||_2 in float64 through torch's sparse CSR product
+    (the vendor sparse library), independent of this library's kernels: the
+    matrix is taken in row chunks of at most `chunk` stored entries, its
+    float32 values promoted to float64."""
+    rp = Hd.row_ptr
+    n, k = X.shape
+    th = torch.as_tensor(np.asarray(theta, dtype=np.float64), device=X.device)
+    acc = torch.zeros(k, dtype=torch.float64, device=X.device)
+    rp_h = rp.cpu().numpy()
+    r0 = 0
+    while r0 < n:
+        r1 = int(np.searchsorted(rp_h, rp_h[r0] + chunk, side="right")) - 1
+        r1 = min(n, max(r1, r0 + 1))
+        p0, p1 = int(rp_h[r0]), int(rp_h[r1])
+        crow = (rp[r0:r1 + 1] - p0).to(torch.int32)
+        A = torch.sparse_csr_tensor(crow, Hd.col[p0:p1], Hd.val[p0:p1].double(), size=(r1 - r0, n))
+        Y = torch.matmul(A, X) - X[r0:r1] * th
+        acc += (Y * Y).sum(0)
+        del A, Y, crow
+        r0 = r1
+    return acc.sqrt().cpu().numpy()
 
 
 def parlett_bounds(theta, resid):
@@ -309,10 +339,9 @@ def large_workload(torch, bbl, name, args):
     50/50 locality, b = k = 8): at most m_max = 40 stored FP32 blocks with
     thick restart, bootstrapped pivot from the leading n_trunc rows.  One
     timed solve (pivot + solve + Ritz vectors + FP64 residual, matrix
-    resident); residuals recomputed on the host in FP64 by the oracle's
-    product; eigenvalue accuracy certified by the quadratic residual bound."""
+    resident); residuals recomputed in FP64 by the vendor sparse library;
+    eigenvalue accuracy certified by the quadratic residual bound."""
     import synthgen
-    import oracle
     w = synthgen.WORKLOADS[name]
     b, k, keep = w.nvec, w.k, args.restart_keep
     t0 = time.time()
@@ -347,11 +376,12 @@ def large_workload(torch, bbl, name, args):
     r, st = res["r"], res["stats"]
     alg = spmm_bytes(H.n, H.nnz, b, 4, 4)
     t_spmm = st["spmm_ms"] / 1e3 / max(st["spmm_timed"], 1)
-    log("host FP64 residuals ...")
+    log("FP64 residuals through the vendor sparse library ...")
     t0 = time.time()
-    X = r.eigvecs.cpu().numpy()
-    hres = oracle.ritz_residuals(H, X, r.eigvals)
-    log("host residuals in %.1f s" % (time.time() - t0))
+    del ws
+    torch.cuda.empty_cache()
+    hres = independent_residuals(torch, Hd, r.eigvecs, r.eigvals)
+    log("residuals in %.1f s" % (time.time() - t0))
     hn = st["hnorm_est"]
     fl = reorth_flops(H.n, b, st["iters"], st["basis_blocks"], st["restarts"], keep, w.m_max)
     out = {
@@ -367,7 +397,7 @@ def large_workload(torch, bbl, name, args):
         "pivot_spmm_calls": res["pivot_stats"]["pivot_spmm_calls"],
         "eigvals": [float(x) for x in r.eigvals],
         "resid_over_hnorm_device": [float(x) / hn for x in r.residuals],
-        "resid_over_hnorm_host_fp64": [float(x) / hn for x in hres],
+        "resid_over_hnorm_fp64_vendor_sparse": [float(x) / hn for x in hres],
         "parlett_bound_abs": parlett_bounds(r.eigvals, hres),
         "spmm": {"kernel": "plain CSR (k_spmm)", "alg_bytes_per_call": alg,
                  "ms_per_call": t_spmm * 1e3, "alg_GBps": alg / t_spmm / 1e9,
@@ -378,17 +408,23 @@ def large_workload(torch, bbl, name, args):
                         "frac_fp64_peak": fl / (st["t_reorth_ms"] / 1e3) / FP64_PEAK},
         "device_GB": torch.cuda.max_memory_allocated() / 1e9,
     }
+    if args.spmm_sweep:
+        out["spmm_block_sweep"] = spmm_block_sweep(torch, bbl, H, w.R, Hd)
     print(json.dumps(out), flush=True)
 
 
-def spmm_block_sweep(torch, bbl, H, R):
+SWEEP_WIDTHS = (1, 2, 4, 8, 12, 16, 32)
+
+
+def spmm_block_sweep(torch, bbl, H, R, Hb=None):
     """SpMM time per operation (one matrix element times one vector) for
-    block widths 1..16, plain CSR kernel and planned kernel (the GPU analogue
-    of the paper's block-size tables)."""
-    Hp = bbl.DeviceCSR.from_host(H, "float32")
-    Hb = bbl.DeviceCSR.from_host(H, "float32", block_rows=R)
+    block widths 1..32, plain CSR kernel and, where a plan exists, the planned
+    kernel (the GPU analogue of the paper's block-size tables)."""
+    if Hb is None:
+        Hb = bbl.DeviceCSR.from_host(H, "float32", block_rows=R)
+    Hp = bbl.DeviceCSR(Hb.n, Hb.row_ptr, Hb.col, Hb.val, 0)
     out = {}
-    for b in (1, 2, 4, 8, 16):
+    for b in SWEEP_WIDTHS:
         V = torch.randn((H.n, b), dtype=torch.float32, device="cuda")
         W = torch.empty_like(V)
         t_plain = time_kernel(torch, lambda: bbl.spmm(Hp, V, W), 10)
@@ -401,8 +437,10 @@ def spmm_block_sweep(torch, bbl, H, R):
                         "planned_alg_GBps": spmm_bytes(H.n, H.nnz, b, 4, 4) / t_pl / 1e9,
                         "plan_slots": plan.slots})
             del plan
-        except bbl.BblError:
+        except (bbl.BblError, RuntimeError):
             pass
+        del V, W
+        torch.cuda.empty_cache()
         out[str(b)] = rec
         log("b=%d %s" % (b, json.dumps(rec)))
     return out
@@ -421,38 +459,134 @@ def time_kernel(torch, fn, iters):
     return start.elapsed_time(stop) / 1e3 / iters
 
 
+def host_info():
+    import platform
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = None
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            q, per = f.read().split()[:2]
+            quota = None if q == "max" else float(q) / float(per)
+    except (OSError, ValueError):
+        pass
+    return {"cpu_model": model or platform.processor(), "cpus_affinity": aff,
+            "cpu_count": os.cpu_count(), "cgroup_cpu_quota": quota,
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS"),
+            "OMP_PROC_BIND": os.environ.get("OMP_PROC_BIND")}
+
+
 def cpu_baseline(H, w, pivot_np, gpu_iters):
-    """Oracle (FP64, host cores) on a bounded sample of the same solve: block
-    iterations m1 and m2 from the same pivot on the same (float32-rounded)
-    matrix; per-iteration cost a + c*j fitted from the two runs and summed to
-    the GPU's iteration count.  The truncated-space pivot solve is timed in
-    full."""
+    """The FP64 oracle on the host cores, as it stands:
+    * the small FP64 workload (n = 2e4, b = k = 4, tol 1e-8, bootstrap from the
+      leading 2000 rows) solved in full and timed;
+    * the benchmark workload on a bounded sample: the truncated pivot solve
+      timed in full; block iterations m = 6 and m = 18 of the solve from the
+      same pivot on the same float32-rounded matrix timed, fitted as a + c j
+      per block (products, recurrence, reorthogonalisation against j blocks);
+      the oracle's dense band eigensolve of each block, O((j b)^3), timed at
+      four sizes up to the final 8 x iterations and summed over the GPU's
+      iteration count with a cubic fit; plus one explicit-residual product.
+    `value` is that estimate of the full solve, in seconds."""
     import oracle
+    import synthgen
+    info = host_info()
+    threads = int(info["OMP_NUM_THREADS"] or info["cpu_count"] or 1)
+    w1 = synthgen.WORKLOADS["small_fp64_n2e4"]
+    H1 = w1.generate()
+    t0 = time.perf_counter()
+    P1 = oracle.bootstrap_pivot(H1, w1.n_trunc, w1.nvec)
+    r1 = oracle.block_lanczos(H1, P1, w1.k, w1.tol, w1.m_max)
+    t_small = time.perf_counter() - t0
     H32 = H.as_float32_values()
     t0 = time.perf_counter()
     oracle.bootstrap_pivot(H32, w.n_trunc, w.nvec, tol=w.tol, m_max=w.m_max, seed=w.seed)
     t_piv = time.perf_counter() - t0
-    m1, m2 = 4, 12
+    m1, m2 = 6, 18
     t0 = time.perf_counter()
     oracle.block_lanczos(H32, pivot_np, w.k, 1e-300, m1, seed=w.seed)
     t1 = time.perf_counter() - t0
     t0 = time.perf_counter()
     oracle.block_lanczos(H32, pivot_np, w.k, 1e-300, m2, seed=w.seed)
     t2 = time.perf_counter() - t0
-    # t(m) = a m + c m^2 / 2  (iteration j costs a + c j)
+    # t(m) = a m + c m^2 / 2  (block j costs a + c j)
     A = np.array([[m1, m1 * m1 / 2.0], [m2, m2 * m2 / 2.0]])
     a, c = np.linalg.solve(A, np.array([t1, t2]))
     a, c = max(a, 0.0), max(c, 0.0)
-    m = gpu_iters
-    est = t_piv + a * m + c * m * m / 2.0 + a  # + one explicit-residual product
+    m, b = gpu_iters, w.nvec
+    rng = np.random.default_rng(0)
+    sizes = [int(round(m * b * f)) for f in (0.25, 0.5, 0.75, 1.0)]
+    te = []
+    for N in sizes:
+        S = rng.standard_normal((N, N))
+        S = S + S.T
+        t0 = time.perf_counter()
+        np.linalg.eigh(S)
+        te.append(time.perf_counter() - t0)
+    # t_eigh(N) = e N^3, least squares over the four sizes
+    N3 = np.array(sizes, dtype=np.float64) ** 3
+    e = float(np.dot(N3, te) / np.dot(N3, N3))
+    t_eig = sum(e * float(j * b) ** 3 for j in range(1, m + 1))
+    est = t_piv + a * m + c * m * m / 2.0 + t_eig + a
     return {
-        "value": est, "unit": "s", "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count())),
-        "kind": "oracle",
-        "sample": ("FP64 oracle on the same matrix (float32-rounded values) and pivot: "
-                   "truncated-space pivot solve timed in full (%.1f s); block iterations "
-                   "m=%d (%.1f s) and m=%d (%.1f s) timed, per-iteration cost a+c*j fitted "
-                   "and summed to the GPU's %d iterations" % (t_piv, m1, t1, m2, t2, m)),
+        "value": est, "unit": "s", "cores": threads, "kind": "oracle",
+        "sample": ("FP64 oracle (C loops + numpy), %s, %s threads: the n=2e4 FP64 workload "
+                   "solved in full in %.2f s (%d blocks); for this workload the truncated "
+                   "pivot solve timed in full (%.1f s), block iterations m=%d (%.1f s) and "
+                   "m=%d (%.1f s) timed and fitted a+c*j per block, dense band eigensolves "
+                   "timed at N=%s (%s s) and fitted e*N^3, all summed to the GPU's %d "
+                   "iterations" % (info["cpu_model"], threads, t_small, r1.iters, t_piv, m1, t1,
+                                   m2, t2, sizes, ["%.2f" % x for x in te], m)),
+        "small_fp64_full_s": t_small, "host": info,
+        "model_terms_s": {"pivot": t_piv, "blocks_linear": a * m + c * m * m / 2.0 + a,
+                          "band_eigensolves": t_eig},
     }
+
+
+def fp64_arm(torch, bbl, H, w, P, r32, spmm_iters):
+    """The same workload with float64 values, basis and products (plain CSR
+    kernel; the float64 plan stages one block per sector): time to solution,
+    SpMM algorithmic GB/s against nnz*12 + 8(n+1) + 2*n*b*8 bytes per call,
+    and the eigenvalue difference from the float32 solve."""
+    Hd64 = bbl.DeviceCSR.from_host(H, "float64", block_rows=w.R)
+    b, k = w.nvec, w.k
+    plan = bbl.spmm_plan(Hd64, b)
+    ws = torch.empty(bbl.lanczos_workspace_bytes(H.n, b, k, w.m_max, bbl.BBL_F64),
+                     dtype=torch.uint8, device="cuda")
+    out = {}
+    for name, pl in (("plain", None), ("planned", plan)):
+        bbl.block_lanczos(Hd64, P, k, w.tol, m_max=w.m_max, seed=w.seed, workspace=ws,
+                          spmm_plan=pl)  # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = bbl.block_lanczos(Hd64, P, k, w.tol, m_max=w.m_max, seed=w.seed, workspace=ws,
+                              time_spmm=True, spmm_plan=pl)
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - t
+        alg = spmm_bytes(H.n, H.nnz, b, 8, 8)
+        t_sp = r.stats["spmm_ms"] / 1e3 / max(r.stats["spmm_timed"], 1)
+        out[name] = {"solve_s": tt, "iters": r.stats["iters"], "converged": bool(r.converged),
+                     "spmm_ms_per_call": t_sp * 1e3, "spmm_alg_GBps": alg / t_sp / 1e9,
+                     "spmm_frac_hbm_peak": alg / t_sp / HBM_PEAK, "alg_bytes_per_call": alg,
+                     "eigvals": [float(x) for x in r.eigvals],
+                     "max_eig_rel_diff_fp32_vs_fp64":
+                         float(np.max(np.abs(r32.eigvals - r.eigvals) / np.abs(r.eigvals))),
+                     "max_resid_over_hnorm": float(np.max(r.residuals) / r.stats["hnorm_est"])}
+        log("fp64 arm (%s): %s" % (name, json.dumps(out[name])))
+    del ws, plan, Hd64
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -480,6 +614,8 @@ def main():
                          "thick-restarted solve, reported on its own JSON line)")
     ap.add_argument("--restart-keep", type=int, default=32,
                     help="Ritz vectors kept by thick restart (large workloads)")
+    ap.add_argument("--no-fp64-arm", action="store_true",
+                    help="skip the float64 solve of the same workload")
     ap.add_argument("--single-vector-arm", action="store_true",
                     help="also solve with block size 1 (the single-vector method) from a "
                          "random start and report vector-equivalent iterations")
@@ -497,7 +633,7 @@ def main():
     import paper_2210_15763_amd as bbl
     bbl.load_library()
     if args.compare_pivots:
-        compare_pivots(torch, bbl, args.weights, args.compare_m_max)
+        compare_pivots(torch, bbl, args.weights, args.compare_m_max, args.spmm_sweep)
         return
     if args.workload != WORKLOAD:
         large_workload(torch, bbl, args.workload, args)
@@ -580,7 +716,17 @@ def main():
     gram_bytes = j * H.n * b * 4 + H.n * b * 8
     gram_flops = 2.0 * H.n * j * b * b
 
+    # the phase split of one more solve with every phase timed (device time;
+    # the band eigensolves run beside the recurrence on their own stream)
+    P_ph, _ = bbl.bootstrap_pivot(Hd, w.n_trunc, b, w.tol, m_max=w.m_max, seed=w.seed)
+    r_ph = bbl.block_lanczos(Hd, P_ph, k, w.tol, m_max=w.m_max, seed=w.seed, workspace=ws_l,
+                             time_phases=True, spmm_plan=step.plan)
+    phases = {f: r_ph.stats[f] for f in ("spmm_ms", "t_threeterm_ms", "t_reorth_ms", "t_qr_ms",
+                                          "t_eig_ms")}
+    log("phases: %s" % json.dumps(phases))
+    hres = None
     extra = {
+        "phases_ms": phases,
         "bootstrap": {"iters": r.stats["iters"], "spmm_calls": r.stats["spmm_calls"],
                       "checks": r.stats["checks"], "deflations": r.stats["deflations"],
                       "reorth_second_passes": r.stats["reorth_second_passes"],
@@ -610,7 +756,7 @@ def main():
                              "main_solve_bytes": by_main, "pivot_solve_bytes": by_piv,
                              "measured_over_roofline": tts / ((by_main + by_piv) / HBM_PEAK)}
     if args.spmm_sweep:
-        extra["spmm_block_sweep"] = spmm_block_sweep(torch, bbl, H, w.R)
+        extra["spmm_block_sweep"] = spmm_block_sweep(torch, bbl, H, w.R, Hd)
     if args.single_vector_arm:
         p1 = bbl.random_pivot(H.n, 1, synthgen.pivot_key(w.seed))
         plan1 = bbl.spmm_plan(Hd, 1)
@@ -633,6 +779,18 @@ def main():
                            "tts_s": time.perf_counter() - t, "converged": bool(rr.converged),
                            "max_eig_rel_diff_vs_bootstrap":
                                float(np.max(np.abs(rr.eigvals - r.eigvals) / np.abs(r.eigvals)))}
+    if not args.no_fp64_arm:
+        extra["fp64_arm"] = fp64_arm(torch, bbl, H, w, P, r, args.spmm_iters)
+    # eigenvalue accuracy of this run: FP64 residuals of the returned pairs
+    # recomputed by the vendor sparse library, and the quadratic residual
+    # bound on each eigenvalue's error
+    hres = independent_residuals(torch, Hd, r.eigvecs, r.eigvals)
+    extra["accuracy"] = {
+        "resid_over_hnorm_fp64_vendor_sparse": [float(x) / r.stats["hnorm_est"] for x in hres],
+        "parlett_bound_abs": parlett_bounds(r.eigvals, hres),
+        "note": "eigenvalue error vs the exact eigenvalues of the stored FP32 matrix is at most "
+                "||r||^2/gap (gap estimated from the neighbouring Ritz values); the FP64 arm "
+                "gives the difference from a float64 solve"}
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample) ...")
