@@ -261,7 +261,7 @@ def compare_pivots(torch, bbl, weights, m_max, sweep=False):
     def learned():
         P, info = bbl.learned_pivot(Hd, params, w.n_trunc, R, b, k, w.tol, m_max=m_max,
                                     seed=w.seed)
-        return P, {"pivot_full_spmm": 6, "used_fallback": info["used_fallback"],
+        return P, {"pivot_full_spmm": 6, "choice": info["choice"],
                    "rr_sums": [float(x) for x in info["rr_sums"]],
                    "truncated_iters": info["stats"]["iters"]}
     run("learned", learned)

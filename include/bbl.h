@@ -150,6 +150,10 @@ typedef struct {
                            marked as having lost rank beyond repair, and block
                            f as needing the second Gram-Schmidt sweep (so it is
                            redone); the solve must then return BBL_E_BREAKDOWN */
+  int32_t feature_vectors; /* learned-pivot features: lowest truncated eigenvectors
+                           extended one hop before the Rayleigh-Ritz step that
+                           selects P_D, 10..32 (0 = default 20) */
+  int32_t reserved;
 } bbl_opts;
 
 /* Option flags.  BBL_FLAG_TIME_SPMM records a pair of HIP events on the
@@ -488,17 +492,19 @@ int bbl_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t step
 
 /*
  * Learned pivot block: features of H (as bbl_pivot_features), the network's
- * first nvec outputs as the n x nvec block, then the fallback rule: the plain
- * bootstrap block (lowest nvec truncated eigenvectors, zero padded) is used
- * instead if the learned block has a non-finite entry, if a squared pivot of
- * the Cholesky factor of its Gram matrix is not above 1e-8 of the largest
- * diagonal entry, or if the sum of its k lowest Rayleigh-Ritz values is not
- * below that of the bootstrap block.
+ * first nvec outputs as the n x nvec block, then the selection: of the
+ * learned block, P_D (the network's own input block, the first nvec of its
+ * columns) and the plain bootstrap block (lowest nvec truncated
+ * eigenvectors, zero padded), the one whose k lowest Rayleigh-Ritz values
+ * sum lowest is returned.  The learned block takes part only if its entries
+ * are finite and every squared pivot of the Cholesky factor of its Gram
+ * matrix is above 1e-8 of the largest diagonal entry; P_D's sum is that of
+ * its own Ritz values; ties go to the bootstrap block, then to P_D.
  *   nvec          1..10;  k  number of Ritz values compared (min(k, nvec))
  *   pivot         device n x nvec float64 output (not orthonormalised)
- *   used_fallback host, 1 if the bootstrap block was returned
- *   rr_sums       host [2]: the two sums (learned, bootstrap), NaN when the
- *                 learned block failed an earlier test
+ *   used_fallback host: 0 the learned block, 1 the bootstrap block, 2 P_D
+ *   rr_sums       host [3]: the sums (learned, bootstrap, P_D); the learned
+ *                 one is NaN when that block failed the finite/Cholesky test
  */
 size_t bbl_learned_pivot_workspace_size(const bbl_csr *H, int64_t n_trunc, int32_t nvec,
                                         int32_t m_max, int32_t basis_dtype, void *stream);

@@ -25,18 +25,20 @@ features (per row i, 28 values)
               lowest Ritz vectors (ascending) form P_D, each column with
               unit norm and its largest-magnitude entry positive.
 
-network    4 linear layers 28 -> 128 -> 128 -> 128 -> 10, ReLU between them;
-           parameters flat in the order W1 (128 x 28, row = output), b1, W2,
-           b2, W3, b3, W4 (10 x 128), b4: 38,026 values.
+network    residual form: the row's 10 P_D amplitudes (features 18..27) plus
+           4 linear layers 28 -> 128 -> 128 -> 128 -> 10 with ReLU between
+           them (a zero output layer returns P_D itself); parameters flat in
+           the order W1 (128 x 28, row = output), b1, W2, b2, W3, b3,
+           W4 (10 x 128), b4: 38,026 values.
 loss       mean over rows and outputs of (out - target)^2, with targets the
            converged eigenvectors X aligned to P_D by orthogonal Procrustes
            (X <- X Q, Q the polar factor of X^T P_D) and scaled by sqrt(n).
 optimiser  Adam (Kingma & Ba 2015) with bias correction.
-fallback   the learned block is replaced by the plain bootstrap block if it
-           has a non-finite entry, if the Cholesky factor of its Gram matrix
-           has a squared pivot below 1e-8 times the largest diagonal entry, or
-           if the sum of its k lowest Rayleigh-Ritz values is not below the
-           same sum for the bootstrap block.
+selection  of the learned block, P_D and the plain bootstrap block, the one
+           whose k lowest Rayleigh-Ritz values sum lowest; the learned block
+           takes part only if its entries are finite and the Cholesky factor
+           of its Gram matrix has every squared pivot above 1e-8 times the
+           largest diagonal entry; ties go to the bootstrap block, then P_D.
 """
 from __future__ import annotations
 
@@ -95,7 +97,7 @@ def truncated_eigs(H, n_t: int, m: int, *, tol: float, m_max: int = 400, seed: i
     if n_t <= dense_max:
         lam, X = np.linalg.eigh(Ht.to_dense())
         return lam[:m], X[:, :m]
-    b = max(1, m // 2)
+    b = min(N_OUT, max(1, m // 2))
     Pt = synthgen.gaussian_block(n_t, b, synthgen.pivot_key(seed + 1))
     res = block_lanczos(Ht, Pt, m, tol, m_max, seed=seed + 1)
     return res.eigvals, res.eigvecs
@@ -128,24 +130,27 @@ def rayleigh_ritz(H, Y: np.ndarray, keep: int, spmm=_spmm):
     return th[:keep], Y @ C[:, :keep]
 
 
-def variant_d(H, n_t: int, *, m: int = N_OUT, tol: float = 1e-8, seed: int = 0,
-              diag: np.ndarray | None = None, spmm=_spmm):
+def variant_d(H, n_t: int, *, m: int = N_OUT, m_trunc: int | None = None, tol: float = 1e-8,
+              seed: int = 0, diag: np.ndarray | None = None, spmm=_spmm):
     """The one-hop, Rayleigh-Ritz-selected block P_D (n x m) and its Ritz
-    values; also returns the truncated eigenpairs it starts from."""
+    values; also returns the truncated eigenpairs it starts from (m_trunc of
+    them, default 2m)."""
     if diag is None:
         diag = diagonal(H)
-    theta, Pt = truncated_eigs(H, n_t, 2 * m, tol=tol, seed=seed)
+    theta, Pt = truncated_eigs(H, n_t, 2 * m if m_trunc is None else m_trunc, tol=tol, seed=seed)
     Y = one_hop_extension(H, Pt, theta, diag, spmm=spmm)
     th_d, PD = rayleigh_ritz(H, Y, m, spmm=spmm)
     return normalise_columns(PD), th_d, theta, Pt
 
 
-def features(H, n_t: int, R: int, *, tol: float = 1e-8, seed: int = 0, spmm=_spmm):
+def features(H, n_t: int, R: int, *, tol: float = 1e-8, seed: int = 0, m_trunc: int | None = None,
+             spmm=_spmm):
     """[n][28] float64 features, P_D, and the plain bootstrap block of 10
     columns (lowest truncated eigenvectors, zero padded)."""
     n = H.n
     d = diagonal(H)
-    PD, th_d, theta, Pt = variant_d(H, n_t, tol=tol, seed=seed, diag=d, spmm=spmm)
+    PD, th_d, theta, Pt = variant_d(H, n_t, m_trunc=m_trunc, tol=tol, seed=seed, diag=d,
+                                    spmm=spmm)
     F = np.zeros((n, N_IN))
     F[:, 0] = (d - d.mean()) / d.std()
     F[:, 1:17] = sector_encoding(n, R)
@@ -197,8 +202,12 @@ def _layers(params: np.ndarray, act: str):
     return W1, b1, W2, b2, W3, b3, W4, b4
 
 
+SKIP = 18   # first P_D amplitude among the features
+
+
 def forward(params: np.ndarray, F: np.ndarray, act: str = "f64"):
-    """Activations [F, h1, h2, h3] and the output [rows][10].  act="bf16"
+    """Activations [F, h1, h2, h3] and the output [rows][10] = the P_D
+    amplitudes F[:, 18:28] plus the layers' correction.  act="bf16"
     evaluates the network the way the matrix-core kernels do: weights and
     hidden activations rounded to bfloat16, so every ReLU decision is taken on
     the same values; the arithmetic itself stays float64."""
@@ -207,7 +216,7 @@ def forward(params: np.ndarray, F: np.ndarray, act: str = "f64"):
     h1 = rnd(np.maximum(F @ W1.T + b1, 0.0))
     h2 = rnd(np.maximum(h1 @ W2.T + b2, 0.0))
     h3 = rnd(np.maximum(h2 @ W3.T + b3, 0.0))
-    return [F, h1, h2, h3], h3 @ W4.T + b4
+    return [F, h1, h2, h3], h3 @ W4.T + b4 + F[:, SKIP:SKIP + N_OUT]
 
 
 def loss_and_grad(params: np.ndarray, F: np.ndarray, T: np.ndarray, act: str = "f64"):
@@ -248,23 +257,39 @@ def rr_sum(H, P: np.ndarray, k: int, spmm=_spmm) -> float:
     return float(np.sum(th))
 
 
-def choose_pivot(H, P_learn: np.ndarray, P_boot: np.ndarray, k: int, spmm=_spmm):
-    """(pivot, used_fallback, reason, (sum_learn, sum_boot))."""
+def choose_pivot(H, P_learn: np.ndarray, P_boot: np.ndarray, k: int, P_D: np.ndarray = None,
+                 theta_d: np.ndarray = None, spmm=_spmm):
+    """The selection of the learned proposer: of the learned block, P_D and
+    the bootstrap block, the one whose k lowest Rayleigh-Ritz values sum
+    lowest (the learned block only if it is finite and its Gram matrix is
+    safely positive definite; ties to the bootstrap block, then P_D).
+    P_D's sum is that of its own Ritz values theta_d (its columns are Ritz
+    vectors, so H is diagonal on their span).  Without P_D the choice is
+    between the learned and the bootstrap block.
+    Returns (pivot, choice, reason, (sum_learn, sum_boot, sum_pd)) with
+    choice "learned", "bootstrap" or "p_d"."""
+    b = P_boot.shape[1]
     sb = rr_sum(H, P_boot, k, spmm=spmm)
+    sd = float(np.sum(theta_d[:min(k, b)])) if P_D is not None else np.inf
+
+    def fallback(reason, sl):
+        if sd < sb:
+            return P_D[:, :b], "p_d", reason, (sl, sb, sd)
+        return P_boot, "bootstrap", reason, (sl, sb, sd)
+
     if not np.all(np.isfinite(P_learn)):
-        return P_boot, True, "nonfinite", (np.nan, sb)
+        return fallback("nonfinite", np.nan)
     G = P_learn.T @ P_learn
-    b = G.shape[0]
     gmax = float(np.max(np.diag(G)))
     L = np.zeros_like(G)
     for j in range(b):   # Cholesky G = L L^T, checking every squared pivot
         piv = G[j, j] - L[j, :j] @ L[j, :j]
         if not piv > 1e-8 * gmax:
-            return P_boot, True, "cholesky", (np.nan, sb)
+            return fallback("cholesky", np.nan)
         L[j, j] = np.sqrt(piv)
         for i in range(j + 1, b):
             L[i, j] = (G[i, j] - L[i, :j] @ L[j, :j]) / L[j, j]
     sl = rr_sum(H, P_learn, k, spmm=spmm)
-    if not sl < sb:
-        return P_boot, True, "rayleigh-ritz", (sl, sb)
-    return P_learn, False, "learned", (sl, sb)
+    if sl < sb and sl < sd:
+        return P_learn, "learned", "learned", (sl, sb, sd)
+    return fallback("rayleigh-ritz", sl)

@@ -50,7 +50,8 @@ class _Opts(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("defl_tau", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("spmm_plan", ctypes.c_void_p), ("restart_keep", ctypes.c_int32),
-                ("max_restarts", ctypes.c_int32), ("fault_block", ctypes.c_int32)]
+                ("max_restarts", ctypes.c_int32), ("fault_block", ctypes.c_int32),
+                ("feature_vectors", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Plan(ctypes.Structure):
@@ -222,11 +223,11 @@ class DeviceCSR:
 
 
 def _opts(m_max, basis_dtype, check_every, seed, defl_tau, flags=0, plan=None, restart_keep=0,
-          fault_block=0, max_restarts=0):
+          fault_block=0, max_restarts=0, feature_vectors=0):
     return _Opts(int(m_max), int(basis_dtype), int(check_every), int(flags), float(defl_tau),
                  int(seed) & (2**64 - 1),
                  ctypes.cast(ctypes.pointer(plan.c), ctypes.c_void_p) if plan is not None else None,
-                 int(restart_keep), int(max_restarts), int(fault_block))
+                 int(restart_keep), int(max_restarts), int(fault_block), int(feature_vectors), 0)
 
 
 class SpmmPlan:
@@ -471,7 +472,7 @@ def _ws(nbytes, device):
 
 def pivot_features(H: DeviceCSR, n_trunc: int, sector_size: int, tol: float, *, m_max: int = 200,
                    seed: int = 0, basis_dtype=None, want_f32: bool = False,
-                   restart_keep: int = 0):
+                   restart_keep: int = 0, feature_vectors: int = 0):
     """Per-row features (bf16 bit patterns as int16, n x 28), optionally their
     float32 values, P_D, the plain bootstrap block of 10 and P_D's Ritz values."""
     torch = _torch()
@@ -488,7 +489,8 @@ def pivot_features(H: DeviceCSR, n_trunc: int, sector_size: int, tol: float, *, 
     PB = torch.empty((H.n, MLP_OUT), dtype=torch.float64, device=dev)
     th = np.zeros(MLP_OUT)
     st = _Stats()
-    o = _opts(m_max, basis_dtype, 0, seed, 1e-12, restart_keep=restart_keep)
+    o = _opts(m_max, basis_dtype, 0, seed, 1e-12, restart_keep=restart_keep,
+              feature_vectors=feature_vectors)
     _check(lib.bbl_pivot_features(ctypes.byref(Hc), n_trunc, sector_size, tol, _ptr(ws),
                                   ws.numel(), ctypes.byref(o), _ptr(F), _ptr(F32), _ptr(PD),
                                   _ptr(PB), th.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st),
@@ -567,7 +569,7 @@ class MlpTrainer:
 
 def learned_pivot(H: DeviceCSR, params, n_trunc: int, sector_size: int, nvec: int, k: int,
                   tol: float, *, m_max: int = 200, seed: int = 0, basis_dtype=None,
-                  restart_keep: int = 0):
+                  restart_keep: int = 0, feature_vectors: int = 0):
     """(pivot n x nvec float64, info dict with used_fallback and rr_sums)."""
     torch = _torch()
     lib = load_library()
@@ -579,11 +581,13 @@ def learned_pivot(H: DeviceCSR, params, n_trunc: int, sector_size: int, nvec: in
                                                   basis_dtype, _stream()), dev)
     P = torch.empty((H.n, nvec), dtype=torch.float64, device=dev)
     fb = ctypes.c_int32(0)
-    sums = np.zeros(2)
+    sums = np.zeros(3)
     st = _Stats()
-    o = _opts(m_max, basis_dtype, 0, seed, 1e-12, restart_keep=restart_keep)
+    o = _opts(m_max, basis_dtype, 0, seed, 1e-12, restart_keep=restart_keep,
+              feature_vectors=feature_vectors)
     _check(lib.bbl_learned_pivot(ctypes.byref(Hc), _ptr(params), n_trunc, sector_size, nvec, k,
                                  tol, _ptr(ws), ws.numel(), ctypes.byref(o), _ptr(P),
                                  ctypes.byref(fb), sums.ctypes.data_as(ctypes.c_void_p),
                                  ctypes.byref(st), _stream()))
-    return P, {"used_fallback": bool(fb.value), "rr_sums": sums, "stats": st.as_dict()}
+    return P, {"used_fallback": fb.value != 0, "choice": ("learned", "bootstrap", "p_d")[fb.value],
+               "rr_sums": sums, "stats": st.as_dict()}

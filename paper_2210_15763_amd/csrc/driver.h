@@ -20,6 +20,7 @@ struct Opts {
   int restart_keep = 0;  // thick restart: Ritz vectors kept (0 = off)
   int max_restarts = 100;
   int fault_block = 0;   // testing: host-forced breakdown + redo (0 = off)
+  int feature_vectors = 0;  // learned pivot: truncated eigenvectors of P_D (0 = 20)
 };
 
 Opts read_opts(const bbl_opts *o, int val_dtype);

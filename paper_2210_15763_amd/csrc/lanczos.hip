@@ -51,6 +51,10 @@ constexpr uint32_t kTagDeflation = 7;
 constexpr int kHn2Slot = 200;          // dres slot: max |A_jj| seen so far (<= ||H||)
 constexpr int kHn2Snap = 202;          // dres slots 202..205: kHn2Slot at the start of block J (J % 4)
 constexpr int kBreakSnap = 128;        // ints 128..131: the breakdown flag at the start of block J (J % 4)
+// chk (256 doubles): [0, 2k] a check's Ritz values, estimates and ||T||_est
+// (k <= 32: up to index 64); [128, 194) a restart's eigensolve results;
+// kChkFlag: the breakdown flag as of the check's launch (one int)
+constexpr int kChkFlag = 240;
 
 size_t dsize(int dt) { return dt == BBL_F32 ? 4 : 8; }
 
@@ -426,8 +430,8 @@ struct Solver {
 
   // A check of the first nblk blocks: the band eigensolve on the check
   // stream once the recurrence has produced B_{nblk-1}.  chk[0..2kk] receives
-  // the Ritz values, residual estimates and ||T||_est, chk[64] (as int) the
-  // QR breakdown flag as of this point; both are copied to pinned memory.
+  // the Ritz values, residual estimates and ||T||_est, chk[kChkFlag] (as int)
+  // the QR breakdown flag as of this point; both are copied to pinned memory.
   // A check due at the end of a block is armed there and launched right
   // after the next block's SpMM is queued, so that it runs beside that block's
   // tall-skinny products instead of holding compute units the SpMM needs (a
@@ -446,7 +450,7 @@ struct Solver {
   }
 
   void launch_check(CheckStream &cq, int nblk, int kk) {
-    int *flag_copy = reinterpret_cast<int *>(chk + 64);
+    int *flag_copy = reinterpret_cast<int *>(chk + kChkFlag);
     BBL_HIP(hipMemcpyAsync(flag_copy, breakdown, sizeof(int), hipMemcpyDeviceToDevice, s));
     BBL_HIP(hipEventRecord(cq.ready, s));
     BBL_HIP(hipStreamWaitEvent(cq.cs, cq.ready, 0));
@@ -788,6 +792,7 @@ Opts read_opts(const bbl_opts *o, int val_dtype) {
     r.restart_keep = o->restart_keep;
     r.max_restarts = o->max_restarts > 0 ? o->max_restarts : r.max_restarts;
     r.fault_block = o->fault_block;
+    r.feature_vectors = o->feature_vectors;
     if (o->defl_tau > 0) r.tau = o->defl_tau;
     r.seed = o->seed;
   }

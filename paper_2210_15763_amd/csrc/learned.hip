@@ -9,9 +9,12 @@
 //             row of P_D -- the 10 lowest Ritz vectors of H on the one-hop
 //             extension of the 20 lowest truncated eigenvectors
 //             (y_ia = (H P)_ia / (theta_a - H_ii) outside the truncation);
-//   network   28 -> 128 -> 128 -> 128 -> 10 with ReLU, BF16 operands on
-//             v_mfma_f32_16x16x16bf16_1k, FP32 accumulation, FP32 master
-//             weights; one fused kernel for inference, one for the gradient;
+//   network   residual form: the 10 P_D amplitudes of the row plus a
+//             correction by 28 -> 128 -> 128 -> 128 -> 10 with ReLU, BF16
+//             operands on v_mfma_f32_16x16x16bf16_1k, FP32 accumulation, FP32
+//             master weights (output layer initialised to zero, so training
+//             starts from P_D itself); one fused kernel for inference, one for
+//             the gradient;
 //   training  Adam on FP32 master weights; targets are converged eigenvectors
 //             aligned to P_D by orthogonal Procrustes and scaled by sqrt(n);
 //   fallback  the plain bootstrap block replaces the learned one when the
@@ -41,7 +44,11 @@ constexpr int oW1 = 0, oB1 = oW1 + kHid * kIn, oW2 = oB1 + kHid, oB2 = oW2 + kHi
               oW3 = oB2 + kHid, oB3 = oW3 + kHid * kHid, oW4 = oB3 + kHid,
               oB4 = oW4 + kOut * kHid;
 static_assert(oB4 + kOut == kParams, "parameter layout");
-constexpr int kTrunc = 2 * kOut;      // truncated eigenvectors extended one hop
+constexpr int kTrunc = 2 * kOut;      // default count of truncated eigenvectors extended one hop
+// truncated eigenvectors of the feature block: opts->feature_vectors, else 2 * 10
+inline int trunc_vectors(const Opts &o) { return o.feature_vectors > 0 ? o.feature_vectors : kTrunc; }
+constexpr int kTruncMax = kMaxBlock;  // the workspaces hold this many
+constexpr int kSkip = 18;             // first P_D amplitude among the inputs (residual form)
 constexpr int SA = kInPad + 8;        // LDS row strides (bf16 elements), padded
 constexpr int SH = kHid + 8;          //   against bank conflicts
 constexpr int SO = kOutPad + 8;
@@ -192,8 +199,9 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ p
     __syncthreads();
     layer_fwd<kFwdRows, kHid, kHid>(sB, SH, w.w3, SH, w.b3, sA, SH);
     __syncthreads();
+    // residual form: the P_D amplitudes (inputs 18..27) plus the network
     layer_out<kFwdRows>(sA, w, [&](int r, int c, float v) {
-      if (c < kOut && r0 + r < rows) out[(r0 + r) * kOut + c] = v;
+      if (c < kOut && r0 + r < rows) out[(r0 + r) * kOut + c] = v + bf2f(sX[r * SA + kSkip + c]);
     });
   }
 }
@@ -317,7 +325,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ para
       const int64_t gr = r0 + r;
       float d = 0.f;
       if (c < kOut && gr < rows) {
-        const float diff = v - T[(idx ? idx[gr] : gr) * kOut + c];
+        const float diff = v + bf2f(s0[r * SA + kSkip + c]) - T[(idx ? idx[gr] : gr) * kOut + c];
         lsum += (double)diff * diff;
         d = scale * diff;
       }
@@ -383,11 +391,12 @@ __global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__re
 __global__ void k_mlp_init(float *__restrict__ p, uint64_t key) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= kParams) return;
+  // hidden layers He-uniform; the output layer (and every bias) zero, so an
+  // untrained network returns the P_D amplitudes unchanged
   int fan = 0;
   if (i < oB1) fan = kIn;
   else if (i >= oW2 && i < oB2) fan = kHid;
   else if (i >= oW3 && i < oB3) fan = kHid;
-  else if (i >= oW4 && i < oB4) fan = kHid;
   if (fan == 0) {
     p[i] = 0.f;
     return;
@@ -729,16 +738,24 @@ struct FeatBufs {
   size_t trunc_bytes;
 };
 
+int check_trunc_vectors(const Opts &o, int64_t n_trunc, int64_t n) {
+  const int mt = trunc_vectors(o);
+  BBL_REQUIRE(mt >= kOut && mt <= kTruncMax, "feature_vectors must be 0 or in 10..32");
+  BBL_REQUIRE(n_trunc >= mt && n_trunc <= n, "n_trunc must be in feature_vectors..n");
+  return mt;
+}
+
 size_t feature_bytes(const bbl_csr &H, int64_t n_t, const Opts &o, hipStream_t s, FeatBufs *fb,
                      void *ws, size_t ws_bytes) {
   const int64_t n = H.n;
-  const size_t tb = truncated_ws_bytes(H, n_t, kOut, kTrunc, o, s);
+  const int mt = kTruncMax;  // room for any feature_vectors setting
+  const size_t tb = truncated_ws_bytes(H, n_t, kOut, mt, o, s);
   Arena a(ws, ws ? ws_bytes : 0);
   if (!ws) a.base = nullptr;
   FeatBufs b{};
-  b.Ppad = a.take<double>((size_t)n * kTrunc);
-  b.HP = a.take<double>((size_t)n * kTrunc);
-  b.Y = a.take<double>((size_t)n * kTrunc);
+  b.Ppad = a.take<double>((size_t)n * mt);
+  b.HP = a.take<double>((size_t)n * mt);
+  b.Y = a.take<double>((size_t)n * mt);
   b.PD = a.take<double>((size_t)n * kOut);
   b.d = a.take<double>((size_t)n);
   b.small = a.take<double>(4096);
@@ -756,14 +773,15 @@ void build_features(const bbl_csr &H, int64_t n_t, int64_t R, double tol, const 
                     const FeatBufs &b, bf16 *F, float *F32, double *theta_d, bbl_stats *stats,
                     hipStream_t s) {
   const int64_t n = H.n;
-  std::vector<double> th(kTrunc);
-  const int st = truncated_solve(H, n_t, kOut, kTrunc, tol, o, b.trunc, b.trunc_bytes, b.Ppad,
+  const int mt = trunc_vectors(o);
+  std::vector<double> th(mt);
+  const int st = truncated_solve(H, n_t, kOut, mt, tol, o, b.trunc, b.trunc_bytes, b.Ppad,
                                  th.data(), stats, s);
   if (st != BBL_OK && st != BBL_E_NOT_CONVERGED)
     throw Error{st, "truncated solve failed: " + std::string(bbl_last_error())};
   // the truncated solve's products, then H P and H Y at width 2 * 10
-  if (stats) stats->pivot_spmm_calls = stats->spmm_calls + 2 * (kTrunc / kOut);
-  if (n > n_t) launch_fill(b.Ppad + (size_t)n_t * kTrunc, (n - n_t) * kTrunc, 0.0, s);
+  if (stats) stats->pivot_spmm_calls = stats->spmm_calls + 2 * (mt / kOut);
+  if (n > n_t) launch_fill(b.Ppad + (size_t)n_t * mt, (n - n_t) * mt, 0.0, s);
   double *dtheta = b.small;           // [0, 32): truncated eigenvalues
   double *G = b.small + 64;           // [64, 64 + 1024)
   double *K = b.small + 64 + 1024;    // [1088, 2112)
@@ -771,21 +789,21 @@ void build_features(const bbl_csr &H, int64_t n_t, int64_t R, double tol, const 
   double *thd = b.small + 3136;       // [3136, 3168)
   double *mean = b.small + 3200, *stats2 = b.small + 3200;  // mean, std
   double *spart = b.small + 3264;     // 256 partials
-  BBL_HIP(hipMemcpyAsync(dtheta, th.data(), kTrunc * sizeof(double), hipMemcpyHostToDevice, s));
+  BBL_HIP(hipMemcpyAsync(dtheta, th.data(), mt * sizeof(double), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_diag, dim3(grid_for(n)), dim3(256), 0, s, n, H.row_ptr, H.col, H.val,
                      H.val_dtype == BBL_F32 ? 1 : 0, b.d);
-  launch_spmm(H, b.Ppad, BBL_F64, b.HP, BBL_F64, kTrunc, s);
-  hipLaunchKernelGGL(k_extend, dim3(grid_for(n * kTrunc)), dim3(256), 0, s, n, n_t, kTrunc,
+  launch_spmm(H, b.Ppad, BBL_F64, b.HP, BBL_F64, mt, s);
+  hipLaunchKernelGGL(k_extend, dim3(grid_for(n * mt)), dim3(256), 0, s, n, n_t, mt,
                      b.Ppad, b.HP, dtheta, b.d, b.Y);
-  launch_spmm(H, b.Y, BBL_F64, b.HP, BBL_F64, kTrunc, s);  // HP <- H Y
-  gram64(n, b.Y, kTrunc, b.Y, kTrunc, b.partial, G, s);
-  gram64(n, b.Y, kTrunc, b.HP, kTrunc, b.partial, K, s);
-  hipLaunchKernelGGL(k_rr_small, dim3(1), dim3(64), 0, s, G, K, kTrunc, kOut, thd, C, b.flag);
-  launch_update(n, b.Y, BBL_F64, kTrunc, 1, (int64_t)n * kTrunc, C, kOut, 1.0, nullptr, BBL_F64,
+  launch_spmm(H, b.Y, BBL_F64, b.HP, BBL_F64, mt, s);  // HP <- H Y
+  gram64(n, b.Y, mt, b.Y, mt, b.partial, G, s);
+  gram64(n, b.Y, mt, b.HP, mt, b.partial, K, s);
+  hipLaunchKernelGGL(k_rr_small, dim3(1), dim3(64), 0, s, G, K, mt, kOut, thd, C, b.flag);
+  launch_update(n, b.Y, BBL_F64, mt, 1, (int64_t)n * mt, C, kOut, 1.0, nullptr, BBL_F64,
                 0.0, b.PD, BBL_F64, s);
   launch_normalize_columns(n, kOut, b.PD, b.partial, kMaxPartialRows, s);
   int flag = 0;
-  std::vector<double> thh(kTrunc);
+  std::vector<double> thh(mt);
   BBL_HIP(hipMemcpyAsync(&flag, b.flag, sizeof(int), hipMemcpyDeviceToHost, s));
   BBL_HIP(hipMemcpyAsync(thh.data(), thd, kOut * sizeof(double), hipMemcpyDeviceToHost, s));
   BBL_HIP(hipStreamSynchronize(s));
@@ -868,12 +886,12 @@ int bbl_pivot_features(const bbl_csr *H, int64_t n_trunc, int64_t sector_size, d
   return guarded([&] {
     validate_csr(H);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    BBL_REQUIRE(n_trunc >= kTrunc && n_trunc <= H->n, "n_trunc must be in 20..n");
     BBL_REQUIRE(sector_size >= 1, "sector_size must be >= 1");
     BBL_REQUIRE(feats && ws, "feats/workspace is NULL");
     BBL_REQUIRE(tol > 0.0, "tol must be > 0");
     const auto t0 = std::chrono::steady_clock::now();
     const Opts o = read_opts(opts, H->val_dtype);
+    const int mt = check_trunc_vectors(o, n_trunc, H->n);
     FeatBufs b{};
     const size_t need = feature_bytes(*H, n_trunc, o, s, &b, ws, ws_bytes);
     if (ws_bytes < need) throw Error{BBL_E_NOMEM, "features workspace too small"};
@@ -883,7 +901,7 @@ int bbl_pivot_features(const bbl_csr *H, int64_t n_trunc, int64_t sector_size, d
       BBL_HIP(hipMemcpyAsync(p_d, b.PD, (size_t)n * kOut * 8, hipMemcpyDeviceToDevice, s));
     if (p_boot)
       hipLaunchKernelGGL((k_copy_cols<double, double>), dim3(grid_for(n * kOut)), dim3(256), 0, s,
-                         n, kOut, b.Ppad, kTrunc, p_boot, kOut);
+                         n, kOut, b.Ppad, mt, p_boot, kOut);
     BBL_HIP(hipStreamSynchronize(s));
     if (stats)
       stats->t_pivot_ms =
@@ -1026,10 +1044,10 @@ int bbl_learned_pivot(const bbl_csr *H, const float *params, int64_t n_trunc, in
     BBL_REQUIRE(params && pivot && ws, "NULL argument");
     BBL_REQUIRE(nvec >= 1 && nvec <= kOut, "nvec must be in 1..10");
     BBL_REQUIRE(k >= 1, "k must be >= 1");
-    BBL_REQUIRE(n_trunc >= kTrunc && n_trunc <= H->n, "n_trunc must be in 20..n");
     BBL_REQUIRE(sector_size >= 1, "sector_size must be >= 1");
     const auto t0 = std::chrono::steady_clock::now();
     const Opts o = read_opts(opts, H->val_dtype);
+    const int mt = check_trunc_vectors(o, n_trunc, H->n);
     const int64_t n = H->n;
     FeatBufs b{};
     const size_t fb = feature_bytes(*H, n_trunc, o, s, &b, ws, ws_bytes);
@@ -1040,12 +1058,13 @@ int bbl_learned_pivot(const bbl_csr *H, const float *params, int64_t n_trunc, in
     double *Pb = a.take<double>((size_t)n * nvec);
     double *HPx = a.take<double>((size_t)n * nvec);
     double *chk = a.take<double>(512);
-    build_features(*H, n_trunc, sector_size, tol, o, b, F, nullptr, nullptr, stats, s);
+    double thd[kOut];
+    build_features(*H, n_trunc, sector_size, tol, o, b, F, nullptr, thd, stats, s);
     mlp_forward(params, F, n, out, s);
     hipLaunchKernelGGL((k_copy_cols<float, double>), dim3(grid_for(n * nvec)), dim3(256), 0, s, n,
                        nvec, out, kOut, Pl, nvec);
     hipLaunchKernelGGL((k_copy_cols<double, double>), dim3(grid_for(n * nvec)), dim3(256), 0, s,
-                       n, nvec, b.Ppad, kTrunc, Pb, nvec);
+                       n, nvec, b.Ppad, mt, Pb, nvec);
     // Rayleigh-Ritz checks of both blocks: chk[0..3) learned, chk[3..6) bootstrap
     double *G = chk + 8, *K = chk + 8 + 128;
     const double *blocks[2] = {Pl, Pb};
@@ -1058,18 +1077,31 @@ int bbl_learned_pivot(const bbl_csr *H, const float *params, int64_t n_trunc, in
     double h[6];
     BBL_HIP(hipMemcpyAsync(h, chk, sizeof(h), hipMemcpyDeviceToHost, s));
     BBL_HIP(hipStreamSynchronize(s));
-    const bool fallback = h[0] != 0.0 || h[1] != 0.0 || !(h[2] < h[5]);
-    BBL_HIP(hipMemcpyAsync(pivot, fallback ? Pb : Pl, (size_t)n * nvec * 8,
-                           hipMemcpyDeviceToDevice, s));
+    // P_D's columns are Ritz vectors of H: on their span H is diagonal, so the
+    // sum of its k lowest Rayleigh-Ritz values is the sum of its own
+    double sd = 0.0;
+    for (int i = 0; i < std::min(k, nvec); ++i) sd += thd[i];
+    const bool learn_ok = h[0] == 0.0 && h[1] == 0.0;
+    int choice;  // 0 learned, 1 bootstrap, 2 P_D
+    if (learn_ok && h[2] < h[5] && h[2] < sd) choice = 0;
+    else if (sd < h[5]) choice = 2;
+    else choice = 1;
+    if (choice == 2)
+      hipLaunchKernelGGL((k_copy_cols<double, double>), dim3(grid_for(n * nvec)), dim3(256), 0, s,
+                         n, nvec, b.PD, kOut, pivot, nvec);
+    else
+      BBL_HIP(hipMemcpyAsync(pivot, choice == 1 ? Pb : Pl, (size_t)n * nvec * 8,
+                             hipMemcpyDeviceToDevice, s));
     BBL_HIP(hipStreamSynchronize(s));
-    if (used_fallback) *used_fallback = fallback ? 1 : 0;
+    if (used_fallback) *used_fallback = choice;
     if (rr_sums) {
       rr_sums[0] = h[2];
       rr_sums[1] = h[5];
+      rr_sums[2] = sd;
     }
     if (stats) {
-      stats->pivot_spmm_calls += 2;  // H P_learn and H P_boot of the fallback test
-      stats->used_fallback = fallback ? 1 : 0;
+      stats->pivot_spmm_calls += 2;  // H P_learn and H P_boot of the selection
+      stats->used_fallback = choice;
       stats->t_pivot_ms =
           std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }

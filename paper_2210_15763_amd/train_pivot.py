@@ -61,17 +61,9 @@ def generate(s: int):
 
 def identity_params(torch):
     """Parameters whose output reproduces feature columns 18..27 (sqrt(n) P_D):
-    the held-out loss of this map is what the network has to beat."""
-    W1 = np.zeros((128, 28))
-    W2 = np.zeros((128, 128))
-    W4 = np.zeros((10, 128))
-    for a in range(10):
-        W1[2 * a, 18 + a], W1[2 * a + 1, 18 + a] = 1.0, -1.0
-        W4[a, 2 * a], W4[a, 2 * a + 1] = 1.0, -1.0
-    W2[np.arange(20), np.arange(20)] = 1.0
-    p = np.concatenate([W1.ravel(), np.zeros(128), W2.ravel(), np.zeros(128), W2.ravel(),
-                        np.zeros(128), W4.ravel(), np.zeros(10)]).astype(np.float32)
-    return torch.from_numpy(p).cuda()
+    in the residual form, all zero.  The held-out loss of this map is what
+    the network has to beat."""
+    return torch.zeros(bbl.MLP_PARAMS, dtype=torch.float32, device="cuda")
 
 
 def build_instance(torch, H, m_max: int):
@@ -93,6 +85,8 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--m-max", type=int, default=200)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--data-out", default=None,
+                    help="also save the training set (features, targets) to this .npz")
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                   "weights", "pivot_mlp_sectored.npy"))
     args = ap.parse_args()

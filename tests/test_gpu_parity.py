@@ -785,3 +785,18 @@ def test_thick_restart_bootstrap_pivot_and_restart_cap(torch, bbl):
     assert ro.converged
     np.testing.assert_allclose(ro.eigvals, oracle.block_lanczos(H, Pref, 4, 1e-8, 200).eigvals,
                                rtol=1e-10)
+
+
+def test_thirty_two_wanted_pairs(torch, bbl):
+    """k = 32, the largest pair count: the check's results fill slots 0..64
+    of its result area, which must not reach the breakdown-flag copy."""
+    note("k=32 wanted pairs")
+    H = synthgen.generate(3000, 300, 12, 0.7, 21)
+    lam = np.linalg.eigvalsh(H.to_dense())
+    Hd = bbl.DeviceCSR.from_host(H, "float64")
+    r = bbl.block_lanczos(Hd, dev(torch, synthgen.gaussian_block(H.n, 8, 4)), 32, 1e-9,
+                          m_max=300)
+    assert r.converged
+    np.testing.assert_allclose(r.eigvals, lam[:32], rtol=1e-10)
+    f = bbl.pivot_features(Hd, 600, 300, 1e-9, m_max=300, feature_vectors=32)
+    assert f["stats"]["converged"] == 1

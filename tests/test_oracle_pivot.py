@@ -174,6 +174,21 @@ def test_backward_matches_central_differences():
         assert abs(fd - g[i]) <= 1e-6 * max(abs(g).max(), 1e-12), (i, fd, g[i])
 
 
+def test_zero_output_layer_returns_the_pd_amplitudes():
+    """Residual form: with W4 = 0 and b4 = 0 the network's output is exactly
+    the P_D amplitudes among its inputs (features 18..27), whatever the
+    hidden layers; a constant b4 shifts every output by that constant."""
+    rng = np.random.default_rng(12)
+    p = rng.standard_normal(op.N_PARAMS) * 0.3
+    p[36736:] = 0.0
+    F = rng.standard_normal((9, 28))
+    _, out = op.forward(p, F)
+    assert np.array_equal(out, F[:, 18:28])
+    p[38016:] = 0.25
+    _, out = op.forward(p, F)
+    np.testing.assert_allclose(out, F[:, 18:28] + 0.25, rtol=0, atol=1e-15)
+
+
 def test_round_bf16_matches_torch():
     import torch
     rng = np.random.default_rng(9)
@@ -253,10 +268,22 @@ def test_fallback_rules():
     Pb[:300] = np.linalg.eigh(Ht)[1][:, :4]
     bad = X[:, :4].copy()
     bad[3, 1] = np.nan
-    assert op.choose_pivot(H, bad, Pb, 4)[2] == "nonfinite"
+    assert op.choose_pivot(H, bad, Pb, 4)[1:3] == ("bootstrap", "nonfinite")
     dup = X[:, :4].copy()
     dup[:, 2] = dup[:, 0]
-    assert op.choose_pivot(H, dup, Pb, 4)[2] == "cholesky"
-    P, fb, why, (sl, sb) = op.choose_pivot(H, X[:, :4], Pb, 4)
-    assert not fb and why == "learned" and sl == pytest.approx(lam[:4].sum(), abs=1e-10)
-    assert op.choose_pivot(H, Pb.copy(), Pb, 4)[2] == "rayleigh-ritz"
+    assert op.choose_pivot(H, dup, Pb, 4)[1:3] == ("bootstrap", "cholesky")
+    P, choice, why, (sl, sb, sd) = op.choose_pivot(H, X[:, :4], Pb, 4)
+    assert choice == "learned" and sl == pytest.approx(lam[:4].sum(), abs=1e-10)
+    # the Courant-Fischer minimum: nothing beats the exact lowest eigenvectors
+    assert sb > lam[:4].sum() - 1e-10
+    assert op.choose_pivot(H, Pb.copy(), Pb, 4)[1:3] == ("bootstrap", "rayleigh-ritz")
+    # a P_D block of exact eigenvectors (theta_d their eigenvalues) wins over
+    # the bootstrap block, and a learned block no better than P_D loses to it
+    PD = X[:, :6]
+    P, choice, why, sums = op.choose_pivot(H, Pb.copy(), Pb, 4, PD, lam[:6])
+    assert choice == "p_d" and np.array_equal(P, PD[:, :4]) and sums[2] == lam[:4].sum()
+    near = X[:, :4] + 1e-3 * np.random.default_rng(2).standard_normal((H.n, 4))
+    assert op.choose_pivot(H, near, Pb, 4, PD, lam[:6])[1] == "p_d"
+    assert op.choose_pivot(H, bad, Pb, 4, PD, lam[:6])[1:3] == ("p_d", "nonfinite")
+    # a P_D block worse than the bootstrap one is not chosen
+    assert op.choose_pivot(H, bad, Pb, 4, PD, lam[:6] + 100.0)[1] == "bootstrap"
