@@ -356,23 +356,31 @@ def large_workload(torch, bbl, name, args):
                      dtype=torch.uint8, device="cuda")
     log("workspace %.1f GB" % (ws.numel() / 1e9))
     res = {}
+    plan = None
     for rep_i in range(max(1, args.steps)):
+        del plan
         torch.cuda.synchronize()
         t = time.perf_counter()
+        plan = None if args.plain_spmm else bbl.spmm_plan(Hd, b)
+        torch.cuda.synchronize()
+        tplan = time.perf_counter() - t
         P, pst = bbl.bootstrap_pivot(Hd, w.n_trunc, b, w.tol, m_max=w.m_max, seed=w.seed,
                                      restart_keep=keep)
         torch.cuda.synchronize()
-        tp = time.perf_counter() - t
-        log("pivot: %.2f s, truncated iters %d restarts %d converged %d" %
-            (tp, pst["iters"], pst["restarts"], pst["converged"]))
+        tp = time.perf_counter() - t - tplan
+        log("plan %.2f s (%s); pivot: %.2f s, truncated iters %d restarts %d converged %d" %
+            (tplan, "none" if plan is None else "%d sets of %d blocks, %.1f GB" %
+             (plan.c.nsets, plan.slots, plan.mem.numel() / 1e9),
+             tp, pst["iters"], pst["restarts"], pst["converged"]))
         r = bbl.block_lanczos(Hd, P, k, w.tol, m_max=w.m_max, seed=w.seed, workspace=ws,
-                              restart_keep=keep, time_phases=True)
+                              restart_keep=keep, time_phases=True, spmm_plan=plan)
         torch.cuda.synchronize()
         tts = time.perf_counter() - t
         st = r.stats
         log("solve %d: tts %.2f s iters %d restarts %d converged %s" %
             (rep_i, tts, st["iters"], st["restarts"], r.converged))
-        res = {"tts_s": tts, "pivot_s": tp, "stats": st, "pivot_stats": pst, "r": r}
+        res = {"tts_s": tts, "pivot_s": tp, "plan_s": tplan, "stats": st, "pivot_stats": pst,
+               "r": r}
     r, st = res["r"], res["stats"]
     alg = spmm_bytes(H.n, H.nnz, b, 4, 4)
     t_spmm = st["spmm_ms"] / 1e3 / max(st["spmm_timed"], 1)
@@ -399,7 +407,11 @@ def large_workload(torch, bbl, name, args):
         "resid_over_hnorm_device": [float(x) / hn for x in r.residuals],
         "resid_over_hnorm_fp64_vendor_sparse": [float(x) / hn for x in hres],
         "parlett_bound_abs": parlett_bounds(r.eigvals, hres),
-        "spmm": {"kernel": "plain CSR (k_spmm)", "alg_bytes_per_call": alg,
+        "plan_s": res["plan_s"],
+        "spmm": {"kernel": "plain CSR (k_spmm)" if plan is None else
+                 "multi-set planned (k_spmm_pipe_ms + k_spmm_rest), %d sets of %d blocks"
+                 % (plan.c.nsets, plan.slots) if plan.c.nsets else "planned (k_spmm_pipe12 + "
+                 "k_spmm_rest)", "alg_bytes_per_call": alg,
                  "ms_per_call": t_spmm * 1e3, "alg_GBps": alg / t_spmm / 1e9,
                  "frac_hbm_peak": alg / t_spmm / HBM_PEAK, "calls_timed": st["spmm_timed"]},
         "phases_ms": {f: st[f] for f in ("spmm_ms", "t_threeterm_ms", "t_reorth_ms", "t_qr_ms",
@@ -612,6 +624,8 @@ def main():
     ap.add_argument("--workload", default=WORKLOAD,
                     help="mid_n2e6 (the timed benchmark) or large_n2e7 / stress_n1e8 (one "
                          "thick-restarted solve, reported on its own JSON line)")
+    ap.add_argument("--plain-spmm", action="store_true",
+                    help="large workloads: the plain CSR kernel instead of the planned one")
     ap.add_argument("--restart-keep", type=int, default=32,
                     help="Ritz vectors kept by thick restart (large workloads)")
     ap.add_argument("--no-fp64-arm", action="store_true",

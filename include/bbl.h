@@ -123,6 +123,26 @@ typedef struct {
    * two 32-bit words (low, high)}; their entries are the row's last. */
   const int64_t *rgroup;  /* [groups + 1] */
   const int32_t *rlist;   /* [n][4] */
+  /* Multi-set layout (nsets > 0; the fields from n_local to brow are then
+   * NULL): when fewer than three column blocks fit in LDS per set (e.g.
+   * 2000-row groups at 8 float32 columns) or the entries need 64-bit
+   * offsets, the group's busiest blocks form nsets sets of `slots` blocks
+   * (blocks: [groups][nsets * slots]), staged in LDS one set after the other.
+   * Each set keeps a dense copy of its entries (16-bit LDS index within the
+   * set, value; the copies lie set after set, group after group, rows in
+   * order); the entries outside every set are kept compactly (global
+   * column, value) and listed per row in rgroup / rlist, whose first-entry
+   * field indexes rcol / rval.  The plan takes 8 (nnz + 16) bytes for the
+   * entries, about as much as H's own arrays, plus per-row descriptors. */
+  int32_t nsets;
+  int32_t reserved;
+  const int64_t *sgroup;  /* [nsets][groups + 1] first copy entry of each group's set-s entries */
+  const int32_t *srow;    /* [nsets][n][2] first and end copy entry of each row, relative to
+                             its group's first rounded down to a multiple of 8 */
+  const uint16_t *slcol;  /* LDS index within its set of every copied entry */
+  const void *sval;       /* its value (float32) */
+  const int32_t *rcol;    /* global column of every entry outside the sets */
+  const void *rval;       /* its value */
 } bbl_spmm_plan;
 
 /* Solver options; a NULL pointer selects the defaults shown. */

@@ -65,7 +65,11 @@ class _Plan(ctypes.Structure):
                 ("alcol", ctypes.c_void_p), ("aval", ctypes.c_void_p),
                 ("bgroup", ctypes.c_void_p), ("brow", ctypes.c_void_p),
                 ("blcol", ctypes.c_void_p), ("bval", ctypes.c_void_p),
-                ("rgroup", ctypes.c_void_p), ("rlist", ctypes.c_void_p)]
+                ("rgroup", ctypes.c_void_p), ("rlist", ctypes.c_void_p),
+                ("nsets", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sgroup", ctypes.c_void_p), ("srow", ctypes.c_void_p),
+                ("slcol", ctypes.c_void_p), ("sval", ctypes.c_void_p),
+                ("rcol", ctypes.c_void_p), ("rval", ctypes.c_void_p)]
 
 
 class _Stats(ctypes.Structure):

@@ -56,6 +56,16 @@ inline int gram_max_partials(size_t cap_doubles, int M, int ny) {
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
+// The dispatch packet holds a launch's size per dimension in work-items
+// (grid x workgroup) as a 32-bit count.  Launches whose grid grows with n stay
+// at or below this many work-items: their kernels stride over the rows, or
+// the rows are split over several launches.
+constexpr int64_t kMaxLaunchItems = (int64_t)1 << 31;
+inline unsigned capped_grid(int64_t blocks, int threads) {
+  const int64_t cap = kMaxLaunchItems / threads;
+  return (unsigned)(blocks < 1 ? 1 : blocks < cap ? blocks : cap);
+}
+
 // ---------------------------------------------------------- kernel launchers
 // SpMM: Y = H X (templated on value/vector/accumulator types inside).
 void launch_spmm(const bbl_csr &H, const void *X, int xdtype, void *Y, int ydtype, int nvec,

@@ -1036,7 +1036,10 @@ int bbl_spmm_planned(const bbl_spmm_plan *plan, const void *V, void *W, void *st
     BBL_REQUIRE(plan && V && W, "NULL argument");
     BBL_REQUIRE(V != W, "V and W must not overlap");
     BBL_REQUIRE(plan->block_rows > 0 && plan->slots >= 1 && plan->slots <= kPlanMaxSlots &&
-                    plan->blocks && plan->n_local && plan->col && plan->row_ptr,
+                    plan->blocks && plan->row_ptr &&
+                    (plan->nsets > 0 ? (plan->sgroup && plan->srow && plan->slcol && plan->sval &&
+                                        plan->rlist && plan->rgroup)
+                                     : (plan->n_local && plan->col)),
                 "plan is not initialised");
     launch_spmm_planned(*plan, V, W, static_cast<hipStream_t>(stream));
     return (int)BBL_OK;

@@ -430,18 +430,19 @@ __global__ void k_sample(int64_t batch, int64_t total, uint64_t key, uint32_t st
 // ------------------------------------------------------------- features
 __global__ void k_diag(int64_t n, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                        const void *__restrict__ val, int f32, double *__restrict__ d) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int64_t lo = rp[i], hi = rp[i + 1];
-  double v = 0.0;
-  while (lo < hi) {  // first position with col >= i
-    const int64_t mid = (lo + hi) >> 1;
-    if (col[mid] < i) lo = mid + 1;
-    else hi = mid;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = rp[i], hi = rp[i + 1];
+    double v = 0.0;
+    while (lo < hi) {  // first position with col >= i
+      const int64_t mid = (lo + hi) >> 1;
+      if (col[mid] < i) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < rp[i + 1] && col[lo] == i)
+      v = f32 ? (double)static_cast<const float *>(val)[lo] : static_cast<const double *>(val)[lo];
+    d[i] = v;
   }
-  if (lo < rp[i + 1] && col[lo] == i)
-    v = f32 ? (double)static_cast<const float *>(val)[lo] : static_cast<const double *>(val)[lo];
-  d[i] = v;
 }
 
 // mode 0: partial sums of d; mode 1: of (d - mean)^2.  Contiguous row ranges
@@ -481,56 +482,59 @@ __global__ void k_stat_final(const double *__restrict__ partial, int P, int64_t 
 __global__ void k_extend(int64_t n, int64_t n_t, int m, const double *__restrict__ P,
                          const double *__restrict__ HP, const double *__restrict__ theta,
                          const double *__restrict__ d, double *__restrict__ Y) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n * m) return;
-  const int64_t i = idx / m;
-  const int a = (int)(idx - i * m);
-  if (i < n_t) {
-    Y[idx] = P[idx];
-    return;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n * m;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / m;
+    const int a = (int)(idx - i * m);
+    if (i < n_t) {
+      Y[idx] = P[idx];
+      continue;
+    }
+    double den = theta[a] - d[i];
+    if (fabs(den) < 1.0) den = den < 0.0 ? -1.0 : 1.0;
+    Y[idx] = HP[idx] / den;
   }
-  double den = theta[a] - d[i];
-  if (fabs(den) < 1.0) den = den < 0.0 ? -1.0 : 1.0;
-  Y[idx] = HP[idx] / den;
 }
 
 __global__ void k_features(int64_t n, int64_t R, const int64_t *__restrict__ rp, double zbar,
                            const double *__restrict__ d, const double *__restrict__ stats,
                            const double *__restrict__ PD, bf16 *__restrict__ F,
                            float *__restrict__ F32) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float f[kIn];
-  f[0] = (float)((d[i] - stats[0]) / stats[1]);
-  const int64_t S = (n + R - 1) / R;
-  const double base = 6.283185307179586476925 * (double)(i / R) / (double)S;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float f[kIn];
+    f[0] = (float)((d[i] - stats[0]) / stats[1]);
+    const int64_t S = (n + R - 1) / R;
+    const double base = 6.283185307179586476925 * (double)(i / R) / (double)S;
 #pragma unroll
-  for (int q = 1; q <= 8; ++q) {
-    double sn, cs;
-    sincos(base * q, &sn, &cs);
-    f[2 * q - 1] = (float)sn;
-    f[2 * q] = (float)cs;
+    for (int q = 1; q <= 8; ++q) {
+      double sn, cs;
+      sincos(base * q, &sn, &cs);
+      f[2 * q - 1] = (float)sn;
+      f[2 * q] = (float)cs;
+    }
+    f[17] = (float)((double)(rp[i + 1] - rp[i]) / zbar);
+    const double sq = sqrt((double)n);
+#pragma unroll
+    for (int a = 0; a < kOut; ++a) f[18 + a] = (float)(sq * PD[i * kOut + a]);
+#pragma unroll
+    for (int c = 0; c < kIn; ++c) F[i * kIn + c] = f2bf(f[c]);
+    if (F32)
+#pragma unroll
+      for (int c = 0; c < kIn; ++c) F32[i * kIn + c] = f[c];
   }
-  f[17] = (float)((double)(rp[i + 1] - rp[i]) / zbar);
-  const double sq = sqrt((double)n);
-#pragma unroll
-  for (int a = 0; a < kOut; ++a) f[18 + a] = (float)(sq * PD[i * kOut + a]);
-#pragma unroll
-  for (int c = 0; c < kIn; ++c) F[i * kIn + c] = f2bf(f[c]);
-  if (F32)
-#pragma unroll
-    for (int c = 0; c < kIn; ++c) F32[i * kIn + c] = f[c];
 }
 
 // dst[i][a] = src[i][a] for a < mc (src row stride ms, dst row stride md)
 template <typename S, typename D>
 __global__ void k_copy_cols(int64_t n, int mc, const S *__restrict__ src, int ms,
                             D *__restrict__ dst, int md) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n * mc) return;
-  const int64_t i = idx / mc;
-  const int a = (int)(idx - i * mc);
-  dst[i * md + a] = (D)src[i * ms + a];
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n * mc;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / mc;
+    const int a = (int)(idx - i * mc);
+    dst[i * md + a] = (D)src[i * ms + a];
+  }
 }
 
 // Rayleigh-Ritz on span(Y) from G = Y^T Y and K = Y^T H Y (m <= 32): whitening
@@ -699,8 +703,9 @@ __global__ __launch_bounds__(64) void k_polar(const double *__restrict__ Min, in
 }
 
 // ------------------------------------------------------------- host side
+// kernels launched on grid_for(n ...) stride over their work
 unsigned grid_for(int64_t work, int threads = 256) {
-  return (unsigned)std::max<int64_t>(1, ceil_div(work, threads));
+  return capped_grid(ceil_div(work, threads), threads);
 }
 
 // Workspace carve-up helper.

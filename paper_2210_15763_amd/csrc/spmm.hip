@@ -341,26 +341,34 @@ int pick_lpr(const bbl_csr &H) {
 template <typename VT, typename XT, typename AT, typename YT, int LPR>
 void spmm_dispatch_b(const bbl_csr &H, const XT *X, YT *Y, int nvec, hipStream_t s) {
   const int rows_per_wg = (256 / kWave) * (kWave / LPR);
-  const int64_t grid = ceil_div(ceil_div(H.n, rows_per_wg), kXcds) * kXcds;
   const VT *val = static_cast<const VT *>(H.val);
-#define BBL_SPMM_CASE(BV)                                                                        \
-  case BV:                                                                                       \
-    hipLaunchKernelGGL((k_spmm<VT, XT, AT, YT, BV, LPR>), dim3(grid), dim3(256), 0, s, H.n,     \
-                       H.row_ptr, H.col, val, X, Y);                                             \
+  // LPR work-items per row: beyond kMaxLaunchItems of them the rows go in
+  // several launches (row_ptr and Y offset; columns stay global)
+  const int64_t max_rows = kMaxLaunchItems / 256 / kXcds * kXcds * rows_per_wg;
+  for (int64_t r0 = 0; r0 < H.n; r0 += max_rows) {
+    const int64_t nr = std::min<int64_t>(max_rows, H.n - r0);
+    const int64_t grid = ceil_div(ceil_div(nr, rows_per_wg), kXcds) * kXcds;
+    const int64_t *rp = H.row_ptr + r0;
+    YT *Yc = Y + r0 * nvec;
+#define BBL_SPMM_CASE(BV)                                                                      \
+  case BV:                                                                                     \
+    hipLaunchKernelGGL((k_spmm<VT, XT, AT, YT, BV, LPR>), dim3(grid), dim3(256), 0, s, nr, rp, \
+                       H.col, val, X, Yc);                                                     \
     break;
-  switch (nvec) {
-    BBL_SPMM_CASE(1)
-    BBL_SPMM_CASE(2)
-    BBL_SPMM_CASE(4)
-    BBL_SPMM_CASE(8)
-    BBL_SPMM_CASE(10)
-    BBL_SPMM_CASE(16)
-    default:
-      hipLaunchKernelGGL((k_spmm_generic<VT, XT, AT, YT, LPR>), dim3(grid), dim3(256), 0, s, H.n,
-                         H.row_ptr, H.col, val, X, Y, nvec);
-  }
+    switch (nvec) {
+      BBL_SPMM_CASE(1)
+      BBL_SPMM_CASE(2)
+      BBL_SPMM_CASE(4)
+      BBL_SPMM_CASE(8)
+      BBL_SPMM_CASE(10)
+      BBL_SPMM_CASE(16)
+      default:
+        hipLaunchKernelGGL((k_spmm_generic<VT, XT, AT, YT, LPR>), dim3(grid), dim3(256), 0, s, nr,
+                           rp, H.col, val, X, Yc, nvec);
+    }
 #undef BBL_SPMM_CASE
-  check_launch("k_spmm");
+    check_launch("k_spmm");
+  }
 }
 
 template <typename VT, typename XT, typename AT, typename YT>
@@ -458,67 +466,69 @@ __global__ __launch_bounds__(256) void k_plan_rows(int64_t n, int64_t G, int slo
                                                    uint16_t *__restrict__ lcol,
                                                    int32_t *__restrict__ rdesc,
                                                    int32_t *__restrict__ bcount) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= n) return;  // uniform per wave
-  const int lane = threadIdx.x & 63;
-  const int64_t g = row / G;
-  int64_t base[2 * kPlanMaxSlots];
+  // one wave per row, uniform per wave; the grid strides over the rows
+  for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < n;
+       row += (int64_t)gridDim.x * 4) {
+    const int lane = threadIdx.x & 63;
+    const int64_t g = row / G;
+    int64_t base[2 * kPlanMaxSlots];
 #pragma unroll
-  for (int k = 0; k < 2 * kPlanMaxSlots; ++k) {
-    const int b = k < width ? blocks[g * width + k] : -1;
-    base[k] = b >= 0 ? (int64_t)b * G : -((int64_t)1 << 62);
-  }
-  // kind (0: set A, 1: set B, 2: remote) and LDS index within the set
-  auto classify = [&](int32_t c, int &loc) {
-    int kind = 2;
-    loc = -1;
+    for (int k = 0; k < 2 * kPlanMaxSlots; ++k) {
+      const int b = k < width ? blocks[g * width + k] : -1;
+      base[k] = b >= 0 ? (int64_t)b * G : -((int64_t)1 << 62);
+    }
+    // kind (0: set A, 1: set B, 2: remote) and LDS index within the set
+    auto classify = [&](int32_t c, int &loc) {
+      int kind = 2;
+      loc = -1;
 #pragma unroll
-    for (int k = 2 * kPlanMaxSlots - 1; k >= 0; --k) {
-      const int64_t o = (int64_t)c - base[k];
-      if (o >= 0 && o < G) {
-        kind = k < slots ? 0 : 1;
-        loc = (int)((k < slots ? k : k - slots) * G + o);
+      for (int k = 2 * kPlanMaxSlots - 1; k >= 0; --k) {
+        const int64_t o = (int64_t)c - base[k];
+        if (o >= 0 && o < G) {
+          kind = k < slots ? 0 : 1;
+          loc = (int)((k < slots ? k : k - slots) * G + o);
+        }
       }
+      return kind;
+    };
+    const int64_t p0 = rp[row], p1 = rp[row + 1];
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int na = 0, nb = 0;
+    for (int64_t p = p0 + lane; p - lane < p1; p += 64) {
+      int loc;
+      const int kind = p < p1 ? classify(col[p], loc) : 3;
+      na += __popcll(__ballot(kind == 0));
+      nb += __popcll(__ballot(kind == 1));
     }
-    return kind;
-  };
-  const int64_t p0 = rp[row], p1 = rp[row + 1];
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  int na = 0, nb = 0;
-  for (int64_t p = p0 + lane; p - lane < p1; p += 64) {
-    int loc;
-    const int kind = p < p1 ? classify(col[p], loc) : 3;
-    na += __popcll(__ballot(kind == 0));
-    nb += __popcll(__ballot(kind == 1));
-  }
-  int ia = 0, ib = 0, ir = 0;
-  for (int64_t p = p0 + lane; p - lane < p1; p += 64) {
-    const bool in = p < p1;
-    const int32_t c = in ? col[p] : 0;
-    int loc = -1;
-    const int kind = in ? classify(c, loc) : 3;
-    const uint64_t ma = __ballot(kind == 0), mb = __ballot(kind == 1), mr = __ballot(kind == 2);
-    int64_t q = -1;
-    if (kind == 0) q = p0 + ia + __popcll(ma & below);
-    else if (kind == 1) q = p0 + na + ib + __popcll(mb & below);
-    else if (kind == 2) q = p0 + na + nb + ir + __popcll(mr & below);
-    if (q >= 0) {
-      col2[q] = kind == 0 ? loc : c;
-      val2[q] = val[p];
-      if (lcol && kind < 2) lcol[q] = (uint16_t)loc;
+    int ia = 0, ib = 0, ir = 0;
+    for (int64_t p = p0 + lane; p - lane < p1; p += 64) {
+      const bool in = p < p1;
+      const int32_t c = in ? col[p] : 0;
+      int loc = -1;
+      const int kind = in ? classify(c, loc) : 3;
+      const uint64_t ma = __ballot(kind == 0), mb = __ballot(kind == 1), mr = __ballot(kind == 2);
+      int64_t q = -1;
+      if (kind == 0) q = p0 + ia + __popcll(ma & below);
+      else if (kind == 1) q = p0 + na + ib + __popcll(mb & below);
+      else if (kind == 2) q = p0 + na + nb + ir + __popcll(mr & below);
+      if (q >= 0) {
+        col2[q] = kind == 0 ? loc : c;
+        val2[q] = val[p];
+        if (lcol && kind < 2) lcol[q] = (uint16_t)loc;
+      }
+      ia += __popcll(ma);
+      ib += __popcll(mb);
+      ir += __popcll(mr);
     }
-    ia += __popcll(ma);
-    ib += __popcll(mb);
-    ir += __popcll(mr);
-  }
-  if (lane == 0) {
-    n_local[row] = na;
-    if (bcount) bcount[2 * row + 1] = nb;
-    if (rdesc) {
-      const int64_t gb = rp[g * G] & ~(int64_t)7;
-      const int4 d = make_int4((int)(p0 - gb), (int)(p0 + na - gb), (int)(p0 + na + nb - gb),
-                               (int)(p1 - gb));
-      *reinterpret_cast<int4 *>(rdesc + 4 * row) = d;
+    if (lane == 0) {
+      n_local[row] = na;
+      if (bcount) bcount[2 * row + 1] = nb;
+      if (rdesc) {
+        const int64_t gb = rp[g * G] & ~(int64_t)7;
+        const int4 d = make_int4((int)(p0 - gb), (int)(p0 + na - gb), (int)(p0 + na + nb - gb),
+                                 (int)(p1 - gb));
+        *reinterpret_cast<int4 *>(rdesc + 4 * row) = d;
+      }
     }
   }
 }
@@ -635,34 +645,215 @@ __global__ __launch_bounds__(256) void k_plan_bfill(int64_t n, int64_t G,
                                                     const int32_t *__restrict__ rpos,
                                                     const int64_t *__restrict__ rgroup,
                                                     int4 *__restrict__ rlist) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= n) return;  // uniform per wave
-  const int lane = threadIdx.x & 63;
-  const int64_t g = row / G;
-  const int na = n_local[row];
-  const int64_t asrc = rp[row], adst = agroup[g] + arow[2 * row];
-  for (int i = lane; i < na; i += 64) {
-    alcol[adst + i] = lcol[asrc + i];
-    aval[adst + i] = val2[asrc + i];
+  // one wave per row, uniform per wave; the grid strides over the rows
+  for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < n;
+       row += (int64_t)gridDim.x * 4) {
+    const int lane = threadIdx.x & 63;
+    const int64_t g = row / G;
+    const int na = n_local[row];
+    const int64_t asrc = rp[row], adst = agroup[g] + arow[2 * row];
+    for (int i = lane; i < na; i += 64) {
+      alcol[adst + i] = lcol[asrc + i];
+      aval[adst + i] = val2[asrc + i];
+    }
+    const int64_t src = asrc + na;
+    const int cnt = brow[2 * row + 1];
+    const int64_t dst = bgroup[g] + brow[2 * row];
+    for (int i = lane; i < cnt; i += 64) {
+      blcol[dst + i] = lcol[src + i];
+      bval[dst + i] = val2[src + i];
+    }
+    if (lane == 0) {
+      const int64_t ga = agroup[g] & ~(int64_t)7;
+      *reinterpret_cast<int2 *>(arow + 2 * row) = make_int2((int)(adst - ga), (int)(adst + na - ga));
+      const int64_t gb = bgroup[g] & ~(int64_t)7;
+      *reinterpret_cast<int2 *>(brow + 2 * row) = make_int2((int)(dst - gb), (int)(dst + cnt - gb));
+      if (rpos[row] >= 0) {
+        // {row, count, first entry (64-bit, low and high word)}
+        const int64_t first = (rp[g * G] & ~(int64_t)7) + rdesc[4 * row + 2];
+        rlist[rgroup[g] + rpos[row]] =
+            make_int4((int)row, rdesc[4 * row + 3] - rdesc[4 * row + 2], (int)(uint32_t)first,
+                      (int)(first >> 32));
+      }
+    }
   }
-  const int64_t src = asrc + na;
-  const int cnt = brow[2 * row + 1];
-  const int64_t dst = bgroup[g] + brow[2 * row];
-  for (int i = lane; i < cnt; i += 64) {
-    blcol[dst + i] = lcol[src + i];
-    bval[dst + i] = val2[src + i];
+}
+
+// ---------------------------------------------------------------------------
+// Multi-set plan (groups whose entries spread over more column blocks than
+// two sets of LDS slots hold, or more than 2^31 entries): the group's busiest
+// nsets * slots blocks form nsets sets of `slots` blocks, staged in LDS one
+// set after the other; every set has a dense copy of its entries (group by
+// group, rows in order, 16-bit LDS index within the set and value), and the
+// entries outside every set are kept compactly (global column and value) for
+// the gather pass.  Built straight from H: nothing of the size of H beside
+// the copies.  Layout of the copies (one region of 8 (nnz + 16) bytes):
+// set values from the front of the value half, rest values from its back;
+// set LDS indices packed from the front of the index half, rest columns
+// from its back.
+
+// Set of an entry of group g with column c: the position of its block among
+// the group's blocks divided by slots, nsets for none.  loc receives the LDS
+// row index within the set.
+__device__ __forceinline__ int ms_classify(int32_t c, const int64_t *base, int width, int slots,
+                                           int64_t G, int &loc) {
+  int kind = width / slots;
+  loc = 0;
+  for (int k = width - 1; k >= 0; --k) {
+    const int64_t o = (int64_t)c - base[k];
+    if (o >= 0 && o < G) {
+      kind = k / slots;
+      loc = (int)((k % slots) * G + o);
+    }
   }
-  if (lane == 0) {
-    const int64_t ga = agroup[g] & ~(int64_t)7;
-    *reinterpret_cast<int2 *>(arow + 2 * row) = make_int2((int)(adst - ga), (int)(adst + na - ga));
-    const int64_t gb = bgroup[g] & ~(int64_t)7;
-    *reinterpret_cast<int2 *>(brow + 2 * row) = make_int2((int)(dst - gb), (int)(dst + cnt - gb));
-    if (rpos[row] >= 0) {
-      // {row, count, first entry (64-bit, low and high word)}
-      const int64_t first = (rp[g * G] & ~(int64_t)7) + rdesc[4 * row + 2];
-      rlist[rgroup[g] + rpos[row]] =
-          make_int4((int)row, rdesc[4 * row + 3] - rdesc[4 * row + 2], (int)(uint32_t)first,
-                    (int)(first >> 32));
+  return kind;
+}
+
+constexpr int kMsMaxWidth = 16;  // blocks of all sets of a group
+
+// Per row (one wave per row): entries per set into srow[(s n + row) 2 + 1],
+// entries outside every set into rcnt[row].
+__global__ __launch_bounds__(256) void k_ms_count(int64_t n, int64_t G, int slots, int width,
+                                                  const int64_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ col,
+                                                  const int32_t *__restrict__ blocks,
+                                                  int32_t *__restrict__ srow,
+                                                  int32_t *__restrict__ rcnt) {
+  // one wave per row, uniform per wave; the grid strides over the rows
+  for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < n;
+       row += (int64_t)gridDim.x * 4) {
+    const int lane = threadIdx.x & 63;
+    const int64_t g = row / G;
+    const int nsets = width / slots;
+    int64_t base[kMsMaxWidth];
+    for (int k = 0; k < width; ++k) {
+      const int b = blocks[g * width + k];
+      base[k] = b >= 0 ? (int64_t)b * G : -((int64_t)1 << 62);
+    }
+    int cnt[kMsMaxWidth + 1] = {};
+    const int64_t p0 = rp[row], p1 = rp[row + 1];
+    for (int64_t p = p0 + lane; p - lane < p1; p += 64) {
+      int loc;
+      const int kind = p < p1 ? ms_classify(col[p], base, width, slots, G, loc) : -1;
+      for (int s = 0; s <= nsets; ++s) cnt[s] += __popcll(__ballot(kind == s));
+    }
+    if (lane == 0) {
+      for (int s = 0; s < nsets; ++s) srow[(s * n + row) * 2 + 1] = cnt[s];
+      rcnt[row] = cnt[nsets];
+    }
+  }
+}
+
+// One workgroup per group: per set, the rows' offsets within the group's
+// copy (srow[..].x) and the group's total (sgroup[s][g + 1]); for the rest,
+// each row's offset among the group's rest entries (rpre), the group's rest
+// total (rtot[g + 1]), and the position of every row that has rest entries
+// among such rows (rpos, -1 if none) with their count (rgroup[g + 1]).
+__global__ __launch_bounds__(256) void k_ms_group(int64_t n, int64_t G, int nsets, int64_t groups,
+                                                  int32_t *__restrict__ srow,
+                                                  int64_t *__restrict__ sgroup,
+                                                  const int32_t *__restrict__ rcnt,
+                                                  int32_t *__restrict__ rpre,
+                                                  int64_t *__restrict__ rtot,
+                                                  int32_t *__restrict__ rpos,
+                                                  int64_t *__restrict__ rgroup) {
+  __shared__ int64_t part[256];
+  const int64_t g = blockIdx.x;
+  const int64_t r0 = g * G, r1 = min(n, r0 + G);
+  for (int s = 0; s < nsets; ++s) {
+    int32_t *sr = srow + (int64_t)s * n * 2;
+    const int64_t tot = group_scan(
+        r0, r1, part, [&](int64_t r) { return (int64_t)sr[2 * r + 1]; },
+        [&](int64_t r, int64_t pre) { sr[2 * r] = (int)pre; });
+    if (threadIdx.x == 0) {
+      sgroup[s * (groups + 1) + g + 1] = tot;
+      if (g == 0) sgroup[s * (groups + 1)] = 0;
+    }
+  }
+  const int64_t rt = group_scan(
+      r0, r1, part, [&](int64_t r) { return (int64_t)rcnt[r]; },
+      [&](int64_t r, int64_t pre) { rpre[r] = (int)pre; });
+  const int64_t nr = group_scan(
+      r0, r1, part, [&](int64_t r) { return (int64_t)(rcnt[r] > 0); },
+      [&](int64_t r, int64_t pre) { rpos[r] = rcnt[r] > 0 ? (int)pre : -1; });
+  if (threadIdx.x == 0) {
+    rtot[g + 1] = rt;
+    rgroup[g + 1] = nr;
+    if (g == 0) rtot[0] = rgroup[0] = 0;
+  }
+}
+
+// Per row (one wave per row): the entries into their set's copy or the rest
+// arrays, each kind in the row's order; then srow[s][row] = {first, end}
+// relative to the group's first copy entry rounded down to 8, and the row's
+// rest list entry {row, count, first rest entry (low, high)}.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_ms_fill(int64_t n, int64_t G, int slots, int width,
+                                                 int64_t groups, const int64_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ col,
+                                                 const VT *__restrict__ val,
+                                                 const int32_t *__restrict__ blocks,
+                                                 int32_t *__restrict__ srow,
+                                                 const int64_t *__restrict__ sgroup,
+                                                 uint16_t *__restrict__ slcol,
+                                                 VT *__restrict__ sval,
+                                                 const int32_t *__restrict__ rcnt,
+                                                 const int32_t *__restrict__ rpre,
+                                                 const int64_t *__restrict__ rtot,
+                                                 const int32_t *__restrict__ rpos,
+                                                 const int64_t *__restrict__ rgroup,
+                                                 int32_t *__restrict__ rcol, VT *__restrict__ rval,
+                                                 int4 *__restrict__ rlist) {
+  // one wave per row, uniform per wave; the grid strides over the rows
+  for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < n;
+       row += (int64_t)gridDim.x * 4) {
+    const int lane = threadIdx.x & 63;
+    const int64_t g = row / G;
+    const int nsets = width / slots;
+    int64_t base[kMsMaxWidth];
+    for (int k = 0; k < width; ++k) {
+      const int b = blocks[g * width + k];
+      base[k] = b >= 0 ? (int64_t)b * G : -((int64_t)1 << 62);
+    }
+    int64_t dst[kMsMaxWidth + 1];
+    for (int s = 0; s < nsets; ++s)
+      dst[s] = sgroup[s * (groups + 1) + g] + srow[((int64_t)s * n + row) * 2];
+    dst[nsets] = rtot[g] + rpre[row];
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t p0 = rp[row], p1 = rp[row + 1];
+    for (int64_t p = p0 + lane; p - lane < p1; p += 64) {
+      const bool in = p < p1;
+      const int32_t c = in ? col[p] : 0;
+      int loc = 0;
+      const int kind = in ? ms_classify(c, base, width, slots, G, loc) : -1;
+      for (int s = 0; s <= nsets; ++s) {
+        const uint64_t m = __ballot(kind == s);
+        if (kind == s) {
+          const int64_t q = dst[s] + __popcll(m & below);
+          if (s < nsets) {
+            slcol[q] = (uint16_t)loc;
+            sval[q] = val[p];
+          } else {
+            rcol[q] = c;
+            rval[q] = val[p];
+          }
+        }
+        dst[s] += __popcll(m);
+      }
+    }
+    if (lane == 0) {
+      for (int s = 0; s < nsets; ++s) {
+        int32_t *d = srow + ((int64_t)s * n + row) * 2;
+        const int64_t gb = sgroup[s * (groups + 1) + g] & ~(int64_t)7;
+        const int64_t first = sgroup[s * (groups + 1) + g] + d[0];
+        d[0] = (int)(first - gb);
+        d[1] = (int)(first + d[1] - gb);
+      }
+      if (rpos[row] >= 0) {
+        const int64_t first = rtot[g] + rpre[row];
+        rlist[rgroup[g] + rpos[row]] =
+            make_int4((int)row, rcnt[row], (int)(uint32_t)first, (int)(first >> 32));
+      }
     }
   }
 }
@@ -980,8 +1171,8 @@ struct StageFill {
   }
 };
 
-// Pass 1 (P2 = false) or pass 2 (P2 = true) over the row groups; `blocks`
-// has 2 slots entries per group (set A, then set B).  Each pass streams the
+// Pass 1 (P2 = false) or pass 2 (P2 = true) over the row groups; `bl` is the
+// set's `slots` block ids for group g.  Each pass streams the
 // plan's dense copy of its set's entries: bases = the per-group offsets into
 // it, descriptors [n][2] = {first, end} of each row as 32-bit offsets from
 // its group's first entry rounded down to a multiple of 8.
@@ -994,7 +1185,7 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
                                          const float *__restrict__ val,
                                          const uint16_t *__restrict__ lcol,
                                          const int32_t *__restrict__ rdesc,
-                                         const int32_t *__restrict__ blocks,
+                                         const int32_t *__restrict__ bl,
                                          const float *__restrict__ X, float *__restrict__ Y,
                                          unsigned char *smem_raw, int ld,
                                          const StageFill<B> *pre = nullptr) {
@@ -1038,7 +1229,6 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
   } else {
     // in two halves where the whole would not fit in registers beside the
     // first stage
-    const int32_t *bl = blocks + g * (2 * slots) + (P2 ? slots : 0);
     constexpr int kAll = stage_pieces<B>(), kHalf = (kAll + 1) / 2;
     if constexpr (kAll <= 10) {
       StageFill<B> fill;
@@ -1215,7 +1405,8 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe12(int64_t n, int64_t G, int 
   const int ld = S ? ld_arg : B;  // row stride of V and W (S: strided halves)
   const int64_t g = xcd_block(blockIdx.x);
   if (g * G >= n) return;  // grid padding: the whole workgroup leaves
-  pipe_run<B, false>(g, n, G, slots, abases, aval, alcol, arow, blocks, X, Y, smem_raw, ld);
+  pipe_run<B, false>(g, n, G, slots, abases, aval, alcol, arow, blocks + g * (2 * slots), X, Y,
+                     smem_raw, ld);
   // set B's blocks are loaded while the rest of the workgroup finishes pass 1
   // (where 16-byte pieces keep the held loads within the register budget of
   // 1024 threads; otherwise pass 2 loads them after the barrier)
@@ -1224,8 +1415,40 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe12(int64_t n, int64_t G, int 
   if (kEarly) fill.issue(n, G, slots, blocks + g * (2 * slots) + slots, X, ld);
   // pass 1's row sums written and its LDS reads done, workgroup-wide
   __syncthreads();
-  pipe_run<B, true>(g, n, G, slots, bbases, bval, blcol, brow, blocks, X, Y, smem_raw, ld,
-                    kEarly ? &fill : nullptr);
+  pipe_run<B, true>(g, n, G, slots, bbases, bval, blcol, brow, blocks + g * (2 * slots) + slots,
+                    X, Y, smem_raw, ld, kEarly ? &fill : nullptr);
+}
+
+// The multi-set pipelined SpMM: one 1024-thread workgroup per group stages
+// set s's blocks and streams its copy, for s = 0 .. nsets - 1; set 0 writes
+// the row sums (16 lanes per row), later sets add theirs (2 lanes per row,
+// reading the previous sums back while they are in the L2).  A set with no
+// entries in the group is skipped.  The rest pass follows as its own kernel.
+template <int B, bool S>
+__global__ __launch_bounds__(1024) void k_spmm_pipe_ms(int64_t n, int64_t G, int slots, int nsets,
+                                                       int64_t groups,
+                                                       const int64_t *__restrict__ sgroup,
+                                                       const float *__restrict__ sval,
+                                                       const uint16_t *__restrict__ slcol,
+                                                       const int32_t *__restrict__ srow,
+                                                       const int32_t *__restrict__ blocks,
+                                                       const float *__restrict__ X,
+                                                       float *__restrict__ Y, int ld_arg) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int ld = S ? ld_arg : B;  // row stride of V and W (S: strided halves)
+  const int64_t g = xcd_block(blockIdx.x);
+  if (g * G >= n) return;  // grid padding: the whole workgroup leaves
+  const int width = nsets * slots;
+  pipe_run<B, false>(g, n, G, slots, sgroup, sval, slcol, srow, blocks + g * width, X, Y,
+                     smem_raw, ld);
+  for (int s = 1; s < nsets; ++s) {
+    const int64_t *sg = sgroup + s * (groups + 1);
+    if (sg[g + 1] == sg[g]) continue;  // uniform: no entries of set s in this group
+    // the previous set's row sums written and its LDS reads done
+    __syncthreads();
+    pipe_run<B, true>(g, n, G, slots, sg, sval, slcol, srow + (int64_t)s * n * 2,
+                      blocks + g * width + s * slots, X, Y, smem_raw, ld);
+  }
 }
 
 // Pass 3: kRestLanes lanes per listed row (rows with entries outside both
@@ -1360,10 +1583,40 @@ void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, int l
   check_launch("k_spmm_rest");
 }
 
+// The multi-set plan: its sets in one workgroup per group, then the rest pass.
+template <int BV, bool S>
+void planned_launch_ms(const bbl_spmm_plan &P, const float *X, float *Y, int ld, hipStream_t s) {
+  auto kern = k_spmm_pipe_ms<BV, S>;
+  const size_t lds = ((size_t)P.slots * P.block_rows + 1) * BV * sizeof(float);
+  static bool attr_set = false;
+  if (!attr_set) {
+    BBL_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPlanLds));
+    attr_set = true;
+  }
+  const int64_t groups = ceil_div(P.n, P.block_rows);
+  hipLaunchKernelGGL(kern, dim3((unsigned)(ceil_div(groups, kXcds) * kXcds)), dim3(kPlanThreads),
+                     lds, s, P.n, (int64_t)P.block_rows, P.slots, P.nsets, groups, P.sgroup,
+                     static_cast<const float *>(P.sval), P.slcol, P.srow, P.blocks, X, Y, ld);
+  check_launch("k_spmm_pipe_ms");
+  const int64_t grid =
+      std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(P.n * kRestLanes, 256)));
+  hipLaunchKernelGGL((k_spmm_rest<BV, S>), dim3((unsigned)grid), dim3(256), 0, s, P.rgroup, groups,
+                     reinterpret_cast<const int4 *>(P.rlist), P.rcol,
+                     static_cast<const float *>(P.rval), X, Y, ld);
+  check_launch("k_spmm_rest");
+}
+
 template <typename VT, typename XT, int BV>
 void planned_launch(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s) {
   if constexpr (std::is_same<VT, float>::value && std::is_same<XT, float>::value &&
                 (BV == 4 || BV == 8 || BV == 10 || BV == 16)) {
+    if (P.nsets > 0) {
+      constexpr int BK = BV == 16 ? 8 : BV;
+      planned_launch_ms<BK, BV != BK>(P, X, Y, BV, s);
+      if constexpr (BV == 16) planned_launch_ms<BK, true>(P, X + 8, Y + 8, BV, s);
+      return;
+    }
     // the pipelined kernel also keeps one all-zero row of V in LDS and takes
     // 32-bit entry offsets; 16 vectors go through it as two halves of 8
     constexpr int BK = BV == 16 ? 8 : BV;
@@ -1479,8 +1732,28 @@ bool plan_local16(const bbl_csr &H, int slots) {
 // per-row 32-bit entry offsets from the group's first entry
 bool plan_desc(const bbl_csr &H) { return H.nnz < ((int64_t)1 << 31) - 64; }
 
+// Multi-set layout: float32 values and vectors at 4, 8, 10 or 16 vectors
+// (16 as two halves of 8), when fewer than three column blocks fit in LDS
+// per set or the entries need 64-bit offsets.  *slots blocks per set,
+// *nsets sets covering the busiest kMsBlocks blocks of each group.
+constexpr int kMsBlocks = 10;
+bool plan_multi(const bbl_csr &H, int nvec, int vec_dtype, int *slots, int *nsets) {
+  if (H.block_rows <= 0 || H.val_dtype != BBL_F32 || vec_dtype != BBL_F32) return false;
+  if (!(nvec == 4 || nvec == 8 || nvec == 10 || nvec == 16)) return false;
+  const int BK = nvec == 16 ? 8 : nvec;
+  const int64_t s = std::min<int64_t>(kPlanMaxSlots,
+                                      ((int64_t)kPlanLds / (BK * 4) - 1) / H.block_rows);
+  if (s < 1 || s * H.block_rows > 65536) return false;
+  if (s >= 3 && plan_desc(H)) return false;
+  *slots = (int)s;
+  *nsets = (int)std::min<int64_t>(kMsMaxWidth / s, ceil_div(kMsBlocks, s));
+  return true;
+}
+
 int spmm_plan_slots(const bbl_csr &H, int nvec, int vec_dtype) {
   if (H.block_rows <= 0) return 0;
+  int ms, mn;
+  if (plan_multi(H, nvec, vec_dtype, &ms, &mn)) return ms;
   if (!(nvec == 1 || nvec == 2 || nvec == 4 || nvec == 8 || nvec == 10 || nvec == 16)) return 0;
   if (nvec == 16 && vec_dtype == BBL_F32 && H.val_dtype == BBL_F32 && plan_desc(H)) {
     // FP32, 16 vectors: the pipelined kernels take the columns in two halves
@@ -1492,7 +1765,31 @@ int spmm_plan_slots(const bbl_csr &H, int nvec, int vec_dtype) {
   return (int)std::min<size_t>(kPlanMaxSlots, kPlanLds / per);
 }
 
+// Regions of a multi-set plan, in order (byte sizes; each 256-aligned).
+struct MsLayout {
+  size_t blocks, sgroup, srow, rcnt, rpre, rtot, rpos, rgroup, rlist, vals, idx;
+};
+MsLayout ms_layout(const bbl_csr &H, int slots, int nsets) {
+  const int64_t groups = ceil_div(H.n, H.block_rows);
+  MsLayout L;
+  L.blocks = (size_t)groups * nsets * slots * 4;
+  L.sgroup = (size_t)nsets * (groups + 1) * 8;
+  L.srow = (size_t)nsets * H.n * 8;
+  L.rcnt = L.rpre = L.rpos = (size_t)H.n * 4;
+  L.rtot = L.rgroup = (size_t)(groups + 1) * 8;
+  L.rlist = (size_t)H.n * 16;
+  L.vals = L.idx = (size_t)(H.nnz + 16) * 4;
+  return L;
+}
+size_t ms_bytes(const MsLayout &L) {
+  return align_up(L.blocks) + align_up(L.sgroup) + align_up(L.srow) + align_up(L.rcnt) +
+         align_up(L.rpre) + align_up(L.rtot) + align_up(L.rpos) + align_up(L.rgroup) +
+         align_up(L.rlist) + align_up(L.vals) + align_up(L.idx) + 256;
+}
+
 size_t spmm_plan_bytes(const bbl_csr &H, int nvec, int vec_dtype) {
+  int ms, mn;
+  if (plan_multi(H, nvec, vec_dtype, &ms, &mn)) return ms_bytes(ms_layout(H, ms, mn));
   const int slots = spmm_plan_slots(H, nvec, vec_dtype);
   if (slots < 1) return 0;
   const int64_t groups = ceil_div(H.n, H.block_rows);
@@ -1513,8 +1810,102 @@ size_t spmm_plan_bytes(const bbl_csr &H, int nvec, int vec_dtype) {
          256;
 }
 
+__global__ void k_add_base(int64_t *a, int64_t m, int64_t base) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) a[i] += base;
+}
+
+// Multi-set plan: block choice, per-row counts, per-group offsets, their scan
+// over groups, the set bases (the copies lie set after set), then the fill.
+// Reads the totals back to the host once (synchronises the stream).
+void build_ms_plan(const bbl_csr &H, int nvec, int vec_dtype, int slots, int nsets, void *mem,
+                   size_t bytes, bbl_spmm_plan *P, hipStream_t s) {
+  const MsLayout L = ms_layout(H, slots, nsets);
+  if (bytes < ms_bytes(L)) throw Error{BBL_E_NOMEM, "plan memory too small"};
+  const int64_t groups = ceil_div(H.n, H.block_rows), G = H.block_rows;
+  const int width = nsets * slots;
+  char *base = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(mem), 256));
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    char *p = base + off;
+    off += align_up(b);
+    return p;
+  };
+  int32_t *blocks = reinterpret_cast<int32_t *>(take(L.blocks));
+  int64_t *sgroup = reinterpret_cast<int64_t *>(take(L.sgroup));
+  int32_t *srow = reinterpret_cast<int32_t *>(take(L.srow));
+  int32_t *rcnt = reinterpret_cast<int32_t *>(take(L.rcnt));
+  int32_t *rpre = reinterpret_cast<int32_t *>(take(L.rpre));
+  int64_t *rtot = reinterpret_cast<int64_t *>(take(L.rtot));
+  int32_t *rpos = reinterpret_cast<int32_t *>(take(L.rpos));
+  int64_t *rgroup = reinterpret_cast<int64_t *>(take(L.rgroup));
+  int32_t *rlist = reinterpret_cast<int32_t *>(take(L.rlist));
+  float *vals = reinterpret_cast<float *>(take(L.vals));
+  char *idx = take(L.idx);
+  hipLaunchKernelGGL(k_plan_blocks, dim3((unsigned)groups), dim3(256), 0, s, H.n, G, width,
+                     H.row_ptr, H.col, blocks);
+  const unsigned grid = capped_grid(ceil_div(H.n, 4), 256);  // one wave per row, strided
+  hipLaunchKernelGGL(k_ms_count, dim3(grid), dim3(256), 0, s, H.n, G, slots, width, H.row_ptr,
+                     H.col, blocks, srow, rcnt);
+  hipLaunchKernelGGL(k_ms_group, dim3((unsigned)groups), dim3(256), 0, s, H.n, G, nsets, groups,
+                     srow, sgroup, rcnt, rpre, rtot, rpos, rgroup);
+  for (int k = 0; k < nsets; ++k)
+    hipLaunchKernelGGL(k_plan_gscan, dim3(1), dim3(1024), 0, s, sgroup + k * (groups + 1), groups);
+  hipLaunchKernelGGL(k_plan_gscan, dim3(1), dim3(1024), 0, s, rtot, groups);
+  hipLaunchKernelGGL(k_plan_gscan, dim3(1), dim3(1024), 0, s, rgroup, groups);
+  check_launch("multi-set plan counts");
+  std::vector<int64_t> tot(nsets + 1);
+  for (int k = 0; k < nsets; ++k)
+    BBL_HIP(hipMemcpyAsync(&tot[k], sgroup + k * (groups + 1) + groups, 8, hipMemcpyDeviceToHost,
+                           s));
+  BBL_HIP(hipMemcpyAsync(&tot[nsets], rtot + groups, 8, hipMemcpyDeviceToHost, s));
+  BBL_HIP(hipStreamSynchronize(s));
+  int64_t run = 0;
+  for (int k = 0; k < nsets; ++k) {
+    if (run > 0)
+      hipLaunchKernelGGL(k_add_base, dim3((unsigned)ceil_div(groups + 1, 256)), dim3(256), 0, s,
+                         sgroup + k * (groups + 1), groups + 1, run);
+    run += tot[k];
+  }
+  const int64_t rest = tot[nsets];
+  BBL_REQUIRE(run + rest == H.nnz, "multi-set plan: entry counts do not add up");
+  uint16_t *slcol = reinterpret_cast<uint16_t *>(idx);
+  int32_t *rcol = reinterpret_cast<int32_t *>(idx + L.idx) - rest;  // from the back
+  float *rval = vals + (H.nnz + 16) - rest;
+  hipLaunchKernelGGL((k_ms_fill<float>), dim3(grid), dim3(256), 0, s, H.n, G, slots, width,
+                     groups, H.row_ptr, H.col, static_cast<const float *>(H.val), blocks, srow,
+                     sgroup, slcol, vals, rcnt, rpre, rtot, rpos, rgroup, rcol, rval,
+                     reinterpret_cast<int4 *>(rlist));
+  check_launch("multi-set plan fill");
+  *P = bbl_spmm_plan{};
+  P->n = H.n;
+  P->nnz = H.nnz;
+  P->block_rows = H.block_rows;
+  P->slots = slots;
+  P->nvec = nvec;
+  P->vec_dtype = vec_dtype;
+  P->val_dtype = H.val_dtype;
+  P->local16 = 1;
+  P->row_ptr = H.row_ptr;
+  P->blocks = blocks;
+  P->rgroup = rgroup;
+  P->rlist = rlist;
+  P->nsets = nsets;
+  P->sgroup = sgroup;
+  P->srow = srow;
+  P->slcol = slcol;
+  P->sval = vals;
+  P->rcol = rcol;
+  P->rval = rval;
+}
+
 void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_t bytes,
                      bbl_spmm_plan *P, hipStream_t s) {
+  {
+    int ms, mn;
+    if (plan_multi(H, nvec, vec_dtype, &ms, &mn))
+      return build_ms_plan(H, nvec, vec_dtype, ms, mn, mem, bytes, P, s);
+  }
   const int slots = spmm_plan_slots(H, nvec, vec_dtype);
   if (slots < 1)
     throw Error{BBL_E_INVALID, "no plan: block_rows must be > 0, nvec in {1,2,4,8,10,16} and "
@@ -1551,7 +1942,7 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
   int32_t *rlist = two ? reinterpret_cast<int32_t *>(take((size_t)H.n * 16)) : nullptr;
   hipLaunchKernelGGL(k_plan_blocks, dim3((unsigned)groups), dim3(256), 0, s, H.n,
                      (int64_t)H.block_rows, width, H.row_ptr, H.col, blocks);
-  const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(H.n, 4));
+  const unsigned grid = capped_grid(ceil_div(H.n, 4), 256);  // one wave per row, strided
   if (H.val_dtype == BBL_F32)
     hipLaunchKernelGGL((k_plan_rows<float>), dim3(grid), dim3(256), 0, s, H.n,
                        (int64_t)H.block_rows, slots, width, H.row_ptr, H.col,
@@ -1585,6 +1976,7 @@ void build_spmm_plan(const bbl_csr &H, int nvec, int vec_dtype, void *mem, size_
                          reinterpret_cast<int4 *>(rlist));
   }
   check_launch("spmm plan");
+  *P = bbl_spmm_plan{};
   P->n = H.n;
   P->nnz = H.nnz;
   P->block_rows = H.block_rows;

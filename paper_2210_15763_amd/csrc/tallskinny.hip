@@ -796,14 +796,23 @@ int update_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, cons
       default: break;
     }
   }
-  const int64_t grid = ceil_div(n, 64);
-  if (ny <= 16)
-    hipLaunchKernelGGL((k_update<XT, YIT, YOT, 1>), dim3((unsigned)grid), dim3(256), 0, s, n, X,
-                       bx, M, xstride, C, ny, alpha, Yin, beta, Yout, when);
-  else
-    hipLaunchKernelGGL((k_update<XT, YIT, YOT, 2>), dim3((unsigned)grid), dim3(256), 0, s, n, X,
-                       bx, M, xstride, C, ny, alpha, Yin, beta, Yout, when);
-  check_launch("k_update");
+  // four work-items per row: beyond kMaxLaunchItems of them the rows go in
+  // several launches (row offsets into every block of X and into Y)
+  const int64_t max_rows = kMaxLaunchItems / 4;
+  for (int64_t r0 = 0; r0 < n; r0 += max_rows) {
+    const int64_t nr = std::min<int64_t>(max_rows, n - r0);
+    const unsigned grid = (unsigned)ceil_div(nr, 64);
+    const XT *Xc = X + r0 * bx;
+    const YIT *Yi = Yin ? Yin + r0 * ny : nullptr;
+    YOT *Yo = Yout + r0 * ny;
+    if (ny <= 16)
+      hipLaunchKernelGGL((k_update<XT, YIT, YOT, 1>), dim3(grid), dim3(256), 0, s, nr, Xc, bx, M,
+                         xstride, C, ny, alpha, Yi, beta, Yo, when);
+    else
+      hipLaunchKernelGGL((k_update<XT, YIT, YOT, 2>), dim3(grid), dim3(256), 0, s, nr, Xc, bx, M,
+                         xstride, C, ny, alpha, Yi, beta, Yo, when);
+    check_launch("k_update");
+  }
   return 0;
 }
 

@@ -147,3 +147,52 @@ def test_full_size_solve_residuals_invariants_and_pivots(torch, bbl, mid, plan):
     assert rr.converged
     # both sets are within the residual bound of true eigenvalues
     np.testing.assert_allclose(rr.eigvals, r.eigvals, rtol=0, atol=2 * w.tol * hn)
+
+
+def test_launches_beyond_32_bit_work_item_counts(torch, bbl):
+    """n = 1.5e8 rows (3 entries each: the diagonal, one in a block seven
+    sectors away, one scattered), 8 FP32 vectors: the plain kernel's 16 lanes
+    per row exceed 2^31 work-items and run as two launches, and the multi-set
+    plan's one-wave-per-row build kernels stride over the rows.  Sampled rows,
+    including both sides of every launch and stride boundary, against the
+    dot-product bound."""
+    n, G, nv = 150_000_000, 2000, 8
+    note("n=1.5e8, 3 entries per row, building on the host")
+    i = np.arange(n, dtype=np.int64)
+    cols = np.stack([i, (i + 7 * G) % n, (i * 7919 + 13) % n], axis=1)
+    del i
+    cols.sort(axis=1)
+    col = cols.reshape(-1).astype(np.int32)
+    del cols
+    val = np.random.default_rng(5).standard_normal(3 * n, dtype=np.float32)
+    rp = np.arange(0, 3 * n + 1, 3, dtype=np.int64)
+
+    class Host:
+        pass
+    H = Host()
+    H.n, H.row_ptr, H.col, H.val = n, rp, col, val
+    Hd = bbl.DeviceCSR.from_host(H, "float32", block_rows=G)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    V = torch.randn(n, nv, device="cuda", generator=g)
+    rng = np.random.default_rng(1)
+    edges = [0, 1, n - 1, 134_217_727, 134_217_728, 134_217_729]
+    edges += [k * 33_554_432 + d for k in (1, 2, 3, 4) for d in (-1, 0, 1)]
+    idx = np.unique(np.concatenate([rng.choice(n, 2000, replace=False), edges]))
+
+    def check(W):
+        Wi = W[torch.from_numpy(idx).cuda()].double().cpu().numpy()
+        c = col.reshape(n, 3)[idx]
+        v = val.reshape(n, 3)[idx].astype(np.float64)
+        Xc = V[torch.from_numpy(c.reshape(-1).astype(np.int64)).cuda()].double().cpu().numpy()
+        Xc = Xc.reshape(len(idx), 3, nv)
+        ref = np.einsum("rj,rja->ra", v, Xc)
+        bound = 5 * U32 / (1 - 5 * U32) * np.einsum("rj,rja->ra", np.abs(v), np.abs(Xc)) + 1e-30
+        assert np.all(np.abs(Wi - ref) <= bound), np.abs(Wi - ref).max()
+
+    note("plain CSR SpMM over two launches")
+    check(bbl.spmm(Hd, V))
+    note("multi-set plan build and planned SpMM")
+    plan = bbl.spmm_plan(Hd, nv)
+    assert plan.c.nsets > 0
+    check(bbl.spmm_planned(plan, V))

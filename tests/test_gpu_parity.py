@@ -116,6 +116,58 @@ def test_planned_spmm_matches_oracle(torch, bbl, nvec, block_rows, prec, q, p):
     assert np.all(np.abs(W - oracle.spmm(Href, Vr)) <= bound)
 
 
+@pytest.mark.parametrize("n,R,q,p,nvec,block_rows", [
+    (40000, 2000, 105, 0.7, 8, 2000), (40000, 2000, 105, 0.7, 16, 2000),
+    (40000, 2000, 105, 0.7, 10, 2000), (40000, 1000, 60, 0.5, 4, 5000),
+    # many small sectors: groups reach more column blocks than the sets
+    # hold, so many entries take the gather pass
+    (60000, 200, 40, 0.3, 8, 2000), (60000, 200, 40, 0.3, 16, 2000),
+    # a ragged last group
+    (41000, 1000, 60, 0.7, 8, 3000)])
+def test_multiset_planned_spmm_matches_oracle(torch, bbl, n, R, q, p, nvec, block_rows):
+    """The multi-set plan (fewer than three column blocks fit in LDS per set):
+    nsets sets of the group's busiest blocks staged one after the other, the
+    rest gathered; the same sums in another order, so the dot-product bound
+    holds entry by entry; bitwise reproducible."""
+    note("multi-set planned spmm n=%d block_rows=%d nvec=%d p=%.1f" % (n, block_rows, nvec, p))
+    H = synthgen.generate(n, R, q, p, 13)
+    Hd = bbl.DeviceCSR.from_host(H, "float32", block_rows=block_rows)
+    plan = bbl.spmm_plan(Hd, nvec)
+    bk = 8 if nvec == 16 else nvec
+    s = min(5, (160 * 1024 // (bk * 4) - 1) // block_rows)
+    assert plan.c.nsets > 0 and plan.slots == s
+    assert plan.c.nsets == min(16 // s, -(-10 // s))
+    V = synthgen.gaussian_block(H.n, nvec, 5)
+    Vd = dev(torch, V.astype(np.float32))
+    W = bbl.spmm_planned(plan, Vd).double().cpu().numpy()
+    W2 = bbl.spmm_planned(plan, Vd).double().cpu().numpy()
+    assert np.array_equal(W, W2)
+    Href = H.as_float32_values()
+    Vr = V.astype(np.float32).astype(np.float64)
+    z = np.diff(H.row_ptr)[:, None]
+    bound = gamma(z + 2, U32) * oracle.spmm_abs(Href, Vr) + 1e-300
+    assert np.all(np.abs(W - oracle.spmm(Href, Vr)) <= bound)
+
+
+def test_multiset_planned_solve(torch, bbl):
+    """A b = 16 FP32 solve with thick restart through the multi-set plan
+    (2000-row sectors, the n = 2e7 shape in small): host FP64 residuals and
+    the same eigenvalues as through the plain CSR kernel."""
+    note("multi-set planned solve b=16")
+    H = synthgen.generate(60000, 2000, 105, 0.7, 4)
+    Hp = bbl.DeviceCSR.from_host(H, "float32", block_rows=2000)
+    plan = bbl.spmm_plan(Hp, 16)
+    assert plan.c.nsets > 0
+    P = bbl.random_pivot(H.n, 16, synthgen.pivot_key(3))
+    rp = bbl.block_lanczos(Hp, P, 10, 1e-6, m_max=20, restart_keep=32, spmm_plan=plan)
+    r = bbl.block_lanczos(Hp, P, 10, 1e-6, m_max=20, restart_keep=32)
+    assert rp.converged and r.converged, (rp.stats, r.stats)
+    hn = rp.stats["hnorm_est"]
+    np.testing.assert_allclose(rp.eigvals, r.eigvals, rtol=0, atol=2e-6 * hn)
+    res = oracle.ritz_residuals(H.as_float32_values(), rp.eigvecs.cpu().numpy(), rp.eigvals)
+    assert np.all(res <= 1e-6 * hn), res / hn
+
+
 def test_spmm_plan_layout_and_errors(torch, bbl):
     note("spmm plan layout")
     H = synthgen.generate(12000, 400, 20, 0.7, 3)
