@@ -156,6 +156,7 @@ def _per_dispatch(rows, counter, match):
 
 
 SPMM_PASSES = ("k_spmm_pipe12<8, false>", "k_spmm_rest<8, false>")
+REORTH_BLOCKS = 50   # basis blocks of the counter runs' gram and update
 
 
 def write_traffic(fetch_dir, write_dir):
@@ -193,6 +194,26 @@ def write_traffic(fetch_dir, write_dir):
     with open(path, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
+    # reorthogonalisation kernels on a REORTH_BLOCKS-block FP32 basis of the
+    # same n: the gram reads the basis and W' (FP64), the update reads both
+    # and writes W'
+    n, b, M = H.n, w.nvec, REORTH_BLOCKS * w.nvec
+    kern = {"gram": ("k_gram_mfma8", 4 * n * M + 8 * n * b),
+            "update": ("k_update_v<float, double, double", 4 * n * M + 16 * n * b)}
+    rr = {"workload": "FP32 basis of %d blocks of %d vectors, n=%d; FP64 W'" % (REORTH_BLOCKS, b, n),
+          "tallskinny_source_hash": source_hash("tallskinny.hip"),
+          "fetch_scale": fetch_scale, "write_scale": write_scale}
+    for name, (match, alg_b) in kern.items():
+        f_k, nf_k = _per_dispatch(fr, "FETCH_SIZE", match)
+        w_k, nw_k = _per_dispatch(wr_, "WRITE_SIZE", match)
+        rd_k, wr_k = f_k * 1024.0 * fetch_scale, w_k * 1024.0 * write_scale
+        rr[name] = {"kernel_match": match, "fetch_kib": f_k, "write_kib": w_k,
+                    "hbm_read_bytes": rd_k, "hbm_write_bytes": wr_k, "alg_bytes": alg_b,
+                    "traffic_over_alg": (rd_k + wr_k) / alg_b, "dispatches": [nf_k, nw_k]}
+    path = os.path.join(ROOT, "profiles", "reorth_mid_n2e6_traffic.json")
+    with open(path, "w") as f:
+        json.dump(rr, f, indent=1)
+    print(json.dumps(rr))
 
 
 def kernels_only(torch, bbl, Hd, b, iters=10):
@@ -201,10 +222,14 @@ def kernels_only(torch, bbl, Hd, b, iters=10):
     plan = bbl.spmm_plan(Hd, b)
     for _ in range(iters):
         bbl.spmm_planned(plan, V, W)
-    Xb = torch.randn((50, Hd.n, b), dtype=torch.float32, device="cuda")
+    Xb = torch.randn((REORTH_BLOCKS, Hd.n, b), dtype=torch.float32, device="cuda")
     Y = torch.randn((Hd.n, b), dtype=torch.float64, device="cuda")
     for _ in range(3):
-        bbl.gram(Xb, 50, b, Y)
+        bbl.gram(Xb, REORTH_BLOCKS, b, Y)
+    C = torch.randn((REORTH_BLOCKS * b, b), dtype=torch.float64, device="cuda")
+    Y2 = torch.empty_like(Y)
+    for _ in range(3):
+        bbl.block_update(Xb, REORTH_BLOCKS, b, C, -1.0, Y, 1.0, Y2)
     a = torch.randn(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     c = torch.empty_like(a)
     for _ in range(iters):

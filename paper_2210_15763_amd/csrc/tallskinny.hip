@@ -37,6 +37,16 @@ template <typename T>
 __device__ __forceinline__ double ld(const T *p) { return (double)*p; }
 
 constexpr int kTilesPerWG = 8;   // 16-column tiles of X handled by one gram WG
+#ifndef BBL_GRAM_WAVES
+#define BBL_GRAM_WAVES 1
+#endif
+#ifndef BBL_GRAM_WAVE_TARGET
+#define BBL_GRAM_WAVE_TARGET 6144
+#endif
+// FP64-MFMA gram over 8-wide FP32 blocks: waves per workgroup, and the
+// number of waves (row chunks x column groups) the grid is sized to
+constexpr int kGramWaves = BBL_GRAM_WAVES;
+constexpr int kGramWaveTarget = BBL_GRAM_WAVE_TARGET;
 
 // partial[p][m][c] for p = blockIdx.x (row chunk), m in this WG's tile group.
 template <typename XT, typename YT, int NT>
@@ -258,17 +268,24 @@ __device__ __forceinline__ Vec<T, N> vload(const T *p) {
 // L2 then serves Y to all of them) and close in dispatch order.  Linear id i:
 // super-block i / (8 gy) holds row chunks 8 sb .. 8 sb + 7, inside it
 // column group (i % (8 gy)) / 8 and row chunk 8 sb + i % 8.
-template <int CG, int U>
-__global__ __launch_bounds__(64) void k_gram_mfma8(int64_t n, const float *__restrict__ X, int M,
-                                                   int64_t xstride, const double *__restrict__ Y,
-                                                   int64_t chunk, int gx, int gy,
-                                                   double *__restrict__ partial,
-                                                   const int *__restrict__ when) {
+//
+// WPG waves per workgroup: the waves of one workgroup take WPG consecutive
+// column groups of the same row chunk (so they read the same rows of Y at
+// about the same time, from the CU's vector cache), gq = ceil(gy / WPG)
+// workgroups per row chunk in the order above.
+template <int CG, int U, int WPG>
+__global__ __launch_bounds__(64 * WPG) void k_gram_mfma8(int64_t n, const float *__restrict__ X,
+                                                         int M, int64_t xstride,
+                                                         const double *__restrict__ Y,
+                                                         int64_t chunk, int gx, int gy,
+                                                         double *__restrict__ partial,
+                                                         const int *__restrict__ when) {
   if (when && *when == 0) return;
-  const int sb = blockIdx.x / (8 * gy), rem = blockIdx.x % (8 * gy);
-  const int cy = rem / 8, cx = sb * 8 + rem % 8;
-  if (cx >= gx) return;
-  const int l = threadIdx.x;
+  const int gq = (gy + WPG - 1) / WPG;
+  const int sb = blockIdx.x / (8 * gq), rem = blockIdx.x % (8 * gq);
+  const int cy = (rem / 8) * WPG + (int)(threadIdx.x >> 6), cx = sb * 8 + rem % 8;
+  if (cx >= gx || cy >= gy) return;
+  const int l = threadIdx.x & 63;
   const int k = l >> 4, g = (l & 15) >> 2, e = l & 3;
   const int c00 = cy * (64 * CG);
   int64_t xo[CG];
@@ -699,15 +716,15 @@ int gram_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const 
     // 45, 90 and 181 blocks run fastest with 1024, 512 and 256 row chunks,
     // 5.1-5.3 TB/s; 20 blocks with 2048 chunks, 4.8 TB/s against 3.6 with
     // 1024)
-    constexpr int CG = 1, U = 2;
+    constexpr int CG = 1, U = 2, WPG = kGramWaves;
     const int gy = (M + 64 * CG - 1) / (64 * CG);
-    int64_t gx = std::min<int64_t>(2048, ceil_div(6144, gy));
+    int64_t gx = std::min<int64_t>(2048, ceil_div(kGramWaveTarget, gy));
     gx = std::max<int64_t>(1, std::min<int64_t>(gx, ceil_div(n, 256)));
     gx = std::min<int64_t>(gx, std::max(1, max_partials));
     int64_t chunk = ceil_div(ceil_div(n, gx), 4 * U) * (4 * U);
     gx = ceil_div(n, chunk);
-    const int64_t grid = ceil_div(gx, 8) * 8 * gy;
-    hipLaunchKernelGGL((k_gram_mfma8<CG, U>), dim3((unsigned)grid), dim3(64), 0, s, n,
+    const int64_t grid = ceil_div(gx, 8) * 8 * ceil_div(gy, WPG);
+    hipLaunchKernelGGL((k_gram_mfma8<CG, U, WPG>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, n,
                        (const float *)X, M, xstride, (const double *)Y, chunk, (int)gx, gy,
                        partial, when);
     check_launch("k_gram_mfma8");
