@@ -47,6 +47,30 @@ constexpr int kTilesPerWG = 8;   // 16-column tiles of X handled by one gram WG
 // number of waves (row chunks x column groups) the grid is sized to
 constexpr int kGramWaves = BBL_GRAM_WAVES;
 constexpr int kGramWaveTarget = BBL_GRAM_WAVE_TARGET;
+#ifndef BBL_G16_CG
+#define BBL_G16_CG 1
+#endif
+#ifndef BBL_G16_U
+#define BBL_G16_U 2
+#endif
+#ifndef BBL_G16_WAVES
+#define BBL_G16_WAVES 6144
+#endif
+#ifndef BBL_U16_U
+#define BBL_U16_U 4
+#endif
+#ifndef BBL_U16_WAVES
+#define BBL_U16_WAVES 8192
+#endif
+// 16-wide blocks on FP64 matrix cores: gram blocks per wave, 16-row tiles
+// in flight and the waves its grid is sized to; update tiles per wave step
+// and grid waves (each wave strides over the row tiles).  Measured at
+// n = 2e7 (1 / 8 / 20 / 40 blocks): gram 6.0 / 4.4 / 3.8 / 3.6 TB/s with one
+// block per wave (two or four per wave: slower, fewer waves resident);
+// update 5.3 / 5.0 / 4.7 / 4.4 TB/s (2 / 8 / 20 / 40 blocks)
+constexpr int kG16CG = BBL_G16_CG, kG16U = BBL_G16_U, kG16Waves = BBL_G16_WAVES;
+constexpr int kU16U = BBL_U16_U, kU16Waves = BBL_U16_WAVES;
+inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 // partial[p][m][c] for p = blockIdx.x (row chunk), m in this WG's tile group.
 template <typename XT, typename YT, int NT>
@@ -213,6 +237,229 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const XT *X, int bx,
         double v = alpha * acc[u][q];
         if (beta != 0.0) v = fma(beta, (double)Yin[r * ny + c], v);
         Yout[r * ny + c] = (YOT)v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 16-wide blocks on v_mfma_f64_4x4x4f64.  At b = 16 the products carry 8 flop
+// per basis byte, near the FP64 ridge, so the VALU forms (scalar C operands,
+// 256 FMAs per row and block) run far below the HBM rate; these kernels put
+// the four independent 4x4x4 products of one instruction on four groups of
+// four rows (operand layout as in k_gram_mfma8: A[i][k] at lane 16k + 4g + i,
+// B[k][j] at 16k + 4g + j, D[i][j] at 16i + 4g + j) and read 16-row tiles,
+// four lanes per row, each lane one 4-column quarter (one float4 or two
+// double2): a load instruction reads 16 whole rows, one contiguous run.
+
+__device__ __forceinline__ void ld4(const float *p, float (&v)[4]) {
+  const float4 t = *reinterpret_cast<const float4 *>(p);
+  v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
+__device__ __forceinline__ void ld4(const double *p, double (&v)[4]) {
+  const double2 a = reinterpret_cast<const double2 *>(p)[0];
+  const double2 b = reinterpret_cast<const double2 *>(p)[1];
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+template <typename T>
+__device__ __forceinline__ void st4(T *p, const double (&v)[4]) {
+  if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<float4 *>(p) = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+  } else {
+    reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
+    reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
+  }
+}
+
+// Gram C = X^T Y, X: nblk blocks of 16 columns, Y: n x 16.  Lane l reads row
+// t + (l >> 2) of each 16-row tile, columns 4 (l & 3) .. +3 of X and of Y.
+// As an A operand (k = l >> 4, g = (l >> 2) & 3, i = l & 3) component q of
+// the X quarter is X[t + 4k + g][4i + q]; as a B operand component h of the
+// Y quarter is Y[t + 4k + g][4j + h] (j = l & 3): product g sums over the
+// rows t + 4k + g, k = 0..3, and D(q, h)[i][j] = C[4i + q][4j + h].  The four
+// products' sums are added by two lane shuffles at the end.  One wave takes
+// CG blocks over one row chunk, U tiles in flight; workgroup order as in
+// k_gram_mfma8 (the column groups of a row chunk on one XCD).
+template <typename XT, typename YT, int CG, int U>
+__global__ __launch_bounds__(64) void k_gram_mfma16(int64_t n, const XT *__restrict__ X, int nblk,
+                                                    int64_t xstride, const YT *__restrict__ Y,
+                                                    int64_t chunk, int gx, int gy,
+                                                    double *__restrict__ partial,
+                                                    const int *__restrict__ when) {
+  if (when && *when == 0) return;
+  const int sb = blockIdx.x / (8 * gy), rem = blockIdx.x % (8 * gy);
+  const int cy = rem / 8, cx = sb * 8 + rem % 8;
+  if (cx >= gx) return;
+  const int l = threadIdx.x;
+  const int rl = l >> 2, e = l & 3;
+  const int b0 = cy * CG;
+  double acc[CG][4][4];
+#pragma unroll
+  for (int c = 0; c < CG; ++c)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int h = 0; h < 4; ++h) acc[c][q][h] = 0.0;
+  const int64_t r0 = (int64_t)cx * chunk;
+  const int64_t r1 = min(n, r0 + chunk);
+  for (int64_t t = r0; t < r1; t += 16 * U) {
+    XT x[U][CG][4];
+    YT y[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = t + 16 * u + rl;
+      const bool ok = r < r1;
+      if (ok) ld4(Y + r * 16 + 4 * e, y[u]);
+      else
+#pragma unroll
+        for (int h = 0; h < 4; ++h) y[u][h] = YT(0);
+#pragma unroll
+      for (int c = 0; c < CG; ++c) {
+        if (ok && b0 + c < nblk) ld4(X + (int64_t)(b0 + c) * xstride + r * 16 + 4 * e, x[u][c]);
+        else
+#pragma unroll
+          for (int q = 0; q < 4; ++q) x[u][c][q] = XT(0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < CG; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int h = 0; h < 4; ++h)
+            acc[c][q][h] = __builtin_amdgcn_mfma_f64_4x4x4f64((double)x[u][c][q], (double)y[u][h],
+                                                              acc[c][q][h], 0, 0, 0);
+  }
+#pragma unroll
+  for (int c = 0; c < CG; ++c)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        double v = acc[c][q][h];
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 8, 64);
+        acc[c][q][h] = v;
+      }
+  if (((l >> 2) & 3) == 0) {
+    const int i = l >> 4, j = l & 3;
+    const int64_t M = (int64_t)nblk * 16;
+    double *out = partial + (int64_t)cx * M * 16;
+#pragma unroll
+    for (int c = 0; c < CG; ++c)
+      if (b0 + c < nblk)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double v4[4] = {acc[c][q][0], acc[c][q][1], acc[c][q][2], acc[c][q][3]};
+          st4(out + ((int64_t)(b0 + c) * 16 + 4 * i + q) * 16 + 4 * j, v4);
+        }
+  }
+}
+
+// Yout = beta Yin + alpha X C over 16-wide blocks, C: (16 nblk) x 16.  A
+// operand (k = l >> 4, g = (l >> 2) & 3, i = l & 3): lane l reads row
+// t + (l & 15) of the tile, basis columns 4k .. 4k + 3 (component q is column
+// 4k + q); B operand (q, h): C[16 blk + 4k + q][4j + h], j = l & 3, which each
+// lane loads per block (four 32-byte runs); D(h)[i][j] at lane 16i + 4g + j is
+// Yout[t + 4g + i][4j + h].  A wave strides over tiles of 16 U rows.
+// GRAM: the wave also sums the Gram matrix of the values it stored: as an A
+// (or B) operand, lane 16k + 4g + j holds row t + 4g + k, columns 4j + h, so
+// the output registers feed sixteen more products per tile directly;
+// gpart[wave][16][16], the four groups' sums added by lane shuffles.
+template <typename XT, typename YIT, typename YOT, int U, bool GRAM>
+__global__ __launch_bounds__(64) void k_update_mfma16(int64_t n, const XT *__restrict__ X, int nblk,
+                                                      int64_t xstride, const double *__restrict__ C,
+                                                      double alpha, const YIT *Yin, double beta,
+                                                      YOT *Yout, const int *__restrict__ when,
+                                                      double *__restrict__ gpart) {
+  if (when && *when == 0) return;
+  const int l = threadIdx.x;
+  const int kq = l >> 4, e = l & 3, ra = l & 15;     // A operand: quarter kq of row ra
+  const int rd = 4 * ((l >> 2) & 3) + (l >> 4);      // D: row of the tile this lane holds
+  double gacc[GRAM ? 4 : 1][GRAM ? 4 : 1];
+  if constexpr (GRAM) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int h = 0; h < 4; ++h) gacc[q][h] = 0.0;
+  }
+  const int64_t tiles = (n + 16 * U - 1) / (16 * U);
+  for (int64_t tt = blockIdx.x; tt < tiles; tt += gridDim.x) {
+    const int64_t t = tt * (16 * U);
+    double acc[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int h = 0; h < 4; ++h) acc[u][h] = 0.0;
+    for (int blk = 0; blk < nblk; ++blk) {
+      double cb[4][4];
+      const double *cp = C + ((int64_t)blk * 16 + 4 * kq) * 16 + 4 * e;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ld4(cp + q * 16, cb[q]);
+      XT x[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = t + 16 * u + ra;
+        if (r < n) ld4(X + (int64_t)blk * xstride + r * 16 + 4 * kq, x[u]);
+        else
+#pragma unroll
+          for (int q = 0; q < 4; ++q) x[u][q] = XT(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int h = 0; h < 4; ++h)
+            acc[u][h] = __builtin_amdgcn_mfma_f64_4x4x4f64((double)x[u][q], cb[q][h], acc[u][h],
+                                                           0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = t + 16 * u + rd;
+      double o[4] = {0.0, 0.0, 0.0, 0.0};
+      if (r < n) {
+        if (beta != 0.0) {
+          YIT yi[4];
+          ld4(Yin + r * 16 + 4 * e, yi);
+#pragma unroll
+          for (int h = 0; h < 4; ++h) o[h] = fma(beta, (double)yi[h], alpha * acc[u][h]);
+        } else {
+#pragma unroll
+          for (int h = 0; h < 4; ++h) o[h] = alpha * acc[u][h];
+        }
+        st4(Yout + r * 16 + 4 * e, o);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) o[h] = (double)(YOT)o[h];  // the values as stored
+      }
+      if constexpr (GRAM) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int h = 0; h < 4; ++h)
+            gacc[q][h] = __builtin_amdgcn_mfma_f64_4x4x4f64(o[q], o[h], gacc[q][h], 0, 0, 0);
+      }
+    }
+  }
+  if constexpr (GRAM) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        double v = gacc[q][h];
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 8, 64);
+        gacc[q][h] = v;
+      }
+    if (((l >> 2) & 3) == 0) {
+      const int i = l >> 4, j = l & 3;
+      double *out = gpart + (int64_t)blockIdx.x * 256;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double v4[4] = {gacc[q][0], gacc[q][1], gacc[q][2], gacc[q][3]};
+        st4(out + (4 * i + q) * 16 + 4 * j, v4);
       }
     }
   }
@@ -688,11 +935,35 @@ int gram_valu(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const Y
   return (int)gx;
 }
 
+template <typename XT, typename YT, int CG, int U>
+int gram_mfma16(int64_t n, const XT *X, int nblk, int64_t xstride, const YT *Y, double *partial,
+                int max_partials, const int *when, hipStream_t s) {
+  const int gy = (int)ceil_div(nblk, CG);
+  int64_t gx = std::min<int64_t>(2048, ceil_div(kG16Waves, gy));
+  gx = std::max<int64_t>(1, std::min<int64_t>(gx, ceil_div(n, 16 * U)));
+  gx = std::min<int64_t>(gx, std::max(1, max_partials));
+  const int64_t chunk = ceil_div(ceil_div(n, gx), 16 * U) * (16 * U);
+  gx = ceil_div(n, chunk);
+  const int64_t grid = ceil_div(gx, 8) * 8 * gy;
+  hipLaunchKernelGGL((k_gram_mfma16<XT, YT, CG, U>), dim3((unsigned)grid), dim3(64), 0, s, n, X,
+                     nblk, xstride, Y, chunk, (int)gx, gy, partial, when);
+  check_launch("k_gram_mfma16");
+  return (int)gx;
+}
+
 template <typename XT, typename YT>
 int gram_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const YT *Y, int ny,
                double *partial, int max_partials, const int *when, hipStream_t s) {
   const int M = nblk * bx;
   constexpr bool f32 = sizeof(XT) == 4;
+  if (bx == 16 && ny == 16 && aligned16(X) && aligned16(Y)) {
+    // one block with float32 operands (A_J = V_J^T W) streams fastest with
+    // one tile in flight (4.6 against 3.4 TB/s at n = 2e7)
+    if (nblk == 1 && sizeof(YT) == 4)
+      return gram_mfma16<XT, YT, 1, 1>(n, X, nblk, xstride, Y, partial, max_partials, when, s);
+    return gram_mfma16<XT, YT, kG16CG, kG16U>(n, X, nblk, xstride, Y, partial, max_partials,
+                                              when, s);
+  }
   if (nblk == 1 && ny == bx && (bx == 4 || bx == 8)) {
     // one block: rows across lanes, 1024 waves at most (4096 ran slower at
     // n = 2e6: 36 against 30 us)
@@ -788,6 +1059,25 @@ void update_valu(int64_t n, const XT *X, int nblk, int64_t xstride, const double
   }
 #undef BBL_UPDV
   check_launch("k_update_v");
+}
+
+// 16-wide blocks on FP64 matrix cores; the fused Gram needs (P + P/8 + 64)
+// x 256 doubles of gpart (partials and the reduction's second stage).
+template <typename XT, typename YIT, typename YOT>
+int update_mfma16(int64_t n, const XT *X, int nblk, int64_t xstride, const double *C,
+                  double alpha, const YIT *Yin, double beta, YOT *Yout, const int *when,
+                  double *gpart, size_t gcap_doubles, hipStream_t s) {
+  constexpr int U = kU16U;
+  const int64_t P = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 16 * U), kU16Waves));
+  if (gpart && (size_t)(P + P / 8 + 64) * 256 > gcap_doubles) gpart = nullptr;
+  if (gpart)
+    hipLaunchKernelGGL((k_update_mfma16<XT, YIT, YOT, U, true>), dim3((unsigned)P), dim3(64), 0, s,
+                       n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart);
+  else
+    hipLaunchKernelGGL((k_update_mfma16<XT, YIT, YOT, U, false>), dim3((unsigned)P), dim3(64), 0,
+                       s, n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, nullptr);
+  check_launch("k_update_mfma16");
+  return gpart ? (int)P : 0;
 }
 
 // gpart: where the Gram partials of Yout may go (nullptr: none wanted).
@@ -896,10 +1186,25 @@ int launch_update_gram_when(int64_t n, const void *X, int xdtype, int bx, int nb
   if (nblk <= 0) {  // empty product: Yout = beta * Yin
     BBL_REQUIRE(false, "update: empty X");
   }
+  const bool xf = xdtype == BBL_F32, yif = yindtype == BBL_F32, yof = youtdtype == BBL_F32;
+  if (bx == 16 && ny == 16 && aligned16(X) && aligned16(C) && aligned16(Yout) &&
+      (beta == 0.0 || aligned16(Yin))) {
+#define BBL_U16(XT, YIT, YOT)                                                                 \
+  return update_mfma16(n, (const XT *)X, nblk, xstride, C, alpha, (const YIT *)Yin, beta,     \
+                       (YOT *)Yout, when, gpart, gcap_doubles, s)
+    if (xf && yif && yof) BBL_U16(float, float, float);
+    else if (xf && yif && !yof) BBL_U16(float, float, double);
+    else if (xf && !yif && yof) BBL_U16(float, double, float);
+    else if (xf && !yif && !yof) BBL_U16(float, double, double);
+    else if (!xf && yif && yof) BBL_U16(double, float, float);
+    else if (!xf && yif && !yof) BBL_U16(double, float, double);
+    else if (!xf && !yif && yof) BBL_U16(double, double, float);
+    else BBL_U16(double, double, double);
+#undef BBL_U16
+  }
   // room for the partials and the reduction's stage-1 sums behind them
   const int64_t P = ceil_div(n, 256 * kUpdRPL);
   if (gpart && (size_t)(P + P / 8 + 64) * ny * ny > gcap_doubles) gpart = nullptr;
-  const bool xf = xdtype == BBL_F32, yif = yindtype == BBL_F32, yof = youtdtype == BBL_F32;
 #define BBL_UPD(XT, YIT, YOT)                                                                 \
   return update_typed(n, (const XT *)X, bx, nblk, xstride, C, ny, alpha, (const YIT *)Yin,    \
                       beta, (YOT *)Yout, when, gpart, s)

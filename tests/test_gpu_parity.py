@@ -375,7 +375,9 @@ def test_spmm_bitwise_reproducible(torch, bbl):
                                              (8, 7, 8, False), (8, 9, 8, True), (8, 37, 8, True),
                                              (8, 1, 8, True), (8, 1, 8, False), (4, 1, 4, True),
                                              (8, 23, 10, True), (8, 4, 10, False),
-                                             (4, 20, 4, False)])
+                                             (4, 20, 4, False), (16, 1, 16, True),
+                                             (16, 1, 16, False), (16, 3, 16, False),
+                                             (16, 5, 16, True), (16, 40, 16, True)])
 def test_gram_and_update_match_numpy(torch, bbl, bx, nblk, ny, xf32):
     """(5003 rows with 16 or more blocks take the wave-split update.)"""
     note("gram/update bx=%d nblk=%d ny=%d f32=%s" % (bx, nblk, ny, xf32))
@@ -401,6 +403,21 @@ def test_gram_and_update_match_numpy(torch, bbl, bx, nblk, ny, xf32):
     Out32 = torch.empty((n, ny), dtype=torch.float32, device="cuda")
     bbl.block_update(Xd, nblk, bx, dev(torch, Cm), 1.0, None, 0.0, Out32)
     np.testing.assert_allclose(Out32.double().cpu().numpy(), Xwide @ Cm, rtol=2e-6, atol=2e-6 * np.abs(Xwide @ Cm).max())
+
+
+@pytest.mark.parametrize("bx,nblk", [(16, 1), (16, 2), (8, 1)])
+def test_gram_of_float32_operands_matches_numpy(torch, bbl, bx, nblk):
+    """The recurrence's A_J = V_J^T W takes both operands in float32 (the
+    SpMM's output); 16-wide blocks run it on FP64 matrix cores."""
+    note("gram f32 x f32 bx=%d nblk=%d" % (bx, nblk))
+    rng = np.random.default_rng(77 + bx + nblk)
+    n = 4099
+    Xb = rng.standard_normal((nblk, n, bx)).astype(np.float32)
+    Y = rng.standard_normal((n, bx)).astype(np.float32)
+    C = bbl.gram(dev(torch, Xb), nblk, bx, dev(torch, Y)).cpu().numpy()
+    Xwide = np.concatenate(list(Xb.astype(np.float64)), axis=1)
+    Cref = Xwide.T @ Y.astype(np.float64)
+    assert np.max(np.abs(C - Cref)) <= 64 * n * U64 * np.max(np.abs(Xwide).T @ np.abs(Y))
 
 
 # ---------------------------------------------------------- band eigensolver
@@ -794,6 +811,24 @@ def test_thick_restart_matches_oracle_and_dense(torch, bbl, seed, b, keep, m_max
     hn = r.stats["hnorm_est"]
     assert np.max(np.abs(Q.T @ Q - np.eye(m * b))) <= 1e-12
     assert np.max(np.abs(Q.T @ oracle.spmm(H, Q) - T)) <= 1e-10 * hn
+
+
+def test_fp64_sixteen_vector_solve_matches_oracle_and_dense(torch, bbl):
+    """b = 16 in FP64 (values, basis and every product on the matrix-core
+    kernels for 16-wide blocks): eigenvalues against the oracle on the same
+    pivot and against a dense eigensolve at 1e-10, residuals on the host."""
+    note("FP64 b=16 solve vs oracle")
+    H = synthgen.generate(3000, 300, 20, 0.7, 21)
+    P = synthgen.gaussian_block(3000, 16, 5)
+    r = bbl.block_lanczos(bbl.DeviceCSR.from_host(H, "float64"), dev(torch, P), 10, 1e-10,
+                          m_max=120, check_every=1)
+    ro = oracle.block_lanczos(H, P, 10, 1e-10, 120)
+    lam = np.linalg.eigvalsh(H.to_dense())[:10]
+    assert r.converged and ro.converged
+    np.testing.assert_allclose(r.eigvals, ro.eigvals, rtol=1e-10)
+    np.testing.assert_allclose(r.eigvals, lam, rtol=1e-10)
+    res = oracle.ritz_residuals(H, r.eigvecs.cpu().numpy(), r.eigvals)
+    assert np.all(res <= 1e-10 * r.stats["hnorm_est"]), res / r.stats["hnorm_est"]
 
 
 def test_thick_restart_fp32_planned_sixteen_vectors(torch, bbl):
