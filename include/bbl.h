@@ -247,7 +247,8 @@ int bbl_spmm(const bbl_csr *H, const void *V, void *W, int32_t nvec, int32_t vec
  * Planned SpMM: the same product for a matrix with the block_rows locality
  * hint, from its prepared form.  bbl_spmm_plan_size returns the device bytes
  * a plan of (H, nvec, vec_dtype) needs, or 0 when no plan can be made
- * (block_rows == 0, nvec not in {1, 2, 4, 8, 10, 16}, or one column block of
+ * (block_rows == 0; nvec not in {1, 2, 4, 8, 10, 16} and not 12 with
+ * float32 vectors; or one column block of
  * V -- block_rows * nvec elements; block_rows * 8 floats plus one row for
  * 16 float32 vectors on float32 values -- larger than the 160 KB of LDS).
  * bbl_spmm_plan_build fills `mem` (device, caller-owned, `bytes` >= the size)

@@ -361,7 +361,9 @@ void spmm_dispatch_b(const bbl_csr &H, const XT *X, YT *Y, int nvec, hipStream_t
       BBL_SPMM_CASE(4)
       BBL_SPMM_CASE(8)
       BBL_SPMM_CASE(10)
+      BBL_SPMM_CASE(12)
       BBL_SPMM_CASE(16)
+      BBL_SPMM_CASE(32)
       default:
         hipLaunchKernelGGL((k_spmm_generic<VT, XT, AT, YT, LPR>), dim3(grid), dim3(256), 0, s, nr,
                            rp, H.col, val, X, Yc, nvec);
@@ -1642,6 +1644,10 @@ void planned_dispatch(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s)
     case 4: planned_launch<VT, XT, 4>(P, X, Y, s); break;
     case 8: planned_launch<VT, XT, 8>(P, X, Y, s); break;
     case 10: planned_launch<VT, XT, 10>(P, X, Y, s); break;
+    case 12:  // float32 only (float64 rows of 12 exceed the register budget)
+      if constexpr (std::is_same<XT, float>::value) planned_launch<VT, XT, 12>(P, X, Y, s);
+      else throw Error{BBL_E_INVALID, "planned SpMM: 12 float64 vectors are not planned"};
+      break;
     case 16: planned_launch<VT, XT, 16>(P, X, Y, s); break;
     default: throw Error{BBL_E_INVALID, "planned SpMM: unsupported nvec"};
   }
@@ -1754,7 +1760,9 @@ int spmm_plan_slots(const bbl_csr &H, int nvec, int vec_dtype) {
   if (H.block_rows <= 0) return 0;
   int ms, mn;
   if (plan_multi(H, nvec, vec_dtype, &ms, &mn)) return ms;
-  if (!(nvec == 1 || nvec == 2 || nvec == 4 || nvec == 8 || nvec == 10 || nvec == 16)) return 0;
+  if (!(nvec == 1 || nvec == 2 || nvec == 4 || nvec == 8 || nvec == 10 || nvec == 16 ||
+        (nvec == 12 && vec_dtype == BBL_F32)))
+    return 0;
   if (nvec == 16 && vec_dtype == BBL_F32 && H.val_dtype == BBL_F32 && plan_desc(H)) {
     // FP32, 16 vectors: the pipelined kernels take the columns in two halves
     // of 8, so a slot holds 8 columns of a block (beside the all-zero row)

@@ -50,7 +50,7 @@ def dev(torch, a):
 
 
 # ------------------------------------------------------------------- SpMM
-@pytest.mark.parametrize("nvec", [1, 3, 4, 8, 10, 16, 32])
+@pytest.mark.parametrize("nvec", [1, 3, 4, 8, 10, 12, 16, 32])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_spmm_matches_oracle_within_dot_product_bound(torch, bbl, nvec, prec):
     note("spmm n=20000 z~40 nvec=%d %s" % (nvec, prec))
@@ -84,7 +84,8 @@ def test_spmm_matches_oracle_within_dot_product_bound(torch, bbl, nvec, prec):
     # rows with most entries outside the staged blocks (several remote steps)
     (8, 400, "f32", 150, 0.7), (8, 400, "f32", 150, 0.1), (4, 400, "f32", 150, 0.3),
     (8, 1000, "f32", 105, 0.7), (10, 1000, "f32", 105, 0.7),
-    (16, 1000, "f32", 105, 0.7), (16, 333, "f32", 150, 0.3)])
+    (16, 1000, "f32", 105, 0.7), (16, 333, "f32", 150, 0.3), (12, 1000, "f32", 105, 0.7),
+    (12, 400, "f32", 150, 0.3)])
 def test_planned_spmm_matches_oracle(torch, bbl, nvec, block_rows, prec, q, p):
     """Rows reordered per group, partner blocks staged in LDS: the same sums
     in another order, so the dot-product bound holds entry by entry (groups
@@ -123,7 +124,10 @@ def test_planned_spmm_matches_oracle(torch, bbl, nvec, block_rows, prec, q, p):
     # hold, so many entries take the gather pass
     (60000, 200, 40, 0.3, 8, 2000), (60000, 200, 40, 0.3, 16, 2000),
     # a ragged last group
-    (41000, 1000, 60, 0.7, 8, 3000)])
+    (41000, 1000, 60, 0.7, 8, 3000),
+    # short rows (~50 entries, half of them far from the row's sector)
+    (60000, 2000, 25, 0.5, 8, 2000), (44000, 2000, 25, 0.5, 10, 2000),
+    (44000, 2000, 25, 0.5, 16, 2000)])
 def test_multiset_planned_spmm_matches_oracle(torch, bbl, n, R, q, p, nvec, block_rows):
     """The multi-set plan (fewer than three column blocks fit in LDS per set):
     nsets sets of the group's busiest blocks staged one after the other, the
