@@ -409,6 +409,27 @@ def test_gram_and_update_match_numpy(torch, bbl, bx, nblk, ny, xf32):
     np.testing.assert_allclose(Out32.double().cpu().numpy(), Xwide @ Cm, rtol=2e-6, atol=2e-6 * np.abs(Xwide @ Cm).max())
 
 
+@pytest.mark.parametrize("n", [1, 7, 17, 33])
+def test_sixteen_wide_products_on_tiny_row_counts(torch, bbl, n):
+    """The 16-wide matrix-core gram and update on fewer rows than one 16-row
+    tile (and a tile and a bit): masked rows contribute nothing; the update
+    also in place (Yin is Yout), as the recurrence calls it."""
+    note("16-wide gram/update n=%d" % n)
+    rng = np.random.default_rng(500 + n)
+    nblk = 3
+    Xb = rng.standard_normal((nblk, n, 16)).astype(np.float32)
+    Y = rng.standard_normal((n, 16))
+    Xd, Yd = dev(torch, Xb), dev(torch, Y)
+    Xwide = np.concatenate(list(Xb.astype(np.float64)), axis=1)
+    C = bbl.gram(Xd, nblk, 16, Yd).cpu().numpy()
+    np.testing.assert_allclose(C, Xwide.T @ Y, rtol=0, atol=64 * n * U64 * np.abs(Xwide).T.dot(np.abs(Y)).max() + 1e-300)
+    Cm = rng.standard_normal((nblk * 16, 16))
+    bbl.block_update(Xd, nblk, 16, dev(torch, Cm), -1.0, Yd, 1.0, Yd)
+    ref = Y - Xwide @ Cm
+    tol = 64 * nblk * 16 * U64 * (np.abs(Y) + np.abs(Xwide) @ np.abs(Cm))
+    assert np.all(np.abs(Yd.cpu().numpy() - ref) <= tol)
+
+
 @pytest.mark.parametrize("bx,nblk", [(16, 1), (16, 2), (8, 1)])
 def test_gram_of_float32_operands_matches_numpy(torch, bbl, bx, nblk):
     """The recurrence's A_J = V_J^T W takes both operands in float32 (the
