@@ -1024,23 +1024,61 @@ __global__ __launch_bounds__(1024) void k_spmm_planned(int64_t n, int64_t G, int
 
 // lanes per row and entries per lane and step: pass 1 takes ~90 % of each
 // row's entries, pass 2 ~10 %
+// T: the value and vector type (float, or double for float64 plans, whose
+// rows of B doubles are staged as they are); double values and 64-byte rows
+// (W: "wide") take fewer entries per lane in pass 2 and fewer LDS rows per
+// product group, within the register budget of a 1024-thread workgroup
+// (128 per lane).
 template <bool P2>
 constexpr int pipe_lpr() { return P2 ? 2 : 16; }
-template <bool P2>
-constexpr int pipe_le() { return P2 ? 16 : 8; }
+template <typename T, int B>
+constexpr bool pipe_wide() { return sizeof(T) == 8 || sizeof(T) * B >= 64; }
+template <bool P2, bool W = false>
+constexpr int pipe_le() { return P2 ? (W ? 8 : 16) : 8; }
+template <bool P2, bool W = false>
+constexpr int pipe_lg() { return W ? (P2 ? 1 : 2) : (P2 ? 2 : 4); }
+template <typename T>
+__device__ __forceinline__ T pipe_fma(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4) return fmaf(a, b, c);
+  else return fma(a, b, c);
+}
 
-template <int B, bool P2>
+template <int B, bool P2, typename T = float>
 struct PipeStage {
   static constexpr int LPR = pipe_lpr<P2>();
   static constexpr int NO = B / LPR > 0 ? B / LPR : 1;  // sums per lane after the reduction
-  static constexpr int LE = pipe_le<P2>();
+  static constexpr int LE = pipe_le<P2, pipe_wide<T, B>()>();
   uint4 lc[LE / 8];             // 16-bit LDS row indices
-  float lv[LE];
-  float yp[P2 ? NO : 1];        // the row's sums so far (pass 2)
+  T lv[LE];
+  T yp[P2 ? NO : 1];            // the row's sums so far (pass 2)
   int llo, lhi;                 // valid entries e: llo <= e < lhi
 };
 
-// NO consecutive floats from a 4 * NO-byte aligned address
+// NO consecutive values from a sizeof(T) * NO-byte aligned address
+template <int NO>
+__device__ __forceinline__ void pipe_vload(const double *p, double (&v)[NO]) {
+  if constexpr (NO % 2 == 0) {
+#pragma unroll
+    for (int i = 0; i < NO / 2; ++i) {
+      const double2 y = reinterpret_cast<const double2 *>(p)[i];
+      v[2 * i] = y.x, v[2 * i + 1] = y.y;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NO; ++i) v[i] = p[i];
+  }
+}
+template <int NO>
+__device__ __forceinline__ void pipe_vstore(double *p, const double (&v)[NO]) {
+  if constexpr (NO % 2 == 0) {
+#pragma unroll
+    for (int i = 0; i < NO / 2; ++i)
+      reinterpret_cast<double2 *>(p)[i] = make_double2(v[2 * i], v[2 * i + 1]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < NO; ++i) p[i] = v[i];
+  }
+}
 template <int NO>
 __device__ __forceinline__ void pipe_vload(const float *p, float (&v)[NO]) {
   if constexpr (NO == 4) {
@@ -1073,22 +1111,24 @@ __device__ __forceinline__ void pipe_vstore(float *p, const float (&v)[NO]) {
 // entries.  Every lane issues the same loads whether or not its entries exist
 // (those without any read position 0 and are masked by the range), so the
 // number of loads in flight is the same on every path.
-template <int B, bool P2>
-__device__ __forceinline__ void pipe_load(PipeStage<B, P2> &st, const uint16_t *__restrict__ lcol,
-                                          const float *__restrict__ val, int ql, int p0, int pl,
-                                          const float *yrow) {
-  constexpr int LE = PipeStage<B, P2>::LE;
+template <int B, bool P2, typename T>
+__device__ __forceinline__ void pipe_load(PipeStage<B, P2, T> &st,
+                                          const uint16_t *__restrict__ lcol,
+                                          const T *__restrict__ val, int ql, int p0, int pl,
+                                          const T *yrow) {
+  constexpr int LE = PipeStage<B, P2, T>::LE;
+  constexpr int PER = 16 / (int)sizeof(T);  // values per 16-byte load
   st.llo = p0 - ql;
   st.lhi = pl - ql;
   const int lq = st.lhi > 0 ? ql : 0;
 #pragma unroll
   for (int i = 0; i < LE / 8; ++i) st.lc[i] = reinterpret_cast<const uint4 *>(lcol + lq)[i];
 #pragma unroll
-  for (int i = 0; i < LE / 4; ++i) {
+  for (int i = 0; i < LE / PER; ++i) {
     const uint4 a = reinterpret_cast<const uint4 *>(val + lq)[i];
-    __builtin_memcpy(st.lv + 4 * i, &a, 16);
+    __builtin_memcpy(st.lv + PER * i, &a, 16);
   }
-  if constexpr (P2) pipe_vload<PipeStage<B, P2>::NO>(yrow, st.yp);
+  if constexpr (P2) pipe_vload<PipeStage<B, P2, T>::NO>(yrow, st.yp);
 }
 
 // Row loads from LDS.  With par = 1 (odd lanes of pass 1 at B = 8) the lane
@@ -1096,6 +1136,10 @@ __device__ __forceinline__ void pipe_load(PipeStage<B, P2> &st, const uint16_t *
 // (a + 4) % 8): the first 16-byte half it reads is the row's second, so the
 // lanes of one LDS read spread over twice as many bank positions.  The row
 // reduction undoes it.
+template <int B>
+__device__ __forceinline__ void pipe_row(const double *p, int, double (&v)[B]) {
+  RowIO<double, B>::load(p, v);
+}
 template <int B>
 __device__ __forceinline__ void pipe_row(const float *p, int par, float (&v)[B]) {
   if constexpr (B == 8) {
@@ -1121,15 +1165,15 @@ __device__ __forceinline__ int pipe_lidx(const uint4 (&c)[N], int e) {
 // bytes, piece item = thread + 1024 j:
 // issue() loads this thread's pieces J0 .. J0 + NJ - 1 into registers,
 // commit() writes them; every load is in flight before the first write.
-template <int B>
+template <int B, typename T = float>
 constexpr int stage_pieces() {
-  constexpr int bytes = (int)sizeof(float) * B;
+  constexpr int bytes = (int)sizeof(T) * B;
   constexpr int piece = bytes % 16 == 0 ? 16 : bytes % 8 == 0 ? 8 : 4;
   return (int)((kPlanLds / piece + 1023) / 1024);
 }
-template <int B, int J0 = 0, int NJ = stage_pieces<B>()>
+template <int B, typename T = float, int J0 = 0, int NJ = stage_pieces<B, T>()>
 struct StageFill {
-  static constexpr int bytes = (int)sizeof(float) * B;
+  static constexpr int bytes = (int)sizeof(T) * B;
   static constexpr int piece = bytes % 16 == 0 ? 16 : bytes % 8 == 0 ? 8 : 4;
   using P = unsigned __attribute__((ext_vector_type(piece / 4)));
   static_assert(NJ <= 64, "one bit per piece");
@@ -1140,7 +1184,7 @@ struct StageFill {
   // wait.  1 <= slots <= kPlanMaxSlots.
   __device__ __forceinline__ void issue(int64_t n, int64_t G, int slots,
                                         const int32_t *__restrict__ bl,
-                                        const float *__restrict__ X, int ld) {
+                                        const T *__restrict__ X, int ld) {
     constexpr int ppr = bytes / piece;  // pieces per row
     const int per_slot = (int)G * ppr;
     const int total = slots * per_slot;
@@ -1162,7 +1206,8 @@ struct StageFill {
       for (int q = 1; q < kPlanMaxSlots; ++q) bk = k == q ? bs[q] : bk;
       const int rin = off / ppr;
       const int64_t r = (int64_t)max(bk, 0) * G + rin;
-      tmp[j] = *reinterpret_cast<const P *>(X + min(r, n - 1) * ld + (off - rin * ppr) * (piece / 4));
+      tmp[j] = *reinterpret_cast<const P *>(X + min(r, n - 1) * ld +
+                                            (off - rin * ppr) * (piece / (int)sizeof(T)));
       if (item < total && bk >= 0 && r < n) keep |= uint64_t(1) << j;
     }
   }
@@ -1181,21 +1226,23 @@ struct StageFill {
 // One pass over group g, run by the whole workgroup (every thread calls it:
 // it holds a barrier).  pre: the set's blocks already loaded by this thread
 // (nullptr: loaded here).
-template <int B, bool P2>
+template <int B, bool P2, typename T = float>
 __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int slots,
                                          const int64_t *__restrict__ bases,
-                                         const float *__restrict__ val,
+                                         const T *__restrict__ val,
                                          const uint16_t *__restrict__ lcol,
                                          const int32_t *__restrict__ rdesc,
                                          const int32_t *__restrict__ bl,
-                                         const float *__restrict__ X, float *__restrict__ Y,
+                                         const T *__restrict__ X, T *__restrict__ Y,
                                          unsigned char *smem_raw, int ld,
-                                         const StageFill<B> *pre = nullptr) {
+                                         const StageFill<B, T> *pre = nullptr) {
   using Desc = int2;
-  using Stage = PipeStage<B, P2>;
+  using Stage = PipeStage<B, P2, T>;
+  // pass 1 at 8 float columns keeps odd lanes' sums rotated (pipe_row)
+  constexpr bool kRot = sizeof(T) == 4 && B == 8 && !P2;
   constexpr int LPR = Stage::LPR, NO = Stage::NO, LE = Stage::LE;
   static_assert(!P2 || B >= LPR, "pass 2 keeps whole components per lane");
-  const float *sX = reinterpret_cast<const float *>(smem_raw);
+  const T *sX = reinterpret_cast<const T *>(smem_raw);
   const int64_t r0 = g * G;
   const int nr = (int)(min(n, r0 + G) - r0);
   constexpr int RPW = kWave / LPR;
@@ -1205,13 +1252,13 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
   const int wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
   const int stride = nwaves * RPW;
   const int zrow = slots * (int)G;  // the all-zero LDS row
-  const int par = (B == 8 && LPR == 16) ? (sub & 1) : 0;
+  const int par = kRot ? (sub & 1) : 0;
   const int cb = NO * sub;          // first of the lane's sums after the reduction (B >= LPR)
   const int64_t base = bases[g] & ~(int64_t)7;
   const uint16_t *lc_b = lcol + base;
-  const float *v_b = val + base;
+  const T *v_b = val + base;
   const Desc *desc = reinterpret_cast<const Desc *>(rdesc) + r0;
-  float *Yw = Y + r0 * ld;
+  T *Yw = Y + r0 * ld;
   auto yrow = [&](int r) { return Yw + (int64_t)(r < nr ? r : 0) * ld + (B >= LPR ? cb : 0); };
 
   // this row group's first row (relative to r0) and the descriptor of its second
@@ -1222,7 +1269,7 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
   int pl = d0.y;
   int qlb = d0.x & ~(LE - 1);
   Stage cur;
-  pipe_load<B, P2>(cur, lc_b, v_b, qlb + LE * sub, d0.x, pl, yrow(row));
+  pipe_load<B, P2, T>(cur, lc_b, v_b, qlb + LE * sub, d0.x, pl, yrow(row));
 
   // stage the set's column blocks (loaded here unless the caller loaded them
   // already), then the all-zero row
@@ -1231,35 +1278,35 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
   } else {
     // in two halves where the whole would not fit in registers beside the
     // first stage
-    constexpr int kAll = stage_pieces<B>(), kHalf = (kAll + 1) / 2;
-    if constexpr (kAll <= 10) {
-      StageFill<B> fill;
+    constexpr int kAll = stage_pieces<B, T>(), kHalf = (kAll + 1) / 2;
+    if constexpr (kAll <= 10 && !pipe_wide<T, B>()) {
+      StageFill<B, T> fill;
       fill.issue(n, G, slots, bl, X, ld);
       fill.commit(smem_raw);
     } else {
-      StageFill<B, 0, kHalf> f0;
+      StageFill<B, T, 0, kHalf> f0;
       f0.issue(n, G, slots, bl, X, ld);
       f0.commit(smem_raw);
-      StageFill<B, kHalf, kAll - kHalf> f1;
+      StageFill<B, T, kHalf, kAll - kHalf> f1;
       f1.issue(n, G, slots, bl, X, ld);
       f1.commit(smem_raw);
     }
   }
-  if (threadIdx.x < B) reinterpret_cast<float *>(smem_raw)[(int64_t)zrow * B + threadIdx.x] = 0.0f;
+  if (threadIdx.x < B) reinterpret_cast<T *>(smem_raw)[(int64_t)zrow * B + threadIdx.x] = T(0);
   __syncthreads();
   if (row >= nr) return;  // no rows for this group of lanes
 
-  float acc[B];
+  T acc[B];
 #pragma unroll
-  for (int a = 0; a < B; ++a) acc[a] = 0.0f;
+  for (int a = 0; a < B; ++a) acc[a] = T(0);
   // A finished row's sums, stored at the start of the following step: a store
   // issued after the step's loads would have to complete before the next
   // step's first wait.
-  constexpr int NOUT = (B == 8 && LPR == 16) ? 1 : (B >= LPR ? NO : B);
-  float out[NOUT];
-  float *yp = nullptr;
+  constexpr int NOUT = kRot ? 1 : (B >= LPR ? NO : B);
+  T out[NOUT];
+  T *yp = nullptr;
   auto store_out = [&]() __attribute__((always_inline)) {
-    if constexpr (B == 8 && LPR == 16) {
+    if constexpr (kRot) {
       if ((sub & 1) == 0) yp[sub >> 1] = out[0];
     } else if constexpr (B >= LPR) {
       pipe_vstore<NO>(yp + cb, out);
@@ -1295,7 +1342,7 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
       store_out();
       yp = nullptr;
     }
-    pipe_load<B, P2>(nxt, lc_b, v_b, sqlb + LE * sub, sp0, spl, yrow(srow));
+    pipe_load<B, P2, T>(nxt, lc_b, v_b, sqlb + LE * sub, sp0, spl, yrow(srow));
     // the descriptor of the row after the one the next step works on
     {
       const int r = last ? nrow + stride : nrow;
@@ -1303,50 +1350,50 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
     }
     // the step's entries, LG LDS rows at a time (fewer in pass 2, whose lanes
     // hold more entries and sums)
-    constexpr int LG = P2 ? 2 : 4;
+    constexpr int LG = pipe_lg<P2, pipe_wide<T, B>()>();
 #pragma unroll
     for (int hf = 0; hf < LE; hf += LG) {
-      float lx[LG][B];
-      float h[LG];
+      T lx[LG][B];
+      T h[LG];
 #pragma unroll
       for (int e = 0; e < LG; ++e) {
         const bool ok = cur.llo <= hf + e && hf + e < cur.lhi;
         const int idx = ok ? pipe_lidx(cur.lc, hf + e) : zrow;
-        h[e] = ok ? cur.lv[hf + e] : 0.0f;
+        h[e] = ok ? cur.lv[hf + e] : T(0);
         pipe_row<B>(sX + idx * B, par, lx[e]);
       }
 #pragma unroll
       for (int e = 0; e < LG; ++e)
 #pragma unroll
-        for (int a = 0; a < B; ++a) acc[a] = fmaf(h[e], lx[e][a], acc[a]);
+        for (int a = 0; a < B; ++a) acc[a] = pipe_fma(h[e], lx[e][a], acc[a]);
     }
     if (last) {
       yp = Yw + (int64_t)row * ld;
-      if constexpr (B == 8 && LPR == 16) {
+      if constexpr (kRot) {
         // halving exchange between lanes of equal parity: afterwards lane sub
         // holds (rotated) component (sub >> 1) & 7
         const bool h8 = sub & 8, h4 = sub & 4, h2 = sub & 2;
-        float k4[4], k2[2];
+        T k4[4], k2[2];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const float send = h8 ? acc[i] : acc[i + 4];
-          const float keep = h8 ? acc[i + 4] : acc[i];
+          const T send = h8 ? acc[i] : acc[i + 4];
+          const T keep = h8 ? acc[i + 4] : acc[i];
           k4[i] = keep + __shfl_xor(send, 8, LPR);
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-          const float send = h4 ? k4[i] : k4[i + 2];
-          const float keep = h4 ? k4[i + 2] : k4[i];
+          const T send = h4 ? k4[i] : k4[i + 2];
+          const T keep = h4 ? k4[i + 2] : k4[i];
           k2[i] = keep + __shfl_xor(send, 4, LPR);
         }
-        const float send = h2 ? k2[0] : k2[1];
-        float k1 = (h2 ? k2[1] : k2[0]) + __shfl_xor(send, 2, LPR);
+        const T send = h2 ? k2[0] : k2[1];
+        T k1 = (h2 ? k2[1] : k2[0]) + __shfl_xor(send, 2, LPR);
         // even lane sub and odd lane sub ^ 9 now hold the same component
         out[0] = k1 + __shfl_xor(k1, 9, LPR);
       } else if constexpr (B >= LPR) {
         // halving exchange: each round keeps the half of the sums selected by
         // one bit of sub, so lane sub ends with components [NO sub, NO sub + NO)
-        float v[B];
+        T v[B];
 #pragma unroll
         for (int a = 0; a < B; ++a) v[a] = acc[a];
 #pragma unroll
@@ -1354,13 +1401,13 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
           const bool up = sub & off;
 #pragma unroll
           for (int i = 0; i < K / 2; ++i) {
-            const float send = up ? v[i] : v[i + K / 2];
-            const float keep = up ? v[i + K / 2] : v[i];
+            const T send = up ? v[i] : v[i + K / 2];
+            const T keep = up ? v[i + K / 2] : v[i];
             v[i] = keep + __shfl_xor(send, off, LPR);
           }
         }
 #pragma unroll
-        for (int i = 0; i < NO; ++i) out[i] = v[i] + (P2 ? cur.yp[i] : 0.0f);
+        for (int i = 0; i < NO; ++i) out[i] = v[i] + (P2 ? cur.yp[i] : T(0));
       } else {
         static_assert(!P2, "pass 2 needs B >= LPR");
 #pragma unroll
@@ -1372,7 +1419,7 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
         for (int a = 0; a < B; ++a) out[a] = acc[a];
       }
 #pragma unroll
-      for (int a = 0; a < B; ++a) acc[a] = 0.0f;
+      for (int a = 0; a < B; ++a) acc[a] = T(0);
       row = nrow;
       nrow += stride;
     }
@@ -1390,35 +1437,37 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
 // of set B as soon as its pass-1 rows are done, pass 2 writes set B over set
 // A in LDS once every thread is past pass 1, and reads pass 1's row sums back
 // while they are still in the L2.
-template <int B, bool S>
+template <int B, bool S, typename T = float>
 __global__ __launch_bounds__(1024) void k_spmm_pipe12(int64_t n, int64_t G, int slots,
                                                       const int64_t *__restrict__ abases,
-                                                      const float *__restrict__ aval,
+                                                      const T *__restrict__ aval,
                                                       const uint16_t *__restrict__ alcol,
                                                       const int32_t *__restrict__ arow,
                                                       const int64_t *__restrict__ bbases,
-                                                      const float *__restrict__ bval,
+                                                      const T *__restrict__ bval,
                                                       const uint16_t *__restrict__ blcol,
                                                       const int32_t *__restrict__ brow,
                                                       const int32_t *__restrict__ blocks,
-                                                      const float *__restrict__ X,
-                                                      float *__restrict__ Y, int ld_arg) {
+                                                      const T *__restrict__ X,
+                                                      T *__restrict__ Y, int ld_arg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ld = S ? ld_arg : B;  // row stride of V and W (S: strided halves)
   const int64_t g = xcd_block(blockIdx.x);
   if (g * G >= n) return;  // grid padding: the whole workgroup leaves
-  pipe_run<B, false>(g, n, G, slots, abases, aval, alcol, arow, blocks + g * (2 * slots), X, Y,
-                     smem_raw, ld);
+  pipe_run<B, false, T>(g, n, G, slots, abases, aval, alcol, arow, blocks + g * (2 * slots), X,
+                        Y, smem_raw, ld);
   // set B's blocks are loaded while the rest of the workgroup finishes pass 1
-  // (where 16-byte pieces keep the held loads within the register budget of
-  // 1024 threads; otherwise pass 2 loads them after the barrier)
-  constexpr bool kEarly = StageFill<B>::piece == 16;
-  StageFill<B> fill;
+  // (where 16-byte pieces of float rows up to 32 bytes keep the held loads
+  // within the register budget of 1024 threads; otherwise pass 2 loads them
+  // after the barrier)
+  constexpr bool kEarly = StageFill<B, T>::piece == 16 && !pipe_wide<T, B>();
+  StageFill<B, T> fill;
   if (kEarly) fill.issue(n, G, slots, blocks + g * (2 * slots) + slots, X, ld);
   // pass 1's row sums written and its LDS reads done, workgroup-wide
   __syncthreads();
-  pipe_run<B, true>(g, n, G, slots, bbases, bval, blcol, brow, blocks + g * (2 * slots) + slots,
-                    X, Y, smem_raw, ld, kEarly ? &fill : nullptr);
+  pipe_run<B, true, T>(g, n, G, slots, bbases, bval, blcol, brow,
+                       blocks + g * (2 * slots) + slots, X, Y, smem_raw, ld,
+                       kEarly ? &fill : nullptr);
 }
 
 // The multi-set pipelined SpMM: one 1024-thread workgroup per group stages
@@ -1461,14 +1510,14 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe_ms(int64_t n, int64_t G, int
 // lane ends with the same, fixed-order total) and lane s adds components
 // s, s + L, ... to the row of W.  A grid-stride loop covers any length.
 constexpr int kRestLanes = 8;
-template <int B, bool S>
+template <int B, bool S, typename T = float>
 __global__ __launch_bounds__(256) void k_spmm_rest(const int64_t *__restrict__ rgroup,
                                                    int64_t groups,
                                                    const int4 *__restrict__ rlist,
                                                    const int32_t *__restrict__ col2,
-                                                   const float *__restrict__ val2,
-                                                   const float *__restrict__ X,
-                                                   float *__restrict__ Y, int ld_arg) {
+                                                   const T *__restrict__ val2,
+                                                   const T *__restrict__ X,
+                                                   T *__restrict__ Y, int ld_arg) {
   constexpr int L = kRestLanes, U = 4, NC = (B + L - 1) / L;
   const int ld = S ? ld_arg : B;  // row stride of V and W (S: strided halves)
   const int64_t total = rgroup[groups];
@@ -1479,31 +1528,31 @@ __global__ __launch_bounds__(256) void k_spmm_rest(const int64_t *__restrict__ r
     const int64_t row = d.x;
     const int cnt = d.y;
     const int64_t first = (int64_t)(uint32_t)d.z | ((int64_t)d.w << 32);
-    float y[NC];
+    T y[NC];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) y[k] = s + k * L < B ? Y[row * ld + s + k * L] : 0.0f;
-    float acc[B];
+    for (int k = 0; k < NC; ++k) y[k] = s + k * L < B ? Y[row * ld + s + k * L] : T(0);
+    T acc[B];
 #pragma unroll
-    for (int a = 0; a < B; ++a) acc[a] = 0.0f;
+    for (int a = 0; a < B; ++a) acc[a] = T(0);
     // the same trip count on all L lanes of the row; every load is issued
     // (past the row's end a lane reloads its last entry and drops the product)
     for (int t0 = 0; t0 < cnt; t0 += L * U) {
       int c[U];
-      float h[U];
+      T h[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int64_t q = first + min(t0 + s + L * u, cnt - 1);
         c[u] = col2[q];
         h[u] = val2[q];
       }
-      float x[U][B];
+      T x[U][B];
 #pragma unroll
-      for (int u = 0; u < U; ++u) RowIO<float, B>::load(X + (int64_t)c[u] * ld, x[u]);
+      for (int u = 0; u < U; ++u) RowIO<T, B>::load(X + (int64_t)c[u] * ld, x[u]);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const bool ok = t0 + s + L * u < cnt;
 #pragma unroll
-        for (int a = 0; a < B; ++a) acc[a] = fmaf(h[u], ok ? x[u][a] : 0.0f, acc[a]);
+        for (int a = 0; a < B; ++a) acc[a] = pipe_fma(h[u], ok ? x[u][a] : T(0), acc[a]);
       }
     }
 #pragma unroll
@@ -1513,7 +1562,7 @@ __global__ __launch_bounds__(256) void k_spmm_rest(const int64_t *__restrict__ r
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       const int a = s + k * L;
-      float v = 0.0f;
+      T v = T(0);
 #pragma unroll
       for (int a2 = 0; a2 < B; ++a2) v = a2 == a ? acc[a2] : v;
       if (a < B) Y[row * ld + a] = y[k] + v;
@@ -1552,17 +1601,18 @@ void planned_launch_t(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s)
 // Whether a plan can run through the pipelined kernels at BK vectors per
 // pass: 16-bit LDS indices, the per-row descriptors and dense copies, and
 // the staged sets plus the all-zero row within the LDS.
-bool plan_pipe_ok(bool local16, bool copies, int slots, int64_t block_rows, int BK) {
-  return local16 && copies && ((size_t)slots * block_rows + 1) * BK * sizeof(float) <= kPlanLds;
+bool plan_pipe_ok(bool local16, bool copies, int slots, int64_t block_rows, int BK,
+                  size_t elem = sizeof(float)) {
+  return local16 && copies && ((size_t)slots * block_rows + 1) * BK * elem <= kPlanLds;
 }
 
 // Passes 1 and 2 in one workgroup per group (pass 1: 16 lanes per row over
 // set A; pass 2: 2 lanes per row over set B), then pass 3 for the rest, one
 // lane per listed row.
-template <int BV, bool S>
-void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, int ld, hipStream_t s) {
-  auto kern = k_spmm_pipe12<BV, S>;
-  const size_t lds = ((size_t)P.slots * P.block_rows + 1) * BV * sizeof(float);
+template <int BV, bool S, typename T = float>
+void planned_launch_pipe(const bbl_spmm_plan &P, const T *X, T *Y, int ld, hipStream_t s) {
+  auto kern = k_spmm_pipe12<BV, S, T>;
+  const size_t lds = ((size_t)P.slots * P.block_rows + 1) * BV * sizeof(T);
   static bool attr_set = false;
   if (!attr_set) {
     BBL_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -1572,16 +1622,16 @@ void planned_launch_pipe(const bbl_spmm_plan &P, const float *X, float *Y, int l
   const int64_t groups = ceil_div(P.n, P.block_rows);
   hipLaunchKernelGGL(kern, dim3((unsigned)(ceil_div(groups, kXcds) * kXcds)), dim3(kPlanThreads),
                      lds, s, P.n, (int64_t)P.block_rows, P.slots, P.agroup,
-                     static_cast<const float *>(P.aval), P.alcol, P.arow, P.bgroup,
-                     static_cast<const float *>(P.bval), P.blcol, P.brow, P.blocks, X, Y, ld);
+                     static_cast<const T *>(P.aval), P.alcol, P.arow, P.bgroup,
+                     static_cast<const T *>(P.bval), P.blcol, P.brow, P.blocks, X, Y, ld);
   check_launch("k_spmm_pipe12");
   // the list's length is on the device: a grid of at most 4096 workgroups
   // (32 rows each) strides over it
   const int64_t grid =
       std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(P.n * kRestLanes, 256)));
-  hipLaunchKernelGGL((k_spmm_rest<BV, S>), dim3((unsigned)grid), dim3(256), 0, s, P.rgroup, groups,
-                     reinterpret_cast<const int4 *>(P.rlist), P.col,
-                     static_cast<const float *>(P.val), X, Y, ld);
+  hipLaunchKernelGGL((k_spmm_rest<BV, S, T>), dim3((unsigned)grid), dim3(256), 0, s, P.rgroup,
+                     groups, reinterpret_cast<const int4 *>(P.rlist), P.col,
+                     static_cast<const T *>(P.val), X, Y, ld);
   check_launch("k_spmm_rest");
 }
 
@@ -1611,6 +1661,16 @@ void planned_launch_ms(const bbl_spmm_plan &P, const float *X, float *Y, int ld,
 
 template <typename VT, typename XT, int BV>
 void planned_launch(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s) {
+  // float64 values and vectors at 4 or 8 columns: the same three passes on
+  // rows of doubles (32 or 64 bytes in LDS)
+  if constexpr (std::is_same<VT, double>::value && std::is_same<XT, double>::value &&
+                (BV == 4 || BV == 8)) {
+    if (plan_pipe_ok(P.local16 && P.lcol, P.rdesc && P.arow && P.brow && P.rlist, P.slots,
+                     P.block_rows, BV, sizeof(double))) {
+      planned_launch_pipe<BV, false, double>(P, X, Y, BV, s);
+      return;
+    }
+  }
   if constexpr (std::is_same<VT, float>::value && std::is_same<XT, float>::value &&
                 (BV == 4 || BV == 8 || BV == 10 || BV == 16)) {
     if (P.nsets > 0) {
