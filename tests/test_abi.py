@@ -97,6 +97,11 @@ def test_plan_size_follows_the_slot_rule_without_a_device():
     d8, d16 = size(bbl.BBL_F64, 1000, 8, bbl.BBL_F64), size(bbl.BBL_F64, 1000, 16, bbl.BBL_F64)
     assert d8 > d16 > 0
     assert 0 < d8 - d16 <= 20 * 2 * 4 + 256
+    # 12 vectors: planned for float32 vectors only (three 48 KB blocks at
+    # 1000 rows); 32 vectors: one 1000-row block would fill the LDS, no plan
+    assert size(bbl.BBL_F32, 1000, 12, bbl.BBL_F32) > 0
+    assert size(bbl.BBL_F64, 1000, 12, bbl.BBL_F64) == 0
+    assert size(bbl.BBL_F32, 1000, 32, bbl.BBL_F32) == 0
 
 
 def test_binding_fails_loudly_without_the_library(tmp_path):
