@@ -57,6 +57,15 @@ def check_rows(W, V64, H, idx):
         assert np.all(np.abs(W[i] - ref) <= bound), (i, np.abs(W[i] - ref).max(), bound.max())
 
 
+def check_sampled_rows(Ws, V32, H, idx):
+    """Ws[t]: the product's row idx[t]; V32: the float32 vectors (host)."""
+    for t, (c, v) in enumerate(rows_of(H, idx)):
+        Vc = V32[c].astype(np.float64)
+        ref = v @ Vc
+        bound = (len(c) + 2) * U32 / (1 - (len(c) + 2) * U32) * (np.abs(v) @ np.abs(Vc)) + 1e-30
+        assert np.all(np.abs(Ws[t] - ref) <= bound), (idx[t], np.abs(Ws[t] - ref).max(), bound.max())
+
+
 @pytest.fixture(scope="module")
 def plan(bbl, mid):
     w, H, Hd = mid
@@ -196,3 +205,33 @@ def test_launches_beyond_32_bit_work_item_counts(torch, bbl):
     plan = bbl.spmm_plan(Hd, nv)
     assert plan.c.nsets > 0
     check(bbl.spmm_planned(plan, V))
+
+
+def test_multiset_plan_beyond_2_31_entries(torch, bbl):
+    """The n = 1e8 recipe (sectors of 2000, ~50 nnz/row, half of each row's
+    entries far from its sector) at n = 4.4e7: about 2.2e9 stored entries,
+    more than a 32-bit offset holds, so the plan is the multi-set one with
+    64-bit set bases; 8 FP32 vectors.  Sampled rows (both sides of the 2^31
+    entry boundary among them) against the dot-product bound, and the result
+    reproducible bit for bit."""
+    w = synthgen.WORKLOADS["stress_n1e8"]
+    n = 44_000_000
+    note("generating n=4.4e7 on the n=1e8 recipe (float32 values)")
+    H = synthgen.generate(n, w.R, w.q, w.p, 3, values="f32")
+    assert H.nnz > 2 ** 31, H.nnz
+    Hd = bbl.DeviceCSR.from_host(H, "float32", block_rows=w.R)
+    note("multi-set plan, nnz=%d" % H.nnz)
+    plan = bbl.spmm_plan(Hd, 8)
+    assert plan.c.nsets > 0
+    V = synthgen.gaussian_block(n, 8, 9).astype(np.float32)
+    Vd = torch.from_numpy(V).cuda()
+    W = bbl.spmm_planned(plan, Vd)
+    W2 = bbl.spmm_planned(plan, Vd)
+    assert torch.equal(W, W2)
+    rp = np.asarray(H.row_ptr)
+    cut = int(np.searchsorted(rp, 2 ** 31, side="right")) - 1  # the row holding entry 2^31
+    rng = np.random.default_rng(4)
+    idx = np.unique(np.concatenate([rng.choice(n, 3000, replace=False),
+                                    [0, n - 1, cut - 1, cut, cut + 1]]))
+    note("checking %d sampled rows" % len(idx))
+    check_sampled_rows(W[torch.from_numpy(idx).cuda()].double().cpu().numpy(), V, H, idx)
