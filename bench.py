@@ -155,7 +155,7 @@ def _per_dispatch(rows, counter, match):
     return float(np.mean(list(per.values()))), len(per)
 
 
-SPMM_PASSES = ("k_spmm_pipe12<8, false>", "k_spmm_rest<8, false>")
+SPMM_PASSES = ("k_spmm_pipe12<8, false, float>", "k_spmm_rest<8, false, float>")
 REORTH_BLOCKS = 50   # basis blocks of the counter runs' gram and update
 
 
@@ -178,7 +178,7 @@ def write_traffic(fetch_dir, write_dir):
     w = synthgen.WORKLOADS[WORKLOAD]
     H = load_matrix(w)
     alg = spmm_bytes(H.n, H.nnz, w.nvec, 4, 4)
-    rec = {"kernel": "k_spmm_pipe12<8, false> + k_spmm_rest<8, false> (one planned SpMM: passes 1 and 2 in "
+    rec = {"kernel": "k_spmm_pipe12<8, false, float> + k_spmm_rest<8, false, float> (one planned SpMM: passes 1 and 2 in "
                      "one kernel, then pass 3; float32 values and vectors, 8 vectors, sectors "
                      "of 1000 rows, two sets of column blocks staged in LDS, the rest gathered)",
            "workload": WORKLOAD, "per_pass_fetch_kib": [x[0] for x in fp],
@@ -855,7 +855,7 @@ def main():
                    "n_trunc": w.n_trunc, "m_max": w.m_max, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK,
-                     "traffic": traffic, "kernel": "k_spmm_pipe12<8, false> + k_spmm_rest<8, false>",
+                     "traffic": traffic, "kernel": "k_spmm_pipe12<8, false, float> + k_spmm_rest<8, false, float>",
                      "alg_bytes_per_launch": alg, "launch_ms": t_live * 1e3},
         "cpu_baseline": cpu,
         "details": extra,
