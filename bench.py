@@ -585,17 +585,46 @@ def cpu_baseline(H, w, pivot_np, gpu_iters):
                    "timed at N=%s (%s s) and fitted e*N^3, all summed to the GPU's %d "
                    "iterations" % (info["cpu_model"], threads, t_small, r1.iters, t_piv, m1, t1,
                                    m2, t2, sizes, ["%.2f" % x for x in te], m)),
-        "small_fp64_full_s": t_small, "host": info,
+        "small_fp64_full_s": t_small, "small_fp64_eigvals": [float(x) for x in r1.eigvals],
+        "host": info,
         "model_terms_s": {"pivot": t_piv, "blocks_linear": a * m + c * m * m / 2.0 + a,
                           "band_eigensolves": t_eig},
     }
 
 
+def small_fp64_leg(torch, bbl):
+    """The small FP64 workload on the GPU (n = 2e4, ~40 nnz/row, b = k = 4,
+    tol 1e-8, bootstrap pivot from the leading 2000 rows, planned SpMM):
+    time to solution of a warm solve (pivot + solve + Ritz vectors + explicit
+    residual), iterations, eigenvalues and residuals; the oracle's solve of
+    the same matrix (CPU baseline leg) gives its eigenvalue error."""
+    import synthgen
+    w1 = synthgen.WORKLOADS["small_fp64_n2e4"]
+    H1 = w1.generate()
+    Hd1 = bbl.DeviceCSR.from_host(H1, "float64", block_rows=w1.R)
+    plan = bbl.spmm_plan(Hd1, w1.nvec)
+    res = None
+    for _ in range(2):  # warm, then timed
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        P1, _st = bbl.bootstrap_pivot(Hd1, w1.n_trunc, w1.nvec, w1.tol, m_max=w1.m_max,
+                                      seed=w1.seed)
+        r1 = bbl.block_lanczos(Hd1, P1, w1.k, w1.tol, m_max=w1.m_max, seed=w1.seed,
+                               spmm_plan=plan)
+        torch.cuda.synchronize()
+        res = (time.perf_counter() - t, r1)
+    tts, r1 = res
+    return {"tts_s": tts, "iters": r1.stats["iters"], "converged": bool(r1.converged),
+            "eigvals": [float(x) for x in r1.eigvals],
+            "max_resid_over_hnorm": float(np.max(r1.residuals) / r1.stats["hnorm_est"])}
+
+
 def fp64_arm(torch, bbl, H, w, P, r32, spmm_iters):
-    """The same workload with float64 values, basis and products (plain CSR
-    kernel; the float64 plan stages one block per sector): time to solution,
-    SpMM algorithmic GB/s against nnz*12 + 8(n+1) + 2*n*b*8 bytes per call,
-    and the eigenvalue difference from the float32 solve."""
+    """The same workload with float64 values, basis and products, through the
+    plain CSR kernel and through the planned SpMM (the pipelined passes on
+    rows of doubles): time to solution, SpMM algorithmic GB/s against
+    nnz*12 + 8(n+1) + 2*n*b*8 bytes per call, and the eigenvalue difference
+    from the float32 solve."""
     Hd64 = bbl.DeviceCSR.from_host(H, "float64", block_rows=w.R)
     b, k = w.nvec, w.k
     plan = bbl.spmm_plan(Hd64, b)
@@ -820,6 +849,8 @@ def main():
                                float(np.max(np.abs(rr.eigvals - r.eigvals) / np.abs(r.eigvals)))}
     if not args.no_fp64_arm:
         extra["fp64_arm"] = fp64_arm(torch, bbl, H, w, P, r, args.spmm_iters)
+    extra["small_fp64"] = small_fp64_leg(torch, bbl)
+    log("small FP64 workload: %s" % json.dumps(extra["small_fp64"]))
     # eigenvalue accuracy of this run: FP64 residuals of the returned pairs
     # recomputed by the vendor sparse library, and the quadratic residual
     # bound on each eigenvalue's error
@@ -834,6 +865,10 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample) ...")
         cpu = cpu_baseline(H, w, P.cpu().numpy(), r.stats["iters"])
+        ref = np.array(cpu["small_fp64_eigvals"])
+        got = np.array(extra["small_fp64"]["eigvals"])
+        extra["small_fp64"]["max_eig_rel_err_vs_oracle"] = float(np.max(np.abs(got - ref) /
+                                                                        np.abs(ref)))
 
     out = {
         "metric": "time-to-solution, 10 eigpairs @1e-6 resid",

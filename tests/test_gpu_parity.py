@@ -85,7 +85,10 @@ def test_spmm_matches_oracle_within_dot_product_bound(torch, bbl, nvec, prec):
     (8, 400, "f32", 150, 0.7), (8, 400, "f32", 150, 0.1), (4, 400, "f32", 150, 0.3),
     (8, 1000, "f32", 105, 0.7), (10, 1000, "f32", 105, 0.7),
     (16, 1000, "f32", 105, 0.7), (16, 333, "f32", 150, 0.3), (12, 1000, "f32", 105, 0.7),
-    (12, 400, "f32", 150, 0.3)])
+    (12, 400, "f32", 150, 0.3),
+    # float64 plans through the pipelined passes (rows of 4 and 8 doubles)
+    (4, 400, "f64", 20, 0.7), (4, 400, "f64", 150, 0.3), (8, 1000, "f64", 105, 0.7),
+    (8, 333, "f64", 150, 0.3)])
 def test_planned_spmm_matches_oracle(torch, bbl, nvec, block_rows, prec, q, p):
     """Rows reordered per group, partner blocks staged in LDS: the same sums
     in another order, so the dot-product bound holds entry by entry (groups
