@@ -1043,11 +1043,17 @@ __device__ __forceinline__ T pipe_fma(T a, T b, T c) {
   else return fma(a, b, c);
 }
 
-template <int B, bool P2, typename T = float>
+// PAIR (16 float columns in one pass): the lanes of a row work in pairs on
+// the same entries, the even lane on columns 0-7 of each staged row, the odd
+// lane on 8-15, so a lane holds the sums and LDS rows of 8 columns (as at
+// B = 8) while the entries are streamed once for all 16.
+template <int B, bool P2, typename T = float, bool PAIR = false>
 struct PipeStage {
   static constexpr int LPR = pipe_lpr<P2>();
-  static constexpr int NO = B / LPR > 0 ? B / LPR : 1;  // sums per lane after the reduction
-  static constexpr int LE = pipe_le<P2, pipe_wide<T, B>()>();
+  static constexpr int BL = PAIR ? B / 2 : B;          // columns per lane
+  static constexpr int LPE = PAIR ? LPR / 2 : LPR;     // lanes per row with distinct entries
+  static constexpr int NO = BL / LPE > 0 ? BL / LPE : 1;  // sums per lane after the reduction
+  static constexpr int LE = pipe_le<P2, pipe_wide<T, BL>()>();
   uint4 lc[LE / 8];             // 16-bit LDS row indices
   T lv[LE];
   T yp[P2 ? NO : 1];            // the row's sums so far (pass 2)
@@ -1111,12 +1117,12 @@ __device__ __forceinline__ void pipe_vstore(float *p, const float (&v)[NO]) {
 // entries.  Every lane issues the same loads whether or not its entries exist
 // (those without any read position 0 and are masked by the range), so the
 // number of loads in flight is the same on every path.
-template <int B, bool P2, typename T>
-__device__ __forceinline__ void pipe_load(PipeStage<B, P2, T> &st,
+template <int B, bool P2, typename T, bool PAIR>
+__device__ __forceinline__ void pipe_load(PipeStage<B, P2, T, PAIR> &st,
                                           const uint16_t *__restrict__ lcol,
                                           const T *__restrict__ val, int ql, int p0, int pl,
                                           const T *yrow) {
-  constexpr int LE = PipeStage<B, P2, T>::LE;
+  constexpr int LE = PipeStage<B, P2, T, PAIR>::LE;
   constexpr int PER = 16 / (int)sizeof(T);  // values per 16-byte load
   st.llo = p0 - ql;
   st.lhi = pl - ql;
@@ -1128,7 +1134,7 @@ __device__ __forceinline__ void pipe_load(PipeStage<B, P2, T> &st,
     const uint4 a = reinterpret_cast<const uint4 *>(val + lq)[i];
     __builtin_memcpy(st.lv + PER * i, &a, 16);
   }
-  if constexpr (P2) pipe_vload<PipeStage<B, P2, T>::NO>(yrow, st.yp);
+  if constexpr (P2) pipe_vload<PipeStage<B, P2, T, PAIR>::NO>(yrow, st.yp);
 }
 
 // Row loads from LDS.  With par = 1 (odd lanes of pass 1 at B = 8) the lane
@@ -1226,7 +1232,7 @@ struct StageFill {
 // One pass over group g, run by the whole workgroup (every thread calls it:
 // it holds a barrier).  pre: the set's blocks already loaded by this thread
 // (nullptr: loaded here).
-template <int B, bool P2, typename T = float>
+template <int B, bool P2, typename T = float, bool PAIR = false>
 __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int slots,
                                          const int64_t *__restrict__ bases,
                                          const T *__restrict__ val,
@@ -1237,29 +1243,34 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
                                          unsigned char *smem_raw, int ld,
                                          const StageFill<B, T> *pre = nullptr) {
   using Desc = int2;
-  using Stage = PipeStage<B, P2, T>;
+  using Stage = PipeStage<B, P2, T, PAIR>;
   // pass 1 at 8 float columns keeps odd lanes' sums rotated (pipe_row)
-  constexpr bool kRot = sizeof(T) == 4 && B == 8 && !P2;
+  constexpr bool kRot = sizeof(T) == 4 && B == 8 && !P2 && !PAIR;
   constexpr int LPR = Stage::LPR, NO = Stage::NO, LE = Stage::LE;
-  static_assert(!P2 || B >= LPR, "pass 2 keeps whole components per lane");
+  constexpr int BL = Stage::BL, LPE = Stage::LPE;
+  static_assert(!P2 || BL >= LPE, "pass 2 keeps whole components per lane");
+  static_assert(!PAIR || (B == 16 && sizeof(T) == 4), "lane pairs: 16 float columns");
   const T *sX = reinterpret_cast<const T *>(smem_raw);
   const int64_t r0 = g * G;
   const int nr = (int)(min(n, r0 + G) - r0);
   constexpr int RPW = kWave / LPR;
-  constexpr int LCH = LE * LPR;
+  constexpr int LCH = LE * LPE;  // entries of a row per step
   const int lane = threadIdx.x & (kWave - 1);
   const int sub = lane & (LPR - 1);
+  const int half = PAIR ? (sub & 1) : 0;        // the lane's 8-column half (PAIR)
+  const int esub = PAIR ? (sub >> 1) : sub;     // the lane's share of the row's entries
   const int wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
   const int stride = nwaves * RPW;
   const int zrow = slots * (int)G;  // the all-zero LDS row
   const int par = kRot ? (sub & 1) : 0;
-  const int cb = NO * sub;          // first of the lane's sums after the reduction (B >= LPR)
+  // first of the lane's sums after the reduction (BL >= LPE)
+  const int cb = BL * half + NO * esub;
   const int64_t base = bases[g] & ~(int64_t)7;
   const uint16_t *lc_b = lcol + base;
   const T *v_b = val + base;
   const Desc *desc = reinterpret_cast<const Desc *>(rdesc) + r0;
   T *Yw = Y + r0 * ld;
-  auto yrow = [&](int r) { return Yw + (int64_t)(r < nr ? r : 0) * ld + (B >= LPR ? cb : 0); };
+  auto yrow = [&](int r) { return Yw + (int64_t)(r < nr ? r : 0) * ld + (BL >= LPE ? cb : 0); };
 
   // this row group's first row (relative to r0) and the descriptor of its second
   int row = wave * RPW + lane / LPR;
@@ -1269,7 +1280,7 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
   int pl = d0.y;
   int qlb = d0.x & ~(LE - 1);
   Stage cur;
-  pipe_load<B, P2, T>(cur, lc_b, v_b, qlb + LE * sub, d0.x, pl, yrow(row));
+  pipe_load<B, P2, T, PAIR>(cur, lc_b, v_b, qlb + LE * esub, d0.x, pl, yrow(row));
 
   // stage the set's column blocks (loaded here unless the caller loaded them
   // already), then the all-zero row
@@ -1296,19 +1307,19 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
   __syncthreads();
   if (row >= nr) return;  // no rows for this group of lanes
 
-  T acc[B];
+  T acc[BL];
 #pragma unroll
-  for (int a = 0; a < B; ++a) acc[a] = T(0);
+  for (int a = 0; a < BL; ++a) acc[a] = T(0);
   // A finished row's sums, stored at the start of the following step: a store
   // issued after the step's loads would have to complete before the next
   // step's first wait.
-  constexpr int NOUT = kRot ? 1 : (B >= LPR ? NO : B);
+  constexpr int NOUT = kRot ? 1 : (BL >= LPE ? NO : BL);
   T out[NOUT];
   T *yp = nullptr;
   auto store_out = [&]() __attribute__((always_inline)) {
     if constexpr (kRot) {
       if ((sub & 1) == 0) yp[sub >> 1] = out[0];
-    } else if constexpr (B >= LPR) {
+    } else if constexpr (BL >= LPE) {
       pipe_vstore<NO>(yp + cb, out);
     } else {
 #pragma unroll
@@ -1342,7 +1353,7 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
       store_out();
       yp = nullptr;
     }
-    pipe_load<B, P2, T>(nxt, lc_b, v_b, sqlb + LE * sub, sp0, spl, yrow(srow));
+    pipe_load<B, P2, T, PAIR>(nxt, lc_b, v_b, sqlb + LE * esub, sp0, spl, yrow(srow));
     // the descriptor of the row after the one the next step works on
     {
       const int r = last ? nrow + stride : nrow;
@@ -1350,22 +1361,22 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
     }
     // the step's entries, LG LDS rows at a time (fewer in pass 2, whose lanes
     // hold more entries and sums)
-    constexpr int LG = pipe_lg<P2, pipe_wide<T, B>()>();
+    constexpr int LG = pipe_lg<P2, pipe_wide<T, BL>()>();
 #pragma unroll
     for (int hf = 0; hf < LE; hf += LG) {
-      T lx[LG][B];
+      T lx[LG][BL];
       T h[LG];
 #pragma unroll
       for (int e = 0; e < LG; ++e) {
         const bool ok = cur.llo <= hf + e && hf + e < cur.lhi;
         const int idx = ok ? pipe_lidx(cur.lc, hf + e) : zrow;
         h[e] = ok ? cur.lv[hf + e] : T(0);
-        pipe_row<B>(sX + idx * B, par, lx[e]);
+        pipe_row<BL>(sX + idx * B + BL * half, par, lx[e]);
       }
 #pragma unroll
       for (int e = 0; e < LG; ++e)
 #pragma unroll
-        for (int a = 0; a < B; ++a) acc[a] = pipe_fma(h[e], lx[e][a], acc[a]);
+        for (int a = 0; a < BL; ++a) acc[a] = pipe_fma(h[e], lx[e][a], acc[a]);
     }
     if (last) {
       yp = Yw + (int64_t)row * ld;
@@ -1390,14 +1401,16 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
         T k1 = (h2 ? k2[1] : k2[0]) + __shfl_xor(send, 2, LPR);
         // even lane sub and odd lane sub ^ 9 now hold the same component
         out[0] = k1 + __shfl_xor(k1, 9, LPR);
-      } else if constexpr (B >= LPR) {
+      } else if constexpr (BL >= LPE) {
         // halving exchange: each round keeps the half of the sums selected by
-        // one bit of sub, so lane sub ends with components [NO sub, NO sub + NO)
-        T v[B];
+        // one bit of esub, so the lane ends with components [NO esub, NO esub
+        // + NO) of its columns (lane pairs: the rounds skip the lowest bit of
+        // sub, which names the half)
+        T v[BL];
 #pragma unroll
-        for (int a = 0; a < B; ++a) v[a] = acc[a];
+        for (int a = 0; a < BL; ++a) v[a] = acc[a];
 #pragma unroll
-        for (int off = LPR / 2, K = B; off > 0; off >>= 1, K >>= 1) {
+        for (int off = LPR / 2, K = BL; off >= (PAIR ? 2 : 1); off >>= 1, K >>= 1) {
           const bool up = sub & off;
 #pragma unroll
           for (int i = 0; i < K / 2; ++i) {
@@ -1409,7 +1422,7 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
 #pragma unroll
         for (int i = 0; i < NO; ++i) out[i] = v[i] + (P2 ? cur.yp[i] : T(0));
       } else {
-        static_assert(!P2, "pass 2 needs B >= LPR");
+        static_assert(!P2 && !PAIR, "pass 2 and lane pairs need BL >= LPE");
 #pragma unroll
         for (int off = LPR / 2; off > 0; off >>= 1) {
 #pragma unroll
@@ -1419,7 +1432,7 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
         for (int a = 0; a < B; ++a) out[a] = acc[a];
       }
 #pragma unroll
-      for (int a = 0; a < B; ++a) acc[a] = T(0);
+      for (int a = 0; a < BL; ++a) acc[a] = T(0);
       row = nrow;
       nrow += stride;
     }
@@ -1475,7 +1488,7 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe12(int64_t n, int64_t G, int 
 // the row sums (16 lanes per row), later sets add theirs (2 lanes per row,
 // reading the previous sums back while they are in the L2).  A set with no
 // entries in the group is skipped.  The rest pass follows as its own kernel.
-template <int B, bool S>
+template <int B, bool S, bool PAIR = false>
 __global__ __launch_bounds__(1024) void k_spmm_pipe_ms(int64_t n, int64_t G, int slots, int nsets,
                                                        int64_t groups,
                                                        const int64_t *__restrict__ sgroup,
@@ -1490,15 +1503,15 @@ __global__ __launch_bounds__(1024) void k_spmm_pipe_ms(int64_t n, int64_t G, int
   const int64_t g = xcd_block(blockIdx.x);
   if (g * G >= n) return;  // grid padding: the whole workgroup leaves
   const int width = nsets * slots;
-  pipe_run<B, false>(g, n, G, slots, sgroup, sval, slcol, srow, blocks + g * width, X, Y,
-                     smem_raw, ld);
+  pipe_run<B, false, float, PAIR>(g, n, G, slots, sgroup, sval, slcol, srow, blocks + g * width,
+                                  X, Y, smem_raw, ld);
   for (int s = 1; s < nsets; ++s) {
     const int64_t *sg = sgroup + s * (groups + 1);
     if (sg[g + 1] == sg[g]) continue;  // uniform: no entries of set s in this group
     // the previous set's row sums written and its LDS reads done
     __syncthreads();
-    pipe_run<B, true>(g, n, G, slots, sg, sval, slcol, srow + (int64_t)s * n * 2,
-                      blocks + g * width + s * slots, X, Y, smem_raw, ld);
+    pipe_run<B, true, float, PAIR>(g, n, G, slots, sg, sval, slcol, srow + (int64_t)s * n * 2,
+                                   blocks + g * width + s * slots, X, Y, smem_raw, ld);
   }
 }
 
@@ -1636,9 +1649,9 @@ void planned_launch_pipe(const bbl_spmm_plan &P, const T *X, T *Y, int ld, hipSt
 }
 
 // The multi-set plan: its sets in one workgroup per group, then the rest pass.
-template <int BV, bool S>
+template <int BV, bool S, bool PAIR = false>
 void planned_launch_ms(const bbl_spmm_plan &P, const float *X, float *Y, int ld, hipStream_t s) {
-  auto kern = k_spmm_pipe_ms<BV, S>;
+  auto kern = k_spmm_pipe_ms<BV, S, PAIR>;
   const size_t lds = ((size_t)P.slots * P.block_rows + 1) * BV * sizeof(float);
   static bool attr_set = false;
   if (!attr_set) {
@@ -1674,9 +1687,18 @@ void planned_launch(const bbl_spmm_plan &P, const XT *X, XT *Y, hipStream_t s) {
   if constexpr (std::is_same<VT, float>::value && std::is_same<XT, float>::value &&
                 (BV == 4 || BV == 8 || BV == 10 || BV == 16)) {
     if (P.nsets > 0) {
-      constexpr int BK = BV == 16 ? 8 : BV;
-      planned_launch_ms<BK, BV != BK>(P, X, Y, BV, s);
-      if constexpr (BV == 16) planned_launch_ms<BK, true>(P, X + 8, Y + 8, BV, s);
+      if constexpr (BV == 16) {
+        // a plan whose sets hold 16-wide rows: one pass with lane pairs;
+        // else (slots sized for 8 columns) two passes over the halves
+        if (((size_t)P.slots * P.block_rows + 1) * 16 * sizeof(float) <= kPlanLds) {
+          planned_launch_ms<16, false, true>(P, X, Y, 16, s);
+        } else {
+          planned_launch_ms<8, true>(P, X, Y, 16, s);
+          planned_launch_ms<8, true>(P, X + 8, Y + 8, 16, s);
+        }
+      } else {
+        planned_launch_ms<BV, false>(P, X, Y, BV, s);
+      }
       return;
     }
     // the pipelined kernel also keeps one all-zero row of V in LDS and takes
@@ -1806,7 +1828,10 @@ constexpr int kMsBlocks = 10;
 bool plan_multi(const bbl_csr &H, int nvec, int vec_dtype, int *slots, int *nsets) {
   if (H.block_rows <= 0 || H.val_dtype != BBL_F32 || vec_dtype != BBL_F32) return false;
   if (!(nvec == 4 || nvec == 8 || nvec == 10 || nvec == 16)) return false;
-  const int BK = nvec == 16 ? 8 : nvec;
+  // 16 vectors: sets of 16-wide rows (one pass, lane pairs) when one block
+  // fits in LDS with the zero row, else 8-column halves
+  const bool w16 = nvec == 16 && ((int64_t)H.block_rows + 1) * 64 <= (int64_t)kPlanLds;
+  const int BK = nvec == 16 && !w16 ? 8 : nvec;
   const int64_t s = std::min<int64_t>(kPlanMaxSlots,
                                       ((int64_t)kPlanLds / (BK * 4) - 1) / H.block_rows);
   if (s < 1 || s * H.block_rows > 65536) return false;

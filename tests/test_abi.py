@@ -78,9 +78,11 @@ def test_null_and_bad_arguments_are_rejected_without_a_device():
 
 def test_plan_size_follows_the_slot_rule_without_a_device():
     """No plan without the block_rows hint or for an unsupported width; a
-    16-vector FP32 plan has the slots, and so the bytes, of an 8-vector one
-    (the pipelined kernels take it as two 8-column halves), while a
-    16-vector FP64 plan stages fewer blocks than an 8-vector FP64 one."""
+    16-vector FP32 plan at 400-row groups has the slots, and so the bytes, of
+    an 8-vector one (the pipelined kernels take it as two 8-column halves); at
+    1000-row groups two 16-wide blocks per set fit, which makes it a
+    multi-set plan (one pass with lane pairs) whose bytes differ; a 16-vector
+    FP64 plan stages fewer blocks than an 8-vector FP64 one."""
     lib = bbl.load_library()
     n, nnz = 20000, 2_000_000
 
@@ -90,8 +92,10 @@ def test_plan_size_follows_the_slot_rule_without_a_device():
 
     assert size(bbl.BBL_F32, 0, 8, bbl.BBL_F32) == 0
     assert size(bbl.BBL_F32, 1000, 3, bbl.BBL_F32) == 0
-    s8, s16 = size(bbl.BBL_F32, 1000, 8, bbl.BBL_F32), size(bbl.BBL_F32, 1000, 16, bbl.BBL_F32)
+    s8, s16 = size(bbl.BBL_F32, 400, 8, bbl.BBL_F32), size(bbl.BBL_F32, 400, 16, bbl.BBL_F32)
     assert s8 > 0 and s16 == s8
+    m8, m16 = size(bbl.BBL_F32, 1000, 8, bbl.BBL_F32), size(bbl.BBL_F32, 1000, 16, bbl.BBL_F32)
+    assert m8 > 0 and m16 > 0 and m16 != m8
     # FP64: 2 slots at 8 vectors (64 KB blocks), 1 at 16 (128 KB): the block
     # table shrinks by groups * 2 * (2 - 1) * 4 bytes (alignment aside)
     d8, d16 = size(bbl.BBL_F64, 1000, 8, bbl.BBL_F64), size(bbl.BBL_F64, 1000, 16, bbl.BBL_F64)

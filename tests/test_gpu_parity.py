@@ -102,10 +102,17 @@ def test_planned_spmm_matches_oracle(torch, bbl, nvec, block_rows, prec, q, p):
     per_block = block_rows * nvec * (4 if prec == "f32" else 8)
     expect = min(5, 160 * 1024 // per_block)
     if nvec == 16 and prec == "f32":
-        # two 8-column passes: a slot holds 8 columns, beside the zero row
-        s8 = min(5, (160 * 1024 // 32 - 1) // block_rows)
-        if s8 >= 1 and s8 * block_rows <= 65536:
-            expect = s8
+        s16 = min(5, (160 * 1024 // 64 - 1) // block_rows)
+        if 1 <= s16 < 3:
+            # two 16-wide blocks per set fit beside the zero row: a multi-set
+            # plan, one pass with lane pairs
+            expect = s16
+            assert plan.c.nsets > 0
+        else:
+            # two 8-column passes: a slot holds 8 columns, beside the zero row
+            s8 = min(5, (160 * 1024 // 32 - 1) // block_rows)
+            if s8 >= 1 and s8 * block_rows <= 65536:
+                expect = s8
     assert plan.slots == expect
     V = synthgen.gaussian_block(H.n, nvec, 5)
     Vd = dev(torch, V.astype(np.float32) if prec == "f32" else V)
@@ -140,7 +147,9 @@ def test_multiset_planned_spmm_matches_oracle(torch, bbl, n, R, q, p, nvec, bloc
     H = synthgen.generate(n, R, q, p, 13)
     Hd = bbl.DeviceCSR.from_host(H, "float32", block_rows=block_rows)
     plan = bbl.spmm_plan(Hd, nvec)
-    bk = 8 if nvec == 16 else nvec
+    # 16 vectors: sets of 16-wide rows (lane pairs) when one block fits
+    # beside the zero row, else 8-column halves
+    bk = 8 if nvec == 16 and (block_rows + 1) * 64 > 160 * 1024 else nvec
     s = min(5, (160 * 1024 // (bk * 4) - 1) // block_rows)
     assert plan.c.nsets > 0 and plan.slots == s
     assert plan.c.nsets == min(16 // s, -(-10 // s))
@@ -620,15 +629,21 @@ def test_fp32_path_matches_oracle_on_rounded_matrix(torch, bbl):
         bbl.block_lanczos(Hp, P[:, :4].contiguous(), 4, 1e-6, m_max=50, spmm_plan=plan)
 
 
-def test_planned_solve_at_sixteen_vectors(torch, bbl):
-    """b = 16 through the planned SpMM's two 8-column passes: residuals of the
+@pytest.mark.parametrize("block_rows", [1000, 400])
+def test_planned_solve_at_sixteen_vectors(torch, bbl, block_rows):
+    """b = 16 through the planned SpMM -- at 1000-row groups one pass over
+    16-wide rows with lane pairs (a multi-set plan of two blocks per set), at
+    400-row groups two passes over 8-column halves: residuals of the
     converged pairs recomputed on the host in FP64, and the same eigenvalues
     (within the residual bound) as the solve through the plain CSR kernel."""
-    note("planned solve b=16")
+    note("planned solve b=16 block_rows=%d" % block_rows)
     H = synthgen.generate(20000, 1000, 105, 0.7, 12)
-    Hp = bbl.DeviceCSR.from_host(H, "float32", block_rows=1000)
+    Hp = bbl.DeviceCSR.from_host(H, "float32", block_rows=block_rows)
     plan = bbl.spmm_plan(Hp, 16)
-    assert plan.slots == 5
+    if block_rows == 1000:
+        assert plan.slots == 2 and plan.c.nsets > 0
+    else:
+        assert plan.slots == 5 and plan.c.nsets == 0
     P = bbl.random_pivot(H.n, 16, synthgen.pivot_key(3))
     rp = bbl.block_lanczos(Hp, P, 10, 1e-6, m_max=120, spmm_plan=plan)
     r = bbl.block_lanczos(Hp, P, 10, 1e-6, m_max=120)
