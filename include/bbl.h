@@ -125,8 +125,10 @@ typedef struct {
   const int32_t *rlist;   /* [n][4] */
   /* Multi-set layout (nsets > 0; the fields from n_local to brow are then
    * NULL): when fewer than three column blocks fit in LDS per set (e.g.
-   * 2000-row groups at 8 float32 columns) or the entries need 64-bit
-   * offsets, the group's busiest blocks form nsets sets of `slots` blocks
+   * 2000-row groups at 8 float32 columns; at 16 columns, blocks of 16-wide
+   * rows where one fits beside the all-zero row, else of 8-column halves) or
+   * the entries need 64-bit offsets, the group's busiest blocks form nsets
+   * sets of `slots` blocks
    * (blocks: [groups][nsets * slots]), staged in LDS one set after the other.
    * Each set keeps a dense copy of its entries (16-bit LDS index within the
    * set, value; the copies lie set after set, group after group, rows in

@@ -1821,7 +1821,8 @@ bool plan_local16(const bbl_csr &H, int slots) {
 bool plan_desc(const bbl_csr &H) { return H.nnz < ((int64_t)1 << 31) - 64; }
 
 // Multi-set layout: float32 values and vectors at 4, 8, 10 or 16 vectors
-// (16 as two halves of 8), when fewer than three column blocks fit in LDS
+// (16 as 16-wide rows read by lane pairs where a block of them fits in LDS,
+// else as two halves of 8), when fewer than three column blocks fit in LDS
 // per set or the entries need 64-bit offsets.  *slots blocks per set,
 // *nsets sets covering the busiest kMsBlocks blocks of each group.
 constexpr int kMsBlocks = 10;
