@@ -714,69 +714,14 @@ __global__ __launch_bounds__(64) void k_gram_v(int64_t n, const XT *__restrict__
 //
 // PF > 1: the loads of PF blocks are issued before their products (for short
 // grids, where each lane's walk over the blocks is latency-bound).
-template <typename XT, typename YIT, typename YOT, int BX, int NY, int RPL, bool GRAM, int PF>
+template <typename XT, typename YIT, typename YOT, int BX, int NY, int RPL, bool GRAM, int PF,
+          bool TL = false>
 __global__ __launch_bounds__(256) void k_update_v(int64_t n, const XT *X, int nblk,
                                                   int64_t xstride, const double *__restrict__ C,
                                                   double alpha, const YIT *Yin, double beta,
                                                   YOT *Yout, const int *__restrict__ when,
                                                   double *__restrict__ gpart) {
   if (when && *when == 0) return;
-  const int64_t base = (int64_t)blockIdx.x * 256 * RPL + threadIdx.x;
-  double acc[RPL][NY];
-#pragma unroll
-  for (int u = 0; u < RPL; ++u)
-#pragma unroll
-    for (int j = 0; j < NY; ++j) acc[u][j] = 0.0;
-  int blk0 = 0;
-  if constexpr (PF > 1) {
-    for (; blk0 + PF <= nblk; blk0 += PF) {
-      Vec<XT, BX> xp[PF][RPL];
-#pragma unroll
-      for (int p = 0; p < PF; ++p)
-#pragma unroll
-        for (int u = 0; u < RPL; ++u) {
-          const int64_t r = base + (int64_t)u * 256;
-          if (r < n) xp[p][u] = vload<XT, BX>(X + (int64_t)(blk0 + p) * xstride + r * BX);
-          else
-#pragma unroll
-            for (int c = 0; c < BX; ++c) xp[p][u].v[c] = XT(0);
-        }
-#pragma unroll
-      for (int p = 0; p < PF; ++p) {
-        const double *cb = C + (int64_t)(blk0 + p) * BX * NY;
-#pragma unroll
-        for (int a = 0; a < BX; ++a) {
-#pragma unroll
-          for (int j = 0; j < NY; ++j) {
-            const double cv = cb[a * NY + j];
-#pragma unroll
-            for (int u = 0; u < RPL; ++u) acc[u][j] = fma((double)xp[p][u].v[a], cv, acc[u][j]);
-          }
-        }
-      }
-    }
-  }
-  for (int blk = blk0; blk < nblk; ++blk) {
-    Vec<XT, BX> xv[RPL];
-#pragma unroll
-    for (int u = 0; u < RPL; ++u) {
-      const int64_t r = base + (int64_t)u * 256;
-      if (r < n) xv[u] = vload<XT, BX>(X + (int64_t)blk * xstride + r * BX);
-      else
-#pragma unroll
-        for (int c = 0; c < BX; ++c) xv[u].v[c] = XT(0);
-    }
-    const double *cb = C + (int64_t)blk * BX * NY;
-#pragma unroll
-    for (int a = 0; a < BX; ++a) {
-#pragma unroll
-      for (int j = 0; j < NY; ++j) {
-        const double cv = cb[a * NY + j];
-#pragma unroll
-        for (int u = 0; u < RPL; ++u) acc[u][j] = fma((double)xv[u].v[a], cv, acc[u][j]);
-      }
-    }
-  }
   constexpr int NP = NY * (NY + 1) / 2;
   constexpr int S = (256 / NP) > 0 ? 256 / NP : 1;  // slices per Gram entry
   static_assert(NP <= 256, "Gram epilogue: too many entries");
@@ -790,36 +735,102 @@ __global__ __launch_bounds__(256) void k_update_v(int64_t n, const XT *X, int nb
     ga = e - gc * (gc + 1) / 2;
   }
   double gsum = 0.0;
+  // tiles of 256 RPL rows: one per workgroup, or (TL: the grid was capped to
+  // bound the Gram partials) a workgroup strides over them
+  auto do_tile = [&](int64_t tl) __attribute__((always_inline)) {
+    const int64_t base = tl * 256 * RPL + threadIdx.x;
+    double acc[RPL][NY];
 #pragma unroll
-  for (int u = 0; u < RPL; ++u) {
-    const int64_t r = base + (int64_t)u * 256;
-    double ov[NY];
+    for (int u = 0; u < RPL; ++u)
 #pragma unroll
-    for (int j = 0; j < NY; ++j) ov[j] = 0.0;
-    if (r < n) {
-      YOT o[NY];
-      if (beta != 0.0) {
-        const Vec<YIT, NY> yi = vload<YIT, NY>(Yin + r * NY);
+      for (int j = 0; j < NY; ++j) acc[u][j] = 0.0;
+    int blk0 = 0;
+    if constexpr (PF > 1) {
+      for (; blk0 + PF <= nblk; blk0 += PF) {
+        Vec<XT, BX> xp[PF][RPL];
 #pragma unroll
-        for (int j = 0; j < NY; ++j) o[j] = (YOT)fma(beta, (double)yi.v[j], alpha * acc[u][j]);
-      } else {
+        for (int p = 0; p < PF; ++p)
 #pragma unroll
-        for (int j = 0; j < NY; ++j) o[j] = (YOT)(alpha * acc[u][j]);
-      }
+          for (int u = 0; u < RPL; ++u) {
+            const int64_t r = base + (int64_t)u * 256;
+            if (r < n) xp[p][u] = vload<XT, BX>(X + (int64_t)(blk0 + p) * xstride + r * BX);
+            else
 #pragma unroll
-      for (int j = 0; j < NY; ++j) {
-        Yout[r * NY + j] = o[j];
-        ov[j] = (double)o[j];
+              for (int c = 0; c < BX; ++c) xp[p][u].v[c] = XT(0);
+          }
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+          const double *cb = C + (int64_t)(blk0 + p) * BX * NY;
+#pragma unroll
+          for (int a = 0; a < BX; ++a) {
+#pragma unroll
+            for (int j = 0; j < NY; ++j) {
+              const double cv = cb[a * NY + j];
+#pragma unroll
+              for (int u = 0; u < RPL; ++u) acc[u][j] = fma((double)xp[p][u].v[a], cv, acc[u][j]);
+            }
+          }
+        }
       }
     }
-    if constexpr (GRAM) {
-      __syncthreads();  // the previous tile is consumed
+    for (int blk = blk0; blk < nblk; ++blk) {
+      Vec<XT, BX> xv[RPL];
 #pragma unroll
-      for (int j = 0; j < NY; ++j) tile[t][j] = ov[j];
-      __syncthreads();
-      if (t < NP * S)
-        for (int q = t % S; q < 256; q += S) gsum = fma(tile[q][ga], tile[q][gc], gsum);
+      for (int u = 0; u < RPL; ++u) {
+        const int64_t r = base + (int64_t)u * 256;
+        if (r < n) xv[u] = vload<XT, BX>(X + (int64_t)blk * xstride + r * BX);
+        else
+#pragma unroll
+          for (int c = 0; c < BX; ++c) xv[u].v[c] = XT(0);
+      }
+      const double *cb = C + (int64_t)blk * BX * NY;
+#pragma unroll
+      for (int a = 0; a < BX; ++a) {
+#pragma unroll
+        for (int j = 0; j < NY; ++j) {
+          const double cv = cb[a * NY + j];
+#pragma unroll
+          for (int u = 0; u < RPL; ++u) acc[u][j] = fma((double)xv[u].v[a], cv, acc[u][j]);
+        }
+      }
     }
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      const int64_t r = base + (int64_t)u * 256;
+      double ov[NY];
+#pragma unroll
+      for (int j = 0; j < NY; ++j) ov[j] = 0.0;
+      if (r < n) {
+        YOT o[NY];
+        if (beta != 0.0) {
+          const Vec<YIT, NY> yi = vload<YIT, NY>(Yin + r * NY);
+#pragma unroll
+          for (int j = 0; j < NY; ++j) o[j] = (YOT)fma(beta, (double)yi.v[j], alpha * acc[u][j]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < NY; ++j) o[j] = (YOT)(alpha * acc[u][j]);
+        }
+#pragma unroll
+        for (int j = 0; j < NY; ++j) {
+          Yout[r * NY + j] = o[j];
+          ov[j] = (double)o[j];
+        }
+      }
+      if constexpr (GRAM) {
+        __syncthreads();  // the previous tile is consumed
+#pragma unroll
+        for (int j = 0; j < NY; ++j) tile[t][j] = ov[j];
+        __syncthreads();
+        if (t < NP * S)
+          for (int q = t % S; q < 256; q += S) gsum = fma(tile[q][ga], tile[q][gc], gsum);
+      }
+    }
+  };
+  if constexpr (TL) {
+    const int64_t ntiles = (n + 256 * RPL - 1) / (256 * RPL);
+    for (int64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) do_tile(tl);
+  } else {
+    do_tile(blockIdx.x);
   }
   if constexpr (GRAM) {
     red[t] = gsum;
@@ -1029,12 +1040,20 @@ int gram_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const 
 }
 
 constexpr int kUpdRPL = 2;  // rows per lane of k_update_v (256-row stride)
+// Workgroups of k_update_v when it also leaves Gram partials (one per
+// workgroup): beyond this many row tiles the workgroups stride over them, so
+// the partials stay within the caller's buffer at any n
+constexpr int64_t kUpdMaxGramParts = 16384;
+inline int64_t update_tiles(int64_t n) { return ceil_div(n, 256 * kUpdRPL); }
+inline int64_t update_gram_parts(int64_t n) {
+  return std::min<int64_t>(update_tiles(n), kUpdMaxGramParts);
+}
 
 template <typename XT, typename YIT, typename YOT, int B, int NY = B>
 void update_valu(int64_t n, const XT *X, int nblk, int64_t xstride, const double *C, double alpha,
                  const YIT *Yin, double beta, YOT *Yout, const int *when, double *gpart,
                  hipStream_t s) {
-  const int64_t grid = ceil_div(n, 256 * kUpdRPL);
+  const int64_t grid = gpart ? update_gram_parts(n) : update_tiles(n);
   // a short grid (few rows) with many blocks: split the blocks over waves
   // (no fused Gram then); a short grid with a few blocks: prefetch four at a
   // time
@@ -1050,7 +1069,11 @@ void update_valu(int64_t n, const XT *X, int nblk, int64_t xstride, const double
 #define BBL_UPDV(G, PF)                                                                        \
   hipLaunchKernelGGL((k_update_v<XT, YIT, YOT, B, NY, kUpdRPL, G, PF>), dim3((unsigned)grid),    \
                      dim3(256), 0, s, n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart)
-  if (gpart) {
+  if (gpart && update_tiles(n) > grid) {  // capped grid: workgroups stride over the tiles
+    hipLaunchKernelGGL((k_update_v<XT, YIT, YOT, B, NY, kUpdRPL, true, 1, true>),
+                       dim3((unsigned)grid), dim3(256), 0, s, n, X, nblk, xstride, C, alpha, Yin,
+                       beta, Yout, when, gpart);
+  } else if (gpart) {
     if (pf) BBL_UPDV(true, 4);
     else BBL_UPDV(true, 1);
   } else {
@@ -1087,7 +1110,7 @@ int update_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, cons
                  int ny, double alpha, const YIT *Yin, double beta, YOT *Yout, const int *when,
                  double *gpart, hipStream_t s) {
   const int M = nblk * bx;
-  const int P = (int)ceil_div(n, 256 * kUpdRPL);
+  const int P = (int)update_gram_parts(n);
   if (bx == 8 && ny == 10) {  // Ritz vectors of b = 8 blocks, k = 10
     update_valu<XT, YIT, YOT, 8, 10>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s);
     return gpart ? P : 0;
@@ -1203,7 +1226,7 @@ int launch_update_gram_when(int64_t n, const void *X, int xdtype, int bx, int nb
 #undef BBL_U16
   }
   // room for the partials and the reduction's stage-1 sums behind them
-  const int64_t P = ceil_div(n, 256 * kUpdRPL);
+  const int64_t P = update_gram_parts(n);
   if (gpart && (size_t)(P + P / 8 + 64) * ny * ny > gcap_doubles) gpart = nullptr;
 #define BBL_UPD(XT, YIT, YOT)                                                                 \
   return update_typed(n, (const XT *)X, bx, nblk, xstride, C, ny, alpha, (const YIT *)Yin,    \

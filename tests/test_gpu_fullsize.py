@@ -235,3 +235,41 @@ def test_multiset_plan_beyond_2_31_entries(torch, bbl):
                                     [0, n - 1, cut - 1, cut, cut + 1]]))
     note("checking %d sampled rows" % len(idx))
     check_sampled_rows(W[torch.from_numpy(idx).cuda()].double().cpu().numpy(), V, H, idx)
+
+
+def test_gram_fused_update_beyond_its_partial_cap(torch, bbl):
+    """n = 9e6 rows: more 512-row tiles than the update keeps Gram partials
+    for (16384), so its workgroups stride over the tiles and still leave the
+    Gram matrix of their output, which the block QR factors.  Twelve blocks
+    of 8 FP32 vectors (no convergence asked: tol 1e-300): the stored basis
+    orthonormal (max |V^T V - I| <= 1e-6) and V^T H V equal to the band matrix
+    the solve built (<= 1e-5 ||H||)."""
+    n, b, m_max = 9_000_000, 8, 12
+    note("generating n=9e6, sectors of 1000, ~20 nnz/row")
+    H = synthgen.generate(n, 1000, 10, 0.7, 17, values="f32")
+    Hd = bbl.DeviceCSR.from_host(H, "float32", block_rows=1000)
+    P = bbl.random_pivot(n, b, synthgen.pivot_key(5))
+    r = bbl.block_lanczos(Hd, P, 4, 1e-300, m_max=m_max, check_every=50)
+    m = r.stats["basis_blocks"]
+    assert m == m_max, r.stats
+    hn = r.stats["hnorm_est"]
+    basis_addr, band_addr = bbl.workspace_views(r.workspace, n, b, 4, m_max, bbl.BBL_F32)
+    ws = r.workspace
+    off = basis_addr - ws.data_ptr()
+    Vall = ws[off:off + m * n * b * 4].view(torch.float32).view(m, n, b)
+    boff = band_addr - ws.data_ptr()
+    band = ws[boff:boff + m * b * (b + 1) * 8].view(torch.float64).view(m * b, b + 1).cpu().numpy()
+    T = np.zeros((m * b, m * b))
+    for i in range(m * b):
+        for d in range(min(b, i) + 1):
+            T[i, i - d] = T[i - d, i] = band[i, d]
+    VtV = np.zeros((m * b, m * b))
+    VtHV = np.zeros((m * b, m * b))
+    for j in range(m):
+        VtV[:, j * b:(j + 1) * b] = bbl.gram(Vall, m, b, Vall[j].double().contiguous()).cpu().numpy()
+        HVj = bbl.spmm(Hd, Vall[j].contiguous()).double()
+        VtHV[:, j * b:(j + 1) * b] = bbl.gram(Vall, m, b, HVj).cpu().numpy()
+    e_orth = np.max(np.abs(VtV - np.eye(m * b)))
+    e_band = np.max(np.abs(VtHV - T)) / hn
+    note("max |V^T V - I| = %.2e, max |V^T H V - T| / ||H|| = %.2e" % (e_orth, e_band))
+    assert e_orth <= 1e-6 and e_band <= 1e-5
