@@ -193,8 +193,10 @@ typedef struct {
   int32_t iters;        /* block iterations (products H V_j of the recurrence)
                            that built the space the returned pairs come from,
                            over all thick-restart cycles (the recurrence may
-                           have built up to two more while the last check ran
-                           beside it) */
+                           have built a few more while the last check ran
+                           beside it: up to two, or four when n < 2^19, whose
+                           blocks are short next to the check's band
+                           eigensolve) */
   int32_t spmm_calls;   /* all products with H, explicit residual checks and
                            the blocks built beside the last check included */
   int32_t deflations;   /* columns replaced because of (near) rank loss */

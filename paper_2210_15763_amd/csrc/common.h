@@ -103,6 +103,8 @@ void launch_update(int64_t n, const void *X, int xdtype, int bx, int nblk, int64
 void launch_fill(double *p, int64_t count, double v, hipStream_t s);
 // *p = v (one lane; a kernel, so it may be recorded into a graph)
 void launch_store_int(int *p, int v, hipStream_t s);
+// *dd = *ds and *id = *is in one launch (a one-thread kernel)
+void launch_copy_pair(double *dd, const double *ds, int *id, const int *is, hipStream_t s);
 
 // Random normal block (Philox4x32-10 + Box-Muller), entry (i, a) from counter
 // (i, a + col0, tag).

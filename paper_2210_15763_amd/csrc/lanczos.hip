@@ -118,6 +118,18 @@ Layout make_layout(int64_t n, int b, int k, int m_max, int bdt, int keep = 0) {
 // -- and every truncated solve of a pivot -- creates no stream, event or
 // pinned buffer of its own.
 constexpr int kLag = 2, kRing = 4;
+// A convergence check is read this many blocks after the block it ends with
+// (and once that block is verified).  Problems of fewer than kShortRows rows
+// (blocks of about 0.1-0.3 ms) read it later than kLag: the band eigensolve
+// takes about 0.7 ms whatever n, and a host that waited for it sooner would
+// leave the main stream idle (n = 20,000, b = 8, 91-94 blocks: 21.0 ms with
+// kLag, 18.6 ms with 4).  The lag is a function of the problem, not of
+// timing, so the check schedule and the results stay deterministic.
+#ifndef BBL_CHECK_LAG_SHORT
+#define BBL_CHECK_LAG_SHORT 4
+#endif
+constexpr int kCheckLagShort = BBL_CHECK_LAG_SHORT;
+constexpr int64_t kShortRows = int64_t(1) << 19;
 constexpr int kIterFlags = 2 * (2 * kMaxBlock + 8);  // int offset in the pinned buffer
 
 // Phase boundaries recorded per block instance when phase timing is on:
@@ -537,14 +549,11 @@ struct Solver {
   // redone on the full path, which decides those branches on the device.
   void iterate(int J, bool fast, const double *hnorm_dev, PhaseTimer &timer, CheckStream &cq,
                Result &R) {
-    if (fast) {  // state as of this block's start, restored if it is redone:
+    if (fast)  // state as of this block's start, restored if it is redone:
       // max |A_jj|, and the sticky breakdown flag (an earlier block may have
       // raised it; the redone block's own QR decides again)
-      BBL_HIP(hipMemcpyAsync(dres + kHn2Snap + J % kRing, dres + kHn2Slot, sizeof(double),
-                             hipMemcpyDeviceToDevice, s));
-      BBL_HIP(hipMemcpyAsync(ints + kBreakSnap + J % kRing, breakdown, sizeof(int),
-                             hipMemcpyDeviceToDevice, s));
-    }
+      launch_copy_pair(dres + kHn2Snap + J % kRing, dres + kHn2Slot, ints + kBreakSnap + J % kRing,
+                       breakdown, s);
     hipEvent_t *ev = timer.begin();
     timer.mark(ev, 0, s);
     if (o.plan) launch_spmm_planned(*o.plan, slot(J), W, s);
@@ -637,6 +646,7 @@ struct Solver {
     int pending = 0, pending_kk = 0;  // blocks and pairs of the check in flight
     std::deque<int> unverified;       // fast blocks whose flags are not read yet
     int qr_snap[kRing] = {};          // qr_calls at the start of block J (J % kRing)
+    const int check_lag = n < kShortRows ? kCheckLagShort : kLag;
     bool redo = false;
     PhaseTimer timer;
     timer.cq = &cq;
@@ -691,7 +701,7 @@ struct Solver {
       }
       // the pending check, once the block it ends with is verified
       const int ok_upto = unverified.empty() ? J : unverified.front() - 1;
-      if (pending && pending - 1 <= ok_upto) {
+      if (pending && pending - 1 <= ok_upto && J >= pending - 1 + check_lag) {
         const int nb = pending;
         pending = 0;
         if (consume_check(cq, nb, pending_kk, false, hnorm_dev, Xout, R)) break;

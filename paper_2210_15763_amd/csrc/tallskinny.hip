@@ -47,6 +47,22 @@ constexpr int kTilesPerWG = 8;   // 16-column tiles of X handled by one gram WG
 // number of waves (row chunks x column groups) the grid is sized to
 constexpr int kGramWaves = BBL_GRAM_WAVES;
 constexpr int kGramWaveTarget = BBL_GRAM_WAVE_TARGET;
+#ifndef BBL_GRAM_SMALL_U
+#define BBL_GRAM_SMALL_U 8
+#endif
+#ifndef BBL_GRAM_SMALL_CHUNK
+#define BBL_GRAM_SMALL_CHUNK 64
+#endif
+#ifndef BBL_GRAM1_MIN_ROWS
+#define BBL_GRAM1_MIN_ROWS 128
+#endif
+// short row counts (a truncated problem), where every kernel is bound by the
+// latency of its serial load rounds, not by bandwidth: row groups of four in
+// flight per wave and rows per wave of the 8-wide FP64-MFMA gram; fewest rows
+// per wave of the one-block gram
+constexpr int kGramSmallU = BBL_GRAM_SMALL_U;
+constexpr int kGramSmallChunk = BBL_GRAM_SMALL_CHUNK;
+constexpr int kGram1MinRows = BBL_GRAM1_MIN_ROWS;
 #ifndef BBL_G16_CG
 #define BBL_G16_CG 1
 #endif
@@ -850,42 +866,95 @@ __global__ __launch_bounds__(256) void k_update_v(int64_t n, const XT *X, int nb
 
 // Update for short row counts (a truncated problem): Yout = beta Yin +
 // alpha X C with the basis blocks split over the eight waves of a workgroup
-// (wave w takes blocks w, w + 8, ...; C stays wave-uniform) and one row per
-// lane, so the grid holds eight times as many waves as one row per lane over
-// all blocks would; the eight partial sums of each row are added in LDS in
-// fixed order, thread t finishing component t / 64 of row t % 64.
-template <typename XT, typename YIT, typename YOT, int BX, int NY>
+// (wave w takes blocks w, w + 8, ...) and one row per lane, so the grid holds
+// eight times as many waves as one row per lane over all blocks would; the
+// eight partial sums of each row are added in LDS in fixed order, thread t
+// finishing component t / 64 of row t % 64.  Lane l loads entry l of a
+// block's BX x NY slice of C (one vector load per block) and the products
+// take the entries with v_readlane: scalar loads of C, whose slices of all
+// blocks do not fit the scalar cache, ran at half this speed (n = 20,000,
+// 91 blocks: 48 against 26 us).
+//
+// GRAM: also gpart[blockIdx.x][a][c] = sum over the workgroup's 64 rows of
+// Yout[r][a] Yout[r][c] (the values as stored): thread (e, q) sums entry e
+// over rows q, q + S, ... and the S slices are added in fixed order.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const unsigned long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+template <typename XT, typename YIT, typename YOT, int BX, int NY, bool GRAM>
 __global__ __launch_bounds__(512) void k_update_w8(int64_t n, const XT *X, int nblk,
                                                    int64_t xstride, const double *__restrict__ C,
                                                    double alpha, const YIT *Yin, double beta,
-                                                   YOT *Yout, const int *__restrict__ when) {
+                                                   YOT *Yout, const int *__restrict__ when,
+                                                   double *__restrict__ gpart) {
   static_assert(NY <= 8, "one component per wave");
+  static_assert(BX * NY <= 64, "one C entry per lane");
+  constexpr int NP = NY * (NY + 1) / 2;
+  constexpr int S = 512 / NP;  // slices per Gram entry
   if (when && *when == 0) return;
   __shared__ double part[8][64][NY];
+  __shared__ double gt[GRAM ? 64 : 1][NY + 1];
+  __shared__ double red[GRAM ? 512 : 1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t r = (int64_t)blockIdx.x * 64 + lane;
   double acc[NY];
 #pragma unroll
   for (int j = 0; j < NY; ++j) acc[j] = 0.0;
-  if (r < n) {
-    for (int blk = w; blk < nblk; blk += 8) {
-      const Vec<XT, BX> xv = vload<XT, BX>(X + (int64_t)blk * xstride + r * BX);
-      const double *cb = C + (int64_t)blk * BX * NY;
+  // the loop is uniform over the wave (v_readlane reads a lane whether it is
+  // active or not, so every lane loads its C entry); rows past n load zeros
+  for (int blk = w; blk < nblk; blk += 8) {
+    Vec<XT, BX> xv;
+    if (r < n) xv = vload<XT, BX>(X + (int64_t)blk * xstride + r * BX);
+    else
 #pragma unroll
-      for (int a = 0; a < BX; ++a)
+      for (int c = 0; c < BX; ++c) xv.v[c] = XT(0);
+    const double cl = lane < BX * NY ? C[(int64_t)blk * BX * NY + lane] : 0.0;
 #pragma unroll
-        for (int j = 0; j < NY; ++j) acc[j] = fma((double)xv.v[a], cb[a * NY + j], acc[j]);
-    }
+    for (int a = 0; a < BX; ++a)
+#pragma unroll
+      for (int j = 0; j < NY; ++j) acc[j] = fma((double)xv.v[a], readlane_f64(cl, a * NY + j), acc[j]);
   }
 #pragma unroll
   for (int j = 0; j < NY; ++j) part[w][lane][j] = acc[j];
   __syncthreads();
+  double o = 0.0;
   if (w < NY && r < n) {
     double v = 0.0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) v += part[q][lane][w];
-    const double o = beta != 0.0 ? fma(beta, (double)Yin[r * NY + w], alpha * v) : alpha * v;
-    Yout[r * NY + w] = (YOT)o;
+    o = beta != 0.0 ? fma(beta, (double)Yin[r * NY + w], alpha * v) : alpha * v;
+    const YOT ov = (YOT)o;
+    Yout[r * NY + w] = ov;
+    o = (double)ov;
+  }
+  if constexpr (GRAM) {
+    if (w < NY) gt[lane][w] = o;
+    __syncthreads();
+    const int t = threadIdx.x;
+    double gsum = 0.0;
+    int ga = 0, gc = 0;
+    if (t < NP * S) {
+      const int e = t / S;
+      while ((gc + 1) * (gc + 2) / 2 <= e) ++gc;
+      ga = e - gc * (gc + 1) / 2;
+      for (int q = t % S; q < 64; q += S) gsum = fma(gt[q][ga], gt[q][gc], gsum);
+    }
+    red[t] = gsum;
+    __syncthreads();
+    if (t < NP) {
+      int c = 0;
+      while ((c + 1) * (c + 2) / 2 <= t) ++c;
+      const int a = t - c * (c + 1) / 2;
+      double v = 0.0;
+      for (int q = 0; q < S; ++q) v += red[t * S + q];
+      double *out = gpart + (int64_t)blockIdx.x * NY * NY;
+      out[a * NY + c] = v;
+      out[c * NY + a] = v;
+    }
   }
 }
 
@@ -979,7 +1048,7 @@ int gram_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const 
     // one block: rows across lanes, 1024 waves at most (4096 ran slower at
     // n = 2e6: 36 against 30 us)
     const int64_t waves = std::max<int64_t>(1, std::min<int64_t>({(int64_t)max_partials - 4, (int64_t)1024,
-                                                                    ceil_div(n, 1024)}));
+                                                                    ceil_div(n, kGram1MinRows)}));
     const int64_t rpw = ceil_div(ceil_div(n, waves), 64) * 64;
     const int64_t nw = ceil_div(n, rpw);
     const int64_t grid = ceil_div(nw, 4);
@@ -998,17 +1067,26 @@ int gram_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const 
     // 45, 90 and 181 blocks run fastest with 1024, 512 and 256 row chunks,
     // 5.1-5.3 TB/s; 20 blocks with 2048 chunks, 4.8 TB/s against 3.6 with
     // 1024)
-    constexpr int CG = 1, U = 2, WPG = kGramWaves;
+    constexpr int CG = 1, WPG = kGramWaves;
     const int gy = (M + 64 * CG - 1) / (64 * CG);
     int64_t gx = std::min<int64_t>(2048, ceil_div(kGramWaveTarget, gy));
-    gx = std::max<int64_t>(1, std::min<int64_t>(gx, ceil_div(n, 256)));
+    // short row counts: shorter row chunks with more rows in flight, so each
+    // wave takes a few load rounds instead of dozens
+    const bool small = ceil_div(n, 256) < gx;
+    const int U = small ? kGramSmallU : 2;
+    gx = std::max<int64_t>(1, std::min<int64_t>(gx, ceil_div(n, small ? kGramSmallChunk : 256)));
     gx = std::min<int64_t>(gx, std::max(1, max_partials));
     int64_t chunk = ceil_div(ceil_div(n, gx), 4 * U) * (4 * U);
     gx = ceil_div(n, chunk);
     const int64_t grid = ceil_div(gx, 8) * 8 * ceil_div(gy, WPG);
-    hipLaunchKernelGGL((k_gram_mfma8<CG, U, WPG>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, n,
-                       (const float *)X, M, xstride, (const double *)Y, chunk, (int)gx, gy,
-                       partial, when);
+    if (small)
+      hipLaunchKernelGGL((k_gram_mfma8<CG, kGramSmallU, WPG>), dim3((unsigned)grid),
+                         dim3(64 * WPG), 0, s, n, (const float *)X, M, xstride,
+                         (const double *)Y, chunk, (int)gx, gy, partial, when);
+    else
+      hipLaunchKernelGGL((k_gram_mfma8<CG, 2, WPG>), dim3((unsigned)grid), dim3(64 * WPG), 0, s,
+                         n, (const float *)X, M, xstride, (const double *)Y, chunk, (int)gx, gy,
+                         partial, when);
     check_launch("k_gram_mfma8");
     return (int)gx;
   }
@@ -1048,6 +1126,14 @@ inline int64_t update_tiles(int64_t n) { return ceil_div(n, 256 * kUpdRPL); }
 inline int64_t update_gram_parts(int64_t n) {
   return std::min<int64_t>(update_tiles(n), kUpdMaxGramParts);
 }
+// the wave-split kernel k_update_w8 (short grids, many blocks); its Gram
+// partials are one per 64 rows
+inline bool update_split(int64_t n, int nblk, int ny) {
+  return update_tiles(n) < 512 && nblk >= 16 && ny <= 8;
+}
+inline int64_t update_parts(int64_t n, int nblk, int ny) {
+  return update_split(n, nblk, ny) ? ceil_div(n, 64) : update_gram_parts(n);
+}
 
 template <typename XT, typename YIT, typename YOT, int B, int NY = B>
 void update_valu(int64_t n, const XT *X, int nblk, int64_t xstride, const double *C, double alpha,
@@ -1057,10 +1143,15 @@ void update_valu(int64_t n, const XT *X, int nblk, int64_t xstride, const double
   // a short grid (few rows) with many blocks: split the blocks over waves
   // (no fused Gram then); a short grid with a few blocks: prefetch four at a
   // time
-  if (grid < 512 && nblk >= 16 && NY <= 8) {
+  if (update_split(n, nblk, NY)) {
     if constexpr (NY <= 8) {
-      hipLaunchKernelGGL((k_update_w8<XT, YIT, YOT, B, NY>), dim3((unsigned)ceil_div(n, 64)),
-                         dim3(512), 0, s, n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when);
+      const dim3 grid8((unsigned)ceil_div(n, 64)), wg8(512);
+      if (gpart)
+        hipLaunchKernelGGL((k_update_w8<XT, YIT, YOT, B, NY, true>), grid8, wg8, 0, s, n,
+                           X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart);
+      else
+        hipLaunchKernelGGL((k_update_w8<XT, YIT, YOT, B, NY, false>), grid8, wg8, 0, s, n,
+                           X, nblk, xstride, C, alpha, Yin, beta, Yout, when, nullptr);
       check_launch("k_update_w8");
       return;
     }
@@ -1110,17 +1201,15 @@ int update_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, cons
                  int ny, double alpha, const YIT *Yin, double beta, YOT *Yout, const int *when,
                  double *gpart, hipStream_t s) {
   const int M = nblk * bx;
-  const int P = (int)update_gram_parts(n);
+  const int P = (int)update_parts(n, nblk, ny);
   if (bx == 8 && ny == 10) {  // Ritz vectors of b = 8 blocks, k = 10
     update_valu<XT, YIT, YOT, 8, 10>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s);
     return gpart ? P : 0;
   }
-  // the wave-split kernel (short grids, many blocks) leaves no Gram partials
-  const bool split = P < 512 && nblk >= 16 && ny <= 8;
   if (ny == bx) {
     switch (bx) {
-      case 4: update_valu<XT, YIT, YOT, 4>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s); return gpart && !split ? P : 0;
-      case 8: update_valu<XT, YIT, YOT, 8>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s); return gpart && !split ? P : 0;
+      case 4: update_valu<XT, YIT, YOT, 4>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s); return gpart ? P : 0;
+      case 8: update_valu<XT, YIT, YOT, 8>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s); return gpart ? P : 0;
       case 10: update_valu<XT, YIT, YOT, 10>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s); return gpart ? P : 0;
       case 16: update_valu<XT, YIT, YOT, 16>(n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart, s); return gpart ? P : 0;
       default: break;
@@ -1226,7 +1315,7 @@ int launch_update_gram_when(int64_t n, const void *X, int xdtype, int bx, int nb
 #undef BBL_U16
   }
   // room for the partials and the reduction's stage-1 sums behind them
-  const int64_t P = update_gram_parts(n);
+  const int64_t P = update_parts(n, nblk, ny);
   if (gpart && (size_t)(P + P / 8 + 64) * ny * ny > gcap_doubles) gpart = nullptr;
 #define BBL_UPD(XT, YIT, YOT)                                                                 \
   return update_typed(n, (const XT *)X, bx, nblk, xstride, C, ny, alpha, (const YIT *)Yin,    \
@@ -1264,6 +1353,18 @@ __global__ void k_store_int(int *p, int v) {
 void launch_store_int(int *p, int v, hipStream_t s) {
   hipLaunchKernelGGL(k_store_int, dim3(1), dim3(64), 0, s, p, v);
   check_launch("k_store_int");
+}
+
+__global__ void k_copy_pair(double *dd, const double *ds, int *id, const int *is) {
+  if (threadIdx.x == 0) {
+    *dd = *ds;
+    *id = *is;
+  }
+}
+
+void launch_copy_pair(double *dd, const double *ds, int *id, const int *is, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_pair, dim3(1), dim3(64), 0, s, dd, ds, id, is);
+  check_launch("k_copy_pair");
 }
 
 void launch_fill(double *p, int64_t count, double v, hipStream_t s) {

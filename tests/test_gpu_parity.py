@@ -21,6 +21,9 @@ pytestmark = pytest.mark.gpu
 
 U64 = 2.0 ** -53
 U32 = 2.0 ** -24
+# blocks after the last block of a convergence check at which the solve reads
+# it, for problems of fewer than 2^19 rows (the tests' sizes)
+CHECK_LAG = 4
 
 
 def note(msg):
@@ -580,8 +583,9 @@ def test_spmm_timing_flag_times_every_block_and_changes_nothing(torch, bbl):
     t = bbl.block_lanczos(Hd, P, 4, 1e-8, m_max=300, time_spmm=True)
     assert a.stats["spmm_timed"] == 0 and a.stats["spmm_ms"] == 0.0
     # every block built is timed: the returned pairs' blocks, plus at most the
-    # two built while the deciding check ran and its last block was verified
-    assert t.stats["iters"] <= t.stats["spmm_timed"] <= t.stats["iters"] + 2
+    # CHECK_LAG built while the deciding check ran and its last block was
+    # verified
+    assert t.stats["iters"] <= t.stats["spmm_timed"] <= t.stats["iters"] + CHECK_LAG
     assert t.stats["spmm_ms"] > 0
     assert np.array_equal(a.eigvals, t.eigvals) and a.stats["iters"] == t.stats["iters"]
 
@@ -773,7 +777,7 @@ def test_phase_timing_fills_the_stats_and_changes_nothing(torch, bbl):
     for f in ("t_threeterm_ms", "t_reorth_ms", "t_qr_ms", "t_restart_ms", "t_eig_ms"):
         assert a.stats[f] == 0.0
     s = t.stats
-    assert s["iters"] <= s["spmm_timed"] <= s["iters"] + 2
+    assert s["iters"] <= s["spmm_timed"] <= s["iters"] + CHECK_LAG
     for f in ("spmm_ms", "t_threeterm_ms", "t_reorth_ms", "t_qr_ms", "t_eig_ms"):
         assert s[f] > 0.0, f
     assert s["spmm_ms"] + s["t_threeterm_ms"] + s["t_reorth_ms"] + s["t_qr_ms"] < s["t_total_ms"]
