@@ -63,6 +63,14 @@ constexpr int kGramWaveTarget = BBL_GRAM_WAVE_TARGET;
 constexpr int kGramSmallU = BBL_GRAM_SMALL_U;
 constexpr int kGramSmallChunk = BBL_GRAM_SMALL_CHUNK;
 constexpr int kGram1MinRows = BBL_GRAM1_MIN_ROWS;
+#ifndef BBL_GRAMV_MIN_CHUNK
+#define BBL_GRAMV_MIN_CHUNK 64
+#endif
+#ifndef BBL_GRAMV_U
+#define BBL_GRAMV_U 4
+#endif
+// fewest rows per wave of the VALU gram, and its rows in flight per wave
+constexpr int kGramVMinChunk = BBL_GRAMV_MIN_CHUNK;
 #ifndef BBL_G16_CG
 #define BBL_G16_CG 1
 #endif
@@ -673,7 +681,7 @@ __global__ __launch_bounds__(64) void k_gram_v(int64_t n, const XT *__restrict__
   const int64_t r0 = (int64_t)blockIdx.x * chunk;
   const int64_t r1 = min(n, r0 + chunk);
   int64_t r = r0;
-  constexpr int U = 4;
+  constexpr int U = BBL_GRAMV_U;
   for (; r + U <= r1; r += U) {
     Vec<XT, CPL> xv[U];
 #pragma unroll
@@ -1005,7 +1013,7 @@ int gram_valu(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const Y
               double *partial, int max_partials, const int *when, hipStream_t s) {
   const int M = nblk * bx;
   const int gy = (M + 64 * CPL - 1) / (64 * CPL);
-  int64_t gx = std::max<int64_t>(1, std::min<int64_t>(2048 / gy + 1, ceil_div(n, 256)));
+  int64_t gx = std::max<int64_t>(1, std::min<int64_t>(2048 / gy + 1, ceil_div(n, kGramVMinChunk)));
   gx = std::min<int64_t>(gx, std::max(1, max_partials));
   int64_t chunk = ceil_div(n, gx);
   gx = ceil_div(n, chunk);
