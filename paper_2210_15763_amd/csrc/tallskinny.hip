@@ -71,6 +71,15 @@ constexpr int kGram1MinRows = BBL_GRAM1_MIN_ROWS;
 #endif
 // fewest rows per wave of the VALU gram, and its rows in flight per wave
 constexpr int kGramVMinChunk = BBL_GRAMV_MIN_CHUNK;
+#ifndef BBL_GRAM10_U
+#define BBL_GRAM10_U 2
+#endif
+// row groups of four in flight per wave of the 10-wide FP64-MFMA gram
+constexpr int kGram10U = BBL_GRAM10_U;
+#ifndef BBL_UPD10_PF
+#define BBL_UPD10_PF 1
+#endif
+constexpr int kUpd10Pf = BBL_UPD10_PF;
 #ifndef BBL_G16_CG
 #define BBL_G16_CG 1
 #endif
@@ -617,6 +626,83 @@ __global__ __launch_bounds__(64 * WPG) void k_gram_mfma8(int64_t n, const float 
     }
 }
 
+// Gram over 10-wide FP32 basis blocks (Y: n x 10) on v_mfma_f64_4x4x4f64,
+// with the operand layout of k_gram_mfma8.  Each block's 10 columns take 12
+// padded columns (three quads, the last ending in two zero columns), so no
+// quad of four consecutive columns straddles two blocks: lane (k, g, e) loads
+// padded columns 64 cy + 16 g + 4 e .. +3 of row r0 + k, two float2 runs
+// (one for the last quad; rows of 40 bytes keep them 8-byte aligned); Y's 10
+// columns are three B operands (columns 4t + e, the last quad padded with
+// zeros).  D lane 16i + 4g + j of product (q, t) holds padded X column
+// 64 cy + 16 g + 4 i + q against Y column 4t + j; padded columns are not
+// stored.  Work split, grid and workgroup order as in k_gram_mfma8.
+template <typename YT, int U>
+__global__ __launch_bounds__(64) void k_gram_mfma10(int64_t n, const float *__restrict__ X,
+                                                    int nblk, int64_t xstride,
+                                                    const YT *__restrict__ Y, int64_t chunk,
+                                                    int gx, int gy, double *__restrict__ partial,
+                                                    const int *__restrict__ when) {
+  if (when && *when == 0) return;
+  const int sb = blockIdx.x / (8 * gy), rem = blockIdx.x % (8 * gy);
+  const int cy = rem / 8, cx = sb * 8 + rem % 8;
+  if (cx >= gx) return;
+  const int l = threadIdx.x;
+  const int k = l >> 4, g = (l & 15) >> 2, e = l & 3;
+  const int Mp = nblk * 12;
+  const int cp = cy * 64 + 16 * g + 4 * e;  // first padded column of this lane's quad
+  const bool ok = cp < Mp;
+  const int a0 = cp % 12;                   // 0, 4 or 8
+  const float *xp = X + (int64_t)(ok ? cp / 12 : 0) * xstride + a0;
+  double acc[4][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) acc[q][t] = 0.0;
+  const int64_t r0 = (int64_t)cx * chunk;
+  const int64_t r1 = min(n, r0 + chunk);
+  for (int64_t rb = r0; rb < r1; rb += 4 * U) {
+    float x[U][4];
+    double y[U][3];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = rb + 4 * u + k;
+      const bool rok = r < r1;
+      y[u][0] = rok ? (double)Y[r * 10 + e] : 0.0;
+      y[u][1] = rok ? (double)Y[r * 10 + 4 + e] : 0.0;
+      y[u][2] = (rok && e < 2) ? (double)Y[r * 10 + 8 + e] : 0.0;
+      float2 p0 = make_float2(0.f, 0.f), p1 = make_float2(0.f, 0.f);
+      if (rok && ok) {
+        p0 = *reinterpret_cast<const float2 *>(xp + r * 10);
+        if (a0 < 8) p1 = *reinterpret_cast<const float2 *>(xp + r * 10 + 2);
+      }
+      x[u][0] = p0.x;
+      x[u][1] = p0.y;
+      x[u][2] = p1.x;
+      x[u][3] = p1.y;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+          acc[q][t] = __builtin_amdgcn_mfma_f64_4x4x4f64((double)x[u][q], y[u][t], acc[q][t], 0,
+                                                         0, 0);
+  }
+  double *out = partial + (int64_t)cx * nblk * 10 * 10;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = cy * 64 + 16 * g + 4 * k + q;  // padded X column of row i = k of D
+    const int a = c % 12;
+    if (c < Mp && a < 10) {
+      const int64_t m = (int64_t)(c / 12) * 10 + a;
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        if (4 * t + e < 10) out[m * 10 + 4 * t + e] = acc[q][t];
+    }
+  }
+}
+
 // Single-block gram C = X^T Y (X, Y: n x B row-major): lane = row, each lane
 // accumulates the B x B outer products of its rows, then one butterfly per
 // wave combines the lanes (fixed order).  partial[p][a][j], p = wave index.
@@ -655,6 +741,52 @@ __global__ __launch_bounds__(256) void k_gram1(int64_t n, const XT *__restrict__
     for (int a = 0; a < B; ++a)
 #pragma unroll
       for (int j = 0; j < B; ++j) out[a * B + j] = acc[a][j];
+  }
+}
+
+// Single-block gram over 10 columns (X, Y: n x 10 row-major): a lane pair
+// shares a row, lane 2p + h taking X columns 5h .. 5h + 4 against all ten Y
+// columns (50 sums per lane, so the wave keeps three-way occupancy where
+// k_gram1's 100 sums per lane would leave one); one butterfly over the lanes
+// of each parity adds them (fixed order).  partial[p][a][j], p = wave index.
+template <typename XT, typename YT>
+__global__ __launch_bounds__(256) void k_gram1_10(int64_t n, const XT *__restrict__ X,
+                                                  const YT *__restrict__ Y,
+                                                  int64_t rows_per_wave,
+                                                  double *__restrict__ partial,
+                                                  const int *__restrict__ when) {
+  if (when && *when == 0) return;
+  const int lane = threadIdx.x & 63, h = lane & 1;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t r0 = wave * rows_per_wave;
+  const int64_t r1 = min(n, r0 + rows_per_wave);
+  double acc[5][10];
+#pragma unroll
+  for (int a = 0; a < 5; ++a)
+#pragma unroll
+    for (int j = 0; j < 10; ++j) acc[a][j] = 0.0;
+  for (int64_t r = r0 + (lane >> 1); r < r1; r += 32) {
+    double x[5];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) x[a] = (double)X[r * 10 + 5 * h + a];
+    const Vec<YT, 10> y = vload<YT, 10>(Y + r * 10);
+#pragma unroll
+    for (int a = 0; a < 5; ++a)
+#pragma unroll
+      for (int j = 0; j < 10; ++j) acc[a][j] = fma(x[a], (double)y.v[j], acc[a][j]);
+  }
+#pragma unroll
+  for (int off = 32; off > 1; off >>= 1)
+#pragma unroll
+    for (int a = 0; a < 5; ++a)
+#pragma unroll
+      for (int j = 0; j < 10; ++j) acc[a][j] += __shfl_xor(acc[a][j], off, 64);
+  if (lane < 2) {
+    double *out = partial + wave * 100 + 50 * h;
+#pragma unroll
+    for (int a = 0; a < 5; ++a)
+#pragma unroll
+      for (int j = 0; j < 10; ++j) out[a * 10 + j] = acc[a][j];
   }
 }
 
@@ -1052,9 +1184,9 @@ int gram_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const 
     return gram_mfma16<XT, YT, kG16CG, kG16U>(n, X, nblk, xstride, Y, partial, max_partials,
                                               when, s);
   }
-  if (nblk == 1 && ny == bx && (bx == 4 || bx == 8)) {
-    // one block: rows across lanes, 1024 waves at most (4096 ran slower at
-    // n = 2e6: 36 against 30 us)
+  if (nblk == 1 && ny == bx && (bx == 4 || bx == 8 || bx == 10)) {
+    // one block: rows across lanes (10 columns: lane pairs), 1024 waves at
+    // most (4096 ran slower at n = 2e6: 36 against 30 us)
     const int64_t waves = std::max<int64_t>(1, std::min<int64_t>({(int64_t)max_partials - 4, (int64_t)1024,
                                                                     ceil_div(n, kGram1MinRows)}));
     const int64_t rpw = ceil_div(ceil_div(n, waves), 64) * 64;
@@ -1063,11 +1195,31 @@ int gram_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const 
     if (bx == 4)
       hipLaunchKernelGGL((k_gram1<XT, YT, 4>), dim3((unsigned)grid), dim3(256), 0, s, n, X, Y, rpw,
                          partial, when);
-    else
+    else if (bx == 8)
       hipLaunchKernelGGL((k_gram1<XT, YT, 8>), dim3((unsigned)grid), dim3(256), 0, s, n, X, Y, rpw,
                          partial, when);
+    else
+      hipLaunchKernelGGL((k_gram1_10<XT, YT>), dim3((unsigned)grid), dim3(256), 0, s, n, X, Y,
+                         rpw, partial, when);
     check_launch("k_gram1");
     return (int)(grid * 4);
+  }
+  if (bx == 10 && ny == 10 && f32 && nblk >= 2) {
+    // 64 padded columns (5 1/3 blocks) per one-wave workgroup, grid and row
+    // chunks as for 8-wide blocks below
+    const int gy = (nblk * 12 + 63) / 64;
+    int64_t gx = std::min<int64_t>(2048, ceil_div(kGramWaveTarget, gy));
+    const bool small = ceil_div(n, 256) < gx;
+    constexpr int U = kGram10U;
+    gx = std::max<int64_t>(1, std::min<int64_t>(gx, ceil_div(n, small ? kGramSmallChunk : 256)));
+    gx = std::min<int64_t>(gx, std::max(1, max_partials));
+    const int64_t chunk = ceil_div(ceil_div(n, gx), 4 * U) * (4 * U);
+    gx = ceil_div(n, chunk);
+    const int64_t grid = ceil_div(gx, 8) * 8 * gy;
+    hipLaunchKernelGGL((k_gram_mfma10<YT, U>), dim3((unsigned)grid), dim3(64), 0, s, n,
+                       (const float *)X, nblk, xstride, Y, chunk, (int)gx, gy, partial, when);
+    check_launch("k_gram_mfma10");
+    return (int)gx;
   }
   if (bx == 8 && ny == 8 && f32 && std::is_same<YT, double>::value && nblk >= 2) {
     // 64 basis columns per one-wave workgroup; about 6k workgroups in all, so
@@ -1165,6 +1317,7 @@ void update_valu(int64_t n, const XT *X, int nblk, int64_t xstride, const double
     }
   }
   const bool pf = grid < 512 && nblk >= 8;
+  const bool pf10 = !pf && B == 10 && NY == 10 && nblk >= 2 * kUpd10Pf && kUpd10Pf > 1;
 #define BBL_UPDV(G, PF)                                                                        \
   hipLaunchKernelGGL((k_update_v<XT, YIT, YOT, B, NY, kUpdRPL, G, PF>), dim3((unsigned)grid),    \
                      dim3(256), 0, s, n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart)
@@ -1174,9 +1327,11 @@ void update_valu(int64_t n, const XT *X, int nblk, int64_t xstride, const double
                        beta, Yout, when, gpart);
   } else if (gpart) {
     if (pf) BBL_UPDV(true, 4);
+    else if (pf10) BBL_UPDV(true, kUpd10Pf);
     else BBL_UPDV(true, 1);
   } else {
     if (pf) BBL_UPDV(false, 4);
+    else if (pf10) BBL_UPDV(false, kUpd10Pf);
     else BBL_UPDV(false, 1);
   }
 #undef BBL_UPDV

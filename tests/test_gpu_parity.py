@@ -396,7 +396,9 @@ def test_spmm_bitwise_reproducible(torch, bbl):
                                              (8, 23, 10, True), (8, 4, 10, False),
                                              (4, 20, 4, False), (16, 1, 16, True),
                                              (16, 1, 16, False), (16, 3, 16, False),
-                                             (16, 5, 16, True), (16, 40, 16, True)])
+                                             (16, 5, 16, True), (16, 40, 16, True),
+                                             (10, 1, 10, True), (10, 1, 10, False),
+                                             (10, 20, 10, True)])
 def test_gram_and_update_match_numpy(torch, bbl, bx, nblk, ny, xf32):
     """(5003 rows with 16 or more blocks take the wave-split update.)"""
     note("gram/update bx=%d nblk=%d ny=%d f32=%s" % (bx, nblk, ny, xf32))
