@@ -76,10 +76,6 @@ constexpr int kGramVMinChunk = BBL_GRAMV_MIN_CHUNK;
 #endif
 // row groups of four in flight per wave of the 10-wide FP64-MFMA gram
 constexpr int kGram10U = BBL_GRAM10_U;
-#ifndef BBL_UPD10_PF
-#define BBL_UPD10_PF 1
-#endif
-constexpr int kUpd10Pf = BBL_UPD10_PF;
 #ifndef BBL_G16_CG
 #define BBL_G16_CG 1
 #endif
@@ -1317,7 +1313,6 @@ void update_valu(int64_t n, const XT *X, int nblk, int64_t xstride, const double
     }
   }
   const bool pf = grid < 512 && nblk >= 8;
-  const bool pf10 = !pf && B == 10 && NY == 10 && nblk >= 2 * kUpd10Pf && kUpd10Pf > 1;
 #define BBL_UPDV(G, PF)                                                                        \
   hipLaunchKernelGGL((k_update_v<XT, YIT, YOT, B, NY, kUpdRPL, G, PF>), dim3((unsigned)grid),    \
                      dim3(256), 0, s, n, X, nblk, xstride, C, alpha, Yin, beta, Yout, when, gpart)
@@ -1327,11 +1322,9 @@ void update_valu(int64_t n, const XT *X, int nblk, int64_t xstride, const double
                        beta, Yout, when, gpart);
   } else if (gpart) {
     if (pf) BBL_UPDV(true, 4);
-    else if (pf10) BBL_UPDV(true, kUpd10Pf);
     else BBL_UPDV(true, 1);
   } else {
     if (pf) BBL_UPDV(false, 4);
-    else if (pf10) BBL_UPDV(false, kUpd10Pf);
     else BBL_UPDV(false, 1);
   }
 #undef BBL_UPDV
