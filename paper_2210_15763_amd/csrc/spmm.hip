@@ -1022,6 +1022,48 @@ __global__ __launch_bounds__(1024) void k_spmm_planned(int64_t n, int64_t G, int
 // outside a lane's part of the row read an all-zero LDS row kept after the
 // staged blocks, with a zero weight, so the LDS reads carry no branches.
 
+// Sum over the 16 lanes of one DPP row (lanes 16r .. 16r + 15), every lane
+// ending with the total, on the VALU: partners lane ^ 1 and lane ^ 2 (quad
+// permutations), then 7 - i within eight lanes and 15 - i within sixteen
+// (half mirror, mirror); each step adds sums over disjoint lane sets.  An
+// xor butterfly through __shfl_xor is a ds_bpermute per value and step,
+// which queues behind the LDS gathers of the product.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f(double x) {
+  const unsigned long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// The partner's value in round `off` of a halving exchange over LPR lanes
+// (16: off = 8, 4, 2, 1; 2: off = 1), on DPP: lane i ^ 8 (row rotation by
+// 8), lane 7 - i within eight (half mirror; with lane pairs, whose lowest
+// bit names the column half, i ^ 6 by a quad permutation and the half
+// mirror), lane i ^ 2, lane i ^ 1.  Each partner differs from the lane in
+// bit `off` of its index, in no higher bit, and (lane pairs) not in the
+// lowest, so the rounds keep and send the same halves as an xor butterfly
+// would, and afterwards every lane holds the sums over all LPR lanes (lane
+// pairs: over those of its half) of the same components.
+template <bool PAIR, typename T>
+__device__ __forceinline__ T halving_partner(T x, int off) {
+  if (off == 8) return dpp_f<0x128>(x);
+  if (off == 4) return PAIR ? dpp_f<0x141>(dpp_f<0xB1>(x)) : dpp_f<0x141>(x);
+  if (off == 2) return dpp_f<0x4E>(x);
+  return dpp_f<0xB1>(x);
+}
+template <typename T>
+__device__ __forceinline__ T row16_sum(T v) {
+  v += dpp_f<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_f<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_f<0x141>(v);  // row_half_mirror
+  v += dpp_f<0x140>(v);  // row_mirror
+  return v;
+}
+
 // lanes per row and entries per lane and step: pass 1 takes ~90 % of each
 // row's entries, pass 2 ~10 %
 // T: the value and vector type (float, or double for float64 plans, whose
@@ -1381,26 +1423,29 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
     if (last) {
       yp = Yw + (int64_t)row * ld;
       if constexpr (kRot) {
-        // halving exchange between lanes of equal parity: afterwards lane sub
-        // holds (rotated) component (sub >> 1) & 7
+        // halving exchange with the DPP partners of halving_partner: lane
+        // 15 - sub first (the opposite parity, so the halves each lane keeps
+        // and sends are chosen by h8 ^ par, which also undoes the odd lanes'
+        // rotation), then 7 - sub within eight, sub ^ 2 and sub ^ 1;
+        // afterwards lanes sub and sub ^ 1 hold component sub >> 1
         const bool h8 = sub & 8, h4 = sub & 4, h2 = sub & 2;
+        const bool f = h8 != (par != 0);
         T k4[4], k2[2];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const T send = h8 ? acc[i] : acc[i + 4];
-          const T keep = h8 ? acc[i + 4] : acc[i];
-          k4[i] = keep + __shfl_xor(send, 8, LPR);
+          const T send = f ? acc[i] : acc[i + 4];
+          const T keep = f ? acc[i + 4] : acc[i];
+          k4[i] = keep + dpp_f<0x140>(send);
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
           const T send = h4 ? k4[i] : k4[i + 2];
           const T keep = h4 ? k4[i + 2] : k4[i];
-          k2[i] = keep + __shfl_xor(send, 4, LPR);
+          k2[i] = keep + dpp_f<0x141>(send);
         }
         const T send = h2 ? k2[0] : k2[1];
-        T k1 = (h2 ? k2[1] : k2[0]) + __shfl_xor(send, 2, LPR);
-        // even lane sub and odd lane sub ^ 9 now hold the same component
-        out[0] = k1 + __shfl_xor(k1, 9, LPR);
+        const T k1 = (h2 ? k2[1] : k2[0]) + dpp_f<0x4E>(send);
+        out[0] = k1 + dpp_f<0xB1>(k1);
       } else if constexpr (BL >= LPE) {
         // halving exchange: each round keeps the half of the sums selected by
         // one bit of esub, so the lane ends with components [NO esub, NO esub
@@ -1416,20 +1461,16 @@ __device__ __forceinline__ void pipe_run(int64_t g, int64_t n, int64_t G, int sl
           for (int i = 0; i < K / 2; ++i) {
             const T send = up ? v[i] : v[i + K / 2];
             const T keep = up ? v[i + K / 2] : v[i];
-            v[i] = keep + __shfl_xor(send, off, LPR);
+            v[i] = keep + halving_partner<PAIR>(send, off);
           }
         }
 #pragma unroll
         for (int i = 0; i < NO; ++i) out[i] = v[i] + (P2 ? cur.yp[i] : T(0));
       } else {
         static_assert(!P2 && !PAIR, "pass 2 and lane pairs need BL >= LPE");
+        static_assert(LPR == 16, "one DPP row per matrix row");
 #pragma unroll
-        for (int off = LPR / 2; off > 0; off >>= 1) {
-#pragma unroll
-          for (int a = 0; a < B; ++a) acc[a] += __shfl_xor(acc[a], off, LPR);
-        }
-#pragma unroll
-        for (int a = 0; a < B; ++a) out[a] = acc[a];
+        for (int a = 0; a < B; ++a) out[a] = row16_sum(acc[a]);
       }
 #pragma unroll
       for (int a = 0; a < BL; ++a) acc[a] = T(0);
