@@ -238,7 +238,7 @@ def kernels_only(torch, bbl, Hd, b, iters=10):
     log("kernels-only done")
 
 
-def compare_pivots(torch, bbl, weights, m_max, sweep=False):
+def compare_pivots(torch, bbl, weights, m_max, sweep=False, n_trunc=0, feature_vectors=0):
     import synthgen
     w = synthgen.WORKLOADS["apply_n5e6"]
     t0 = time.time()
@@ -247,6 +247,8 @@ def compare_pivots(torch, bbl, weights, m_max, sweep=False):
     Hd = bbl.DeviceCSR.from_host(H, "float32", block_rows=w.R)
     params = torch.from_numpy(np.load(weights, allow_pickle=False)).cuda()
     b, k, R = w.nvec, w.k, w.R
+    nt = n_trunc or w.n_trunc  # truncation rows (default: 1 % of n)
+    fv = feature_vectors       # truncated vectors behind P_D (0: the default 20)
     arms = {}
 
     def run(name, make):
@@ -273,19 +275,19 @@ def compare_pivots(torch, bbl, weights, m_max, sweep=False):
                            {"pivot_full_spmm": 0}))
 
     def boot():
-        P, st = bbl.bootstrap_pivot(Hd, w.n_trunc, b, w.tol, m_max=m_max, seed=w.seed)
+        P, st = bbl.bootstrap_pivot(Hd, nt, b, w.tol, m_max=m_max, seed=w.seed)
         return P, {"pivot_full_spmm": 0, "truncated_iters": st["iters"]}
     run("bootstrap", boot)
 
     def variant_d():
-        f = bbl.pivot_features(Hd, w.n_trunc, R, w.tol, m_max=m_max, seed=w.seed)
+        f = bbl.pivot_features(Hd, nt, R, w.tol, m_max=m_max, seed=w.seed, feature_vectors=fv)
         return f["p_d"][:, :b].contiguous(), {"pivot_full_spmm": 4,
                                               "truncated_iters": f["stats"]["iters"]}
     run("variant_d", variant_d)
 
     def learned():
-        P, info = bbl.learned_pivot(Hd, params, w.n_trunc, R, b, k, w.tol, m_max=m_max,
-                                    seed=w.seed)
+        P, info = bbl.learned_pivot(Hd, params, nt, R, b, k, w.tol, m_max=m_max,
+                                    seed=w.seed, feature_vectors=fv)
         return P, {"pivot_full_spmm": 6, "choice": info["choice"],
                    "rr_sums": [float(x) for x in info["rr_sums"]],
                    "truncated_iters": info["stats"]["iters"]}
@@ -297,7 +299,8 @@ def compare_pivots(torch, bbl, weights, m_max, sweep=False):
     if sweep:
         arms["spmm_block_sweep"] = spmm_block_sweep(torch, bbl, H, R, Hd)
     print(json.dumps({"mode": "compare-pivots", "workload": "sectored symmetric CSR n=5e6, "
-                      "~300 nnz/row, FP32, b=k=10, tol=1e-6, truncation 50000 rows, seed 200",
+                      "~300 nnz/row, FP32, b=k=10, tol=1e-6, truncation %d rows, P_D from %d "
+                      "truncated vectors, seed 200" % (nt, fv or 20),
                       "n": H.n, "nnz": H.nnz, "m_max": m_max, "weights": os.path.basename(weights),
                       "arms": arms}), flush=True)
 
@@ -673,6 +676,10 @@ def main():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2210_15763_amd", "weights",
                                                       "pivot_mlp_sectored.npy"))
     ap.add_argument("--compare-m-max", type=int, default=300)
+    ap.add_argument("--compare-trunc", type=int, default=0,
+                    help="--compare-pivots: truncation rows (default 50,000, 1 %% of n)")
+    ap.add_argument("--feature-vectors", type=int, default=0,
+                    help="--compare-pivots: truncated vectors behind P_D, 10..32 (default 20)")
     ap.add_argument("--spmm-sweep", action="store_true",
                     help="SpMM time per operation for block widths 1..16 (plain and planned)")
     ap.add_argument("--workload", default=WORKLOAD,
@@ -701,7 +708,8 @@ def main():
     import paper_2210_15763_amd as bbl
     bbl.load_library()
     if args.compare_pivots:
-        compare_pivots(torch, bbl, args.weights, args.compare_m_max, args.spmm_sweep)
+        compare_pivots(torch, bbl, args.weights, args.compare_m_max, args.spmm_sweep,
+                       args.compare_trunc, args.feature_vectors)
         return
     if args.workload != WORKLOAD:
         large_workload(torch, bbl, args.workload, args)
