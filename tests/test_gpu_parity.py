@@ -426,6 +426,23 @@ def test_gram_and_update_match_numpy(torch, bbl, bx, nblk, ny, xf32):
     np.testing.assert_allclose(Out32.double().cpu().numpy(), Xwide @ Cm, rtol=2e-6, atol=2e-6 * np.abs(Xwide @ Cm).max())
 
 
+@pytest.mark.parametrize("bx", [8, 10])
+def test_gram_at_a_row_count_past_the_short_row_path(torch, bbl, bx):
+    """The 8- and 10-wide matrix-core grams at 700,003 rows (row chunks of 256
+    rows and more, two row groups in flight; the parity case above, at 5003
+    rows, takes the short-row launch) against numpy in float64."""
+    note("gram bx=%d n=700003" % bx)
+    rng = np.random.default_rng(bx)
+    n, nblk = 700_003, 5
+    Xb = rng.standard_normal((nblk, n, bx)).astype(np.float32)
+    Y = rng.standard_normal((n, bx))
+    C = bbl.gram(dev(torch, Xb), nblk, bx, dev(torch, Y)).cpu().numpy()
+    Xwide = np.concatenate([Xb[i].astype(np.float64) for i in range(nblk)], axis=1)
+    Cref = Xwide.T @ Y
+    bound = 64 * n * U64 * (np.abs(Xwide).T @ np.abs(Y))
+    assert np.all(np.abs(C.reshape(Cref.shape) - Cref) <= bound)
+
+
 @pytest.mark.parametrize("n", [1, 7, 17, 33])
 def test_sixteen_wide_products_on_tiny_row_counts(torch, bbl, n):
     """The 16-wide matrix-core gram and update on fewer rows than one 16-row
