@@ -47,6 +47,11 @@ constexpr int kTilesPerWG = 8;   // 16-column tiles of X handled by one gram WG
 // number of waves (row chunks x column groups) the grid is sized to
 constexpr int kGramWaves = BBL_GRAM_WAVES;
 constexpr int kGramWaveTarget = BBL_GRAM_WAVE_TARGET;
+// most row chunks of the 8- and 10-wide grams: with one or two column groups
+// (up to 16 blocks of 8) the wave target needs 3072-6144 chunks; at 2048 the
+// grid left the chip a third full (n = 1e8, 5 / 8 / 16 blocks: 2.7 / 3.5 /
+// 5.2 TB/s, now 5.3 / 5.9 / 5.9)
+constexpr int kGramMaxChunks = 8192;
 #ifndef BBL_GRAM_SMALL_U
 #define BBL_GRAM_SMALL_U 8
 #endif
@@ -1221,7 +1226,7 @@ int gram_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const 
     // 64 padded columns (5 1/3 blocks) per one-wave workgroup, grid and row
     // chunks as for 8-wide blocks below
     const int gy = (nblk * 12 + 63) / 64;
-    int64_t gx = std::min<int64_t>(2048, ceil_div(kGramWaveTarget, gy));
+    int64_t gx = std::min<int64_t>(kGramMaxChunks, ceil_div(kGramWaveTarget, gy));
     const bool small = ceil_div(n, 256) < gx;
     constexpr int U = kGram10U;
     gx = std::max<int64_t>(1, std::min<int64_t>(gx, ceil_div(n, small ? kGramSmallChunk : 256)));
@@ -1242,7 +1247,7 @@ int gram_typed(int64_t n, const XT *X, int bx, int nblk, int64_t xstride, const 
     // 1024)
     constexpr int CG = 1, WPG = kGramWaves;
     const int gy = (M + 64 * CG - 1) / (64 * CG);
-    int64_t gx = std::min<int64_t>(2048, ceil_div(kGramWaveTarget, gy));
+    int64_t gx = std::min<int64_t>(kGramMaxChunks, ceil_div(kGramWaveTarget, gy));
     // short row counts: shorter row chunks with more rows in flight, so each
     // wave takes a few load rounds instead of dozens
     const bool small = ceil_div(n, 256) < gx;
