@@ -712,6 +712,10 @@ __device__ __forceinline__ int ms_classify(int32_t c, const int64_t *base, int w
 }
 
 constexpr int kMsMaxWidth = 16;  // blocks of all sets of a group
+#ifndef BBL_MS_ROWS_PER_WAVE
+#define BBL_MS_ROWS_PER_WAVE 16
+#endif
+constexpr int kMsRowsPerWave = BBL_MS_ROWS_PER_WAVE;  // rows per wave of the plan's count and fill
 
 // Per row (one wave per row): entries per set into srow[(s n + row) 2 + 1],
 // entries outside every set into rcnt[row].
@@ -721,16 +725,22 @@ __global__ __launch_bounds__(256) void k_ms_count(int64_t n, int64_t G, int slot
                                                   const int32_t *__restrict__ blocks,
                                                   int32_t *__restrict__ srow,
                                                   int32_t *__restrict__ rcnt) {
-  // one wave per row, uniform per wave; the grid strides over the rows
-  for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < n;
-       row += (int64_t)gridDim.x * 4) {
-    const int lane = threadIdx.x & 63;
+  // one wave per row, uniform per wave; each wave takes a run of rows, so
+  // the group's block bases are loaded once per group it meets
+  const int64_t nw = (int64_t)gridDim.x * 4, wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t rpw = (n + nw - 1) / nw, ra = wv * rpw, rb = min(n, ra + rpw);
+  const int lane = threadIdx.x & 63;
+  const int nsets = width / slots;
+  int64_t gcur = -1;
+  int64_t base[kMsMaxWidth];
+  for (int64_t row = ra; row < rb; ++row) {
     const int64_t g = row / G;
-    const int nsets = width / slots;
-    int64_t base[kMsMaxWidth];
-    for (int k = 0; k < width; ++k) {
-      const int b = blocks[g * width + k];
-      base[k] = b >= 0 ? (int64_t)b * G : -((int64_t)1 << 62);
+    if (g != gcur) {
+      gcur = g;
+      for (int k = 0; k < width; ++k) {
+        const int b = blocks[g * width + k];
+        base[k] = b >= 0 ? (int64_t)b * G : -((int64_t)1 << 62);
+      }
     }
     int cnt[kMsMaxWidth + 1] = {};
     const int64_t p0 = rp[row], p1 = rp[row + 1];
@@ -806,16 +816,22 @@ __global__ __launch_bounds__(256) void k_ms_fill(int64_t n, int64_t G, int slots
                                                  const int64_t *__restrict__ rgroup,
                                                  int32_t *__restrict__ rcol, VT *__restrict__ rval,
                                                  int4 *__restrict__ rlist) {
-  // one wave per row, uniform per wave; the grid strides over the rows
-  for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < n;
-       row += (int64_t)gridDim.x * 4) {
-    const int lane = threadIdx.x & 63;
+  // one wave per row, uniform per wave; each wave takes a run of rows, so
+  // the group's block bases are loaded once per group it meets
+  const int64_t nw = (int64_t)gridDim.x * 4, wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t rpw = (n + nw - 1) / nw, ra = wv * rpw, rb = min(n, ra + rpw);
+  const int lane = threadIdx.x & 63;
+  const int nsets = width / slots;
+  int64_t gcur = -1;
+  int64_t base[kMsMaxWidth];
+  for (int64_t row = ra; row < rb; ++row) {
     const int64_t g = row / G;
-    const int nsets = width / slots;
-    int64_t base[kMsMaxWidth];
-    for (int k = 0; k < width; ++k) {
-      const int b = blocks[g * width + k];
-      base[k] = b >= 0 ? (int64_t)b * G : -((int64_t)1 << 62);
+    if (g != gcur) {
+      gcur = g;
+      for (int k = 0; k < width; ++k) {
+        const int b = blocks[g * width + k];
+        base[k] = b >= 0 ? (int64_t)b * G : -((int64_t)1 << 62);
+      }
     }
     // the per-set destinations stay in registers: every loop over the sets
     // runs to kMsMaxWidth with a guard (a loop to the run-time set count
@@ -1989,7 +2005,8 @@ void build_ms_plan(const bbl_csr &H, int nvec, int vec_dtype, int slots, int nse
   char *idx = take(L.idx);
   hipLaunchKernelGGL(k_plan_blocks, dim3((unsigned)groups), dim3(256), 0, s, H.n, G, width,
                      H.row_ptr, H.col, blocks);
-  const unsigned grid = capped_grid(ceil_div(H.n, 4), 256);  // one wave per row, strided
+  // one wave per row, runs of kMsRowsPerWave rows per wave
+  const unsigned grid = capped_grid(ceil_div(H.n, 4 * kMsRowsPerWave), 256);
   hipLaunchKernelGGL(k_ms_count, dim3(grid), dim3(256), 0, s, H.n, G, slots, width, H.row_ptr,
                      H.col, blocks, srow, rcnt);
   hipLaunchKernelGGL(k_ms_group, dim3((unsigned)groups), dim3(256), 0, s, H.n, G, nsets, groups,
