@@ -699,8 +699,8 @@ def main():
         write_traffic(*args.traffic)
         return
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: the hot path has no multi-GPU build "
-              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the hot path has no multi-GPU build; "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
