@@ -88,7 +88,13 @@ constexpr int kGram10U = BBL_GRAM10_U;
 #define BBL_G16_U 2
 #endif
 #ifndef BBL_G16_WAVES
-#define BBL_G16_WAVES 6144
+#define BBL_G16_WAVES 49152
+#endif
+#ifndef BBL_G16_MIN_WAVES
+#define BBL_G16_MIN_WAVES 6144
+#endif
+#ifndef BBL_G16_MIN_ROWS
+#define BBL_G16_MIN_ROWS 1024
 #endif
 #ifndef BBL_U16_U
 #define BBL_U16_U 4
@@ -98,11 +104,22 @@ constexpr int kGram10U = BBL_GRAM10_U;
 #endif
 // 16-wide blocks on FP64 matrix cores: gram blocks per wave, 16-row tiles
 // in flight and the waves its grid is sized to; update tiles per wave step
-// and grid waves (each wave strides over the row tiles).  Measured at
-// n = 2e7 (1 / 8 / 20 / 40 blocks): gram 6.0 / 4.4 / 3.8 / 3.6 TB/s with one
-// block per wave (two or four per wave: slower, fewer waves resident);
-// update 5.3 / 5.0 / 4.7 / 4.4 TB/s (2 / 8 / 20 / 40 blocks)
+// and grid waves (each wave strides over the row tiles).  The gram's waves
+// of one row chunk (one per block, on one XCD) share the chunk's rows of W'
+// through the L2, which holds them only while the chunk is short: its grid
+// aims at kG16Waves waves (at most 2048 row chunks, and no more partial sums
+// than the buffer holds) but takes chunks of no fewer than kG16MinRows rows
+// beyond kG16MinWaves waves, so short problems keep their partial-sum traffic
+// small.  Measured at n = 2e7 (4 / 8 / 20 / 40 blocks): 4.5-5.0 / 4.4 /
+// 3.8 / 3.6 TB/s with 6144 waves (154 chunks of 130,000 rows at 40 blocks),
+// 4.7-5.4 / 4.7-4.8 / 4.5 / 4.4 with 49152 (840 chunks at 40 blocks, the
+// buffer's cap), no faster with the buffer and the chunk cap raised to
+// 98,304 or 196,608 waves; one block per wave (two or four per wave:
+// slower, fewer waves resident).  Update 5.3 / 5.0 / 4.7 / 4.4 TB/s (2 / 8 /
+// 20 / 40 blocks; 1-2 % faster at 32768 waves, not taken: its fused Gram's
+// partials grow with the grid)
 constexpr int kG16CG = BBL_G16_CG, kG16U = BBL_G16_U, kG16Waves = BBL_G16_WAVES;
+constexpr int kG16MinWaves = BBL_G16_MIN_WAVES, kG16MinRows = BBL_G16_MIN_ROWS;
 constexpr int kU16U = BBL_U16_U, kU16Waves = BBL_U16_WAVES;
 inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
@@ -1177,7 +1194,9 @@ template <typename XT, typename YT, int CG, int U>
 int gram_mfma16(int64_t n, const XT *X, int nblk, int64_t xstride, const YT *Y, double *partial,
                 int max_partials, const int *when, hipStream_t s) {
   const int gy = (int)ceil_div(nblk, CG);
-  int64_t gx = std::min<int64_t>(2048, ceil_div(kG16Waves, gy));
+  int64_t gx = std::max(ceil_div(kG16MinWaves, gy),
+                        std::min(ceil_div(kG16Waves, gy), ceil_div(n, kG16MinRows)));
+  gx = std::min<int64_t>(2048, gx);
   gx = std::max<int64_t>(1, std::min<int64_t>(gx, ceil_div(n, 16 * U)));
   gx = std::min<int64_t>(gx, std::max(1, max_partials));
   const int64_t chunk = ceil_div(ceil_div(n, gx), 16 * U) * (16 * U);
